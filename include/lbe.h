@@ -1,0 +1,167 @@
+/*
+ * lbe.h -- C ABI of the MI355X (gfx950) Lattice Boltzmann Electrokinetics
+ * library: one time step of the LBE method with metallic electrodes of
+ * Asta, Palaia, Trizac, Levesque and Rotenberg, "Lattice Boltzmann
+ * Electrokinetics simulation of nanocapacitors" (arXiv:1907.04732).
+ *
+ * Units are lattice units: dx = dt = k_B T = e = 1; phi is the reduced
+ * potential beta e psi (Sec. II C); the permittivity is 1/(4 pi l_B).
+ *
+ * Site order everywhere: r = x + nx*(y + ny*z), x fastest, periodic wrap in
+ * all three directions.  Node types: 0 = fluid, e >= 1 = solid node of
+ * electrode e (1..LBE_MAX_ELECTRODES).
+ *
+ * D3Q19 velocity order (populations in lbe_observables and f_init):
+ *   0 ( 0, 0, 0)
+ *   1 (+1, 0, 0)  2 (-1, 0, 0)  3 ( 0,+1, 0)  4 ( 0,-1, 0)  5 ( 0, 0,+1)  6 ( 0, 0,-1)
+ *   7 (+1,+1, 0)  8 (-1,-1, 0)  9 (+1,-1, 0) 10 (-1,+1, 0)
+ *  11 (+1, 0,+1) 12 (-1, 0,-1) 13 (+1, 0,-1) 14 (-1, 0,+1)
+ *  15 ( 0,+1,+1) 16 ( 0,-1,-1) 17 ( 0,+1,-1) 18 ( 0,-1,+1)
+ * weights 1/3 (rest), 1/18 (nearest), 1/36 (next-nearest)  (Sec. II B).
+ *
+ * Ownership: every host array passed in is copied during the call; the
+ * library keeps no host pointer.  The library owns all device memory and
+ * frees it in lbe_destroy.  Output pointers are caller-allocated host
+ * buffers.  A context is bound to one HIP stream and one device and is not
+ * thread-safe; separate contexts are independent.
+ *
+ * Errors: every int-returning call returns LBE_OK (0) or a negative code;
+ * lbe_last_error(ctx) describes the last failure of that context.
+ */
+#ifndef LBE_H
+#define LBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBE_OK = 0,
+  LBE_EINVAL = -1,     /* bad parameter, dimension, pointer or non-finite input */
+  LBE_EGEOM = -2,      /* geometry the solver cannot handle (see lbe_init) */
+  LBE_ENOMEM = -3,     /* host or device allocation failed */
+  LBE_EDEVICE = -4,    /* HIP runtime error, or no gfx950 device */
+  LBE_ENOCONV = -5,    /* Poisson solve hit max_iter before tol */
+  LBE_ENONFINITE = -6  /* a NaN/Inf appeared in the Poisson residual */
+};
+
+enum { LBE_FP64 = 0, LBE_FP32_MIXED = 1 };   /* precision form */
+enum { LBE_SOR4 = 0, LBE_MG = 1 };           /* Poisson solver */
+enum { LBE_ALLOW_FLOATING = 1 };             /* flags */
+enum { LBE_MAX_SPECIES = 4, LBE_MAX_ELECTRODES = 64, LBE_MAX_SITES = 100000000 };
+
+typedef struct lbe_ctx lbe_ctx;
+
+typedef struct {
+  int32_t nx, ny, nz;   /* lattice size, each >= 1 */
+  int32_t nspecies;     /* 1..4 ionic species */
+  int32_t z[4];         /* valencies z_k */
+  double D[4];          /* diffusion coefficients D_k >= 0 (Eqs. 9-10) */
+  double lB;            /* Bjerrum length l_B >= 0 */
+  double tau;           /* BGK relaxation time, > 1/2; nu = (tau - 1/2)/3 */
+  double rho0;          /* fluid density of the rest state, > 0 */
+  double Eapp[3];       /* applied field beta e E dx (Sec. III A 4) */
+  double omega;         /* SOR relaxation factor in (0, 2), diagonal-normalised */
+  double tol;           /* Poisson stop: ||R||_inf <= tol; tol <= 0: exactly
+                           max_iter sweeps (or cycles) and no LBE_ENOCONV */
+  int32_t max_iter;     /* sweep (SOR) or cycle (MG) limit per solve, >= 0 */
+  int32_t check_every;  /* sweeps between residual checks, >= 1 */
+  int32_t flags;        /* LBE_ALLOW_FLOATING: accept fluid regions that touch
+                           no electrode (their mean potential is left free) */
+  int32_t precision;    /* LBE_FP64 | LBE_FP32_MIXED */
+  int32_t poisson;      /* LBE_SOR4 | LBE_MG */
+  int32_t mg_levels;    /* multigrid levels (LBE_MG), >= 2 */
+  int32_t mg_nu1, mg_nu2; /* pre/post smoothing sweeps (LBE_MG) */
+  int32_t reserved;
+  void *stream;         /* hipStream_t to run on; NULL = library-owned stream */
+} lbe_params;
+
+typedef struct {
+  int64_t step;           /* time steps taken since lbe_init */
+  int32_t nelectrodes;    /* largest node type */
+  int32_t poisson_iters;  /* sweeps (or cycles) of the last Poisson solve */
+  double poisson_resid;   /* ||R||_inf after the last Poisson solve */
+  double mass;            /* sum over fluid nodes of rho */
+  double nk[4];           /* sum over fluid nodes of n_k */
+  double q_ion;           /* sum over fluid nodes of sum_k z_k n_k */
+  int64_t poisson_total;  /* sweeps (or cycles) summed over all solves */
+} lbe_obs;
+
+/*
+ * Create a context and bring it to time 0 (Sec. III A: the uncharged state
+ * right after the voltage is applied): populations f_init (19*N, order
+ * above; NULL = rest state w_i rho0 on fluid nodes), concentrations n_init
+ * (nspecies*N, species-major; NULL = n_ref[k] on every fluid node; values on
+ * solid nodes are ignored and set to 0), potential phi_s on solid nodes
+ * (N values, fluid entries ignored).  Then solves Poisson for n(0) starting
+ * from phi = 0 on fluid nodes and records Q(0).
+ *
+ * Errors: LBE_EINVAL for tau <= 1/2, omega outside (0, 2), a dimension < 1,
+ * more than LBE_MAX_SITES sites,
+ * nspecies outside 1..4, negative or non-finite D, l_B < 0, rho0 <= 0,
+ * check_every < 1, more than LBE_MAX_ELECTRODES electrodes, a NaN/Inf in any
+ * input, or NULL type/phi_s/out; LBE_EGEOM when two neighbouring fluid nodes
+ * share a four-colour class (a periodic fluid extent that is odd and > 2
+ * along an axis) or when a fluid region touches no electrode and
+ * LBE_ALLOW_FLOATING is not set; LBE_EDEVICE without a usable device;
+ * LBE_ENOCONV / LBE_ENONFINITE from the first solve (no context is made).
+ */
+int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
+             const double *n_init, const double *n_ref, const double *f_init, lbe_ctx **out);
+
+/*
+ * Advance nsteps time steps (Sec. II B-C).  Each step: link fluxes (Eq. 10)
+ * and the electrostatic force on the fluid, the velocity u(t); ions
+ * n(t+1) = n(t) - sum of link fluxes (Eq. 9); BGK collision with the force
+ * and streaming with halfway bounce-back (Eq. 8); Poisson for n(t+1) with
+ * the mid-link Dirichlet Laplacian (Eqs. 13, 15), warm-started; the
+ * electrode charges Q(t+1) by Gauss's law (Eq. 16) appended to the history.
+ * On LBE_ENOCONV / LBE_ENONFINITE the call stops after the failing solve:
+ * n and f hold time t+1, phi the last iterate, the step is counted and its
+ * charge is not recorded.
+ */
+int lbe_step(lbe_ctx *ctx, int64_t nsteps);
+
+/* Re-solve Poisson for the current concentrations, warm-started from the
+ * current potential (Sec. II C).  iters/resid may be NULL. */
+int lbe_poisson(lbe_ctx *ctx, int32_t *iters, double *resid);
+
+/* Charge of each electrode, in units of e, from Gauss's law on the current
+ * potential (Eq. 16 with the Laplacian of Eq. 15 taken on the electrode's
+ * solid nodes, the difference doubled on each solid-fluid link).
+ * q has room for ne >= nelectrodes values.  LBE_EINVAL if ne is too small. */
+int lbe_electrode_charge(lbe_ctx *ctx, double *q, int32_t ne);
+
+/*
+ * Copy observables to host buffers; any pointer may be NULL to skip it.
+ * totals: lbe_obs; phi: N; n: nspecies*N; u: 3*N component-major (u[a*N+r],
+ * the velocity of Guo forcing, (sum_i f_i c_i + F/2)/rho, of the current
+ * state); f: 19*N pre-collision populations of the current time; q_hist:
+ * up to q_hist_cap rows of nelectrodes charges, Q(0), Q(1), ...;
+ * *q_hist_len (if not NULL) receives the number of rows recorded.
+ */
+int lbe_observables(lbe_ctx *ctx, lbe_obs *totals, double *phi, double *n, double *u,
+                    double *f, double *q_hist, int64_t q_hist_cap, int64_t *q_hist_len);
+
+void lbe_destroy(lbe_ctx *ctx);
+const char *lbe_strerror(int code);
+const char *lbe_last_error(const lbe_ctx *ctx);
+
+/* Kernel timing for the roofline measurement: enable=1 brackets every
+ * launch of every kernel kind with HIP events on the context's stream;
+ * lbe_kernel_times returns, per kind, total milliseconds and launch counts
+ * since enabling (syncs the stream).  Kinds are listed by lbe_kernel_name. */
+int lbe_profile(lbe_ctx *ctx, int enable);
+int lbe_kernel_times(lbe_ctx *ctx, double *ms, int64_t *launches, int32_t nkinds);
+const char *lbe_kernel_name(int32_t kind);
+int32_t lbe_num_kernel_kinds(void);
+
+/* The velocity set as the library uses it (19*3 ints, 19 weights). */
+void lbe_velocities(int32_t *c, double *w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBE_H */

@@ -1,0 +1,250 @@
+"""Python binding of liblbe.so, the gfx950 Lattice Boltzmann Electrokinetics
+library (arXiv:1907.04732).  Argument marshalling only: every step of the
+method runs in the HIP kernels behind include/lbe.h.  There is no CPU
+fallback; importing works without a GPU, creating a context needs one.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbe.so")
+
+OK, EINVAL, EGEOM, ENOMEM, EDEVICE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32_MIXED = 0, 1
+SOR4, MG = 0, 1
+ALLOW_FLOATING = 1
+
+# public entry points of include/lbe.h
+ENTRY_POINTS = (
+    "lbe_init", "lbe_step", "lbe_poisson", "lbe_electrode_charge", "lbe_observables",
+    "lbe_destroy", "lbe_strerror", "lbe_last_error", "lbe_profile", "lbe_kernel_times",
+    "lbe_kernel_name", "lbe_num_kernel_kinds", "lbe_velocities",
+)
+
+
+class Params(C.Structure):
+    """Mirror of lbe_params."""
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nspecies", C.c_int32),
+        ("z", C.c_int32 * 4),
+        ("D", C.c_double * 4),
+        ("lB", C.c_double), ("tau", C.c_double), ("rho0", C.c_double),
+        ("Eapp", C.c_double * 3),
+        ("omega", C.c_double), ("tol", C.c_double),
+        ("max_iter", C.c_int32), ("check_every", C.c_int32),
+        ("flags", C.c_int32), ("precision", C.c_int32), ("poisson", C.c_int32),
+        ("mg_levels", C.c_int32), ("mg_nu1", C.c_int32), ("mg_nu2", C.c_int32),
+        ("reserved", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+class Obs(C.Structure):
+    """Mirror of lbe_obs."""
+    _fields_ = [
+        ("step", C.c_int64), ("nelectrodes", C.c_int32), ("poisson_iters", C.c_int32),
+        ("poisson_resid", C.c_double), ("mass", C.c_double), ("nk", C.c_double * 4),
+        ("q_ion", C.c_double), ("poisson_total", C.c_int64),
+    ]
+
+
+class LbeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbe error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblbe.so (built by paper_1907_04732_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} is missing: build it with `python -m paper_1907_04732_amd.build` "
+                      "(there is no CPU fallback)")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    d = P(C.c_double)
+    lib.lbe_init.argtypes = [P(Params), P(C.c_uint8), d, d, d, d, P(C.c_void_p)]
+    lib.lbe_init.restype = C.c_int
+    lib.lbe_step.argtypes = [C.c_void_p, C.c_int64]
+    lib.lbe_step.restype = C.c_int
+    lib.lbe_poisson.argtypes = [C.c_void_p, P(C.c_int32), d]
+    lib.lbe_poisson.restype = C.c_int
+    lib.lbe_electrode_charge.argtypes = [C.c_void_p, d, C.c_int32]
+    lib.lbe_electrode_charge.restype = C.c_int
+    lib.lbe_observables.argtypes = [C.c_void_p, P(Obs), d, d, d, d, d, C.c_int64, P(C.c_int64)]
+    lib.lbe_observables.restype = C.c_int
+    lib.lbe_destroy.argtypes = [C.c_void_p]
+    lib.lbe_destroy.restype = None
+    lib.lbe_strerror.argtypes = [C.c_int]
+    lib.lbe_strerror.restype = C.c_char_p
+    lib.lbe_last_error.argtypes = [C.c_void_p]
+    lib.lbe_last_error.restype = C.c_char_p
+    lib.lbe_profile.argtypes = [C.c_void_p, C.c_int]
+    lib.lbe_profile.restype = C.c_int
+    lib.lbe_kernel_times.argtypes = [C.c_void_p, d, P(C.c_int64), C.c_int32]
+    lib.lbe_kernel_times.restype = C.c_int
+    lib.lbe_kernel_name.argtypes = [C.c_int32]
+    lib.lbe_kernel_name.restype = C.c_char_p
+    lib.lbe_num_kernel_kinds.argtypes = []
+    lib.lbe_num_kernel_kinds.restype = C.c_int32
+    lib.lbe_velocities.argtypes = [P(C.c_int32), d]
+    lib.lbe_velocities.restype = None
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(shape, z, D, lB, tau=1.0, rho0=1.0, Eapp=(0.0, 0.0, 0.0), omega=1.8, tol=1e-10,
+                max_iter=200000, check_every=4, flags=0, precision=FP64, poisson=SOR4,
+                mg_levels=3, mg_nu1=2, mg_nu2=2, stream=None) -> Params:
+    p = Params()
+    p.nx, p.ny, p.nz = (int(v) for v in shape)
+    if not 1 <= len(z) <= 4 or len(D) != len(z):
+        raise ValueError("1..4 species with one valency and one D each")
+    p.nspecies = len(z)
+    for k in range(len(z)):
+        p.z[k] = int(z[k])
+        p.D[k] = float(D[k])
+    p.lB, p.tau, p.rho0 = float(lB), float(tau), float(rho0)
+    for a in range(3):
+        p.Eapp[a] = float(Eapp[a])
+    p.omega, p.tol = float(omega), float(tol)
+    p.max_iter, p.check_every, p.flags = int(max_iter), int(check_every), int(flags)
+    p.precision, p.poisson = int(precision), int(poisson)
+    p.mg_levels, p.mg_nu1, p.mg_nu2 = int(mg_levels), int(mg_nu1), int(mg_nu2)
+    p.stream = stream
+    return p
+
+
+def velocities():
+    lib = load()
+    c = (C.c_int32 * 57)()
+    w = np.empty(19)
+    lib.lbe_velocities(c, _dptr(w))
+    return np.array(list(c), dtype=np.int64).reshape(19, 3), w
+
+
+def kernel_names():
+    lib = load()
+    return [lib.lbe_kernel_name(k).decode() for k in range(lib.lbe_num_kernel_kinds())]
+
+
+class Lbe:
+    """One LBE context on the current HIP device (see include/lbe.h)."""
+
+    def __init__(self, params: Params, node_type, phi_s, n_init=None, n_ref=None, f_init=None):
+        lib = load()
+        self._lib = lib
+        self.p = params
+        self.N = params.nx * params.ny * params.nz
+        self.K = params.nspecies
+        t = np.ascontiguousarray(node_type, dtype=np.uint8).reshape(-1)
+        ps = np.ascontiguousarray(phi_s, dtype=np.float64).reshape(-1)
+        if t.size != self.N or ps.size != self.N:
+            raise ValueError("node_type and phi_s need nx*ny*nz entries")
+        ni = None if n_init is None else np.ascontiguousarray(n_init, dtype=np.float64).reshape(-1)
+        nr = None if n_ref is None else np.ascontiguousarray(n_ref, dtype=np.float64).reshape(-1)
+        fi = None if f_init is None else np.ascontiguousarray(f_init, dtype=np.float64).reshape(-1)
+        if ni is not None and ni.size != self.K * self.N:
+            raise ValueError("n_init needs nspecies*N entries")
+        if nr is not None and nr.size < self.K:
+            raise ValueError("n_ref needs nspecies entries")
+        if fi is not None and fi.size != 19 * self.N:
+            raise ValueError("f_init needs 19*N entries")
+        h = C.c_void_p()
+        rc = lib.lbe_init(C.byref(params), t.ctypes.data_as(C.POINTER(C.c_uint8)), _dptr(ps),
+                          _dptr(ni), _dptr(nr), _dptr(fi), C.byref(h))
+        if rc:
+            raise LbeError(rc, lib.lbe_last_error(None).decode())
+        self.h = h
+        self.ne = int(t.max()) if t.size else 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.lbe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc):
+        if rc:
+            raise LbeError(rc, self._lib.lbe_last_error(self.h).decode())
+
+    def step(self, nsteps=1):
+        self._check(self._lib.lbe_step(self.h, int(nsteps)))
+
+    def poisson(self):
+        it = C.c_int32()
+        res = C.c_double()
+        self._check(self._lib.lbe_poisson(self.h, C.byref(it), C.byref(res)))
+        return it.value, res.value
+
+    def electrode_charge(self):
+        q = np.zeros(max(self.ne, 1))
+        self._check(self._lib.lbe_electrode_charge(self.h, _dptr(q), len(q)))
+        return q[: self.ne]
+
+    def totals(self):
+        o = Obs()
+        self._check(self._lib.lbe_observables(self.h, C.byref(o), None, None, None, None, None, 0,
+                                              None))
+        return dict(step=o.step, nelectrodes=o.nelectrodes, poisson_iters=o.poisson_iters,
+                    poisson_resid=o.poisson_resid, mass=o.mass, nk=list(o.nk)[: self.K],
+                    q_ion=o.q_ion, poisson_total=o.poisson_total)
+
+    def fields(self, f=True):
+        """dict with phi (N), n (K,N), u (3,N) and, if f, populations (19,N)."""
+        N, K = self.N, self.K
+        phi = np.empty(N)
+        n = np.empty(K * N)
+        u = np.empty(3 * N)
+        fp = np.empty(19 * N) if f else None
+        self._check(self._lib.lbe_observables(self.h, None, _dptr(phi), _dptr(n), _dptr(u),
+                                              _dptr(fp), None, 0, None))
+        out = dict(phi=phi, n=n.reshape(K, N), u=u.reshape(3, N))
+        if f:
+            out["f"] = fp.reshape(19, N)
+        return out
+
+    def qhist(self):
+        ln = C.c_int64()
+        self._check(self._lib.lbe_observables(self.h, None, None, None, None, None, None, 0,
+                                              C.byref(ln)))
+        rows = ln.value
+        out = np.empty(max(rows * self.ne, 1))
+        self._check(self._lib.lbe_observables(self.h, None, None, None, None, None, _dptr(out),
+                                              rows, None))
+        return out[: rows * self.ne].reshape(rows, self.ne)
+
+    def profile(self, enable=True):
+        self._check(self._lib.lbe_profile(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        n = self._lib.lbe_num_kernel_kinds()
+        ms = np.zeros(n)
+        cnt = np.zeros(n, dtype=np.int64)
+        self._check(self._lib.lbe_kernel_times(self.h, _dptr(ms),
+                                               cnt.ctypes.data_as(C.POINTER(C.c_int64)), n))
+        return {kernel_names()[k]: (float(ms[k]), int(cnt[k])) for k in range(n)}

@@ -1,0 +1,1093 @@
+// lbe_capi.cpp -- the C ABI of include/lbe.h: parameter and geometry
+// checks, device state, and the per-step driver that sequences the kernels of
+// lbe_kernels.hip on one HIP stream.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/lbe.h"
+#include "lbe_internal.h"
+
+using namespace lbe;
+
+struct lbe_ctx {
+  lbe_params p{};
+  Lattice L{};
+  Phys P{};
+  int K = 0, ne = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  // device state (FP64 form)
+  uint32_t *mask = nullptr;
+  double *phi = nullptr, *src = nullptr, *u = nullptr;
+  double *n[2] = {nullptr, nullptr};
+  double *f[2] = {nullptr, nullptr};
+  // mixed form: FP32 deviations h = f - w rho0, nu = n - n_ref, FP32 velocity
+  float *h32[2] = {nullptr, nullptr};
+  float *nu32[2] = {nullptr, nullptr};
+  float *u32 = nullptr;
+  double *obs = nullptr;  // FP64 scratch for observables of the mixed form (22 N)
+  bool mixed = false;
+  std::vector<uint8_t> type_h;  // node types (host copy)
+  int cur = 0;
+
+  // reductions
+  double *partial = nullptr;
+  unsigned *counter = nullptr;
+  double *dout = nullptr;  // small device results (residual, totals)
+  double *hpin = nullptr;  // pinned host mirror of dout
+
+  // electrode charge tables
+  int *iface = nullptr, *blk_elec = nullptr, *blk_begin = nullptr, *blk_end = nullptr;
+  int nblk_charge = 0;
+  double *qcur = nullptr;
+  double *qhist = nullptr;
+  int64_t qcap = 0, qlen = 0;
+
+  // multigrid hierarchy (LBE_MG): level 0 is the lattice itself
+  struct MgDev {
+    MgLevel lv{};
+    MgTransfer tr{};  // from the previous (finer) level
+    uint32_t *mask = nullptr;
+    bool own_mask = false;
+    void *e = nullptr, *r = nullptr;  // correction and right-hand side (T)
+  };
+  std::vector<MgDev> mg;
+  int mg_coarse_sweeps = 0;
+
+  // statistics
+  int64_t step = 0;
+  int last_iters = 0;
+  double last_resid = 0.0;
+  int64_t total_iters = 0;
+
+  // profiling
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KK_COUNT];
+  std::vector<hipEvent_t> pool;
+  double ms[KK_COUNT] = {};
+  int64_t launches[KK_COUNT] = {};
+
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+int fail(lbe_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  else g_init_error = msg;
+  return code;
+}
+
+int hip_fail(lbe_ctx *c, hipError_t e, const char *what) {
+  return fail(c, e == hipErrorOutOfMemory ? LBE_ENOMEM : LBE_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, call)                                   \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return hip_fail((c), e_, #call); \
+  } while (0)
+
+// ---- profiling -----------------------------------------------------------
+
+hipEvent_t take_event(lbe_ctx *c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int flush_profile(lbe_ctx *c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < KK_COUNT; ++k) {
+    for (auto &pr : c->pending[k]) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) c->ms[k] += t;
+      c->launches[k] += 1;
+      c->pool.push_back(pr.first);
+      c->pool.push_back(pr.second);
+    }
+    c->pending[k].clear();
+  }
+  return LBE_OK;
+}
+
+template <class Launch>
+int run(lbe_ctx *c, KernelKind kind, Launch &&launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (c->prof) {
+    a = take_event(c);
+    b = take_event(c);
+    if (a) (void)hipEventRecord(a, c->stream);
+  }
+  hipError_t e = launch();
+  if (c->prof && a && b) {
+    (void)hipEventRecord(b, c->stream);
+    c->pending[kind].emplace_back(a, b);
+    size_t tot = 0;
+    for (int k = 0; k < KK_COUNT; ++k) tot += c->pending[k].size();
+    if (tot > 16384) {
+      int rc = flush_profile(c);
+      if (rc) return rc;
+    }
+  }
+  if (e != hipSuccess) return hip_fail(c, e, kKernelNames[kind]);
+  return LBE_OK;
+}
+
+// ---- validation and geometry ---------------------------------------------
+
+int validate(const lbe_params *p) {
+  if (!p) return fail(nullptr, LBE_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return fail(nullptr, LBE_EINVAL, "lattice dimensions must be >= 1");
+  // 32-bit site indices: 19 population arrays must stay below 2^31 entries
+  if ((long long)p->nx * p->ny * p->nz > LBE_MAX_SITES)
+    return fail(nullptr, LBE_EINVAL, "lattice larger than LBE_MAX_SITES");
+  if (p->nspecies < 1 || p->nspecies > LBE_MAX_SPECIES)
+    return fail(nullptr, LBE_EINVAL, "nspecies must be in 1..4");
+  if (!(p->tau > 0.5)) return fail(nullptr, LBE_EINVAL, "tau must exceed 1/2");
+  if (!(p->omega > 0.0 && p->omega < 2.0))
+    return fail(nullptr, LBE_EINVAL, "omega must lie in (0, 2)");
+  if (!(p->rho0 > 0.0) || !(p->lB >= 0.0) || !isfinite(p->lB) || !isfinite(p->rho0) ||
+      !isfinite(p->tol) || p->max_iter < 0 || p->check_every < 1)
+    return fail(nullptr, LBE_EINVAL, "bad rho0, lB, tol, max_iter or check_every");
+  for (int k = 0; k < p->nspecies; ++k)
+    if (!(p->D[k] >= 0.0) || !isfinite(p->D[k]))
+      return fail(nullptr, LBE_EINVAL, "diffusion coefficients must be finite and >= 0");
+  for (int a = 0; a < 3; ++a)
+    if (!isfinite(p->Eapp[a])) return fail(nullptr, LBE_EINVAL, "applied field must be finite");
+  if (p->precision != LBE_FP64 && p->precision != LBE_FP32_MIXED)
+    return fail(nullptr, LBE_EINVAL, "unsupported precision form");
+  if (p->poisson != LBE_SOR4 && p->poisson != LBE_MG)
+    return fail(nullptr, LBE_EINVAL, "unsupported Poisson solver");
+  if (p->poisson == LBE_MG && (p->mg_levels < 0 || p->mg_levels == 1 || p->mg_levels > 16 ||
+                               p->mg_nu1 < 0 || p->mg_nu2 < 0 || p->mg_nu1 + p->mg_nu2 < 1))
+    return fail(nullptr, LBE_EINVAL, "bad multigrid levels or smoothing counts");
+  return LBE_OK;
+}
+
+struct HostGeometry {
+  std::vector<uint32_t> mask;
+  std::vector<int> iface;  // interface solid sites grouped by electrode
+  std::vector<int> blk_elec, blk_begin, blk_end;
+  uint32_t selfm = 0;
+};
+
+inline int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+int build_geometry(const lbe_params *p, const uint8_t *type, int ne, HostGeometry &g) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const long N = (long)nx * ny * nz;
+  for (int i = 1; i < NQ; ++i) {
+    bool self = (CX[i] == 0 || nx == 1) && (CY[i] == 0 || ny == 1) && (CZ[i] == 0 || nz == 1);
+    if (self) g.selfm |= 1u << (i - 1);
+  }
+  g.mask.assign(N, 0u);
+  std::vector<int> nb((size_t)N * NQ);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const long r = x + (long)nx * (y + (long)ny * z);
+        uint32_t m = type[r] ? SOLID_BIT : 0u;
+        for (int i = 0; i < NQ; ++i) {
+          const long rn = wrap(x + CX[i], nx) + (long)nx * (wrap(y + CY[i], ny) + (long)ny * wrap(z + CZ[i], nz));
+          nb[(size_t)i * N + r] = (int)rn;
+          if (i && type[rn]) m |= 1u << (i - 1);
+        }
+        g.mask[r] = m;
+      }
+  // four-colour order: neighbouring fluid nodes must differ in colour
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const long r = x + (long)nx * (y + (long)ny * z);
+        if (type[r]) continue;
+        const int cr = ((x + z) & 1) + 2 * ((y + z) & 1);
+        for (int i = 1; i < NQ; ++i) {
+          const int xn = wrap(x + CX[i], nx), yn = wrap(y + CY[i], ny), zn = wrap(z + CZ[i], nz);
+          const long rn = nb[(size_t)i * N + r];
+          if (rn == r || type[rn]) continue;
+          if ((((xn + zn) & 1) + 2 * ((yn + zn) & 1)) == cr)
+            return fail(nullptr, LBE_EGEOM,
+                        "four-colour order invalid: periodic fluid extent along an axis is odd and > 2");
+        }
+      }
+  // every fluid region must touch an electrode
+  if (!(p->flags & LBE_ALLOW_FLOATING)) {
+    std::vector<char> seen(N, 0);
+    std::vector<long> stack;
+    for (long r0 = 0; r0 < N; ++r0) {
+      if (type[r0] || seen[r0]) continue;
+      bool touches = false;
+      stack.clear();
+      stack.push_back(r0);
+      seen[r0] = 1;
+      while (!stack.empty()) {
+        const long r = stack.back();
+        stack.pop_back();
+        for (int i = 1; i < NQ; ++i) {
+          const long rn = nb[(size_t)i * N + r];
+          if (type[rn]) {
+            touches = true;
+            continue;
+          }
+          if (!seen[rn]) {
+            seen[rn] = 1;
+            stack.push_back(rn);
+          }
+        }
+      }
+      if (!touches) return fail(nullptr, LBE_EGEOM, "a fluid region touches no electrode");
+    }
+  }
+  // interface solid nodes per electrode and the charge kernel's block table
+  constexpr int B = 256;
+  for (int e = 1; e <= ne; ++e) {
+    const int begin = (int)g.iface.size();
+    for (long r = 0; r < N; ++r) {
+      if (type[r] != e) continue;
+      if ((g.mask[r] & ~SOLID_BIT) != ((1u << 18) - 1u)) g.iface.push_back((int)r);
+    }
+    const int end = (int)g.iface.size();
+    for (int b = begin; b < end; b += B) {
+      g.blk_elec.push_back(e - 1);
+      g.blk_begin.push_back(b);
+      g.blk_end.push_back(std::min(b + B, end));
+    }
+  }
+  return LBE_OK;
+}
+
+template <class T>
+int dalloc(lbe_ctx *c, T **ptr, size_t count) {
+  if (count == 0) count = 1;
+  HIPCHK(c, hipMalloc((void **)ptr, sizeof(T) * count));
+  return LBE_OK;
+}
+
+// ---- steps ----------------------------------------------------------------
+
+int read_scalars(lbe_ctx *c, int count) {
+  HIPCHK(c, hipMemcpyAsync(c->hpin, c->dout, sizeof(double) * count, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBE_OK;
+}
+
+int residual(lbe_ctx *c, double *out) {
+  int rc = run(c, KK_RESID, [&] {
+    return launch_resid_f64(c->stream, c->L, c->mask, c->src, c->phi, c->partial, c->counter,
+                            c->dout);
+  });
+  if (rc) return rc;
+  rc = read_scalars(c, 1);
+  if (rc) return rc;
+  *out = c->hpin[0];
+  return LBE_OK;
+}
+
+int sor_sweeps(lbe_ctx *c, int count) {
+  for (int s = 0; s < count; ++s)
+    for (int col = 0; col < 4; ++col) {
+      int rc = run(c, KK_SOR, [&] {
+        return launch_sor_f64(c->stream, c->L, c->P, col, c->mask, c->src, c->phi);
+      });
+      if (rc) return rc;
+    }
+  return LBE_OK;
+}
+
+// Poisson solve (Sec. II C), warm-started; same stopping schedule as the
+// oracle: residual before the first sweep and after every check_every.
+int sor_solve(lbe_ctx *c) {
+  const lbe_params &p = c->p;
+  int sweeps = 0;
+  double res = 0.0;
+  int rc;
+  if (p.tol <= 0.0) {
+    rc = sor_sweeps(c, p.max_iter);
+    if (rc) return rc;
+    sweeps = p.max_iter;
+    rc = residual(c, &res);
+    if (rc) return rc;
+    c->last_iters = sweeps;
+    c->last_resid = res;
+    c->total_iters += sweeps;
+    if (!isfinite(res)) return fail(c, LBE_ENONFINITE, "non-finite Poisson residual");
+    return LBE_OK;
+  }
+  for (;;) {
+    rc = residual(c, &res);
+    if (rc) return rc;
+    c->last_iters = sweeps;
+    c->last_resid = res;
+    if (!isfinite(res)) {
+      c->total_iters += sweeps;
+      return fail(c, LBE_ENONFINITE, "non-finite Poisson residual");
+    }
+    if (res <= p.tol) break;
+    if (sweeps >= p.max_iter) {
+      c->total_iters += sweeps;
+      char buf[160];
+      snprintf(buf, sizeof buf, "Poisson not converged: residual %.3e after %d sweeps", res, sweeps);
+      return fail(c, LBE_ENOCONV, buf);
+    }
+    const int m = std::min(p.check_every, p.max_iter - sweeps);
+    rc = sor_sweeps(c, m);
+    if (rc) return rc;
+    sweeps += m;
+  }
+  c->total_iters += sweeps;
+  return LBE_OK;
+}
+
+
+// ---- multigrid hierarchy ----------------------------------------------------
+
+// Four-colour order valid on a level: no two neighbouring fluid cells share a
+// colour (self links excluded).
+bool colouring_ok(int nx, int ny, int nz, const std::vector<uint8_t> &solid) {
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const long r = x + (long)nx * (y + (long)ny * z);
+        if (solid[r]) continue;
+        const int cr = ((x + z) & 1) + 2 * ((y + z) & 1);
+        for (int i = 1; i < NQ; ++i) {
+          const int xn = wrap(x + CX[i], nx), yn = wrap(y + CY[i], ny), zn = wrap(z + CZ[i], nz);
+          const long rn = xn + (long)nx * (yn + (long)ny * zn);
+          if (rn == r || solid[rn]) continue;
+          if ((((xn + zn) & 1) + 2 * ((yn + zn) & 1)) == cr) return false;
+        }
+      }
+  return true;
+}
+
+std::vector<uint32_t> level_mask(int nx, int ny, int nz, const std::vector<uint8_t> &solid) {
+  std::vector<uint32_t> m((size_t)nx * ny * nz);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const long r = x + (long)nx * (y + (long)ny * z);
+        uint32_t v = solid[r] ? SOLID_BIT : 0u;
+        for (int i = 1; i < NQ; ++i) {
+          const long rn = wrap(x + CX[i], nx) + (long)nx * (wrap(y + CY[i], ny) + (long)ny * wrap(z + CZ[i], nz));
+          if (solid[rn]) v |= 1u << (i - 1);
+        }
+        m[r] = v;
+      }
+  return m;
+}
+
+uint32_t level_selfm(int nx, int ny, int nz) {
+  uint32_t s = 0;
+  for (int i = 1; i < NQ; ++i)
+    if ((CX[i] == 0 || nx == 1) && (CY[i] == 0 || ny == 1) && (CZ[i] == 0 || nz == 1))
+      s |= 1u << (i - 1);
+  return s;
+}
+
+// Coarsen one level: cells pair up along every axis longer than 1 (one half
+// block at the end of an odd axis); offsets minimise blocks that mix solid
+// and fluid; a block is solid when at least half of its children are.
+void coarsen(int nx, int ny, int nz, const std::vector<uint8_t> &solid, int &cx, int &cy,
+             int &cz, int &ox, int &oy, int &oz, std::vector<uint8_t> &csolid) {
+  cx = nx > 1 ? (nx + 1) / 2 : 1;
+  cy = ny > 1 ? (ny + 1) / 2 : 1;
+  cz = nz > 1 ? (nz + 1) / 2 : 1;
+  const long nc = (long)cx * cy * cz;
+  long best = -1;
+  std::vector<int> ns(nc), nf(nc);
+  for (int tz = 0; tz < (nz > 1 ? 2 : 1); ++tz)
+    for (int ty = 0; ty < (ny > 1 ? 2 : 1); ++ty)
+      for (int tx = 0; tx < (nx > 1 ? 2 : 1); ++tx) {
+        std::fill(ns.begin(), ns.end(), 0);
+        std::fill(nf.begin(), nf.end(), 0);
+        for (int z = 0; z < nz; ++z)
+          for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+              const long r = x + (long)nx * (y + (long)ny * z);
+              const long R = (wrap(x - tx, nx) / 2) + (long)cx * ((wrap(y - ty, ny) / 2) + (long)cy * (wrap(z - tz, nz) / 2));
+              (solid[r] ? ns : nf)[R]++;
+            }
+        long mixed = 0;
+        for (long R = 0; R < nc; ++R) mixed += (ns[R] && nf[R]);
+        if (best < 0 || mixed < best) {
+          best = mixed;
+          ox = tx;
+          oy = ty;
+          oz = tz;
+          csolid.assign(nc, 0);
+          for (long R = 0; R < nc; ++R) csolid[R] = 2 * ns[R] >= ns[R] + nf[R];
+        }
+      }
+}
+
+int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
+  const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
+  const int maxl = only_top ? 1 : (c->p.mg_levels > 0 ? c->p.mg_levels : 16);
+  int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
+  std::vector<uint8_t> solid((size_t)nx * ny * nz);
+  for (size_t r = 0; r < solid.size(); ++r) solid[r] = type[r] != 0;
+  lbe_ctx::MgDev l0;
+  l0.lv = MgLevel{nx, ny, nz, nx * ny, nx * ny * nz, c->L.selfm, 1.0, 1.0};
+  l0.mask = c->mask;
+  HIPCHK(c, hipMalloc(&l0.e, esz * l0.lv.n));
+  HIPCHK(c, hipMalloc(&l0.r, esz * l0.lv.n));
+  c->mg.push_back(l0);
+  double h2 = 1.0;
+  for (int l = 1; l < maxl; ++l) {
+    if (c->p.mg_levels == 0 && (long)nx * ny * nz <= 2048) break;
+    if (nx <= 2 && ny <= 2 && nz <= 2) break;
+    int cx, cy, cz, ox = 0, oy = 0, oz = 0;
+    std::vector<uint8_t> cs;
+    coarsen(nx, ny, nz, solid, cx, cy, cz, ox, oy, oz, cs);
+    if (std::find(cs.begin(), cs.end(), 0) == cs.end()) break;  // no fluid left
+    if (!colouring_ok(cx, cy, cz, cs)) break;
+    h2 *= 4.0;
+    lbe_ctx::MgDev L;
+    L.lv = MgLevel{cx, cy, cz, cx * cy, cx * cy * cz, level_selfm(cx, cy, cz), h2, 1.0 / h2};
+    L.tr = MgTransfer{c->mg.back().lv, L.lv, ox, oy, oz};
+    const std::vector<uint32_t> m = level_mask(cx, cy, cz, cs);
+    HIPCHK(c, hipMalloc((void **)&L.mask, sizeof(uint32_t) * m.size()));
+    L.own_mask = true;
+    c->mg.push_back(L);  // owned from here on, freed with the context
+    lbe_ctx::MgDev &B = c->mg.back();
+    HIPCHK(c, hipMemcpy(B.mask, m.data(), sizeof(uint32_t) * m.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMalloc(&B.e, esz * B.lv.n));
+    HIPCHK(c, hipMalloc(&B.r, esz * B.lv.n));
+    HIPCHK(c, hipMemset(B.e, 0, esz * B.lv.n));
+    nx = cx;
+    ny = cy;
+    nz = cz;
+    solid.swap(cs);
+  }
+  const MgLevel &top = c->mg.back().lv;
+  c->mg_coarse_sweeps = 2 * std::max({top.nx, top.ny, top.nz}) + 10;
+  return LBE_OK;
+}
+
+template <class T>
+int mg_vcycle(lbe_ctx *c, size_t l) {
+  lbe_ctx::MgDev &L = c->mg[l];
+  T *e = (T *)L.e, *r = (T *)L.r;
+  int rc;
+  if (l + 1 == c->mg.size()) {
+    return run(c, KK_MG_COARSE, [&] {
+      return launch_mg_coarse<T>(c->stream, L.lv, c->p.omega, c->mg_coarse_sweeps, L.mask, r, e);
+    });
+  }
+  auto smooth = [&](int count) -> int {
+    for (int s = 0; s < count; ++s)
+      for (int col = 0; col < 4; ++col) {
+        int rc2 = run(c, KK_MG_SMOOTH, [&] {
+          return launch_mg_smooth<T>(c->stream, L.lv, 1.0, col, L.mask, r, e);
+        });
+        if (rc2) return rc2;
+      }
+    return LBE_OK;
+  };
+  if ((rc = smooth(c->p.mg_nu1))) return rc;
+  lbe_ctx::MgDev &C = c->mg[l + 1];
+  rc = run(c, KK_MG_RESTRICT, [&] {
+    return launch_mg_restrict<T>(c->stream, C.tr, L.mask, C.mask, r, e, (T *)C.r, (T *)C.e);
+  });
+  if (rc) return rc;
+  if ((rc = mg_vcycle<T>(c, l + 1))) return rc;
+  rc = run(c, KK_MG_PROLONG, [&] {
+    return launch_mg_prolong<T>(c->stream, C.tr, L.mask, C.mask, (const T *)C.e, e);
+  });
+  if (rc) return rc;
+  return smooth(c->p.mg_nu2);
+}
+
+// Defect correction: residual in FP64, correction by one V-cycle, phi += e.
+template <class T>
+int mg_solve(lbe_ctx *c) {
+  const lbe_params &p = c->p;
+  lbe_ctx::MgDev &L0 = c->mg[0];
+  int cycles = 0;
+  for (;;) {
+    int rc = run(c, KK_MG_RESID, [&] {
+      return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi, (T *)L0.r,
+                                      (T *)L0.e, c->partial, c->counter, c->dout);
+    });
+    if (rc) return rc;
+    if ((rc = read_scalars(c, 1))) return rc;
+    const double res = c->hpin[0];
+    c->last_iters = cycles;
+    c->last_resid = res;
+    if (!isfinite(res)) {
+      c->total_iters += cycles;
+      return fail(c, LBE_ENONFINITE, "non-finite Poisson residual");
+    }
+    if (p.tol > 0.0 && res <= p.tol) break;
+    if (cycles >= p.max_iter) {
+      c->total_iters += cycles;
+      if (p.tol <= 0.0) return LBE_OK;
+      char buf[160];
+      snprintf(buf, sizeof buf, "Poisson not converged: residual %.3e after %d cycles", res, cycles);
+      return fail(c, LBE_ENOCONV, buf);
+    }
+    if ((rc = mg_vcycle<T>(c, 0))) return rc;
+    rc = run(c, KK_CORRECT, [&] {
+      return launch_mg_correct<T>(c->stream, L0.lv.n, c->mask, (const T *)L0.e, c->phi);
+    });
+    if (rc) return rc;
+    ++cycles;
+  }
+  c->total_iters += cycles;
+  return LBE_OK;
+}
+
+int grow_history(lbe_ctx *c) {
+  if (c->qlen < c->qcap) return LBE_OK;
+  const int64_t cap = c->qcap ? 2 * c->qcap : 4096;
+  double *nh = nullptr;
+  int rc = dalloc(c, &nh, (size_t)cap * std::max(c->ne, 1));
+  if (rc) return rc;
+  if (c->qhist) {
+    HIPCHK(c, hipMemcpyAsync(nh, c->qhist, sizeof(double) * c->qlen * std::max(c->ne, 1),
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(c->qhist);
+  }
+  c->qhist = nh;
+  c->qcap = cap;
+  return LBE_OK;
+}
+
+// Mixed form with SOR: FP64 residual, check_every FP32 SOR sweeps on the
+// correction from zero (the same iterates as SOR on phi, accumulated in FP32),
+// then phi += e.  Counts sweeps.
+int mixed_sor_solve(lbe_ctx *c) {
+  const lbe_params &p = c->p;
+  lbe_ctx::MgDev &L0 = c->mg[0];
+  int sweeps = 0;
+  for (;;) {
+    int rc = run(c, KK_MG_RESID, [&] {
+      return launch_mg_outer_resid<float>(c->stream, L0.lv, c->mask, c->src, c->phi,
+                                          (float *)L0.r, (float *)L0.e, c->partial, c->counter,
+                                          c->dout);
+    });
+    if (rc) return rc;
+    if ((rc = read_scalars(c, 1))) return rc;
+    const double res = c->hpin[0];
+    c->last_iters = sweeps;
+    c->last_resid = res;
+    if (!isfinite(res)) {
+      c->total_iters += sweeps;
+      return fail(c, LBE_ENONFINITE, "non-finite Poisson residual");
+    }
+    if (p.tol > 0.0 && res <= p.tol) break;
+    if (sweeps >= p.max_iter) {
+      c->total_iters += sweeps;
+      if (p.tol <= 0.0) return LBE_OK;
+      char buf[160];
+      snprintf(buf, sizeof buf, "Poisson not converged: residual %.3e after %d sweeps", res, sweeps);
+      return fail(c, LBE_ENOCONV, buf);
+    }
+    const int m = std::min(p.check_every, p.max_iter - sweeps);
+    for (int s2 = 0; s2 < m; ++s2)
+      for (int col = 0; col < 4; ++col) {
+        rc = run(c, KK_SOR32, [&] {
+          return launch_mg_smooth<float>(c->stream, L0.lv, p.omega, col, c->mask,
+                                         (const float *)L0.r, (float *)L0.e);
+        });
+        if (rc) return rc;
+      }
+    rc = run(c, KK_CORRECT, [&] {
+      return launch_mg_correct<float>(c->stream, L0.lv.n, c->mask, (const float *)L0.e, c->phi);
+    });
+    if (rc) return rc;
+    sweeps += m;
+  }
+  c->total_iters += sweeps;
+  return LBE_OK;
+}
+
+int poisson_solve(lbe_ctx *c) {
+  if (c->mixed) return c->p.poisson == LBE_MG ? mg_solve<float>(c) : mixed_sor_solve(c);
+  if (c->p.poisson == LBE_MG) return mg_solve<double>(c);
+  return sor_solve(c);
+}
+
+int charges_to(lbe_ctx *c, double *dst) {
+  if (c->ne == 0) return LBE_OK;
+  if (c->nblk_charge == 0) {  // no electrode touches the fluid
+    HIPCHK(c, hipMemsetAsync(dst, 0, sizeof(double) * c->ne, c->stream));
+    return LBE_OK;
+  }
+  const double q_scale = -6.0 / (4.0 * M_PI * c->p.lB);
+  return run(c, KK_CHARGE, [&] {
+    return launch_charge(c->stream, c->L, q_scale, c->mask, c->phi, c->iface, c->blk_elec,
+                         c->blk_begin, c->blk_end, c->nblk_charge, c->ne, c->partial, c->counter,
+                         dst);
+  });
+}
+
+int record_charge(lbe_ctx *c) {
+  int rc = grow_history(c);
+  if (rc) return rc;
+  rc = charges_to(c, c->qhist + c->qlen * std::max(c->ne, 1));
+  if (rc) return rc;
+  c->qlen++;
+  return LBE_OK;
+}
+
+int one_step(lbe_ctx *c) {
+  const int a = c->cur, b = 1 - c->cur;
+  int rc = run(c, KK_FLUID, [&] {
+    if (c->mixed)
+      return launch_fluid_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[a], c->h32[a],
+                              c->h32[b], c->u32);
+    return launch_fluid_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[a], c->f[a], c->f[b],
+                            c->u);
+  });
+  if (rc) return rc;
+  rc = run(c, KK_IONS, [&] {
+    if (c->mixed)
+      return launch_ions_f32(c->stream, c->L, c->P, c->mask, c->phi, c->u32, c->nu32[a],
+                             c->nu32[b], c->src);
+    return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->phi, c->u, c->n[a], c->n[b],
+                           c->src);
+  });
+  if (rc) return rc;
+  c->cur = b;
+  c->step++;
+  rc = poisson_solve(c);
+  if (rc) return rc;
+  return record_charge(c);
+}
+
+void free_ctx(lbe_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  void *ptrs[] = {c->mask, c->phi, c->src, c->u, c->n[0], c->n[1], c->f[0], c->f[1],
+                  c->h32[0], c->h32[1], c->nu32[0], c->nu32[1], c->u32, c->obs,
+                  c->partial, c->counter, c->dout, c->iface, c->blk_elec, c->blk_begin,
+                  c->blk_end, c->qcur, c->qhist};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  for (auto &L : c->mg) {
+    if (L.own_mask && L.mask) (void)hipFree(L.mask);
+    if (L.e) (void)hipFree(L.e);
+    if (L.r) (void)hipFree(L.r);
+  }
+  if (c->hpin) (void)hipHostFree(c->hpin);
+  for (int k = 0; k < KK_COUNT; ++k)
+    for (auto &pr : c->pending[k]) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+}  // namespace
+
+// ---- public API -------------------------------------------------------------
+
+extern "C" {
+
+const char *lbe_strerror(int code) {
+  switch (code) {
+    case LBE_OK: return "ok";
+    case LBE_EINVAL: return "invalid argument";
+    case LBE_EGEOM: return "invalid geometry";
+    case LBE_ENOMEM: return "out of memory";
+    case LBE_EDEVICE: return "device error";
+    case LBE_ENOCONV: return "Poisson solve did not converge";
+    case LBE_ENONFINITE: return "non-finite value";
+    default: return "unknown error";
+  }
+}
+
+const char *lbe_last_error(const lbe_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+void lbe_velocities(int32_t *c, double *w) {
+  for (int i = 0; i < NQ; ++i) {
+    if (c) {
+      c[3 * i] = CX[i];
+      c[3 * i + 1] = CY[i];
+      c[3 * i + 2] = CZ[i];
+    }
+    if (w) w[i] = WQ[i];
+  }
+}
+
+int32_t lbe_num_kernel_kinds(void) { return KK_COUNT; }
+const char *lbe_kernel_name(int32_t kind) {
+  return (kind >= 0 && kind < KK_COUNT) ? kKernelNames[kind] : "";
+}
+
+int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
+             const double *n_init, const double *n_ref, const double *f_init, lbe_ctx **out) {
+  g_init_error.clear();
+  if (!out) return fail(nullptr, LBE_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(params);
+  if (rc) return rc;
+  if (!type || !phi_s) return fail(nullptr, LBE_EINVAL, "type and phi_s are required");
+  const lbe_params &p = *params;
+  const long N = (long)p.nx * p.ny * p.nz;
+  const int K = p.nspecies;
+  int ne = 0;
+  for (long r = 0; r < N; ++r) ne = std::max(ne, (int)type[r]);
+  if (ne > LBE_MAX_ELECTRODES) return fail(nullptr, LBE_EINVAL, "more than 64 electrodes");
+  for (long r = 0; r < N; ++r)
+    if (type[r] && !isfinite(phi_s[r]))
+      return fail(nullptr, LBE_EINVAL, "non-finite electrode potential");
+  if (!n_init && !n_ref) return fail(nullptr, LBE_EINVAL, "n_init or n_ref is required");
+  std::vector<double> n0((size_t)K * N, 0.0);
+  for (int k = 0; k < K; ++k)
+    for (long r = 0; r < N; ++r) {
+      if (type[r]) continue;
+      const double v = n_init ? n_init[(size_t)k * N + r] : n_ref[k];
+      if (!isfinite(v)) return fail(nullptr, LBE_EINVAL, "non-finite initial concentration");
+      n0[(size_t)k * N + r] = v;
+    }
+  // populations in pull form: stored_i(r - c_i) = f_i(r), or the node's own
+  // opposite slot when r - c_i is solid
+  std::vector<double> fs((size_t)NQ * N, 0.0);
+  for (long r = 0; r < N; ++r) {
+    if (type[r]) continue;
+    const int z = (int)(r / ((long)p.nx * p.ny));
+    const int rem = (int)(r - (long)z * p.nx * p.ny);
+    const int y = rem / p.nx, x = rem - y * p.nx;
+    for (int i = 0; i < NQ; ++i) {
+      const double v = f_init ? f_init[(size_t)i * N + r] : WQ[i] * p.rho0;
+      if (!isfinite(v)) return fail(nullptr, LBE_EINVAL, "non-finite initial population");
+      const long rs = wrap(x - CX[i], p.nx) + (long)p.nx * (wrap(y - CY[i], p.ny) + (long)p.ny * wrap(z - CZ[i], p.nz));
+      if (i == 0) fs[r] = v;
+      else if (type[rs]) fs[(size_t)OPP[i] * N + r] = v;
+      else fs[(size_t)i * N + rs] = v;
+    }
+  }
+  HostGeometry g;
+  rc = build_geometry(&p, type, ne, g);
+  if (rc) return rc;
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(nullptr, LBE_EDEVICE, "no HIP device");
+  lbe_ctx *c = new lbe_ctx();
+  c->p = p;
+  c->K = K;
+  c->ne = ne;
+  (void)hipGetDevice(&c->device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess ||
+      strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    std::string arch = prop.gcnArchName;
+    free_ctx(c);
+    return fail(nullptr, LBE_EDEVICE, "library is built for gfx950, device is " + arch);
+  }
+  c->L.nx = p.nx;
+  c->L.ny = p.ny;
+  c->L.nz = p.nz;
+  c->L.nxy = p.nx * p.ny;
+  c->L.n = (int)N;
+  c->L.selfm = g.selfm;
+  c->P.K = K;
+  for (int k = 0; k < K; ++k) {
+    c->P.z[k] = p.z[k];
+    c->P.dk[k] = p.D[k] / A0;
+  }
+  for (int i = 0; i < NQ; ++i)
+    c->P.Ec[i] = p.Eapp[0] * CX[i] + p.Eapp[1] * CY[i] + p.Eapp[2] * CZ[i];
+  c->P.tau = p.tau;
+  c->P.src_scale = 4.0 * M_PI * p.lB / 6.0;
+  c->P.omega = p.omega;
+  c->mixed = p.precision == LBE_FP32_MIXED;
+  c->type_h.assign(type, type + N);
+  // references of the mixed form: n_ref, else the fluid mean of n_init
+  {
+    long nfl = 0;
+    for (long r = 0; r < N; ++r) nfl += type[r] == 0;
+    double qref = 0.0;
+    for (int k = 0; k < K; ++k) {
+      double ref = 0.0;
+      if (n_ref) {
+        ref = n_ref[k];
+      } else if (nfl) {
+        for (long r = 0; r < N; ++r) ref += n0[(size_t)k * N + r];
+        ref /= (double)nfl;
+      }
+      if (!isfinite(ref)) {
+        free_ctx(c);
+        return fail(nullptr, LBE_EINVAL, "non-finite reference concentration");
+      }
+      c->P.nref_d[k] = ref;
+      c->P.nref_f[k] = (float)ref;
+      c->P.dk_f[k] = (float)c->P.dk[k];
+      qref += p.z[k] * ref;
+    }
+    c->P.qref = qref;
+    c->P.rho0_d = p.rho0;
+    c->P.rho0_f = (float)p.rho0;
+    c->P.itau_f = (float)(1.0 / p.tau);
+  }
+
+#define TRY(x)          \
+  do {                  \
+    rc = (x);           \
+    if (rc) goto fail_; \
+  } while (0)
+  if (p.stream) {
+    c->stream = (hipStream_t)p.stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      rc = fail(c, LBE_EDEVICE, "stream creation failed");
+      goto fail_;
+    }
+    c->own_stream = true;
+  }
+  {
+    const int nres = residual_blocks(c->L);
+    const int ntot = totals_blocks(c->L) * (2 + K);
+    const int npart = std::max({nres, ntot, (int)g.blk_elec.size(), 1});
+    TRY(dalloc(c, &c->mask, N));
+    TRY(dalloc(c, &c->phi, N));
+    TRY(dalloc(c, &c->src, N));
+    if (c->mixed) {
+      TRY(dalloc(c, &c->u32, 3 * N));
+      TRY(dalloc(c, &c->obs, (size_t)(NQ + 3) * N));
+      for (int s = 0; s < 2; ++s) {
+        TRY(dalloc(c, &c->nu32[s], (size_t)K * N));
+        TRY(dalloc(c, &c->h32[s], (size_t)NQ * N));
+      }
+    } else {
+      TRY(dalloc(c, &c->u, 3 * N));
+      for (int s = 0; s < 2; ++s) {
+        TRY(dalloc(c, &c->n[s], (size_t)K * N));
+        TRY(dalloc(c, &c->f[s], (size_t)NQ * N));
+      }
+    }
+    TRY(dalloc(c, &c->partial, npart));
+    TRY(dalloc(c, &c->counter, 1));
+    TRY(dalloc(c, &c->dout, 16));
+    TRY(dalloc(c, &c->iface, g.iface.size()));
+    TRY(dalloc(c, &c->blk_elec, g.blk_elec.size()));
+    TRY(dalloc(c, &c->blk_begin, g.blk_begin.size()));
+    TRY(dalloc(c, &c->blk_end, g.blk_end.size()));
+    TRY(dalloc(c, &c->qcur, std::max(ne, 1)));
+    if (hipHostMalloc((void **)&c->hpin, 64 * sizeof(double)) != hipSuccess) {
+      rc = fail(c, LBE_ENOMEM, "pinned host buffer");
+      goto fail_;
+    }
+    c->nblk_charge = (int)g.blk_elec.size();
+
+    std::vector<double> phi0(N, 0.0), src0(N, 0.0);
+    std::vector<float> nu0, h0;
+    if (c->mixed) {
+      nu0.assign((size_t)K * N, 0.f);
+      h0.assign((size_t)NQ * N, 0.f);
+      for (int k = 0; k < K; ++k)
+        for (long r = 0; r < N; ++r)
+          if (!type[r]) nu0[(size_t)k * N + r] = (float)(n0[(size_t)k * N + r] - c->P.nref_d[k]);
+      for (int i = 0; i < NQ; ++i)
+        for (long r = 0; r < N; ++r)
+          if (!type[r]) h0[(size_t)i * N + r] = (float)(fs[(size_t)i * N + r] - WQ[i] * p.rho0);
+    }
+    for (long r = 0; r < N; ++r) {
+      if (type[r]) {
+        phi0[r] = phi_s[r];
+        continue;
+      }
+      double q = 0.0;
+      if (c->mixed) {
+        q = c->P.qref;
+        for (int k = 0; k < K; ++k) q += p.z[k] * (double)nu0[(size_t)k * N + r];
+      } else {
+        for (int k = 0; k < K; ++k) q += p.z[k] * n0[(size_t)k * N + r];
+      }
+      src0[r] = c->P.src_scale * q;
+    }
+    auto up = [&](void *d, const void *h, size_t bytes) -> int {
+      if (!bytes) return LBE_OK;
+      HIPCHK(c, hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->stream));
+      return LBE_OK;
+    };
+    TRY(up(c->mask, g.mask.data(), sizeof(uint32_t) * N));
+    TRY(up(c->phi, phi0.data(), sizeof(double) * N));
+    TRY(up(c->src, src0.data(), sizeof(double) * N));
+    for (int s = 0; s < 2; ++s) {
+      if (c->mixed) {
+        TRY(up(c->nu32[s], nu0.data(), sizeof(float) * K * N));
+        TRY(up(c->h32[s], h0.data(), sizeof(float) * NQ * N));
+      } else {
+        TRY(up(c->n[s], n0.data(), sizeof(double) * K * N));
+        TRY(up(c->f[s], fs.data(), sizeof(double) * NQ * N));
+      }
+    }
+    TRY(up(c->iface, g.iface.data(), sizeof(int) * g.iface.size()));
+    TRY(up(c->blk_elec, g.blk_elec.data(), sizeof(int) * g.blk_elec.size()));
+    TRY(up(c->blk_begin, g.blk_begin.data(), sizeof(int) * g.blk_begin.size()));
+    TRY(up(c->blk_end, g.blk_end.data(), sizeof(int) * g.blk_end.size()));
+    if ((c->u && hipMemsetAsync(c->u, 0, sizeof(double) * 3 * N, c->stream) != hipSuccess) ||
+        (c->u32 && hipMemsetAsync(c->u32, 0, sizeof(float) * 3 * N, c->stream) != hipSuccess) ||
+        hipMemsetAsync(c->counter, 0, sizeof(unsigned), c->stream) != hipSuccess) {
+      rc = fail(c, LBE_EDEVICE, "memset failed");
+      goto fail_;
+    }
+    // synchronous: the host vectors go out of scope
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+      rc = fail(c, LBE_EDEVICE, "stream synchronize failed");
+      goto fail_;
+    }
+  }
+  if (p.poisson == LBE_MG || c->mixed) TRY(build_multigrid(c, type, p.poisson != LBE_MG));
+  TRY(poisson_solve(c));
+  TRY(record_charge(c));
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    rc = fail(c, LBE_EDEVICE, "stream synchronize failed");
+    goto fail_;
+  }
+#undef TRY
+  *out = c;
+  return LBE_OK;
+fail_:
+  g_init_error = c->err;
+  free_ctx(c);
+  return rc;
+}
+
+int lbe_step(lbe_ctx *c, int64_t nsteps) {
+  if (!c || nsteps < 0) return fail(c, LBE_EINVAL, "bad context or step count");
+  for (int64_t t = 0; t < nsteps; ++t) {
+    int rc = one_step(c);
+    if (rc) return rc;
+  }
+  return LBE_OK;
+}
+
+int lbe_poisson(lbe_ctx *c, int32_t *iters, double *resid) {
+  if (!c) return fail(c, LBE_EINVAL, "context is NULL");
+  int rc = poisson_solve(c);
+  if (iters) *iters = c->last_iters;
+  if (resid) *resid = c->last_resid;
+  return rc;
+}
+
+int lbe_electrode_charge(lbe_ctx *c, double *q, int32_t ne) {
+  if (!c || (!q && ne > 0)) return fail(c, LBE_EINVAL, "bad arguments");
+  if (ne < c->ne) return fail(c, LBE_EINVAL, "q has room for fewer values than electrodes");
+  if (c->ne == 0) return LBE_OK;
+  int rc = charges_to(c, c->qcur);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(q, c->qcur, sizeof(double) * c->ne, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBE_OK;
+}
+
+int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double *u, double *f,
+                    double *q_hist, int64_t q_hist_cap, int64_t *q_hist_len) {
+  if (!c) return fail(c, LBE_EINVAL, "context is NULL");
+  const long N = c->L.n;
+  const int K = c->K;
+  int rc;
+  if (totals) {
+    rc = run(c, KK_TOTALS, [&] {
+      if (c->mixed)
+        return launch_totals_f32(c->stream, c->L, c->P, c->mask, c->h32[c->cur], c->nu32[c->cur],
+                                 c->partial, c->counter, c->dout);
+      return launch_totals_f64(c->stream, c->L, K, c->p.z, c->mask, c->f[c->cur], c->n[c->cur],
+                               c->partial, c->counter, c->dout);
+    });
+    if (rc) return rc;
+    rc = read_scalars(c, 2 + K);
+    if (rc) return rc;
+    memset(totals, 0, sizeof *totals);
+    totals->step = c->step;
+    totals->nelectrodes = c->ne;
+    totals->poisson_iters = c->last_iters;
+    totals->poisson_resid = c->last_resid;
+    totals->mass = c->hpin[0];
+    totals->q_ion = c->hpin[1];
+    for (int k = 0; k < K; ++k) totals->nk[k] = c->hpin[2 + k];
+    totals->poisson_total = c->total_iters;
+  }
+  if (u || f) {
+    // FP64 form: the next step's output buffers are free between steps
+    double *fpre = c->mixed ? c->obs : c->f[1 - c->cur];
+    double *uo = c->mixed ? c->obs + (size_t)NQ * N : c->u;
+    rc = run(c, KK_OBSERVE, [&] {
+      if (c->mixed)
+        return launch_observe_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[c->cur],
+                                  c->h32[c->cur], fpre, uo);
+      return launch_observe_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[c->cur],
+                                c->f[c->cur], fpre, uo);
+    });
+    if (rc) return rc;
+    if (f) HIPCHK(c, hipMemcpyAsync(f, fpre, sizeof(double) * NQ * N, hipMemcpyDeviceToHost, c->stream));
+    if (u) HIPCHK(c, hipMemcpyAsync(u, uo, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c->stream));
+  }
+  if (phi) HIPCHK(c, hipMemcpyAsync(phi, c->phi, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
+  std::vector<float> nu_h;
+  if (n) {
+    if (c->mixed) {
+      nu_h.resize((size_t)K * N);
+      HIPCHK(c, hipMemcpyAsync(nu_h.data(), c->nu32[c->cur], sizeof(float) * K * N,
+                               hipMemcpyDeviceToHost, c->stream));
+    } else {
+      HIPCHK(c, hipMemcpyAsync(n, c->n[c->cur], sizeof(double) * K * N, hipMemcpyDeviceToHost, c->stream));
+    }
+  }
+  if (q_hist && q_hist_cap > 0 && c->ne > 0) {
+    const int64_t rows = std::min(q_hist_cap, c->qlen);
+    HIPCHK(c, hipMemcpyAsync(q_hist, c->qhist, sizeof(double) * rows * c->ne, hipMemcpyDeviceToHost,
+                             c->stream));
+  }
+  if (q_hist_len) *q_hist_len = c->qlen;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (n && c->mixed)
+    for (int k = 0; k < K; ++k)
+      for (long r = 0; r < N; ++r)
+        n[(size_t)k * N + r] = c->type_h[r] ? 0.0 : c->P.nref_d[k] + (double)nu_h[(size_t)k * N + r];
+  return LBE_OK;
+}
+
+void lbe_destroy(lbe_ctx *c) { free_ctx(c); }
+
+int lbe_profile(lbe_ctx *c, int enable) {
+  if (!c) return fail(c, LBE_EINVAL, "context is NULL");
+  int rc = flush_profile(c);
+  if (rc) return rc;
+  for (int k = 0; k < KK_COUNT; ++k) {
+    c->ms[k] = 0.0;
+    c->launches[k] = 0;
+  }
+  c->prof = enable != 0;
+  return LBE_OK;
+}
+
+int lbe_kernel_times(lbe_ctx *c, double *ms, int64_t *launches, int32_t nkinds) {
+  if (!c) return fail(c, LBE_EINVAL, "context is NULL");
+  int rc = flush_profile(c);
+  if (rc) return rc;
+  for (int k = 0; k < nkinds && k < KK_COUNT; ++k) {
+    if (ms) ms[k] = c->ms[k];
+    if (launches) launches[k] = c->launches[k];
+  }
+  return LBE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// lbe_internal.h -- declarations shared by the host driver and the HIP
+// kernels of the LBE library (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbe {
+
+// D3Q19 (Sec. II B of arXiv:1907.04732) in the order documented in lbe.h.
+constexpr int NQ = 19;
+constexpr int CX[NQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+// opposite direction: pairs (1,2), (3,4), ... (17,18)
+constexpr int OPP[NQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+constexpr double W0 = 1.0 / 3.0, W1 = 1.0 / 18.0, W2 = 1.0 / 36.0;
+constexpr double WQ[NQ] = {W0, W1, W1, W1, W1, W1, W1, W2, W2, W2, W2,
+                           W2, W2, W2, W2, W2, W2, W2, W2};
+constexpr double SQRT2 = 1.4142135623730951;
+// link length |c_i| (Delta_i of Eq. 10)
+constexpr double LEN[NQ] = {0.0, 1, 1, 1, 1, 1, 1, SQRT2, SQRT2, SQRT2, SQRT2,
+                            SQRT2, SQRT2, SQRT2, SQRT2, SQRT2, SQRT2, SQRT2, SQRT2};
+// lattice factor A0 = 1 + 2 sqrt(2) of Eq. 9 (D3Q19)
+constexpr double A0 = 1.0 + 2.0 * SQRT2;
+
+// Per-node flag word: bit (i-1), i = 1..18, set when the neighbour r + c_i
+// is solid; bit 31 set when the node itself is solid.
+constexpr uint32_t SOLID_BIT = 1u << 31;
+
+struct Lattice {
+  int nx, ny, nz;
+  int nxy;
+  int n;            // sites
+  uint32_t selfm;   // bit (i-1) set when link i maps a node onto itself
+};
+
+// Physical constants of one context, passed by value to the kernels.
+struct Phys {
+  int K;                 // species
+  int z[4];
+  double dk[4];          // D_k / A0
+  double Ec[NQ];         // E_app . c_i
+  double tau;
+  double src_scale;      // 4 pi l_B / 6
+  double omega;
+  // mixed form: references of the deviation storage
+  double rho0_d;         // rest density rho0
+  double nref_d[4];      // n_ref,k
+  double qref;           // sum_k z_k n_ref,k
+  float rho0_f, itau_f;
+  float nref_f[4], dk_f[4];
+};
+
+// One multigrid level (cell-centred; spacing h = 2^level in fine units).
+struct MgLevel {
+  int nx, ny, nz, nxy, n;
+  uint32_t selfm;
+  double h2, inv_h2;
+};
+
+// Fine level f -> coarse level c: coarse cell (X, Y, Z) holds the fine cells
+// whose shifted indices ((x - ox) mod nx, ...) are (2X or 2X+1, ...).
+struct MgTransfer {
+  MgLevel f, c;
+  int ox, oy, oz;
+};
+
+enum KernelKind {
+  KK_FLUID = 0,   // force + LB collide/stream (pull), writes u
+  KK_IONS,        // ion link fluxes + update, writes Poisson source
+  KK_SOR,         // one colour of the FP64 SOR sweep
+  KK_RESID,       // FP64 residual inf-norm
+  KK_CHARGE,      // electrode charges
+  KK_TOTALS,      // conserved totals
+  KK_OBSERVE,     // pre-collision populations and velocity
+  KK_SOR32,       // one colour of the FP32 correction sweep
+  KK_CORRECT,     // phi += e
+  KK_MG_RESID,    // outer FP64 residual feeding the multigrid correction
+  KK_MG_SMOOTH,   // one colour of the level smoother
+  KK_MG_RESTRICT, // residual + restriction to the next level
+  KK_MG_PROLONG,  // trilinear prolongation + correction
+  KK_MG_COARSE,   // coarsest-level solve in one work-group
+  KK_COUNT
+};
+
+extern const char *const kKernelNames[KK_COUNT];
+
+// ---- launchers (lbe_kernels.hip) -----------------------------------------
+// All take the stream; they return hipSuccess or the launch error.
+hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                            const double *phi, const double *n, const double *fin, double *fout,
+                            double *u);
+hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                           const double *phi, const double *u, const double *n, double *nout,
+                           double *src);
+hipError_t launch_sor_f64(hipStream_t s, const Lattice &L, const Phys &P, int colour,
+                          const uint32_t *mask, const double *src, double *phi);
+// residual inf-norm over fluid nodes into *out (device); partial/counter are
+// scratch of size >= residual_blocks(L) and 1
+int residual_blocks(const Lattice &L);
+hipError_t launch_resid_f64(hipStream_t s, const Lattice &L, const uint32_t *mask,
+                            const double *src, const double *phi, double *partial,
+                            unsigned *counter, double *out);
+hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
+                         const double *phi, const int *iface_site, const int *blk_elec,
+                         const int *blk_begin, const int *blk_end, int nblocks, int ne,
+                         double *partial, unsigned *counter, double *out);
+hipError_t launch_totals_f64(hipStream_t s, const Lattice &L, int K, const int *z,
+                             const uint32_t *mask, const double *fin, const double *n,
+                             double *partial, unsigned *counter, double *out /*2+K*/);
+hipError_t launch_observe_f64(hipStream_t s, const Lattice &L, const Phys &P,
+                              const uint32_t *mask, const double *phi, const double *n,
+                              const double *fin, double *fpre, double *u);
+int totals_blocks(const Lattice &L);
+
+// mixed form (lbe_kernels_f32.hip): h = f - w rho0 and nu = n - n_ref in FP32
+hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                            const double *phi, const float *nu, const float *hin, float *hout,
+                            float *u);
+hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                           const double *phi, const float *u, const float *nu, float *nuout,
+                           double *src);
+hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
+                              const uint32_t *mask, const double *phi, const float *nu,
+                              const float *hin, double *fpre, double *u);
+hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                             const float *hin, const float *nu, double *partial,
+                             unsigned *counter, double *out);
+
+// multigrid (lbe_mg.hip); T = double (FP64 form) or float (mixed form)
+template <class T>
+hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
+                                 const double *src, const double *phi, T *r0, T *e0,
+                                 double *partial, unsigned *counter, double *out);
+template <class T>
+hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int colour,
+                            const uint32_t *mask, const T *rhs, T *e);
+template <class T>
+hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
+                              const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec);
+template <class T>
+hipError_t launch_mg_prolong(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
+                             const uint32_t *mc, const T *ec, T *ef);
+template <class T>
+hipError_t launch_mg_coarse(hipStream_t s, const MgLevel &lv, double omega, int sweeps,
+                            const uint32_t *mask, const T *rhs, T *e);
+template <class T>
+hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T *e, double *phi);
+
+}  // namespace lbe

@@ -1,0 +1,478 @@
+// lbe_kernels.hip -- HIP kernels (gfx950) of one Lattice Boltzmann
+// Electrokinetics time step with metallic electrodes (arXiv:1907.04732).
+//
+// Data layout in HBM: structure of arrays, site r = x + nx*(y + ny*z), one
+// array per population / species / component.  Populations are kept in the
+// "pull" form: the array holds post-collision values at the node they left,
+// and a step gathers f_i(r) from r - c_i (or from the node's own opposite
+// population when r - c_i is solid: halfway bounce-back), collides, and
+// writes the result back at r.  Every kernel is one thread per site with
+// consecutive threads on consecutive x, so each of the 19 population
+// streams and each neighbour read is a contiguous, coalesced access.
+//
+// FP64 kernels.  All reductions are deterministic: block trees followed by a
+// fixed-order combination in the last block to finish.
+#include <math.h>
+
+#include "lbe_device.h"
+#include "lbe_internal.h"
+
+namespace lbe {
+
+const char *const kKernelNames[KK_COUNT] = {
+    "fluid", "ions", "sor", "resid", "charge", "totals", "observe", "sor32", "correct",
+    "mg_resid", "mg_smooth", "mg_restrict", "mg_prolong", "mg_coarse"};
+
+namespace {
+
+// ---- force on the fluid (reading: excess part of the link flux, Eq. 10,
+// projected on the node; Eq. 3 force e rho_el (-grad psi + E_app)) ---------
+
+template <int K>
+__device__ __forceinline__ void link_force(const Lattice &L, const Phys &P, int r, uint32_t m,
+                                           const Offs &o, const double *__restrict__ phi,
+                                           const double *__restrict__ n, double ph,
+                                           const double (&nr)[K], double &F0, double &F1,
+                                           double &F2) {
+  const int N = L.n;
+  F0 = F1 = F2 = 0.0;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;
+    const int rn = nbr(o, r, i);
+    const double dphi = phi[rn] - ph - P.Ec[i];
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      g += excess_link(nr[k], n[k * N + rn], P.z[k] * dphi, 0.5 / LEN[i]);
+    const double c = 3.0 * WQ[i] * LEN[i] * g;
+    if (CX[i]) F0 += CX[i] * c;
+    if (CY[i]) F1 += CY[i] * c;
+    if (CZ[i]) F2 += CZ[i] * c;
+  }
+}
+
+// gather pre-collision populations (streaming with halfway bounce-back)
+__device__ __forceinline__ void pull(const Lattice &L, int r, uint32_t m, const Offs &o,
+                                     const double *__restrict__ fin, double (&f)[NQ]) {
+  const int N = L.n;
+  f[0] = fin[r];
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    const int j = OPP[i];
+    f[i] = solid_link(m, j) ? fin[j * N + r] : fin[i * N + nbr(o, r, j)];
+  }
+}
+
+// ---- pass A: force, moments, BGK + Guo forcing, write post-collision f and u
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_fluid_f64(Lattice L, Phys P,
+                                                     const uint32_t *__restrict__ mask,
+                                                     const double *__restrict__ phi,
+                                                     const double *__restrict__ n,
+                                                     const double *__restrict__ fin,
+                                                     double *__restrict__ fout,
+                                                     double *__restrict__ u) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) return;
+  const int N = L.n;
+  Offs o;
+  site_offsets(L, r, o);
+  const double ph = phi[r];
+  double nr[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) nr[k] = n[k * N + r];
+  double F0, F1, F2;
+  link_force<K>(L, P, r, m, o, phi, n, ph, nr, F0, F1, F2);
+
+  double f[NQ];
+  pull(L, r, m, o, fin, f);
+  double rho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    rho += f[i];
+    if (CX[i]) m0 += CX[i] * f[i];
+    if (CY[i]) m1 += CY[i] * f[i];
+    if (CZ[i]) m2 += CZ[i] * f[i];
+  }
+  // Guo forcing: velocity with the half-force shift
+  const double ux = (m0 + 0.5 * F0) / rho;
+  const double uy = (m1 + 0.5 * F1) / rho;
+  const double uz = (m2 + 0.5 * F2) / rho;
+  const double uu = ux * ux + uy * uy + uz * uz;
+  const double itau = 1.0 / P.tau;
+  const double guo = 1.0 - 0.5 * itau;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+    const double feq = WQ[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    const double s = ((3.0 * (CX[i] - ux) + 9.0 * cu * CX[i]) * F0 +
+                      (3.0 * (CY[i] - uy) + 9.0 * cu * CY[i]) * F1 +
+                      (3.0 * (CZ[i] - uz) + 9.0 * cu * CZ[i]) * F2) *
+                     (guo * WQ[i]);
+    fout[i * N + r] = f[i] - (f[i] - feq) * itau + s;
+  }
+  u[r] = ux;
+  u[N + r] = uy;
+  u[2 * N + r] = uz;
+}
+
+// ---- pass B: ion link fluxes (Eqs. 9-10) + advection, new Poisson source --
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_ions_f64(Lattice L, Phys P,
+                                                    const uint32_t *__restrict__ mask,
+                                                    const double *__restrict__ phi,
+                                                    const double *__restrict__ u,
+                                                    const double *__restrict__ n,
+                                                    double *__restrict__ nout,
+                                                    double *__restrict__ src) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) return;
+  const int N = L.n;
+  Offs o;
+  site_offsets(L, r, o);
+  const double ph = phi[r];
+  const double ux = u[r], uy = u[N + r], uz = u[2 * N + r];
+  double nr[K], acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    nr[k] = n[k * N + r];
+    acc[k] = 0.0;
+  }
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;  // no flux into an electrode
+    const int rn = nbr(o, r, i);
+    const double dphi = phi[rn] - ph - P.Ec[i];
+    double cu_h = 0.0, cu_t = 0.0;
+    if (CX[i]) { cu_h += CX[i] * ux; cu_t += CX[i] * u[rn]; }
+    if (CY[i]) { cu_h += CY[i] * uy; cu_t += CY[i] * u[N + rn]; }
+    if (CZ[i]) { cu_h += CZ[i] * uz; cu_t += CZ[i] * u[2 * N + rn]; }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double nn = n[k * N + rn];
+      const double g = excess_link(nr[k], nn, P.z[k] * dphi, 0.5 / LEN[i]);
+      const double j = P.dk[k] * (g - (nn - nr[k]) / LEN[i]);
+      const double J = 3.0 * WQ[i] * (nr[k] * cu_h + nn * cu_t);
+      acc[k] += j + J;
+    }
+  }
+  double q = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double v = nr[k] - acc[k];
+    nout[k * N + r] = v;
+    q += P.z[k] * v;
+  }
+  src[r] = P.src_scale * q;
+}
+
+// ---- Poisson: one colour of the four-colour SOR sweep (Eqs. 13, 15) --------
+// colour(x, y, z) = ((x + z) & 1) + 2 ((y + z) & 1); no two D3Q19 neighbours
+// share a colour, so a colour's nodes update independently.
+
+__global__ __launch_bounds__(BLOCK) void k_sor_f64(Lattice L, double omega, int colour, int hx,
+                                                   int hy, const uint32_t *__restrict__ mask,
+                                                   const double *__restrict__ src,
+                                                   double *__restrict__ phi) {
+  const int t = blockIdx.x * BLOCK + threadIdx.x;
+  const int plane = hx * hy;
+  if (t >= plane * L.nz) return;
+  const int z = t / plane;
+  const int rem = t - z * plane;
+  const int iy = rem / hx;
+  const int ix = rem - iy * hx;
+  const int x = 2 * ix + ((colour ^ z) & 1);
+  const int y = 2 * iy + (((colour >> 1) ^ z) & 1);
+  if (x >= L.nx || y >= L.ny) return;
+  const int r = x + L.nx * (y + L.ny * z);
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) return;
+  Offs o;
+  site_offsets(L, r, o);
+  double num = 0.0, den = 0.0;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if ((L.selfm >> (i - 1)) & 1u) continue;
+    const double ws = solid_link(m, i) ? 2.0 * WQ[i] : WQ[i];
+    num += ws * phi[nbr(o, r, i)];
+    den += ws;
+  }
+  num += src[r];
+  phi[r] = (1.0 - omega) * phi[r] + omega * (num / den);
+}
+
+// residual R = L_h phi + 4 pi l_B rho_el = 6 [sum_i w_i s_i (phi' - phi) + src]
+__global__ __launch_bounds__(BLOCK) void k_resid_f64(Lattice L, const uint32_t *__restrict__ mask,
+                                                     const double *__restrict__ src,
+                                                     const double *__restrict__ phi,
+                                                     double *__restrict__ partial,
+                                                     unsigned *__restrict__ counter,
+                                                     double *__restrict__ out) {
+  __shared__ double sm[BLOCK / WAVE];
+  __shared__ double tree[BLOCK];
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  double a = 0.0;
+  if (r < L.n) {
+    const uint32_t m = mask[r];
+    if (!(m & SOLID_BIT)) {
+      Offs o;
+      site_offsets(L, r, o);
+      const double ph = phi[r];
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 1; i < NQ; ++i) {
+        if ((L.selfm >> (i - 1)) & 1u) continue;
+        const double ws = solid_link(m, i) ? 2.0 * WQ[i] : WQ[i];
+        acc += ws * (phi[nbr(o, r, i)] - ph);
+      }
+      a = fabs(6.0 * (acc + src[r]));
+    }
+  }
+  a = block_max(a, sm);
+  if (threadIdx.x == 0) partial[blockIdx.x] = a;
+  if (arrive_last(counter)) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) v = nanmax(v, partial[b]);
+    tree[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) tree[threadIdx.x] = nanmax(tree[threadIdx.x], tree[threadIdx.x + s]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      out[0] = tree[0];
+      atomicExch(counter, 0u);
+    }
+  }
+}
+
+// ---- electrode charge (Eq. 16): Q_e = -(6/4 pi l_B) sum over the electrode's
+// interface nodes of sum_{fluid links} 2 w_i (phi' - phi_s) ----------------
+
+__global__ __launch_bounds__(BLOCK) void k_charge(Lattice L, double q_scale,
+                                                  const uint32_t *__restrict__ mask,
+                                                  const double *__restrict__ phi,
+                                                  const int *__restrict__ iface_site,
+                                                  const int *__restrict__ blk_elec,
+                                                  const int *__restrict__ blk_begin,
+                                                  const int *__restrict__ blk_end, int ne,
+                                                  double *__restrict__ partial,
+                                                  unsigned *__restrict__ counter,
+                                                  double *__restrict__ out) {
+  __shared__ double sm[BLOCK / WAVE];
+  const int b = blockIdx.x;
+  const int idx = blk_begin[b] + threadIdx.x;
+  double v = 0.0;
+  if (idx < blk_end[b]) {
+    const int r = iface_site[idx];
+    const uint32_t m = mask[r];
+    Offs o;
+    site_offsets(L, r, o);
+    const double ps = phi[r];
+    double lap = 0.0;
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      if (solid_link(m, i)) continue;
+      lap += WQ[i] * 2.0 * (phi[nbr(o, r, i)] - ps);
+    }
+    v = q_scale * lap;
+  }
+  v = block_sum(v, sm);
+  if (threadIdx.x == 0) partial[b] = v;
+  if (arrive_last(counter)) {
+    // per electrode, Neumaier-compensated sum of its blocks in block order
+    for (int e = threadIdx.x; e < ne; e += BLOCK) {
+      double s = 0.0, c = 0.0;
+      for (int k = 0; k < (int)gridDim.x; ++k) {
+        if (blk_elec[k] != e) continue;
+        const double x = partial[k];
+        const double t = s + x;
+        c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+        s = t;
+      }
+      out[e] = s + c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
+  }
+}
+
+// ---- conserved totals: mass, ionic charge, species amounts ------------------
+
+__global__ __launch_bounds__(BLOCK) void k_totals_f64(Lattice L, int K, int4 zk,
+                                                      const uint32_t *__restrict__ mask,
+                                                      const double *__restrict__ fin,
+                                                      const double *__restrict__ n,
+                                                      double *__restrict__ partial,
+                                                      unsigned *__restrict__ counter,
+                                                      double *__restrict__ out) {
+  __shared__ double sm[BLOCK / WAVE];
+  __shared__ double tree[BLOCK];
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int N = L.n;
+  const int nq = 2 + K;
+  const int zz[4] = {zk.x, zk.y, zk.z, zk.w};
+  bool fluid = r < N && !(mask[r] & SOLID_BIT);
+  for (int q = 0; q < nq; ++q) {
+    double v = 0.0;
+    if (fluid) {
+      if (q == 0) {
+        for (int i = 0; i < NQ; ++i) v += fin[i * N + r];
+      } else if (q == 1) {
+        for (int k = 0; k < K; ++k) v += zz[k] * n[k * N + r];
+      } else {
+        v = n[(q - 2) * N + r];
+      }
+    }
+    v = block_sum(v, sm);
+    if (threadIdx.x == 0) partial[q * gridDim.x + blockIdx.x] = v;
+  }
+  if (arrive_last(counter)) {
+    for (int q = 0; q < nq; ++q) {
+      double v = 0.0;
+      for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) v += partial[q * gridDim.x + b];
+      tree[threadIdx.x] = v;
+      __syncthreads();
+      for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) out[q] = tree[0];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
+  }
+}
+
+// ---- observables: pre-collision populations and the Guo velocity ----------
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_observe_f64(Lattice L, Phys P,
+                                                       const uint32_t *__restrict__ mask,
+                                                       const double *__restrict__ phi,
+                                                       const double *__restrict__ n,
+                                                       const double *__restrict__ fin,
+                                                       double *__restrict__ fpre,
+                                                       double *__restrict__ u) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const int N = L.n;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) {
+    for (int i = 0; i < NQ; ++i) fpre[i * N + r] = 0.0;
+    u[r] = u[N + r] = u[2 * N + r] = 0.0;
+    return;
+  }
+  Offs o;
+  site_offsets(L, r, o);
+  const double ph = phi[r];
+  double nr[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) nr[k] = n[k * N + r];
+  double F0, F1, F2;
+  link_force<K>(L, P, r, m, o, phi, n, ph, nr, F0, F1, F2);
+  double f[NQ];
+  pull(L, r, m, o, fin, f);
+  double rho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    fpre[i * N + r] = f[i];
+    rho += f[i];
+    if (CX[i]) m0 += CX[i] * f[i];
+    if (CY[i]) m1 += CY[i] * f[i];
+    if (CZ[i]) m2 += CZ[i] * f[i];
+  }
+  u[r] = (m0 + 0.5 * F0) / rho;
+  u[N + r] = (m1 + 0.5 * F1) / rho;
+  u[2 * N + r] = (m2 + 0.5 * F2) / rho;
+}
+
+}  // namespace
+
+// ---- launchers ------------------------------------------------------------
+
+#define LBE_DISPATCH_K(K, CALL)                 \
+  switch (K) {                                  \
+    case 1: CALL(1); break;                     \
+    case 2: CALL(2); break;                     \
+    case 3: CALL(3); break;                     \
+    default: CALL(4); break;                    \
+  }
+
+hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                            const double *phi, const double *n, const double *fin, double *fout,
+                            double *u) {
+#define CALL(KK) \
+  hipLaunchKernelGGL(k_fluid_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, n, fin, fout, u)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                           const double *phi, const double *u, const double *n, double *nout,
+                           double *src) {
+#define CALL(KK) \
+  hipLaunchKernelGGL(k_ions_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, u, n, nout, src)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_sor_f64(hipStream_t s, const Lattice &L, const Phys &P, int colour,
+                          const uint32_t *mask, const double *src, double *phi) {
+  const int hx = (L.nx + 1) / 2, hy = (L.ny + 1) / 2;
+  const long threads = (long)hx * hy * L.nz;
+  hipLaunchKernelGGL(k_sor_f64, dim3(blocks_for(threads)), dim3(BLOCK), 0, s, L, P.omega, colour,
+                     hx, hy, mask, src, phi);
+  return hipGetLastError();
+}
+
+int residual_blocks(const Lattice &L) { return (int)blocks_for(L.n); }
+int totals_blocks(const Lattice &L) { return (int)blocks_for(L.n); }
+
+hipError_t launch_resid_f64(hipStream_t s, const Lattice &L, const uint32_t *mask,
+                            const double *src, const double *phi, double *partial,
+                            unsigned *counter, double *out) {
+  hipLaunchKernelGGL(k_resid_f64, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, mask, src, phi,
+                     partial, counter, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
+                         const double *phi, const int *iface_site, const int *blk_elec,
+                         const int *blk_begin, const int *blk_end, int nblocks, int ne,
+                         double *partial, unsigned *counter, double *out) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_charge, dim3(nblocks), dim3(BLOCK), 0, s, L, q_scale, mask, phi,
+                     iface_site, blk_elec, blk_begin, blk_end, ne, partial, counter, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_totals_f64(hipStream_t s, const Lattice &L, int K, const int *z,
+                             const uint32_t *mask, const double *fin, const double *n,
+                             double *partial, unsigned *counter, double *out) {
+  int4 zk = make_int4(z[0], K > 1 ? z[1] : 0, K > 2 ? z[2] : 0, K > 3 ? z[3] : 0);
+  hipLaunchKernelGGL(k_totals_f64, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, K, zk, mask, fin,
+                     n, partial, counter, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_observe_f64(hipStream_t s, const Lattice &L, const Phys &P,
+                              const uint32_t *mask, const double *phi, const double *n,
+                              const double *fin, double *fpre, double *u) {
+#define CALL(KK) \
+  hipLaunchKernelGGL(k_observe_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, n, fin, fpre, u)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+}  // namespace lbe

@@ -1,0 +1,309 @@
+// lbe_kernels_f32.hip -- the mixed-precision form of the LBE step (gfx950).
+//
+// Populations are stored and collided in FP32 as deviations from the rest
+// state, h_i = f_i - w_i rho0, and concentrations as deviations from a
+// reference, nu_k = n_k - n_ref,k: the physical signals (|u| ~ 1e-4, charge
+// densities ~ 1e-3 n_ref) then keep FP32's relative precision instead of
+// being rounded against the O(1) background.  The potential stays FP64: it is
+// read once per step, and the differences phi' - phi that drive migration
+// (~1e-3 of phi) are taken in FP64 before rounding.  The Poisson source
+// (4 pi l_B / 6) rho_el is accumulated in FP64 from the FP32 deviations.
+// Same layout and pull-form streaming as the FP64 kernels (lbe_kernels.hip).
+#include <math.h>
+
+#include "lbe_device.h"
+#include "lbe_internal.h"
+
+namespace lbe {
+namespace {
+
+__device__ __forceinline__ float excess_link_f(float nh, float nt, float delta, float inv2len) {
+  return -(nt * expm1f(delta) - nh * expm1f(-delta)) * inv2len;
+}
+
+template <int K>
+__device__ __forceinline__ void link_force_f32(const Lattice &L, const Phys &P, int r, uint32_t m,
+                                               const Offs &o, const double *__restrict__ phi,
+                                               const float *__restrict__ nu, double ph,
+                                               const float (&nr)[K], float &F0, float &F1,
+                                               float &F2) {
+  const int N = L.n;
+  F0 = F1 = F2 = 0.f;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;
+    const int rn = nbr(o, r, i);
+    const double dphi = phi[rn] - ph - P.Ec[i];
+    float g = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      g += excess_link_f(nr[k], P.nref_f[k] + nu[k * N + rn], float(P.z[k] * dphi),
+                         float(0.5 / LEN[i]));
+    const float c = float(3.0 * WQ[i] * LEN[i]) * g;
+    if (CX[i]) F0 += CX[i] * c;
+    if (CY[i]) F1 += CY[i] * c;
+    if (CZ[i]) F2 += CZ[i] * c;
+  }
+}
+
+__device__ __forceinline__ void pull_f32(const Lattice &L, int r, uint32_t m, const Offs &o,
+                                         const float *__restrict__ hin, float (&h)[NQ]) {
+  const int N = L.n;
+  h[0] = hin[r];
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    const int j = OPP[i];
+    h[i] = solid_link(m, j) ? hin[j * N + r] : hin[i * N + nbr(o, r, j)];
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_fluid_f32(Lattice L, Phys P,
+                                                     const uint32_t *__restrict__ mask,
+                                                     const double *__restrict__ phi,
+                                                     const float *__restrict__ nu,
+                                                     const float *__restrict__ hin,
+                                                     float *__restrict__ hout,
+                                                     float *__restrict__ u) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) return;
+  const int N = L.n;
+  Offs o;
+  site_offsets(L, r, o);
+  const double ph = phi[r];
+  float nr[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) nr[k] = P.nref_f[k] + nu[k * N + r];
+  float F0, F1, F2;
+  link_force_f32<K>(L, P, r, m, o, phi, nu, ph, nr, F0, F1, F2);
+
+  float h[NQ];
+  pull_f32(L, r, m, o, hin, h);
+  float drho = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    drho += h[i];
+    if (CX[i]) m0 += CX[i] * h[i];
+    if (CY[i]) m1 += CY[i] * h[i];
+    if (CZ[i]) m2 += CZ[i] * h[i];
+  }
+  // sum_i w_i rho0 c_i = 0, so the momentum is carried by the deviations
+  const float rho = P.rho0_f + drho;
+  const float ux = (m0 + 0.5f * F0) / rho;
+  const float uy = (m1 + 0.5f * F1) / rho;
+  const float uz = (m2 + 0.5f * F2) / rho;
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float itau = P.itau_f;
+  const float guo = 1.f - 0.5f * itau;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const float w = float(WQ[i]);
+    const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+    // equilibrium minus the rest state w_i rho0
+    const float heq = w * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+    const float s = ((3.f * (CX[i] - ux) + 9.f * cu * CX[i]) * F0 +
+                     (3.f * (CY[i] - uy) + 9.f * cu * CY[i]) * F1 +
+                     (3.f * (CZ[i] - uz) + 9.f * cu * CZ[i]) * F2) *
+                    (guo * w);
+    hout[i * N + r] = h[i] - (h[i] - heq) * itau + s;
+  }
+  u[r] = ux;
+  u[N + r] = uy;
+  u[2 * N + r] = uz;
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_ions_f32(Lattice L, Phys P,
+                                                    const uint32_t *__restrict__ mask,
+                                                    const double *__restrict__ phi,
+                                                    const float *__restrict__ u,
+                                                    const float *__restrict__ nu,
+                                                    float *__restrict__ nuout,
+                                                    double *__restrict__ src) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) return;
+  const int N = L.n;
+  Offs o;
+  site_offsets(L, r, o);
+  const double ph = phi[r];
+  const float ux = u[r], uy = u[N + r], uz = u[2 * N + r];
+  float dv[K], nr[K], acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    dv[k] = nu[k * N + r];
+    nr[k] = P.nref_f[k] + dv[k];
+    acc[k] = 0.f;
+  }
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;
+    const int rn = nbr(o, r, i);
+    const double dphi = phi[rn] - ph - P.Ec[i];
+    float cu_h = 0.f, cu_t = 0.f;
+    if (CX[i]) { cu_h += CX[i] * ux; cu_t += CX[i] * u[rn]; }
+    if (CY[i]) { cu_h += CY[i] * uy; cu_t += CY[i] * u[N + rn]; }
+    if (CZ[i]) { cu_h += CZ[i] * uz; cu_t += CZ[i] * u[2 * N + rn]; }
+    const float w3 = float(3.0 * WQ[i]);
+    const float il = float(1.0 / LEN[i]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float dn = nu[k * N + rn];
+      const float nn = P.nref_f[k] + dn;
+      const float g = excess_link_f(nr[k], nn, float(P.z[k] * dphi), float(0.5 / LEN[i]));
+      // the ideal part uses the deviations directly: (n' - n) = (nu' - nu)
+      const float j = P.dk_f[k] * (g - (dn - dv[k]) * il);
+      const float J = w3 * (nr[k] * cu_h + nn * cu_t);
+      acc[k] += j + J;
+    }
+  }
+  double q = P.qref;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float v = dv[k] - acc[k];
+    nuout[k * N + r] = v;
+    q += P.z[k] * double(v);
+  }
+  src[r] = P.src_scale * q;
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_observe_f32(Lattice L, Phys P,
+                                                       const uint32_t *__restrict__ mask,
+                                                       const double *__restrict__ phi,
+                                                       const float *__restrict__ nu,
+                                                       const float *__restrict__ hin,
+                                                       double *__restrict__ fpre,
+                                                       double *__restrict__ u) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const int N = L.n;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) {
+    for (int i = 0; i < NQ; ++i) fpre[i * N + r] = 0.0;
+    u[r] = u[N + r] = u[2 * N + r] = 0.0;
+    return;
+  }
+  Offs o;
+  site_offsets(L, r, o);
+  const double ph = phi[r];
+  float nr[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) nr[k] = P.nref_f[k] + nu[k * N + r];
+  float F0, F1, F2;
+  link_force_f32<K>(L, P, r, m, o, phi, nu, ph, nr, F0, F1, F2);
+  float h[NQ];
+  pull_f32(L, r, m, o, hin, h);
+  double drho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    fpre[i * N + r] = WQ[i] * P.rho0_d + double(h[i]);
+    drho += h[i];
+    if (CX[i]) m0 += CX[i] * double(h[i]);
+    if (CY[i]) m1 += CY[i] * double(h[i]);
+    if (CZ[i]) m2 += CZ[i] * double(h[i]);
+  }
+  const double rho = P.rho0_d + drho;
+  u[r] = (m0 + 0.5 * F0) / rho;
+  u[N + r] = (m1 + 0.5 * F1) / rho;
+  u[2 * N + r] = (m2 + 0.5 * F2) / rho;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_totals_f32(Lattice L, Phys P,
+                                                      const uint32_t *__restrict__ mask,
+                                                      const float *__restrict__ hin,
+                                                      const float *__restrict__ nu,
+                                                      double *__restrict__ partial,
+                                                      unsigned *__restrict__ counter,
+                                                      double *__restrict__ out) {
+  __shared__ double sm[BLOCK / WAVE];
+  __shared__ double tree[BLOCK];
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int N = L.n;
+  const int K = P.K;
+  const int nq = 2 + K;
+  const bool fluid = r < N && !(mask[r] & SOLID_BIT);
+  for (int q = 0; q < nq; ++q) {
+    double v = 0.0;
+    if (fluid) {
+      if (q == 0) {
+        v = P.rho0_d;
+        for (int i = 0; i < NQ; ++i) v += double(hin[i * N + r]);
+      } else if (q == 1) {
+        for (int k = 0; k < K; ++k) v += P.z[k] * (P.nref_d[k] + double(nu[k * N + r]));
+      } else {
+        v = P.nref_d[q - 2] + double(nu[(q - 2) * N + r]);
+      }
+    }
+    v = block_sum(v, sm);
+    if (threadIdx.x == 0) partial[q * gridDim.x + blockIdx.x] = v;
+  }
+  if (arrive_last(counter)) {
+    for (int q = 0; q < nq; ++q) {
+      double v = 0.0;
+      for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) v += partial[q * gridDim.x + b];
+      tree[threadIdx.x] = v;
+      __syncthreads();
+      for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) out[q] = tree[0];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicExch(counter, 0u);
+  }
+}
+
+}  // namespace
+
+#define LBE_DISPATCH_K(K, CALL) \
+  switch (K) {                  \
+    case 1: CALL(1); break;     \
+    case 2: CALL(2); break;     \
+    case 3: CALL(3); break;     \
+    default: CALL(4); break;    \
+  }
+
+hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                            const double *phi, const float *nu, const float *hin, float *hout,
+                            float *u) {
+#define CALL(KK) \
+  hipLaunchKernelGGL(k_fluid_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, nu, hin, hout, u)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                           const double *phi, const float *u, const float *nu, float *nuout,
+                           double *src) {
+#define CALL(KK) \
+  hipLaunchKernelGGL(k_ions_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, u, nu, nuout, src)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
+                              const uint32_t *mask, const double *phi, const float *nu,
+                              const float *hin, double *fpre, double *u) {
+#define CALL(KK) \
+  hipLaunchKernelGGL(k_observe_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, nu, hin, fpre, u)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                             const float *hin, const float *nu, double *partial,
+                             unsigned *counter, double *out) {
+  hipLaunchKernelGGL(k_totals_f32, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, hin, nu,
+                     partial, counter, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbe

@@ -1,0 +1,99 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point that
+include/lbe.h declares, agrees with the oracle on the velocity set, and
+rejects bad input with the documented codes before touching a device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1907_04732_amd as lbe
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "lbe.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbe_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbe.load()
+    names = header_functions()
+    assert "lbe_init" in names and "lbe_step" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(lbe.ENTRY_POINTS) <= set(names)
+
+
+def test_velocity_set_matches_oracle_order():
+    import oracle
+    c, w = lbe.velocities()
+    co, wo = oracle.velocities()
+    assert (c == co).all()
+    assert np.array_equal(w, wo)
+
+
+def test_error_strings():
+    lib = lbe.load()
+    for code in (lbe.OK, lbe.EINVAL, lbe.EGEOM, lbe.ENOMEM, lbe.EDEVICE, lbe.ENOCONV, lbe.ENONFINITE):
+        assert lib.lbe_strerror(code)
+    assert lbe.kernel_names()[0] == "fluid"
+
+
+def _slab_params(**kw):
+    shape, t, ps = W.slab(2, 2, 8, 1)
+    base = dict(shape=shape, z=(1, -1), D=(0.05, 0.05), lB=0.4)
+    base.update(kw)
+    return lbe.make_params(**base), t, ps
+
+
+@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(omega=2.0), dict(omega=-0.1),
+                                dict(check_every=0), dict(lB=-1.0), dict(rho0=0.0),
+                                dict(D=(0.05, -1.0)), dict(Eapp=(np.nan, 0, 0)),
+                                dict(precision=7), dict(poisson=9)])
+def test_invalid_parameters_rejected(kw):
+    p, t, ps = _slab_params(**kw)
+    with pytest.raises(lbe.LbeError) as e:
+        lbe.Lbe(p, t, ps, None, (1e-3, 1e-3))
+    assert e.value.code == lbe.EINVAL
+
+
+def test_invalid_dimensions_and_inputs():
+    p = lbe.make_params((0, 2, 10), (1, -1), (0.05, 0.05), 0.4)
+    with pytest.raises(lbe.LbeError) as e:
+        lbe.Lbe(p, np.zeros(0, np.uint8), np.zeros(0), None, (1e-3, 1e-3))
+    assert e.value.code == lbe.EINVAL
+    p, t, ps = _slab_params()
+    n0 = np.full((2, t.size), 1e-3)
+    n0[1, 9] = np.inf
+    with pytest.raises(lbe.LbeError) as e:
+        lbe.Lbe(p, t, ps, n0)
+    assert e.value.code == lbe.EINVAL
+    ps2 = ps.copy()
+    ps2[0] = np.nan
+    with pytest.raises(lbe.LbeError) as e:
+        lbe.Lbe(p, t, ps2, None, (1e-3, 1e-3))
+    assert e.value.code == lbe.EINVAL
+
+
+def test_geometry_rejected():
+    shape = (4, 4, 4)
+    p = lbe.make_params(shape, (1, -1), (0.05, 0.05), 0.4)
+    with pytest.raises(lbe.LbeError) as e:  # fluid touching no electrode
+        lbe.Lbe(p, np.zeros(64, np.uint8), np.zeros(64), None, (1e-3, 1e-3))
+    assert e.value.code == lbe.EGEOM
+    shape, t, ps = W.slab(3, 2, 8, 1)  # odd periodic extent > 2
+    p = lbe.make_params(shape, (1, -1), (0.05, 0.05), 0.4)
+    with pytest.raises(lbe.LbeError) as e:
+        lbe.Lbe(p, t, ps, None, (1e-3, 1e-3))
+    assert e.value.code == lbe.EGEOM
+    shape, t, ps = W.slab(2, 2, 8, 1)
+    t = t.copy()
+    t[0] = 70  # too many electrodes
+    p = lbe.make_params(shape, (1, -1), (0.05, 0.05), 0.4)
+    with pytest.raises(lbe.LbeError) as e:
+        lbe.Lbe(p, t, ps, None, (1e-3, 1e-3))
+    assert e.value.code == lbe.EINVAL

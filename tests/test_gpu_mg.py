@@ -1,0 +1,83 @@
+"""Multigrid Poisson (LBE_MG) on the GPU against the FP64 oracle's SOR.
+
+Both solve the same linear system (Eq. 2 with the Laplacian of Eq. 15) to a
+residual tol; they differ by at most |A^-1| tol in the potential.  For a gap
+of L lattice units |A^-1| <= L^2/8, so with tol = 1e-14 and L <= 32 the
+potentials agree to 1.3e-11 absolute; the tests allow 2e-11 relative to the
+electrode voltage scale 0.1 for phi and the same relative bound for n, f, Q.
+"""
+import numpy as np
+import pytest
+
+import gpu_cases as G
+import oracle
+import paper_1907_04732_amd as lbe
+import workloads as W
+from test_gpu_parity import U_SCALE, rel, residual_numpy
+
+pytestmark = pytest.mark.gpu
+
+MG_TOL = 2e-11
+
+
+def mg_pair(name, tol=1e-14, steps=None):
+    kw, shape, t, ps, n0, nref, nsteps, _ = G.case(name)
+    o = oracle.Oracle(oracle.make_params(shape, **kw, tol=tol, max_iter=10**6, check_every=1), t,
+                      ps, n0, nref)
+    g = lbe.Lbe(lbe.make_params(shape, **kw, tol=tol, max_iter=200, poisson=lbe.MG, mg_levels=0,
+                                mg_nu1=2, mg_nu2=2), t, ps, n0, nref)
+    return o, g, (nsteps if steps is None else steps), t
+
+
+@pytest.mark.parametrize("name", ["slab_4x4x34", "coax_16x16x4", "random_6x10x14_k3",
+                                  "slab_1x1x34"])
+def test_mg_matches_oracle(name):
+    o, g, nsteps, t = mg_pair(name)
+    o.step(nsteps)
+    g.step(nsteps)
+    fo, fg = o.fields(), g.fields()
+    vscale = 0.1
+    errs = dict(phi=rel(fg["phi"], fo["phi"], vscale), n=rel(fg["n"], fo["n"]),
+                f=rel(fg["f"], fo["f"]), q=rel(g.qhist(), o.qhist()),
+                u=rel(fg["u"], fo["u"], max(np.abs(fo["u"]).max(), U_SCALE)))
+    tot = g.totals()
+    print(name, {k: f"{v:.2e}" for k, v in errs.items()}, "cycles", tot["poisson_iters"])
+    for k, v in errs.items():
+        assert v <= MG_TOL, (k, errs)
+    assert tot["poisson_resid"] <= 1e-14
+
+
+def test_mg_converges_fast_on_full_slab():
+    """64x64x130 electro-osmosis slab at the production tolerance: the
+    multigrid solve reaches ||R|| <= 1e-10 in a few V-cycles per step, and the
+    returned potential satisfies Poisson's equation (residual recomputed)."""
+    w = W.eo_slab(noise=True)
+    p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, Eapp=w.Eapp, omega=w.omega,
+                        tol=1e-10, max_iter=100, poisson=lbe.MG, mg_levels=0)
+    g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref)
+    init_cycles = g.totals()["poisson_iters"]
+    cyc = []
+    for _ in range(5):
+        g.step(1)
+        cyc.append(g.totals()["poisson_iters"])
+    print("init cycles", init_cycles, "per step", cyc)
+    assert init_cycles <= 40 and max(cyc) <= 10
+    fg = g.fields(f=False)
+    R = residual_numpy(w.shape, w.node_type, fg["phi"], fg["n"], w.z, w.lB)
+    assert np.abs(R).max() <= 1.01e-10
+
+
+def test_mg_and_sor_agree_on_full_slab():
+    """FP64 SOR and multigrid from the same input, 2 steps at tol 1e-12."""
+    w = W.eo_slab(noise=True)
+    common = dict(tau=w.tau, Eapp=w.Eapp, omega=1.9, tol=1e-12)
+    a = lbe.Lbe(lbe.make_params(w.shape, w.z, w.D, w.lB, max_iter=10**6, **common), w.node_type,
+                w.phi_s, w.n_init, w.n_ref)
+    b = lbe.Lbe(lbe.make_params(w.shape, w.z, w.D, w.lB, max_iter=200, poisson=lbe.MG, **common),
+                w.node_type, w.phi_s, w.n_init, w.n_ref)
+    a.step(2)
+    b.step(2)
+    fa, fb = a.fields(f=False), b.fields(f=False)
+    # |A^-1| <= L^2/8 = 2048 for the 128-plane gap: 2e-9 absolute on phi
+    assert rel(fb["phi"], fa["phi"], 0.2) <= 2e-8
+    assert rel(fb["n"], fa["n"]) <= 2e-8
