@@ -1,12 +1,16 @@
-"""Benchmark: full LBE time steps (fluid + ions + Poisson + charge) per second
-on the parallel-plate electro-osmosis slab, 64 x 64 x 130 lattice sites.
+"""Benchmark: full LBE time steps (fluid + ions + Poisson + electrode charge)
+per second on the parallel-plate electro-osmosis slab, 64 x 64 x 130 lattice
+sites (128 fluid planes, Debye length 8, +-0.1 kT/e, E_x = 1e-3), Poisson
+solved to ||R||_inf <= 1e-10 every step.
 
-Prints ONE JSON line (rank 0, one GPU):
-  metric "MLUPS per full LBE step (fluid+ions+Poisson)" = lattice sites x
-  steps / wall seconds / 1e6, counting every site, with the inputs resident
-  in HBM; a roofline object for the kernel that takes the most GPU time, and
-  the FP64 oracle timed on the host cores on a bounded sample of the same
-  workload.
+Prints ONE JSON line.  `value` is the headline form (FP32-mixed storage and
+collision, multigrid Poisson correction inside FP64 defect correction); the
+FP64 form with multigrid and the FP64 form with the paper's SOR solver are
+measured in the same run under "forms".  MLUPS = lattice sites x steps / wall
+seconds / 1e6 over the timed steps, inputs resident in HBM.  A second window
+of the same length brackets every launch with HIP events on the library's
+stream to give per-kernel average durations; the roofline object is for the
+kernel with the largest total time.  cpu_baseline times the FP64 oracle.
 """
 from __future__ import annotations
 
@@ -16,8 +20,6 @@ import os
 import sys
 import time
 
-import numpy as np
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -26,24 +28,35 @@ import workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per lattice site for one launch of each kernel
-# (FP64 form).  fluid: 19 populations in + out, 2 species in, phi, 3 velocity
-# components out, the node's flag word.  ions: 2 species in + out, phi, 3
-# velocity components in, Poisson source out, flag word.  sor (one colour
-# launch, per lattice site): the launch must read phi at every node of the
-# other three colours (6 B per site), read and write its own quarter (4 B),
-# read the source (2 B) and flag word (1 B) of its quarter.  resid: phi,
-# source and flag word once.
-BYTES_PER_SITE_F64 = {"fluid": 19 * 16 + 16 + 8 + 24 + 4, "ions": 32 + 8 + 24 + 8 + 4,
-                      "sor": 13, "resid": 20, "charge": 0, "totals": 0, "observe": 0,
-                      "sor32": 0, "correct": 0}
 
+def bytes_per_site(kind: str, form: str, K: int):
+    """Algorithmic HBM bytes per lattice site for one launch of a kernel kind
+    (None for kernels whose launches differ in size, e.g. coarse levels).
 
-def make_context(w: W.Workload, precision: int, solver: int, check_every: int):
-    p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, rho0=w.rho0, Eapp=w.Eapp,
-                        omega=w.omega, tol=w.tol, max_iter=1_000_000, check_every=check_every,
-                        precision=precision, poisson=solver)
-    return lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref)
+    fluid: 19 populations in + out, K concentrations, phi (FP64), velocity
+      out, flag word.  ions: K concentrations in + out, phi, velocity in,
+      Poisson source (FP64) out, flag word.  One colour of a four-colour
+      sweep on the finest level must read the correction (or phi) at every
+      node of the other three colours, read and write its own quarter, and
+      read its quarter's right-hand side and flag word.  Residual: phi, source,
+      flag word (+ the correction's right-hand side and zeroed correction it
+      writes, multigrid).  correct: phi read + write, correction, flag word.
+    """
+    f64 = form == "fp64"
+    pop = 8 if f64 else 4     # population / concentration storage
+    vel = 8 if f64 else 4     # velocity storage
+    cor = 8 if f64 else 4     # Poisson correction storage (multigrid)
+    table = {
+        "fluid": 19 * pop * 2 + K * pop + 8 + 3 * vel + 4,
+        "ions": 2 * K * pop + 8 + 3 * vel + 8 + 4,
+        "sor": (6 * 8 + 8 * 2 + 8 + 4) / 4,          # FP64 phi sweep, one colour
+        "sor32": (6 * 4 + 4 * 2 + 4 + 4) / 4,        # FP32 correction sweep
+        "mg_smooth0": (6 * cor + cor * 2 + cor + 4) / 4,
+        "resid": 8 + 8 + 4,
+        "mg_resid": 8 + 8 + 4 + 2 * cor,
+        "correct": 16 + cor + 4,
+    }
+    return table.get(kind)
 
 
 def sync():
@@ -55,10 +68,64 @@ def sync():
         pass
 
 
+def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, check_every: int):
+    precision = lbe.FP64 if form == "fp64" else lbe.FP32_MIXED
+    poisson = lbe.SOR4 if solver == "sor" else lbe.MG
+    p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, rho0=w.rho0, Eapp=w.Eapp,
+                        omega=w.omega, tol=w.tol, max_iter=1_000_000, check_every=check_every,
+                        precision=precision, poisson=poisson)
+    g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref)
+    N = w.node_type.size
+    nfluid = int((w.node_type == 0).sum())
+    g.step(warmup)
+    tot0 = g.totals()
+    sync()
+    t0 = time.perf_counter()
+    g.step(steps)
+    sync()
+    el = time.perf_counter() - t0
+    tot1 = g.totals()
+    iters = (tot1["poisson_total"] - tot0["poisson_total"]) / steps
+    mlups = N * steps / el / 1e6
+    print(f"bench: {form}/{solver}: {steps} steps in {el:.4f} s, {mlups:.2f} MLUPS, "
+          f"{iters:.2f} {'sweeps' if solver == 'sor' else 'cycles'}/step", file=sys.stderr,
+          flush=True)
+
+    # second window: HIP events around every launch, on the library's stream
+    g.profile(True)
+    g.step(steps)
+    kt = g.kernel_times()
+    g.profile(False)
+    g.close()
+    kernels = {}
+    for k, (ms, cnt) in sorted(kt.items(), key=lambda kv: -kv[1][0]):
+        if not cnt:
+            continue
+        avg = ms / 1e3 / cnt
+        b = bytes_per_site(k, form, len(w.z))
+        row = {"total_ms": round(ms, 4), "launches": cnt, "avg_us": round(avg * 1e6, 3)}
+        if b is not None:
+            row["bytes_per_launch"] = int(b * N)
+            row["achieved_GBs"] = round(b * N / avg / 1e9, 1)
+            row["frac"] = round(b * N / avg / 1e9 / HBM_PEAK_GBS, 4)
+        kernels[k] = row
+        print(f"bench:   {k:12s} {ms:9.3f} ms, {cnt:6d} launches, {avg * 1e6:8.2f} us avg"
+              + (f", {row['achieved_GBs']:8.1f} GB/s" if b is not None else ""),
+              file=sys.stderr, flush=True)
+    dom = next(iter(kernels))
+    d = kernels[dom]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": d.get("achieved_GBs"), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": d.get("frac"), "bytes_per_launch": d.get("bytes_per_launch"),
+            "avg_launch_us": d["avg_us"], "traffic": None}
+    return {"mlups": round(mlups, 3), "ms_per_step": round(el / steps * 1e3, 4),
+            "fluid_mlups": round(nfluid * steps / el / 1e6, 3),
+            "poisson_iters_per_step": round(iters, 3), "roofline": roof, "kernels": kernels}
+
+
 def cpu_baseline(w_full: W.Workload, seconds=20.0):
     """The FP64 oracle on a lateral 16 x 16 crop of the same slab (same
     column physics, Poisson tolerance and SOR settings), timed over whole
-    steps after its initial solve; returned as MLUPS."""
+    steps after its initial solve; MLUPS counts the crop's sites."""
     import oracle
     crop = W.eo_slab(noise=True, nx=16, ny=16, nfluid=w_full.shape[2] - 2)
     p = oracle.make_params(crop.shape, crop.z, crop.D, crop.lB, crop.tau, crop.rho0, crop.Eapp,
@@ -72,87 +139,81 @@ def cpu_baseline(w_full: W.Workload, seconds=20.0):
         el = time.perf_counter() - t0
         if el >= seconds or steps >= 200:
             break
-    return dict(value=n * steps / el / 1e6, unit="MLUPS", cores=1, kind="oracle",
+    return dict(value=round(n * steps / el / 1e6, 5), unit="MLUPS", cores=1, kind="oracle",
                 sample=f"16x16x{crop.shape[2]} lateral crop of the slab, {steps} steps after the "
-                       f"initial solve, tol {crop.tol:g}, single-threaded C oracle")
+                       f"initial solve, tol {crop.tol:g}, SOR omega {crop.omega}, "
+                       "single-threaded C oracle")
+
+
+def copy_calibration(nbytes=1 << 28, reps=5):
+    """A plain device copy of known size (torch), for scaling the hardware
+    FETCH_SIZE / WRITE_SIZE counters in a profiling run."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"bench: copy calibration {reps} x {nbytes} bytes", file=sys.stderr, flush=True)
+
+
+FORMS = {"fp32-mg": ("fp32", "mg"), "fp64-mg": ("fp64", "mg"), "fp64-sor": ("fp64", "sor"),
+         "fp32-sor": ("fp32", "sor")}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--solver", choices=["sor", "mg"], default="sor")
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--forms", default="fp32-mg,fp64-mg,fp64-sor",
+                    help="comma list of " + ",".join(FORMS) + "; the first is the headline")
     ap.add_argument("--check-every", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the LBE step is not sharded across GPUs in this "
+        print("bench.py measures one GPU: the LBE step is not sharded across GPUs in this "
               "build (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-
-    precision = lbe.FP64 if args.form == "fp64" else lbe.FP32_MIXED
-    solver = lbe.SOR4 if args.solver == "sor" else lbe.MG
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     w = W.eo_slab(noise=True)
     N = w.node_type.size
-    nfluid = int((w.node_type == 0).sum())
-    print(f"bench: {w.name}, {N} sites, form {args.form}, solver {args.solver}", file=sys.stderr,
-          flush=True)
-    g = make_context(w, precision, solver, args.check_every)
-    g.step(args.warmup)
-    tot0 = g.totals()
-    sync()
-    t0 = time.perf_counter()
-    g.step(args.steps)
-    sync()
-    el = time.perf_counter() - t0
-    tot1 = g.totals()
-    sweeps = (tot1["poisson_total"] - tot0["poisson_total"]) / args.steps
-    mlups = N * args.steps / el / 1e6
-    print(f"bench: {args.steps} steps in {el:.3f} s, {mlups:.2f} MLUPS, {sweeps:.1f} sweeps/step",
-          file=sys.stderr, flush=True)
-
-    # second timed window with per-launch HIP events on the library's stream
-    g.profile(True)
-    g.step(args.steps)
-    kt = g.kernel_times()
-    g.profile(False)
-    bytes_tab = BYTES_PER_SITE_F64
-    dom = max(kt, key=lambda k: kt[k][0])
-    ms, cnt = kt[dom]
-    avg_s = ms / 1e3 / max(cnt, 1)
-    per_launch_bytes = bytes_tab.get(dom, 0) * N
-    achieved = per_launch_bytes / avg_s / 1e9 if avg_s > 0 else 0.0
-    for k, (kms, kc) in sorted(kt.items(), key=lambda kv: -kv[1][0]):
-        if kc:
-            print(f"bench: kernel {k:8s} {kms:9.3f} ms total, {kc:7d} launches, "
-                  f"{kms / kc * 1e3:8.2f} us avg", file=sys.stderr, flush=True)
-
+    print(f"bench: {w.name}, {N} sites", file=sys.stderr, flush=True)
+    if args.copy_calibration:
+        copy_calibration()
+    res = {}
+    for name in forms:
+        form, solver = FORMS[name]
+        # SOR needs hundreds of sweeps per step: time fewer steps
+        steps = args.steps if solver == "mg" else max(2, args.steps // 10)
+        res[name] = run_form(w, form, solver, steps, args.warmup if solver == "mg" else 2,
+                             args.check_every)
+    head = res[forms[0]]
+    hform, hsolver = FORMS[forms[0]]
     out = {
         "metric": "MLUPS per full LBE step (fluid+ions+Poisson)",
-        "value": round(mlups, 3),
+        "value": head["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": args.steps if hsolver == "mg" else max(2, args.steps // 10),
         "warmup": args.warmup,
-        "ms_per_step": round(el / args.steps * 1e3, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == lbe.FP64 else "f32+f64",
+        "dtype": "f64" if hform == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "sites": N, "fluid_sites": nfluid,
-                   "form": args.form, "poisson": args.solver, "omega": w.omega, "tol": w.tol,
-                   "debye": w.extra["debye"], "Eapp": list(w.Eapp),
-                   "sweeps_per_step": round(sweeps, 2),
-                   "fluid_mlups": round(nfluid * args.steps / el / 1e6, 3)},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "bytes_per_launch": per_launch_bytes,
-                     "avg_launch_us": round(avg_s * 1e6, 3), "traffic": None},
+        "config": {"workload": w.name, "sites": N, "fluid_sites": int((w.node_type == 0).sum()),
+                   "form": forms[0], "tol": w.tol, "debye": w.extra["debye"],
+                   "Eapp": list(w.Eapp), "omega": w.omega,
+                   "poisson_iters_per_step": head["poisson_iters_per_step"],
+                   "fluid_mlups": head["fluid_mlups"]},
+        "roofline": head["roofline"],
+        "forms": {k: {kk: v[kk] for kk in ("mlups", "ms_per_step", "poisson_iters_per_step",
+                                            "roofline")} for k, v in res.items()},
+        "kernels": head["kernels"],
     }
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)

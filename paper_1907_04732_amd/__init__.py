@@ -17,6 +17,7 @@ OK, EINVAL, EGEOM, ENOMEM, EDEVICE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5,
 FP64, FP32_MIXED = 0, 1
 SOR4, MG = 0, 1
 ALLOW_FLOATING = 1
+EXTRAPOLATE = 2
 
 # public entry points of include/lbe.h
 ENTRY_POINTS = (
@@ -108,7 +109,7 @@ def _dptr(a):
 
 def make_params(shape, z, D, lB, tau=1.0, rho0=1.0, Eapp=(0.0, 0.0, 0.0), omega=1.8, tol=1e-10,
                 max_iter=200000, check_every=4, flags=0, precision=FP64, poisson=SOR4,
-                mg_levels=3, mg_nu1=2, mg_nu2=2, stream=None) -> Params:
+                mg_levels=0, mg_nu1=2, mg_nu2=2, stream=None) -> Params:
     p = Params()
     p.nx, p.ny, p.nz = (int(v) for v in shape)
     if not 1 <= len(z) <= 4 or len(D) != len(z):

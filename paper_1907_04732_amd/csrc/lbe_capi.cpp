@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -27,6 +28,7 @@ struct lbe_ctx {
   // device state (FP64 form)
   uint32_t *mask = nullptr;
   double *phi = nullptr, *src = nullptr, *u = nullptr;
+  double *phi_prev = nullptr;  // converged phi of the previous step (LBE_EXTRAPOLATE)
   double *n[2] = {nullptr, nullptr};
   double *f[2] = {nullptr, nullptr};
   // mixed form: FP32 deviations h = f - w rho0, nu = n - n_ref, FP32 velocity
@@ -40,9 +42,13 @@ struct lbe_ctx {
 
   // reductions
   double *partial = nullptr;
-  unsigned *counter = nullptr;
-  double *dout = nullptr;  // small device results (residual, totals)
+  double *dout = nullptr;  // small device results (totals)
   double *hpin = nullptr;  // pinned host mirror of dout
+  SolveCtl *ctl = nullptr;    // device control block of the running Poisson solve
+  SolveCtl *ctl_h = nullptr;  // pinned host mirror
+  int pred_iters = 0;         // iterations the last time-step solve needed
+  bool use_graphs = true;     // replay one solver unit as a captured HIP graph
+  hipGraphExec_t unit_exec = nullptr;
 
   // electrode charge tables
   int *iface = nullptr, *blk_elec = nullptr, *blk_begin = nullptr, *blk_end = nullptr;
@@ -61,6 +67,14 @@ struct lbe_ctx {
   };
   std::vector<MgDev> mg;
   int mg_coarse_sweeps = 0;
+  // coarsest level solved exactly: inverse of its operator over fluid cells
+  int mg_nf = 0;
+  void *mg_ainv = nullptr;  // T[nf * nf]
+  int *mg_fcell = nullptr;  // fluid index -> cell
+  // levels from mg_small_from down run in one work-group in LDS (-1: none)
+  int mg_small_from = -1;
+  MgSmall mg_small{};
+  size_t mg_small_lds = 0;
 
   // statistics
   int64_t step = 0;
@@ -172,6 +186,8 @@ int validate(const lbe_params *p) {
       return fail(nullptr, LBE_EINVAL, "diffusion coefficients must be finite and >= 0");
   for (int a = 0; a < 3; ++a)
     if (!isfinite(p->Eapp[a])) return fail(nullptr, LBE_EINVAL, "applied field must be finite");
+  if (p->flags & ~(LBE_ALLOW_FLOATING | LBE_EXTRAPOLATE))
+    return fail(nullptr, LBE_EINVAL, "unknown flags");
   if (p->precision != LBE_FP64 && p->precision != LBE_FP32_MIXED)
     return fail(nullptr, LBE_EINVAL, "unsupported precision form");
   if (p->poisson != LBE_SOR4 && p->poisson != LBE_MG)
@@ -290,73 +306,120 @@ int read_scalars(lbe_ctx *c, int count) {
   return LBE_OK;
 }
 
-int residual(lbe_ctx *c, double *out) {
-  int rc = run(c, KK_RESID, [&] {
-    return launch_resid_f64(c->stream, c->L, c->mask, c->src, c->phi, c->partial, c->counter,
-                            c->dout);
-  });
-  if (rc) return rc;
-  rc = read_scalars(c, 1);
-  if (rc) return rc;
-  *out = c->hpin[0];
+int reset_ctl(lbe_ctx *c) {
+  *c->ctl_h = SolveCtl{0.0, c->p.tol, 0, 0, 0, 0, 0, 0};
+  HIPCHK(c, hipMemcpyAsync(c->ctl, c->ctl_h, sizeof(SolveCtl), hipMemcpyHostToDevice, c->stream));
   return LBE_OK;
 }
 
-int sor_sweeps(lbe_ctx *c, int count) {
-  for (int s = 0; s < count; ++s)
-    for (int col = 0; col < 4; ++col) {
-      int rc = run(c, KK_SOR, [&] {
-        return launch_sor_f64(c->stream, c->L, c->P, col, c->mask, c->src, c->phi);
-      });
-      if (rc) return rc;
-    }
+int read_ctl(lbe_ctx *c) {
+  HIPCHK(c, hipMemcpyAsync(c->ctl_h, c->ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return LBE_OK;
 }
 
-// Poisson solve (Sec. II C), warm-started; same stopping schedule as the
-// oracle: residual before the first sweep and after every check_every.
-int sor_solve(lbe_ctx *c) {
+// A warm-started iterative Poisson solve (Sec. II C) with device-side
+// stopping.  step(m) queues m iterations (sweeps or cycles) and check(m) a
+// residual check that counts those m; both are no-ops on the device once the
+// solve is done.  Same schedule as the oracle: a check before the first
+// iteration and after every `per_check`.  The host queues as many iterations
+// as the previous time step needed and synchronises once; if that was not
+// enough it adds a quarter more (at least one unit) and synchronises again.
+// A unit (per_check iterations + check) is captured once as a HIP graph and
+// replayed (not while per-kernel profiling is on).
+template <class Step, class Check>
+int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&step,
+              Check &&check) {
   const lbe_params &p = c->p;
-  int sweeps = 0;
-  double res = 0.0;
   int rc;
-  if (p.tol <= 0.0) {
-    rc = sor_sweeps(c, p.max_iter);
-    if (rc) return rc;
-    sweeps = p.max_iter;
-    rc = residual(c, &res);
-    if (rc) return rc;
-    c->last_iters = sweeps;
-    c->last_resid = res;
-    c->total_iters += sweeps;
-    if (!isfinite(res)) return fail(c, LBE_ENONFINITE, "non-finite Poisson residual");
+  auto unit_direct = [&](int m) -> int {
+    int r2 = step(m);
+    return r2 ? r2 : check(m);
+  };
+  auto unit_once = [&](int m) -> int {
+    if (c->prof || !c->use_graphs || m != per_check) return unit_direct(m);
+    if (!c->unit_exec) {
+      hipGraph_t g = nullptr;
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      const int r2 = unit_direct(m);
+      const hipError_t e = hipStreamEndCapture(c->stream, &g);
+      if (r2) {
+        if (g) (void)hipGraphDestroy(g);
+        return r2;
+      }
+      if (e != hipSuccess) return hip_fail(c, e, "graph capture");
+      const hipError_t e2 = hipGraphInstantiate(&c->unit_exec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e2 != hipSuccess) return hip_fail(c, e2, "graph instantiate");
+    }
+    HIPCHK(c, hipGraphLaunch(c->unit_exec, c->stream));
+    return LBE_OK;
+  };
+  if ((rc = reset_ctl(c))) return rc;
+  if (p.tol <= 0.0) {  // exactly max_iter iterations
+    for (int it = 0; it < p.max_iter; it += per_check)
+      if ((rc = step(std::min(per_check, p.max_iter - it)))) return rc;
+    if ((rc = check(p.max_iter))) return rc;
+    if ((rc = read_ctl(c))) return rc;
+    c->last_iters = p.max_iter;
+    c->last_resid = c->ctl_h->resid;
+    c->total_iters += p.max_iter;
+    if (c->ctl_h->nonfinite) return fail(c, LBE_ENONFINITE, "non-finite Poisson residual");
     return LBE_OK;
   }
+  if ((rc = check(0))) return rc;
+  int queued = 0;
+  int target = std::max(c->pred_iters, per_check);
   for (;;) {
-    rc = residual(c, &res);
-    if (rc) return rc;
-    c->last_iters = sweeps;
-    c->last_resid = res;
-    if (!isfinite(res)) {
-      c->total_iters += sweeps;
-      return fail(c, LBE_ENONFINITE, "non-finite Poisson residual");
+    target = std::min(target, p.max_iter);
+    while (queued < target) {
+      const int m = std::min(per_check, p.max_iter - queued);
+      if ((rc = unit_once(m))) return rc;
+      queued += m;
     }
-    if (res <= p.tol) break;
-    if (sweeps >= p.max_iter) {
-      c->total_iters += sweeps;
+    if ((rc = read_ctl(c))) return rc;
+    if (c->ctl_h->done) break;
+    if (queued >= p.max_iter) {
+      c->last_iters = queued;
+      c->last_resid = c->ctl_h->resid;
+      c->total_iters += queued;
       char buf[160];
-      snprintf(buf, sizeof buf, "Poisson not converged: residual %.3e after %d sweeps", res, sweeps);
+      snprintf(buf, sizeof buf, "Poisson not converged: residual %.3e after %d %s",
+               c->ctl_h->resid, queued, unit);
       return fail(c, LBE_ENOCONV, buf);
     }
-    const int m = std::min(p.check_every, p.max_iter - sweeps);
-    rc = sor_sweeps(c, m);
-    if (rc) return rc;
-    sweeps += m;
+    target = queued + std::max(per_check, queued / 4);
   }
-  c->total_iters += sweeps;
+  const int iters = c->ctl_h->iters;
+  c->last_iters = iters;
+  c->last_resid = c->ctl_h->resid;
+  c->total_iters += iters;
+  if (c->ctl_h->nonfinite) return fail(c, LBE_ENONFINITE, "non-finite Poisson residual");
+  if (learn) c->pred_iters = iters;
   return LBE_OK;
 }
 
+// FP64 SOR on phi itself (Eq. 13 with Eq. 15, four colours).
+int sor_solve(lbe_ctx *c, bool learn) {
+  return run_solve(
+      c, c->p.check_every, learn, "sweeps",
+      [&](int m) -> int {
+        for (int s2 = 0; s2 < m; ++s2)
+          for (int col = 0; col < 4; ++col) {
+            int rc = run(c, KK_SOR, [&] {
+              return launch_sor_f64(c->stream, c->L, c->P, col, c->mask, c->src, c->phi, c->ctl);
+            });
+            if (rc) return rc;
+          }
+        return LBE_OK;
+      },
+      [&](int add) -> int {
+        return run(c, KK_RESID, [&] {
+          return launch_resid_f64(c->stream, c->L, c->mask, c->src, c->phi, c->partial, c->ctl,
+                                  add);
+        });
+      });
+}
 
 // ---- multigrid hierarchy ----------------------------------------------------
 
@@ -439,6 +502,139 @@ void coarsen(int nx, int ny, int nz, const std::vector<uint8_t> &solid, int &cx,
       }
 }
 
+// Dense inverse of the coarsest operator A e = (6/h^2) sum_i w_i s_i (e - e_i)
+// over its fluid cells (Cholesky in FP64; A is symmetric positive definite when
+// every fluid region touches an electrode).  Not built when the level has
+// more than kMaxDense fluid cells or A is singular (floating regions): the
+// coarsest level is then swept instead.
+constexpr int kMaxDense = 512;
+
+int build_coarse_inverse(lbe_ctx *c, const std::vector<uint8_t> &solid) {
+  const MgLevel &lv = c->mg.back().lv;
+  std::vector<int> fidx(lv.n, -1), fcell;
+  for (int r = 0; r < lv.n; ++r)
+    if (!solid[r]) {
+      fidx[r] = (int)fcell.size();
+      fcell.push_back(r);
+    }
+  const int nf = (int)fcell.size();
+  if (nf == 0 || nf > kMaxDense) return LBE_OK;
+  std::vector<double> A((size_t)nf * nf, 0.0);
+  const double sc = 6.0 * lv.inv_h2;
+  for (int j = 0; j < nf; ++j) {
+    const int r = fcell[j];
+    const int z = r / lv.nxy, y = (r - z * lv.nxy) / lv.nx, x = r - z * lv.nxy - y * lv.nx;
+    for (int i = 1; i < NQ; ++i) {
+      if ((lv.selfm >> (i - 1)) & 1u) continue;
+      const int rn = wrap(x + CX[i], lv.nx) + lv.nx * (wrap(y + CY[i], lv.ny) + lv.ny * wrap(z + CZ[i], lv.nz));
+      if (solid[rn]) {
+        A[(size_t)j * nf + j] += sc * 2.0 * WQ[i];
+      } else {
+        A[(size_t)j * nf + j] += sc * WQ[i];
+        A[(size_t)j * nf + fidx[rn]] -= sc * WQ[i];
+      }
+    }
+  }
+  // Cholesky A = L L^T (lower triangle in place)
+  for (int j = 0; j < nf; ++j) {
+    double d = A[(size_t)j * nf + j];
+    for (int k = 0; k < j; ++k) d -= A[(size_t)j * nf + k] * A[(size_t)j * nf + k];
+    if (!(d > 1e-12 * sc)) return LBE_OK;  // singular: keep the sweeps
+    d = sqrt(d);
+    A[(size_t)j * nf + j] = d;
+    for (int i = j + 1; i < nf; ++i) {
+      double v = A[(size_t)i * nf + j];
+      for (int k = 0; k < j; ++k) v -= A[(size_t)i * nf + k] * A[(size_t)j * nf + k];
+      A[(size_t)i * nf + j] = v / d;
+    }
+  }
+  // inverse column by column: solve L y = e_k, L^T x = y
+  std::vector<double> inv((size_t)nf * nf), y(nf);
+  for (int col = 0; col < nf; ++col) {
+    for (int i = 0; i < nf; ++i) {
+      double v = (i == col) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= A[(size_t)i * nf + k] * y[k];
+      y[i] = v / A[(size_t)i * nf + i];
+    }
+    for (int i = nf - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < nf; ++k) v -= A[(size_t)k * nf + i] * inv[(size_t)k * nf + col];
+      inv[(size_t)i * nf + col] = v / A[(size_t)i * nf + i];
+    }
+  }
+  HIPCHK(c, hipMalloc((void **)&c->mg_fcell, sizeof(int) * nf));
+  HIPCHK(c, hipMemcpy(c->mg_fcell, fcell.data(), sizeof(int) * nf, hipMemcpyHostToDevice));
+  if (c->mixed) {
+    std::vector<float> f32(inv.begin(), inv.end());
+    HIPCHK(c, hipMalloc(&c->mg_ainv, sizeof(float) * f32.size()));
+    HIPCHK(c, hipMemcpy(c->mg_ainv, f32.data(), sizeof(float) * f32.size(), hipMemcpyHostToDevice));
+  } else {
+    HIPCHK(c, hipMalloc(&c->mg_ainv, sizeof(double) * inv.size()));
+    HIPCHK(c, hipMemcpy(c->mg_ainv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice));
+  }
+  c->mg_nf = nf;
+  return LBE_OK;
+}
+
+// Choose the first level, of at most 2048 cells, from which the rest of the
+// hierarchy fits in one work-group's LDS (correction and right-hand side per
+// cell in T, flag words).  Larger levels are faster as multi-block kernels.
+int plan_small_levels(lbe_ctx *c) {
+  c->mg_small_from = -1;
+  if (c->mg.size() < 2 || getenv("LBE_NO_SMALL_MG")) return LBE_OK;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return LBE_OK;
+  const size_t limit = prop.sharedMemPerBlock;
+  const size_t tsz = c->mixed ? sizeof(float) : sizeof(double);
+  const int L = (int)c->mg.size();
+  for (int from = 0; from < L; ++from) {
+    // one compute unit sweeps the set: only worth it while the levels are tiny
+    if (L - from > MG_MAX_SMALL || c->mg[from].lv.n > 2048) continue;
+    size_t tbytes = 0, mbytes = 0;
+    for (int k = from; k < L; ++k) {
+      tbytes += 2 * tsz * (size_t)c->mg[k].lv.n;
+      mbytes += 4 * (size_t)c->mg[k].lv.n;
+    }
+    const size_t total = tbytes + mbytes;
+    if (total > limit) continue;
+    MgSmall S{};
+    S.nlev = L - from;
+    size_t te = 0;  // in T elements
+    for (int k = 0; k < S.nlev; ++k) {
+      const lbe_ctx::MgDev &D = c->mg[from + k];
+      S.lv[k] = D.lv;
+      if (k) S.tr[k] = D.tr;
+      S.mask[k] = D.mask;
+      S.off_e[k] = (int)te;
+      te += D.lv.n;
+      S.off_r[k] = (int)te;
+      te += D.lv.n;
+    }
+    size_t me = te * tsz / 4;  // flag words follow, in 4-byte units
+    for (int k = 0; k < S.nlev; ++k) {
+      S.off_m[k] = (int)me;
+      me += c->mg[from + k].lv.n;
+    }
+    S.nu1 = c->p.mg_nu1;
+    S.nu2 = c->p.mg_nu2;
+    S.nf = c->mg_nf;
+    S.ainv = c->mg_ainv;
+    S.fcell = c->mg_fcell;
+    S.coarse_sweeps = c->mg_coarse_sweeps;
+    S.omega = c->p.omega;
+    const hipError_t e = c->mixed ? prepare_mg_small<float>(total) : prepare_mg_small<double>(total);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return LBE_OK;
+    }
+    c->mg_small = S;
+    c->mg_small_from = from;
+    c->mg_small_lds = total;
+    return LBE_OK;
+  }
+  return LBE_OK;
+}
+
 int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
   const size_t esz = c->mixed ? sizeof(float) : sizeof(double);
   const int maxl = only_top ? 1 : (c->p.mg_levels > 0 ? c->p.mg_levels : 16);
@@ -453,7 +649,7 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
   c->mg.push_back(l0);
   double h2 = 1.0;
   for (int l = 1; l < maxl; ++l) {
-    if (c->p.mg_levels == 0 && (long)nx * ny * nz <= 2048) break;
+    if (c->p.mg_levels == 0 && (long)nx * ny * nz <= kMaxDense) break;
     if (nx <= 2 && ny <= 2 && nz <= 2) break;
     int cx, cy, cz, ox = 0, oy = 0, oz = 0;
     std::vector<uint8_t> cs;
@@ -480,80 +676,96 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
   }
   const MgLevel &top = c->mg.back().lv;
   c->mg_coarse_sweeps = 2 * std::max({top.nx, top.ny, top.nz}) + 10;
-  return LBE_OK;
+  if (c->mg.size() > 1) {
+    int rc = build_coarse_inverse(c, solid);
+    if (rc) return rc;
+  }
+  return plan_small_levels(c);
 }
 
+// One V-cycle from level l: e (zeroed by the residual / restriction kernel)
+// -> pre-smoothing -> restriction -> V-cycle below -> prolongation ->
+// post-smoothing; *out receives the level's correction.
 template <class T>
-int mg_vcycle(lbe_ctx *c, size_t l) {
+int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
   lbe_ctx::MgDev &L = c->mg[l];
-  T *e = (T *)L.e, *r = (T *)L.r;
+  T *A = (T *)L.e, *r = (T *)L.r;
   int rc;
-  if (l + 1 == c->mg.size()) {
-    return run(c, KK_MG_COARSE, [&] {
-      return launch_mg_coarse<T>(c->stream, L.lv, c->p.omega, c->mg_coarse_sweeps, L.mask, r, e);
+  if ((int)l == c->mg_small_from) {
+    *out = A;
+    return run(c, KK_MG_SMALL, [&] {
+      return launch_mg_small<T>(c->stream, c->mg_small, c->mg_small_lds, r, A, c->ctl);
     });
   }
-  auto smooth = [&](int count) -> int {
-    for (int s = 0; s < count; ++s)
+  if (l + 1 == c->mg.size()) {
+    *out = A;
+    if (c->mg_ainv)
+      return run(c, KK_MG_COARSE, [&] {
+        return launch_mg_coarse_dense<T>(c->stream, c->mg_nf, (const T *)c->mg_ainv, c->mg_fcell,
+                                         r, A, c->ctl);
+      });
+    return run(c, KK_MG_COARSE, [&] {
+      return launch_mg_coarse<T>(c->stream, L.lv, c->p.omega, c->mg_coarse_sweeps, L.mask, r, A,
+                                 c->ctl);
+    });
+  }
+  const KernelKind sk = l == 0 ? KK_MG_SMOOTH0 : KK_MG_SMOOTH;
+  T *cur = A;
+  // four-colour Gauss-Seidel, in place
+  auto smooth = [&](int sweeps) -> int {
+    for (int s2 = 0; s2 < sweeps; ++s2)
       for (int col = 0; col < 4; ++col) {
-        int rc2 = run(c, KK_MG_SMOOTH, [&] {
-          return launch_mg_smooth<T>(c->stream, L.lv, 1.0, col, L.mask, r, e);
+        const int r2 = run(c, sk, [&] {
+          return launch_mg_smooth<T>(c->stream, L.lv, 1.0, col, L.mask, r, cur, c->ctl);
         });
-        if (rc2) return rc2;
+        if (r2) return r2;
       }
     return LBE_OK;
   };
   if ((rc = smooth(c->p.mg_nu1))) return rc;
   lbe_ctx::MgDev &C = c->mg[l + 1];
   rc = run(c, KK_MG_RESTRICT, [&] {
-    return launch_mg_restrict<T>(c->stream, C.tr, L.mask, C.mask, r, e, (T *)C.r, (T *)C.e);
+    return launch_mg_restrict<T>(c->stream, C.tr, L.mask, C.mask, r, cur, (T *)C.r, (T *)C.e,
+                                 c->ctl);
   });
   if (rc) return rc;
-  if ((rc = mg_vcycle<T>(c, l + 1))) return rc;
+  T *ce = nullptr;
+  if ((rc = mg_vcycle<T>(c, l + 1, &ce))) return rc;
   rc = run(c, KK_MG_PROLONG, [&] {
-    return launch_mg_prolong<T>(c->stream, C.tr, L.mask, C.mask, (const T *)C.e, e);
+    return launch_mg_prolong<T>(c->stream, C.tr, L.mask, C.mask, (const T *)ce, cur, c->ctl);
   });
   if (rc) return rc;
-  return smooth(c->p.mg_nu2);
+  if ((rc = smooth(c->p.mg_nu2))) return rc;
+  *out = cur;
+  return LBE_OK;
 }
 
-// Defect correction: residual in FP64, correction by one V-cycle, phi += e.
+// Defect correction: residual in FP64 (which also zeroes e and stores the
+// right-hand side for the correction), one V-cycle for e, phi += e.
 template <class T>
-int mg_solve(lbe_ctx *c) {
-  const lbe_params &p = c->p;
+int mg_solve(lbe_ctx *c, bool learn) {
   lbe_ctx::MgDev &L0 = c->mg[0];
-  int cycles = 0;
-  for (;;) {
-    int rc = run(c, KK_MG_RESID, [&] {
-      return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi, (T *)L0.r,
-                                      (T *)L0.e, c->partial, c->counter, c->dout);
-    });
-    if (rc) return rc;
-    if ((rc = read_scalars(c, 1))) return rc;
-    const double res = c->hpin[0];
-    c->last_iters = cycles;
-    c->last_resid = res;
-    if (!isfinite(res)) {
-      c->total_iters += cycles;
-      return fail(c, LBE_ENONFINITE, "non-finite Poisson residual");
-    }
-    if (p.tol > 0.0 && res <= p.tol) break;
-    if (cycles >= p.max_iter) {
-      c->total_iters += cycles;
-      if (p.tol <= 0.0) return LBE_OK;
-      char buf[160];
-      snprintf(buf, sizeof buf, "Poisson not converged: residual %.3e after %d cycles", res, cycles);
-      return fail(c, LBE_ENOCONV, buf);
-    }
-    if ((rc = mg_vcycle<T>(c, 0))) return rc;
-    rc = run(c, KK_CORRECT, [&] {
-      return launch_mg_correct<T>(c->stream, L0.lv.n, c->mask, (const T *)L0.e, c->phi);
-    });
-    if (rc) return rc;
-    ++cycles;
-  }
-  c->total_iters += cycles;
-  return LBE_OK;
+  return run_solve(
+      c, 1, learn, "cycles",
+      [&](int m) -> int {
+        for (int k = 0; k < m; ++k) {
+          T *e0 = nullptr;
+          int rc = mg_vcycle<T>(c, 0, &e0);
+          if (rc) return rc;
+          rc = run(c, KK_CORRECT, [&] {
+            return launch_mg_correct<T>(c->stream, L0.lv.n, c->mask, (const T *)e0, c->phi,
+                                        c->ctl);
+          });
+          if (rc) return rc;
+        }
+        return LBE_OK;
+      },
+      [&](int add) -> int {
+        return run(c, KK_MG_RESID, [&] {
+          return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi, (T *)L0.r,
+                                          (T *)L0.e, c->partial, c->ctl, add);
+        });
+      });
 }
 
 int grow_history(lbe_ctx *c) {
@@ -576,56 +788,38 @@ int grow_history(lbe_ctx *c) {
 // Mixed form with SOR: FP64 residual, check_every FP32 SOR sweeps on the
 // correction from zero (the same iterates as SOR on phi, accumulated in FP32),
 // then phi += e.  Counts sweeps.
-int mixed_sor_solve(lbe_ctx *c) {
-  const lbe_params &p = c->p;
+int mixed_sor_solve(lbe_ctx *c, bool learn) {
   lbe_ctx::MgDev &L0 = c->mg[0];
-  int sweeps = 0;
-  for (;;) {
-    int rc = run(c, KK_MG_RESID, [&] {
-      return launch_mg_outer_resid<float>(c->stream, L0.lv, c->mask, c->src, c->phi,
-                                          (float *)L0.r, (float *)L0.e, c->partial, c->counter,
-                                          c->dout);
-    });
-    if (rc) return rc;
-    if ((rc = read_scalars(c, 1))) return rc;
-    const double res = c->hpin[0];
-    c->last_iters = sweeps;
-    c->last_resid = res;
-    if (!isfinite(res)) {
-      c->total_iters += sweeps;
-      return fail(c, LBE_ENONFINITE, "non-finite Poisson residual");
-    }
-    if (p.tol > 0.0 && res <= p.tol) break;
-    if (sweeps >= p.max_iter) {
-      c->total_iters += sweeps;
-      if (p.tol <= 0.0) return LBE_OK;
-      char buf[160];
-      snprintf(buf, sizeof buf, "Poisson not converged: residual %.3e after %d sweeps", res, sweeps);
-      return fail(c, LBE_ENOCONV, buf);
-    }
-    const int m = std::min(p.check_every, p.max_iter - sweeps);
-    for (int s2 = 0; s2 < m; ++s2)
-      for (int col = 0; col < 4; ++col) {
-        rc = run(c, KK_SOR32, [&] {
-          return launch_mg_smooth<float>(c->stream, L0.lv, p.omega, col, c->mask,
-                                         (const float *)L0.r, (float *)L0.e);
+  return run_solve(
+      c, c->p.check_every, learn, "sweeps",
+      [&](int m) -> int {
+        for (int s2 = 0; s2 < m; ++s2)
+          for (int col = 0; col < 4; ++col) {
+            int rc = run(c, KK_SOR32, [&] {
+              return launch_mg_smooth<float>(c->stream, L0.lv, c->p.omega, col, c->mask,
+                                             (const float *)L0.r, (float *)L0.e, c->ctl);
+            });
+            if (rc) return rc;
+          }
+        return run(c, KK_CORRECT, [&] {
+          return launch_mg_correct<float>(c->stream, L0.lv.n, c->mask, (const float *)L0.e,
+                                          c->phi, c->ctl);
         });
-        if (rc) return rc;
-      }
-    rc = run(c, KK_CORRECT, [&] {
-      return launch_mg_correct<float>(c->stream, L0.lv.n, c->mask, (const float *)L0.e, c->phi);
-    });
-    if (rc) return rc;
-    sweeps += m;
-  }
-  c->total_iters += sweeps;
-  return LBE_OK;
+      },
+      [&](int add) -> int {
+        return run(c, KK_MG_RESID, [&] {
+          return launch_mg_outer_resid<float>(c->stream, L0.lv, c->mask, c->src, c->phi,
+                                              (float *)L0.r, (float *)L0.e, c->partial, c->ctl,
+                                              add);
+        });
+      });
 }
 
-int poisson_solve(lbe_ctx *c) {
-  if (c->mixed) return c->p.poisson == LBE_MG ? mg_solve<float>(c) : mixed_sor_solve(c);
-  if (c->p.poisson == LBE_MG) return mg_solve<double>(c);
-  return sor_solve(c);
+// learn: remember the iteration count to size the next time step's queue
+int poisson_solve(lbe_ctx *c, bool learn) {
+  if (c->mixed) return c->p.poisson == LBE_MG ? mg_solve<float>(c, learn) : mixed_sor_solve(c, learn);
+  if (c->p.poisson == LBE_MG) return mg_solve<double>(c, learn);
+  return sor_solve(c, learn);
 }
 
 int charges_to(lbe_ctx *c, double *dst) {
@@ -637,7 +831,7 @@ int charges_to(lbe_ctx *c, double *dst) {
   const double q_scale = -6.0 / (4.0 * M_PI * c->p.lB);
   return run(c, KK_CHARGE, [&] {
     return launch_charge(c->stream, c->L, q_scale, c->mask, c->phi, c->iface, c->blk_elec,
-                         c->blk_begin, c->blk_end, c->nblk_charge, c->ne, c->partial, c->counter,
+                         c->blk_begin, c->blk_end, c->nblk_charge, c->ne, c->partial,
                          dst);
   });
 }
@@ -671,7 +865,13 @@ int one_step(lbe_ctx *c) {
   if (rc) return rc;
   c->cur = b;
   c->step++;
-  rc = poisson_solve(c);
+  if (c->phi_prev) {
+    rc = run(c, KK_EXTRAP, [&] {
+      return launch_extrapolate(c->stream, c->L, c->mask, c->phi, c->phi_prev);
+    });
+    if (rc) return rc;
+  }
+  rc = poisson_solve(c, true);
   if (rc) return rc;
   return record_charge(c);
 }
@@ -679,9 +879,9 @@ int one_step(lbe_ctx *c) {
 void free_ctx(lbe_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  void *ptrs[] = {c->mask, c->phi, c->src, c->u, c->n[0], c->n[1], c->f[0], c->f[1],
+  void *ptrs[] = {c->mask, c->phi, c->phi_prev, c->src, c->u, c->n[0], c->n[1], c->f[0], c->f[1],
                   c->h32[0], c->h32[1], c->nu32[0], c->nu32[1], c->u32, c->obs,
-                  c->partial, c->counter, c->dout, c->iface, c->blk_elec, c->blk_begin,
+                  c->partial, c->dout, c->ctl, c->iface, c->blk_elec, c->blk_begin,
                   c->blk_end, c->qcur, c->qhist};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
@@ -690,7 +890,11 @@ void free_ctx(lbe_ctx *c) {
     if (L.e) (void)hipFree(L.e);
     if (L.r) (void)hipFree(L.r);
   }
+  if (c->unit_exec) (void)hipGraphExecDestroy(c->unit_exec);
+  if (c->mg_ainv) (void)hipFree(c->mg_ainv);
+  if (c->mg_fcell) (void)hipFree(c->mg_fcell);
   if (c->hpin) (void)hipHostFree(c->hpin);
+  if (c->ctl_h) (void)hipHostFree(c->ctl_h);
   for (int k = 0; k < KK_COUNT; ++k)
     for (auto &pr : c->pending[k]) {
       (void)hipEventDestroy(pr.first);
@@ -817,6 +1021,10 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
   c->P.src_scale = 4.0 * M_PI * p.lB / 6.0;
   c->P.omega = p.omega;
   c->mixed = p.precision == LBE_FP32_MIXED;
+  {
+    const char *ng = getenv("LBE_NO_GRAPHS");
+    c->use_graphs = !(ng && *ng && *ng != '0');
+  }
   c->type_h.assign(type, type + N);
   // references of the mixed form: n_ref, else the fluid mean of n_init
   {
@@ -882,8 +1090,12 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
       }
     }
     TRY(dalloc(c, &c->partial, npart));
-    TRY(dalloc(c, &c->counter, 1));
     TRY(dalloc(c, &c->dout, 16));
+    TRY(dalloc(c, &c->ctl, 1));
+    if (hipHostMalloc((void **)&c->ctl_h, sizeof(SolveCtl)) != hipSuccess) {
+      rc = fail(c, LBE_ENOMEM, "pinned host buffer");
+      goto fail_;
+    }
     TRY(dalloc(c, &c->iface, g.iface.size()));
     TRY(dalloc(c, &c->blk_elec, g.blk_elec.size()));
     TRY(dalloc(c, &c->blk_begin, g.blk_begin.size()));
@@ -943,8 +1155,7 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
     TRY(up(c->blk_begin, g.blk_begin.data(), sizeof(int) * g.blk_begin.size()));
     TRY(up(c->blk_end, g.blk_end.data(), sizeof(int) * g.blk_end.size()));
     if ((c->u && hipMemsetAsync(c->u, 0, sizeof(double) * 3 * N, c->stream) != hipSuccess) ||
-        (c->u32 && hipMemsetAsync(c->u32, 0, sizeof(float) * 3 * N, c->stream) != hipSuccess) ||
-        hipMemsetAsync(c->counter, 0, sizeof(unsigned), c->stream) != hipSuccess) {
+        (c->u32 && hipMemsetAsync(c->u32, 0, sizeof(float) * 3 * N, c->stream) != hipSuccess)) {
       rc = fail(c, LBE_EDEVICE, "memset failed");
       goto fail_;
     }
@@ -955,8 +1166,16 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
     }
   }
   if (p.poisson == LBE_MG || c->mixed) TRY(build_multigrid(c, type, p.poisson != LBE_MG));
-  TRY(poisson_solve(c));
+  TRY(poisson_solve(c, false));
   TRY(record_charge(c));
+  if (p.flags & LBE_EXTRAPOLATE) {
+    TRY(dalloc(c, &c->phi_prev, N));
+    if (hipMemcpyAsync(c->phi_prev, c->phi, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                       c->stream) != hipSuccess) {
+      rc = fail(c, LBE_EDEVICE, "copy failed");
+      goto fail_;
+    }
+  }
   if (hipStreamSynchronize(c->stream) != hipSuccess) {
     rc = fail(c, LBE_EDEVICE, "stream synchronize failed");
     goto fail_;
@@ -981,7 +1200,7 @@ int lbe_step(lbe_ctx *c, int64_t nsteps) {
 
 int lbe_poisson(lbe_ctx *c, int32_t *iters, double *resid) {
   if (!c) return fail(c, LBE_EINVAL, "context is NULL");
-  int rc = poisson_solve(c);
+  int rc = poisson_solve(c, false);
   if (iters) *iters = c->last_iters;
   if (resid) *resid = c->last_resid;
   return rc;
@@ -1008,9 +1227,9 @@ int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double 
     rc = run(c, KK_TOTALS, [&] {
       if (c->mixed)
         return launch_totals_f32(c->stream, c->L, c->P, c->mask, c->h32[c->cur], c->nu32[c->cur],
-                                 c->partial, c->counter, c->dout);
+                                 c->partial, c->dout);
       return launch_totals_f64(c->stream, c->L, K, c->p.z, c->mask, c->f[c->cur], c->n[c->cur],
-                               c->partial, c->counter, c->dout);
+                               c->partial, c->dout);
     });
     if (rc) return rc;
     rc = read_scalars(c, 2 + K);

@@ -38,12 +38,6 @@ __device__ __forceinline__ int nbr(const Offs &o, int r, int i) {
 
 __device__ __forceinline__ bool solid_link(uint32_t m, int i) { return (m >> (i - 1)) & 1u; }
 
-// Excess (electrostatic) part of the symmetrised link flux of Eq. 10:
-//   g = -[n' expm1(delta) - n expm1(-delta)] / (2 Delta),
-// with delta = z (phi' - phi - E . c_i); the ideal part is -(n' - n)/Delta.
-__device__ __forceinline__ double excess_link(double nh, double nt, double delta, double inv2len) {
-  return -(nt * expm1(delta) - nh * expm1(-delta)) * inv2len;
-}
 
 // NaN-propagating max
 __device__ __forceinline__ double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
@@ -74,15 +68,118 @@ __device__ double block_sum(double v, double *sm) {
   return v;
 }
 
-// True in every thread of the last block to arrive.  The caller's thread 0
-// must have written its partial before the call.
-__device__ bool arrive_last(unsigned *counter) {
-  __shared__ bool last;
-  __threadfence();
-  if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+// ---- second stage of the reductions: one block combines the per-block
+// partials in a fixed order (the kernel boundary orders the partial writes
+// before these reads, with no device-wide fence in the first stage).
+
+// out[0] = max over partial[0..nb)
+__global__ __launch_bounds__(BLOCK) void k_final_max(const double *__restrict__ partial, int nb,
+                                                     double *__restrict__ out) {
+  __shared__ double tree[BLOCK];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += BLOCK) v = nanmax(v, partial[b]);
+  tree[threadIdx.x] = v;
   __syncthreads();
-  if (last) __threadfence();
-  return last;
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) tree[threadIdx.x] = nanmax(tree[threadIdx.x], tree[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = tree[0];
+}
+
+// Residual check of a Poisson solve: max over the block maxima into
+// ctl->resid; marks the solve done when the residual is <= tol or not finite.
+__global__ __launch_bounds__(BLOCK) void k_final_resid(const double *__restrict__ partial, int nb,
+                                                       SolveCtl *__restrict__ ctl, int add) {
+  __shared__ double tree[BLOCK];
+  if (ctl->done) return;
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += BLOCK) v = nanmax(v, partial[b]);
+  tree[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) tree[threadIdx.x] = nanmax(tree[threadIdx.x], tree[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double res = tree[0];
+    const int count = ctl->count + add;
+    ctl->count = count;
+    ctl->resid = res;
+    ctl->checks += 1;
+    const bool bad = !(res == res) || res > 1.7976931348623157e308;
+    if (bad || (ctl->tol > 0.0 && res <= ctl->tol)) {
+      ctl->done = 1;
+      ctl->iters = count;
+      ctl->nonfinite = bad;
+    }
+  }
+}
+
+// out[q] = sum over partial[q*nb .. q*nb + nb), q < nq (fixed pairwise order)
+__global__ __launch_bounds__(BLOCK) void k_final_sum(const double *__restrict__ partial, int nb,
+                                                     int nq, double *__restrict__ out) {
+  __shared__ double tree[BLOCK];
+  for (int q = 0; q < nq; ++q) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BLOCK) v += partial[q * nb + b];
+    tree[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = tree[0];
+    __syncthreads();
+  }
+}
+
+// ---- the link-flux exponentials -------------------------------------------
+// The symmetrised flux of Eq. 10 needs n' e^delta - n e^-delta.  Writing
+// e^(+-delta) = 1 + C +- S with S = sinh(delta), C = cosh(delta) - 1 gives
+//   n' expm1(delta) - n expm1(-delta) = (n' + n) S + (n' - n) C
+// exactly.  For |delta| <= 1/2 both come from their Taylor series (next
+// terms below 1e-17 relative); beyond, from expm1.
+
+__device__ __forceinline__ void sinh_coshm1(double d, double &S, double &C) {
+  if (fabs(d) <= 0.5) {
+    const double x = d * d;
+    S = d * (1.0 + x * (1.0 / 6 + x * (1.0 / 120 + x * (1.0 / 5040 + x * (1.0 / 362880 +
+             x * (1.0 / 39916800 + x * (1.0 / 6227020800.0)))))));
+    C = x * (0.5 + x * (1.0 / 24 + x * (1.0 / 720 + x * (1.0 / 40320 + x * (1.0 / 3628800 +
+             x * (1.0 / 479001600 + x * (1.0 / 87178291200.0)))))));
+  } else {
+    const double ep = expm1(d), em = expm1(-d);
+    S = 0.5 * (ep - em);
+    C = 0.5 * (ep + em);
+  }
+}
+
+// Excess (electrostatic) part of the symmetrised link flux of Eq. 10:
+//   g = -[n' expm1(delta) - n expm1(-delta)] / (2 Delta),
+// with delta = z (phi' - phi - E . c_i); the ideal part is -(n' - n)/Delta.
+__device__ __forceinline__ double excess_link(double nh, double nt, double delta, double inv2len) {
+  double S, C;
+  sinh_coshm1(delta, S, C);
+  return -((nt + nh) * S + (nt - nh) * C) * inv2len;
+}
+
+__device__ __forceinline__ void sinh_coshm1f(float d, float &S, float &C) {
+  if (fabsf(d) <= 0.5f) {
+    const float x = d * d;
+    S = d * (1.f + x * (1.f / 6 + x * (1.f / 120 + x * (1.f / 5040 + x * (1.f / 362880)))));
+    C = x * (0.5f + x * (1.f / 24 + x * (1.f / 720 + x * (1.f / 40320 + x * (1.f / 3628800)))));
+  } else {
+    const float ep = expm1f(d), em = expm1f(-d);
+    S = 0.5f * (ep - em);
+    C = 0.5f * (ep + em);
+  }
+}
+
+__device__ __forceinline__ float excess_link_f(float nh, float nt, float delta, float inv2len) {
+  float S, C;
+  sinh_coshm1f(delta, S, C);
+  return -((nt + nh) * S + (nt - nh) * C) * inv2len;
 }
 
 inline unsigned blocks_for(long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }

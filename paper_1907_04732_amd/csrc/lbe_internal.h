@@ -66,6 +66,37 @@ struct MgTransfer {
   int ox, oy, oz;
 };
 
+// Device-side control of one Poisson solve.  The residual check sets `done`
+// once ||R||_inf <= tol (or the residual is not finite); every kernel of the
+// solve returns at once when `done` is set, so the host can queue a predicted
+// number of sweeps or cycles and synchronise once.
+struct SolveCtl {
+  double resid;   // last residual inf-norm
+  double tol;     // <= 0: never done (fixed iteration count)
+  int done;
+  int iters;      // sweeps or cycles completed when done was set
+  int checks;     // residual evaluations so far
+  int nonfinite;  // the residual was NaN or Inf
+  int count;      // sweeps or cycles completed so far (each check adds its unit)
+  int pad;
+};
+
+// The coarse end of the hierarchy handled by one work-group in LDS.
+constexpr int MG_MAX_SMALL = 8;
+struct MgSmall {
+  int nlev;                               // levels in the set; the last is the coarsest
+  MgLevel lv[MG_MAX_SMALL];
+  MgTransfer tr[MG_MAX_SMALL];            // tr[k]: level k-1 -> k, k >= 1
+  const uint32_t *mask[MG_MAX_SMALL];
+  int off_e[MG_MAX_SMALL], off_r[MG_MAX_SMALL], off_m[MG_MAX_SMALL];  // LDS offsets (elements)
+  int nu1, nu2;
+  int nf;                                 // coarsest exact solve: fluid cells, inverse, cells
+  const void *ainv;
+  const int *fcell;
+  int coarse_sweeps;
+  double omega;
+};
+
 enum KernelKind {
   KK_FLUID = 0,   // force + LB collide/stream (pull), writes u
   KK_IONS,        // ion link fluxes + update, writes Poisson source
@@ -77,10 +108,13 @@ enum KernelKind {
   KK_SOR32,       // one colour of the FP32 correction sweep
   KK_CORRECT,     // phi += e
   KK_MG_RESID,    // outer FP64 residual feeding the multigrid correction
-  KK_MG_SMOOTH,   // one colour of the level smoother
+  KK_MG_SMOOTH,   // one colour of the smoother on a coarse level
+  KK_MG_SMOOTH0,  // one colour of the smoother on the finest level
   KK_MG_RESTRICT, // residual + restriction to the next level
   KK_MG_PROLONG,  // trilinear prolongation + correction
   KK_MG_COARSE,   // coarsest-level solve in one work-group
+  KK_EXTRAP,      // warm start phi <- 2 phi - phi_prev
+  KK_MG_SMALL,    // the coarse levels of a V-cycle in one work-group
   KK_COUNT
 };
 
@@ -95,24 +129,30 @@ hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const
                            const double *phi, const double *u, const double *n, double *nout,
                            double *src);
 hipError_t launch_sor_f64(hipStream_t s, const Lattice &L, const Phys &P, int colour,
-                          const uint32_t *mask, const double *src, double *phi);
-// residual inf-norm over fluid nodes into *out (device); partial/counter are
-// scratch of size >= residual_blocks(L) and 1
+                          const uint32_t *mask, const double *src, double *phi,
+                          const SolveCtl *ctl);
+// residual inf-norm over fluid nodes into *out (device); partial is scratch
+// of size >= residual_blocks(L)
 int residual_blocks(const Lattice &L);
+// residual check after `add` more iterations: ||R||_inf into ctl->resid;
+// sets ctl->done (with iters = the iterations counted so far)
 hipError_t launch_resid_f64(hipStream_t s, const Lattice &L, const uint32_t *mask,
-                            const double *src, const double *phi, double *partial,
-                            unsigned *counter, double *out);
+                            const double *src, const double *phi, double *partial, SolveCtl *ctl,
+                            int add);
 hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
                          const double *phi, const int *iface_site, const int *blk_elec,
                          const int *blk_begin, const int *blk_end, int nblocks, int ne,
-                         double *partial, unsigned *counter, double *out);
+                         double *partial, double *out);
 hipError_t launch_totals_f64(hipStream_t s, const Lattice &L, int K, const int *z,
                              const uint32_t *mask, const double *fin, const double *n,
-                             double *partial, unsigned *counter, double *out /*2+K*/);
+                             double *partial, double *out /*2+K*/);
 hipError_t launch_observe_f64(hipStream_t s, const Lattice &L, const Phys &P,
                               const uint32_t *mask, const double *phi, const double *n,
                               const double *fin, double *fpre, double *u);
 int totals_blocks(const Lattice &L);
+// on fluid nodes: phi_prev <- phi, phi <- 2 phi - phi_prev (linear extrapolation in time)
+hipError_t launch_extrapolate(hipStream_t s, const Lattice &L, const uint32_t *mask, double *phi,
+                              double *phi_prev);
 
 // mixed form (lbe_kernels_f32.hip): h = f - w rho0 and nu = n - n_ref in FP32
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
@@ -125,27 +165,38 @@ hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
                               const uint32_t *mask, const double *phi, const float *nu,
                               const float *hin, double *fpre, double *u);
 hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                             const float *hin, const float *nu, double *partial,
-                             unsigned *counter, double *out);
+                             const float *hin, const float *nu, double *partial, double *out);
 
 // multigrid (lbe_mg.hip); T = double (FP64 form) or float (mixed form)
 template <class T>
 hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
                                  const double *src, const double *phi, T *r0, T *e0,
-                                 double *partial, unsigned *counter, double *out);
+                                 double *partial, SolveCtl *ctl, int add);
 template <class T>
 hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int colour,
-                            const uint32_t *mask, const T *rhs, T *e);
+                            const uint32_t *mask, const T *rhs, T *e, const SolveCtl *ctl);
 template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
-                              const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec);
+                              const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
+                              const SolveCtl *ctl);
 template <class T>
 hipError_t launch_mg_prolong(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
-                             const uint32_t *mc, const T *ec, T *ef);
+                             const uint32_t *mc, const T *ec, T *ef, const SolveCtl *ctl);
 template <class T>
 hipError_t launch_mg_coarse(hipStream_t s, const MgLevel &lv, double omega, int sweeps,
-                            const uint32_t *mask, const T *rhs, T *e);
+                            const uint32_t *mask, const T *rhs, T *e, const SolveCtl *ctl);
 template <class T>
-hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T *e, double *phi);
+hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T *e, double *phi,
+                             const SolveCtl *ctl);
+// coarse end of a V-cycle in one work-group; r_in/e_out on the set's finest level
+template <class T>
+hipError_t launch_mg_small(hipStream_t s, const MgSmall &S, size_t lds_bytes, const T *r_in,
+                           T *e_out, const SolveCtl *ctl);
+template <class T>
+hipError_t prepare_mg_small(size_t lds_bytes);
+// coarsest level by a dense precomputed inverse over its nf fluid cells
+template <class T>
+hipError_t launch_mg_coarse_dense(hipStream_t s, int nf, const T *ainv, const int *fcell,
+                                  const T *rhs, T *e, const SolveCtl *ctl);
 
 }  // namespace lbe

@@ -21,7 +21,7 @@ namespace lbe {
 
 const char *const kKernelNames[KK_COUNT] = {
     "fluid", "ions", "sor", "resid", "charge", "totals", "observe", "sor32", "correct",
-    "mg_resid", "mg_smooth", "mg_restrict", "mg_prolong", "mg_coarse"};
+    "mg_resid", "mg_smooth", "mg_smooth0", "mg_restrict", "mg_prolong", "mg_coarse", "extrap", "mg_small"};
 
 namespace {
 
@@ -180,7 +180,9 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f64(Lattice L, Phys P,
 __global__ __launch_bounds__(BLOCK) void k_sor_f64(Lattice L, double omega, int colour, int hx,
                                                    int hy, const uint32_t *__restrict__ mask,
                                                    const double *__restrict__ src,
-                                                   double *__restrict__ phi) {
+                                                   double *__restrict__ phi,
+                                                   const SolveCtl *__restrict__ ctl) {
+  if (ctl->done) return;
   const int t = blockIdx.x * BLOCK + threadIdx.x;
   const int plane = hx * hy;
   if (t >= plane * L.nz) return;
@@ -208,15 +210,15 @@ __global__ __launch_bounds__(BLOCK) void k_sor_f64(Lattice L, double omega, int 
   phi[r] = (1.0 - omega) * phi[r] + omega * (num / den);
 }
 
-// residual R = L_h phi + 4 pi l_B rho_el = 6 [sum_i w_i s_i (phi' - phi) + src]
+// residual R = L_h phi + 4 pi l_B rho_el = 6 [sum_i w_i s_i (phi' - phi) + src];
+// block maxima of |R| into partial[] (second stage: k_final_max)
 __global__ __launch_bounds__(BLOCK) void k_resid_f64(Lattice L, const uint32_t *__restrict__ mask,
                                                      const double *__restrict__ src,
                                                      const double *__restrict__ phi,
                                                      double *__restrict__ partial,
-                                                     unsigned *__restrict__ counter,
-                                                     double *__restrict__ out) {
+                                                     const SolveCtl *__restrict__ ctl) {
   __shared__ double sm[BLOCK / WAVE];
-  __shared__ double tree[BLOCK];
+  if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   double a = 0.0;
   if (r < L.n) {
@@ -237,20 +239,6 @@ __global__ __launch_bounds__(BLOCK) void k_resid_f64(Lattice L, const uint32_t *
   }
   a = block_max(a, sm);
   if (threadIdx.x == 0) partial[blockIdx.x] = a;
-  if (arrive_last(counter)) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) v = nanmax(v, partial[b]);
-    tree[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) tree[threadIdx.x] = nanmax(tree[threadIdx.x], tree[threadIdx.x + s]);
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      out[0] = tree[0];
-      atomicExch(counter, 0u);
-    }
-  }
 }
 
 // ---- electrode charge (Eq. 16): Q_e = -(6/4 pi l_B) sum over the electrode's
@@ -260,12 +248,9 @@ __global__ __launch_bounds__(BLOCK) void k_charge(Lattice L, double q_scale,
                                                   const uint32_t *__restrict__ mask,
                                                   const double *__restrict__ phi,
                                                   const int *__restrict__ iface_site,
-                                                  const int *__restrict__ blk_elec,
                                                   const int *__restrict__ blk_begin,
-                                                  const int *__restrict__ blk_end, int ne,
-                                                  double *__restrict__ partial,
-                                                  unsigned *__restrict__ counter,
-                                                  double *__restrict__ out) {
+                                                  const int *__restrict__ blk_end,
+                                                  double *__restrict__ partial) {
   __shared__ double sm[BLOCK / WAVE];
   const int b = blockIdx.x;
   const int idx = blk_begin[b] + threadIdx.x;
@@ -286,21 +271,22 @@ __global__ __launch_bounds__(BLOCK) void k_charge(Lattice L, double q_scale,
   }
   v = block_sum(v, sm);
   if (threadIdx.x == 0) partial[b] = v;
-  if (arrive_last(counter)) {
-    // per electrode, Neumaier-compensated sum of its blocks in block order
-    for (int e = threadIdx.x; e < ne; e += BLOCK) {
-      double s = 0.0, c = 0.0;
-      for (int k = 0; k < (int)gridDim.x; ++k) {
-        if (blk_elec[k] != e) continue;
-        const double x = partial[k];
-        const double t = s + x;
-        c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-        s = t;
-      }
-      out[e] = s + c;
+}
+
+// per electrode, Neumaier-compensated sum of its blocks in block order
+__global__ __launch_bounds__(BLOCK) void k_final_charge(const double *__restrict__ partial,
+                                                        const int *__restrict__ blk_elec, int nb,
+                                                        int ne, double *__restrict__ out) {
+  for (int e = threadIdx.x; e < ne; e += BLOCK) {
+    double s = 0.0, c = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      if (blk_elec[k] != e) continue;
+      const double x = partial[k];
+      const double t = s + x;
+      c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
+      s = t;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
+    out[e] = s + c;
   }
 }
 
@@ -310,16 +296,13 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f64(Lattice L, int K, int4 zk,
                                                       const uint32_t *__restrict__ mask,
                                                       const double *__restrict__ fin,
                                                       const double *__restrict__ n,
-                                                      double *__restrict__ partial,
-                                                      unsigned *__restrict__ counter,
-                                                      double *__restrict__ out) {
+                                                      double *__restrict__ partial) {
   __shared__ double sm[BLOCK / WAVE];
-  __shared__ double tree[BLOCK];
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   const int N = L.n;
   const int nq = 2 + K;
   const int zz[4] = {zk.x, zk.y, zk.z, zk.w};
-  bool fluid = r < N && !(mask[r] & SOLID_BIT);
+  const bool fluid = r < N && !(mask[r] & SOLID_BIT);
   for (int q = 0; q < nq; ++q) {
     double v = 0.0;
     if (fluid) {
@@ -333,21 +316,6 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f64(Lattice L, int K, int4 zk,
     }
     v = block_sum(v, sm);
     if (threadIdx.x == 0) partial[q * gridDim.x + blockIdx.x] = v;
-  }
-  if (arrive_last(counter)) {
-    for (int q = 0; q < nq; ++q) {
-      double v = 0.0;
-      for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) v += partial[q * gridDim.x + b];
-      tree[threadIdx.x] = v;
-      __syncthreads();
-      for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) out[q] = tree[0];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
   }
 }
 
@@ -394,6 +362,17 @@ __global__ __launch_bounds__(BLOCK) void k_observe_f64(Lattice L, Phys P,
   u[2 * N + r] = (m2 + 0.5 * F2) / rho;
 }
 
+// warm start of the next Poisson solve by linear extrapolation in time
+__global__ __launch_bounds__(BLOCK) void k_extrapolate(int n, const uint32_t *__restrict__ mask,
+                                                       double *__restrict__ phi,
+                                                       double *__restrict__ phi_prev) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= n || (mask[r] & SOLID_BIT)) return;
+  const double now = phi[r];
+  phi[r] = 2.0 * now - phi_prev[r];
+  phi_prev[r] = now;
+}
+
 }  // namespace
 
 // ---- launchers ------------------------------------------------------------
@@ -427,11 +406,19 @@ hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const
 }
 
 hipError_t launch_sor_f64(hipStream_t s, const Lattice &L, const Phys &P, int colour,
-                          const uint32_t *mask, const double *src, double *phi) {
+                          const uint32_t *mask, const double *src, double *phi,
+                          const SolveCtl *ctl) {
   const int hx = (L.nx + 1) / 2, hy = (L.ny + 1) / 2;
   const long threads = (long)hx * hy * L.nz;
   hipLaunchKernelGGL(k_sor_f64, dim3(blocks_for(threads)), dim3(BLOCK), 0, s, L, P.omega, colour,
-                     hx, hy, mask, src, phi);
+                     hx, hy, mask, src, phi, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_extrapolate(hipStream_t s, const Lattice &L, const uint32_t *mask, double *phi,
+                              double *phi_prev) {
+  hipLaunchKernelGGL(k_extrapolate, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L.n, mask, phi,
+                     phi_prev);
   return hipGetLastError();
 }
 
@@ -439,29 +426,33 @@ int residual_blocks(const Lattice &L) { return (int)blocks_for(L.n); }
 int totals_blocks(const Lattice &L) { return (int)blocks_for(L.n); }
 
 hipError_t launch_resid_f64(hipStream_t s, const Lattice &L, const uint32_t *mask,
-                            const double *src, const double *phi, double *partial,
-                            unsigned *counter, double *out) {
-  hipLaunchKernelGGL(k_resid_f64, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, mask, src, phi,
-                     partial, counter, out);
+                            const double *src, const double *phi, double *partial, SolveCtl *ctl,
+                            int add) {
+  const int nb = (int)blocks_for(L.n);
+  hipLaunchKernelGGL(k_resid_f64, dim3(nb), dim3(BLOCK), 0, s, L, mask, src, phi, partial, ctl);
+  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(BLOCK), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
 
 hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
                          const double *phi, const int *iface_site, const int *blk_elec,
                          const int *blk_begin, const int *blk_end, int nblocks, int ne,
-                         double *partial, unsigned *counter, double *out) {
+                         double *partial, double *out) {
   if (nblocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_charge, dim3(nblocks), dim3(BLOCK), 0, s, L, q_scale, mask, phi,
-                     iface_site, blk_elec, blk_begin, blk_end, ne, partial, counter, out);
+                     iface_site, blk_begin, blk_end, partial);
+  hipLaunchKernelGGL(k_final_charge, dim3(1), dim3(BLOCK), 0, s, partial, blk_elec, nblocks, ne,
+                     out);
   return hipGetLastError();
 }
 
 hipError_t launch_totals_f64(hipStream_t s, const Lattice &L, int K, const int *z,
                              const uint32_t *mask, const double *fin, const double *n,
-                             double *partial, unsigned *counter, double *out) {
+                             double *partial, double *out) {
   int4 zk = make_int4(z[0], K > 1 ? z[1] : 0, K > 2 ? z[2] : 0, K > 3 ? z[3] : 0);
-  hipLaunchKernelGGL(k_totals_f64, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, K, zk, mask, fin,
-                     n, partial, counter, out);
+  const int nb = (int)blocks_for(L.n);
+  hipLaunchKernelGGL(k_totals_f64, dim3(nb), dim3(BLOCK), 0, s, L, K, zk, mask, fin, n, partial);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(BLOCK), 0, s, partial, nb, 2 + K, out);
   return hipGetLastError();
 }
 

@@ -17,10 +17,6 @@
 namespace lbe {
 namespace {
 
-__device__ __forceinline__ float excess_link_f(float nh, float nt, float delta, float inv2len) {
-  return -(nt * expm1f(delta) - nh * expm1f(-delta)) * inv2len;
-}
-
 template <int K>
 __device__ __forceinline__ void link_force_f32(const Lattice &L, const Phys &P, int r, uint32_t m,
                                                const Offs &o, const double *__restrict__ phi,
@@ -216,11 +212,8 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f32(Lattice L, Phys P,
                                                       const uint32_t *__restrict__ mask,
                                                       const float *__restrict__ hin,
                                                       const float *__restrict__ nu,
-                                                      double *__restrict__ partial,
-                                                      unsigned *__restrict__ counter,
-                                                      double *__restrict__ out) {
+                                                      double *__restrict__ partial) {
   __shared__ double sm[BLOCK / WAVE];
-  __shared__ double tree[BLOCK];
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   const int N = L.n;
   const int K = P.K;
@@ -240,21 +233,6 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f32(Lattice L, Phys P,
     }
     v = block_sum(v, sm);
     if (threadIdx.x == 0) partial[q * gridDim.x + blockIdx.x] = v;
-  }
-  if (arrive_last(counter)) {
-    for (int q = 0; q < nq; ++q) {
-      double v = 0.0;
-      for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) v += partial[q * gridDim.x + b];
-      tree[threadIdx.x] = v;
-      __syncthreads();
-      for (int s = BLOCK / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) out[q] = tree[0];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
   }
 }
 
@@ -299,10 +277,10 @@ hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
 }
 
 hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                             const float *hin, const float *nu, double *partial,
-                             unsigned *counter, double *out) {
-  hipLaunchKernelGGL(k_totals_f32, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, hin, nu,
-                     partial, counter, out);
+                             const float *hin, const float *nu, double *partial, double *out) {
+  const int nb = (int)blocks_for(L.n);
+  hipLaunchKernelGGL(k_totals_f32, dim3(nb), dim3(BLOCK), 0, s, L, P, mask, hin, nu, partial);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(BLOCK), 0, s, partial, nb, 2 + P.K, out);
   return hipGetLastError();
 }
 

@@ -21,13 +21,12 @@
 // global memory with barriers between colours.
 #include <math.h>
 
+#include "lbe_device.h"
 #include "lbe_internal.h"
 
 namespace lbe {
 namespace {
 
-constexpr int BLOCK = 256;
-constexpr int WAVE = 64;
 constexpr int COARSE_BLOCK = 1024;
 
 struct Coords {
@@ -48,10 +47,6 @@ __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >
 __device__ __forceinline__ int nbr_of(const MgLevel &lv, const Coords &c, int i) {
   return wrapi(c.x + CX[i], lv.nx) + lv.nx * (wrapi(c.y + CY[i], lv.ny) + lv.ny * wrapi(c.z + CZ[i], lv.nz));
 }
-
-__device__ __forceinline__ bool solid_link(uint32_t m, int i) { return (m >> (i - 1)) & 1u; }
-
-__device__ __forceinline__ double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
 
 // A e at a fluid cell, in the level's units: (6/h^2) sum_i w_i s_i (e - e_i)
 template <class T>
@@ -76,11 +71,9 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
                                                        const double *__restrict__ phi,
                                                        T *__restrict__ r0, T *__restrict__ e0,
                                                        double *__restrict__ partial,
-                                                       unsigned *__restrict__ counter,
-                                                       double *__restrict__ out) {
+                                                       const SolveCtl *__restrict__ ctl) {
   __shared__ double sm[BLOCK / WAVE];
-  __shared__ double tree[BLOCK];
-  __shared__ bool last;
+  if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   double a = 0.0;
   if (r < lv.n) {
@@ -102,32 +95,8 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
     r0[r] = T(R);
     e0[r] = T(0);
   }
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) a = nanmax(a, __shfl_xor(a, off));
-  if ((threadIdx.x & (WAVE - 1)) == 0) sm[threadIdx.x / WAVE] = a;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 1; k < BLOCK / WAVE; ++k) a = nanmax(a, sm[k]);
-    partial[blockIdx.x] = a;
-    __threadfence();
-    last = atomicAdd(counter, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    double v = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += BLOCK) v = nanmax(v, partial[b]);
-    tree[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) tree[threadIdx.x] = nanmax(tree[threadIdx.x], tree[threadIdx.x + s]);
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      out[0] = tree[0];
-      atomicExch(counter, 0u);
-    }
-  }
+  a = block_max(a, sm);
+  if (threadIdx.x == 0) partial[blockIdx.x] = a;
 }
 
 // ---- smoother: one colour of Gauss-Seidel / SOR on A e = r ------------------
@@ -135,7 +104,9 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_smooth(MgLevel lv, T omega, int colour, int hx, int hy,
                                                   const uint32_t *__restrict__ mask,
-                                                  const T *__restrict__ rhs, T *__restrict__ e) {
+                                                  const T *__restrict__ rhs, T *__restrict__ e,
+                                                  const SolveCtl *__restrict__ ctl) {
+  if (ctl->done) return;
   const int t = blockIdx.x * BLOCK + threadIdx.x;
   const int plane = hx * hy;
   if (t >= plane * lv.nz) return;
@@ -170,7 +141,9 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(MgTransfer tr, const uint32_
                                                     const uint32_t *__restrict__ mc,
                                                     const T *__restrict__ rf,
                                                     const T *__restrict__ ef, T *__restrict__ rc,
-                                                    T *__restrict__ ec) {
+                                                    T *__restrict__ ec,
+                                                    const SolveCtl *__restrict__ ctl) {
+  if (ctl->done) return;
   const int R = blockIdx.x * BLOCK + threadIdx.x;
   if (R >= tr.c.n) return;
   ec[R] = T(0);
@@ -210,13 +183,11 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(MgTransfer tr, const uint32_
 
 // ---- prolongation: e_f += trilinear interpolation of e_c --------------------
 
+// trilinear interpolation of e_c at fine cell r (mirrored across solid cells)
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_prolong(MgTransfer tr, const uint32_t *__restrict__ mf,
-                                                   const uint32_t *__restrict__ mc,
-                                                   const T *__restrict__ ec, T *__restrict__ ef) {
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
-  if (r >= tr.f.n) return;
-  if (mf[r] & SOLID_BIT) return;
+__device__ __forceinline__ T prolong_value(const MgTransfer &tr, int r,
+                                           const uint32_t *__restrict__ mc,
+                                           const T *__restrict__ ec) {
   const Coords c = coords_of(r, tr.f.nx, tr.f.nxy);
   // position in the block re-indexing, parent cell and the nearer neighbour
   int P[3], Nb[3];
@@ -236,6 +207,7 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(MgTransfer tr, const uint32_t
     }
   }
   const int parent = P[0] + tr.c.nx * (P[1] + tr.c.ny * P[2]);
+  if (mc[parent] & SOLID_BIT) return T(0);
   const T ep = ec[parent];
   T v = T(0);
 #pragma unroll
@@ -250,8 +222,19 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(MgTransfer tr, const uint32_t
     const T val = (mc[R] & SOLID_BIT) ? -ep : ec[R];
     v += w * val;
   }
-  if (mc[parent] & SOLID_BIT) v = T(0);
-  ef[r] += v;
+  return v;
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_prolong(MgTransfer tr, const uint32_t *__restrict__ mf,
+                                                   const uint32_t *__restrict__ mc,
+                                                   const T *__restrict__ ec, T *__restrict__ ef,
+                                                   const SolveCtl *__restrict__ ctl) {
+  if (ctl->done) return;
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= tr.f.n) return;
+  if (mf[r] & SOLID_BIT) return;
+  ef[r] += prolong_value<T>(tr, r, mc, ec);
 }
 
 // ---- coarsest level: one work-group, colour sweeps with barriers ------------
@@ -260,7 +243,9 @@ template <class T>
 __global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, int sweeps,
                                                          const uint32_t *__restrict__ mask,
                                                          const T *__restrict__ rhs,
-                                                         T *__restrict__ e) {
+                                                         T *__restrict__ e,
+                                                         const SolveCtl *__restrict__ ctl) {
+  if (ctl->done) return;
   for (int s = 0; s < sweeps; ++s) {
     for (int col = 0; col < 4; ++col) {
       for (int r = threadIdx.x; r < lv.n; r += COARSE_BLOCK) {
@@ -285,85 +270,280 @@ __global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, in
   }
 }
 
+// ---- coarsest level, exact: e = A^-1 r over the level's fluid cells ----------
+// One wavefront per row of the precomputed inverse (row-major, nf x nf).
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_coarse_dense(int nf, const T *__restrict__ ainv,
+                                                        const int *__restrict__ fcell,
+                                                        const T *__restrict__ rhs,
+                                                        T *__restrict__ e,
+                                                        const SolveCtl *__restrict__ ctl) {
+  if (ctl->done) return;
+  const int row = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
+  if (row >= nf) return;
+  const T *a = ainv + (size_t)row * nf;
+  T acc = T(0);
+  for (int k = lane; k < nf; k += WAVE) acc += a[k] * rhs[fcell[k]];
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) e[fcell[row]] = acc;
+}
+
+// ---- the coarse end of the V-cycle in one work-group --------------------------
+// Levels S.lv[0..nlev-1] live in LDS (correction, right-hand side and flag
+// word per cell).  Same arithmetic as the multi-kernel path: four-colour
+// Gauss-Seidel, mean-of-children restriction, mirrored trilinear
+// prolongation, exact (dense inverse) or swept coarsest level.
+
+constexpr int SMALL_BLOCK = 1024;
+
+template <class T>
+__device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const uint32_t *sm) {
+  const MgLevel &lv = S.lv[k];
+  T *e = lds + S.off_e[k];
+  const T *rh = lds + S.off_r[k];
+  const uint32_t *mk = sm + S.off_m[k];
+  const int hx = (lv.nx + 1) / 2, hy = (lv.ny + 1) / 2, plane = hx * hy;
+  const T hs = T(lv.h2 / 6.0);
+  for (int s = 0; s < sweeps; ++s)
+    for (int col = 0; col < 4; ++col) {
+      for (int t = threadIdx.x; t < plane * lv.nz; t += SMALL_BLOCK) {
+        Coords c;
+        c.z = t / plane;
+        const int rem = t - c.z * plane;
+        const int iy = rem / hx, ix = rem - iy * hx;
+        c.x = 2 * ix + ((col ^ c.z) & 1);
+        c.y = 2 * iy + (((col >> 1) ^ c.z) & 1);
+        if (c.x >= lv.nx || c.y >= lv.ny) continue;
+        const int r = c.x + lv.nx * (c.y + lv.ny * c.z);
+        const uint32_t m = mk[r];
+        if (m & SOLID_BIT) continue;
+        T num = T(0), den = T(0);
+#pragma unroll
+        for (int i = 1; i < NQ; ++i) {
+          if ((lv.selfm >> (i - 1)) & 1u) continue;
+          const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
+          num += ws * e[nbr_of(lv, c, i)];
+          den += ws;
+        }
+        num += hs * rh[r];
+        e[r] = num / den;  // Gauss-Seidel (omega = 1)
+      }
+      __syncthreads();
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(SMALL_BLOCK) void k_mg_small(MgSmall S, const T *__restrict__ r_in,
+                                                          T *__restrict__ e_out,
+                                                          const SolveCtl *__restrict__ ctl) {
+  extern __shared__ double smem_raw[];
+  if (ctl->done) return;
+  T *lds = reinterpret_cast<T *>(smem_raw);
+  uint32_t *sm = reinterpret_cast<uint32_t *>(smem_raw);  // flag words, offsets in 4-byte units
+  // flags of every level, rhs and zero correction of the first
+  for (int k = 0; k < S.nlev; ++k)
+    for (int r = threadIdx.x; r < S.lv[k].n; r += SMALL_BLOCK) sm[S.off_m[k] + r] = S.mask[k][r];
+  for (int r = threadIdx.x; r < S.lv[0].n; r += SMALL_BLOCK) {
+    lds[S.off_r[0] + r] = r_in[r];
+    lds[S.off_e[0] + r] = T(0);
+  }
+  __syncthreads();
+  // down: smooth, restrict
+  for (int k = 0; k + 1 < S.nlev; ++k) {
+    small_smooth<T>(S, k, S.nu1, lds, sm);
+    const MgTransfer &tr = S.tr[k + 1];
+    const T *ef = lds + S.off_e[k];
+    const T *rf = lds + S.off_r[k];
+    const uint32_t *mf = sm + S.off_m[k];
+    const uint32_t *mc = sm + S.off_m[k + 1];
+    for (int R = threadIdx.x; R < tr.c.n; R += SMALL_BLOCK) {
+      lds[S.off_e[k + 1] + R] = T(0);
+      T val = T(0);
+      if (!(mc[R] & SOLID_BIT)) {
+        const Coords C = coords_of(R, tr.c.nx, tr.c.nxy);
+        T sum = T(0);
+        int cnt = 0;
+        for (int dz = 0; dz < 2; ++dz) {
+          const int zp = 2 * C.z + dz;
+          if (zp >= tr.f.nz) break;
+          const int z = wrapi(zp + tr.oz, tr.f.nz);
+          for (int dy = 0; dy < 2; ++dy) {
+            const int yp = 2 * C.y + dy;
+            if (yp >= tr.f.ny) break;
+            const int y = wrapi(yp + tr.oy, tr.f.ny);
+            for (int dx = 0; dx < 2; ++dx) {
+              const int xp = 2 * C.x + dx;
+              if (xp >= tr.f.nx) break;
+              const int x = wrapi(xp + tr.ox, tr.f.nx);
+              const int r = x + tr.f.nx * (y + tr.f.ny * z);
+              const uint32_t m = mf[r];
+              if (m & SOLID_BIT) continue;
+              Coords c;
+              c.x = x;
+              c.y = y;
+              c.z = z;
+              sum += rf[r] - apply_A<T>(tr.f, r, m, c, ef);
+              ++cnt;
+            }
+          }
+        }
+        val = cnt ? sum / T(cnt) : T(0);
+      }
+      lds[S.off_r[k + 1] + R] = val;
+    }
+    __syncthreads();
+  }
+  // coarsest
+  {
+    const int k = S.nlev - 1;
+    T *e = lds + S.off_e[k];
+    const T *rh = lds + S.off_r[k];
+    if (S.ainv) {
+      const T *ainv = reinterpret_cast<const T *>(S.ainv);
+      const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+      for (int row = wv; row < S.nf; row += SMALL_BLOCK / WAVE) {
+        const T *a = ainv + (size_t)row * S.nf;
+        T acc = T(0);
+        for (int j = lane; j < S.nf; j += WAVE) acc += a[j] * rh[S.fcell[j]];
+#pragma unroll
+        for (int off = WAVE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) e[S.fcell[row]] = acc;
+      }
+      __syncthreads();
+    } else {
+      small_smooth<T>(S, k, S.coarse_sweeps, lds, sm);
+    }
+  }
+  // up: prolong, smooth
+  for (int k = S.nlev - 2; k >= 0; --k) {
+    const MgTransfer &tr = S.tr[k + 1];
+    const T *ec = lds + S.off_e[k + 1];
+    T *ef = lds + S.off_e[k];
+    const uint32_t *mf = sm + S.off_m[k];
+    const uint32_t *mc = sm + S.off_m[k + 1];
+    for (int r = threadIdx.x; r < tr.f.n; r += SMALL_BLOCK) {
+      if (mf[r] & SOLID_BIT) continue;
+      ef[r] += prolong_value<T>(tr, r, mc, ec);
+    }
+    __syncthreads();
+    small_smooth<T>(S, k, S.nu2, lds, sm);
+  }
+  for (int r = threadIdx.x; r < S.lv[0].n; r += SMALL_BLOCK) e_out[r] = lds[S.off_e[0] + r];
+}
+
 // ---- phi += e --------------------------------------------------------------
 
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_correct(int n, const uint32_t *__restrict__ mask,
                                                    const T *__restrict__ e,
-                                                   double *__restrict__ phi) {
+                                                   double *__restrict__ phi,
+                                                   const SolveCtl *__restrict__ ctl) {
+  if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= n) return;
   if (mask[r] & SOLID_BIT) return;
   phi[r] += double(e[r]);
 }
 
-inline unsigned blocks_for(long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
-
 }  // namespace
 
 template <class T>
 hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
                                  const double *src, const double *phi, T *r0, T *e0,
-                                 double *partial, unsigned *counter, double *out) {
-  hipLaunchKernelGGL(k_outer_resid<T>, dim3(blocks_for(lv.n)), dim3(BLOCK), 0, s, lv, mask, src,
-                     phi, r0, e0, partial, counter, out);
+                                 double *partial, SolveCtl *ctl, int add) {
+  const int nb = (int)blocks_for(lv.n);
+  hipLaunchKernelGGL(k_outer_resid<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, src, phi, r0, e0,
+                     partial, ctl);
+  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(BLOCK), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int colour,
-                            const uint32_t *mask, const T *rhs, T *e) {
+                            const uint32_t *mask, const T *rhs, T *e, const SolveCtl *ctl) {
   const int hx = (lv.nx + 1) / 2, hy = (lv.ny + 1) / 2;
   hipLaunchKernelGGL(k_smooth<T>, dim3(blocks_for((long)hx * hy * lv.nz)), dim3(BLOCK), 0, s, lv,
-                     T(omega), colour, hx, hy, mask, rhs, e);
+                     T(omega), colour, hx, hy, mask, rhs, e, ctl);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
-                              const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec) {
+                              const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
+                              const SolveCtl *ctl) {
   hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(tr.c.n)), dim3(BLOCK), 0, s, tr, mf, mc, rf,
-                     ef, rc, ec);
+                     ef, rc, ec, ctl);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_mg_prolong(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
-                             const uint32_t *mc, const T *ec, T *ef) {
+                             const uint32_t *mc, const T *ec, T *ef, const SolveCtl *ctl) {
   hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for(tr.f.n)), dim3(BLOCK), 0, s, tr, mf, mc, ec,
-                     ef);
+                     ef, ctl);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t launch_mg_coarse(hipStream_t s, const MgLevel &lv, double omega, int sweeps,
-                            const uint32_t *mask, const T *rhs, T *e) {
+                            const uint32_t *mask, const T *rhs, T *e, const SolveCtl *ctl) {
   hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(COARSE_BLOCK), 0, s, lv, T(omega), sweeps, mask,
-                     rhs, e);
+                     rhs, e, ctl);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T *e,
-                             double *phi) {
-  hipLaunchKernelGGL(k_correct<T>, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, mask, e, phi);
+hipError_t launch_mg_coarse_dense(hipStream_t s, int nf, const T *ainv, const int *fcell,
+                                  const T *rhs, T *e, const SolveCtl *ctl) {
+  const int rows_per_block = BLOCK / WAVE;
+  hipLaunchKernelGGL(k_coarse_dense<T>, dim3((nf + rows_per_block - 1) / rows_per_block),
+                     dim3(BLOCK), 0, s, nf, ainv, fcell, rhs, e, ctl);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t prepare_mg_small(size_t lds_bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mg_small<T>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+}
+
+template <class T>
+hipError_t launch_mg_small(hipStream_t s, const MgSmall &S, size_t lds_bytes, const T *r_in,
+                           T *e_out, const SolveCtl *ctl) {
+  hipLaunchKernelGGL(k_mg_small<T>, dim3(1), dim3(SMALL_BLOCK), lds_bytes, s, S, r_in, e_out, ctl);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T *e, double *phi,
+                             const SolveCtl *ctl) {
+  hipLaunchKernelGGL(k_correct<T>, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, mask, e, phi, ctl);
   return hipGetLastError();
 }
 
 #define LBE_MG_INSTANTIATE(T)                                                                   \
   template hipError_t launch_mg_outer_resid<T>(hipStream_t, const MgLevel &, const uint32_t *,  \
                                                const double *, const double *, T *, T *,       \
-                                               double *, unsigned *, double *);                 \
+                                               double *, SolveCtl *, int);                      \
   template hipError_t launch_mg_smooth<T>(hipStream_t, const MgLevel &, double, int,            \
-                                          const uint32_t *, const T *, T *);                    \
+                                          const uint32_t *, const T *, T *, const SolveCtl *);  \
   template hipError_t launch_mg_restrict<T>(hipStream_t, const MgTransfer &, const uint32_t *,  \
-                                            const uint32_t *, const T *, const T *, T *, T *);  \
+                                            const uint32_t *, const T *, const T *, T *, T *,   \
+                                            const SolveCtl *);                                  \
   template hipError_t launch_mg_prolong<T>(hipStream_t, const MgTransfer &, const uint32_t *,   \
-                                           const uint32_t *, const T *, T *);                   \
+                                           const uint32_t *, const T *, T *, const SolveCtl *); \
   template hipError_t launch_mg_coarse<T>(hipStream_t, const MgLevel &, double, int,            \
-                                          const uint32_t *, const T *, T *);                    \
+                                          const uint32_t *, const T *, T *, const SolveCtl *);  \
   template hipError_t launch_mg_correct<T>(hipStream_t, int, const uint32_t *, const T *,       \
-                                           double *);
+                                           double *, const SolveCtl *);                         \
+  template hipError_t launch_mg_coarse_dense<T>(hipStream_t, int, const T *, const int *,       \
+                                                const T *, T *, const SolveCtl *);              \
+  template hipError_t prepare_mg_small<T>(size_t);                                              \
+  template hipError_t launch_mg_small<T>(hipStream_t, const MgSmall &, size_t, const T *, T *,  \
+                                         const SolveCtl *);
 
 LBE_MG_INSTANTIATE(double)
 LBE_MG_INSTANTIATE(float)

@@ -81,3 +81,21 @@ def test_mg_and_sor_agree_on_full_slab():
     # |A^-1| <= L^2/8 = 2048 for the 128-plane gap: 2e-9 absolute on phi
     assert rel(fb["phi"], fa["phi"], 0.2) <= 2e-8
     assert rel(fb["n"], fa["n"]) <= 2e-8
+
+
+@pytest.mark.parametrize("precision", [lbe.FP64, lbe.FP32_MIXED])
+def test_extrapolated_warm_start_same_fixed_point(precision):
+    """LBE_EXTRAPOLATE only changes the initial guess of each solve
+    (2 phi(t) - phi(t-1)); at tol = 1e-13 the trajectory matches the FP64
+    oracle to the solver-tolerance bound (FP32 bars for the mixed form)."""
+    kw, shape, t, ps, n0, nref, _, _ = G.case("slab_4x4x34")
+    o = oracle.Oracle(oracle.make_params(shape, **kw, tol=1e-13, max_iter=10**6, check_every=1),
+                      t, ps, n0, nref)
+    g = lbe.Lbe(lbe.make_params(shape, **kw, tol=1e-13, max_iter=200, poisson=lbe.MG,
+                                precision=precision, flags=lbe.EXTRAPOLATE), t, ps, n0, nref)
+    o.step(300)
+    g.step(300)
+    fo, fg = o.fields(), g.fields(f=False)
+    tol = 1e-10 if precision == lbe.FP64 else 1e-5
+    assert rel(fg["phi"], fo["phi"], 0.1) <= tol
+    assert rel(g.qhist(), o.qhist()) <= tol
