@@ -38,7 +38,9 @@ def bytes_per_site(kind: str, form: str, K: int):
       Poisson source (FP64) out, flag word.  One colour of a four-colour
       sweep on the finest level must read the correction (or phi) at every
       node of the other three colours, read and write its own quarter, and
-      read its quarter's right-hand side and flag word.  Residual: phi, source,
+      read its quarter's right-hand side and flag word.  A Jacobi sweep on the
+      finest multigrid level reads the correction, right-hand side and flag
+      word and writes the new correction.  Residual: phi, source,
       flag word (+ the correction's right-hand side and zeroed correction it
       writes, multigrid).  correct: phi read + write, correction, flag word.
     """
@@ -51,7 +53,7 @@ def bytes_per_site(kind: str, form: str, K: int):
         "ions": 2 * K * pop + 8 + 3 * vel + 8 + 4,
         "sor": (6 * 8 + 8 * 2 + 8 + 4) / 4,          # FP64 phi sweep, one colour
         "sor32": (6 * 4 + 4 * 2 + 4 + 4) / 4,        # FP32 correction sweep
-        "mg_smooth0": (6 * cor + cor * 2 + cor + 4) / 4,
+        "mg_smooth0": 3 * cor + 4,                   # Jacobi sweep (default smoother)
         "resid": 8 + 8 + 4,
         "mg_resid": 8 + 8 + 4 + 2 * cor,
         "correct": 16 + cor + 4,
@@ -71,9 +73,12 @@ def sync():
 def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, check_every: int):
     precision = lbe.FP64 if form == "fp64" else lbe.FP32_MIXED
     poisson = lbe.SOR4 if solver == "sor" else lbe.MG
+    # multigrid forms start each solve from 2 phi(t) - phi(t-1); the SOR form
+    # keeps the paper's warm start from phi(t)
+    flags = lbe.EXTRAPOLATE if solver == "mg" else 0
     p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, rho0=w.rho0, Eapp=w.Eapp,
                         omega=w.omega, tol=w.tol, max_iter=1_000_000, check_every=check_every,
-                        precision=precision, poisson=poisson)
+                        precision=precision, poisson=poisson, flags=flags)
     g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref)
     N = w.node_type.size
     nfluid = int((w.node_type == 0).sum())

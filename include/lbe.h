@@ -49,6 +49,7 @@ enum {
 
 enum { LBE_FP64 = 0, LBE_FP32_MIXED = 1 };   /* precision form */
 enum { LBE_SOR4 = 0, LBE_MG = 1 };           /* Poisson solver */
+enum { LBE_MG_JACOBI = 0, LBE_MG_GS4 = 1 };  /* multigrid smoother */
 enum { LBE_ALLOW_FLOATING = 1, LBE_EXTRAPOLATE = 2 };  /* flags */
 enum { LBE_MAX_SPECIES = 4, LBE_MAX_ELECTRODES = 64, LBE_MAX_SITES = 100000000 };
 
@@ -78,8 +79,11 @@ typedef struct {
   int32_t mg_levels;    /* multigrid levels (LBE_MG): 0 = coarsen until at most
                            512 cells remain, whose operator is inverted exactly;
                            else the number of levels (>= 2) */
-  int32_t mg_nu1, mg_nu2; /* pre/post smoothing sweeps (LBE_MG) */
-  int32_t reserved;
+  int32_t mg_nu1, mg_nu2; /* pre/post smoothing sweeps (LBE_MG); Jacobi sweeps
+                           run in pairs, an odd count is rounded up */
+  int32_t mg_smoother;  /* LBE_MG_JACOBI: undamped Jacobi (smoothing factor 1/2
+                           for this stencil, one parallel launch per sweep);
+                           LBE_MG_GS4: four-colour Gauss-Seidel */
   void *stream;         /* hipStream_t to run on; NULL = library-owned stream */
 } lbe_params;
 

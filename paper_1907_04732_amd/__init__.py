@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "liblbe.so")
 OK, EINVAL, EGEOM, ENOMEM, EDEVICE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32_MIXED = 0, 1
 SOR4, MG = 0, 1
+MG_JACOBI, MG_GS4 = 0, 1
 ALLOW_FLOATING = 1
 EXTRAPOLATE = 2
 
@@ -39,7 +40,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int32), ("check_every", C.c_int32),
         ("flags", C.c_int32), ("precision", C.c_int32), ("poisson", C.c_int32),
         ("mg_levels", C.c_int32), ("mg_nu1", C.c_int32), ("mg_nu2", C.c_int32),
-        ("reserved", C.c_int32),
+        ("mg_smoother", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -109,7 +110,7 @@ def _dptr(a):
 
 def make_params(shape, z, D, lB, tau=1.0, rho0=1.0, Eapp=(0.0, 0.0, 0.0), omega=1.8, tol=1e-10,
                 max_iter=200000, check_every=4, flags=0, precision=FP64, poisson=SOR4,
-                mg_levels=0, mg_nu1=2, mg_nu2=2, stream=None) -> Params:
+                mg_levels=0, mg_nu1=2, mg_nu2=2, mg_smoother=MG_JACOBI, stream=None) -> Params:
     p = Params()
     p.nx, p.ny, p.nz = (int(v) for v in shape)
     if not 1 <= len(z) <= 4 or len(D) != len(z):
@@ -125,6 +126,7 @@ def make_params(shape, z, D, lB, tau=1.0, rho0=1.0, Eapp=(0.0, 0.0, 0.0), omega=
     p.max_iter, p.check_every, p.flags = int(max_iter), int(check_every), int(flags)
     p.precision, p.poisson = int(precision), int(poisson)
     p.mg_levels, p.mg_nu1, p.mg_nu2 = int(mg_levels), int(mg_nu1), int(mg_nu2)
+    p.mg_smoother = int(mg_smoother)
     p.stream = stream
     return p
 

@@ -64,9 +64,11 @@ struct lbe_ctx {
     uint32_t *mask = nullptr;
     bool own_mask = false;
     void *e = nullptr, *r = nullptr;  // correction and right-hand side (T)
+    void *e2 = nullptr;               // second correction buffer (Jacobi smoothing)
   };
   std::vector<MgDev> mg;
   int mg_coarse_sweeps = 0;
+  double mg_jacobi = 0.0;   // > 0: Jacobi smoothing with this weight (else Gauss-Seidel)
   // coarsest level solved exactly: inverse of its operator over fluid cells
   int mg_nf = 0;
   void *mg_ainv = nullptr;  // T[nf * nf]
@@ -195,6 +197,8 @@ int validate(const lbe_params *p) {
   if (p->poisson == LBE_MG && (p->mg_levels < 0 || p->mg_levels == 1 || p->mg_levels > 16 ||
                                p->mg_nu1 < 0 || p->mg_nu2 < 0 || p->mg_nu1 + p->mg_nu2 < 1))
     return fail(nullptr, LBE_EINVAL, "bad multigrid levels or smoothing counts");
+  if (p->poisson == LBE_MG && p->mg_smoother != LBE_MG_JACOBI && p->mg_smoother != LBE_MG_GS4)
+    return fail(nullptr, LBE_EINVAL, "unknown multigrid smoother");
   return LBE_OK;
 }
 
@@ -645,6 +649,7 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
   l0.lv = MgLevel{nx, ny, nz, nx * ny, nx * ny * nz, c->L.selfm, 1.0, 1.0};
   l0.mask = c->mask;
   HIPCHK(c, hipMalloc(&l0.e, esz * l0.lv.n));
+  HIPCHK(c, hipMalloc(&l0.e2, esz * l0.lv.n));
   HIPCHK(c, hipMalloc(&l0.r, esz * l0.lv.n));
   c->mg.push_back(l0);
   double h2 = 1.0;
@@ -667,6 +672,7 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
     lbe_ctx::MgDev &B = c->mg.back();
     HIPCHK(c, hipMemcpy(B.mask, m.data(), sizeof(uint32_t) * m.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMalloc(&B.e, esz * B.lv.n));
+    HIPCHK(c, hipMalloc(&B.e2, esz * B.lv.n));
     HIPCHK(c, hipMalloc(&B.r, esz * B.lv.n));
     HIPCHK(c, hipMemset(B.e, 0, esz * B.lv.n));
     nx = cx;
@@ -711,8 +717,23 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
   }
   const KernelKind sk = l == 0 ? KK_MG_SMOOTH0 : KK_MG_SMOOTH;
   T *cur = A;
-  // four-colour Gauss-Seidel, in place
+  // four-colour Gauss-Seidel in place, or damped Jacobi in pairs cur -> e2 -> cur
   auto smooth = [&](int sweeps) -> int {
+    if (c->mg_jacobi > 0.0) {
+      for (int s2 = 0; s2 < sweeps; s2 += 2) {
+        int r2 = run(c, sk, [&] {
+          return launch_jacobi<T>(c->stream, L.lv, c->mg_jacobi, L.lv.h2 / 6.0, L.mask, r, cur,
+                                  (T *)L.e2, c->ctl);
+        });
+        if (r2) return r2;
+        r2 = run(c, sk, [&] {
+          return launch_jacobi<T>(c->stream, L.lv, c->mg_jacobi, L.lv.h2 / 6.0, L.mask, r,
+                                  (const T *)L.e2, cur, c->ctl);
+        });
+        if (r2) return r2;
+      }
+      return LBE_OK;
+    }
     for (int s2 = 0; s2 < sweeps; ++s2)
       for (int col = 0; col < 4; ++col) {
         const int r2 = run(c, sk, [&] {
@@ -888,6 +909,7 @@ void free_ctx(lbe_ctx *c) {
   for (auto &L : c->mg) {
     if (L.own_mask && L.mask) (void)hipFree(L.mask);
     if (L.e) (void)hipFree(L.e);
+    if (L.e2) (void)hipFree(L.e2);
     if (L.r) (void)hipFree(L.r);
   }
   if (c->unit_exec) (void)hipGraphExecDestroy(c->unit_exec);
@@ -1024,6 +1046,7 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
   {
     const char *ng = getenv("LBE_NO_GRAPHS");
     c->use_graphs = !(ng && *ng && *ng != '0');
+    c->mg_jacobi = p.mg_smoother == LBE_MG_JACOBI ? 1.0 : 0.0;
   }
   c->type_h.assign(type, type + N);
   // references of the mixed form: n_ref, else the fluid mean of n_init

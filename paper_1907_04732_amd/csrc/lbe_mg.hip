@@ -134,6 +134,38 @@ __global__ __launch_bounds__(BLOCK) void k_smooth(MgLevel lv, T omega, int colou
   e[r] = (T(1) - omega) * e[r] + omega * (num / den);
 }
 
+// ---- damped Jacobi sweep (one launch, every cell in parallel) --------------
+// x_out = x_in + omega ([sum_i w_i s_i x_in(r+c_i) + hs rhs] / sum_i w_i s_i - x_in)
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
+                                                  const uint32_t *__restrict__ mask,
+                                                  const T *__restrict__ rhs,
+                                                  const T *__restrict__ x_in,
+                                                  T *__restrict__ x_out,
+                                                  const SolveCtl *__restrict__ ctl) {
+  if (ctl->done) return;
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= lv.n) return;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) {
+    x_out[r] = T(0);
+    return;
+  }
+  const Coords c = coords_of(r, lv.nx, lv.nxy);
+  T num = T(0), den = T(0);
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if ((lv.selfm >> (i - 1)) & 1u) continue;
+    const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
+    num += ws * x_in[nbr_of(lv, c, i)];
+    den += ws;
+  }
+  num += hs * rhs[r];
+  const T xr = x_in[r];
+  x_out[r] = xr + omega * (num / den - xr);
+}
+
 // ---- restriction: coarse rhs = mean of the fluid children's residuals -------
 
 template <class T>
@@ -471,6 +503,15 @@ hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int 
 }
 
 template <class T>
+hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double hs,
+                         const uint32_t *mask, const T *rhs, const T *x_in, T *x_out,
+                         const SolveCtl *ctl) {
+  hipLaunchKernelGGL(k_jacobi<T>, dim3(blocks_for(lv.n)), dim3(BLOCK), 0, s, lv, T(omega), T(hs),
+                     mask, rhs, x_in, x_out, ctl);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
                               const SolveCtl *ctl) {
@@ -530,6 +571,9 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                                double *, SolveCtl *, int);                      \
   template hipError_t launch_mg_smooth<T>(hipStream_t, const MgLevel &, double, int,            \
                                           const uint32_t *, const T *, T *, const SolveCtl *);  \
+  template hipError_t launch_jacobi<T>(hipStream_t, const MgLevel &, double, double,             \
+                                         const uint32_t *, const T *, const T *, T *,           \
+                                         const SolveCtl *);                                     \
   template hipError_t launch_mg_restrict<T>(hipStream_t, const MgTransfer &, const uint32_t *,  \
                                             const uint32_t *, const T *, const T *, T *, T *,   \
                                             const SolveCtl *);                                  \

@@ -67,43 +67,55 @@ def radial_distance(shape):
 def sphere_packing(n=192, zlo=16, zhi=159, counter=(176, 191), rmin=6.0, rmax=10.0,
                    fraction=0.3, phi_spheres=0.05, phi_counter=-0.05, seed=5, max_tries=200000):
     """Porous electrode: random sequential addition of non-overlapping spheres
-    (radius uniform in [rmin, rmax], periodic in x and y) inside the slab
-    zlo <= z <= zhi until the solid fraction of that slab reaches `fraction`;
-    all spheres are electrode 1.  Planes counter[0]..counter[1] are electrode 2."""
+    (radius uniform in [rmin, rmax], periodic in x and y, at least one lattice
+    spacing apart) inside the slab zlo <= z <= zhi until the solid fraction of
+    that slab reaches `fraction`; all spheres are electrode 1.  Planes
+    counter[0]..counter[1] are electrode 2."""
     rng = np.random.default_rng(seed)
     t = np.zeros((n, n, n), dtype=np.uint8)
     target = fraction * n * n * (zhi - zlo + 1)
-    centres = []
+    centres = np.zeros((0, 3))
+    radii = np.zeros(0)
     solid = 0
-    zz, yy, xx = np.mgrid[0:n, 0:n, 0:n]
     tries = 0
     while solid < target and tries < max_tries:
         tries += 1
         rad = rng.uniform(rmin, rmax)
         c = np.array([rng.uniform(0, n), rng.uniform(0, n),
                       rng.uniform(zlo + rad, zhi + 1 - rad)])
-        ok = True
-        for (c2, r2) in centres:
-            d = c - c2
-            d[:2] -= n * np.round(d[:2] / n)
-            if np.dot(d, d) < (rad + r2 + 1.0) ** 2:
-                ok = False
-                break
-        if not ok:
-            continue
-        centres.append((c, rad))
-        dx = xx - c[0]
-        dx -= n * np.round(dx / n)
-        dy = yy - c[1]
-        dy -= n * np.round(dy / n)
-        dz = zz - c[2]
-        inside = dx * dx + dy * dy + dz * dz < rad * rad
-        newly = inside & (t == 0)
-        t[newly] = 1
-        solid += int(newly.sum())
+        if len(radii):
+            d = centres - c
+            d[:, :2] -= n * np.round(d[:, :2] / n)
+            if np.any((d * d).sum(1) < (radii + rad + 1.0) ** 2):
+                continue
+        centres = np.vstack([centres, c])
+        radii = np.append(radii, rad)
+        lo = np.floor(c - rad).astype(int)
+        hi = np.ceil(c + rad).astype(int) + 1
+        zz, yy, xx = np.mgrid[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        inside = (xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2 < rad * rad
+        zi, yi, xi = zz[inside], yy[inside] % n, xx[inside] % n
+        fresh = t[zi, yi, xi] == 0
+        t[zi[fresh], yi[fresh], xi[fresh]] = 1
+        solid += int(fresh.sum())
     t[counter[0]:counter[1] + 1] = 2
     ps = np.where(t == 1, phi_spheres, np.where(t == 2, phi_counter, 0.0))
     return (n, n, n), t.reshape(-1), ps.reshape(-1)
+
+
+def porous_electrode(noise=True, n=192):
+    """Porous electrode: 192^3 lattice, seeded packing of spheres (radius
+    6-10, solid fraction 0.3 of z in [16, 159]) at +0.05 facing a flat
+    counter-electrode (z in [176, 191]) at -0.05, 1:1 salt with Debye length 4,
+    tau = 1, D = 0.05."""
+    lB, debye = 0.4, 4.0
+    rs = salt_for_debye(debye, lB)
+    scale = n / 192.0
+    shape, t, ps = sphere_packing(n=n, zlo=int(16 * scale), zhi=int(159 * scale),
+                                  counter=(int(176 * scale), n - 1), seed=5)
+    n_init = noisy_concentrations(t, [rs, rs], 1e-6, seed=5) if noise else None
+    return Workload(f"porous_electrode_{n}^3", shape, t, ps, (1, -1), (0.05, 0.05), lB, 1.0, 1.0,
+                    (0.0, 0.0, 0.0), (rs, rs), n_init, 1.8, 1e-10, 4000, dict(debye=debye))
 
 
 def noisy_concentrations(node_type, rho, rel=1e-6, seed=1):
