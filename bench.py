@@ -29,34 +29,43 @@ import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
-def bytes_per_site(kind: str, form: str, K: int):
-    """Algorithmic HBM bytes per lattice site for one launch of a kernel kind
-    (None for kernels whose launches differ in size, e.g. coarse levels).
+def bytes_per_cell(kind: str, form: str, K: int):
+    """Algorithmic HBM bytes per cell of the grid level a launch works on
+    (lattice sites for the finest level), or None where no byte model applies
+    (the one-work-group coarse-level kernel, the electrode-charge gather).
 
-    fluid: 19 populations in + out, K concentrations, phi (FP64), velocity
-      out, flag word.  ions: K concentrations in + out, phi, velocity in,
-      Poisson source (FP64) out, flag word.  One colour of a four-colour
-      sweep on the finest level must read the correction (or phi) at every
-      node of the other three colours, read and write its own quarter, and
-      read its quarter's right-hand side and flag word.  A Jacobi sweep on the
-      finest multigrid level reads the correction, right-hand side and flag
-      word and writes the new correction.  Residual: phi, source,
-      flag word (+ the correction's right-hand side and zeroed correction it
-      writes, multigrid).  correct: phi read + write, correction, flag word.
+    fluid: 19 populations in + out, K concentrations in, K partially
+      updated concentrations out, phi (FP64), velocity out, flag word.
+      ions (advection pass): K concentrations, K partial updates in, K new
+      concentrations out, velocity in, Poisson source (FP64) out, flag word.  One colour of a four-colour SOR
+      sweep reads phi (or the correction) at every site, and reads the
+      source, reads the flag word and writes the value of its own quarter.
+      Jacobi sweep (the multigrid smoother): correction in and out,
+      right-hand side, flag word.  Restriction, per fine cell: correction,
+      residual and flag word in; per coarse cell (1/8): flag word in, rhs and
+      zeroed correction out.  Prolongation, per fine cell: correction in and
+      out, flag word; per coarse cell: correction and flag word.  Outer
+      residual: phi, source, flag word in; correction rhs and zeroed
+      correction out (multigrid).  correct: phi in + out, correction, flag
+      word.  extrap: phi and previous phi in + out, flag word.
     """
     f64 = form == "fp64"
     pop = 8 if f64 else 4     # population / concentration storage
     vel = 8 if f64 else 4     # velocity storage
     cor = 8 if f64 else 4     # Poisson correction storage (multigrid)
     table = {
-        "fluid": 19 * pop * 2 + K * pop + 8 + 3 * vel + 4,
-        "ions": 2 * K * pop + 8 + 3 * vel + 8 + 4,
-        "sor": (6 * 8 + 8 * 2 + 8 + 4) / 4,          # FP64 phi sweep, one colour
-        "sor32": (6 * 4 + 4 * 2 + 4 + 4) / 4,        # FP32 correction sweep
-        "mg_smooth0": 3 * cor + 4,                   # Jacobi sweep (default smoother)
+        "fluid": 19 * pop * 2 + 2 * K * pop + 8 + 3 * vel + 4,
+        "ions": 3 * K * pop + 3 * vel + 8 + 4,
+        "sor": 8 + (8 + 8 + 4) / 4,
+        "sor32": 4 + (4 + 4 + 4) / 4,
+        "mg_smooth0": 3 * cor + 4,
+        "mg_smooth": 3 * cor + 4,
+        "mg_restrict": 2 * cor + 4 + (4 + 2 * cor) / 8,
+        "mg_prolong": 2 * cor + 4 + (cor + 4) / 8,
         "resid": 8 + 8 + 4,
         "mg_resid": 8 + 8 + 4 + 2 * cor,
         "correct": 16 + cor + 4,
+        "extrap": 32 + 4,
     }
     return table.get(kind)
 
@@ -82,6 +91,7 @@ def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, che
     g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref)
     N = w.node_type.size
     nfluid = int((w.node_type == 0).sum())
+    ffrac = nfluid / N
     g.step(warmup)
     tot0 = g.totals()
     sync()
@@ -103,20 +113,24 @@ def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, che
     g.profile(False)
     g.close()
     kernels = {}
-    for k, (ms, cnt) in sorted(kt.items(), key=lambda kv: -kv[1][0]):
+    for k, (ms, cnt, cells) in sorted(kt.items(), key=lambda kv: -kv[1][0]):
         if not cnt:
             continue
         avg = ms / 1e3 / cnt
-        b = bytes_per_site(k, form, len(w.z))
-        row = {"total_ms": round(ms, 4), "launches": cnt, "avg_us": round(avg * 1e6, 3)}
+        b = bytes_per_cell(k, form, len(w.z))
+        row = {"total_ms": round(ms, 4), "launches": cnt, "avg_us": round(avg * 1e6, 3),
+               "cells_per_launch": int(round(cells / cnt))}
         if b is not None:
-            row["bytes_per_launch"] = int(b * N)
-            row["achieved_GBs"] = round(b * N / avg / 1e9, 1)
-            row["frac"] = round(b * N / avg / 1e9 / HBM_PEAK_GBS, 4)
+            # solid cells only read their flag word
+            per_launch = (ffrac * b + (1.0 - ffrac) * 4) * cells / cnt
+            row["bytes_per_launch"] = int(round(per_launch))
+            row["achieved_GBs"] = round(per_launch / avg / 1e9, 1)
+            row["frac"] = round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4)
         kernels[k] = row
         print(f"bench:   {k:12s} {ms:9.3f} ms, {cnt:6d} launches, {avg * 1e6:8.2f} us avg"
               + (f", {row['achieved_GBs']:8.1f} GB/s" if b is not None else ""),
               file=sys.stderr, flush=True)
+    # roofline object: the kernel kind with the largest total time
     dom = next(iter(kernels))
     d = kernels[dom]
     roof = {"bound": "hbm", "kernel": dom, "achieved": d.get("achieved_GBs"), "peak": HBM_PEAK_GBS,
@@ -165,6 +179,32 @@ def copy_calibration(nbytes=1 << 28, reps=5):
 FORMS = {"fp32-mg": ("fp32", "mg"), "fp64-mg": ("fp64", "mg"), "fp64-sor": ("fp64", "sor"),
          "fp32-sor": ("fp32", "sor")}
 
+# Larger lattices whose working sets exceed the 256 MB last-level cache, so
+# that the fluid and ion kernels stream from HBM: the coaxial capacitor
+# (1.64 M sites) and the porous electrode (7.08 M sites).
+SHAPES = {"coaxial_160x160x64": lambda: W.coaxial(noise=True),
+          "porous_electrode_192^3": lambda: W.porous_electrode(noise=True)}
+
+
+def run_shapes(names, forms, steps, warmup, check_every):
+    out = {}
+    for name in names:
+        w = SHAPES[name]()
+        nfluid = int((w.node_type == 0).sum())
+        print(f"bench: {w.name}, {w.node_type.size} sites, {nfluid} fluid", file=sys.stderr,
+              flush=True)
+        res = {}
+        for f in forms:
+            form, solver = FORMS[f]
+            r = run_form(w, form, solver, steps, warmup, check_every)
+            keep = {k: r["kernels"][k] for k in ("fluid", "ions") if k in r["kernels"]}
+            res[f] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"],
+                      "poisson_iters_per_step": r["poisson_iters_per_step"],
+                      "roofline": r["roofline"], "step_kernels": keep}
+        out[w.name] = {"sites": int(w.node_type.size), "fluid_sites": nfluid, "steps": steps,
+                       "forms": res}
+    return out
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -177,6 +217,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--shapes", default=",".join(SHAPES),
+                    help="comma list of larger lattices measured beside the headline (empty: none)")
+    ap.add_argument("--shape-forms", default="fp32-mg,fp64-mg")
+    ap.add_argument("--shape-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the LBE step is not sharded across GPUs in this "
@@ -220,6 +264,10 @@ def main():
                                             "roofline")} for k, v in res.items()},
         "kernels": head["kernels"],
     }
+    shapes = [x.strip() for x in args.shapes.split(",") if x.strip()]
+    if shapes:
+        out["shapes"] = run_shapes(shapes, [f.strip() for f in args.shape_forms.split(",")],
+                                   args.shape_steps, args.warmup, args.check_every)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -159,11 +159,16 @@ const char *lbe_strerror(int code);
 const char *lbe_last_error(const lbe_ctx *ctx);
 
 /* Kernel timing for the roofline measurement: enable=1 brackets every
- * launch of every kernel kind with HIP events on the context's stream;
- * lbe_kernel_times returns, per kind, total milliseconds and launch counts
- * since enabling (syncs the stream).  Kinds are listed by lbe_kernel_name. */
+ * launch of every kernel kind with HIP events on the context's stream (and
+ * launches directly instead of replaying captured graphs); enable=0 stops.
+ * Either call clears the counters.  lbe_kernel_times returns, per kind,
+ * total milliseconds, launch counts and cells covered (the sum over launches
+ * of the cell count of the grid level each launch works on: lattice sites
+ * for the finest level) since enabling; it synchronises the stream.  Any of
+ * the three host arrays (nkinds entries) may be NULL.  Kinds are listed by
+ * lbe_kernel_name. */
 int lbe_profile(lbe_ctx *ctx, int enable);
-int lbe_kernel_times(lbe_ctx *ctx, double *ms, int64_t *launches, int32_t nkinds);
+int lbe_kernel_times(lbe_ctx *ctx, double *ms, int64_t *launches, int64_t *cells, int32_t nkinds);
 const char *lbe_kernel_name(int32_t kind);
 int32_t lbe_num_kernel_kinds(void);
 

@@ -92,7 +92,7 @@ def load(path: str = LIB_PATH):
     lib.lbe_last_error.restype = C.c_char_p
     lib.lbe_profile.argtypes = [C.c_void_p, C.c_int]
     lib.lbe_profile.restype = C.c_int
-    lib.lbe_kernel_times.argtypes = [C.c_void_p, d, P(C.c_int64), C.c_int32]
+    lib.lbe_kernel_times.argtypes = [C.c_void_p, d, P(C.c_int64), P(C.c_int64), C.c_int32]
     lib.lbe_kernel_times.restype = C.c_int
     lib.lbe_kernel_name.argtypes = [C.c_int32]
     lib.lbe_kernel_name.restype = C.c_char_p
@@ -245,9 +245,12 @@ class Lbe:
         self._check(self._lib.lbe_profile(self.h, 1 if enable else 0))
 
     def kernel_times(self):
+        """{kind: (total ms, launches, cells covered)} since profile(True)."""
         n = self._lib.lbe_num_kernel_kinds()
         ms = np.zeros(n)
         cnt = np.zeros(n, dtype=np.int64)
-        self._check(self._lib.lbe_kernel_times(self.h, _dptr(ms),
-                                               cnt.ctypes.data_as(C.POINTER(C.c_int64)), n))
-        return {kernel_names()[k]: (float(ms[k]), int(cnt[k])) for k in range(n)}
+        cells = np.zeros(n, dtype=np.int64)
+        i64 = C.POINTER(C.c_int64)
+        self._check(self._lib.lbe_kernel_times(self.h, _dptr(ms), cnt.ctypes.data_as(i64),
+                                               cells.ctypes.data_as(i64), n))
+        return {kernel_names()[k]: (float(ms[k]), int(cnt[k]), int(cells[k])) for k in range(n)}

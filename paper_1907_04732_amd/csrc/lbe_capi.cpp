@@ -86,10 +86,15 @@ struct lbe_ctx {
 
   // profiling
   bool prof = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KK_COUNT];
+  struct Timed {
+    hipEvent_t a, b;
+    int64_t units;
+  };
+  std::vector<Timed> pending[KK_COUNT];
   std::vector<hipEvent_t> pool;
   double ms[KK_COUNT] = {};
   int64_t launches[KK_COUNT] = {};
+  int64_t units[KK_COUNT] = {};
 
   std::string err;
 };
@@ -133,18 +138,21 @@ int flush_profile(lbe_ctx *c) {
   for (int k = 0; k < KK_COUNT; ++k) {
     for (auto &pr : c->pending[k]) {
       float t = 0.f;
-      if (hipEventElapsedTime(&t, pr.first, pr.second) == hipSuccess) c->ms[k] += t;
+      if (hipEventElapsedTime(&t, pr.a, pr.b) == hipSuccess) c->ms[k] += t;
       c->launches[k] += 1;
-      c->pool.push_back(pr.first);
-      c->pool.push_back(pr.second);
+      c->units[k] += pr.units;
+      c->pool.push_back(pr.a);
+      c->pool.push_back(pr.b);
     }
     c->pending[k].clear();
   }
   return LBE_OK;
 }
 
+// Launches one kernel kind; `units` is the number of cells of the level it
+// covers (lattice sites on the finest), summed per kind while profiling.
 template <class Launch>
-int run(lbe_ctx *c, KernelKind kind, Launch &&launch) {
+int run(lbe_ctx *c, KernelKind kind, int64_t units, Launch &&launch) {
   hipEvent_t a = nullptr, b = nullptr;
   if (c->prof) {
     a = take_event(c);
@@ -154,7 +162,7 @@ int run(lbe_ctx *c, KernelKind kind, Launch &&launch) {
   hipError_t e = launch();
   if (c->prof && a && b) {
     (void)hipEventRecord(b, c->stream);
-    c->pending[kind].emplace_back(a, b);
+    c->pending[kind].push_back({a, b, units});
     size_t tot = 0;
     for (int k = 0; k < KK_COUNT; ++k) tot += c->pending[k].size();
     if (tot > 16384) {
@@ -410,7 +418,7 @@ int sor_solve(lbe_ctx *c, bool learn) {
       [&](int m) -> int {
         for (int s2 = 0; s2 < m; ++s2)
           for (int col = 0; col < 4; ++col) {
-            int rc = run(c, KK_SOR, [&] {
+            int rc = run(c, KK_SOR, c->L.n, [&] {
               return launch_sor_f64(c->stream, c->L, c->P, col, c->mask, c->src, c->phi, c->ctl);
             });
             if (rc) return rc;
@@ -418,7 +426,7 @@ int sor_solve(lbe_ctx *c, bool learn) {
         return LBE_OK;
       },
       [&](int add) -> int {
-        return run(c, KK_RESID, [&] {
+        return run(c, KK_RESID, c->L.n, [&] {
           return launch_resid_f64(c->stream, c->L, c->mask, c->src, c->phi, c->partial, c->ctl,
                                   add);
         });
@@ -509,9 +517,8 @@ void coarsen(int nx, int ny, int nz, const std::vector<uint8_t> &solid, int &cx,
 // Dense inverse of the coarsest operator A e = (6/h^2) sum_i w_i s_i (e - e_i)
 // over its fluid cells (Cholesky in FP64; A is symmetric positive definite when
 // every fluid region touches an electrode).  Not built when the level has
-// more than kMaxDense fluid cells or A is singular (floating regions): the
+// more than MG_MAX_DENSE fluid cells or A is singular (floating regions): the
 // coarsest level is then swept instead.
-constexpr int kMaxDense = 512;
 
 int build_coarse_inverse(lbe_ctx *c, const std::vector<uint8_t> &solid) {
   const MgLevel &lv = c->mg.back().lv;
@@ -522,7 +529,7 @@ int build_coarse_inverse(lbe_ctx *c, const std::vector<uint8_t> &solid) {
       fcell.push_back(r);
     }
   const int nf = (int)fcell.size();
-  if (nf == 0 || nf > kMaxDense) return LBE_OK;
+  if (nf == 0 || nf > MG_MAX_DENSE) return LBE_OK;
   std::vector<double> A((size_t)nf * nf, 0.0);
   const double sc = 6.0 * lv.inv_h2;
   for (int j = 0; j < nf; ++j) {
@@ -566,6 +573,11 @@ int build_coarse_inverse(lbe_ctx *c, const std::vector<uint8_t> &solid) {
       inv[(size_t)i * nf + col] = v / A[(size_t)i * nf + i];
     }
   }
+  // the kernels read the inverse column-major: at[j * nf + row] = inv[row][j]
+  std::vector<double> at((size_t)nf * nf);
+  for (int row = 0; row < nf; ++row)
+    for (int j = 0; j < nf; ++j) at[(size_t)j * nf + row] = inv[(size_t)row * nf + j];
+  inv.swap(at);
   HIPCHK(c, hipMalloc((void **)&c->mg_fcell, sizeof(int) * nf));
   HIPCHK(c, hipMemcpy(c->mg_fcell, fcell.data(), sizeof(int) * nf, hipMemcpyHostToDevice));
   if (c->mixed) {
@@ -594,9 +606,11 @@ int plan_small_levels(lbe_ctx *c) {
   for (int from = 0; from < L; ++from) {
     // one compute unit sweeps the set: only worth it while the levels are tiny
     if (L - from > MG_MAX_SMALL || c->mg[from].lv.n > 2048) continue;
-    size_t tbytes = 0, mbytes = 0;
+    // per cell: correction and right-hand side (and the second Jacobi buffer)
+    const size_t per_cell = c->mg_jacobi > 0.0 ? 3 : 2;
+    size_t tbytes = tsz * (size_t)std::max(c->mg_nf, 0), mbytes = 0;
     for (int k = from; k < L; ++k) {
-      tbytes += 2 * tsz * (size_t)c->mg[k].lv.n;
+      tbytes += per_cell * tsz * (size_t)c->mg[k].lv.n;
       mbytes += 4 * (size_t)c->mg[k].lv.n;
     }
     const size_t total = tbytes + mbytes;
@@ -613,7 +627,11 @@ int plan_small_levels(lbe_ctx *c) {
       te += D.lv.n;
       S.off_r[k] = (int)te;
       te += D.lv.n;
+      S.off_e2[k] = (int)te;
+      if (per_cell == 3) te += D.lv.n;
     }
+    S.off_x = (int)te;
+    te += std::max(c->mg_nf, 0);
     size_t me = te * tsz / 4;  // flag words follow, in 4-byte units
     for (int k = 0; k < S.nlev; ++k) {
       S.off_m[k] = (int)me;
@@ -626,6 +644,7 @@ int plan_small_levels(lbe_ctx *c) {
     S.fcell = c->mg_fcell;
     S.coarse_sweeps = c->mg_coarse_sweeps;
     S.omega = c->p.omega;
+    S.jacobi = c->mg_jacobi;
     const hipError_t e = c->mixed ? prepare_mg_small<float>(total) : prepare_mg_small<double>(total);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -654,7 +673,7 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
   c->mg.push_back(l0);
   double h2 = 1.0;
   for (int l = 1; l < maxl; ++l) {
-    if (c->p.mg_levels == 0 && (long)nx * ny * nz <= kMaxDense) break;
+    if (c->p.mg_levels == 0 && (long)nx * ny * nz <= MG_MAX_DENSE) break;
     if (nx <= 2 && ny <= 2 && nz <= 2) break;
     int cx, cy, cz, ox = 0, oy = 0, oz = 0;
     std::vector<uint8_t> cs;
@@ -699,18 +718,18 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
   int rc;
   if ((int)l == c->mg_small_from) {
     *out = A;
-    return run(c, KK_MG_SMALL, [&] {
+    return run(c, KK_MG_SMALL, L.lv.n, [&] {
       return launch_mg_small<T>(c->stream, c->mg_small, c->mg_small_lds, r, A, c->ctl);
     });
   }
   if (l + 1 == c->mg.size()) {
     *out = A;
     if (c->mg_ainv)
-      return run(c, KK_MG_COARSE, [&] {
+      return run(c, KK_MG_COARSE, L.lv.n, [&] {
         return launch_mg_coarse_dense<T>(c->stream, c->mg_nf, (const T *)c->mg_ainv, c->mg_fcell,
                                          r, A, c->ctl);
       });
-    return run(c, KK_MG_COARSE, [&] {
+    return run(c, KK_MG_COARSE, L.lv.n, [&] {
       return launch_mg_coarse<T>(c->stream, L.lv, c->p.omega, c->mg_coarse_sweeps, L.mask, r, A,
                                  c->ctl);
     });
@@ -721,12 +740,12 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
   auto smooth = [&](int sweeps) -> int {
     if (c->mg_jacobi > 0.0) {
       for (int s2 = 0; s2 < sweeps; s2 += 2) {
-        int r2 = run(c, sk, [&] {
+        int r2 = run(c, sk, L.lv.n, [&] {
           return launch_jacobi<T>(c->stream, L.lv, c->mg_jacobi, L.lv.h2 / 6.0, L.mask, r, cur,
                                   (T *)L.e2, c->ctl);
         });
         if (r2) return r2;
-        r2 = run(c, sk, [&] {
+        r2 = run(c, sk, L.lv.n, [&] {
           return launch_jacobi<T>(c->stream, L.lv, c->mg_jacobi, L.lv.h2 / 6.0, L.mask, r,
                                   (const T *)L.e2, cur, c->ctl);
         });
@@ -736,7 +755,7 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
     }
     for (int s2 = 0; s2 < sweeps; ++s2)
       for (int col = 0; col < 4; ++col) {
-        const int r2 = run(c, sk, [&] {
+        const int r2 = run(c, sk, L.lv.n, [&] {
           return launch_mg_smooth<T>(c->stream, L.lv, 1.0, col, L.mask, r, cur, c->ctl);
         });
         if (r2) return r2;
@@ -745,14 +764,14 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
   };
   if ((rc = smooth(c->p.mg_nu1))) return rc;
   lbe_ctx::MgDev &C = c->mg[l + 1];
-  rc = run(c, KK_MG_RESTRICT, [&] {
+  rc = run(c, KK_MG_RESTRICT, L.lv.n, [&] {
     return launch_mg_restrict<T>(c->stream, C.tr, L.mask, C.mask, r, cur, (T *)C.r, (T *)C.e,
                                  c->ctl);
   });
   if (rc) return rc;
   T *ce = nullptr;
   if ((rc = mg_vcycle<T>(c, l + 1, &ce))) return rc;
-  rc = run(c, KK_MG_PROLONG, [&] {
+  rc = run(c, KK_MG_PROLONG, L.lv.n, [&] {
     return launch_mg_prolong<T>(c->stream, C.tr, L.mask, C.mask, (const T *)ce, cur, c->ctl);
   });
   if (rc) return rc;
@@ -773,7 +792,7 @@ int mg_solve(lbe_ctx *c, bool learn) {
           T *e0 = nullptr;
           int rc = mg_vcycle<T>(c, 0, &e0);
           if (rc) return rc;
-          rc = run(c, KK_CORRECT, [&] {
+          rc = run(c, KK_CORRECT, L0.lv.n, [&] {
             return launch_mg_correct<T>(c->stream, L0.lv.n, c->mask, (const T *)e0, c->phi,
                                         c->ctl);
           });
@@ -782,7 +801,7 @@ int mg_solve(lbe_ctx *c, bool learn) {
         return LBE_OK;
       },
       [&](int add) -> int {
-        return run(c, KK_MG_RESID, [&] {
+        return run(c, KK_MG_RESID, L0.lv.n, [&] {
           return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi, (T *)L0.r,
                                           (T *)L0.e, c->partial, c->ctl, add);
         });
@@ -816,19 +835,19 @@ int mixed_sor_solve(lbe_ctx *c, bool learn) {
       [&](int m) -> int {
         for (int s2 = 0; s2 < m; ++s2)
           for (int col = 0; col < 4; ++col) {
-            int rc = run(c, KK_SOR32, [&] {
+            int rc = run(c, KK_SOR32, L0.lv.n, [&] {
               return launch_mg_smooth<float>(c->stream, L0.lv, c->p.omega, col, c->mask,
                                              (const float *)L0.r, (float *)L0.e, c->ctl);
             });
             if (rc) return rc;
           }
-        return run(c, KK_CORRECT, [&] {
+        return run(c, KK_CORRECT, L0.lv.n, [&] {
           return launch_mg_correct<float>(c->stream, L0.lv.n, c->mask, (const float *)L0.e,
                                           c->phi, c->ctl);
         });
       },
       [&](int add) -> int {
-        return run(c, KK_MG_RESID, [&] {
+        return run(c, KK_MG_RESID, L0.lv.n, [&] {
           return launch_mg_outer_resid<float>(c->stream, L0.lv, c->mask, c->src, c->phi,
                                               (float *)L0.r, (float *)L0.e, c->partial, c->ctl,
                                               add);
@@ -850,7 +869,7 @@ int charges_to(lbe_ctx *c, double *dst) {
     return LBE_OK;
   }
   const double q_scale = -6.0 / (4.0 * M_PI * c->p.lB);
-  return run(c, KK_CHARGE, [&] {
+  return run(c, KK_CHARGE, c->L.n, [&] {
     return launch_charge(c->stream, c->L, q_scale, c->mask, c->phi, c->iface, c->blk_elec,
                          c->blk_begin, c->blk_end, c->nblk_charge, c->ne, c->partial,
                          dst);
@@ -868,26 +887,25 @@ int record_charge(lbe_ctx *c) {
 
 int one_step(lbe_ctx *c) {
   const int a = c->cur, b = 1 - c->cur;
-  int rc = run(c, KK_FLUID, [&] {
+  int rc = run(c, KK_FLUID, c->L.n, [&] {
     if (c->mixed)
       return launch_fluid_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[a], c->h32[a],
-                              c->h32[b], c->u32);
+                              c->h32[b], c->u32, c->nu32[b]);
     return launch_fluid_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[a], c->f[a], c->f[b],
-                            c->u);
+                            c->u, c->n[b]);
   });
   if (rc) return rc;
-  rc = run(c, KK_IONS, [&] {
+  rc = run(c, KK_IONS, c->L.n, [&] {
     if (c->mixed)
-      return launch_ions_f32(c->stream, c->L, c->P, c->mask, c->phi, c->u32, c->nu32[a],
-                             c->nu32[b], c->src);
-    return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->phi, c->u, c->n[a], c->n[b],
-                           c->src);
+      return launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a], c->nu32[b],
+                             c->src);
+    return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a], c->n[b], c->src);
   });
   if (rc) return rc;
   c->cur = b;
   c->step++;
   if (c->phi_prev) {
-    rc = run(c, KK_EXTRAP, [&] {
+    rc = run(c, KK_EXTRAP, c->L.n, [&] {
       return launch_extrapolate(c->stream, c->L, c->mask, c->phi, c->phi_prev);
     });
     if (rc) return rc;
@@ -919,8 +937,8 @@ void free_ctx(lbe_ctx *c) {
   if (c->ctl_h) (void)hipHostFree(c->ctl_h);
   for (int k = 0; k < KK_COUNT; ++k)
     for (auto &pr : c->pending[k]) {
-      (void)hipEventDestroy(pr.first);
-      (void)hipEventDestroy(pr.second);
+      (void)hipEventDestroy(pr.a);
+      (void)hipEventDestroy(pr.b);
     }
   for (auto e : c->pool) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1247,7 +1265,7 @@ int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double 
   const int K = c->K;
   int rc;
   if (totals) {
-    rc = run(c, KK_TOTALS, [&] {
+    rc = run(c, KK_TOTALS, c->L.n, [&] {
       if (c->mixed)
         return launch_totals_f32(c->stream, c->L, c->P, c->mask, c->h32[c->cur], c->nu32[c->cur],
                                  c->partial, c->dout);
@@ -1271,7 +1289,7 @@ int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double 
     // FP64 form: the next step's output buffers are free between steps
     double *fpre = c->mixed ? c->obs : c->f[1 - c->cur];
     double *uo = c->mixed ? c->obs + (size_t)NQ * N : c->u;
-    rc = run(c, KK_OBSERVE, [&] {
+    rc = run(c, KK_OBSERVE, c->L.n, [&] {
       if (c->mixed)
         return launch_observe_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[c->cur],
                                   c->h32[c->cur], fpre, uo);
@@ -1316,18 +1334,20 @@ int lbe_profile(lbe_ctx *c, int enable) {
   for (int k = 0; k < KK_COUNT; ++k) {
     c->ms[k] = 0.0;
     c->launches[k] = 0;
+    c->units[k] = 0;
   }
   c->prof = enable != 0;
   return LBE_OK;
 }
 
-int lbe_kernel_times(lbe_ctx *c, double *ms, int64_t *launches, int32_t nkinds) {
+int lbe_kernel_times(lbe_ctx *c, double *ms, int64_t *launches, int64_t *cells, int32_t nkinds) {
   if (!c) return fail(c, LBE_EINVAL, "context is NULL");
   int rc = flush_profile(c);
   if (rc) return rc;
   for (int k = 0; k < nkinds && k < KK_COUNT; ++k) {
     if (ms) ms[k] = c->ms[k];
     if (launches) launches[k] = c->launches[k];
+    if (cells) cells[k] = c->units[k];
   }
   return LBE_OK;
 }

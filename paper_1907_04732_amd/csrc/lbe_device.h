@@ -38,6 +38,17 @@ __device__ __forceinline__ int nbr(const Offs &o, int r, int i) {
 
 __device__ __forceinline__ bool solid_link(uint32_t m, int i) { return (m >> (i - 1)) & 1u; }
 
+// v[i] = a[r + c_i] for the 19 velocities (v[0] = a[r]).  Every load is
+// unconditional (periodic neighbours are always in range) and issued before
+// any value is used, so a wave keeps all of them in flight together instead
+// of paying one memory round trip per link behind a branch.
+template <class T>
+__device__ __forceinline__ void gather(const Offs &o, int r, const T *__restrict__ a, T (&v)[NQ]) {
+  v[0] = a[r];
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) v[i] = a[nbr(o, r, i)];
+}
+
 
 // NaN-propagating max
 __device__ __forceinline__ double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
@@ -141,17 +152,40 @@ __global__ __launch_bounds__(BLOCK) void k_final_sum(const double *__restrict__ 
 // exactly.  For |delta| <= 1/2 both come from their Taylor series (next
 // terms below 1e-17 relative); beyond, from expm1.
 
+constexpr double TAYLOR_MAX = 0.5;  // |delta| up to which the series are used
+
+__device__ __forceinline__ void sinh_coshm1_series(double d, double &S, double &C) {
+  const double x = d * d;
+  S = d * (1.0 + x * (1.0 / 6 + x * (1.0 / 120 + x * (1.0 / 5040 + x * (1.0 / 362880 +
+           x * (1.0 / 39916800 + x * (1.0 / 6227020800.0)))))));
+  C = x * (0.5 + x * (1.0 / 24 + x * (1.0 / 720 + x * (1.0 / 40320 + x * (1.0 / 3628800 +
+           x * (1.0 / 479001600 + x * (1.0 / 87178291200.0)))))));
+}
+
 __device__ __forceinline__ void sinh_coshm1(double d, double &S, double &C) {
-  if (fabs(d) <= 0.5) {
-    const double x = d * d;
-    S = d * (1.0 + x * (1.0 / 6 + x * (1.0 / 120 + x * (1.0 / 5040 + x * (1.0 / 362880 +
-             x * (1.0 / 39916800 + x * (1.0 / 6227020800.0)))))));
-    C = x * (0.5 + x * (1.0 / 24 + x * (1.0 / 720 + x * (1.0 / 40320 + x * (1.0 / 3628800 +
-             x * (1.0 / 479001600 + x * (1.0 / 87178291200.0)))))));
+  if (fabs(d) <= TAYLOR_MAX) {
+    sinh_coshm1_series(d, S, C);
   } else {
     const double ep = expm1(d), em = expm1(-d);
     S = 0.5 * (ep - em);
     C = 0.5 * (ep + em);
+  }
+}
+
+// sinh and cosh - 1 of z delta for valence z, from S1, C1 of delta: for
+// z = +-1 they are reused (both the series and the expm1 form are exactly odd
+// and even in delta, so the values equal a direct evaluation bit for bit);
+// other valences are evaluated directly.  z is uniform across the launch.
+__device__ __forceinline__ void valence_sc(int z, double delta, double S1, double C1, double &S,
+                                           double &C) {
+  if (z == 1) {
+    S = S1;
+    C = C1;
+  } else if (z == -1) {
+    S = -S1;
+    C = C1;
+  } else {
+    sinh_coshm1(z * delta, S, C);
   }
 }
 
@@ -164,11 +198,23 @@ __device__ __forceinline__ double excess_link(double nh, double nt, double delta
   return -((nt + nh) * S + (nt - nh) * C) * inv2len;
 }
 
+// the series branch only (valid for |delta| <= TAYLOR_MAX); branch-free
+__device__ __forceinline__ double excess_link_series(double nh, double nt, double delta,
+                                                     double inv2len) {
+  double S, C;
+  sinh_coshm1_series(delta, S, C);
+  return -((nt + nh) * S + (nt - nh) * C) * inv2len;
+}
+
+__device__ __forceinline__ void sinh_coshm1f_series(float d, float &S, float &C) {
+  const float x = d * d;
+  S = d * (1.f + x * (1.f / 6 + x * (1.f / 120 + x * (1.f / 5040 + x * (1.f / 362880)))));
+  C = x * (0.5f + x * (1.f / 24 + x * (1.f / 720 + x * (1.f / 40320 + x * (1.f / 3628800)))));
+}
+
 __device__ __forceinline__ void sinh_coshm1f(float d, float &S, float &C) {
-  if (fabsf(d) <= 0.5f) {
-    const float x = d * d;
-    S = d * (1.f + x * (1.f / 6 + x * (1.f / 120 + x * (1.f / 5040 + x * (1.f / 362880)))));
-    C = x * (0.5f + x * (1.f / 24 + x * (1.f / 720 + x * (1.f / 40320 + x * (1.f / 3628800)))));
+  if (fabsf(d) <= float(TAYLOR_MAX)) {
+    sinh_coshm1f_series(d, S, C);
   } else {
     const float ep = expm1f(d), em = expm1f(-d);
     S = 0.5f * (ep - em);
@@ -176,9 +222,30 @@ __device__ __forceinline__ void sinh_coshm1f(float d, float &S, float &C) {
   }
 }
 
+__device__ __forceinline__ void valence_scf(int z, double delta, float d1, float S1, float C1,
+                                            float &S, float &C) {
+  if (z == 1) {
+    S = S1;
+    C = C1;
+  } else if (z == -1) {
+    S = -S1;
+    C = C1;
+  } else {
+    sinh_coshm1f(float(z * delta), S, C);
+  }
+  (void)d1;
+}
+
 __device__ __forceinline__ float excess_link_f(float nh, float nt, float delta, float inv2len) {
   float S, C;
   sinh_coshm1f(delta, S, C);
+  return -((nt + nh) * S + (nt - nh) * C) * inv2len;
+}
+
+__device__ __forceinline__ float excess_link_f_series(float nh, float nt, float delta,
+                                                      float inv2len) {
+  float S, C;
+  sinh_coshm1f_series(delta, S, C);
   return -((nt + nh) * S + (nt - nh) * C) * inv2len;
 }
 

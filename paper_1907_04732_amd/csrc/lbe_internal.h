@@ -83,23 +83,27 @@ struct SolveCtl {
 
 // The coarse end of the hierarchy handled by one work-group in LDS.
 constexpr int MG_MAX_SMALL = 8;
+constexpr int MG_MAX_DENSE = 512;         // largest coarsest level solved with a dense inverse
 struct MgSmall {
   int nlev;                               // levels in the set; the last is the coarsest
   MgLevel lv[MG_MAX_SMALL];
   MgTransfer tr[MG_MAX_SMALL];            // tr[k]: level k-1 -> k, k >= 1
   const uint32_t *mask[MG_MAX_SMALL];
   int off_e[MG_MAX_SMALL], off_r[MG_MAX_SMALL], off_m[MG_MAX_SMALL];  // LDS offsets (elements)
+  int off_e2[MG_MAX_SMALL];               // second Jacobi buffer per level
+  int off_x;                              // compact right-hand side of the exact solve (T)
   int nu1, nu2;
-  int nf;                                 // coarsest exact solve: fluid cells, inverse, cells
-  const void *ainv;
+  int nf;                                 // coarsest exact solve: fluid cells,
+  const void *ainv;                       // inverse (column-major), cell of each row
   const int *fcell;
   int coarse_sweeps;
   double omega;
+  double jacobi;                          // > 0: Jacobi smoothing with this weight, else GS
 };
 
 enum KernelKind {
-  KK_FLUID = 0,   // force + LB collide/stream (pull), writes u
-  KK_IONS,        // ion link fluxes + update, writes Poisson source
+  KK_FLUID = 0,   // link fluxes, force, LB collide/stream (pull); writes u, n*
+  KK_IONS,        // advective ion fluxes, n(t+1), Poisson source
   KK_SOR,         // one colour of the FP64 SOR sweep
   KK_RESID,       // FP64 residual inf-norm
   KK_CHARGE,      // electrode charges
@@ -122,12 +126,14 @@ extern const char *const kKernelNames[KK_COUNT];
 
 // ---- launchers (lbe_kernels.hip) -----------------------------------------
 // All take the stream; they return hipSuccess or the launch error.
+// Step pass A: link fluxes, force, collide-stream; writes f', u and
+// n* = n - (diffusion-migration outflow) into nstar.
 hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const double *n, const double *fin, double *fout,
-                            double *u);
+                            double *u, double *nstar);
+// Step pass B: advective outflow with u; nio holds n* on entry, n(t+1) on exit.
 hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const double *phi, const double *u, const double *n, double *nout,
-                           double *src);
+                           const double *u, const double *n, double *nio, double *src);
 hipError_t launch_sor_f64(hipStream_t s, const Lattice &L, const Phys &P, int colour,
                           const uint32_t *mask, const double *src, double *phi,
                           const SolveCtl *ctl);
@@ -157,10 +163,9 @@ hipError_t launch_extrapolate(hipStream_t s, const Lattice &L, const uint32_t *m
 // mixed form (lbe_kernels_f32.hip): h = f - w rho0 and nu = n - n_ref in FP32
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
-                            float *u);
+                            float *u, float *nustar);
 hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const double *phi, const float *u, const float *nu, float *nuout,
-                           double *src);
+                           const float *u, const float *nu, float *nuio, double *src);
 hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
                               const uint32_t *mask, const double *phi, const float *nu,
                               const float *hin, double *fpre, double *u);

@@ -64,7 +64,11 @@ __device__ __forceinline__ void pull(const Lattice &L, int r, uint32_t m, const 
   }
 }
 
-// ---- pass A: force, moments, BGK + Guo forcing, write post-collision f and u
+// ---- pass A: link fluxes, force, moments, BGK + Guo forcing --------------
+// Each fluid link's excess flux g_k (Eq. 10) is evaluated once and used
+// twice: projected on the node as the fluid force, and in the
+// diffusion-migration flux j_k = D_k/A0 (g_k - (n_k' - n_k)/Delta_i).  Writes
+// post-collision f, u, and n*_k = n_k - sum_i j_k (completed by pass B).
 
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_fluid_f64(Lattice L, Phys P,
@@ -73,7 +77,8 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f64(Lattice L, Phys P,
                                                      const double *__restrict__ n,
                                                      const double *__restrict__ fin,
                                                      double *__restrict__ fout,
-                                                     double *__restrict__ u) {
+                                                     double *__restrict__ u,
+                                                     double *__restrict__ nstar) {
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
@@ -82,11 +87,35 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f64(Lattice L, Phys P,
   Offs o;
   site_offsets(L, r, o);
   const double ph = phi[r];
-  double nr[K];
+  double nr[K], js[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) nr[k] = n[k * N + r];
-  double F0, F1, F2;
-  link_force<K>(L, P, r, m, o, phi, n, ph, nr, F0, F1, F2);
+  for (int k = 0; k < K; ++k) {
+    nr[k] = n[k * N + r];
+    js[k] = 0.0;
+  }
+  double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;  // no flux into an electrode
+    const int rn = nbr(o, r, i);
+    const double dphi = phi[rn] - ph - P.Ec[i];
+    double S1, C1;
+    sinh_coshm1(dphi, S1, C1);
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double nt = n[k * N + rn];
+      double S, C;
+      valence_sc(P.z[k], dphi, S1, C1, S, C);
+      const double gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * (0.5 / LEN[i]);
+      g += gk;
+      js[k] += P.dk[k] * (gk - (nt - nr[k]) / LEN[i]);
+    }
+    const double c = 3.0 * WQ[i] * LEN[i] * g;
+    if (CX[i]) F0 += CX[i] * c;
+    if (CY[i]) F1 += CY[i] * c;
+    if (CZ[i]) F2 += CZ[i] * c;
+  }
 
   double f[NQ];
   pull(L, r, m, o, fin, f);
@@ -118,17 +147,20 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f64(Lattice L, Phys P,
   u[r] = ux;
   u[N + r] = uy;
   u[2 * N + r] = uz;
+#pragma unroll
+  for (int k = 0; k < K; ++k) nstar[k * N + r] = nr[k] - js[k];
 }
 
-// ---- pass B: ion link fluxes (Eqs. 9-10) + advection, new Poisson source --
+// ---- pass B: advective link fluxes with the step's velocity, new n and
+// Poisson source.  J_k = 3 w_i c_i . (n_k u + n_k' u') on every fluid link;
+// n_k(t+1) = n*_k - sum_i J_k, updated in place in nio. -------------------
 
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_ions_f64(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
-                                                    const double *__restrict__ phi,
                                                     const double *__restrict__ u,
                                                     const double *__restrict__ n,
-                                                    double *__restrict__ nout,
+                                                    double *__restrict__ nio,
                                                     double *__restrict__ src) {
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= L.n) return;
@@ -137,37 +169,29 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f64(Lattice L, Phys P,
   const int N = L.n;
   Offs o;
   site_offsets(L, r, o);
-  const double ph = phi[r];
   const double ux = u[r], uy = u[N + r], uz = u[2 * N + r];
-  double nr[K], acc[K];
+  double nr[K], Js[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     nr[k] = n[k * N + r];
-    acc[k] = 0.0;
+    Js[k] = 0.0;
   }
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
-    if (solid_link(m, i)) continue;  // no flux into an electrode
+    if (solid_link(m, i)) continue;
     const int rn = nbr(o, r, i);
-    const double dphi = phi[rn] - ph - P.Ec[i];
     double cu_h = 0.0, cu_t = 0.0;
     if (CX[i]) { cu_h += CX[i] * ux; cu_t += CX[i] * u[rn]; }
     if (CY[i]) { cu_h += CY[i] * uy; cu_t += CY[i] * u[N + rn]; }
     if (CZ[i]) { cu_h += CZ[i] * uz; cu_t += CZ[i] * u[2 * N + rn]; }
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double nn = n[k * N + rn];
-      const double g = excess_link(nr[k], nn, P.z[k] * dphi, 0.5 / LEN[i]);
-      const double j = P.dk[k] * (g - (nn - nr[k]) / LEN[i]);
-      const double J = 3.0 * WQ[i] * (nr[k] * cu_h + nn * cu_t);
-      acc[k] += j + J;
-    }
+    for (int k = 0; k < K; ++k) Js[k] += 3.0 * WQ[i] * (nr[k] * cu_h + n[k * N + rn] * cu_t);
   }
   double q = 0.0;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const double v = nr[k] - acc[k];
-    nout[k * N + r] = v;
+    const double v = nio[k * N + r] - Js[k];
+    nio[k * N + r] = v;
     q += P.z[k] * v;
   }
   src[r] = P.src_scale * q;
@@ -198,16 +222,19 @@ __global__ __launch_bounds__(BLOCK) void k_sor_f64(Lattice L, double omega, int 
   if (m & SOLID_BIT) return;
   Offs o;
   site_offsets(L, r, o);
+  double pn[NQ];
+  gather(o, r, phi, pn);
+  const double sr = src[r];
   double num = 0.0, den = 0.0;
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((L.selfm >> (i - 1)) & 1u) continue;
     const double ws = solid_link(m, i) ? 2.0 * WQ[i] : WQ[i];
-    num += ws * phi[nbr(o, r, i)];
+    num += ws * pn[i];
     den += ws;
   }
-  num += src[r];
-  phi[r] = (1.0 - omega) * phi[r] + omega * (num / den);
+  num += sr;
+  phi[r] = (1.0 - omega) * pn[0] + omega * (num / den);
 }
 
 // residual R = L_h phi + 4 pi l_B rho_el = 6 [sum_i w_i s_i (phi' - phi) + src];
@@ -226,15 +253,17 @@ __global__ __launch_bounds__(BLOCK) void k_resid_f64(Lattice L, const uint32_t *
     if (!(m & SOLID_BIT)) {
       Offs o;
       site_offsets(L, r, o);
-      const double ph = phi[r];
+      double pn[NQ];
+      gather(o, r, phi, pn);
+      const double sr = src[r];
       double acc = 0.0;
 #pragma unroll
       for (int i = 1; i < NQ; ++i) {
         if ((L.selfm >> (i - 1)) & 1u) continue;
         const double ws = solid_link(m, i) ? 2.0 * WQ[i] : WQ[i];
-        acc += ws * (phi[nbr(o, r, i)] - ph);
+        acc += ws * (pn[i] - pn[0]);
       }
-      a = fabs(6.0 * (acc + src[r]));
+      a = fabs(6.0 * (acc + sr));
     }
   }
   a = block_max(a, sm);
@@ -260,12 +289,13 @@ __global__ __launch_bounds__(BLOCK) void k_charge(Lattice L, double q_scale,
     const uint32_t m = mask[r];
     Offs o;
     site_offsets(L, r, o);
-    const double ps = phi[r];
+    double pn[NQ];
+    gather(o, r, phi, pn);
     double lap = 0.0;
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
       if (solid_link(m, i)) continue;
-      lap += WQ[i] * 2.0 * (phi[nbr(o, r, i)] - ps);
+      lap += WQ[i] * 2.0 * (pn[i] - pn[0]);
     }
     v = q_scale * lap;
   }
@@ -387,19 +417,18 @@ __global__ __launch_bounds__(BLOCK) void k_extrapolate(int n, const uint32_t *__
 
 hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const double *n, const double *fin, double *fout,
-                            double *u) {
+                            double *u, double *nstar) {
 #define CALL(KK) \
-  hipLaunchKernelGGL(k_fluid_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, n, fin, fout, u)
+  hipLaunchKernelGGL(k_fluid_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, n, fin, fout, u, nstar)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   return hipGetLastError();
 }
 
 hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const double *phi, const double *u, const double *n, double *nout,
-                           double *src) {
+                           const double *u, const double *n, double *nio, double *src) {
 #define CALL(KK) \
-  hipLaunchKernelGGL(k_ions_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, u, n, nout, src)
+  hipLaunchKernelGGL(k_ions_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, u, n, nio, src)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   return hipGetLastError();

@@ -53,6 +53,9 @@ __device__ __forceinline__ void pull_f32(const Lattice &L, int r, uint32_t m, co
   }
 }
 
+// Pass A: each fluid link's excess flux (Eq. 10) evaluated once, used for the
+// fluid force and for the diffusion-migration flux; collision; writes h, u and
+// nu*_k = nu_k - sum_i j_k (completed by k_ions_f32).
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_fluid_f32(Lattice L, Phys P,
                                                      const uint32_t *__restrict__ mask,
@@ -60,7 +63,8 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f32(Lattice L, Phys P,
                                                      const float *__restrict__ nu,
                                                      const float *__restrict__ hin,
                                                      float *__restrict__ hout,
-                                                     float *__restrict__ u) {
+                                                     float *__restrict__ u,
+                                                     float *__restrict__ nustar) {
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
@@ -69,11 +73,40 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f32(Lattice L, Phys P,
   Offs o;
   site_offsets(L, r, o);
   const double ph = phi[r];
-  float nr[K];
+  float dv[K], nr[K], js[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) nr[k] = P.nref_f[k] + nu[k * N + r];
-  float F0, F1, F2;
-  link_force_f32<K>(L, P, r, m, o, phi, nu, ph, nr, F0, F1, F2);
+  for (int k = 0; k < K; ++k) {
+    dv[k] = nu[k * N + r];
+    nr[k] = P.nref_f[k] + dv[k];
+    js[k] = 0.f;
+  }
+  float F0 = 0.f, F1 = 0.f, F2 = 0.f;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;  // no flux into an electrode
+    const int rn = nbr(o, r, i);
+    const double dphi = phi[rn] - ph - P.Ec[i];
+    const float d1 = float(dphi);
+    float S1, C1;
+    sinh_coshm1f(d1, S1, C1);
+    const float il = float(1.0 / LEN[i]);
+    float g = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float dn = nu[k * N + rn];
+      const float nt = P.nref_f[k] + dn;
+      float S, C;
+      valence_scf(P.z[k], dphi, d1, S1, C1, S, C);
+      const float gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * float(0.5 / LEN[i]);
+      g += gk;
+      // the ideal part uses the deviations directly: (n' - n) = (nu' - nu)
+      js[k] += P.dk_f[k] * (gk - (dn - dv[k]) * il);
+    }
+    const float c = float(3.0 * WQ[i] * LEN[i]) * g;
+    if (CX[i]) F0 += CX[i] * c;
+    if (CY[i]) F1 += CY[i] * c;
+    if (CZ[i]) F2 += CZ[i] * c;
+  }
 
   float h[NQ];
   pull_f32(L, r, m, o, hin, h);
@@ -108,15 +141,19 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f32(Lattice L, Phys P,
   u[r] = ux;
   u[N + r] = uy;
   u[2 * N + r] = uz;
+#pragma unroll
+  for (int k = 0; k < K; ++k) nustar[k * N + r] = dv[k] - js[k];
 }
 
+// Pass B: advective link fluxes J_k = 3 w_i c_i . (n_k u + n_k' u') with the
+// step's velocity; nu_k(t+1) = nu*_k - sum_i J_k in place in nuio; Poisson
+// source (4 pi l_B / 6) rho_el accumulated in FP64.
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_ions_f32(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
-                                                    const double *__restrict__ phi,
                                                     const float *__restrict__ u,
                                                     const float *__restrict__ nu,
-                                                    float *__restrict__ nuout,
+                                                    float *__restrict__ nuio,
                                                     double *__restrict__ src) {
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= L.n) return;
@@ -125,42 +162,31 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f32(Lattice L, Phys P,
   const int N = L.n;
   Offs o;
   site_offsets(L, r, o);
-  const double ph = phi[r];
   const float ux = u[r], uy = u[N + r], uz = u[2 * N + r];
-  float dv[K], nr[K], acc[K];
+  float nr[K], Js[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    dv[k] = nu[k * N + r];
-    nr[k] = P.nref_f[k] + dv[k];
-    acc[k] = 0.f;
+    nr[k] = P.nref_f[k] + nu[k * N + r];
+    Js[k] = 0.f;
   }
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if (solid_link(m, i)) continue;
     const int rn = nbr(o, r, i);
-    const double dphi = phi[rn] - ph - P.Ec[i];
     float cu_h = 0.f, cu_t = 0.f;
     if (CX[i]) { cu_h += CX[i] * ux; cu_t += CX[i] * u[rn]; }
     if (CY[i]) { cu_h += CY[i] * uy; cu_t += CY[i] * u[N + rn]; }
     if (CZ[i]) { cu_h += CZ[i] * uz; cu_t += CZ[i] * u[2 * N + rn]; }
     const float w3 = float(3.0 * WQ[i]);
-    const float il = float(1.0 / LEN[i]);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const float dn = nu[k * N + rn];
-      const float nn = P.nref_f[k] + dn;
-      const float g = excess_link_f(nr[k], nn, float(P.z[k] * dphi), float(0.5 / LEN[i]));
-      // the ideal part uses the deviations directly: (n' - n) = (nu' - nu)
-      const float j = P.dk_f[k] * (g - (dn - dv[k]) * il);
-      const float J = w3 * (nr[k] * cu_h + nn * cu_t);
-      acc[k] += j + J;
-    }
+    for (int k = 0; k < K; ++k)
+      Js[k] += w3 * (nr[k] * cu_h + (P.nref_f[k] + nu[k * N + rn]) * cu_t);
   }
   double q = P.qref;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const float v = dv[k] - acc[k];
-    nuout[k * N + r] = v;
+    const float v = nuio[k * N + r] - Js[k];
+    nuio[k * N + r] = v;
     q += P.z[k] * double(v);
   }
   src[r] = P.src_scale * q;
@@ -248,19 +274,18 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f32(Lattice L, Phys P,
 
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
-                            float *u) {
+                            float *u, float *nustar) {
 #define CALL(KK) \
-  hipLaunchKernelGGL(k_fluid_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, nu, hin, hout, u)
+  hipLaunchKernelGGL(k_fluid_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, nu, hin, hout, u, nustar)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   return hipGetLastError();
 }
 
 hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const double *phi, const float *u, const float *nu, float *nuout,
-                           double *src) {
+                           const float *u, const float *nu, float *nuio, double *src) {
 #define CALL(KK) \
-  hipLaunchKernelGGL(k_ions_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, u, nu, nuout, src)
+  hipLaunchKernelGGL(k_ions_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, u, nu, nuio, src)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   return hipGetLastError();

@@ -48,17 +48,28 @@ __device__ __forceinline__ int nbr_of(const MgLevel &lv, const Coords &c, int i)
   return wrapi(c.x + CX[i], lv.nx) + lv.nx * (wrapi(c.y + CY[i], lv.ny) + lv.ny * wrapi(c.z + CZ[i], lv.nz));
 }
 
+// v[i] = e at the neighbour c + c_i of a level's cell (v[0] = e[r]); all loads
+// are issued before any value is used
+template <class T>
+__device__ __forceinline__ void gather_lv(const MgLevel &lv, const Coords &c, int r,
+                                          const T *__restrict__ e, T (&v)[NQ]) {
+  v[0] = e[r];
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) v[i] = e[nbr_of(lv, c, i)];
+}
+
 // A e at a fluid cell, in the level's units: (6/h^2) sum_i w_i s_i (e - e_i)
 template <class T>
 __device__ __forceinline__ T apply_A(const MgLevel &lv, int r, uint32_t m, const Coords &c,
                                      const T *__restrict__ e) {
-  const T er = e[r];
+  T v[NQ];
+  gather_lv(lv, c, r, e, v);
   T acc = T(0);
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((lv.selfm >> (i - 1)) & 1u) continue;
     const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
-    acc += ws * (er - e[nbr_of(lv, c, i)]);
+    acc += ws * (v[0] - v[i]);
   }
   return T(6.0) * T(lv.inv_h2) * acc;
 }
@@ -81,15 +92,17 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
     double R = 0.0;
     if (!(m & SOLID_BIT)) {
       const Coords c = coords_of(r, lv.nx, lv.nxy);
-      const double ph = phi[r];
+      double pn[NQ];
+      gather_lv(lv, c, r, phi, pn);
+      const double sr = src[r];
       double acc = 0.0;
 #pragma unroll
       for (int i = 1; i < NQ; ++i) {
         if ((lv.selfm >> (i - 1)) & 1u) continue;
         const double ws = solid_link(m, i) ? 2.0 * WQ[i] : WQ[i];
-        acc += ws * (phi[nbr_of(lv, c, i)] - ph);
+        acc += ws * (pn[i] - pn[0]);
       }
-      R = 6.0 * (acc + src[r]);
+      R = 6.0 * (acc + sr);
       a = fabs(R);
     }
     r0[r] = T(R);
@@ -122,16 +135,19 @@ __global__ __launch_bounds__(BLOCK) void k_smooth(MgLevel lv, T omega, int colou
   const int r = c.x + lv.nx * (c.y + lv.ny * z);
   const uint32_t m = mask[r];
   if (m & SOLID_BIT) return;
+  T v[NQ];
+  gather_lv(lv, c, r, (const T *)e, v);
+  const T rr = rhs[r];
   T num = T(0), den = T(0);
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((lv.selfm >> (i - 1)) & 1u) continue;
     const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
-    num += ws * e[nbr_of(lv, c, i)];
+    num += ws * v[i];
     den += ws;
   }
-  num += T(lv.h2 / 6.0) * rhs[r];
-  e[r] = (T(1) - omega) * e[r] + omega * (num / den);
+  num += T(lv.h2 / 6.0) * rr;
+  e[r] = (T(1) - omega) * v[0] + omega * (num / den);
 }
 
 // ---- damped Jacobi sweep (one launch, every cell in parallel) --------------
@@ -153,20 +169,58 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
     return;
   }
   const Coords c = coords_of(r, lv.nx, lv.nxy);
+  T v[NQ];
+  gather_lv(lv, c, r, x_in, v);
+  const T rr = rhs[r];
   T num = T(0), den = T(0);
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((lv.selfm >> (i - 1)) & 1u) continue;
     const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
-    num += ws * x_in[nbr_of(lv, c, i)];
+    num += ws * v[i];
     den += ws;
   }
-  num += hs * rhs[r];
-  const T xr = x_in[r];
+  num += hs * rr;
+  const T xr = v[0];
   x_out[r] = xr + omega * (num / den - xr);
 }
 
 // ---- restriction: coarse rhs = mean of the fluid children's residuals -------
+// Eight consecutive lanes take the eight children of one coarse cell (lane
+// bits = dx, dy, dz) and combine their residuals with cross-lane adds, so
+// each lane evaluates one fine-cell residual.  Groups of eight never straddle
+// a wavefront.
+
+// Residual of child j (bits dx, dy, dz) of coarse cell R, or nothing when
+// the child is solid or falls outside an odd-sized fine level.
+template <class T>
+__device__ __forceinline__ void restrict_child(const MgTransfer &tr, int R, int j,
+                                               const uint32_t *__restrict__ mf,
+                                               const T *__restrict__ rf,
+                                               const T *__restrict__ ef, T &v, int &cnt) {
+  const Coords C = coords_of(R, tr.c.nx, tr.c.nxy);
+  const int xp = 2 * C.x + (j & 1), yp = 2 * C.y + ((j >> 1) & 1), zp = 2 * C.z + (j >> 2);
+  if (xp >= tr.f.nx || yp >= tr.f.ny || zp >= tr.f.nz) return;
+  Coords c;
+  c.x = wrapi(xp + tr.ox, tr.f.nx);
+  c.y = wrapi(yp + tr.oy, tr.f.ny);
+  c.z = wrapi(zp + tr.oz, tr.f.nz);
+  const int r = c.x + tr.f.nx * (c.y + tr.f.ny * c.z);
+  const uint32_t m = mf[r];
+  if (m & SOLID_BIT) return;
+  v = rf[r] - apply_A<T>(tr.f, r, m, c, ef);
+  cnt = 1;
+}
+
+// sum of v and cnt over the eight lanes of an aligned group
+template <class T>
+__device__ __forceinline__ void group8_sum(T &v, int &cnt) {
+#pragma unroll
+  for (int off = 1; off < 8; off <<= 1) {
+    v += __shfl_xor(v, off);
+    cnt += __shfl_xor(cnt, off);
+  }
+}
 
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_restrict(MgTransfer tr, const uint32_t *__restrict__ mf,
@@ -176,41 +230,20 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(MgTransfer tr, const uint32_
                                                     T *__restrict__ ec,
                                                     const SolveCtl *__restrict__ ctl) {
   if (ctl->done) return;
-  const int R = blockIdx.x * BLOCK + threadIdx.x;
-  if (R >= tr.c.n) return;
-  ec[R] = T(0);
-  if (mc[R] & SOLID_BIT) {
-    rc[R] = T(0);
-    return;
-  }
-  const Coords C = coords_of(R, tr.c.nx, tr.c.nxy);
-  T sum = T(0);
+  const int t = blockIdx.x * BLOCK + threadIdx.x;
+  const int R = t >> 3, j = t & 7;
+  T v = T(0);
   int cnt = 0;
-  for (int dz = 0; dz < 2; ++dz) {
-    const int zp = 2 * C.z + dz;
-    if (zp >= tr.f.nz) break;
-    const int z = wrapi(zp + tr.oz, tr.f.nz);
-    for (int dy = 0; dy < 2; ++dy) {
-      const int yp = 2 * C.y + dy;
-      if (yp >= tr.f.ny) break;
-      const int y = wrapi(yp + tr.oy, tr.f.ny);
-      for (int dx = 0; dx < 2; ++dx) {
-        const int xp = 2 * C.x + dx;
-        if (xp >= tr.f.nx) break;
-        const int x = wrapi(xp + tr.ox, tr.f.nx);
-        const int r = x + tr.f.nx * (y + tr.f.ny * z);
-        const uint32_t m = mf[r];
-        if (m & SOLID_BIT) continue;
-        Coords c;
-        c.x = x;
-        c.y = y;
-        c.z = z;
-        sum += rf[r] - apply_A<T>(tr.f, r, m, c, ef);
-        ++cnt;
-      }
-    }
+  bool fluid = false;
+  if (R < tr.c.n) {
+    fluid = !(mc[R] & SOLID_BIT);
+    if (fluid) restrict_child<T>(tr, R, j, mf, rf, ef, v, cnt);
   }
-  rc[R] = cnt ? sum / T(cnt) : T(0);
+  group8_sum(v, cnt);
+  if (j == 0 && R < tr.c.n) {
+    ec[R] = T(0);
+    rc[R] = (fluid && cnt) ? v / T(cnt) : T(0);
+  }
 }
 
 // ---- prolongation: e_f += trilinear interpolation of e_c --------------------
@@ -238,20 +271,28 @@ __device__ __forceinline__ T prolong_value(const MgTransfer &tr, int r,
       wgt[a] = T(0.75);
     }
   }
-  const int parent = P[0] + tr.c.nx * (P[1] + tr.c.ny * P[2]);
-  if (mc[parent] & SOLID_BIT) return T(0);
-  const T ep = ec[parent];
-  T v = T(0);
+  // flags and corrections of the eight surrounding coarse cells (k = 0 is the
+  // parent), loaded together before use
+  uint32_t mk[8];
+  T ev[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int ix = (k & 1) ? Nb[0] : P[0];
     const int iy = (k & 2) ? Nb[1] : P[1];
     const int iz = (k & 4) ? Nb[2] : P[2];
+    const int R = ix + tr.c.nx * (iy + tr.c.ny * iz);
+    mk[k] = mc[R];
+    ev[k] = ec[R];
+  }
+  if (mk[0] & SOLID_BIT) return T(0);
+  const T ep = ev[0];
+  T v = T(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
     const T w = ((k & 1) ? T(1) - wgt[0] : wgt[0]) * ((k & 2) ? T(1) - wgt[1] : wgt[1]) *
                 ((k & 4) ? T(1) - wgt[2] : wgt[2]);
     if (w == T(0)) continue;
-    const int R = ix + tr.c.nx * (iy + tr.c.ny * iz);
-    const T val = (mc[R] & SOLID_BIT) ? -ep : ec[R];
+    const T val = (mk[k] & SOLID_BIT) ? -ep : ev[k];
     v += w * val;
   }
   return v;
@@ -266,7 +307,8 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(MgTransfer tr, const uint32_t
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= tr.f.n) return;
   if (mf[r] & SOLID_BIT) return;
-  ef[r] += prolong_value<T>(tr, r, mc, ec);
+  const T e0 = ef[r];
+  ef[r] = e0 + prolong_value<T>(tr, r, mc, ec);
 }
 
 // ---- coarsest level: one work-group, colour sweeps with barriers ------------
@@ -303,7 +345,18 @@ __global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, in
 }
 
 // ---- coarsest level, exact: e = A^-1 r over the level's fluid cells ----------
-// One wavefront per row of the precomputed inverse (row-major, nf x nf).
+// Eight lanes per row: lane `part` sums the columns j = part (mod 8), then the
+// group adds its partial sums.  The inverse is stored column-major
+// (ainv[j * nf + row]).
+
+template <class T>
+__device__ __forceinline__ T dense_row_part(int nf, const T *__restrict__ ainv,
+                                            const T *__restrict__ x, int row, int part) {
+  T acc = T(0);
+#pragma unroll 6
+  for (int j = part; j < nf; j += 8) acc += ainv[(size_t)j * nf + row] * x[j];
+  return acc;
+}
 
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_coarse_dense(int nf, const T *__restrict__ ainv,
@@ -311,16 +364,16 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_dense(int nf, const T *__restr
                                                         const T *__restrict__ rhs,
                                                         T *__restrict__ e,
                                                         const SolveCtl *__restrict__ ctl) {
+  __shared__ T xc[MG_MAX_DENSE];
   if (ctl->done) return;
-  const int row = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
-  const int lane = threadIdx.x & (WAVE - 1);
-  if (row >= nf) return;
-  const T *a = ainv + (size_t)row * nf;
-  T acc = T(0);
-  for (int k = lane; k < nf; k += WAVE) acc += a[k] * rhs[fcell[k]];
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) e[fcell[row]] = acc;
+  for (int j = threadIdx.x; j < nf; j += BLOCK) xc[j] = rhs[fcell[j]];
+  __syncthreads();
+  const int t = blockIdx.x * BLOCK + threadIdx.x;
+  const int row = t >> 3, part = t & 7;
+  T acc = row < nf ? dense_row_part(nf, ainv, xc, row, part) : T(0);
+  int dummy = 0;
+  group8_sum(acc, dummy);
+  if (part == 0 && row < nf) e[fcell[row]] = acc;
 }
 
 // ---- the coarse end of the V-cycle in one work-group --------------------------
@@ -337,8 +390,41 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
   T *e = lds + S.off_e[k];
   const T *rh = lds + S.off_r[k];
   const uint32_t *mk = sm + S.off_m[k];
-  const int hx = (lv.nx + 1) / 2, hy = (lv.ny + 1) / 2, plane = hx * hy;
   const T hs = T(lv.h2 / 6.0);
+  if (S.jacobi > 0.0) {
+    // Jacobi in pairs e -> e2 -> e, the arithmetic of k_jacobi
+    T *e2 = lds + S.off_e2[k];
+    const T om = T(S.jacobi);
+    for (int s = 0; s < sweeps; s += 2)
+      for (int pass = 0; pass < 2; ++pass) {
+        const T *xi = pass ? e2 : e;
+        T *xo = pass ? e : e2;
+        for (int r = threadIdx.x; r < lv.n; r += SMALL_BLOCK) {
+          const uint32_t m = mk[r];
+          if (m & SOLID_BIT) {
+            xo[r] = T(0);
+            continue;
+          }
+          const Coords c = coords_of(r, lv.nx, lv.nxy);
+          T v[NQ];
+          gather_lv(lv, c, r, xi, v);
+          T num = T(0), den = T(0);
+#pragma unroll
+          for (int i = 1; i < NQ; ++i) {
+            if ((lv.selfm >> (i - 1)) & 1u) continue;
+            const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
+            num += ws * v[i];
+            den += ws;
+          }
+          num += hs * rh[r];
+          xo[r] = v[0] + om * (num / den - v[0]);
+        }
+        __syncthreads();
+      }
+    return;
+  }
+  // four-colour Gauss-Seidel
+  const int hx = (lv.nx + 1) / 2, hy = (lv.ny + 1) / 2, plane = hx * hy;
   for (int s = 0; s < sweeps; ++s)
     for (int col = 0; col < 4; ++col) {
       for (int t = threadIdx.x; t < plane * lv.nz; t += SMALL_BLOCK) {
@@ -352,12 +438,14 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
         const int r = c.x + lv.nx * (c.y + lv.ny * c.z);
         const uint32_t m = mk[r];
         if (m & SOLID_BIT) continue;
+        T v[NQ];
+        gather_lv(lv, c, r, (const T *)e, v);
         T num = T(0), den = T(0);
 #pragma unroll
         for (int i = 1; i < NQ; ++i) {
           if ((lv.selfm >> (i - 1)) & 1u) continue;
           const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
-          num += ws * e[nbr_of(lv, c, i)];
+          num += ws * v[i];
           den += ws;
         }
         num += hs * rh[r];
@@ -383,7 +471,7 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_mg_small(MgSmall S, const T *__
     lds[S.off_e[0] + r] = T(0);
   }
   __syncthreads();
-  // down: smooth, restrict
+  // down: smooth, restrict (eight lanes per coarse cell, as k_restrict)
   for (int k = 0; k + 1 < S.nlev; ++k) {
     small_smooth<T>(S, k, S.nu1, lds, sm);
     const MgTransfer &tr = S.tr[k + 1];
@@ -391,40 +479,17 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_mg_small(MgSmall S, const T *__
     const T *rf = lds + S.off_r[k];
     const uint32_t *mf = sm + S.off_m[k];
     const uint32_t *mc = sm + S.off_m[k + 1];
-    for (int R = threadIdx.x; R < tr.c.n; R += SMALL_BLOCK) {
-      lds[S.off_e[k + 1] + R] = T(0);
-      T val = T(0);
-      if (!(mc[R] & SOLID_BIT)) {
-        const Coords C = coords_of(R, tr.c.nx, tr.c.nxy);
-        T sum = T(0);
-        int cnt = 0;
-        for (int dz = 0; dz < 2; ++dz) {
-          const int zp = 2 * C.z + dz;
-          if (zp >= tr.f.nz) break;
-          const int z = wrapi(zp + tr.oz, tr.f.nz);
-          for (int dy = 0; dy < 2; ++dy) {
-            const int yp = 2 * C.y + dy;
-            if (yp >= tr.f.ny) break;
-            const int y = wrapi(yp + tr.oy, tr.f.ny);
-            for (int dx = 0; dx < 2; ++dx) {
-              const int xp = 2 * C.x + dx;
-              if (xp >= tr.f.nx) break;
-              const int x = wrapi(xp + tr.ox, tr.f.nx);
-              const int r = x + tr.f.nx * (y + tr.f.ny * z);
-              const uint32_t m = mf[r];
-              if (m & SOLID_BIT) continue;
-              Coords c;
-              c.x = x;
-              c.y = y;
-              c.z = z;
-              sum += rf[r] - apply_A<T>(tr.f, r, m, c, ef);
-              ++cnt;
-            }
-          }
-        }
-        val = cnt ? sum / T(cnt) : T(0);
+    for (int t = threadIdx.x; t < 8 * tr.c.n; t += SMALL_BLOCK) {
+      const int R = t >> 3, j = t & 7;
+      const bool fluid = !(mc[R] & SOLID_BIT);
+      T v = T(0);
+      int cnt = 0;
+      if (fluid) restrict_child<T>(tr, R, j, mf, rf, ef, v, cnt);
+      group8_sum(v, cnt);
+      if (j == 0) {
+        lds[S.off_e[k + 1] + R] = T(0);
+        lds[S.off_r[k + 1] + R] = (fluid && cnt) ? v / T(cnt) : T(0);
       }
-      lds[S.off_r[k + 1] + R] = val;
     }
     __syncthreads();
   }
@@ -434,15 +499,17 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_mg_small(MgSmall S, const T *__
     T *e = lds + S.off_e[k];
     const T *rh = lds + S.off_r[k];
     if (S.ainv) {
+      // compact right-hand side over the fluid cells, then eight lanes per row
       const T *ainv = reinterpret_cast<const T *>(S.ainv);
-      const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
-      for (int row = wv; row < S.nf; row += SMALL_BLOCK / WAVE) {
-        const T *a = ainv + (size_t)row * S.nf;
-        T acc = T(0);
-        for (int j = lane; j < S.nf; j += WAVE) acc += a[j] * rh[S.fcell[j]];
-#pragma unroll
-        for (int off = WAVE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-        if (lane == 0) e[S.fcell[row]] = acc;
+      T *xc = lds + S.off_x;
+      for (int j = threadIdx.x; j < S.nf; j += SMALL_BLOCK) xc[j] = rh[S.fcell[j]];
+      __syncthreads();
+      for (int t = threadIdx.x; t < 8 * S.nf; t += SMALL_BLOCK) {
+        const int row = t >> 3, part = t & 7;
+        T acc = dense_row_part(S.nf, ainv, xc, row, part);
+        int dummy = 0;
+        group8_sum(acc, dummy);
+        if (part == 0) e[S.fcell[row]] = acc;
       }
       __syncthreads();
     } else {
@@ -458,7 +525,8 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_mg_small(MgSmall S, const T *__
     const uint32_t *mc = sm + S.off_m[k + 1];
     for (int r = threadIdx.x; r < tr.f.n; r += SMALL_BLOCK) {
       if (mf[r] & SOLID_BIT) continue;
-      ef[r] += prolong_value<T>(tr, r, mc, ec);
+      const T e0 = ef[r];
+      ef[r] = e0 + prolong_value<T>(tr, r, mc, ec);
     }
     __syncthreads();
     small_smooth<T>(S, k, S.nu2, lds, sm);
@@ -515,8 +583,8 @@ template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
                               const SolveCtl *ctl) {
-  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(tr.c.n)), dim3(BLOCK), 0, s, tr, mf, mc, rf,
-                     ef, rc, ec, ctl);
+  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(8L * tr.c.n)), dim3(BLOCK), 0, s, tr, mf, mc,
+                     rf, ef, rc, ec, ctl);
   return hipGetLastError();
 }
 
@@ -539,9 +607,8 @@ hipError_t launch_mg_coarse(hipStream_t s, const MgLevel &lv, double omega, int 
 template <class T>
 hipError_t launch_mg_coarse_dense(hipStream_t s, int nf, const T *ainv, const int *fcell,
                                   const T *rhs, T *e, const SolveCtl *ctl) {
-  const int rows_per_block = BLOCK / WAVE;
-  hipLaunchKernelGGL(k_coarse_dense<T>, dim3((nf + rows_per_block - 1) / rows_per_block),
-                     dim3(BLOCK), 0, s, nf, ainv, fcell, rhs, e, ctl);
+  hipLaunchKernelGGL(k_coarse_dense<T>, dim3(blocks_for(8L * nf)), dim3(BLOCK), 0, s, nf, ainv,
+                     fcell, rhs, e, ctl);
   return hipGetLastError();
 }
 
