@@ -9,8 +9,12 @@ FP64 form with multigrid and the FP64 form with the paper's SOR solver are
 measured in the same run under "forms".  MLUPS = lattice sites x steps / wall
 seconds / 1e6 over the timed steps, inputs resident in HBM.  A second window
 of the same length brackets every launch with HIP events on the library's
-stream to give per-kernel average durations; the roofline object is for the
-kernel with the largest total time.  cpu_baseline times the FP64 oracle.
+stream to give per-kernel average durations and the cells each launch
+covers; the roofline object is for the kernel kind with the largest total
+time, with measured traffic from the rocprofv3 summary in profiles/ when the
+kernel sources are unchanged since it was taken.  "shapes" repeats the
+measurement on the coaxial (1.64 M sites) and porous-electrode (7.08 M
+sites) lattices.  cpu_baseline times the FP64 oracle.
 """
 from __future__ import annotations
 
@@ -70,6 +74,37 @@ def bytes_per_cell(kind: str, form: str, K: int):
     return table.get(kind)
 
 
+def sources_hash():
+    """Hash of the kernel sources (file names and contents under csrc/)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1907_04732_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """Measured bytes per launch, {(form, kind): fetch + write}, from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary in profiles/, or {} when there
+    is none or the kernel sources have changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"step_traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return {}
+    rows, src = {}, None
+    with open(path) as fh:
+        for line in fh:
+            t = line.split()
+            if len(t) == 5 and t[0] == "traffic":
+                rows[(t[1], t[2])] = float(t[3]) + float(t[4])
+            elif len(t) == 2 and t[0] == "sources":
+                src = t[1]
+    return rows if src == sources_hash() else {}
+
+
 def sync():
     try:
         import torch
@@ -79,7 +114,8 @@ def sync():
         pass
 
 
-def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, check_every: int):
+def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, check_every: int,
+             traffic=None):
     precision = lbe.FP64 if form == "fp64" else lbe.FP32_MIXED
     poisson = lbe.SOR4 if solver == "sor" else lbe.MG
     # multigrid forms start each solve from 2 phi(t) - phi(t-1); the SOR form
@@ -126,6 +162,9 @@ def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, che
             row["bytes_per_launch"] = int(round(per_launch))
             row["achieved_GBs"] = round(per_launch / avg / 1e9, 1)
             row["frac"] = round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4)
+        t = (traffic or {}).get((f"{form}-{solver}", k))
+        if t is not None:
+            row["traffic_bytes_per_launch"] = int(t)
         kernels[k] = row
         print(f"bench:   {k:12s} {ms:9.3f} ms, {cnt:6d} launches, {avg * 1e6:8.2f} us avg"
               + (f", {row['achieved_GBs']:8.1f} GB/s" if b is not None else ""),
@@ -135,7 +174,7 @@ def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, che
     d = kernels[dom]
     roof = {"bound": "hbm", "kernel": dom, "achieved": d.get("achieved_GBs"), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": d.get("frac"), "bytes_per_launch": d.get("bytes_per_launch"),
-            "avg_launch_us": d["avg_us"], "traffic": None}
+            "avg_launch_us": d["avg_us"], "traffic": d.get("traffic_bytes_per_launch")}
     return {"mlups": round(mlups, 3), "ms_per_step": round(el / steps * 1e3, 4),
             "fluid_mlups": round(nfluid * steps / el / 1e6, 3),
             "poisson_iters_per_step": round(iters, 3), "roofline": roof, "kernels": kernels}
@@ -232,13 +271,14 @@ def main():
     print(f"bench: {w.name}, {N} sites", file=sys.stderr, flush=True)
     if args.copy_calibration:
         copy_calibration()
+    traffic = load_traffic(w.name)
     res = {}
     for name in forms:
         form, solver = FORMS[name]
         # SOR needs hundreds of sweeps per step: time fewer steps
         steps = args.steps if solver == "mg" else max(2, args.steps // 10)
         res[name] = run_form(w, form, solver, steps, args.warmup if solver == "mg" else 2,
-                             args.check_every)
+                             args.check_every, traffic)
     head = res[forms[0]]
     hform, hsolver = FORMS[forms[0]]
     out = {

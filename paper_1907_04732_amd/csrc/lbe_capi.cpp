@@ -381,7 +381,13 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
   }
   if ((rc = check(0))) return rc;
   int queued = 0;
-  int target = std::max(c->pred_iters, per_check);
+  // While profiling, one unit at a time with a read of the stop flag after
+  // each, so that no timed launch is an early exit (the result is the same).
+  int target = c->prof ? per_check : std::max(c->pred_iters, per_check);
+  if (c->prof) {
+    if ((rc = read_ctl(c))) return rc;
+    if (c->ctl_h->done) target = 0;  // converged before the first unit
+  }
   for (;;) {
     target = std::min(target, p.max_iter);
     while (queued < target) {
@@ -400,7 +406,7 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
                c->ctl_h->resid, queued, unit);
       return fail(c, LBE_ENOCONV, buf);
     }
-    target = queued + std::max(per_check, queued / 4);
+    target = queued + (c->prof ? per_check : std::max(per_check, queued / 4));
   }
   const int iters = c->ctl_h->iters;
   c->last_iters = iters;
