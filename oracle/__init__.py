@@ -23,6 +23,7 @@ _SRC = os.path.join(_HERE, "lbe_oracle.c")
 _LIB = os.path.join(_HERE, "liblbe_oracle.so")
 
 FLAG_ALLOW_FLOATING = 1
+FLAG_NAIVE_DIRICHLET = 4  # first-order scheme: potential on the solid nodes, Eq. 12 everywhere
 
 OK, EINVAL, EGEOM, ENOMEM, ENOCONV, ENONFINITE = 0, -1, -2, -3, -5, -6
 
@@ -82,6 +83,8 @@ def _load(path=None):
     lib.orc_step.restype = C.c_int
     lib.orc_poisson.argtypes = [C.c_void_p, P(C.c_int), d]
     lib.orc_poisson.restype = C.c_int
+    lib.orc_set_electrode_potential.argtypes = [C.c_void_p, d]
+    lib.orc_set_electrode_potential.restype = C.c_int
     lib.orc_electrode_charge.argtypes = [C.c_void_p, d, C.c_int]
     lib.orc_electrode_charge.restype = C.c_int
     lib.orc_num_electrodes.argtypes = [C.c_void_p]
@@ -192,6 +195,14 @@ class Oracle:
         res = C.c_double()
         self._check(self._lib.orc_poisson(self.h, C.byref(it), C.byref(res)))
         return it.value, res.value
+
+    def set_electrode_potential(self, phi_s):
+        """New potentials of the solid nodes (length N, fluid entries ignored);
+        re-solves Poisson and replaces the current step's recorded charge."""
+        ps = np.ascontiguousarray(phi_s, dtype=np.float64)
+        if ps.size != self.N:
+            raise ValueError("phi_s must have one entry per lattice site")
+        self._check(self._lib.orc_set_electrode_potential(self.h, _dptr(ps)))
 
     def electrode_charge(self):
         q = np.zeros(max(self.ne, 1))

@@ -41,6 +41,9 @@
  *   R7 the modified Laplacian is applied with the factor 2 on both ends of a
  *      solid-fluid link; solid-solid links carry no charge;
  *   R9 SOR is diagonal-normalised and sweeps four colours in a fixed order.
+ *
+ * Flag ORC_FLAG_NAIVE_DIRICHLET selects the first-order scheme the paper
+ * contrasts with (potential held on the solid nodes, Eq. 12 everywhere).
  */
 #include <math.h>
 #include <stdint.h>
@@ -57,6 +60,11 @@
 #define ORC_ENONFINITE -6
 
 #define ORC_FLAG_ALLOW_FLOATING 1 /* fluid regions that touch no electrode */
+/* The paper's first-order contrast (Sec. II C, before Eq. 14): the electrode
+ * potential is held on the solid nodes and the plain Laplacian of Eq. 12 is
+ * used on every link (factor 1 instead of 2 on solid-fluid links), both in
+ * the Poisson equation and in Gauss's law for the charge. */
+#define ORC_FLAG_NAIVE_DIRICHLET 4
 
 /* ---- D3Q19 (Sec. II B): rest, 6 nearest, 12 next-nearest neighbours --- */
 #define NQ 19
@@ -166,12 +174,17 @@ static double charge_density(const orc_state *s, long r) {
  * Dirichlet value phi_s at the mid-link.  A link from a node to itself (a box
  * of size 1 along an axis) has a zero difference and is left out.
  */
+/* Factor on a solid-fluid link: 2 (Eq. 15), or 1 in the naive mode (Eq. 12). */
+static double wall_factor(const orc_state *s) {
+  return (s->p.flags & ORC_FLAG_NAIVE_DIRICHLET) ? 1.0 : 2.0;
+}
+
 static double laplacian_fluid(const orc_state *s, long r) {
   double acc = 0.0;
   for (int i = 1; i < NQ; ++i) {
     long rn = nbr(s, r, i);
     if (rn == r) continue;
-    double factor = is_fluid(s, rn) ? 1.0 : 2.0;
+    double factor = is_fluid(s, rn) ? 1.0 : wall_factor(s);
     acc += weight(i) * factor * (s->phi[rn] - s->phi[r]);
   }
   return 6.0 * acc; /* 2 / c_s^2 = 6 */
@@ -204,7 +217,7 @@ static void sor_update(orc_state *s, long r) {
   for (int i = 1; i < NQ; ++i) {
     long rn = nbr(s, r, i);
     if (rn == r) continue;
-    double ws = weight(i) * (is_fluid(s, rn) ? 1.0 : 2.0);
+    double ws = weight(i) * (is_fluid(s, rn) ? 1.0 : wall_factor(s));
     num += ws * s->phi[rn];
     den += ws;
   }
@@ -273,7 +286,7 @@ static void electrode_charges(const orc_state *s, double *q) {
     for (int i = 1; i < NQ; ++i) {
       long rn = nbr(s, r, i);
       if (!is_fluid(s, rn)) continue;
-      lap += weight(i) * 2.0 * (s->phi[rn] - s->phi[r]);
+      lap += weight(i) * wall_factor(s) * (s->phi[rn] - s->phi[r]);
     }
     q[e - 1] += -(6.0 * lap) / (4.0 * M_PI * s->p.lB);
   }
@@ -547,6 +560,10 @@ static int validate(const orc_params *p, char *err, size_t errlen) {
       snprintf(err, errlen, "applied field must be finite");
       return ORC_EINVAL;
     }
+  if (p->flags & ~(ORC_FLAG_ALLOW_FLOATING | ORC_FLAG_NAIVE_DIRICHLET)) {
+    snprintf(err, errlen, "unknown flags");
+    return ORC_EINVAL;
+  }
   return ORC_OK;
 }
 
@@ -670,6 +687,31 @@ int orc_step(orc_state *s, long nsteps) {
     rc = record_charge(s);
     if (rc) return rc;
   }
+  return ORC_OK;
+}
+
+/*
+ * New electrode potentials (a time-dependent or non-linear voltage study,
+ * Sec. I and IV): phi_s[r] is taken for every solid node (fluid entries are
+ * ignored), Poisson is re-solved for the current concentrations (warm start
+ * from the current phi), and the charge recorded for the current step is
+ * replaced by the one of the new potentials.
+ */
+int orc_set_electrode_potential(orc_state *s, const double *phi_s) {
+  if (!s || !phi_s) return ORC_EINVAL;
+  for (long r = 0; r < s->N; ++r)
+    if (s->type[r] && !isfinite(phi_s[r])) {
+      snprintf(s->err, sizeof s->err, "non-finite electrode potential");
+      return ORC_EINVAL;
+    }
+  for (long r = 0; r < s->N; ++r)
+    if (s->type[r]) {
+      s->phi_s[r] = phi_s[r];
+      s->phi[r] = phi_s[r];
+    }
+  int rc = poisson_solve(s);
+  if (rc) return rc;
+  if (s->ne && s->qlen > 0) electrode_charges(s, s->qhist + (s->qlen - 1) * s->ne);
   return ORC_OK;
 }
 

@@ -405,3 +405,106 @@ def pin_advection_shear(libpath=None):
               + a * U * math.sin(k) * (2 + math.cos(q)) / 3 * np.sin(k * x) * np.sin(q * y))
     err = np.abs(n1 - expect).max() / (a * U)
     assert err < 1e-9, err
+
+
+# ---- first-order scheme, electrode potentials, non-linear steady state ------
+
+NAIVE = oracle.FLAG_NAIVE_DIRICHLET
+
+
+def pin_naive_neutral_slab(layers=1, nxy=2, libpath=None):
+    """The first-order scheme the paper contrasts with (Sec. II C, Fig. 1):
+    phi_s held on the solid nodes and the plain Laplacian of Eq. 12 on every
+    link.  In a neutral liquid the discrete solution is then exactly linear
+    through the last solid node of each electrode, nf + 1 spacings apart, and
+    Gauss's law with the same Laplacian gives Q(0) = eps dV / (nf + 1) per
+    unit area: the dielectric capacitance with a gap one spacing too wide, a
+    first-order error."""
+    nf, V1, V2 = 32, 0.05, -0.05
+    shape, t, ps = W.slab(nxy, nxy, nf, layers, V1, V2)
+    o = _run(shape, t, ps, (1, -1), (0.05, 0.05), n_ref=(1e-3, 1e-3), tol=1e-14, omega=1.8,
+             flags=NAIVE, libpath=libpath)
+    phi = o.fields()["phi"].reshape(shape[2], nxy, nxy)
+    zc = np.arange(layers, layers + nf) - (layers - 1)  # distance from the last solid node
+    exact = V1 + (V2 - V1) * zc / (nf + 1)
+    err = np.abs(phi[layers:layers + nf] - exact[:, None, None]).max()
+    assert err < 1e-13, err
+    q = o.electrode_charge()
+    q0 = T.permittivity(LB) / (nf + 1) * (V1 - V2) * nxy * nxy
+    assert abs(q[0] - q0) < 1e-10 * abs(q0) and abs(q[1] + q0) < 1e-10 * abs(q0), (q, q0)
+    return q
+
+
+def pin_naive_gauss_identity(libpath=None):
+    """Gauss's law telescopes with the plain Laplacian too: with factor 1 on
+    both ends of every solid-fluid link, sum_e Q_e + Q_ion = eps sum_fluid R
+    for any potential."""
+    shape, t, ps = W.coax(16, 16, 4, 2.5, 7.0, 0.07, -0.03)
+    rng = np.random.default_rng(8)
+    N = t.size
+    n0 = np.where(t == 0, 1e-3 * (1 + 0.3 * rng.uniform(-1, 1, (2, N))), 0.0)
+    o = _run(shape, t, ps, (1, -1), (0.05, 0.05), n_init=n0, tol=0.0, max_iter=3, flags=NAIVE,
+             libpath=libpath)
+    q = o.electrode_charge()
+    n = o.fields()["n"]
+    qion = (n[0] - n[1])[t == 0].sum()
+    R = o.residual()
+    rhs = R[t == 0].sum() / (4 * math.pi * LB)
+    assert abs(R).max() > 1e-6
+    assert abs(q.sum() + qion - rhs) < 1e-12 * (abs(q).sum() + abs(qion)), (q.sum() + qion, rhs)
+
+
+def pin_set_potential(libpath=None):
+    """New electrode potentials in a neutral slab: after the call the
+    potential is the new linear profile with phi_s at mid-link and the charge
+    recorded for the current step is the new dielectric charge (Sec. III A 2);
+    the history keeps its length."""
+    nf, nxy = 16, 2
+    shape, t, ps = W.slab(nxy, nxy, nf, 1, 0.05, -0.05)
+    # no ions: the liquid stays neutral through the steps taken first
+    o = _run(shape, t, ps, (1, -1), (0.05, 0.05), n_ref=(0.0, 0.0), tol=1e-14, omega=1.8,
+             check_every=1, libpath=libpath)
+    o.step(3)
+    len0 = o.qhist().shape[0]
+    V1, V2 = 0.2, -0.1
+    o.set_electrode_potential(np.where(t == 1, V1, np.where(t == 2, V2, 0.0)))
+    phi = o.fields()["phi"].reshape(shape[2], nxy, nxy)[1:nf + 1]
+    exact = V1 + (V2 - V1) * (np.arange(1, nf + 1) - 0.5) / nf
+    assert np.abs(phi - exact[:, None, None]).max() < 1e-13
+    qh = o.qhist()
+    q0 = T.dielectric_slab_capacitance(LB, nf) * (V1 - V2) * nxy * nxy
+    assert qh.shape[0] == len0
+    assert abs(qh[-1, 0] - q0) < 1e-10 * q0 and abs(qh[-1, 1] + q0) < 1e-10 * q0
+    assert np.allclose(qh[:-1, 0], qh[0, 0], rtol=1e-9)  # earlier entries untouched
+
+
+def pin_nonlinear_steady_state(z=(1, -1), D=(0.2, 0.2), V=0.5, debye=4.0, flags=0, steps=8000,
+                               libpath=None):
+    """Exact steady state beyond the linear regime (Sec. II C: the voltage need
+    not be small): on a 32-plane slab the LBE relaxes to the Boltzmann
+    distribution in the discrete non-linear Poisson-Boltzmann potential,
+    computed independently by Newton's method (theory.nonlinear_pb_slab);
+    the potential, the concentrations and the electrode charge agree.  Works
+    for any valences (salt of valences z with bulk concentrations in the
+    ratio that makes it neutral), unequal D and either wall scheme."""
+    nf = 32
+    zz = np.asarray(z, float)
+    # neutral salt: concentrations ~ 1/|z_k|, scaled to the requested Debye length
+    ratio = 1.0 / np.abs(zz)
+    rs = ratio / (4 * math.pi * LB * debye * debye * float((zz * zz * ratio).sum()))
+    shape, t, ps = W.slab(1, 1, nf, 1, V, -V)
+    o = _run(shape, t, ps, tuple(z), tuple(D), n_ref=tuple(rs), tol=1e-13, omega=1.8,
+             check_every=1, max_iter=100000, flags=flags, libpath=libpath)
+    o.step(steps)
+    f = o.fields()
+    phi = f["phi"][1:nf + 1]
+    n = f["n"][:, 1:nf + 1]
+    wall = 1.0 if flags & NAIVE else 2.0
+    phi_th, n_th = T.nonlinear_pb_slab(nf, z, rs * nf, LB, V, -V, wall=wall)
+    assert np.abs(phi - phi_th).max() < 1e-8 * V, np.abs(phi - phi_th).max()
+    assert np.abs(n / n_th - 1).max() < 1e-7, np.abs(n / n_th - 1).max()
+    eps = T.permittivity(LB)
+    q1 = -eps * wall * (phi_th[0] - V)  # Eq. 16 on the column, c_z = +1 links weigh 1/6
+    q = o.electrode_charge()
+    assert abs(q[0] / q1 - 1) < 1e-7 and abs(q[1] / q[0] + 1) < 1e-6, (q, q1)
+    return o

@@ -8,17 +8,17 @@ import oracle_pins as P
 # (name, original text, planted text, pins expected to notice)
 MUTATIONS = [
     ("wall factor 1 in the Laplacian",
-     "double factor = is_fluid(s, rn) ? 1.0 : 2.0;", "double factor = 1.0;",
+     "double factor = is_fluid(s, rn) ? 1.0 : wall_factor(s);", "double factor = 1.0;",
      [P.pin_neutral_slab, P.pin_uniform_charge]),
     ("wall factor 1 in the SOR update",
-     "double ws = weight(i) * (is_fluid(s, rn) ? 1.0 : 2.0);", "double ws = weight(i);",
+     "double ws = weight(i) * (is_fluid(s, rn) ? 1.0 : wall_factor(s));", "double ws = weight(i);",
      [P.pin_neutral_slab, P.pin_uniform_charge]),
     ("source term off by 2",
      "num += 4.0 * M_PI * s->p.lB / 6.0 * charge_density(s, r);",
      "num += 4.0 * M_PI * s->p.lB / 3.0 * charge_density(s, r);",
      [P.pin_uniform_charge]),
     ("electrode charge without the wall factor",
-     "lap += weight(i) * 2.0 * (s->phi[rn] - s->phi[r]);",
+     "lap += weight(i) * wall_factor(s) * (s->phi[rn] - s->phi[r]);",
      "lap += weight(i) * (s->phi[rn] - s->phi[r]);",
      [P.pin_neutral_slab, P.pin_gauss_identity]),
     ("electrode charge with the wrong sign",
@@ -60,6 +60,25 @@ MUTATIONS = [
     ("relaxation time ignored",
      "double post = fi - (fi - feq) / tau + src;", "double post = fi - (fi - feq) + src;",
      [P.pin_shear_wave]),
+    ("first-order scheme keeps the factor 2 in Gauss's law",
+     "lap += weight(i) * wall_factor(s) * (s->phi[rn] - s->phi[r]);",
+     "lap += weight(i) * 2.0 * (s->phi[rn] - s->phi[r]);",
+     [P.pin_naive_neutral_slab, P.pin_naive_gauss_identity]),
+    ("first-order flag ignored",
+     "return (s->p.flags & ORC_FLAG_NAIVE_DIRICHLET) ? 1.0 : 2.0;", "return 2.0;",
+     [P.pin_naive_neutral_slab]),
+    ("new electrode potential not applied before the solve",
+     "      s->phi_s[r] = phi_s[r];\n      s->phi[r] = phi_s[r];\n    }\n  int rc = poisson_solve(s);",
+     "      s->phi_s[r] = phi_s[r];\n    }\n  int rc = poisson_solve(s);",
+     [P.pin_set_potential]),
+    ("charge of the new potential not recorded",
+     "if (s->ne && s->qlen > 0) electrode_charges(s, s->qhist + (s->qlen - 1) * s->ne);",
+     "",
+     [P.pin_set_potential]),
+    ("excess flux linearised in delta",
+     "return -(n_there * expm1(delta) - n_here * expm1(-delta)) / (2.0 * len);",
+     "return -(n_there * delta + n_here * delta) / (2.0 * len);",
+     [P.pin_nonlinear_steady_state]),
     ("bounce-back into the same direction",
      "s->fnew[(long)opposite(i) * s->N + r] = post;", "s->fnew[(long)i * s->N + r] = post;",
      [P.pin_eo_slab, P.pin_equilibrium_moments]),

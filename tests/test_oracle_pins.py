@@ -183,3 +183,23 @@ def test_equilibrium_moments():
 
 def test_advection_shear():
     P.pin_advection_shear()
+
+
+@pytest.mark.parametrize("layers,nxy", [(1, 2), (3, 1)])
+def test_naive_neutral_slab_first_order(layers, nxy):
+    P.pin_naive_neutral_slab(layers, nxy)
+
+
+def test_naive_gauss_identity():
+    P.pin_naive_gauss_identity()
+
+
+def test_set_electrode_potential():
+    P.pin_set_potential()
+
+
+@pytest.mark.parametrize("z,D,V,flags", [((1, -1), (0.2, 0.2), 0.5, 0),
+                                         ((2, -1), (0.2, 0.35), 0.25, 0),
+                                         ((1, -1), (0.2, 0.2), 0.5, P.NAIVE)])
+def test_nonlinear_steady_state(z, D, V, flags):
+    P.pin_nonlinear_steady_state(z, D, V, flags=flags)

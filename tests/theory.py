@@ -134,3 +134,56 @@ def coax_eo_velocity(r, R1, R2, kappa, psi1, psi2, E, lB, tau, rho0=1.0):
     eta = viscosity(tau, rho0)
     r = np.asarray(r, dtype=float)
     return eps * E * (psi2 - psi1) / eta * (coax_f(r, R1, R2, kappa) - np.log(r / R1) / math.log(R2 / R1))
+
+
+def nonlinear_pb_slab(nf, z, amounts, lB, phi1, phi2, wall=2.0, tol=1e-15, max_newton=100):
+    """Steady state of the LBE between parallel plates, reduced to z.
+
+    With no flow every link flux of Eq. 10 vanishes when n'/n = exp(-z (phi' -
+    phi)), i.e. n_k = A_k exp(-z_k phi) (Boltzmann), with A_k set by the
+    conserved amount per lattice column `amounts[k]`.  For a laterally uniform
+    field the D3Q19 Laplacian of Eq. 12 / 15 reduces to a second difference
+    along z (the five links with c_z = +1 carry total weight 1/6, so
+    6 sum_i w_i s_i (phi' - phi) = s_+ (phi(z+1) - phi) + s_- (phi(z-1) - phi));
+    a link into an electrode plane has s = `wall` (2 for Eq. 15, 1 for the
+    first-order scheme with phi_s on the solid node).  phi on the nf fluid
+    planes solves the discrete non-linear Poisson-Boltzmann equation
+      L phi + 4 pi l_B sum_k z_k A_k(phi) exp(-z_k phi) = 0,
+    by Newton's method with the exact Jacobian (A_k depends on phi through the
+    normalisation).  Returns phi (nf,), n (K, nf)."""
+    z = np.asarray(z, dtype=float)
+    amounts = np.asarray(amounts, dtype=float)
+    c = 4.0 * math.pi * lB
+    # linear operator with the wall terms moved to b: L phi = M phi + b
+    M = np.zeros((nf, nf))
+    b = np.zeros(nf)
+    for i in range(nf):
+        M[i, i] = -2.0
+        if i > 0:
+            M[i, i - 1] = 1.0
+        else:
+            M[i, i] += 1.0 - wall
+            b[i] += wall * phi1
+        if i < nf - 1:
+            M[i, i + 1] = 1.0
+        else:
+            M[i, i] += 1.0 - wall
+            b[i] += wall * phi2
+    phi = phi1 + (phi2 - phi1) * (np.arange(nf) + 0.5) / nf
+    for _ in range(max_newton):
+        E = np.exp(-np.outer(z, phi))            # (K, nf)
+        S = E.sum(axis=1)
+        A = amounts / S
+        n = A[:, None] * E
+        F = M @ phi + b + c * (z[:, None] * n).sum(axis=0)
+        J = M.copy()
+        for k in range(z.size):
+            # d n_k(i) / d phi_j = -z_k n_k(i) delta_ij + n_k(i) z_k E_k(j) / S_k
+            J += c * z[k] * (np.diag(-z[k] * n[k]) + np.outer(n[k], z[k] * E[k] / S[k]))
+        step = np.linalg.solve(J, -F)
+        phi = phi + step
+        if np.abs(step).max() < tol:
+            break
+    E = np.exp(-np.outer(z, phi))
+    n = (amounts / E.sum(axis=1))[:, None] * E
+    return phi, n
