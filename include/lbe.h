@@ -50,7 +50,7 @@ enum {
 enum { LBE_FP64 = 0, LBE_FP32_MIXED = 1 };   /* precision form */
 enum { LBE_SOR4 = 0, LBE_MG = 1 };           /* Poisson solver */
 enum { LBE_MG_JACOBI = 0, LBE_MG_GS4 = 1 };  /* multigrid smoother */
-enum { LBE_ALLOW_FLOATING = 1, LBE_EXTRAPOLATE = 2 };  /* flags */
+enum { LBE_ALLOW_FLOATING = 1, LBE_EXTRAPOLATE = 2, LBE_NAIVE_DIRICHLET = 4 };  /* flags */
 enum { LBE_MAX_SPECIES = 4, LBE_MAX_ELECTRODES = 64, LBE_MAX_SITES = 100000000 };
 
 typedef struct lbe_ctx lbe_ctx;
@@ -73,7 +73,12 @@ typedef struct {
                            no electrode (their mean potential is left free);
                            LBE_EXTRAPOLATE: start each time step's Poisson
                            solve from 2 phi(t) - phi(t-1) instead of phi(t)
-                           (same tolerance, fewer iterations) */
+                           (same tolerance, fewer iterations);
+                           LBE_NAIVE_DIRICHLET: the first-order scheme the
+                           paper contrasts with (Sec. II C, Fig. 1): phi_s
+                           held on the solid nodes and the plain Laplacian of
+                           Eq. 12 (factor 1 on solid-fluid links) in Poisson
+                           and in Gauss's law, instead of Eq. 15 */
   int32_t precision;    /* LBE_FP64 | LBE_FP32_MIXED */
   int32_t poisson;      /* LBE_SOR4 | LBE_MG */
   int32_t mg_levels;    /* multigrid levels (LBE_MG): 0 = coarsen until at most
@@ -136,6 +141,18 @@ int lbe_step(lbe_ctx *ctx, int64_t nsteps);
 /* Re-solve Poisson for the current concentrations, warm-started from the
  * current potential (Sec. II C).  iters/resid may be NULL. */
 int lbe_poisson(lbe_ctx *ctx, int32_t *iters, double *resid);
+
+/*
+ * New electrode potentials, for time-dependent or non-linear voltage studies
+ * (Sec. I and IV name both): phi_s holds N values, of which the solid nodes'
+ * are taken (fluid entries ignored, host memory, copied).  Poisson is then
+ * re-solved for the current concentrations (warm start from the current
+ * potential), and the charge recorded for the current step is replaced by
+ * the one of the new potentials, so the history keeps one row per step.
+ * Errors: LBE_EINVAL for NULL or a non-finite solid value (nothing changed);
+ * LBE_ENOCONV / LBE_ENONFINITE from the solve (the new potentials are kept).
+ */
+int lbe_set_electrode_potential(lbe_ctx *ctx, const double *phi_s);
 
 /* Charge of each electrode, in units of e, from Gauss's law on the current
  * potential (Eq. 16 with the Laplacian of Eq. 15 taken on the electrode's

@@ -19,10 +19,12 @@ SOR4, MG = 0, 1
 MG_JACOBI, MG_GS4 = 0, 1
 ALLOW_FLOATING = 1
 EXTRAPOLATE = 2
+NAIVE_DIRICHLET = 4
 
 # public entry points of include/lbe.h
 ENTRY_POINTS = (
-    "lbe_init", "lbe_step", "lbe_poisson", "lbe_electrode_charge", "lbe_observables",
+    "lbe_init", "lbe_step", "lbe_poisson", "lbe_set_electrode_potential",
+    "lbe_electrode_charge", "lbe_observables",
     "lbe_destroy", "lbe_strerror", "lbe_last_error", "lbe_profile", "lbe_kernel_times",
     "lbe_kernel_name", "lbe_num_kernel_kinds", "lbe_velocities",
 )
@@ -80,6 +82,8 @@ def load(path: str = LIB_PATH):
     lib.lbe_step.restype = C.c_int
     lib.lbe_poisson.argtypes = [C.c_void_p, P(C.c_int32), d]
     lib.lbe_poisson.restype = C.c_int
+    lib.lbe_set_electrode_potential.argtypes = [C.c_void_p, d]
+    lib.lbe_set_electrode_potential.restype = C.c_int
     lib.lbe_electrode_charge.argtypes = [C.c_void_p, d, C.c_int32]
     lib.lbe_electrode_charge.restype = C.c_int
     lib.lbe_observables.argtypes = [C.c_void_p, P(Obs), d, d, d, d, d, C.c_int64, P(C.c_int64)]
@@ -203,6 +207,14 @@ class Lbe:
         res = C.c_double()
         self._check(self._lib.lbe_poisson(self.h, C.byref(it), C.byref(res)))
         return it.value, res.value
+
+    def set_electrode_potential(self, phi_s):
+        """New solid-node potentials (N values, fluid entries ignored); Poisson
+        is re-solved and the current step's recorded charge replaced."""
+        ps = np.ascontiguousarray(phi_s, dtype=np.float64)
+        if ps.size != self.N:
+            raise ValueError("phi_s must have one entry per lattice site")
+        self._check(self._lib.lbe_set_electrode_potential(self.h, _dptr(ps)))
 
     def electrode_charge(self):
         q = np.zeros(max(self.ne, 1))

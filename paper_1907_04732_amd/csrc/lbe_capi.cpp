@@ -52,6 +52,10 @@ struct lbe_ctx {
 
   // electrode charge tables
   int *iface = nullptr, *blk_elec = nullptr, *blk_begin = nullptr, *blk_end = nullptr;
+  // solid sites and their new potentials (lbe_set_electrode_potential)
+  std::vector<int> solid_h;
+  int *solid_idx = nullptr;
+  double *solid_val = nullptr;
   int nblk_charge = 0;
   double *qcur = nullptr;
   double *qhist = nullptr;
@@ -196,7 +200,7 @@ int validate(const lbe_params *p) {
       return fail(nullptr, LBE_EINVAL, "diffusion coefficients must be finite and >= 0");
   for (int a = 0; a < 3; ++a)
     if (!isfinite(p->Eapp[a])) return fail(nullptr, LBE_EINVAL, "applied field must be finite");
-  if (p->flags & ~(LBE_ALLOW_FLOATING | LBE_EXTRAPOLATE))
+  if (p->flags & ~(LBE_ALLOW_FLOATING | LBE_EXTRAPOLATE | LBE_NAIVE_DIRICHLET))
     return fail(nullptr, LBE_EINVAL, "unknown flags");
   if (p->precision != LBE_FP64 && p->precision != LBE_FP32_MIXED)
     return fail(nullptr, LBE_EINVAL, "unsupported precision form");
@@ -545,7 +549,7 @@ int build_coarse_inverse(lbe_ctx *c, const std::vector<uint8_t> &solid) {
       if ((lv.selfm >> (i - 1)) & 1u) continue;
       const int rn = wrap(x + CX[i], lv.nx) + lv.nx * (wrap(y + CY[i], lv.ny) + lv.ny * wrap(z + CZ[i], lv.nz));
       if (solid[rn]) {
-        A[(size_t)j * nf + j] += sc * 2.0 * WQ[i];
+        A[(size_t)j * nf + j] += sc * lv.wall * WQ[i];
       } else {
         A[(size_t)j * nf + j] += sc * WQ[i];
         A[(size_t)j * nf + fidx[rn]] -= sc * WQ[i];
@@ -671,7 +675,7 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
   std::vector<uint8_t> solid((size_t)nx * ny * nz);
   for (size_t r = 0; r < solid.size(); ++r) solid[r] = type[r] != 0;
   lbe_ctx::MgDev l0;
-  l0.lv = MgLevel{nx, ny, nz, nx * ny, nx * ny * nz, c->L.selfm, 1.0, 1.0};
+  l0.lv = MgLevel{nx, ny, nz, nx * ny, nx * ny * nz, c->L.selfm, 1.0, 1.0, c->L.wall};
   l0.mask = c->mask;
   HIPCHK(c, hipMalloc(&l0.e, esz * l0.lv.n));
   HIPCHK(c, hipMalloc(&l0.e2, esz * l0.lv.n));
@@ -688,7 +692,8 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
     if (!colouring_ok(cx, cy, cz, cs)) break;
     h2 *= 4.0;
     lbe_ctx::MgDev L;
-    L.lv = MgLevel{cx, cy, cz, cx * cy, cx * cy * cz, level_selfm(cx, cy, cz), h2, 1.0 / h2};
+    L.lv = MgLevel{cx, cy, cz, cx * cy, cx * cy * cz, level_selfm(cx, cy, cz), h2, 1.0 / h2,
+                   c->L.wall};
     L.tr = MgTransfer{c->mg.back().lv, L.lv, ox, oy, oz};
     const std::vector<uint32_t> m = level_mask(cx, cy, cz, cs);
     HIPCHK(c, hipMalloc((void **)&L.mask, sizeof(uint32_t) * m.size()));
@@ -927,7 +932,7 @@ void free_ctx(lbe_ctx *c) {
   void *ptrs[] = {c->mask, c->phi, c->phi_prev, c->src, c->u, c->n[0], c->n[1], c->f[0], c->f[1],
                   c->h32[0], c->h32[1], c->nu32[0], c->nu32[1], c->u32, c->obs,
                   c->partial, c->dout, c->ctl, c->iface, c->blk_elec, c->blk_begin,
-                  c->blk_end, c->qcur, c->qhist};
+                  c->blk_end, c->qcur, c->qhist, c->solid_idx, c->solid_val};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   for (auto &L : c->mg) {
@@ -1056,6 +1061,7 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
   c->L.nxy = p.nx * p.ny;
   c->L.n = (int)N;
   c->L.selfm = g.selfm;
+  c->L.wall = (p.flags & LBE_NAIVE_DIRICHLET) ? 1.0 : 2.0;
   c->P.K = K;
   for (int k = 0; k < K; ++k) {
     c->P.z[k] = p.z[k];
@@ -1251,6 +1257,37 @@ int lbe_poisson(lbe_ctx *c, int32_t *iters, double *resid) {
   if (iters) *iters = c->last_iters;
   if (resid) *resid = c->last_resid;
   return rc;
+}
+
+int lbe_set_electrode_potential(lbe_ctx *c, const double *phi_s) {
+  if (!c || !phi_s) return fail(c, LBE_EINVAL, "bad arguments");
+  if (!c->solid_idx) {
+    for (size_t r = 0; r < c->type_h.size(); ++r)
+      if (c->type_h[r]) c->solid_h.push_back((int)r);
+    if (c->solid_h.empty()) return LBE_OK;  // no electrode: nothing to set
+    HIPCHK(c, hipMalloc((void **)&c->solid_idx, sizeof(int) * c->solid_h.size()));
+    HIPCHK(c, hipMalloc((void **)&c->solid_val, sizeof(double) * c->solid_h.size()));
+    HIPCHK(c, hipMemcpy(c->solid_idx, c->solid_h.data(), sizeof(int) * c->solid_h.size(),
+                        hipMemcpyHostToDevice));
+  }
+  const size_t S = c->solid_h.size();
+  std::vector<double> val(S);
+  for (size_t j = 0; j < S; ++j) {
+    val[j] = phi_s[c->solid_h[j]];
+    if (!std::isfinite(val[j])) return fail(c, LBE_EINVAL, "non-finite electrode potential");
+  }
+  HIPCHK(c, hipMemcpyAsync(c->solid_val, val.data(), sizeof(double) * S, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, launch_scatter(c->stream, (int)S, c->solid_idx, c->solid_val, c->phi));
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // val leaves scope
+  int rc = poisson_solve(c, false);
+  if (rc) return rc;
+  if (c->ne && c->qlen > 0) {
+    rc = charges_to(c, c->qhist + (c->qlen - 1) * c->ne);
+    if (rc) return rc;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBE_OK;
 }
 
 int lbe_electrode_charge(lbe_ctx *c, double *q, int32_t ne) {

@@ -33,6 +33,7 @@ struct Lattice {
   int nxy;
   int n;            // sites
   uint32_t selfm;   // bit (i-1) set when link i maps a node onto itself
+  double wall;      // factor on a solid-fluid link: 2 (Eq. 15) or 1 (first-order scheme)
 };
 
 // Physical constants of one context, passed by value to the kernels.
@@ -57,6 +58,7 @@ struct MgLevel {
   int nx, ny, nz, nxy, n;
   uint32_t selfm;
   double h2, inv_h2;
+  double wall;      // as Lattice::wall
 };
 
 // Fine level f -> coarse level c: coarse cell (X, Y, Z) holds the fine cells
@@ -134,6 +136,9 @@ hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, cons
 // Step pass B: advective outflow with u; nio holds n* on entry, n(t+1) on exit.
 hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                            const double *u, const double *n, double *nio, double *src);
+// dst[idx[t]] = val[t] for t < count (new solid-node potentials)
+hipError_t launch_scatter(hipStream_t s, int count, const int *idx, const double *val,
+                          double *dst);
 hipError_t launch_sor_f64(hipStream_t s, const Lattice &L, const Phys &P, int colour,
                           const uint32_t *mask, const double *src, double *phi,
                           const SolveCtl *ctl);

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(BLOCK) void k_sor_f64(Lattice L, double omega, int 
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((L.selfm >> (i - 1)) & 1u) continue;
-    const double ws = solid_link(m, i) ? 2.0 * WQ[i] : WQ[i];
+    const double ws = solid_link(m, i) ? L.wall * WQ[i] : WQ[i];
     num += ws * pn[i];
     den += ws;
   }
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(BLOCK) void k_resid_f64(Lattice L, const uint32_t *
 #pragma unroll
       for (int i = 1; i < NQ; ++i) {
         if ((L.selfm >> (i - 1)) & 1u) continue;
-        const double ws = solid_link(m, i) ? 2.0 * WQ[i] : WQ[i];
+        const double ws = solid_link(m, i) ? L.wall * WQ[i] : WQ[i];
         acc += ws * (pn[i] - pn[0]);
       }
       a = fabs(6.0 * (acc + sr));
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(BLOCK) void k_charge(Lattice L, double q_scale,
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
       if (solid_link(m, i)) continue;
-      lap += WQ[i] * 2.0 * (pn[i] - pn[0]);
+      lap += WQ[i] * L.wall * (pn[i] - pn[0]);
     }
     v = q_scale * lap;
   }
@@ -392,6 +392,14 @@ __global__ __launch_bounds__(BLOCK) void k_observe_f64(Lattice L, Phys P,
   u[2 * N + r] = (m2 + 0.5 * F2) / rho;
 }
 
+// dst[idx[t]] = val[t]: new potentials of the solid nodes
+__global__ __launch_bounds__(BLOCK) void k_scatter(int count, const int *__restrict__ idx,
+                                                   const double *__restrict__ val,
+                                                   double *__restrict__ dst) {
+  const int t = blockIdx.x * BLOCK + threadIdx.x;
+  if (t < count) dst[idx[t]] = val[t];
+}
+
 // warm start of the next Poisson solve by linear extrapolation in time
 __global__ __launch_bounds__(BLOCK) void k_extrapolate(int n, const uint32_t *__restrict__ mask,
                                                        double *__restrict__ phi,
@@ -441,6 +449,13 @@ hipError_t launch_sor_f64(hipStream_t s, const Lattice &L, const Phys &P, int co
   const long threads = (long)hx * hy * L.nz;
   hipLaunchKernelGGL(k_sor_f64, dim3(blocks_for(threads)), dim3(BLOCK), 0, s, L, P.omega, colour,
                      hx, hy, mask, src, phi, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(hipStream_t s, int count, const int *idx, const double *val,
+                          double *dst) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(count)), dim3(BLOCK), 0, s, count, idx, val, dst);
   return hipGetLastError();
 }
 

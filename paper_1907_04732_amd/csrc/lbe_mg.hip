@@ -68,7 +68,7 @@ __device__ __forceinline__ T apply_A(const MgLevel &lv, int r, uint32_t m, const
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((lv.selfm >> (i - 1)) & 1u) continue;
-    const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
+    const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
     acc += ws * (v[0] - v[i]);
   }
   return T(6.0) * T(lv.inv_h2) * acc;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
 #pragma unroll
       for (int i = 1; i < NQ; ++i) {
         if ((lv.selfm >> (i - 1)) & 1u) continue;
-        const double ws = solid_link(m, i) ? 2.0 * WQ[i] : WQ[i];
+        const double ws = solid_link(m, i) ? lv.wall * WQ[i] : WQ[i];
         acc += ws * (pn[i] - pn[0]);
       }
       R = 6.0 * (acc + sr);
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(BLOCK) void k_smooth(MgLevel lv, T omega, int colou
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((lv.selfm >> (i - 1)) & 1u) continue;
-    const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
+    const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
     num += ws * v[i];
     den += ws;
   }
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((lv.selfm >> (i - 1)) & 1u) continue;
-    const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
+    const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
     num += ws * v[i];
     den += ws;
   }
@@ -285,14 +285,16 @@ __device__ __forceinline__ T prolong_value(const MgTransfer &tr, int r,
     ev[k] = ec[R];
   }
   if (mk[0] & SOLID_BIT) return T(0);
-  const T ep = ev[0];
+  // value beyond a wall: mirrored (-e) when the wall lies on the cell face
+  // (factor 2), zero when it lies on the solid cell (first-order scheme)
+  const T ep = tr.c.wall > 1.5 ? -ev[0] : T(0);
   T v = T(0);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const T w = ((k & 1) ? T(1) - wgt[0] : wgt[0]) * ((k & 2) ? T(1) - wgt[1] : wgt[1]) *
                 ((k & 4) ? T(1) - wgt[2] : wgt[2]);
     if (w == T(0)) continue;
-    const T val = (mk[k] & SOLID_BIT) ? -ep : ev[k];
+    const T val = (mk[k] & SOLID_BIT) ? ep : ev[k];
     v += w * val;
   }
   return v;
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, in
 #pragma unroll
         for (int i = 1; i < NQ; ++i) {
           if ((lv.selfm >> (i - 1)) & 1u) continue;
-          const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
+          const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
           num += ws * e[nbr_of(lv, c, i)];
           den += ws;
         }
@@ -412,7 +414,7 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
 #pragma unroll
           for (int i = 1; i < NQ; ++i) {
             if ((lv.selfm >> (i - 1)) & 1u) continue;
-            const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
+            const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
             num += ws * v[i];
             den += ws;
           }
@@ -444,7 +446,7 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
 #pragma unroll
         for (int i = 1; i < NQ; ++i) {
           if ((lv.selfm >> (i - 1)) & 1u) continue;
-          const T ws = solid_link(m, i) ? T(2.0 * WQ[i]) : T(WQ[i]);
+          const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
           num += ws * v[i];
           den += ws;
         }
