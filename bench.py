@@ -121,10 +121,19 @@ def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, che
     # multigrid forms start each solve from 2 phi(t) - phi(t-1); the SOR form
     # keeps the paper's warm start from phi(t)
     flags = lbe.EXTRAPOLATE if solver == "mg" else 0
-    p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, rho0=w.rho0, Eapp=w.Eapp,
-                        omega=w.omega, tol=w.tol, max_iter=1_000_000, check_every=check_every,
-                        precision=precision, poisson=poisson, flags=flags)
-    g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref)
+    p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, rho0=getattr(w, "rho0", 1.0),
+                        Eapp=getattr(w, "Eapp", (0.0, 0.0, 0.0)), omega=getattr(w, "omega", 1.8),
+                        tol=getattr(w, "tol", 1e-10), max_iter=1_000_000,
+                        check_every=check_every, precision=precision, poisson=poisson,
+                        flags=flags)
+    t_init = time.perf_counter()
+    if isinstance(w, W.Batch):
+        g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref.reshape(-1), system=w.system,
+                    nsys=len(w.L))
+    else:
+        g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref)
+    print(f"bench: {form}/{solver}: context ready in {time.perf_counter() - t_init:.2f} s",
+          file=sys.stderr, flush=True)
     N = w.node_type.size
     nfluid = int((w.node_type == 0).sum())
     ffrac = nfluid / N
@@ -220,9 +229,12 @@ FORMS = {"fp32-mg": ("fp32", "mg"), "fp64-mg": ("fp64", "mg"), "fp64-sor": ("fp6
 
 # Larger lattices whose working sets exceed the 256 MB last-level cache, so
 # that the fluid and ion kernels stream from HBM: the coaxial capacitor
-# (1.64 M sites) and the porous electrode (7.08 M sites).
+# (1.64 M sites) and the porous electrode (7.08 M sites); and the parameter
+# sweep of 96 independent 8x8xL plate systems (L 16..256, Debye length 2..16,
+# voltage 0.01..0.2) packed in one lattice (0.94 M sites).
 SHAPES = {"coaxial_160x160x64": lambda: W.coaxial(noise=True),
-          "porous_electrode_192^3": lambda: W.porous_electrode(noise=True)}
+          "porous_electrode_192^3": lambda: W.porous_electrode(noise=True),
+          "batched_96_slabs": lambda: W.batch_slabs(noise=True)}
 
 
 def run_shapes(names, forms, steps, warmup, check_every):

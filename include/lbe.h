@@ -51,7 +51,8 @@ enum { LBE_FP64 = 0, LBE_FP32_MIXED = 1 };   /* precision form */
 enum { LBE_SOR4 = 0, LBE_MG = 1 };           /* Poisson solver */
 enum { LBE_MG_JACOBI = 0, LBE_MG_GS4 = 1 };  /* multigrid smoother */
 enum { LBE_ALLOW_FLOATING = 1, LBE_EXTRAPOLATE = 2, LBE_NAIVE_DIRICHLET = 4 };  /* flags */
-enum { LBE_MAX_SPECIES = 4, LBE_MAX_ELECTRODES = 64, LBE_MAX_SITES = 100000000 };
+enum { LBE_MAX_SPECIES = 4, LBE_MAX_ELECTRODES = 255, LBE_MAX_SITES = 100000000,
+       LBE_MAX_SYSTEMS = 8192 };
 
 typedef struct lbe_ctx lbe_ctx;
 
@@ -124,6 +125,28 @@ typedef struct {
  */
 int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
              const double *n_init, const double *n_ref, const double *f_init, lbe_ctx **out);
+
+/*
+ * Many independent systems in one context (the parameter sweeps of Sec. III:
+ * plates of several widths, Debye lengths and voltages).  The systems share
+ * one lattice, each enclosed by its own electrodes, and every kernel launch
+ * advances all of them.  system[r] (N values, host) is the index
+ * 0..nsys-1 of the system a fluid node belongs to (solid entries ignored);
+ * no fluid-fluid link may join two systems.  n_ref holds nsys*nspecies
+ * values, system-major: the default initial concentrations of each system
+ * and, in LBE_FP32_MIXED, the reference of its deviation storage (so each
+ * system keeps FP32's relative precision whatever its salt concentration);
+ * NULL = each system's fluid mean of n_init.  Populations start at rest.
+ * Electrode charges, the Poisson tolerance and all outputs are those of
+ * lbe_init for the whole lattice (one electrode id per electrode, up to
+ * LBE_MAX_ELECTRODES in total).
+ * Errors: as lbe_init, plus LBE_EINVAL for NULL system, nsys outside
+ * 1..LBE_MAX_SYSTEMS or an index >= nsys, and LBE_EGEOM when a fluid link
+ * joins two systems.
+ */
+int lbe_init_batch(const lbe_params *params, const uint8_t *type, const double *phi_s,
+                   const double *n_init, const double *n_ref, const uint16_t *system,
+                   int32_t nsys, lbe_ctx **out);
 
 /*
  * Advance nsteps time steps (Sec. II B-C).  Each step: link fluxes (Eq. 10)

@@ -23,7 +23,7 @@ NAIVE_DIRICHLET = 4
 
 # public entry points of include/lbe.h
 ENTRY_POINTS = (
-    "lbe_init", "lbe_step", "lbe_poisson", "lbe_set_electrode_potential",
+    "lbe_init", "lbe_init_batch", "lbe_step", "lbe_poisson", "lbe_set_electrode_potential",
     "lbe_electrode_charge", "lbe_observables",
     "lbe_destroy", "lbe_strerror", "lbe_last_error", "lbe_profile", "lbe_kernel_times",
     "lbe_kernel_name", "lbe_num_kernel_kinds", "lbe_velocities",
@@ -78,6 +78,9 @@ def load(path: str = LIB_PATH):
     d = P(C.c_double)
     lib.lbe_init.argtypes = [P(Params), P(C.c_uint8), d, d, d, d, P(C.c_void_p)]
     lib.lbe_init.restype = C.c_int
+    lib.lbe_init_batch.argtypes = [P(Params), P(C.c_uint8), d, d, d, P(C.c_uint16), C.c_int32,
+                                   P(C.c_void_p)]
+    lib.lbe_init_batch.restype = C.c_int
     lib.lbe_step.argtypes = [C.c_void_p, C.c_int64]
     lib.lbe_step.restype = C.c_int
     lib.lbe_poisson.argtypes = [C.c_void_p, P(C.c_int32), d]
@@ -151,7 +154,10 @@ def kernel_names():
 class Lbe:
     """One LBE context on the current HIP device (see include/lbe.h)."""
 
-    def __init__(self, params: Params, node_type, phi_s, n_init=None, n_ref=None, f_init=None):
+    def __init__(self, params: Params, node_type, phi_s, n_init=None, n_ref=None, f_init=None,
+                 system=None, nsys=None):
+        """system (N ints) and nsys select lbe_init_batch: independent systems
+        in one lattice, n_ref then holding nsys x nspecies values."""
         lib = load()
         self._lib = lib
         self.p = params
@@ -166,13 +172,24 @@ class Lbe:
         fi = None if f_init is None else np.ascontiguousarray(f_init, dtype=np.float64).reshape(-1)
         if ni is not None and ni.size != self.K * self.N:
             raise ValueError("n_init needs nspecies*N entries")
-        if nr is not None and nr.size < self.K:
-            raise ValueError("n_ref needs nspecies entries")
+        nsys = 1 if system is None else int(nsys if nsys is not None else np.max(system) + 1)
+        if nr is not None and nr.size < self.K * nsys:
+            raise ValueError("n_ref needs nspecies (x nsys) entries")
         if fi is not None and fi.size != 19 * self.N:
             raise ValueError("f_init needs 19*N entries")
         h = C.c_void_p()
-        rc = lib.lbe_init(C.byref(params), t.ctypes.data_as(C.POINTER(C.c_uint8)), _dptr(ps),
-                          _dptr(ni), _dptr(nr), _dptr(fi), C.byref(h))
+        if system is None:
+            rc = lib.lbe_init(C.byref(params), t.ctypes.data_as(C.POINTER(C.c_uint8)), _dptr(ps),
+                              _dptr(ni), _dptr(nr), _dptr(fi), C.byref(h))
+        else:
+            if fi is not None:
+                raise ValueError("batched systems start from rest populations")
+            sy = np.ascontiguousarray(system, dtype=np.uint16).reshape(-1)
+            if sy.size != self.N:
+                raise ValueError("system needs N entries")
+            rc = lib.lbe_init_batch(C.byref(params), t.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                    _dptr(ps), _dptr(ni), _dptr(nr),
+                                    sy.ctypes.data_as(C.POINTER(C.c_uint16)), nsys, C.byref(h))
         if rc:
             raise LbeError(rc, lib.lbe_last_error(None).decode())
         self.h = h

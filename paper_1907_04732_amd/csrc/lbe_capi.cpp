@@ -52,6 +52,12 @@ struct lbe_ctx {
 
   // electrode charge tables
   int *iface = nullptr, *blk_elec = nullptr, *blk_begin = nullptr, *blk_end = nullptr;
+  // per-system references of the mixed form (device tables) and each node's system
+  std::vector<uint16_t> sys_h;
+  double *nref_d_tab = nullptr, *qref_tab = nullptr;
+  float *nref_f_tab = nullptr;
+  std::vector<double> nref_h;  // host copy, [4 s + k]
+  std::vector<double> qref_h;  // host copy, [s]
   // solid sites and their new potentials (lbe_set_electrode_potential)
   std::vector<int> solid_h;
   int *solid_idx = nullptr;
@@ -223,7 +229,8 @@ struct HostGeometry {
 
 inline int wrap(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-int build_geometry(const lbe_params *p, const uint8_t *type, int ne, HostGeometry &g) {
+int build_geometry(const lbe_params *p, const uint8_t *type, const uint16_t *sys, int ne,
+                   HostGeometry &g) {
   const int nx = p->nx, ny = p->ny, nz = p->nz;
   const long N = (long)nx * ny * nz;
   for (int i = 1; i < NQ; ++i) {
@@ -236,11 +243,14 @@ int build_geometry(const lbe_params *p, const uint8_t *type, int ne, HostGeometr
     for (int y = 0; y < ny; ++y)
       for (int x = 0; x < nx; ++x) {
         const long r = x + (long)nx * (y + (long)ny * z);
-        uint32_t m = type[r] ? SOLID_BIT : 0u;
+        uint32_t m = type[r] ? SOLID_BIT : (uint32_t)sys[r] << SYS_SHIFT;
         for (int i = 0; i < NQ; ++i) {
           const long rn = wrap(x + CX[i], nx) + (long)nx * (wrap(y + CY[i], ny) + (long)ny * wrap(z + CZ[i], nz));
           nb[(size_t)i * N + r] = (int)rn;
           if (i && type[rn]) m |= 1u << (i - 1);
+          // independent systems: no fluid link may join two of them
+          if (i && !type[r] && !type[rn] && sys[rn] != sys[r])
+            return fail(nullptr, LBE_EGEOM, "a fluid link joins two systems");
         }
         g.mask[r] = m;
       }
@@ -290,12 +300,12 @@ int build_geometry(const lbe_params *p, const uint8_t *type, int ne, HostGeometr
   }
   // interface solid nodes per electrode and the charge kernel's block table
   constexpr int B = 256;
+  std::vector<std::vector<int>> by_elec(ne + 1);
+  for (long r = 0; r < N; ++r)
+    if (type[r] && (g.mask[r] & ~SOLID_BIT) != ((1u << 18) - 1u)) by_elec[type[r]].push_back((int)r);
   for (int e = 1; e <= ne; ++e) {
     const int begin = (int)g.iface.size();
-    for (long r = 0; r < N; ++r) {
-      if (type[r] != e) continue;
-      if ((g.mask[r] & ~SOLID_BIT) != ((1u << 18) - 1u)) g.iface.push_back((int)r);
-    }
+    g.iface.insert(g.iface.end(), by_elec[e].begin(), by_elec[e].end());
     const int end = (int)g.iface.size();
     for (int b = begin; b < end; b += B) {
       g.blk_elec.push_back(e - 1);
@@ -490,9 +500,13 @@ uint32_t level_selfm(int nx, int ny, int nz) {
 
 // Coarsen one level: cells pair up along every axis longer than 1 (one half
 // block at the end of an odd axis); offsets minimise blocks that mix solid
-// and fluid; a block is solid when at least half of its children are.
-void coarsen(int nx, int ny, int nz, const std::vector<uint8_t> &solid, int &cx, int &cy,
-             int &cz, int &ox, int &oy, int &oz, std::vector<uint8_t> &csolid) {
+// and fluid; a block is solid when at least half of its children are, or
+// when its fluid children belong to different independent systems (so that
+// batched systems stay decoupled on every level).  sys / csys: system of
+// each fluid cell of the fine / coarse level.
+void coarsen(int nx, int ny, int nz, const std::vector<uint8_t> &solid,
+             const std::vector<uint16_t> &sys, int &cx, int &cy, int &cz, int &ox, int &oy,
+             int &oz, std::vector<uint8_t> &csolid, std::vector<uint16_t> &csys) {
   cx = nx > 1 ? (nx + 1) / 2 : 1;
   cy = ny > 1 ? (ny + 1) / 2 : 1;
   cz = nz > 1 ? (nz + 1) / 2 : 1;
@@ -520,6 +534,22 @@ void coarsen(int nx, int ny, int nz, const std::vector<uint8_t> &solid, int &cx,
           oz = tz;
           csolid.assign(nc, 0);
           for (long R = 0; R < nc; ++R) csolid[R] = 2 * ns[R] >= ns[R] + nf[R];
+        }
+      }
+  // systems of the coarse cells, with the chosen offsets
+  csys.assign(nc, 0);
+  std::vector<uint8_t> seen(nc, 0);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const long r = x + (long)nx * (y + (long)ny * z);
+        if (solid[r]) continue;
+        const long R = (wrap(x - ox, nx) / 2) + (long)cx * ((wrap(y - oy, ny) / 2) + (long)cy * (wrap(z - oz, nz) / 2));
+        if (!seen[R]) {
+          seen[R] = 1;
+          csys[R] = sys[r];
+        } else if (csys[R] != sys[r]) {
+          csolid[R] = 1;
         }
       }
 }
@@ -674,6 +704,7 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
   int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
   std::vector<uint8_t> solid((size_t)nx * ny * nz);
   for (size_t r = 0; r < solid.size(); ++r) solid[r] = type[r] != 0;
+  std::vector<uint16_t> sys = c->sys_h;
   lbe_ctx::MgDev l0;
   l0.lv = MgLevel{nx, ny, nz, nx * ny, nx * ny * nz, c->L.selfm, 1.0, 1.0, c->L.wall};
   l0.mask = c->mask;
@@ -687,9 +718,12 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
     if (nx <= 2 && ny <= 2 && nz <= 2) break;
     int cx, cy, cz, ox = 0, oy = 0, oz = 0;
     std::vector<uint8_t> cs;
-    coarsen(nx, ny, nz, solid, cx, cy, cz, ox, oy, oz, cs);
+    std::vector<uint16_t> csy;
+    coarsen(nx, ny, nz, solid, sys, cx, cy, cz, ox, oy, oz, cs, csy);
     if (std::find(cs.begin(), cs.end(), 0) == cs.end()) break;  // no fluid left
-    if (!colouring_ok(cx, cy, cz, cs)) break;
+    // the four-colour smoother needs a proper colouring on every level;
+    // Jacobi smoothing (and the dense coarsest solve) does not
+    if (c->mg_jacobi == 0.0 && !colouring_ok(cx, cy, cz, cs)) break;
     h2 *= 4.0;
     lbe_ctx::MgDev L;
     L.lv = MgLevel{cx, cy, cz, cx * cy, cx * cy * cz, level_selfm(cx, cy, cz), h2, 1.0 / h2,
@@ -709,6 +743,7 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
     ny = cy;
     nz = cz;
     solid.swap(cs);
+    sys.swap(csy);
   }
   const MgLevel &top = c->mg.back().lv;
   c->mg_coarse_sweeps = 2 * std::max({top.nx, top.ny, top.nz}) + 10;
@@ -741,8 +776,8 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
                                          r, A, c->ctl);
       });
     return run(c, KK_MG_COARSE, L.lv.n, [&] {
-      return launch_mg_coarse<T>(c->stream, L.lv, c->p.omega, c->mg_coarse_sweeps, L.mask, r, A,
-                                 c->ctl);
+      return launch_mg_coarse<T>(c->stream, L.lv, c->p.omega, c->mg_jacobi, c->mg_coarse_sweeps,
+                                 L.mask, r, A, (T *)L.e2, c->ctl);
     });
   }
   const KernelKind sk = l == 0 ? KK_MG_SMOOTH0 : KK_MG_SMOOTH;
@@ -932,7 +967,8 @@ void free_ctx(lbe_ctx *c) {
   void *ptrs[] = {c->mask, c->phi, c->phi_prev, c->src, c->u, c->n[0], c->n[1], c->f[0], c->f[1],
                   c->h32[0], c->h32[1], c->nu32[0], c->nu32[1], c->u32, c->obs,
                   c->partial, c->dout, c->ctl, c->iface, c->blk_elec, c->blk_begin,
-                  c->blk_end, c->qcur, c->qhist, c->solid_idx, c->solid_val};
+                  c->blk_end, c->qcur, c->qhist, c->solid_idx, c->solid_val,
+                  c->nref_d_tab, c->qref_tab, c->nref_f_tab};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   for (auto &L : c->mg) {
@@ -993,8 +1029,14 @@ const char *lbe_kernel_name(int32_t kind) {
   return (kind >= 0 && kind < KK_COUNT) ? kKernelNames[kind] : "";
 }
 
-int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
-             const double *n_init, const double *n_ref, const double *f_init, lbe_ctx **out) {
+}  // extern "C"
+
+namespace {
+
+// lbe_init and lbe_init_batch: system == nullptr means one system (nsys = 1).
+int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s,
+              const double *n_init, const double *n_ref, const double *f_init,
+              const uint16_t *system, int nsys, lbe_ctx **out) {
   g_init_error.clear();
   if (!out) return fail(nullptr, LBE_EINVAL, "out is NULL");
   *out = nullptr;
@@ -1006,7 +1048,15 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
   const int K = p.nspecies;
   int ne = 0;
   for (long r = 0; r < N; ++r) ne = std::max(ne, (int)type[r]);
-  if (ne > LBE_MAX_ELECTRODES) return fail(nullptr, LBE_EINVAL, "more than 64 electrodes");
+  if (ne > LBE_MAX_ELECTRODES) return fail(nullptr, LBE_EINVAL, "too many electrodes");
+  if (nsys < 1 || nsys > LBE_MAX_SYSTEMS) return fail(nullptr, LBE_EINVAL, "bad system count");
+  std::vector<uint16_t> sys_h(N, 0);
+  if (system)
+    for (long r = 0; r < N; ++r) {
+      if (type[r]) continue;
+      if (system[r] >= nsys) return fail(nullptr, LBE_EINVAL, "system index out of range");
+      sys_h[r] = system[r];
+    }
   for (long r = 0; r < N; ++r)
     if (type[r] && !isfinite(phi_s[r]))
       return fail(nullptr, LBE_EINVAL, "non-finite electrode potential");
@@ -1015,7 +1065,7 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
   for (int k = 0; k < K; ++k)
     for (long r = 0; r < N; ++r) {
       if (type[r]) continue;
-      const double v = n_init ? n_init[(size_t)k * N + r] : n_ref[k];
+      const double v = n_init ? n_init[(size_t)k * N + r] : n_ref[(size_t)sys_h[r] * K + k];
       if (!isfinite(v)) return fail(nullptr, LBE_EINVAL, "non-finite initial concentration");
       n0[(size_t)k * N + r] = v;
     }
@@ -1037,7 +1087,7 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
     }
   }
   HostGeometry g;
-  rc = build_geometry(&p, type, ne, g);
+  rc = build_geometry(&p, type, sys_h.data(), ne, g);
   if (rc) return rc;
 
   int ndev = 0;
@@ -1079,29 +1129,29 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
     c->mg_jacobi = p.mg_smoother == LBE_MG_JACOBI ? 1.0 : 0.0;
   }
   c->type_h.assign(type, type + N);
-  // references of the mixed form: n_ref, else the fluid mean of n_init
+  c->sys_h = sys_h;
+  // references of the mixed form per system: n_ref, else the system's fluid
+  // mean of n_init
   {
-    long nfl = 0;
-    for (long r = 0; r < N; ++r) nfl += type[r] == 0;
-    double qref = 0.0;
-    for (int k = 0; k < K; ++k) {
-      double ref = 0.0;
-      if (n_ref) {
-        ref = n_ref[k];
-      } else if (nfl) {
-        for (long r = 0; r < N; ++r) ref += n0[(size_t)k * N + r];
-        ref /= (double)nfl;
-      }
-      if (!isfinite(ref)) {
-        free_ctx(c);
-        return fail(nullptr, LBE_EINVAL, "non-finite reference concentration");
-      }
-      c->P.nref_d[k] = ref;
-      c->P.nref_f[k] = (float)ref;
-      c->P.dk_f[k] = (float)c->P.dk[k];
-      qref += p.z[k] * ref;
+    std::vector<double> sum((size_t)nsys * 4, 0.0);
+    std::vector<long> cnt(nsys, 0);
+    for (long r = 0; r < N; ++r) {
+      if (type[r]) continue;
+      cnt[sys_h[r]]++;
+      for (int k = 0; k < K; ++k) sum[(size_t)sys_h[r] * 4 + k] += n0[(size_t)k * N + r];
     }
-    c->P.qref = qref;
+    c->nref_h.assign((size_t)nsys * 4, 0.0);
+    for (int sy = 0; sy < nsys; ++sy)
+      for (int k = 0; k < K; ++k) {
+        double ref = n_ref ? n_ref[(size_t)sy * K + k]
+                           : (cnt[sy] ? sum[(size_t)sy * 4 + k] / (double)cnt[sy] : 0.0);
+        if (!isfinite(ref)) {
+          free_ctx(c);
+          return fail(nullptr, LBE_EINVAL, "non-finite reference concentration");
+        }
+        c->nref_h[(size_t)sy * 4 + k] = ref;
+      }
+    for (int k = 0; k < K; ++k) c->P.dk_f[k] = (float)c->P.dk[k];
     c->P.rho0_d = p.rho0;
     c->P.rho0_f = (float)p.rho0;
     c->P.itau_f = (float)(1.0 / p.tau);
@@ -1128,6 +1178,28 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
     TRY(dalloc(c, &c->mask, N));
     TRY(dalloc(c, &c->phi, N));
     TRY(dalloc(c, &c->src, N));
+    {
+      std::vector<float> rf(c->nref_h.begin(), c->nref_h.end());
+      std::vector<double> qr(nsys, 0.0);
+      for (int sy = 0; sy < nsys; ++sy)
+        for (int k = 0; k < K; ++k) qr[sy] += p.z[k] * c->nref_h[(size_t)sy * 4 + k];
+      TRY(dalloc(c, &c->nref_d_tab, c->nref_h.size()));
+      TRY(dalloc(c, &c->nref_f_tab, rf.size()));
+      TRY(dalloc(c, &c->qref_tab, qr.size()));
+      if (hipMemcpy(c->nref_d_tab, c->nref_h.data(), sizeof(double) * c->nref_h.size(),
+                    hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(c->nref_f_tab, rf.data(), sizeof(float) * rf.size(), hipMemcpyHostToDevice) !=
+              hipSuccess ||
+          hipMemcpy(c->qref_tab, qr.data(), sizeof(double) * qr.size(), hipMemcpyHostToDevice) !=
+              hipSuccess) {
+        rc = fail(c, LBE_EDEVICE, "copy of the reference tables failed");
+        goto fail_;
+      }
+      c->P.nref_d = c->nref_d_tab;
+      c->P.nref_f = c->nref_f_tab;
+      c->P.qref = c->qref_tab;
+      c->qref_h = qr;
+    }
     if (c->mixed) {
       TRY(dalloc(c, &c->u32, 3 * N));
       TRY(dalloc(c, &c->obs, (size_t)(NQ + 3) * N));
@@ -1167,7 +1239,9 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
       h0.assign((size_t)NQ * N, 0.f);
       for (int k = 0; k < K; ++k)
         for (long r = 0; r < N; ++r)
-          if (!type[r]) nu0[(size_t)k * N + r] = (float)(n0[(size_t)k * N + r] - c->P.nref_d[k]);
+          if (!type[r])
+            nu0[(size_t)k * N + r] =
+                (float)(n0[(size_t)k * N + r] - c->nref_h[(size_t)sys_h[r] * 4 + k]);
       for (int i = 0; i < NQ; ++i)
         for (long r = 0; r < N; ++r)
           if (!type[r]) h0[(size_t)i * N + r] = (float)(fs[(size_t)i * N + r] - WQ[i] * p.rho0);
@@ -1179,7 +1253,7 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
       }
       double q = 0.0;
       if (c->mixed) {
-        q = c->P.qref;
+        q = c->qref_h[sys_h[r]];
         for (int k = 0; k < K; ++k) q += p.z[k] * (double)nu0[(size_t)k * N + r];
       } else {
         for (int k = 0; k < K; ++k) q += p.z[k] * n0[(size_t)k * N + r];
@@ -1240,6 +1314,26 @@ fail_:
   g_init_error = c->err;
   free_ctx(c);
   return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
+             const double *n_init, const double *n_ref, const double *f_init, lbe_ctx **out) {
+  return init_impl(params, type, phi_s, n_init, n_ref, f_init, nullptr, 1, out);
+}
+
+int lbe_init_batch(const lbe_params *params, const uint8_t *type, const double *phi_s,
+                   const double *n_init, const double *n_ref, const uint16_t *system,
+                   int32_t nsys, lbe_ctx **out) {
+  if (!system) {
+    g_init_error.clear();
+    if (out) *out = nullptr;
+    return fail(nullptr, LBE_EINVAL, "system is NULL");
+  }
+  return init_impl(params, type, phi_s, n_init, n_ref, nullptr, system, nsys, out);
 }
 
 int lbe_step(lbe_ctx *c, int64_t nsteps) {
@@ -1364,7 +1458,8 @@ int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double 
   if (n && c->mixed)
     for (int k = 0; k < K; ++k)
       for (long r = 0; r < N; ++r)
-        n[(size_t)k * N + r] = c->type_h[r] ? 0.0 : c->P.nref_d[k] + (double)nu_h[(size_t)k * N + r];
+        n[(size_t)k * N + r] =
+            c->type_h[r] ? 0.0 : c->nref_h[(size_t)c->sys_h[r] * 4 + k] + (double)nu_h[(size_t)k * N + r];
   return LBE_OK;
 }
 

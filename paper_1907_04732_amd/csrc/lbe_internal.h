@@ -27,6 +27,12 @@ constexpr double A0 = 1.0 + 2.0 * SQRT2;
 // Per-node flag word: bit (i-1), i = 1..18, set when the neighbour r + c_i
 // is solid; bit 31 set when the node itself is solid.
 constexpr uint32_t SOLID_BIT = 1u << 31;
+// Bits 18..30 of a fluid node's flag word: the index of the independent
+// system it belongs to (batched runs; 0 otherwise).
+constexpr int SYS_SHIFT = 18;
+constexpr uint32_t SYS_MASK = 0x1fffu;
+constexpr int MAX_SYSTEMS = 8192;
+__host__ __device__ inline int system_of(uint32_t m) { return (int)((m >> SYS_SHIFT) & SYS_MASK); }
 
 struct Lattice {
   int nx, ny, nz;
@@ -45,12 +51,13 @@ struct Phys {
   double tau;
   double src_scale;      // 4 pi l_B / 6
   double omega;
-  // mixed form: references of the deviation storage
+  // mixed form: references of the deviation storage, per system s
   double rho0_d;         // rest density rho0
-  double nref_d[4];      // n_ref,k
-  double qref;           // sum_k z_k n_ref,k
+  const double *nref_d;  // n_ref,k of system s at [4 s + k] (device)
+  const float *nref_f;   // the same in FP32 (device)
+  const double *qref;    // sum_k z_k n_ref,k of system s at [s] (device)
   float rho0_f, itau_f;
-  float nref_f[4], dk_f[4];
+  float dk_f[4];
 };
 
 // One multigrid level (cell-centred; spacing h = 2^level in fine units).
@@ -199,8 +206,9 @@ template <class T>
 hipError_t launch_mg_prolong(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                              const uint32_t *mc, const T *ec, T *ef, const SolveCtl *ctl);
 template <class T>
-hipError_t launch_mg_coarse(hipStream_t s, const MgLevel &lv, double omega, int sweeps,
-                            const uint32_t *mask, const T *rhs, T *e, const SolveCtl *ctl);
+hipError_t launch_mg_coarse(hipStream_t s, const MgLevel &lv, double omega, double jacobi,
+                            int sweeps, const uint32_t *mask, const T *rhs, T *e, T *e2,
+                            const SolveCtl *ctl);
 template <class T>
 hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T *e, double *phi,
                              const SolveCtl *ctl);

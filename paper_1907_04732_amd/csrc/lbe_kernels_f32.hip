@@ -21,8 +21,8 @@ template <int K>
 __device__ __forceinline__ void link_force_f32(const Lattice &L, const Phys &P, int r, uint32_t m,
                                                const Offs &o, const double *__restrict__ phi,
                                                const float *__restrict__ nu, double ph,
-                                               const float (&nr)[K], float &F0, float &F1,
-                                               float &F2) {
+                                               const float *ref, const float (&nr)[K], float &F0,
+                                               float &F1, float &F2) {
   const int N = L.n;
   F0 = F1 = F2 = 0.f;
 #pragma unroll
@@ -33,7 +33,7 @@ __device__ __forceinline__ void link_force_f32(const Lattice &L, const Phys &P, 
     float g = 0.f;
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      g += excess_link_f(nr[k], P.nref_f[k] + nu[k * N + rn], float(P.z[k] * dphi),
+      g += excess_link_f(nr[k], ref[k] + nu[k * N + rn], float(P.z[k] * dphi),
                          float(0.5 / LEN[i]));
     const float c = float(3.0 * WQ[i] * LEN[i]) * g;
     if (CX[i]) F0 += CX[i] * c;
@@ -73,11 +73,13 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f32(Lattice L, Phys P,
   Offs o;
   site_offsets(L, r, o);
   const double ph = phi[r];
+  // deviation reference of this node's system (fluid neighbours share it)
+  const float *ref = P.nref_f + 4 * system_of(m);
   float dv[K], nr[K], js[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     dv[k] = nu[k * N + r];
-    nr[k] = P.nref_f[k] + dv[k];
+    nr[k] = ref[k] + dv[k];
     js[k] = 0.f;
   }
   float F0 = 0.f, F1 = 0.f, F2 = 0.f;
@@ -94,7 +96,7 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f32(Lattice L, Phys P,
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const float dn = nu[k * N + rn];
-      const float nt = P.nref_f[k] + dn;
+      const float nt = ref[k] + dn;
       float S, C;
       valence_scf(P.z[k], dphi, d1, S1, C1, S, C);
       const float gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * float(0.5 / LEN[i]);
@@ -163,10 +165,12 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f32(Lattice L, Phys P,
   Offs o;
   site_offsets(L, r, o);
   const float ux = u[r], uy = u[N + r], uz = u[2 * N + r];
+  const int sy = system_of(m);
+  const float *ref = P.nref_f + 4 * sy;
   float nr[K], Js[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    nr[k] = P.nref_f[k] + nu[k * N + r];
+    nr[k] = ref[k] + nu[k * N + r];
     Js[k] = 0.f;
   }
 #pragma unroll
@@ -180,9 +184,9 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f32(Lattice L, Phys P,
     const float w3 = float(3.0 * WQ[i]);
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      Js[k] += w3 * (nr[k] * cu_h + (P.nref_f[k] + nu[k * N + rn]) * cu_t);
+      Js[k] += w3 * (nr[k] * cu_h + (ref[k] + nu[k * N + rn]) * cu_t);
   }
-  double q = P.qref;
+  double q = P.qref[sy];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const float v = nuio[k * N + r] - Js[k];
@@ -212,11 +216,12 @@ __global__ __launch_bounds__(BLOCK) void k_observe_f32(Lattice L, Phys P,
   Offs o;
   site_offsets(L, r, o);
   const double ph = phi[r];
+  const float *ref = P.nref_f + 4 * system_of(m);
   float nr[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) nr[k] = P.nref_f[k] + nu[k * N + r];
+  for (int k = 0; k < K; ++k) nr[k] = ref[k] + nu[k * N + r];
   float F0, F1, F2;
-  link_force_f32<K>(L, P, r, m, o, phi, nu, ph, nr, F0, F1, F2);
+  link_force_f32<K>(L, P, r, m, o, phi, nu, ph, ref, nr, F0, F1, F2);
   float h[NQ];
   pull_f32(L, r, m, o, hin, h);
   double drho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
@@ -244,7 +249,9 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f32(Lattice L, Phys P,
   const int N = L.n;
   const int K = P.K;
   const int nq = 2 + K;
-  const bool fluid = r < N && !(mask[r] & SOLID_BIT);
+  const uint32_t m = r < N ? mask[r] : SOLID_BIT;
+  const bool fluid = !(m & SOLID_BIT);
+  const double *ref = P.nref_d + 4 * system_of(m);
   for (int q = 0; q < nq; ++q) {
     double v = 0.0;
     if (fluid) {
@@ -252,9 +259,9 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f32(Lattice L, Phys P,
         v = P.rho0_d;
         for (int i = 0; i < NQ; ++i) v += double(hin[i * N + r]);
       } else if (q == 1) {
-        for (int k = 0; k < K; ++k) v += P.z[k] * (P.nref_d[k] + double(nu[k * N + r]));
+        for (int k = 0; k < K; ++k) v += P.z[k] * (ref[k] + double(nu[k * N + r]));
       } else {
-        v = P.nref_d[q - 2] + double(nu[(q - 2) * N + r]);
+        v = ref[q - 2] + double(nu[(q - 2) * N + r]);
       }
     }
     v = block_sum(v, sm);

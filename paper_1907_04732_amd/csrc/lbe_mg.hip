@@ -313,15 +313,48 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(MgTransfer tr, const uint32_t
   ef[r] = e0 + prolong_value<T>(tr, r, mc, ec);
 }
 
-// ---- coarsest level: one work-group, colour sweeps with barriers ------------
+// ---- coarsest level: one work-group, sweeps with barriers ----------------------
+// Jacobi in pairs through e2 (jacobi > 0, the level needs no colouring) or
+// four-colour Gauss-Seidel with relaxation omega.
 
 template <class T>
-__global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, int sweeps,
+__global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, T jacobi, int sweeps,
                                                          const uint32_t *__restrict__ mask,
                                                          const T *__restrict__ rhs,
-                                                         T *__restrict__ e,
+                                                         T *__restrict__ e, T *__restrict__ e2,
                                                          const SolveCtl *__restrict__ ctl) {
   if (ctl->done) return;
+  const T hs = T(lv.h2 / 6.0);
+  if (jacobi > T(0)) {
+    for (int s = 0; s < sweeps; s += 2)
+      for (int pass = 0; pass < 2; ++pass) {
+        const T *xi = pass ? e2 : e;
+        T *xo = pass ? e : e2;
+        for (int r = threadIdx.x; r < lv.n; r += COARSE_BLOCK) {
+          const uint32_t m = mask[r];
+          if (m & SOLID_BIT) {
+            xo[r] = T(0);
+            continue;
+          }
+          const Coords c = coords_of(r, lv.nx, lv.nxy);
+          T v[NQ];
+          gather_lv(lv, c, r, xi, v);
+          T num = T(0), den = T(0);
+#pragma unroll
+          for (int i = 1; i < NQ; ++i) {
+            if ((lv.selfm >> (i - 1)) & 1u) continue;
+            const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
+            num += ws * v[i];
+            den += ws;
+          }
+          num += hs * rhs[r];
+          xo[r] = v[0] + jacobi * (num / den - v[0]);
+        }
+        __threadfence_block();
+        __syncthreads();
+      }
+    return;
+  }
   for (int s = 0; s < sweeps; ++s) {
     for (int col = 0; col < 4; ++col) {
       for (int r = threadIdx.x; r < lv.n; r += COARSE_BLOCK) {
@@ -337,7 +370,7 @@ __global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, in
           num += ws * e[nbr_of(lv, c, i)];
           den += ws;
         }
-        num += T(lv.h2 / 6.0) * rhs[r];
+        num += hs * rhs[r];
         e[r] = (T(1) - omega) * e[r] + omega * (num / den);
       }
       __threadfence_block();
@@ -599,10 +632,11 @@ hipError_t launch_mg_prolong(hipStream_t s, const MgTransfer &tr, const uint32_t
 }
 
 template <class T>
-hipError_t launch_mg_coarse(hipStream_t s, const MgLevel &lv, double omega, int sweeps,
-                            const uint32_t *mask, const T *rhs, T *e, const SolveCtl *ctl) {
-  hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(COARSE_BLOCK), 0, s, lv, T(omega), sweeps, mask,
-                     rhs, e, ctl);
+hipError_t launch_mg_coarse(hipStream_t s, const MgLevel &lv, double omega, double jacobi,
+                            int sweeps, const uint32_t *mask, const T *rhs, T *e, T *e2,
+                            const SolveCtl *ctl) {
+  hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(COARSE_BLOCK), 0, s, lv, T(omega), T(jacobi),
+                     sweeps, mask, rhs, e, e2, ctl);
   return hipGetLastError();
 }
 
@@ -648,8 +682,9 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                             const SolveCtl *);                                  \
   template hipError_t launch_mg_prolong<T>(hipStream_t, const MgTransfer &, const uint32_t *,   \
                                            const uint32_t *, const T *, T *, const SolveCtl *); \
-  template hipError_t launch_mg_coarse<T>(hipStream_t, const MgLevel &, double, int,            \
-                                          const uint32_t *, const T *, T *, const SolveCtl *);  \
+  template hipError_t launch_mg_coarse<T>(hipStream_t, const MgLevel &, double, double, int,    \
+                                          const uint32_t *, const T *, T *, T *,                \
+                                          const SolveCtl *);                                    \
   template hipError_t launch_mg_correct<T>(hipStream_t, int, const uint32_t *, const T *,       \
                                            double *, const SolveCtl *);                         \
   template hipError_t launch_mg_coarse_dense<T>(hipStream_t, int, const T *, const int *,       \

@@ -91,10 +91,23 @@ def test_geometry_rejected():
     with pytest.raises(lbe.LbeError) as e:
         lbe.Lbe(p, t, ps, None, (1e-3, 1e-3))
     assert e.value.code == lbe.EGEOM
+
+
+
+def test_batched_systems_rejected():
+    """lbe_init_batch validates the system map before touching a device."""
     shape, t, ps = W.slab(2, 2, 8, 1)
-    t = t.copy()
-    t[0] = 70  # too many electrodes
     p = lbe.make_params(shape, (1, -1), (0.05, 0.05), 0.4)
-    with pytest.raises(lbe.LbeError) as e:
-        lbe.Lbe(p, t, ps, None, (1e-3, 1e-3))
+    sy = np.zeros(t.size, np.uint16)
+    nref = np.full((2, 2), 1e-3)
+    with pytest.raises(lbe.LbeError) as e:  # index >= nsys
+        lbe.Lbe(p, t, ps, None, nref, system=sy + 2, nsys=2)
     assert e.value.code == lbe.EINVAL
+    with pytest.raises(lbe.LbeError) as e:  # nsys out of range
+        lbe.Lbe(p, t, ps, None, nref, system=sy, nsys=0)
+    assert e.value.code == lbe.EINVAL
+    half = sy.copy()
+    half[t.size // 2:] = 1  # one fluid column split between two systems
+    with pytest.raises(lbe.LbeError) as e:
+        lbe.Lbe(p, t, ps, None, nref, system=half, nsys=2)
+    assert e.value.code == lbe.EGEOM

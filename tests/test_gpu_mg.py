@@ -4,7 +4,10 @@ Both solve the same linear system (Eq. 2 with the Laplacian of Eq. 15) to a
 residual tol; they differ by at most |A^-1| tol in the potential.  For a gap
 of L lattice units |A^-1| <= L^2/8, so with tol = 1e-14 and L <= 32 the
 potentials agree to 1.3e-11 absolute; the tests allow 2e-11 relative to the
-electrode voltage scale 0.1 for phi and the same relative bound for n, f, Q.
+electrode voltage scale 0.1 for phi and the same relative bound for n, f.
+The electrode charge is set by the potential drop between the wall and the
+first fluid plane, about dV/(2L) = 1.6e-3 here, so its bound is
+1.3e-11 / 1.6e-3 ~ 1e-8 relative.
 """
 import numpy as np
 import pytest
@@ -18,6 +21,7 @@ from test_gpu_parity import U_SCALE, rel, residual_numpy
 pytestmark = pytest.mark.gpu
 
 MG_TOL = 2e-11
+MG_QTOL = 1e-8
 
 
 def mg_pair(name, tol=1e-14, steps=None):
@@ -43,7 +47,7 @@ def test_mg_matches_oracle(name):
     tot = g.totals()
     print(name, {k: f"{v:.2e}" for k, v in errs.items()}, "cycles", tot["poisson_iters"])
     for k, v in errs.items():
-        assert v <= MG_TOL, (k, errs)
+        assert v <= (MG_QTOL if k == "q" else MG_TOL), (k, errs)
     assert tot["poisson_resid"] <= 1e-14
 
 

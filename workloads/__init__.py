@@ -188,3 +188,67 @@ def coaxial(noise=True, nx=160, ny=160, nz=64, R1=8.0, R2=72.0):
     return Workload(f"coaxial_{nx}x{ny}x{nz}", shape, t, ps, (1, -1), (0.05, 0.05), lB, 0.8, 1.0,
                     (0.0, 0.0, 1e-3), (rs, rs), n_init, 1.8, 1e-10, 30000,
                     dict(debye=debye, R1=R1, R2=R2, dV=-0.1))
+
+
+@dataclass
+class Batch:
+    """Independent parallel-plate systems stacked along z in one lattice."""
+    name: str
+    shape: tuple
+    node_type: np.ndarray
+    phi_s: np.ndarray
+    system: np.ndarray          # system index of every node (0 on solid nodes)
+    n_ref: np.ndarray           # (nsys, K) salt concentration of each system
+    n_init: np.ndarray | None
+    z: tuple
+    D: tuple
+    lB: float
+    tau: float
+    L: np.ndarray               # fluid planes of each system
+    V: np.ndarray               # voltage across each system
+    debye: np.ndarray           # Debye length of each system
+    z0: np.ndarray              # first fluid plane of each system
+
+
+def batch_slabs(nsys=96, nxy=8, Lmin=16, Lmax=256, Vmin=0.01, Vmax=0.2, dmin=2.0, dmax=16.0,
+                seed=4, noise=True, lB=0.4, D=0.05):
+    """Parameter sweep of parallel-plate capacitors (Sec. III A): nsys systems,
+    each nxy x nxy periodic with L fluid planes (L uniform in Lmin..Lmax),
+    voltage V uniform in [Vmin, Vmax] (+V/2 and -V/2 on its electrodes),
+    Debye length uniform in [dmin, dmax] (1:1 salt, l_B = 0.4).  Each system
+    is one electrode plane, L fluid planes and one or two electrode planes
+    (an even number of planes in all, so the four-colour order of each
+    system is the one it has alone), stacked along z; system s owns
+    electrodes 2s + 1 (bottom) and 2s + 2 (top).  Seeded."""
+    rng = np.random.default_rng(seed)
+    L = rng.integers(Lmin, Lmax + 1, nsys)
+    V = rng.uniform(Vmin, Vmax, nsys)
+    debye = rng.uniform(dmin, dmax, nsys)
+    planes = L + 2 + ((L + 2) % 2)
+    nz = int(planes.sum())
+    t = np.zeros((nz, nxy, nxy), np.uint8)
+    ps = np.zeros((nz, nxy, nxy))
+    sy = np.zeros((nz, nxy, nxy), np.uint16)
+    z0 = np.zeros(nsys, int)
+    z = 0
+    for s in range(nsys):
+        t[z] = 2 * s + 1
+        ps[z] = 0.5 * V[s]
+        z0[s] = z + 1
+        sy[z + 1:z + 1 + L[s]] = s
+        t[z + 1 + L[s]:z + planes[s]] = 2 * s + 2
+        ps[z + 1 + L[s]:z + planes[s]] = -0.5 * V[s]
+        z += planes[s]
+    rs = np.array([salt_for_debye(d, lB) for d in debye])
+    n_ref = np.stack([rs, rs], axis=1)
+    t = t.reshape(-1)
+    sy = sy.reshape(-1)
+    n_init = None
+    if noise:
+        rng2 = np.random.default_rng(seed + 1000)
+        n_init = np.empty((2, t.size))
+        for k in range(2):
+            n_init[k] = rs[sy] * (1.0 + 1e-6 * rng2.uniform(-1.0, 1.0, t.size))
+        n_init[:, t != 0] = 0.0
+    return Batch(f"batched_{nsys}_slabs_{nxy}x{nxy}", (nxy, nxy, nz), t, ps.reshape(-1), sy,
+                 n_ref, n_init, (1, -1), (D, D), lB, 1.0, L, V, debye, z0)
