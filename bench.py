@@ -70,6 +70,10 @@ def bytes_per_cell(kind: str, form: str, K: int):
         "mg_resid": 8 + 8 + 4 + 2 * cor,
         "correct": 16 + cor + 4,
         "extrap": 32 + 4,
+        "fcg_beta": cor + 8 + 4,
+        "fcg_dir": cor + 16 + 4,
+        "fcg_apply": 8 + 8 + 8 + 4,
+        "fcg_update": 8 + 8 + 16 + 16 + 2 * cor + 4,
     }
     return table.get(kind)
 
@@ -105,22 +109,38 @@ def load_traffic(workload: str):
     return rows if src == sources_hash() else {}
 
 
+_torch = None
+
+
+def init_device():
+    """Bring the device up through torch before the library touches it (torch
+    does not attach to a device the HIP runtime has already initialised in
+    this process); torch.cuda.synchronize() then waits for every stream on
+    the device, the library's own included."""
+    global _torch
+    import torch
+    torch.cuda.init()
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU visible to torch")
+    torch.zeros(1, device="cuda")
+    torch.cuda.synchronize()
+    _torch = torch
+
+
 def sync():
-    try:
-        import torch
-        if torch.cuda.is_available():
-            torch.cuda.synchronize()
-    except Exception:
-        pass
+    _torch.cuda.synchronize()
 
 
 def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, check_every: int,
-             traffic=None):
+             traffic=None, krylov=False):
     precision = lbe.FP64 if form == "fp64" else lbe.FP32_MIXED
     poisson = lbe.SOR4 if solver == "sor" else lbe.MG
     # multigrid forms start each solve from 2 phi(t) - phi(t-1); the SOR form
-    # keeps the paper's warm start from phi(t)
+    # keeps the paper's warm start from phi(t).  Krylov acceleration of the
+    # V-cycle where coarse levels represent the electrodes poorly.
     flags = lbe.EXTRAPOLATE if solver == "mg" else 0
+    if krylov and solver == "mg":
+        flags |= lbe.KRYLOV
     p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, rho0=getattr(w, "rho0", 1.0),
                         Eapp=getattr(w, "Eapp", (0.0, 0.0, 0.0)), omega=getattr(w, "omega", 1.8),
                         tol=getattr(w, "tol", 1e-10), max_iter=1_000_000,
@@ -247,13 +267,13 @@ def run_shapes(names, forms, steps, warmup, check_every):
         res = {}
         for f in forms:
             form, solver = FORMS[f]
-            r = run_form(w, form, solver, steps, warmup, check_every)
+            r = run_form(w, form, solver, steps, warmup, check_every, krylov=True)
             keep = {k: r["kernels"][k] for k in ("fluid", "ions") if k in r["kernels"]}
             res[f] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"],
                       "poisson_iters_per_step": r["poisson_iters_per_step"],
                       "roofline": r["roofline"], "step_kernels": keep}
         out[w.name] = {"sites": int(w.node_type.size), "fluid_sites": nfluid, "steps": steps,
-                       "forms": res}
+                       "poisson": "multigrid-preconditioned flexible CG", "forms": res}
     return out
 
 
@@ -277,6 +297,7 @@ def main():
         print("bench.py measures one GPU: the LBE step is not sharded across GPUs in this "
               "build (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    init_device()
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     w = W.eo_slab(noise=True)
     N = w.node_type.size

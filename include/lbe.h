@@ -50,7 +50,8 @@ enum {
 enum { LBE_FP64 = 0, LBE_FP32_MIXED = 1 };   /* precision form */
 enum { LBE_SOR4 = 0, LBE_MG = 1 };           /* Poisson solver */
 enum { LBE_MG_JACOBI = 0, LBE_MG_GS4 = 1 };  /* multigrid smoother */
-enum { LBE_ALLOW_FLOATING = 1, LBE_EXTRAPOLATE = 2, LBE_NAIVE_DIRICHLET = 4 };  /* flags */
+enum { LBE_ALLOW_FLOATING = 1, LBE_EXTRAPOLATE = 2, LBE_NAIVE_DIRICHLET = 4,
+       LBE_KRYLOV = 8 };  /* flags */
 enum { LBE_MAX_SPECIES = 4, LBE_MAX_ELECTRODES = 255, LBE_MAX_SITES = 100000000,
        LBE_MAX_SYSTEMS = 8192 };
 
@@ -79,7 +80,11 @@ typedef struct {
                            paper contrasts with (Sec. II C, Fig. 1): phi_s
                            held on the solid nodes and the plain Laplacian of
                            Eq. 12 (factor 1 on solid-fluid links) in Poisson
-                           and in Gauss's law, instead of Eq. 15 */
+                           and in Gauss's law, instead of Eq. 15;
+                           LBE_KRYLOV (with LBE_MG): each multigrid V-cycle
+                           preconditions flexible conjugate gradients (same
+                           fixed point and tolerance; fewer cycles where
+                           coarse levels represent the electrodes poorly) */
   int32_t precision;    /* LBE_FP64 | LBE_FP32_MIXED */
   int32_t poisson;      /* LBE_SOR4 | LBE_MG */
   int32_t mg_levels;    /* multigrid levels (LBE_MG): 0 = coarsen until at most

@@ -20,6 +20,7 @@ MG_JACOBI, MG_GS4 = 0, 1
 ALLOW_FLOATING = 1
 EXTRAPOLATE = 2
 NAIVE_DIRICHLET = 4
+KRYLOV = 8
 
 # public entry points of include/lbe.h
 ENTRY_POINTS = (

@@ -52,6 +52,9 @@ struct lbe_ctx {
 
   // electrode charge tables
   int *iface = nullptr, *blk_elec = nullptr, *blk_begin = nullptr, *blk_end = nullptr;
+  // flexible-CG state (LBE_KRYLOV): residual, direction, A direction (FP64)
+  double *kr = nullptr, *kp = nullptr, *kq = nullptr;
+  KrylovCtl *kc = nullptr;
   // per-system references of the mixed form (device tables) and each node's system
   std::vector<uint16_t> sys_h;
   double *nref_d_tab = nullptr, *qref_tab = nullptr;
@@ -206,7 +209,7 @@ int validate(const lbe_params *p) {
       return fail(nullptr, LBE_EINVAL, "diffusion coefficients must be finite and >= 0");
   for (int a = 0; a < 3; ++a)
     if (!isfinite(p->Eapp[a])) return fail(nullptr, LBE_EINVAL, "applied field must be finite");
-  if (p->flags & ~(LBE_ALLOW_FLOATING | LBE_EXTRAPOLATE | LBE_NAIVE_DIRICHLET))
+  if (p->flags & ~(LBE_ALLOW_FLOATING | LBE_EXTRAPOLATE | LBE_NAIVE_DIRICHLET | LBE_KRYLOV))
     return fail(nullptr, LBE_EINVAL, "unknown flags");
   if (p->precision != LBE_FP64 && p->precision != LBE_FP32_MIXED)
     return fail(nullptr, LBE_EINVAL, "unsupported precision form");
@@ -827,10 +830,53 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
 }
 
 // Defect correction: residual in FP64 (which also zeroes e and stores the
-// right-hand side for the correction), one V-cycle for e, phi += e.
+// right-hand side for the correction), one V-cycle for e, phi += e.  With
+// LBE_KRYLOV the V-cycle preconditions flexible conjugate gradients instead
+// (one V-cycle and one operator application per iteration).
 template <class T>
 int mg_solve(lbe_ctx *c, bool learn) {
   lbe_ctx::MgDev &L0 = c->mg[0];
+  if (c->kc) {
+    const int n = L0.lv.n;
+    return run_solve(
+        c, 1, learn, "cycles",
+        [&](int m) -> int {
+          for (int k = 0; k < m; ++k) {
+            T *z = nullptr;
+            int rc = mg_vcycle<T>(c, 0, &z);
+            if (rc) return rc;
+            rc = run(c, KK_FCG_BETA, n, [&] {
+              return launch_fcg_beta<T>(c->stream, n, c->mask, (const T *)z, c->kq, c->partial,
+                                        c->kc, c->ctl);
+            });
+            if (rc) return rc;
+            rc = run(c, KK_FCG_DIR, n, [&] {
+              return launch_fcg_dir<T>(c->stream, n, c->mask, (const T *)z, c->kp, c->kc, c->ctl);
+            });
+            if (rc) return rc;
+            rc = run(c, KK_FCG_APPLY, n, [&] {
+              return launch_fcg_apply(c->stream, L0.lv, c->mask, c->kp, c->kr, c->kq, c->partial,
+                                      c->kc, c->ctl);
+            });
+            if (rc) return rc;
+            // every iteration ends with its own stop check (one cycle each)
+            rc = run(c, KK_FCG_UPDATE, n, [&] {
+              return launch_fcg_update<T>(c->stream, n, c->mask, c->kp, c->kq, c->phi, c->kr,
+                                          (T *)L0.r, (T *)L0.e, c->partial, c->kc, c->ctl, 1);
+            });
+            if (rc) return rc;
+          }
+          return LBE_OK;
+        },
+        [&](int add) -> int {
+          if (add) return LBE_OK;  // each update kernel has checked already
+          return run(c, KK_MG_RESID, n, [&] {
+            return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi,
+                                            (T *)L0.r, (T *)L0.e, c->partial, c->ctl, 0, c->kr,
+                                            c->kc);
+          });
+        });
+  }
   return run_solve(
       c, 1, learn, "cycles",
       [&](int m) -> int {
@@ -849,7 +895,7 @@ int mg_solve(lbe_ctx *c, bool learn) {
       [&](int add) -> int {
         return run(c, KK_MG_RESID, L0.lv.n, [&] {
           return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi, (T *)L0.r,
-                                          (T *)L0.e, c->partial, c->ctl, add);
+                                          (T *)L0.e, c->partial, c->ctl, add, nullptr, nullptr);
         });
       });
 }
@@ -896,7 +942,7 @@ int mixed_sor_solve(lbe_ctx *c, bool learn) {
         return run(c, KK_MG_RESID, L0.lv.n, [&] {
           return launch_mg_outer_resid<float>(c->stream, L0.lv, c->mask, c->src, c->phi,
                                               (float *)L0.r, (float *)L0.e, c->partial, c->ctl,
-                                              add);
+                                              add, nullptr, nullptr);
         });
       });
 }
@@ -968,7 +1014,7 @@ void free_ctx(lbe_ctx *c) {
                   c->h32[0], c->h32[1], c->nu32[0], c->nu32[1], c->u32, c->obs,
                   c->partial, c->dout, c->ctl, c->iface, c->blk_elec, c->blk_begin,
                   c->blk_end, c->qcur, c->qhist, c->solid_idx, c->solid_val,
-                  c->nref_d_tab, c->qref_tab, c->nref_f_tab};
+                  c->nref_d_tab, c->qref_tab, c->nref_f_tab, c->kr, c->kp, c->kq, c->kc};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   for (auto &L : c->mg) {
@@ -1293,6 +1339,18 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     }
   }
   if (p.poisson == LBE_MG || c->mixed) TRY(build_multigrid(c, type, p.poisson != LBE_MG));
+  if (p.poisson == LBE_MG && (p.flags & LBE_KRYLOV)) {
+    TRY(dalloc(c, &c->kr, N));
+    TRY(dalloc(c, &c->kp, N));
+    TRY(dalloc(c, &c->kq, N));
+    TRY(dalloc(c, &c->kc, 1));
+    if (hipMemsetAsync(c->kp, 0, sizeof(double) * N, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->kq, 0, sizeof(double) * N, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->kc, 0, sizeof(KrylovCtl), c->stream) != hipSuccess) {
+      rc = fail(c, LBE_EDEVICE, "memset failed");
+      goto fail_;
+    }
+  }
   TRY(poisson_solve(c, false));
   TRY(record_charge(c));
   if (p.flags & LBE_EXTRAPOLATE) {

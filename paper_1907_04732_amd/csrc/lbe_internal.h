@@ -90,6 +90,14 @@ struct SolveCtl {
   int pad;
 };
 
+// Flexible conjugate gradients preconditioned by one V-cycle (device state).
+struct KrylovCtl {
+  double alpha, beta;
+  double pq_prev;  // (p, A p) of the previous direction
+  int first;       // 1 until the first direction of a solve is formed
+  int pad;
+};
+
 // The coarse end of the hierarchy handled by one work-group in LDS.
 constexpr int MG_MAX_SMALL = 8;
 constexpr int MG_MAX_DENSE = 512;         // largest coarsest level solved with a dense inverse
@@ -128,6 +136,10 @@ enum KernelKind {
   KK_MG_COARSE,   // coarsest-level solve in one work-group
   KK_EXTRAP,      // warm start phi <- 2 phi - phi_prev
   KK_MG_SMALL,    // the coarse levels of a V-cycle in one work-group
+  KK_FCG_BETA,    // Krylov: (z, q_prev) and beta
+  KK_FCG_DIR,     // Krylov: p = z + beta p
+  KK_FCG_APPLY,   // Krylov: q = A p, (p, q), (r, p), alpha
+  KK_FCG_UPDATE,  // Krylov: phi += alpha p, r -= alpha q, stop check
   KK_COUNT
 };
 
@@ -188,7 +200,26 @@ hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, con
 template <class T>
 hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
                                  const double *src, const double *phi, T *r0, T *e0,
-                                 double *partial, SolveCtl *ctl, int add);
+                                 double *partial, SolveCtl *ctl, int add, double *r64,
+                                 KrylovCtl *kc);
+// Flexible CG on A e = R (A = -L_h, level 0), preconditioner z = V-cycle(r):
+//   beta = -(z, q_prev) / (p_prev, q_prev) (0 for the first direction),
+//   p = z + beta p,  q = A p,  alpha = (r, p) / (p, q),
+//   phi += alpha p,  r -= alpha q  (r also copied to r0 in T, e0 zeroed),
+// then the stop check on ||r||_inf.
+template <class T>
+hipError_t launch_fcg_beta(hipStream_t s, int n, const uint32_t *mask, const T *z,
+                           const double *q, double *partial, KrylovCtl *kc, const SolveCtl *ctl);
+template <class T>
+hipError_t launch_fcg_dir(hipStream_t s, int n, const uint32_t *mask, const T *z, double *p,
+                          const KrylovCtl *kc, const SolveCtl *ctl);
+hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
+                            const double *p, const double *r, double *q, double *partial,
+                            KrylovCtl *kc, const SolveCtl *ctl);
+template <class T>
+hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const double *p,
+                             const double *q, double *phi, double *r, T *r0, T *e0,
+                             double *partial, const KrylovCtl *kc, SolveCtl *ctl, int add);
 template <class T>
 hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int colour,
                             const uint32_t *mask, const T *rhs, T *e, const SolveCtl *ctl);

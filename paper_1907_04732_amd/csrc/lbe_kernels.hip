@@ -21,7 +21,8 @@ namespace lbe {
 
 const char *const kKernelNames[KK_COUNT] = {
     "fluid", "ions", "sor", "resid", "charge", "totals", "observe", "sor32", "correct",
-    "mg_resid", "mg_smooth", "mg_smooth0", "mg_restrict", "mg_prolong", "mg_coarse", "extrap", "mg_small"};
+    "mg_resid", "mg_smooth", "mg_smooth0", "mg_restrict", "mg_prolong", "mg_coarse", "extrap", "mg_small",
+    "fcg_beta", "fcg_dir", "fcg_apply", "fcg_update"};
 
 namespace {
 

@@ -82,10 +82,13 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
                                                        const double *__restrict__ phi,
                                                        T *__restrict__ r0, T *__restrict__ e0,
                                                        double *__restrict__ partial,
-                                                       const SolveCtl *__restrict__ ctl) {
+                                                       const SolveCtl *__restrict__ ctl,
+                                                       double *__restrict__ r64,
+                                                       KrylovCtl *__restrict__ kc) {
   __shared__ double sm[BLOCK / WAVE];
   if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (kc && r == 0) kc->first = 1;  // a new Krylov sequence starts from this residual
   double a = 0.0;
   if (r < lv.n) {
     const uint32_t m = mask[r];
@@ -103,6 +106,135 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
         acc += ws * (pn[i] - pn[0]);
       }
       R = 6.0 * (acc + sr);
+      a = fabs(R);
+    }
+    r0[r] = T(R);
+    e0[r] = T(0);
+    if (r64) r64[r] = R;
+  }
+  a = block_max(a, sm);
+  if (threadIdx.x == 0) partial[blockIdx.x] = a;
+}
+
+// ---- flexible conjugate gradients around the V-cycle -------------------------
+// The V-cycle is a fixed but non-symmetric preconditioner (mean restriction is
+// not the transpose of the mirrored prolongation, and the mixed form applies it
+// in FP32), so directions are A-orthogonalised against the previous one only
+// (flexible CG with one stored direction).  All scalars stay on the device.
+
+// partial sums of (a, b) over fluid sites, one per block (fixed tree order)
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_fcg_dot(int n, const uint32_t *__restrict__ mask,
+                                                   const T *__restrict__ a,
+                                                   const double *__restrict__ b,
+                                                   double *__restrict__ partial,
+                                                   const SolveCtl *__restrict__ ctl) {
+  __shared__ double sm[BLOCK / WAVE];
+  if (ctl->done) return;
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  double v = 0.0;
+  if (r < n && !(mask[r] & SOLID_BIT)) v = double(a[r]) * b[r];
+  v = block_sum(v, sm);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+// fixed-order sum of nb partials by one block (valid in thread 0)
+__device__ double sum_partials(const double *__restrict__ partial, int nb, double *tree) {
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += BLOCK) v += partial[b];
+  tree[threadIdx.x] = v;
+  __syncthreads();
+  for (int s2 = BLOCK / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) tree[threadIdx.x] += tree[threadIdx.x + s2];
+    __syncthreads();
+  }
+  return tree[0];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fcg_beta(const double *__restrict__ partial, int nb,
+                                                    KrylovCtl *__restrict__ kc,
+                                                    const SolveCtl *__restrict__ ctl) {
+  __shared__ double tree[BLOCK];
+  if (ctl->done) return;
+  const double zq = sum_partials(partial, nb, tree);
+  if (threadIdx.x == 0) kc->beta = (kc->first || kc->pq_prev == 0.0) ? 0.0 : -zq / kc->pq_prev;
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_fcg_dir(int n, const uint32_t *__restrict__ mask,
+                                                   const T *__restrict__ z, double *__restrict__ p,
+                                                   const KrylovCtl *__restrict__ kc,
+                                                   const SolveCtl *__restrict__ ctl) {
+  if (ctl->done) return;
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= n || (mask[r] & SOLID_BIT)) return;
+  const double beta = kc->beta;
+  p[r] = beta == 0.0 ? double(z[r]) : double(z[r]) + beta * p[r];
+}
+
+// q = A p on fluid sites (p = 0 on solid ones), partials of (p, q) and (r, p)
+__global__ __launch_bounds__(BLOCK) void k_fcg_apply(MgLevel lv, const uint32_t *__restrict__ mask,
+                                                     const double *__restrict__ p,
+                                                     const double *__restrict__ rv,
+                                                     double *__restrict__ q,
+                                                     double *__restrict__ partial,
+                                                     const SolveCtl *__restrict__ ctl) {
+  __shared__ double sm[BLOCK / WAVE];
+  if (ctl->done) return;
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  double pq = 0.0, rp = 0.0;
+  if (r < lv.n) {
+    const uint32_t m = mask[r];
+    if (!(m & SOLID_BIT)) {
+      const Coords c = coords_of(r, lv.nx, lv.nxy);
+      const double qr = apply_A<double>(lv, r, m, c, p);
+      q[r] = qr;
+      pq = p[r] * qr;
+      rp = rv[r] * p[r];
+    }
+  }
+  pq = block_sum(pq, sm);
+  if (threadIdx.x == 0) partial[blockIdx.x] = pq;
+  rp = block_sum(rp, sm);
+  if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = rp;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fcg_alpha(const double *__restrict__ partial, int nb,
+                                                     KrylovCtl *__restrict__ kc,
+                                                     const SolveCtl *__restrict__ ctl) {
+  __shared__ double tree[BLOCK];
+  if (ctl->done) return;
+  const double pq = sum_partials(partial, nb, tree);
+  __syncthreads();
+  const double rp = sum_partials(partial + nb, nb, tree);
+  if (threadIdx.x == 0) {
+    kc->alpha = pq > 0.0 ? rp / pq : 0.0;
+    kc->pq_prev = pq;
+    kc->first = 0;
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_fcg_update(int n, const uint32_t *__restrict__ mask,
+                                                      const double *__restrict__ p,
+                                                      const double *__restrict__ q,
+                                                      double *__restrict__ phi,
+                                                      double *__restrict__ rv,
+                                                      T *__restrict__ r0, T *__restrict__ e0,
+                                                      double *__restrict__ partial,
+                                                      const KrylovCtl *__restrict__ kc,
+                                                      const SolveCtl *__restrict__ ctl) {
+  __shared__ double sm[BLOCK / WAVE];
+  if (ctl->done) return;
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  double a = 0.0;
+  if (r < n) {
+    double R = 0.0;
+    if (!(mask[r] & SOLID_BIT)) {
+      const double alpha = kc->alpha;
+      phi[r] += alpha * p[r];
+      R = rv[r] - alpha * q[r];
+      rv[r] = R;
       a = fabs(R);
     }
     r0[r] = T(R);
@@ -588,10 +720,47 @@ __global__ __launch_bounds__(BLOCK) void k_correct(int n, const uint32_t *__rest
 template <class T>
 hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
                                  const double *src, const double *phi, T *r0, T *e0,
-                                 double *partial, SolveCtl *ctl, int add) {
+                                 double *partial, SolveCtl *ctl, int add, double *r64,
+                                 KrylovCtl *kc) {
   const int nb = (int)blocks_for(lv.n);
   hipLaunchKernelGGL(k_outer_resid<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, src, phi, r0, e0,
-                     partial, ctl);
+                     partial, ctl, r64, kc);
+  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(BLOCK), 0, s, partial, nb, ctl, add);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fcg_beta(hipStream_t s, int n, const uint32_t *mask, const T *z,
+                           const double *q, double *partial, KrylovCtl *kc, const SolveCtl *ctl) {
+  const int nb = (int)blocks_for(n);
+  hipLaunchKernelGGL(k_fcg_dot<T>, dim3(nb), dim3(BLOCK), 0, s, n, mask, z, q, partial, ctl);
+  hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(BLOCK), 0, s, partial, nb, kc, ctl);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fcg_dir(hipStream_t s, int n, const uint32_t *mask, const T *z, double *p,
+                          const KrylovCtl *kc, const SolveCtl *ctl) {
+  hipLaunchKernelGGL(k_fcg_dir<T>, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, mask, z, p, kc, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
+                            const double *p, const double *r, double *q, double *partial,
+                            KrylovCtl *kc, const SolveCtl *ctl) {
+  const int nb = (int)blocks_for(lv.n);
+  hipLaunchKernelGGL(k_fcg_apply, dim3(nb), dim3(BLOCK), 0, s, lv, mask, p, r, q, partial, ctl);
+  hipLaunchKernelGGL(k_fcg_alpha, dim3(1), dim3(BLOCK), 0, s, partial, nb, kc, ctl);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const double *p,
+                             const double *q, double *phi, double *r, T *r0, T *e0,
+                             double *partial, const KrylovCtl *kc, SolveCtl *ctl, int add) {
+  const int nb = (int)blocks_for(n);
+  hipLaunchKernelGGL(k_fcg_update<T>, dim3(nb), dim3(BLOCK), 0, s, n, mask, p, q, phi, r, r0, e0,
+                     partial, kc, ctl);
   hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(BLOCK), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
@@ -671,7 +840,16 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
 #define LBE_MG_INSTANTIATE(T)                                                                   \
   template hipError_t launch_mg_outer_resid<T>(hipStream_t, const MgLevel &, const uint32_t *,  \
                                                const double *, const double *, T *, T *,       \
-                                               double *, SolveCtl *, int);                      \
+                                               double *, SolveCtl *, int, double *,            \
+                                               KrylovCtl *);                                   \
+  template hipError_t launch_fcg_beta<T>(hipStream_t, int, const uint32_t *, const T *,         \
+                                         const double *, double *, KrylovCtl *,                 \
+                                         const SolveCtl *);                                     \
+  template hipError_t launch_fcg_dir<T>(hipStream_t, int, const uint32_t *, const T *, double *, \
+                                        const KrylovCtl *, const SolveCtl *);                   \
+  template hipError_t launch_fcg_update<T>(hipStream_t, int, const uint32_t *, const double *,  \
+                                           const double *, double *, double *, T *, T *,        \
+                                           double *, const KrylovCtl *, SolveCtl *, int);       \
   template hipError_t launch_mg_smooth<T>(hipStream_t, const MgLevel &, double, int,            \
                                           const uint32_t *, const T *, T *, const SolveCtl *);  \
   template hipError_t launch_jacobi<T>(hipStream_t, const MgLevel &, double, double,             \
