@@ -81,7 +81,8 @@ typedef struct {
                            held on the solid nodes and the plain Laplacian of
                            Eq. 12 (factor 1 on solid-fluid links) in Poisson
                            and in Gauss's law, instead of Eq. 15;
-                           LBE_KRYLOV (with LBE_MG): each multigrid V-cycle
+                           LBE_KRYLOV (LBE_MG only, else LBE_EINVAL): each
+                           multigrid V-cycle
                            preconditions flexible conjugate gradients (same
                            fixed point and tolerance; fewer cycles where
                            coarse levels represent the electrodes poorly) */

@@ -211,6 +211,8 @@ int validate(const lbe_params *p) {
     if (!isfinite(p->Eapp[a])) return fail(nullptr, LBE_EINVAL, "applied field must be finite");
   if (p->flags & ~(LBE_ALLOW_FLOATING | LBE_EXTRAPOLATE | LBE_NAIVE_DIRICHLET | LBE_KRYLOV))
     return fail(nullptr, LBE_EINVAL, "unknown flags");
+  if ((p->flags & LBE_KRYLOV) && p->poisson != LBE_MG)
+    return fail(nullptr, LBE_EINVAL, "LBE_KRYLOV accelerates the multigrid solver only");
   if (p->precision != LBE_FP64 && p->precision != LBE_FP32_MIXED)
     return fail(nullptr, LBE_EINVAL, "unsupported precision form");
   if (p->poisson != LBE_SOR4 && p->poisson != LBE_MG)

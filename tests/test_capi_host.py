@@ -53,7 +53,8 @@ def _slab_params(**kw):
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(omega=2.0), dict(omega=-0.1),
                                 dict(check_every=0), dict(lB=-1.0), dict(rho0=0.0),
                                 dict(D=(0.05, -1.0)), dict(Eapp=(np.nan, 0, 0)),
-                                dict(precision=7), dict(poisson=9), dict(flags=8),
+                                dict(precision=7), dict(poisson=9), dict(flags=16),
+                                dict(flags=8),  # Krylov acceleration needs multigrid
                                 dict(poisson=1, mg_levels=1), dict(poisson=1, mg_nu1=0, mg_nu2=0)])
 def test_invalid_parameters_rejected(kw):
     p, t, ps = _slab_params(**kw)
