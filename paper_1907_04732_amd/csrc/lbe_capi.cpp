@@ -752,7 +752,9 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
   }
   const MgLevel &top = c->mg.back().lv;
   c->mg_coarse_sweeps = 2 * std::max({top.nx, top.ny, top.nz}) + 10;
-  if (c->mg.size() > 1) {
+  // the coarsest level (the only one on a lattice of at most 512 cells) is
+  // inverted exactly when it is small and non-singular
+  if (!only_top) {
     int rc = build_coarse_inverse(c, solid);
     if (rc) return rc;
   }

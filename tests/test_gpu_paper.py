@@ -72,17 +72,22 @@ def test_coaxial_neutral_profile_and_dielectric_capacitance():
 
 
 def test_slab_charging_time_and_capacitance():
-    """Fig. 4-5 setting (32 fluid planes, lambda_D = 4, D = 0.05): Q(0) is the
-    dielectric charge, Q(t) relaxes with the linearised PNP charging time
-    within 3%, and the final charge gives the Debye-Hueckel capacitance within
-    1.5% (Eq. 18, finite-gap form)."""
+    """Fig. 4-5 setting (32 fluid planes, lambda_D = 4, D = 0.05), mixed form:
+    Q(0) is the dielectric charge, Q(t) relaxes with the linearised PNP
+    charging time within 3%, and the final charge gives the Debye-Hueckel
+    capacitance within 1.5% (Eq. 18, finite-gap form).  The exponential fit
+    stops at 1e-2 of the initial deviation: the mixed form conserves the ions
+    to FP32 rounding of the deviation updates (about 6e-8 relative over these
+    20000 steps), which moves the final charge by ~3e-5 relative and would
+    bias a fit reaching further into the tail (FP64 gives the same time for
+    any window down to 1e-4)."""
     shape, t, ps = W.slab(2, 2, 32, 1, 0.05, -0.05)
     g, q = steady_charge(shape, t, ps, 4.0, 0.05, 20000, precision=lbe.FP32_MIXED)
     qq = q[:, 0] / 4  # per column
     assert abs(qq[0] / (T.dielectric_slab_capacitance(LB, 32) * 0.1) - 1) < 1e-6
     d = qq[-1] - qq
     tt = np.arange(qq.size)
-    m = (d < 0.2 * d[0]) & (d > 1e-4 * d[0])
+    m = (d < 0.2 * d[0]) & (d > 1e-2 * d[0])
     tau = -1 / np.polyfit(tt[m], np.log(d[m]), 1)[0]
     assert abs(tau * T.charging_rate_slab(4.0, 32.0, 0.05) - 1) < 0.03
     assert abs(qq[-1] / 0.1 / T.dh_slab_capacitance(LB, 4.0, 32.0) - 1) < 0.015
