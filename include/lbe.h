@@ -183,6 +183,47 @@ int lbe_poisson(lbe_ctx *ctx, int32_t *iters, double *resid);
  */
 int lbe_set_electrode_potential(lbe_ctx *ctx, const double *phi_s);
 
+/*
+ * Reverse mode (gradients of the electrode charge), FP64 form only.
+ *
+ * lbe_record advances nsteps time steps exactly as lbe_step does and keeps,
+ * in device memory owned by the context, a checkpoint of the state (stored
+ * populations, concentrations, potential, and phi(t-1) under
+ * LBE_EXTRAPOLATE) at the first step and every `every` steps after it, plus
+ * the final state: ceil(nsteps/every) + 1 states of (19 + nspecies + 1) N
+ * doubles (one more N with LBE_EXTRAPOLATE).  It replaces an earlier record.
+ * Errors: LBE_EINVAL for nsteps < 0, every < 1 or an LBE_FP32_MIXED
+ * context; LBE_ENOMEM; the errors of lbe_step (then no record is kept).
+ *
+ * lbe_adjoint returns the gradient of L = sum_e qbar[e] Q_e(t1), with Q_e
+ * the charges of Eq. 16 at the end t1 of the record (qbar: nelectrodes
+ * weights), with respect to
+ *   grad_phi_s (N): the potential of every solid node (0 on fluid nodes;
+ *     the derivative with respect to one electrode's voltage is the sum
+ *     over its nodes);
+ *   grad_lB (1 value): the Bjerrum length;
+ *   grad_n (nspecies*N): the concentrations at the start t0 of the record;
+ *   grad_f (19*N): the pre-collision populations at t0 (the layout of
+ *     lbe_init's f_init).
+ * Host buffers; any of the four may be NULL.  The derivative is that of the
+ * discrete step, taken backwards: streaming and collision (Eq. 8), the link
+ * fluxes and the force they exert (Eqs. 9-10), and Poisson (Eqs. 13-15),
+ * whose fluid-node operator is symmetric, so each reverse step solves one
+ * more Poisson problem with the context's solver, stopped at the same
+ * residual tolerance.  The states between checkpoints are recomputed (one
+ * more forward pass in all), which takes min(every, nsteps) more states of
+ * (19 + nspecies + 1) N doubles and 2 (19 + nspecies) N + 8 N more.  The
+ * context is left at t1, and the record stays valid for further calls with
+ * other weights until the state moves (lbe_step, lbe_record,
+ * lbe_set_electrode_potential).
+ * Errors: LBE_EINVAL for NULL qbar, a non-finite weight, no valid record, no
+ * electrode or l_B = 0; LBE_ENOMEM; LBE_ENOCONV / LBE_ENONFINITE from a
+ * recomputed step or an adjoint solve.
+ */
+int lbe_record(lbe_ctx *ctx, int64_t nsteps, int32_t every);
+int lbe_adjoint(lbe_ctx *ctx, const double *qbar, double *grad_phi_s, double *grad_lB,
+                double *grad_n, double *grad_f);
+
 /* Charge of each electrode, in units of e, from Gauss's law on the current
  * potential (Eq. 16 with the Laplacian of Eq. 15 taken on the electrode's
  * solid nodes, the difference doubled on each solid-fluid link).

@@ -25,7 +25,7 @@ KRYLOV = 8
 # public entry points of include/lbe.h
 ENTRY_POINTS = (
     "lbe_init", "lbe_init_batch", "lbe_step", "lbe_poisson", "lbe_set_electrode_potential",
-    "lbe_electrode_charge", "lbe_observables",
+    "lbe_record", "lbe_adjoint", "lbe_electrode_charge", "lbe_observables",
     "lbe_destroy", "lbe_strerror", "lbe_last_error", "lbe_profile", "lbe_kernel_times",
     "lbe_kernel_name", "lbe_num_kernel_kinds", "lbe_velocities",
 )
@@ -88,6 +88,10 @@ def load(path: str = LIB_PATH):
     lib.lbe_poisson.restype = C.c_int
     lib.lbe_set_electrode_potential.argtypes = [C.c_void_p, d]
     lib.lbe_set_electrode_potential.restype = C.c_int
+    lib.lbe_record.argtypes = [C.c_void_p, C.c_int64, C.c_int32]
+    lib.lbe_record.restype = C.c_int
+    lib.lbe_adjoint.argtypes = [C.c_void_p, d, d, d, d, d]
+    lib.lbe_adjoint.restype = C.c_int
     lib.lbe_electrode_charge.argtypes = [C.c_void_p, d, C.c_int32]
     lib.lbe_electrode_charge.restype = C.c_int
     lib.lbe_observables.argtypes = [C.c_void_p, P(Obs), d, d, d, d, d, C.c_int64, P(C.c_int64)]
@@ -233,6 +237,35 @@ class Lbe:
         if ps.size != self.N:
             raise ValueError("phi_s must have one entry per lattice site")
         self._check(self._lib.lbe_set_electrode_potential(self.h, _dptr(ps)))
+
+    def record(self, nsteps, every=64):
+        """Advance nsteps steps keeping checkpoints every `every` steps for
+        adjoint() (FP64 form)."""
+        self._check(self._lib.lbe_record(self.h, int(nsteps), int(every)))
+
+    def adjoint(self, qbar, phi_s=True, lB=True, n=True, f=True):
+        """Gradient of sum_e qbar[e] Q_e at the end of the record: dict with
+        phi_s (N), lB (float), n (K, N) at the record's start and f (19, N),
+        the pre-collision populations at its start (each only if asked)."""
+        qb = np.ascontiguousarray(qbar, dtype=np.float64).reshape(-1)
+        if qb.size != self.ne:
+            raise ValueError("one weight per electrode")
+        g_ps = np.empty(self.N) if phi_s else None
+        g_lb = np.zeros(1) if lB else None
+        g_n = np.empty(self.K * self.N) if n else None
+        g_f = np.empty(19 * self.N) if f else None
+        self._check(self._lib.lbe_adjoint(self.h, _dptr(qb), _dptr(g_ps), _dptr(g_lb), _dptr(g_n),
+                                          _dptr(g_f)))
+        out = {}
+        if phi_s:
+            out["phi_s"] = g_ps
+        if lB:
+            out["lB"] = float(g_lb[0])
+        if n:
+            out["n"] = g_n.reshape(self.K, self.N)
+        if f:
+            out["f"] = g_f.reshape(19, self.N)
+        return out
 
     def electrode_charge(self):
         q = np.zeros(max(self.ne, 1))

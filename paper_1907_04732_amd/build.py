@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbe.so")
-SOURCES = ["lbe_kernels.hip", "lbe_kernels_f32.hip", "lbe_mg.hip", "lbe_capi.cpp"]
+SOURCES = ["lbe_kernels.hip", "lbe_kernels_f32.hip", "lbe_mg.hip", "lbe_adjoint.hip", "lbe_capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,365 @@
+// lbe_adjoint.hip -- reverse-mode (adjoint) kernels of the FP64 time step
+// (gfx950).  They give the gradient of a weighted sum of electrode charges
+// L = sum_e qbar_e Q_e(T) (Eq. 16) with respect to the electrode potentials,
+// the Bjerrum length and the initial state, by running the step of
+// Secs. II B-C backwards.
+//
+// State at time t: stored (post-collision, pull-form) populations P_t, ion
+// concentrations n_t, and phi_t = Phi(n_t), the Poisson solution for n_t.
+// Adjoint state: A_t = dL/d(pre-collision populations at t) and
+// nb_t = dL/dn_t with phi_t's dependence on n_t already folded in.
+//
+// One reverse step t+1 -> t (the state at t is recomputed from a checkpoint):
+//  1. k_adj_fluid: the adjoint of streaming (a gather of A_{t+1} along +c_i,
+//     or the node's own opposite slot across a wall), of the BGK collision
+//     with the Guo source, and of u = (m + F/2)/rho; the velocity also feeds
+//     the advective link fluxes, whose share of the velocity adjoint is
+//     gathered here.  Writes A_t, the force adjoint Fb and u.
+//  2. k_adj_ions: the adjoint of the link fluxes of Eq. 10 (diffusion,
+//     migration, advection) and of the force they exert, per link pair:
+//     both ends of a fluid link see the same flux with opposite signs, so the
+//     pair's adjoint is  Gb_k = d_k (nb_k(r') - nb_k(r)) + 3 w_i Delta_i
+//     c_i . (Fb(r) + Fb(r')),  and each end takes its own partial
+//     derivatives.  Writes nb_t (before the fold) and the Poisson adjoint's
+//     source from the potential adjoint phib.
+//  3. the Poisson adjoint: the fluid-node operator of Eq. 15 is symmetric, so
+//     lambda solves L_h lambda = phib with zero wall values, by the same
+//     solver as the forward step.
+//  4. k_adj_fold: nb_k += -4 pi l_B z_k lambda; sums lambda over time (the
+//     electrode potentials enter Poisson linearly, so their gradient is one
+//     gather of that sum at the end) and lambda . rho_el for d/dl_B.
+#include <math.h>
+
+#include "lbe_device.h"
+#include "lbe_internal.h"
+
+namespace lbe {
+namespace {
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_adj_fluid(Lattice L, Phys P,
+                                                     const uint32_t *__restrict__ mask,
+                                                     const double *__restrict__ phi,
+                                                     const double *__restrict__ n,
+                                                     const double *__restrict__ fin,
+                                                     const double *__restrict__ abar_in,
+                                                     const double *__restrict__ nbar_in,
+                                                     double *__restrict__ abar_out,
+                                                     double *__restrict__ fbar,
+                                                     double *__restrict__ u) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) return;
+  const int N = L.n;
+  Offs o;
+  site_offsets(L, r, o);
+  const double ph = phi[r];
+  double nr[K], nbr_r[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    nr[k] = n[k * N + r];
+    nbr_r[k] = nbar_in[k * N + r];
+  }
+  // force of the link fluxes (as in pass A) and the advective flux's share
+  // of the velocity adjoint: sum_i 3 w_i c_i sum_k (nb_k(r') - nb_k(r)) n_k(r)
+  double F0 = 0.0, F1 = 0.0, F2 = 0.0, V0 = 0.0, V1 = 0.0, V2 = 0.0;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;
+    const int rn = nbr(o, r, i);
+    const double dphi = phi[rn] - ph - P.Ec[i];
+    double S1, C1;
+    sinh_coshm1(dphi, S1, C1);
+    double g = 0.0, adv = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double nt = n[k * N + rn];
+      double S, C;
+      valence_sc(P.z[k], dphi, S1, C1, S, C);
+      g += -((nt + nr[k]) * S + (nt - nr[k]) * C) * (0.5 / LEN[i]);
+      adv += (nbar_in[k * N + rn] - nbr_r[k]) * nr[k];
+    }
+    const double c = 3.0 * WQ[i] * LEN[i] * g;
+    const double a = 3.0 * WQ[i] * adv;
+    if (CX[i]) { F0 += CX[i] * c; V0 += CX[i] * a; }
+    if (CY[i]) { F1 += CY[i] * c; V1 += CY[i] * a; }
+    if (CZ[i]) { F2 += CZ[i] * c; V2 += CZ[i] * a; }
+  }
+  double f[NQ];
+  pull(L, r, m, o, fin, f);
+  double rho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    rho += f[i];
+    if (CX[i]) m0 += CX[i] * f[i];
+    if (CY[i]) m1 += CY[i] * f[i];
+    if (CZ[i]) m2 += CZ[i] * f[i];
+  }
+  const double irho = 1.0 / rho;
+  const double ux = (m0 + 0.5 * F0) * irho;
+  const double uy = (m1 + 0.5 * F1) * irho;
+  const double uz = (m2 + 0.5 * F2) * irho;
+  const double uu = ux * ux + uy * uy + uz * uz;
+  // adjoint of the collision output: transposed streaming
+  double pb[NQ];
+  pb[0] = abar_in[r];
+#pragma unroll
+  for (int i = 1; i < NQ; ++i)
+    pb[i] = solid_link(m, i) ? abar_in[OPP[i] * N + r] : abar_in[i * N + nbr(o, r, i)];
+  // moments of a_i = pb_i w_i that the collision's derivatives need
+  double s0 = 0.0, re = 0.0;
+  double s1x = 0.0, s1y = 0.0, s1z = 0.0, sux = 0.0, suy = 0.0, suz = 0.0;
+  double sfx = 0.0, sfy = 0.0, sfz = 0.0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const double a = pb[i] * WQ[i];
+    const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+    const double cF = CX[i] * F0 + CY[i] * F1 + CZ[i] * F2;
+    s0 += a;
+    re += a * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    if (CX[i]) { s1x += CX[i] * a; sux += CX[i] * a * cu; sfx += CX[i] * a * cF; }
+    if (CY[i]) { s1y += CY[i] * a; suy += CY[i] * a * cu; sfy += CY[i] * a * cF; }
+    if (CZ[i]) { s1z += CZ[i] * a; suz += CZ[i] * a * cu; sfz += CZ[i] * a * cF; }
+  }
+  const double beta = 1.0 / P.tau;
+  const double gam = 1.0 - 0.5 * beta;
+  // d(feq_i)/du and d(source_i)/dF share G = 3 s1 + 9 su - 3 u s0
+  const double Gx = 3.0 * s1x + 9.0 * sux - 3.0 * ux * s0;
+  const double Gy = 3.0 * s1y + 9.0 * suy - 3.0 * uy * s0;
+  const double Gz = 3.0 * s1z + 9.0 * suz - 3.0 * uz * s0;
+  const double ubx = beta * rho * Gx + gam * (9.0 * sfx - 3.0 * F0 * s0) + V0;
+  const double uby = beta * rho * Gy + gam * (9.0 * sfy - 3.0 * F1 * s0) + V1;
+  const double ubz = beta * rho * Gz + gam * (9.0 * sfz - 3.0 * F2 * s0) + V2;
+  // u = (m + F/2) / rho
+  const double mbx = ubx * irho, mby = uby * irho, mbz = ubz * irho;
+  const double rhob = beta * re - (ubx * ux + uby * uy + ubz * uz) * irho;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i)
+    abar_out[i * N + r] = (1.0 - beta) * pb[i] + rhob + (CX[i] * mbx + CY[i] * mby + CZ[i] * mbz);
+  fbar[r] = gam * Gx + 0.5 * mbx;
+  fbar[N + r] = gam * Gy + 0.5 * mby;
+  fbar[2 * N + r] = gam * Gz + 0.5 * mbz;
+  u[r] = ux;
+  u[N + r] = uy;
+  u[2 * N + r] = uz;
+}
+
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_adj_ions(Lattice L, Phys P,
+                                                    const uint32_t *__restrict__ mask,
+                                                    const double *__restrict__ phi,
+                                                    const double *__restrict__ n,
+                                                    const double *__restrict__ u,
+                                                    const double *__restrict__ fbar,
+                                                    const double *__restrict__ nbar_in,
+                                                    double *__restrict__ nbar_out,
+                                                    double *__restrict__ src) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) return;
+  const int N = L.n;
+  Offs o;
+  site_offsets(L, r, o);
+  const double ph = phi[r];
+  const double ux = u[r], uy = u[N + r], uz = u[2 * N + r];
+  const double fx = fbar[r], fy = fbar[N + r], fz = fbar[2 * N + r];
+  double nr[K], nbr_r[K], acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    nr[k] = n[k * N + r];
+    nbr_r[k] = nbar_in[k * N + r];
+    acc[k] = 0.0;
+  }
+  double phib = 0.0;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;
+    const int rn = nbr(o, r, i);
+    const double dphi = phi[rn] - ph - P.Ec[i];
+    double S1, C1;
+    sinh_coshm1(dphi, S1, C1);
+    double fs = 0.0, cu = 0.0;
+    if (CX[i]) { fs += CX[i] * (fx + fbar[rn]); cu += CX[i] * ux; }
+    if (CY[i]) { fs += CY[i] * (fy + fbar[N + rn]); cu += CY[i] * uy; }
+    if (CZ[i]) { fs += CZ[i] * (fz + fbar[2 * N + rn]); cu += CZ[i] * uz; }
+    const double h = 0.5 / LEN[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double nt = n[k * N + rn];
+      double S, C;
+      valence_sc(P.z[k], dphi, S1, C1, S, C);
+      const double pbk = nbar_in[k * N + rn] - nbr_r[k];
+      const double gb = P.dk[k] * pbk + 3.0 * WQ[i] * LEN[i] * fs;
+      // d g / d n(r) = expm1(-delta) / (2 Delta); ideal and advective parts
+      acc[k] += gb * (C - S) * h + P.dk[k] * pbk / LEN[i] + pbk * 3.0 * WQ[i] * cu;
+      // -z d g / d delta = z [n' e^delta + n e^-delta] / (2 Delta)
+      phib += gb * P.z[k] * (nt * (1.0 + C + S) + nr[k] * (1.0 + C - S)) * h;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) nbar_out[k * N + r] = nbr_r[k] + acc[k];
+  // the solver zeroes 6 [sum_i w_i s_i (lambda' - lambda) + src]
+  src[r] = -phib / 6.0;
+}
+
+// nb_k += -4 pi l_B z_k lambda; lam_sum += lambda; lam_keep = lambda (warm
+// start of the next adjoint solve); block sums of lambda . rho_el
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_adj_fold(Lattice L, Phys P,
+                                                    const uint32_t *__restrict__ mask,
+                                                    const double *__restrict__ lam,
+                                                    const double *__restrict__ n,
+                                                    double *__restrict__ nbar,
+                                                    double *__restrict__ lam_sum,
+                                                    double *__restrict__ lam_keep,
+                                                    double *__restrict__ partial) {
+  __shared__ double sm[BLOCK / WAVE];
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int N = L.n;
+  double v = 0.0;
+  if (r < N && !(mask[r] & SOLID_BIT)) {
+    const double l = lam[r];
+    const double s = -6.0 * P.src_scale * l;  // -4 pi l_B lambda
+    double q = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      q += P.z[k] * n[k * N + r];
+      nbar[k * N + r] += s * P.z[k];
+    }
+    lam_sum[r] += l;
+    lam_keep[r] = l;
+    v = l * q;
+  }
+  v = block_sum(v, sm);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+// acc[0] += scale * sum of partial[0..nb) (fixed order)
+__global__ __launch_bounds__(BLOCK) void k_adj_accumulate(const double *__restrict__ partial,
+                                                          int nb, double scale,
+                                                          double *__restrict__ acc) {
+  __shared__ double tree[BLOCK];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += BLOCK) v += partial[b];
+  tree[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) acc[0] += scale * tree[0];
+}
+
+// Seed of the reverse sweep, L = sum_e qbar_e Q_e:
+//  fluid r:  dL/dphi(r) = q_scale wall sum over links to an electrode node r'
+//            of w_i qbar_{e(r')}, stored as the adjoint solve's source -phib/6;
+//  solid r:  the explicit derivative -q_scale wall qbar_e sum over links to
+//            fluid nodes of w_i (phi_s(r) enters Eq. 16 directly).
+__global__ __launch_bounds__(BLOCK) void k_adj_seed(Lattice L, double q_scale,
+                                                    const uint32_t *__restrict__ mask,
+                                                    const uint8_t *__restrict__ type,
+                                                    const double *__restrict__ qbar,
+                                                    double *__restrict__ src,
+                                                    double *__restrict__ gphis) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  Offs o;
+  site_offsets(L, r, o);
+  double acc = 0.0;
+  if (m & SOLID_BIT) {
+    for (int i = 1; i < NQ; ++i)
+      if (!solid_link(m, i)) acc += WQ[i];
+    gphis[r] = -q_scale * L.wall * qbar[type[r] - 1] * acc;
+    src[r] = 0.0;
+    return;
+  }
+  for (int i = 1; i < NQ; ++i)
+    if (solid_link(m, i)) acc += WQ[i] * qbar[type[nbr(o, r, i)] - 1];
+  gphis[r] = 0.0;
+  src[r] = -(q_scale * L.wall * acc) / 6.0;
+}
+
+// gphis(r) += -6 wall sum over links to fluid nodes r' of w_i lam_sum(r'):
+// the transpose of the wall term that phi_s contributes to Eq. 15
+__global__ __launch_bounds__(BLOCK) void k_adj_phis(Lattice L, const uint32_t *__restrict__ mask,
+                                                    const double *__restrict__ lam_sum,
+                                                    double *__restrict__ gphis) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  if (!(m & SOLID_BIT)) return;
+  Offs o;
+  site_offsets(L, r, o);
+  double acc = 0.0;
+  for (int i = 1; i < NQ; ++i)
+    if (!solid_link(m, i)) acc += WQ[i] * lam_sum[nbr(o, r, i)];
+  gphis[r] += -6.0 * L.wall * acc;
+}
+
+}  // namespace
+
+#define LBE_DISPATCH_K(K, CALL) \
+  switch (K) {                  \
+    case 1: CALL(1); break;     \
+    case 2: CALL(2); break;     \
+    case 3: CALL(3); break;     \
+    default: CALL(4); break;    \
+  }
+
+hipError_t launch_adj_fluid(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                            const double *phi, const double *n, const double *fin,
+                            const double *abar_in, const double *nbar_in, double *abar_out,
+                            double *fbar, double *u) {
+#define CALL(KK)                                                                               \
+  hipLaunchKernelGGL(k_adj_fluid<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, \
+                     n, fin, abar_in, nbar_in, abar_out, fbar, u)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_ions(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                           const double *phi, const double *n, const double *u,
+                           const double *fbar, const double *nbar_in, double *nbar_out,
+                           double *src) {
+#define CALL(KK)                                                                              \
+  hipLaunchKernelGGL(k_adj_ions<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, \
+                     n, u, fbar, nbar_in, nbar_out, src)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_fold(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                           const double *lam, const double *n, double *nbar, double *lam_sum,
+                           double *lam_keep, double *partial, double *lb_acc) {
+  const int nb = (int)blocks_for(L.n);
+#define CALL(KK)                                                                          \
+  hipLaunchKernelGGL(k_adj_fold<KK>, dim3(nb), dim3(BLOCK), 0, s, L, P, mask, lam, n, nbar, \
+                     lam_sum, lam_keep, partial)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  // dL/dl_B gathers -4 pi lambda . rho_el from every reverse step
+  hipLaunchKernelGGL(k_adj_accumulate, dim3(1), dim3(BLOCK), 0, s, partial, nb, -4.0 * M_PI,
+                     lb_acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_seed(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
+                           const uint8_t *type, const double *qbar, double *src, double *gphis) {
+  hipLaunchKernelGGL(k_adj_seed, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, q_scale, mask, type,
+                     qbar, src, gphis);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_phis(hipStream_t s, const Lattice &L, const uint32_t *mask,
+                           const double *lam_sum, double *gphis) {
+  hipLaunchKernelGGL(k_adj_phis, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, mask, lam_sum,
+                     gphis);
+  return hipGetLastError();
+}
+
+}  // namespace lbe

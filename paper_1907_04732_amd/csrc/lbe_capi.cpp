@@ -91,6 +91,29 @@ struct lbe_ctx {
   MgSmall mg_small{};
   size_t mg_small_lds = 0;
 
+  // reverse mode: checkpoints kept by lbe_record, buffers of lbe_adjoint
+  struct Tape {
+    int64_t t0 = -1;      // step at which the recorded steps start (-1: none)
+    int64_t nsteps = 0;
+    int every = 1;        // steps between checkpoints
+    int nck = 0;          // checkpoints at t0, t0 + every, ...; slot nck holds the end state
+    int cap = 0;          // checkpoint slots allocated
+    size_t ck_len = 0;    // doubles per checkpoint: f, n, phi (and phi_prev)
+    double *ck = nullptr;
+    double *seg = nullptr;  // the states of one segment, recomputed (f, n, phi per slot)
+    int seg_cap = 0;
+  } tape;
+  double *abar[2] = {nullptr, nullptr};  // adjoint of the pre-collision populations
+  double *nbar[2] = {nullptr, nullptr};  // adjoint of the concentrations
+  double *fbar = nullptr;      // adjoint of the force (3 N)
+  double *lam = nullptr;       // last Poisson adjoint (warm start; zero on solid nodes)
+  double *lam_sum = nullptr;   // Poisson adjoints summed over the reverse steps
+  double *gphis = nullptr;     // gradient with respect to phi_s
+  double *src_keep = nullptr;  // the forward Poisson source, restored after the sweep
+  double *qbar_d = nullptr, *lb_acc = nullptr;
+  uint8_t *type_d = nullptr;
+  int adj_pred = 0;  // iterations the last adjoint solve needed
+
   // statistics
   int64_t step = 0;
   int last_iters = 0;
@@ -981,7 +1004,9 @@ int record_charge(lbe_ctx *c) {
   return LBE_OK;
 }
 
-int one_step(lbe_ctx *c) {
+// record = false: a replay of a recorded step (reverse mode), which neither
+// counts the step nor appends its charge
+int one_step(lbe_ctx *c, bool record = true) {
   const int a = c->cur, b = 1 - c->cur;
   int rc = run(c, KK_FLUID, c->L.n, [&] {
     if (c->mixed)
@@ -999,7 +1024,7 @@ int one_step(lbe_ctx *c) {
   });
   if (rc) return rc;
   c->cur = b;
-  c->step++;
+  if (record) c->step++;
   if (c->phi_prev) {
     rc = run(c, KK_EXTRAP, c->L.n, [&] {
       return launch_extrapolate(c->stream, c->L, c->mask, c->phi, c->phi_prev);
@@ -1008,7 +1033,171 @@ int one_step(lbe_ctx *c) {
   }
   rc = poisson_solve(c, true);
   if (rc) return rc;
-  return record_charge(c);
+  return record ? record_charge(c) : LBE_OK;
+}
+
+// ---- reverse mode -----------------------------------------------------------
+
+// copy the state (stored populations, n, phi, and phi_prev when extrapolating
+// and `prev`) to / from device memory laid out as consecutive arrays
+int save_state(lbe_ctx *c, double *dst, bool prev) {
+  const size_t N = c->L.n, K = c->K;
+  HIPCHK(c, hipMemcpyAsync(dst, c->f[c->cur], sizeof(double) * NQ * N, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(dst + NQ * N, c->n[c->cur], sizeof(double) * K * N,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dst + (NQ + K) * N, c->phi, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (prev && c->phi_prev)
+    HIPCHK(c, hipMemcpyAsync(dst + (NQ + K + 1) * N, c->phi_prev, sizeof(double) * N,
+                             hipMemcpyDeviceToDevice, c->stream));
+  return LBE_OK;
+}
+
+int load_state(lbe_ctx *c, const double *src) {
+  const size_t N = c->L.n, K = c->K;
+  HIPCHK(c, hipMemcpyAsync(c->f[c->cur], src, sizeof(double) * NQ * N, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->n[c->cur], src + NQ * N, sizeof(double) * K * N,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->phi, src + (NQ + K) * N, sizeof(double) * N, hipMemcpyDeviceToDevice,
+                           c->stream));
+  if (c->phi_prev)
+    HIPCHK(c, hipMemcpyAsync(c->phi_prev, src + (NQ + K + 1) * N, sizeof(double) * N,
+                             hipMemcpyDeviceToDevice, c->stream));
+  return LBE_OK;
+}
+
+int adjoint_buffers(lbe_ctx *c) {
+  const size_t N = c->L.n, K = c->K;
+  if (!c->fbar) {
+    int rc;
+    for (int s = 0; s < 2; ++s) {
+      if ((rc = dalloc(c, &c->abar[s], NQ * N))) return rc;
+      if ((rc = dalloc(c, &c->nbar[s], K * N))) return rc;
+    }
+    if ((rc = dalloc(c, &c->lam, N)) || (rc = dalloc(c, &c->lam_sum, N)) ||
+        (rc = dalloc(c, &c->gphis, N)) || (rc = dalloc(c, &c->src_keep, N)) ||
+        (rc = dalloc(c, &c->qbar_d, std::max(c->ne, 1))) || (rc = dalloc(c, &c->lb_acc, 1)) ||
+        (rc = dalloc(c, &c->type_d, N)))
+      return rc;
+    HIPCHK(c, hipMemcpyAsync(c->type_d, c->type_h.data(), N, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // fbar is allocated last: its presence marks the set complete
+    if ((rc = dalloc(c, &c->fbar, 3 * N))) return rc;
+  }
+  const int slots = (int)std::min<int64_t>(c->tape.every, std::max<int64_t>(c->tape.nsteps, 1));
+  if (c->tape.seg_cap < slots) {
+    if (c->tape.seg) (void)hipFree(c->tape.seg);
+    c->tape.seg = nullptr;
+    c->tape.seg_cap = 0;
+    int rc = dalloc(c, &c->tape.seg, (size_t)slots * (NQ + K + 1) * N);
+    if (rc) return rc;
+    c->tape.seg_cap = slots;
+  }
+  return LBE_OK;
+}
+
+// Poisson adjoint: L_h lambda = phib with zero wall values; phib arrives as
+// the source -phib/6 in c->src, the warm start in c->lam.  Leaves lambda in
+// c->phi.  Keeps its own iteration count for the queue of the next adjoint
+// solve.
+int adjoint_solve(lbe_ctx *c) {
+  HIPCHK(c, hipMemcpyAsync(c->phi, c->lam, sizeof(double) * c->L.n, hipMemcpyDeviceToDevice,
+                           c->stream));
+  std::swap(c->pred_iters, c->adj_pred);
+  const int rc = poisson_solve(c, true);
+  std::swap(c->pred_iters, c->adj_pred);
+  return rc;
+}
+
+int adjoint_fold(lbe_ctx *c, const double *n, double *nbar) {
+  return run(c, KK_ADJ_FOLD, c->L.n, [&] {
+    return launch_adj_fold(c->stream, c->L, c->P, c->mask, c->phi, n, nbar, c->lam_sum, c->lam,
+                           c->partial, c->lb_acc);
+  });
+}
+
+// The reverse sweep of lbe_adjoint; the caller restores the end state.
+int adjoint_sweep(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *grad_lB,
+                  double *grad_n, double *grad_f) {
+  lbe_ctx::Tape &T = c->tape;
+  const size_t N = c->L.n, K = c->K;
+  const size_t slot_len = (NQ + K + 1) * N;
+  int rc;
+  int cur = 0;
+  HIPCHK(c, hipMemsetAsync(c->abar[0], 0, sizeof(double) * NQ * N, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->abar[1], 0, sizeof(double) * NQ * N, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->nbar[0], 0, sizeof(double) * K * N, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->nbar[1], 0, sizeof(double) * K * N, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->lam, 0, sizeof(double) * N, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->lam_sum, 0, sizeof(double) * N, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->lb_acc, 0, sizeof(double), c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->qbar_d, qbar, sizeof(double) * c->ne, hipMemcpyHostToDevice,
+                           c->stream));
+  // dQ_e/dl_B = -Q_e / l_B at fixed potential (Eq. 16)
+  std::vector<double> qend(c->ne);
+  HIPCHK(c, hipMemcpyAsync(qend.data(), c->qhist + (c->qlen - 1) * c->ne,
+                           sizeof(double) * c->ne, hipMemcpyDeviceToHost, c->stream));
+  const double q_scale = -6.0 / (4.0 * M_PI * c->p.lB);
+  if ((rc = run(c, KK_ADJ_SEED, c->L.n, [&] {
+         return launch_adj_seed(c->stream, c->L, q_scale, c->mask, c->type_d, c->qbar_d, c->src,
+                                c->gphis);
+       })))
+    return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // qbar and qend
+  double lb_explicit = 0.0;
+  for (int e = 0; e < c->ne; ++e) lb_explicit -= qbar[e] * qend[e] / c->p.lB;
+  // phi(T) depends on n(T): fold its adjoint in
+  if ((rc = adjoint_solve(c))) return rc;
+  if ((rc = adjoint_fold(c, c->n[c->cur], c->nbar[cur]))) return rc;
+  for (int sg = T.nck - 1; sg >= 0; --sg) {
+    const int64_t a = (int64_t)sg * T.every;
+    const int64_t b = std::min<int64_t>(a + T.every, T.nsteps);
+    if ((rc = load_state(c, T.ck + (size_t)sg * T.ck_len))) return rc;
+    for (int64_t t = a; t < b; ++t) {
+      if ((rc = save_state(c, T.seg + (size_t)(t - a) * slot_len, false))) return rc;
+      if (t + 1 < b && (rc = one_step(c, false))) return rc;
+    }
+    for (int64_t t = b - 1; t >= a; --t) {
+      const double *fs = T.seg + (size_t)(t - a) * slot_len;
+      const double *ns = fs + NQ * N;
+      const double *ps = ns + K * N;
+      const int nxt = 1 - cur;
+      if ((rc = run(c, KK_ADJ_FLUID, c->L.n, [&] {
+             return launch_adj_fluid(c->stream, c->L, c->P, c->mask, ps, ns, fs, c->abar[cur],
+                                     c->nbar[cur], c->abar[nxt], c->fbar, c->u);
+           })))
+        return rc;
+      if ((rc = run(c, KK_ADJ_IONS, c->L.n, [&] {
+             return launch_adj_ions(c->stream, c->L, c->P, c->mask, ps, ns, c->u, c->fbar,
+                                    c->nbar[cur], c->nbar[nxt], c->src);
+           })))
+        return rc;
+      if ((rc = adjoint_solve(c))) return rc;
+      if ((rc = adjoint_fold(c, ns, c->nbar[nxt]))) return rc;
+      cur = nxt;
+    }
+  }
+  if ((rc = run(c, KK_ADJ_SEED, c->L.n, [&] {
+         return launch_adj_phis(c->stream, c->L, c->mask, c->lam_sum, c->gphis);
+       })))
+    return rc;
+  double lb_sweep = 0.0;
+  HIPCHK(c, hipMemcpyAsync(&lb_sweep, c->lb_acc, sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
+  if (grad_phi_s)
+    HIPCHK(c, hipMemcpyAsync(grad_phi_s, c->gphis, sizeof(double) * N, hipMemcpyDeviceToHost,
+                             c->stream));
+  if (grad_n)
+    HIPCHK(c, hipMemcpyAsync(grad_n, c->nbar[cur], sizeof(double) * K * N, hipMemcpyDeviceToHost,
+                             c->stream));
+  if (grad_f)
+    HIPCHK(c, hipMemcpyAsync(grad_f, c->abar[cur], sizeof(double) * NQ * N,
+                             hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (grad_lB) *grad_lB = lb_explicit + lb_sweep;
+  return LBE_OK;
 }
 
 void free_ctx(lbe_ctx *c) {
@@ -1018,7 +1207,10 @@ void free_ctx(lbe_ctx *c) {
                   c->h32[0], c->h32[1], c->nu32[0], c->nu32[1], c->u32, c->obs,
                   c->partial, c->dout, c->ctl, c->iface, c->blk_elec, c->blk_begin,
                   c->blk_end, c->qcur, c->qhist, c->solid_idx, c->solid_val,
-                  c->nref_d_tab, c->qref_tab, c->nref_f_tab, c->kr, c->kp, c->kq, c->kc};
+                  c->nref_d_tab, c->qref_tab, c->nref_f_tab, c->kr, c->kp, c->kq, c->kc,
+                  c->tape.ck, c->tape.seg, c->abar[0], c->abar[1], c->nbar[0], c->nbar[1],
+                  c->fbar, c->lam, c->lam_sum, c->gphis, c->src_keep, c->qbar_d, c->lb_acc,
+                  c->type_d};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   for (auto &L : c->mg) {
@@ -1407,6 +1599,73 @@ int lbe_step(lbe_ctx *c, int64_t nsteps) {
   return LBE_OK;
 }
 
+int lbe_record(lbe_ctx *c, int64_t nsteps, int32_t every) {
+  if (!c || nsteps < 0 || every < 1)
+    return fail(c, LBE_EINVAL, "bad context, step count or checkpoint interval");
+  if (c->mixed) return fail(c, LBE_EINVAL, "reverse mode needs the FP64 form");
+  lbe_ctx::Tape &T = c->tape;
+  T.t0 = -1;
+  const size_t N = c->L.n;
+  const size_t ck_len = (NQ + c->K + 1 + (c->phi_prev ? 1 : 0)) * N;
+  const int64_t nck = (nsteps + every - 1) / every;
+  if (nck + 1 > (int64_t)INT32_MAX) return fail(c, LBE_EINVAL, "too many checkpoints");
+  if (T.cap < nck + 1) {
+    if (T.ck) (void)hipFree(T.ck);
+    T.ck = nullptr;
+    T.cap = 0;
+    int rc = dalloc(c, &T.ck, (size_t)(nck + 1) * ck_len);
+    if (rc) return rc;
+    T.cap = (int)(nck + 1);
+  }
+  T.ck_len = ck_len;
+  for (int64_t t = 0; t < nsteps; ++t) {
+    int rc;
+    if (t % every == 0 && (rc = save_state(c, T.ck + (size_t)(t / every) * ck_len, true)))
+      return rc;
+    if ((rc = one_step(c))) return rc;
+  }
+  int rc = save_state(c, T.ck + (size_t)nck * ck_len, true);
+  if (rc) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  T.t0 = c->step - nsteps;
+  T.nsteps = nsteps;
+  T.every = every;
+  T.nck = (int)nck;
+  return LBE_OK;
+}
+
+int lbe_adjoint(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *grad_lB,
+                double *grad_n, double *grad_f) {
+  if (!c || !qbar) return fail(c, LBE_EINVAL, "bad arguments");
+  lbe_ctx::Tape &T = c->tape;
+  if (T.t0 < 0) return fail(c, LBE_EINVAL, "no recorded steps (lbe_record)");
+  if (c->step != T.t0 + T.nsteps || c->qlen < 1)
+    return fail(c, LBE_EINVAL, "the state is not the end of the recorded steps");
+  if (c->ne == 0) return fail(c, LBE_EINVAL, "no electrode charge to differentiate");
+  if (!(c->p.lB > 0.0)) return fail(c, LBE_EINVAL, "reverse mode needs l_B > 0");
+  for (int e = 0; e < c->ne; ++e)
+    if (!std::isfinite(qbar[e])) return fail(c, LBE_EINVAL, "non-finite charge weight");
+  int rc = adjoint_buffers(c);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->src_keep, c->src, sizeof(double) * c->L.n, hipMemcpyDeviceToDevice,
+                           c->stream));
+  const int keep_iters = c->last_iters, keep_pred = c->pred_iters;
+  const double keep_resid = c->last_resid;
+  const int64_t keep_total = c->total_iters;
+  rc = adjoint_sweep(c, qbar, grad_phi_s, grad_lB, grad_n, grad_f);
+  // back to the end of the recorded steps, whatever happened
+  const int rc2 = load_state(c, T.ck + (size_t)T.nck * T.ck_len);
+  if (rc2 == LBE_OK)
+    (void)hipMemcpyAsync(c->src, c->src_keep, sizeof(double) * c->L.n, hipMemcpyDeviceToDevice,
+                         c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  c->last_iters = keep_iters;
+  c->pred_iters = keep_pred;
+  c->last_resid = keep_resid;
+  c->total_iters = keep_total;
+  return rc ? rc : rc2;
+}
+
 int lbe_poisson(lbe_ctx *c, int32_t *iters, double *resid) {
   if (!c) return fail(c, LBE_EINVAL, "context is NULL");
   int rc = poisson_solve(c, false);
@@ -1434,6 +1693,7 @@ int lbe_set_electrode_potential(lbe_ctx *c, const double *phi_s) {
   }
   HIPCHK(c, hipMemcpyAsync(c->solid_val, val.data(), sizeof(double) * S, hipMemcpyHostToDevice,
                            c->stream));
+  c->tape.t0 = -1;  // a record of earlier potentials no longer matches the state
   HIPCHK(c, launch_scatter(c->stream, (int)S, c->solid_idx, c->solid_val, c->phi));
   HIPCHK(c, hipStreamSynchronize(c->stream));  // val leaves scope
   int rc = poisson_solve(c, false);

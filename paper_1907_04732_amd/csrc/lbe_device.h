@@ -49,6 +49,20 @@ __device__ __forceinline__ void gather(const Offs &o, int r, const T *__restrict
   for (int i = 1; i < NQ; ++i) v[i] = a[nbr(o, r, i)];
 }
 
+// gather pre-collision populations from the pull-form array (streaming with
+// halfway bounce-back): f_i(r) = stored_i(r - c_i), or the node's own
+// opposite slot when r - c_i is solid
+__device__ __forceinline__ void pull(const Lattice &L, int r, uint32_t m, const Offs &o,
+                                     const double *__restrict__ fin, double (&f)[NQ]) {
+  const int N = L.n;
+  f[0] = fin[r];
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    const int j = OPP[i];
+    f[i] = solid_link(m, j) ? fin[j * N + r] : fin[i * N + nbr(o, r, j)];
+  }
+}
+
 
 // NaN-propagating max
 __device__ __forceinline__ double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }

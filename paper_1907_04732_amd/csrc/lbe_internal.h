@@ -140,6 +140,10 @@ enum KernelKind {
   KK_FCG_DIR,     // Krylov: p = z + beta p
   KK_FCG_APPLY,   // Krylov: q = A p, (p, q), (r, p), alpha
   KK_FCG_UPDATE,  // Krylov: phi += alpha p, r -= alpha q, stop check
+  KK_ADJ_FLUID,   // reverse step: streaming, collision and velocity adjoints
+  KK_ADJ_IONS,    // reverse step: link-flux and force adjoints, Poisson-adjoint source
+  KK_ADJ_FOLD,    // reverse step: fold the Poisson adjoint into the ion adjoint
+  KK_ADJ_SEED,    // reverse sweep: seed from the charge weights; phi_s gradient
   KK_COUNT
 };
 
@@ -195,6 +199,27 @@ hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
                               const float *hin, double *fpre, double *u);
 hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                              const float *hin, const float *nu, double *partial, double *out);
+
+// reverse mode (lbe_adjoint.hip), FP64 form.  fin: the stored populations of
+// the state at t; abar_in/nbar_in: adjoints at t+1; writes the adjoints at t.
+hipError_t launch_adj_fluid(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                            const double *phi, const double *n, const double *fin,
+                            const double *abar_in, const double *nbar_in, double *abar_out,
+                            double *fbar, double *u);
+// writes nbar_out (before the Poisson fold) and src = -phib/6
+hipError_t launch_adj_ions(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                           const double *phi, const double *n, const double *u,
+                           const double *fbar, const double *nbar_in, double *nbar_out,
+                           double *src);
+// with lam the Poisson adjoint: nbar += -4 pi l_B z lam, lam_sum += lam,
+// lam_keep = lam, *lb_acc += -4 pi sum lam rho_el (partial: residual_blocks(L))
+hipError_t launch_adj_fold(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                           const double *lam, const double *n, double *nbar, double *lam_sum,
+                           double *lam_keep, double *partial, double *lb_acc);
+hipError_t launch_adj_seed(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
+                           const uint8_t *type, const double *qbar, double *src, double *gphis);
+hipError_t launch_adj_phis(hipStream_t s, const Lattice &L, const uint32_t *mask,
+                           const double *lam_sum, double *gphis);
 
 // multigrid (lbe_mg.hip); T = double (FP64 form) or float (mixed form)
 template <class T>

@@ -22,7 +22,8 @@ namespace lbe {
 const char *const kKernelNames[KK_COUNT] = {
     "fluid", "ions", "sor", "resid", "charge", "totals", "observe", "sor32", "correct",
     "mg_resid", "mg_smooth", "mg_smooth0", "mg_restrict", "mg_prolong", "mg_coarse", "extrap", "mg_small",
-    "fcg_beta", "fcg_dir", "fcg_apply", "fcg_update"};
+    "fcg_beta", "fcg_dir", "fcg_apply", "fcg_update", "adj_fluid", "adj_ions", "adj_fold",
+    "adj_seed"};
 
 namespace {
 
@@ -50,18 +51,6 @@ __device__ __forceinline__ void link_force(const Lattice &L, const Phys &P, int 
     if (CX[i]) F0 += CX[i] * c;
     if (CY[i]) F1 += CY[i] * c;
     if (CZ[i]) F2 += CZ[i] * c;
-  }
-}
-
-// gather pre-collision populations (streaming with halfway bounce-back)
-__device__ __forceinline__ void pull(const Lattice &L, int r, uint32_t m, const Offs &o,
-                                     const double *__restrict__ fin, double (&f)[NQ]) {
-  const int N = L.n;
-  f[0] = fin[r];
-#pragma unroll
-  for (int i = 1; i < NQ; ++i) {
-    const int j = OPP[i];
-    f[i] = solid_link(m, j) ? fin[j * N + r] : fin[i * N + nbr(o, r, j)];
   }
 }
 

@@ -75,3 +75,30 @@ def case(name):
 
 PARITY_CASES = ["slab_4x4x34", "slab_1x1x34", "coax_16x16x4", "random_6x10x14_k3",
                 "random_8x6x10_k4", "slab_2x2x18_k1"]
+
+
+def _rest(node_type, rho0=1.0):
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    return np.where(np.asarray(node_type).reshape(-1)[None, :] == 0, w[:, None] * rho0, 0.0)
+
+
+def adjoint_case(kind):
+    """Small cases of the reverse-mode tests: (shape, type, phi_s, n_init (K, N),
+    f_init (19, N), parameters, flags); "k2_field": two electrodes, 1:1 salt
+    and an applied field; "k3_naive": three electrodes, a divalent species and
+    the first-order wall scheme."""
+    if kind == "k2_field":
+        shape = (6, 6, 12)
+        t, ps = random_geometry(shape, 2, seed=7, fill=0.15)
+        n0 = W.noisy_concentrations(t, (3e-3, 3e-3), 5e-2, seed=2)
+        kw = dict(z=(1, -1), D=(0.05, 0.08), lB=0.4, tau=0.9, Eapp=(2e-3, 0.0, 1e-3))
+        flags = 0
+    else:  # multivalent, three electrodes, first-order wall scheme
+        shape = (4, 6, 10)
+        t, ps = random_geometry(shape, 3, seed=11, fill=0.2)
+        n0 = W.noisy_concentrations(t, (2e-3, 3e-3, 0.5e-3), 5e-2, seed=4)
+        kw = dict(z=(1, -1, 2), D=(0.05, 0.03, 0.02), lB=0.4, tau=1.1, Eapp=(0.0, -1e-3, 5e-4))
+        flags = 4  # first-order wall scheme (the same bit in the oracle and the library)
+    rng = np.random.default_rng(3)
+    f0 = _rest(t) * (1.0 + 1e-3 * rng.uniform(-1, 1, (19, t.size)))
+    return shape, t, ps, n0, f0, kw, flags

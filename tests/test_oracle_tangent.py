@@ -28,21 +28,7 @@ LB = 0.4
 
 
 def _case(kind):
-    if kind == "k2_field":
-        shape = (6, 6, 12)
-        t, ps = G.random_geometry(shape, 2, seed=7, fill=0.15)
-        n0 = W.noisy_concentrations(t, (3e-3, 3e-3), 5e-2, seed=2)
-        kw = dict(z=(1, -1), D=(0.05, 0.08), lB=LB, tau=0.9, Eapp=(2e-3, 0.0, 1e-3))
-        flags = 0
-    else:  # multivalent, three electrodes, first-order wall scheme
-        shape = (4, 6, 10)
-        t, ps = G.random_geometry(shape, 3, seed=11, fill=0.2)
-        n0 = W.noisy_concentrations(t, (2e-3, 3e-3, 0.5e-3), 5e-2, seed=4)
-        kw = dict(z=(1, -1, 2), D=(0.05, 0.03, 0.02), lB=LB, tau=1.1, Eapp=(0.0, -1e-3, 5e-4))
-        flags = oracle.FLAG_NAIVE_DIRICHLET
-    rng = np.random.default_rng(3)
-    f0 = TG.rest_populations(t) * (1.0 + 1e-3 * rng.uniform(-1, 1, (19, t.size)))
-    return shape, t, ps, n0, f0, kw, flags
+    return G.adjoint_case(kind)
 
 
 def _oracle(shape, t, ps, n0, f0, kw, flags):
