@@ -184,16 +184,16 @@ int lbe_poisson(lbe_ctx *ctx, int32_t *iters, double *resid);
 int lbe_set_electrode_potential(lbe_ctx *ctx, const double *phi_s);
 
 /*
- * Reverse mode (gradients of the electrode charge), FP64 form only.
+ * Reverse mode (gradients of the electrode charge).
  *
  * lbe_record advances nsteps time steps exactly as lbe_step does and keeps,
- * in device memory owned by the context, a checkpoint of the state (stored
- * populations, concentrations, potential, and phi(t-1) under
- * LBE_EXTRAPOLATE) at the first step and every `every` steps after it, plus
- * the final state: ceil(nsteps/every) + 1 states of (19 + nspecies + 1) N
- * doubles (one more N with LBE_EXTRAPOLATE).  It replaces an earlier record.
- * Errors: LBE_EINVAL for nsteps < 0, every < 1 or an LBE_FP32_MIXED
- * context; LBE_ENOMEM; the errors of lbe_step (then no record is kept).
+ * in device memory owned by the context, a checkpoint of the state at the
+ * first step and every `every` steps after it, plus the final state:
+ * ceil(nsteps/every) + 1 states of (19 + nspecies) N values in the
+ * context's storage (8 bytes each in LBE_FP64, 4 in LBE_FP32_MIXED) and N
+ * doubles of potential (2 N under LBE_EXTRAPOLATE).  It replaces an earlier
+ * record.  Errors: LBE_EINVAL for nsteps < 0 or every < 1; LBE_ENOMEM; the
+ * errors of lbe_step (then no record is kept).
  *
  * lbe_adjoint returns the gradient of L = sum_e qbar[e] Q_e(t1), with Q_e
  * the charges of Eq. 16 at the end t1 of the record (qbar: nelectrodes
@@ -206,13 +206,16 @@ int lbe_set_electrode_potential(lbe_ctx *ctx, const double *phi_s);
  *   grad_f (19*N): the pre-collision populations at t0 (the layout of
  *     lbe_init's f_init).
  * Host buffers; any of the four may be NULL.  The derivative is that of the
- * discrete step, taken backwards: streaming and collision (Eq. 8), the link
- * fluxes and the force they exert (Eqs. 9-10), and Poisson (Eqs. 13-15),
- * whose fluid-node operator is symmetric, so each reverse step solves one
- * more Poisson problem with the context's solver, stopped at the same
- * residual tolerance.  The states between checkpoints are recomputed (one
- * more forward pass in all), which takes min(every, nsteps) more states of
- * (19 + nspecies + 1) N doubles and 2 (19 + nspecies) N + 8 N more.  The
+ * FP64 step, taken backwards along the recorded trajectory (in
+ * LBE_FP32_MIXED, the mixed-precision one): streaming and collision
+ * (Eq. 8), the link fluxes and the force they exert (Eqs. 9-10), and
+ * Poisson (Eqs. 13-15), whose fluid-node operator is symmetric, so each
+ * reverse step solves one more Poisson problem with the context's solver,
+ * stopped at the same residual tolerance.  The states of one segment between
+ * checkpoints are recomputed (one more forward pass in all) and kept as
+ * density, momentum, concentrations and potential: min(every, nsteps)
+ * states of (5 + nspecies) N doubles (FP32 concentrations in the mixed
+ * form), plus (2 (19 + nspecies) + 9) N doubles of adjoint fields.  The
  * context is left at t1, and the record stays valid for further calls with
  * other weights until the state moves (lbe_step, lbe_record,
  * lbe_set_electrode_potential).

@@ -6,6 +6,11 @@
 //
 // State at time t: stored (post-collision, pull-form) populations P_t, ion
 // concentrations n_t, and phi_t = Phi(n_t), the Poisson solution for n_t.
+// The collision depends on the pre-collision populations only through their
+// density and momentum, so a recomputed state is kept as (rho, m, n, phi):
+// k_adj_moments takes the moments of the pulled populations.  The state may
+// be stored in FP64 or in the mixed form (FP32 deviations h = f - w rho0 and
+// nu = n - n_ref); the adjoint arithmetic is FP64 either way.
 // Adjoint state: A_t = dL/d(pre-collision populations at t) and
 // nb_t = dL/dn_t with phi_t's dependence on n_t already folded in.
 //
@@ -36,12 +41,64 @@
 namespace lbe {
 namespace {
 
-template <int K>
+// FP64 values of the stored state: populations and concentrations kept in
+// FP64, or as FP32 deviations from w_i rho0 and from the system's n_ref
+__device__ __forceinline__ double load_f(const double *f, int i, int idx, int N, double) {
+  return f[i * N + idx];
+}
+__device__ __forceinline__ double load_f(const float *f, int i, int idx, int N, double rho0) {
+  return (double)f[i * N + idx] + WQ[i] * rho0;
+}
+__device__ __forceinline__ double load_n(const double *n, int k, int idx, int N, const double *) {
+  return n[k * N + idx];
+}
+__device__ __forceinline__ double load_n(const float *n, int k, int idx, int N,
+                                         const double *ref) {
+  return ref[k] + (double)n[k * N + idx];
+}
+
+// rho and m = sum_i f_i c_i of the pre-collision populations (the pull of the
+// stored array), into rhom[0..3][r]
+template <class S>
+__global__ __launch_bounds__(BLOCK) void k_adj_moments(Lattice L, Phys P,
+                                                       const uint32_t *__restrict__ mask,
+                                                       const S *__restrict__ fin,
+                                                       double *__restrict__ rhom) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) return;
+  const int N = L.n;
+  Offs o;
+  site_offsets(L, r, o);
+  double f[NQ];
+  f[0] = load_f(fin, 0, r, N, P.rho0_d);
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    const int j = OPP[i];
+    // opposite directions share their weight, so either index converts h
+    f[i] = solid_link(m, j) ? load_f(fin, j, r, N, P.rho0_d) : load_f(fin, i, nbr(o, r, j), N, P.rho0_d);
+  }
+  double rho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    rho += f[i];
+    if (CX[i]) m0 += CX[i] * f[i];
+    if (CY[i]) m1 += CY[i] * f[i];
+    if (CZ[i]) m2 += CZ[i] * f[i];
+  }
+  rhom[r] = rho;
+  rhom[N + r] = m0;
+  rhom[2 * N + r] = m1;
+  rhom[3 * N + r] = m2;
+}
+
+template <int K, class ST>
 __global__ __launch_bounds__(BLOCK) void k_adj_fluid(Lattice L, Phys P,
                                                      const uint32_t *__restrict__ mask,
                                                      const double *__restrict__ phi,
-                                                     const double *__restrict__ n,
-                                                     const double *__restrict__ fin,
+                                                     const ST *__restrict__ n,
+                                                     const double *__restrict__ rhom,
                                                      const double *__restrict__ abar_in,
                                                      const double *__restrict__ nbar_in,
                                                      double *__restrict__ abar_out,
@@ -55,10 +112,11 @@ __global__ __launch_bounds__(BLOCK) void k_adj_fluid(Lattice L, Phys P,
   Offs o;
   site_offsets(L, r, o);
   const double ph = phi[r];
+  const double *ref = P.nref_d + 4 * system_of(m);
   double nr[K], nbr_r[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    nr[k] = n[k * N + r];
+    nr[k] = load_n(n, k, r, N, ref);
     nbr_r[k] = nbar_in[k * N + r];
   }
   // force of the link fluxes (as in pass A) and the advective flux's share
@@ -74,7 +132,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_fluid(Lattice L, Phys P,
     double g = 0.0, adv = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const double nt = n[k * N + rn];
+      const double nt = load_n(n, k, rn, N, ref);
       double S, C;
       valence_sc(P.z[k], dphi, S1, C1, S, C);
       g += -((nt + nr[k]) * S + (nt - nr[k]) * C) * (0.5 / LEN[i]);
@@ -86,16 +144,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_fluid(Lattice L, Phys P,
     if (CY[i]) { F1 += CY[i] * c; V1 += CY[i] * a; }
     if (CZ[i]) { F2 += CZ[i] * c; V2 += CZ[i] * a; }
   }
-  double f[NQ];
-  pull(L, r, m, o, fin, f);
-  double rho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    rho += f[i];
-    if (CX[i]) m0 += CX[i] * f[i];
-    if (CY[i]) m1 += CY[i] * f[i];
-    if (CZ[i]) m2 += CZ[i] * f[i];
-  }
+  const double rho = rhom[r], m0 = rhom[N + r], m1 = rhom[2 * N + r], m2 = rhom[3 * N + r];
   const double irho = 1.0 / rho;
   const double ux = (m0 + 0.5 * F0) * irho;
   const double uy = (m1 + 0.5 * F1) * irho;
@@ -145,11 +194,11 @@ __global__ __launch_bounds__(BLOCK) void k_adj_fluid(Lattice L, Phys P,
   u[2 * N + r] = uz;
 }
 
-template <int K>
+template <int K, class ST>
 __global__ __launch_bounds__(BLOCK) void k_adj_ions(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
                                                     const double *__restrict__ phi,
-                                                    const double *__restrict__ n,
+                                                    const ST *__restrict__ n,
                                                     const double *__restrict__ u,
                                                     const double *__restrict__ fbar,
                                                     const double *__restrict__ nbar_in,
@@ -165,10 +214,11 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ions(Lattice L, Phys P,
   const double ph = phi[r];
   const double ux = u[r], uy = u[N + r], uz = u[2 * N + r];
   const double fx = fbar[r], fy = fbar[N + r], fz = fbar[2 * N + r];
+  const double *ref = P.nref_d + 4 * system_of(m);
   double nr[K], nbr_r[K], acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    nr[k] = n[k * N + r];
+    nr[k] = load_n(n, k, r, N, ref);
     nbr_r[k] = nbar_in[k * N + r];
     acc[k] = 0.0;
   }
@@ -187,7 +237,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ions(Lattice L, Phys P,
     const double h = 0.5 / LEN[i];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const double nt = n[k * N + rn];
+      const double nt = load_n(n, k, rn, N, ref);
       double S, C;
       valence_sc(P.z[k], dphi, S1, C1, S, C);
       const double pbk = nbar_in[k * N + rn] - nbr_r[k];
@@ -206,11 +256,11 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ions(Lattice L, Phys P,
 
 // nb_k += -4 pi l_B z_k lambda; lam_sum += lambda; lam_keep = lambda (warm
 // start of the next adjoint solve); block sums of lambda . rho_el
-template <int K>
+template <int K, class ST>
 __global__ __launch_bounds__(BLOCK) void k_adj_fold(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
                                                     const double *__restrict__ lam,
-                                                    const double *__restrict__ n,
+                                                    const ST *__restrict__ n,
                                                     double *__restrict__ nbar,
                                                     double *__restrict__ lam_sum,
                                                     double *__restrict__ lam_keep,
@@ -219,13 +269,15 @@ __global__ __launch_bounds__(BLOCK) void k_adj_fold(Lattice L, Phys P,
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   const int N = L.n;
   double v = 0.0;
-  if (r < N && !(mask[r] & SOLID_BIT)) {
+  const uint32_t m = r < N ? mask[r] : SOLID_BIT;
+  if (!(m & SOLID_BIT)) {
     const double l = lam[r];
     const double s = -6.0 * P.src_scale * l;  // -4 pi l_B lambda
+    const double *ref = P.nref_d + 4 * system_of(m);
     double q = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      q += P.z[k] * n[k * N + r];
+      q += P.z[k] * load_n(n, k, r, N, ref);
       nbar[k * N + r] += s * P.z[k];
     }
     lam_sum[r] += l;
@@ -309,36 +361,46 @@ __global__ __launch_bounds__(BLOCK) void k_adj_phis(Lattice L, const uint32_t *_
     default: CALL(4); break;    \
   }
 
+template <class S>
+hipError_t launch_adj_moments(hipStream_t s, const Lattice &L, const Phys &P,
+                              const uint32_t *mask, const S *fin, double *rhom) {
+  hipLaunchKernelGGL(k_adj_moments<S>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, fin,
+                     rhom);
+  return hipGetLastError();
+}
+
+template <class S>
 hipError_t launch_adj_fluid(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                            const double *phi, const double *n, const double *fin,
+                            const double *phi, const S *n, const double *rhom,
                             const double *abar_in, const double *nbar_in, double *abar_out,
                             double *fbar, double *u) {
-#define CALL(KK)                                                                               \
-  hipLaunchKernelGGL(k_adj_fluid<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, \
-                     n, fin, abar_in, nbar_in, abar_out, fbar, u)
+#define CALL(KK)                                                                     \
+  hipLaunchKernelGGL((k_adj_fluid<KK, S>), dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, \
+                     mask, phi, n, rhom, abar_in, nbar_in, abar_out, fbar, u)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   return hipGetLastError();
 }
 
+template <class S>
 hipError_t launch_adj_ions(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const double *phi, const double *n, const double *u,
-                           const double *fbar, const double *nbar_in, double *nbar_out,
-                           double *src) {
-#define CALL(KK)                                                                              \
-  hipLaunchKernelGGL(k_adj_ions<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, \
-                     n, u, fbar, nbar_in, nbar_out, src)
+                           const double *phi, const S *n, const double *u, const double *fbar,
+                           const double *nbar_in, double *nbar_out, double *src) {
+#define CALL(KK)                                                                    \
+  hipLaunchKernelGGL((k_adj_ions<KK, S>), dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, \
+                     mask, phi, n, u, fbar, nbar_in, nbar_out, src)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   return hipGetLastError();
 }
 
+template <class S>
 hipError_t launch_adj_fold(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const double *lam, const double *n, double *nbar, double *lam_sum,
+                           const double *lam, const S *n, double *nbar, double *lam_sum,
                            double *lam_keep, double *partial, double *lb_acc) {
   const int nb = (int)blocks_for(L.n);
-#define CALL(KK)                                                                          \
-  hipLaunchKernelGGL(k_adj_fold<KK>, dim3(nb), dim3(BLOCK), 0, s, L, P, mask, lam, n, nbar, \
+#define CALL(KK)                                                                             \
+  hipLaunchKernelGGL((k_adj_fold<KK, S>), dim3(nb), dim3(BLOCK), 0, s, L, P, mask, lam, n, nbar, \
                      lam_sum, lam_keep, partial)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
@@ -347,6 +409,24 @@ hipError_t launch_adj_fold(hipStream_t s, const Lattice &L, const Phys &P, const
                      lb_acc);
   return hipGetLastError();
 }
+
+#define LBE_ADJ_INSTANTIATE(S)                                                                   \
+  template hipError_t launch_adj_moments<S>(hipStream_t, const Lattice &, const Phys &,         \
+                                            const uint32_t *, const S *, double *);             \
+  template hipError_t launch_adj_fluid<S>(hipStream_t, const Lattice &, const Phys &,           \
+                                          const uint32_t *, const double *, const S *,          \
+                                          const double *, const double *, const double *,       \
+                                          double *, double *, double *);                        \
+  template hipError_t launch_adj_ions<S>(hipStream_t, const Lattice &, const Phys &,            \
+                                         const uint32_t *, const double *, const S *,           \
+                                         const double *, const double *, const double *,        \
+                                         double *, double *);                                   \
+  template hipError_t launch_adj_fold<S>(hipStream_t, const Lattice &, const Phys &,            \
+                                         const uint32_t *, const double *, const S *, double *, \
+                                         double *, double *, double *, double *);
+LBE_ADJ_INSTANTIATE(double)
+LBE_ADJ_INSTANTIATE(float)
+#undef LBE_ADJ_INSTANTIATE
 
 hipError_t launch_adj_seed(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
                            const uint8_t *type, const double *qbar, double *src, double *gphis) {

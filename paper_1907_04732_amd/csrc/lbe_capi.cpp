@@ -98,14 +98,14 @@ struct lbe_ctx {
     int every = 1;        // steps between checkpoints
     int nck = 0;          // checkpoints at t0, t0 + every, ...; slot nck holds the end state
     int cap = 0;          // checkpoint slots allocated
-    size_t ck_len = 0;    // doubles per checkpoint: f, n, phi (and phi_prev)
-    double *ck = nullptr;
-    double *seg = nullptr;  // the states of one segment, recomputed (f, n, phi per slot)
+    char *ck = nullptr;   // checkpoints: populations, concentrations, phi (and phi_prev)
+    char *seg = nullptr;  // the recomputed states of one segment: rho, m, n, phi
     int seg_cap = 0;
   } tape;
   double *abar[2] = {nullptr, nullptr};  // adjoint of the pre-collision populations
   double *nbar[2] = {nullptr, nullptr};  // adjoint of the concentrations
   double *fbar = nullptr;      // adjoint of the force (3 N)
+  double *adj_u = nullptr;     // velocity of the reverse step (3 N)
   double *lam = nullptr;       // last Poisson adjoint (warm start; zero on solid nodes)
   double *lam_sum = nullptr;   // Poisson adjoints summed over the reverse steps
   double *gphis = nullptr;     // gradient with respect to phi_s
@@ -1038,34 +1038,82 @@ int one_step(lbe_ctx *c, bool record = true) {
 
 // ---- reverse mode -----------------------------------------------------------
 
-// copy the state (stored populations, n, phi, and phi_prev when extrapolating
-// and `prev`) to / from device memory laid out as consecutive arrays
-int save_state(lbe_ctx *c, double *dst, bool prev) {
-  const size_t N = c->L.n, K = c->K;
-  HIPCHK(c, hipMemcpyAsync(dst, c->f[c->cur], sizeof(double) * NQ * N, hipMemcpyDeviceToDevice,
-                           c->stream));
-  HIPCHK(c, hipMemcpyAsync(dst + NQ * N, c->n[c->cur], sizeof(double) * K * N,
-                           hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(dst + (NQ + K) * N, c->phi, sizeof(double) * N, hipMemcpyDeviceToDevice,
-                           c->stream));
-  if (prev && c->phi_prev)
-    HIPCHK(c, hipMemcpyAsync(dst + (NQ + K + 1) * N, c->phi_prev, sizeof(double) * N,
-                             hipMemcpyDeviceToDevice, c->stream));
+inline size_t pad256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Byte layout of a saved state.  A checkpoint holds the populations and
+// concentrations in the context's storage (FP64, or the FP32 deviations of
+// the mixed form), phi and, under LBE_EXTRAPOLATE, phi(t-1).  A recomputed
+// state of one reverse step holds rho and m (4 N FP64: the collision sees the
+// populations only through them), the concentrations and phi.
+struct StateLayout {
+  size_t f, n, phi, prev, bytes;
+};
+
+StateLayout checkpoint_layout(const lbe_ctx *c) {
+  const size_t N = c->L.n, sf = c->mixed ? sizeof(float) : sizeof(double);
+  StateLayout l;
+  l.f = 0;
+  l.n = pad256(NQ * N * sf);
+  l.phi = l.n + pad256(c->K * N * sf);
+  l.prev = l.phi + pad256(N * sizeof(double));
+  l.bytes = l.prev + (c->phi_prev ? pad256(N * sizeof(double)) : 0);
+  return l;
+}
+
+StateLayout slot_layout(const lbe_ctx *c) {
+  const size_t N = c->L.n, sf = c->mixed ? sizeof(float) : sizeof(double);
+  StateLayout l;
+  l.f = 0;
+  l.n = pad256(4 * N * sizeof(double));
+  l.phi = l.n + pad256(c->K * N * sf);
+  l.prev = l.bytes = l.phi + pad256(N * sizeof(double));
+  return l;
+}
+
+void *cur_pops(lbe_ctx *c) { return c->mixed ? (void *)c->h32[c->cur] : (void *)c->f[c->cur]; }
+void *cur_concs(lbe_ctx *c) { return c->mixed ? (void *)c->nu32[c->cur] : (void *)c->n[c->cur]; }
+
+int copy_dd(lbe_ctx *c, void *dst, const void *src, size_t bytes) {
+  HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
   return LBE_OK;
 }
 
-int load_state(lbe_ctx *c, const double *src) {
-  const size_t N = c->L.n, K = c->K;
-  HIPCHK(c, hipMemcpyAsync(c->f[c->cur], src, sizeof(double) * NQ * N, hipMemcpyDeviceToDevice,
-                           c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->n[c->cur], src + NQ * N, sizeof(double) * K * N,
-                           hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->phi, src + (NQ + K) * N, sizeof(double) * N, hipMemcpyDeviceToDevice,
-                           c->stream));
-  if (c->phi_prev)
-    HIPCHK(c, hipMemcpyAsync(c->phi_prev, src + (NQ + K + 1) * N, sizeof(double) * N,
-                             hipMemcpyDeviceToDevice, c->stream));
+int save_state(lbe_ctx *c, char *dst) {
+  const StateLayout l = checkpoint_layout(c);
+  const size_t N = c->L.n, sf = c->mixed ? sizeof(float) : sizeof(double);
+  int rc;
+  if ((rc = copy_dd(c, dst + l.f, cur_pops(c), NQ * N * sf)) ||
+      (rc = copy_dd(c, dst + l.n, cur_concs(c), c->K * N * sf)) ||
+      (rc = copy_dd(c, dst + l.phi, c->phi, N * sizeof(double))))
+    return rc;
+  if (c->phi_prev) return copy_dd(c, dst + l.prev, c->phi_prev, N * sizeof(double));
   return LBE_OK;
+}
+
+int load_state(lbe_ctx *c, const char *src) {
+  const StateLayout l = checkpoint_layout(c);
+  const size_t N = c->L.n, sf = c->mixed ? sizeof(float) : sizeof(double);
+  int rc;
+  if ((rc = copy_dd(c, cur_pops(c), src + l.f, NQ * N * sf)) ||
+      (rc = copy_dd(c, cur_concs(c), src + l.n, c->K * N * sf)) ||
+      (rc = copy_dd(c, c->phi, src + l.phi, N * sizeof(double))))
+    return rc;
+  if (c->phi_prev) return copy_dd(c, c->phi_prev, src + l.prev, N * sizeof(double));
+  return LBE_OK;
+}
+
+// the current state as a reverse step needs it
+int save_slot(lbe_ctx *c, char *dst) {
+  const StateLayout l = slot_layout(c);
+  const size_t N = c->L.n, sf = c->mixed ? sizeof(float) : sizeof(double);
+  int rc = run(c, KK_ADJ_MOMENTS, c->L.n, [&] {
+    double *rhom = (double *)(dst + l.f);
+    if (c->mixed)
+      return launch_adj_moments<float>(c->stream, c->L, c->P, c->mask, c->h32[c->cur], rhom);
+    return launch_adj_moments<double>(c->stream, c->L, c->P, c->mask, c->f[c->cur], rhom);
+  });
+  if (rc || (rc = copy_dd(c, dst + l.n, cur_concs(c), c->K * N * sf))) return rc;
+  return copy_dd(c, dst + l.phi, c->phi, N * sizeof(double));
 }
 
 int adjoint_buffers(lbe_ctx *c) {
@@ -1078,8 +1126,8 @@ int adjoint_buffers(lbe_ctx *c) {
     }
     if ((rc = dalloc(c, &c->lam, N)) || (rc = dalloc(c, &c->lam_sum, N)) ||
         (rc = dalloc(c, &c->gphis, N)) || (rc = dalloc(c, &c->src_keep, N)) ||
-        (rc = dalloc(c, &c->qbar_d, std::max(c->ne, 1))) || (rc = dalloc(c, &c->lb_acc, 1)) ||
-        (rc = dalloc(c, &c->type_d, N)))
+        (rc = dalloc(c, &c->adj_u, 3 * N)) || (rc = dalloc(c, &c->qbar_d, std::max(c->ne, 1))) ||
+        (rc = dalloc(c, &c->lb_acc, 1)) || (rc = dalloc(c, &c->type_d, N)))
       return rc;
     HIPCHK(c, hipMemcpyAsync(c->type_d, c->type_h.data(), N, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1091,7 +1139,7 @@ int adjoint_buffers(lbe_ctx *c) {
     if (c->tape.seg) (void)hipFree(c->tape.seg);
     c->tape.seg = nullptr;
     c->tape.seg_cap = 0;
-    int rc = dalloc(c, &c->tape.seg, (size_t)slots * (NQ + K + 1) * N);
+    int rc = dalloc(c, &c->tape.seg, (size_t)slots * slot_layout(c).bytes);
     if (rc) return rc;
     c->tape.seg_cap = slots;
   }
@@ -1111,19 +1159,21 @@ int adjoint_solve(lbe_ctx *c) {
   return rc;
 }
 
-int adjoint_fold(lbe_ctx *c, const double *n, double *nbar) {
+template <class S>
+int adjoint_fold(lbe_ctx *c, const S *n, double *nbar) {
   return run(c, KK_ADJ_FOLD, c->L.n, [&] {
-    return launch_adj_fold(c->stream, c->L, c->P, c->mask, c->phi, n, nbar, c->lam_sum, c->lam,
-                           c->partial, c->lb_acc);
+    return launch_adj_fold<S>(c->stream, c->L, c->P, c->mask, c->phi, n, nbar, c->lam_sum, c->lam,
+                              c->partial, c->lb_acc);
   });
 }
 
 // The reverse sweep of lbe_adjoint; the caller restores the end state.
+template <class S>
 int adjoint_sweep(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *grad_lB,
                   double *grad_n, double *grad_f) {
   lbe_ctx::Tape &T = c->tape;
   const size_t N = c->L.n, K = c->K;
-  const size_t slot_len = (NQ + K + 1) * N;
+  const StateLayout ck = checkpoint_layout(c), sl = slot_layout(c);
   int rc;
   int cur = 0;
   HIPCHK(c, hipMemsetAsync(c->abar[0], 0, sizeof(double) * NQ * N, c->stream));
@@ -1150,32 +1200,34 @@ int adjoint_sweep(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *gr
   for (int e = 0; e < c->ne; ++e) lb_explicit -= qbar[e] * qend[e] / c->p.lB;
   // phi(T) depends on n(T): fold its adjoint in
   if ((rc = adjoint_solve(c))) return rc;
-  if ((rc = adjoint_fold(c, c->n[c->cur], c->nbar[cur]))) return rc;
+  if ((rc = adjoint_fold<S>(c, (const S *)cur_concs(c), c->nbar[cur]))) return rc;
   for (int sg = T.nck - 1; sg >= 0; --sg) {
     const int64_t a = (int64_t)sg * T.every;
     const int64_t b = std::min<int64_t>(a + T.every, T.nsteps);
-    if ((rc = load_state(c, T.ck + (size_t)sg * T.ck_len))) return rc;
+    if ((rc = load_state(c, T.ck + (size_t)sg * ck.bytes))) return rc;
     for (int64_t t = a; t < b; ++t) {
-      if ((rc = save_state(c, T.seg + (size_t)(t - a) * slot_len, false))) return rc;
+      if ((rc = save_slot(c, T.seg + (size_t)(t - a) * sl.bytes))) return rc;
       if (t + 1 < b && (rc = one_step(c, false))) return rc;
     }
     for (int64_t t = b - 1; t >= a; --t) {
-      const double *fs = T.seg + (size_t)(t - a) * slot_len;
-      const double *ns = fs + NQ * N;
-      const double *ps = ns + K * N;
+      const char *slot = T.seg + (size_t)(t - a) * sl.bytes;
+      const double *rhom = (const double *)(slot + sl.f);
+      const S *ns = (const S *)(slot + sl.n);
+      const double *ps = (const double *)(slot + sl.phi);
       const int nxt = 1 - cur;
       if ((rc = run(c, KK_ADJ_FLUID, c->L.n, [&] {
-             return launch_adj_fluid(c->stream, c->L, c->P, c->mask, ps, ns, fs, c->abar[cur],
-                                     c->nbar[cur], c->abar[nxt], c->fbar, c->u);
+             return launch_adj_fluid<S>(c->stream, c->L, c->P, c->mask, ps, ns, rhom,
+                                        c->abar[cur], c->nbar[cur], c->abar[nxt], c->fbar,
+                                        c->adj_u);
            })))
         return rc;
       if ((rc = run(c, KK_ADJ_IONS, c->L.n, [&] {
-             return launch_adj_ions(c->stream, c->L, c->P, c->mask, ps, ns, c->u, c->fbar,
-                                    c->nbar[cur], c->nbar[nxt], c->src);
+             return launch_adj_ions<S>(c->stream, c->L, c->P, c->mask, ps, ns, c->adj_u, c->fbar,
+                                       c->nbar[cur], c->nbar[nxt], c->src);
            })))
         return rc;
       if ((rc = adjoint_solve(c))) return rc;
-      if ((rc = adjoint_fold(c, ns, c->nbar[nxt]))) return rc;
+      if ((rc = adjoint_fold<S>(c, ns, c->nbar[nxt]))) return rc;
       cur = nxt;
     }
   }
@@ -1209,8 +1261,8 @@ void free_ctx(lbe_ctx *c) {
                   c->blk_end, c->qcur, c->qhist, c->solid_idx, c->solid_val,
                   c->nref_d_tab, c->qref_tab, c->nref_f_tab, c->kr, c->kp, c->kq, c->kc,
                   c->tape.ck, c->tape.seg, c->abar[0], c->abar[1], c->nbar[0], c->nbar[1],
-                  c->fbar, c->lam, c->lam_sum, c->gphis, c->src_keep, c->qbar_d, c->lb_acc,
-                  c->type_d};
+                  c->fbar, c->adj_u, c->lam, c->lam_sum, c->gphis, c->src_keep, c->qbar_d,
+                  c->lb_acc, c->type_d};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   for (auto &L : c->mg) {
@@ -1602,29 +1654,25 @@ int lbe_step(lbe_ctx *c, int64_t nsteps) {
 int lbe_record(lbe_ctx *c, int64_t nsteps, int32_t every) {
   if (!c || nsteps < 0 || every < 1)
     return fail(c, LBE_EINVAL, "bad context, step count or checkpoint interval");
-  if (c->mixed) return fail(c, LBE_EINVAL, "reverse mode needs the FP64 form");
   lbe_ctx::Tape &T = c->tape;
   T.t0 = -1;
-  const size_t N = c->L.n;
-  const size_t ck_len = (NQ + c->K + 1 + (c->phi_prev ? 1 : 0)) * N;
+  const size_t bytes = checkpoint_layout(c).bytes;
   const int64_t nck = (nsteps + every - 1) / every;
   if (nck + 1 > (int64_t)INT32_MAX) return fail(c, LBE_EINVAL, "too many checkpoints");
   if (T.cap < nck + 1) {
     if (T.ck) (void)hipFree(T.ck);
     T.ck = nullptr;
     T.cap = 0;
-    int rc = dalloc(c, &T.ck, (size_t)(nck + 1) * ck_len);
+    int rc = dalloc(c, &T.ck, (size_t)(nck + 1) * bytes);
     if (rc) return rc;
     T.cap = (int)(nck + 1);
   }
-  T.ck_len = ck_len;
   for (int64_t t = 0; t < nsteps; ++t) {
     int rc;
-    if (t % every == 0 && (rc = save_state(c, T.ck + (size_t)(t / every) * ck_len, true)))
-      return rc;
+    if (t % every == 0 && (rc = save_state(c, T.ck + (size_t)(t / every) * bytes))) return rc;
     if ((rc = one_step(c))) return rc;
   }
-  int rc = save_state(c, T.ck + (size_t)nck * ck_len, true);
+  int rc = save_state(c, T.ck + (size_t)nck * bytes);
   if (rc) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   T.t0 = c->step - nsteps;
@@ -1652,9 +1700,10 @@ int lbe_adjoint(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *grad
   const int keep_iters = c->last_iters, keep_pred = c->pred_iters;
   const double keep_resid = c->last_resid;
   const int64_t keep_total = c->total_iters;
-  rc = adjoint_sweep(c, qbar, grad_phi_s, grad_lB, grad_n, grad_f);
+  rc = c->mixed ? adjoint_sweep<float>(c, qbar, grad_phi_s, grad_lB, grad_n, grad_f)
+                : adjoint_sweep<double>(c, qbar, grad_phi_s, grad_lB, grad_n, grad_f);
   // back to the end of the recorded steps, whatever happened
-  const int rc2 = load_state(c, T.ck + (size_t)T.nck * T.ck_len);
+  const int rc2 = load_state(c, T.ck + (size_t)T.nck * checkpoint_layout(c).bytes);
   if (rc2 == LBE_OK)
     (void)hipMemcpyAsync(c->src, c->src_keep, sizeof(double) * c->L.n, hipMemcpyDeviceToDevice,
                          c->stream);

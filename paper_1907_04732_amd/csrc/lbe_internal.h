@@ -144,6 +144,7 @@ enum KernelKind {
   KK_ADJ_IONS,    // reverse step: link-flux and force adjoints, Poisson-adjoint source
   KK_ADJ_FOLD,    // reverse step: fold the Poisson adjoint into the ion adjoint
   KK_ADJ_SEED,    // reverse sweep: seed from the charge weights; phi_s gradient
+  KK_ADJ_MOMENTS, // reverse sweep: rho and m of a recomputed state
   KK_COUNT
 };
 
@@ -200,21 +201,28 @@ hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
 hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                              const float *hin, const float *nu, double *partial, double *out);
 
-// reverse mode (lbe_adjoint.hip), FP64 form.  fin: the stored populations of
-// the state at t; abar_in/nbar_in: adjoints at t+1; writes the adjoints at t.
+// reverse mode (lbe_adjoint.hip).  S: storage of the recomputed state,
+// double (FP64 form) or float (mixed form: h = f - w rho0, nu = n - n_ref).
+// rho and momentum of the pulled populations into rhom (4 N)
+template <class S>
+hipError_t launch_adj_moments(hipStream_t s, const Lattice &L, const Phys &P,
+                              const uint32_t *mask, const S *fin, double *rhom);
+// abar_in/nbar_in: adjoints at t+1; writes abar_out, the force adjoint and u
+template <class S>
 hipError_t launch_adj_fluid(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                            const double *phi, const double *n, const double *fin,
+                            const double *phi, const S *n, const double *rhom,
                             const double *abar_in, const double *nbar_in, double *abar_out,
                             double *fbar, double *u);
 // writes nbar_out (before the Poisson fold) and src = -phib/6
+template <class S>
 hipError_t launch_adj_ions(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const double *phi, const double *n, const double *u,
-                           const double *fbar, const double *nbar_in, double *nbar_out,
-                           double *src);
+                           const double *phi, const S *n, const double *u, const double *fbar,
+                           const double *nbar_in, double *nbar_out, double *src);
 // with lam the Poisson adjoint: nbar += -4 pi l_B z lam, lam_sum += lam,
 // lam_keep = lam, *lb_acc += -4 pi sum lam rho_el (partial: residual_blocks(L))
+template <class S>
 hipError_t launch_adj_fold(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const double *lam, const double *n, double *nbar, double *lam_sum,
+                           const double *lam, const S *n, double *nbar, double *lam_sum,
                            double *lam_keep, double *partial, double *lb_acc);
 hipError_t launch_adj_seed(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
                            const uint8_t *type, const double *qbar, double *src, double *gphis);
