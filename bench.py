@@ -14,7 +14,9 @@ covers; the roofline object is for the kernel kind with the largest total
 time, with measured traffic from the rocprofv3 summary in profiles/ when the
 kernel sources are unchanged since it was taken.  "shapes" repeats the
 measurement on the coaxial (1.64 M sites) and porous-electrode (7.08 M
-sites) lattices.  cpu_baseline times the FP64 oracle.
+sites) lattices.  "adjoint" times the reverse mode on the porous electrode
+(a checkpointed FP32-mixed record and one gradient of the electrode charge).
+cpu_baseline times the FP64 oracle.
 """
 from __future__ import annotations
 
@@ -51,7 +53,15 @@ def bytes_per_cell(kind: str, form: str, K: int):
       out, flag word; per coarse cell: correction and flag word.  Outer
       residual: phi, source, flag word in; correction rhs and zeroed
       correction out (multigrid).  correct: phi in + out, correction, flag
-      word.  extrap: phi and previous phi in + out, flag word.
+      word.  extrap: phi and the two previous potentials in + out, flag word.
+      Reverse mode: adj_moments reads the 19 stored populations and writes
+      rho and m; adj_fluid reads phi, the K concentrations, rho and m, the 19
+      population adjoints and K concentration adjoints of t+1, and writes 19
+      population adjoints, the force adjoint and u; adj_ions reads phi, K
+      concentrations, u, force adjoint, K concentration adjoints and writes K
+      adjoints and the Poisson-adjoint source; adj_fold reads lambda and K
+      concentrations, updates K adjoints and the summed lambda, writes the
+      warm start.
     """
     f64 = form == "fp64"
     pop = 8 if f64 else 4     # population / concentration storage
@@ -69,11 +79,16 @@ def bytes_per_cell(kind: str, form: str, K: int):
         "resid": 8 + 8 + 4,
         "mg_resid": 8 + 8 + 4 + 2 * cor,
         "correct": 16 + cor + 4,
-        "extrap": 32 + 4,
+        "extrap": 48 + 4,
         "fcg_beta": cor + 8 + 4,
         "fcg_dir": cor + 16 + 4,
         "fcg_apply": 8 + 8 + 8 + 4,
         "fcg_update": 8 + 8 + 16 + 16 + 2 * cor + 4,
+        # reverse mode: FP64 adjoint fields, concentrations in the form's storage
+        "adj_moments": 19 * pop + 32 + 4,
+        "adj_fluid": 8 + K * pop + 32 + 2 * 19 * 8 + 8 * K + 24 + 24 + 4,
+        "adj_ions": 8 + K * pop + 24 + 24 + 2 * 8 * K + 8 + 4,
+        "adj_fold": 8 + K * pop + 2 * 8 * K + 16 + 8 + 4,
     }
     return table.get(kind)
 
@@ -135,8 +150,8 @@ def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, che
              traffic=None, krylov=False):
     precision = lbe.FP64 if form == "fp64" else lbe.FP32_MIXED
     poisson = lbe.SOR4 if solver == "sor" else lbe.MG
-    # multigrid forms start each solve from 2 phi(t) - phi(t-1); the SOR form
-    # keeps the paper's warm start from phi(t).  Krylov acceleration of the
+    # multigrid forms start each solve from the quadratic extrapolation of the
+    # last three potentials; the SOR form keeps the paper's warm start from phi(t).  Krylov acceleration of the
     # V-cycle where coarse levels represent the electrodes poorly.
     flags = lbe.EXTRAPOLATE if solver == "mg" else 0
     if krylov and solver == "mg":
@@ -277,6 +292,71 @@ def run_shapes(names, forms, steps, warmup, check_every):
     return out
 
 
+def run_adjoint(w: W.Workload, form: str, steps: int, every: int, check_every: int):
+    """Reverse mode on workload w: lbe_record of `steps` steps with a
+    checkpoint every `every`, then one lbe_adjoint (gradient of electrode 1's
+    charge with respect to every node potential, l_B and the initial state),
+    which recomputes each segment and runs one reverse step plus one adjoint
+    Poisson solve per step.  MLUPS count lattice sites x steps.  A second
+    lbe_adjoint call with HIP events around every launch gives the kernel
+    averages."""
+    precision = lbe.FP64 if form == "fp64" else lbe.FP32_MIXED
+    p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, rho0=w.rho0, Eapp=w.Eapp,
+                        omega=w.omega, tol=w.tol, max_iter=1_000_000, check_every=check_every,
+                        precision=precision, poisson=lbe.MG, flags=lbe.EXTRAPOLATE | lbe.KRYLOV)
+    g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref)
+    N = w.node_type.size
+    ffrac = float((w.node_type == 0).sum()) / N
+    qbar = [1.0] + [0.0] * (g.ne - 1)
+    sync()
+    t0 = time.perf_counter()
+    g.record(steps, every)
+    sync()
+    t_rec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    grad = g.adjoint(qbar)
+    sync()
+    t_adj = time.perf_counter() - t0
+    dv = float(grad["phi_s"][w.node_type == 1].sum())
+    print(f"bench: adjoint {form}: record {steps} steps in {t_rec:.3f} s, reverse sweep in "
+          f"{t_adj:.3f} s, dQ1/dV1 = {dv:.6e}", file=sys.stderr, flush=True)
+    g.profile(True)
+    g.adjoint(qbar)
+    kt = g.kernel_times()
+    g.profile(False)
+    g.close()
+    kernels = {}
+    for k, (ms, cnt, cells) in sorted(kt.items(), key=lambda kv: -kv[1][0]):
+        if not cnt:
+            continue
+        avg = ms / 1e3 / cnt
+        row = {"total_ms": round(ms, 4), "launches": cnt, "avg_us": round(avg * 1e6, 3)}
+        b = bytes_per_cell(k, form, len(w.z))
+        if b is not None:
+            per_launch = (ffrac * b + (1.0 - ffrac) * 4) * cells / cnt
+            row["bytes_per_launch"] = int(round(per_launch))
+            row["achieved_GBs"] = round(per_launch / avg / 1e9, 1)
+            row["frac"] = round(per_launch / avg / 1e9 / HBM_PEAK_GBS, 4)
+        kernels[k] = row
+        print(f"bench:   {k:12s} {ms:9.3f} ms, {cnt:6d} launches, {avg * 1e6:8.2f} us avg"
+              + (f", {row['achieved_GBs']:8.1f} GB/s" if b is not None else ""),
+              file=sys.stderr, flush=True)
+    adj = [k for k in kernels if k.startswith("adj_") and "frac" in kernels[k]]
+    dom = adj[0] if adj else None
+    roof = None
+    if dom:
+        d = kernels[dom]
+        roof = {"bound": "hbm", "kernel": dom, "achieved": d["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": d["frac"], "bytes_per_launch": d["bytes_per_launch"],
+                "avg_launch_us": d["avg_us"], "traffic": None}
+    return {"workload": w.name, "form": form, "steps": steps, "checkpoint_every": every,
+            "objective": "charge of electrode 1 at the last step",
+            "record_mlups": round(N * steps / t_rec / 1e6, 3),
+            "reverse_mlups": round(N * steps / t_adj / 1e6, 3),
+            "gradient_mlups": round(N * steps / (t_rec + t_adj) / 1e6, 3),
+            "dQ1_dV1": dv, "roofline": roof, "kernels": kernels}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +372,11 @@ def main():
                     help="comma list of larger lattices measured beside the headline (empty: none)")
     ap.add_argument("--shape-forms", default="fp32-mg,fp64-mg")
     ap.add_argument("--shape-steps", type=int, default=20)
+    ap.add_argument("--adjoint-forms", default="fp32-mg",
+                    help="forms of the reverse-mode measurement on the porous electrode "
+                         "(empty: none)")
+    ap.add_argument("--adjoint-steps", type=int, default=400)
+    ap.add_argument("--adjoint-every", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the LBE step is not sharded across GPUs in this "
@@ -341,6 +426,11 @@ def main():
     if shapes:
         out["shapes"] = run_shapes(shapes, [f.strip() for f in args.shape_forms.split(",")],
                                    args.shape_steps, args.warmup, args.check_every)
+    aforms = [f.strip() for f in args.adjoint_forms.split(",") if f.strip()]
+    if aforms:
+        wp = W.porous_electrode(noise=True)
+        out["adjoint"] = {f: run_adjoint(wp, FORMS[f][0], args.adjoint_steps, args.adjoint_every,
+                                         args.check_every) for f in aforms}
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

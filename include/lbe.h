@@ -74,8 +74,11 @@ typedef struct {
   int32_t flags;        /* LBE_ALLOW_FLOATING: accept fluid regions that touch
                            no electrode (their mean potential is left free);
                            LBE_EXTRAPOLATE: start each time step's Poisson
-                           solve from 2 phi(t) - phi(t-1) instead of phi(t)
-                           (same tolerance, fewer iterations);
+                           solve from the quadratic extrapolation in time
+                           3 phi(t) - 3 phi(t-1) + phi(t-2) instead of phi(t)
+                           (linear on the second step after lbe_init or
+                           lbe_set_electrode_potential, phi(t) on the first;
+                           same tolerance, fewer iterations);
                            LBE_NAIVE_DIRICHLET: the first-order scheme the
                            paper contrasts with (Sec. II C, Fig. 1): phi_s
                            held on the solid nodes and the plain Laplacian of
@@ -191,7 +194,7 @@ int lbe_set_electrode_potential(lbe_ctx *ctx, const double *phi_s);
  * first step and every `every` steps after it, plus the final state:
  * ceil(nsteps/every) + 1 states of (19 + nspecies) N values in the
  * context's storage (8 bytes each in LBE_FP64, 4 in LBE_FP32_MIXED) and N
- * doubles of potential (2 N under LBE_EXTRAPOLATE).  It replaces an earlier
+ * doubles of potential (3 N under LBE_EXTRAPOLATE: the two earlier ones).  It replaces an earlier
  * record.  Errors: LBE_EINVAL for nsteps < 0 or every < 1; LBE_ENOMEM; the
  * errors of lbe_step (then no record is kept).
  *

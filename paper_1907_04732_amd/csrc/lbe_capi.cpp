@@ -28,7 +28,8 @@ struct lbe_ctx {
   // device state (FP64 form)
   uint32_t *mask = nullptr;
   double *phi = nullptr, *src = nullptr, *u = nullptr;
-  double *phi_prev = nullptr;  // converged phi of the previous step (LBE_EXTRAPOLATE)
+  double *phi_prev = nullptr;  // converged phi(t-1), phi(t-2) (LBE_EXTRAPOLATE, 2 N)
+  int extrap_hist = 0;         // how many of the two are valid
   double *n[2] = {nullptr, nullptr};
   double *f[2] = {nullptr, nullptr};
   // mixed form: FP32 deviations h = f - w rho0, nu = n - n_ref, FP32 velocity
@@ -101,6 +102,7 @@ struct lbe_ctx {
     char *ck = nullptr;   // checkpoints: populations, concentrations, phi (and phi_prev)
     char *seg = nullptr;  // the recomputed states of one segment: rho, m, n, phi
     int seg_cap = 0;
+    std::vector<int> hist;  // extrapolation history length at each checkpoint
   } tape;
   double *abar[2] = {nullptr, nullptr};  // adjoint of the pre-collision populations
   double *nbar[2] = {nullptr, nullptr};  // adjoint of the concentrations
@@ -1027,9 +1029,10 @@ int one_step(lbe_ctx *c, bool record = true) {
   if (record) c->step++;
   if (c->phi_prev) {
     rc = run(c, KK_EXTRAP, c->L.n, [&] {
-      return launch_extrapolate(c->stream, c->L, c->mask, c->phi, c->phi_prev);
+      return launch_extrapolate(c->stream, c->L, c->extrap_hist, c->mask, c->phi, c->phi_prev);
     });
     if (rc) return rc;
+    c->extrap_hist = std::min(c->extrap_hist + 1, 2);
   }
   rc = poisson_solve(c, true);
   if (rc) return rc;
@@ -1056,7 +1059,7 @@ StateLayout checkpoint_layout(const lbe_ctx *c) {
   l.n = pad256(NQ * N * sf);
   l.phi = l.n + pad256(c->K * N * sf);
   l.prev = l.phi + pad256(N * sizeof(double));
-  l.bytes = l.prev + (c->phi_prev ? pad256(N * sizeof(double)) : 0);
+  l.bytes = l.prev + (c->phi_prev ? pad256(2 * N * sizeof(double)) : 0);
   return l;
 }
 
@@ -1086,7 +1089,7 @@ int save_state(lbe_ctx *c, char *dst) {
       (rc = copy_dd(c, dst + l.n, cur_concs(c), c->K * N * sf)) ||
       (rc = copy_dd(c, dst + l.phi, c->phi, N * sizeof(double))))
     return rc;
-  if (c->phi_prev) return copy_dd(c, dst + l.prev, c->phi_prev, N * sizeof(double));
+  if (c->phi_prev) return copy_dd(c, dst + l.prev, c->phi_prev, 2 * N * sizeof(double));
   return LBE_OK;
 }
 
@@ -1098,7 +1101,7 @@ int load_state(lbe_ctx *c, const char *src) {
       (rc = copy_dd(c, cur_concs(c), src + l.n, c->K * N * sf)) ||
       (rc = copy_dd(c, c->phi, src + l.phi, N * sizeof(double))))
     return rc;
-  if (c->phi_prev) return copy_dd(c, c->phi_prev, src + l.prev, N * sizeof(double));
+  if (c->phi_prev) return copy_dd(c, c->phi_prev, src + l.prev, 2 * N * sizeof(double));
   return LBE_OK;
 }
 
@@ -1205,6 +1208,7 @@ int adjoint_sweep(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *gr
     const int64_t a = (int64_t)sg * T.every;
     const int64_t b = std::min<int64_t>(a + T.every, T.nsteps);
     if ((rc = load_state(c, T.ck + (size_t)sg * ck.bytes))) return rc;
+    c->extrap_hist = T.hist[(size_t)sg];
     for (int64_t t = a; t < b; ++t) {
       if ((rc = save_slot(c, T.seg + (size_t)(t - a) * sl.bytes))) return rc;
       if (t + 1 < b && (rc = one_step(c, false))) return rc;
@@ -1602,10 +1606,10 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
   TRY(poisson_solve(c, false));
   TRY(record_charge(c));
   if (p.flags & LBE_EXTRAPOLATE) {
-    TRY(dalloc(c, &c->phi_prev, N));
-    if (hipMemcpyAsync(c->phi_prev, c->phi, sizeof(double) * N, hipMemcpyDeviceToDevice,
-                       c->stream) != hipSuccess) {
-      rc = fail(c, LBE_EDEVICE, "copy failed");
+    TRY(dalloc(c, &c->phi_prev, 2 * N));
+    c->extrap_hist = 0;  // the first step starts from phi(0) itself
+    if (hipMemsetAsync(c->phi_prev, 0, sizeof(double) * 2 * N, c->stream) != hipSuccess) {
+      rc = fail(c, LBE_EDEVICE, "memset failed");
       goto fail_;
     }
   }
@@ -1667,11 +1671,16 @@ int lbe_record(lbe_ctx *c, int64_t nsteps, int32_t every) {
     if (rc) return rc;
     T.cap = (int)(nck + 1);
   }
+  T.hist.assign((size_t)nck + 1, 0);
   for (int64_t t = 0; t < nsteps; ++t) {
     int rc;
-    if (t % every == 0 && (rc = save_state(c, T.ck + (size_t)(t / every) * bytes))) return rc;
+    if (t % every == 0) {
+      T.hist[(size_t)(t / every)] = c->extrap_hist;
+      if ((rc = save_state(c, T.ck + (size_t)(t / every) * bytes))) return rc;
+    }
     if ((rc = one_step(c))) return rc;
   }
+  T.hist[(size_t)nck] = c->extrap_hist;
   int rc = save_state(c, T.ck + (size_t)nck * bytes);
   if (rc) return rc;
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1704,6 +1713,7 @@ int lbe_adjoint(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *grad
                 : adjoint_sweep<double>(c, qbar, grad_phi_s, grad_lB, grad_n, grad_f);
   // back to the end of the recorded steps, whatever happened
   const int rc2 = load_state(c, T.ck + (size_t)T.nck * checkpoint_layout(c).bytes);
+  c->extrap_hist = T.hist[(size_t)T.nck];
   if (rc2 == LBE_OK)
     (void)hipMemcpyAsync(c->src, c->src_keep, sizeof(double) * c->L.n, hipMemcpyDeviceToDevice,
                          c->stream);
@@ -1747,6 +1757,7 @@ int lbe_set_electrode_potential(lbe_ctx *c, const double *phi_s) {
   HIPCHK(c, hipStreamSynchronize(c->stream));  // val leaves scope
   int rc = poisson_solve(c, false);
   if (rc) return rc;
+  c->extrap_hist = 0;  // the earlier potentials belong to other electrode values
   if (c->ne && c->qlen > 0) {
     rc = charges_to(c, c->qhist + (c->qlen - 1) * c->ne);
     if (rc) return rc;

@@ -134,7 +134,7 @@ enum KernelKind {
   KK_MG_RESTRICT, // residual + restriction to the next level
   KK_MG_PROLONG,  // trilinear prolongation + correction
   KK_MG_COARSE,   // coarsest-level solve in one work-group
-  KK_EXTRAP,      // warm start phi <- 2 phi - phi_prev
+  KK_EXTRAP,      // warm start: phi extrapolated in time from the last solutions
   KK_MG_SMALL,    // the coarse levels of a V-cycle in one work-group
   KK_FCG_BETA,    // Krylov: (z, q_prev) and beta
   KK_FCG_DIR,     // Krylov: p = z + beta p
@@ -185,9 +185,11 @@ hipError_t launch_observe_f64(hipStream_t s, const Lattice &L, const Phys &P,
                               const uint32_t *mask, const double *phi, const double *n,
                               const double *fin, double *fpre, double *u);
 int totals_blocks(const Lattice &L);
-// on fluid nodes: phi_prev <- phi, phi <- 2 phi - phi_prev (linear extrapolation in time)
-hipError_t launch_extrapolate(hipStream_t s, const Lattice &L, const uint32_t *mask, double *phi,
-                              double *phi_prev);
+// on fluid nodes, with prev = [phi(t-1) | phi(t-2)] (2 N): phi <- its
+// extrapolation in time of the given order (0 constant, 1 linear, 2
+// quadratic), then the history shifts: prev <- [phi(t) | phi(t-1)]
+hipError_t launch_extrapolate(hipStream_t s, const Lattice &L, int order, const uint32_t *mask,
+                              double *phi, double *prev);
 
 // mixed form (lbe_kernels_f32.hip): h = f - w rho0 and nu = n - n_ref in FP32
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,

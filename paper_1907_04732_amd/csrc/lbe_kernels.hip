@@ -390,15 +390,21 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int count, const int *__restr
   if (t < count) dst[idx[t]] = val[t];
 }
 
-// warm start of the next Poisson solve by linear extrapolation in time
-__global__ __launch_bounds__(BLOCK) void k_extrapolate(int n, const uint32_t *__restrict__ mask,
+// warm start of the next Poisson solve by extrapolation in time from the
+// last converged potentials p1 = phi(t-1), p2 = phi(t-2) (prev = [p1 | p2]):
+// order 2: 3 phi - 3 p1 + p2 (quadratic), 1: 2 phi - p1, 0: phi; then the
+// history shifts
+__global__ __launch_bounds__(BLOCK) void k_extrapolate(int n, int order,
+                                                       const uint32_t *__restrict__ mask,
                                                        double *__restrict__ phi,
-                                                       double *__restrict__ phi_prev) {
+                                                       double *__restrict__ prev) {
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= n || (mask[r] & SOLID_BIT)) return;
-  const double now = phi[r];
-  phi[r] = 2.0 * now - phi_prev[r];
-  phi_prev[r] = now;
+  const double now = phi[r], p1 = prev[r];
+  if (order >= 2) phi[r] = 3.0 * (now - p1) + prev[n + r];
+  else if (order == 1) phi[r] = 2.0 * now - p1;
+  prev[n + r] = p1;
+  prev[r] = now;
 }
 
 }  // namespace
@@ -449,10 +455,10 @@ hipError_t launch_scatter(hipStream_t s, int count, const int *idx, const double
   return hipGetLastError();
 }
 
-hipError_t launch_extrapolate(hipStream_t s, const Lattice &L, const uint32_t *mask, double *phi,
-                              double *phi_prev) {
-  hipLaunchKernelGGL(k_extrapolate, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L.n, mask, phi,
-                     phi_prev);
+hipError_t launch_extrapolate(hipStream_t s, const Lattice &L, int order, const uint32_t *mask,
+                              double *phi, double *prev) {
+  hipLaunchKernelGGL(k_extrapolate, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L.n, order, mask,
+                     phi, prev);
   return hipGetLastError();
 }
 
