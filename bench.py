@@ -35,7 +35,7 @@ import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
-def bytes_per_cell(kind: str, form: str, K: int):
+def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False):
     """Algorithmic HBM bytes per cell of the grid level a launch works on
     (lattice sites for the finest level), or None where no byte model applies
     (the one-work-group coarse-level kernel, the electrode-charge gather).
@@ -43,7 +43,9 @@ def bytes_per_cell(kind: str, form: str, K: int):
     fluid: 19 populations in + out, K concentrations in, K partially
       updated concentrations out, phi (FP64), velocity out, flag word.
       ions (advection pass): K concentrations, K partial updates in, K new
-      concentrations out, velocity in, Poisson source (FP64) out, flag word.  One colour of a four-colour SOR
+      concentrations out, velocity in, Poisson source (FP64) out, flag word;
+      with the extrapolated warm start also phi and the two previous
+      potentials in + out.  One colour of a four-colour SOR
       sweep reads phi (or the correction) at every site, and reads the
       source, reads the flag word and writes the value of its own quarter.
       Jacobi sweep (the multigrid smoother): correction in and out,
@@ -53,7 +55,7 @@ def bytes_per_cell(kind: str, form: str, K: int):
       out, flag word; per coarse cell: correction and flag word.  Outer
       residual: phi, source, flag word in; correction rhs and zeroed
       correction out (multigrid).  correct: phi in + out, correction, flag
-      word.  extrap: phi and the two previous potentials in + out, flag word.
+      word.
       Reverse mode: adj_moments reads the 19 stored populations and writes
       rho and m; adj_fluid reads phi, the K concentrations, rho and m, the 19
       population adjoints and K concentration adjoints of t+1, and writes 19
@@ -69,7 +71,7 @@ def bytes_per_cell(kind: str, form: str, K: int):
     cor = 8 if f64 else 4     # Poisson correction storage (multigrid)
     table = {
         "fluid": 19 * pop * 2 + 2 * K * pop + 8 + 3 * vel + 4,
-        "ions": 3 * K * pop + 3 * vel + 8 + 4,
+        "ions": 3 * K * pop + 3 * vel + 8 + 4 + (48 if extrap else 0),
         "sor": 8 + (8 + 8 + 4) / 4,
         "sor32": 4 + (4 + 4 + 4) / 4,
         "mg_smooth0": 3 * cor + 4,
@@ -79,7 +81,6 @@ def bytes_per_cell(kind: str, form: str, K: int):
         "resid": 8 + 8 + 4,
         "mg_resid": 8 + 8 + 4 + 2 * cor,
         "correct": 16 + cor + 4,
-        "extrap": 48 + 4,
         "fcg_beta": cor + 8 + 4,
         "fcg_dir": cor + 16 + 4,
         "fcg_apply": 8 + 8 + 8 + 4,
@@ -197,7 +198,7 @@ def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, che
         if not cnt:
             continue
         avg = ms / 1e3 / cnt
-        b = bytes_per_cell(k, form, len(w.z))
+        b = bytes_per_cell(k, form, len(w.z), extrap=bool(flags & lbe.EXTRAPOLATE))
         row = {"total_ms": round(ms, 4), "launches": cnt, "avg_us": round(avg * 1e6, 3),
                "cells_per_launch": int(round(cells / cnt))}
         if b is not None:
@@ -331,7 +332,7 @@ def run_adjoint(w: W.Workload, form: str, steps: int, every: int, check_every: i
             continue
         avg = ms / 1e3 / cnt
         row = {"total_ms": round(ms, 4), "launches": cnt, "avg_us": round(avg * 1e6, 3)}
-        b = bytes_per_cell(k, form, len(w.z))
+        b = bytes_per_cell(k, form, len(w.z), extrap=True)
         if b is not None:
             per_launch = (ffrac * b + (1.0 - ffrac) * 4) * cells / cnt
             row["bytes_per_launch"] = int(round(per_launch))

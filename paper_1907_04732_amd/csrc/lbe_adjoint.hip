@@ -289,19 +289,12 @@ __global__ __launch_bounds__(BLOCK) void k_adj_fold(Lattice L, Phys P,
 }
 
 // acc[0] += scale * sum of partial[0..nb) (fixed order)
-__global__ __launch_bounds__(BLOCK) void k_adj_accumulate(const double *__restrict__ partial,
+__global__ __launch_bounds__(FINAL) void k_adj_accumulate(const double *__restrict__ partial,
                                                           int nb, double scale,
                                                           double *__restrict__ acc) {
-  __shared__ double tree[BLOCK];
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nb; b += BLOCK) v += partial[b];
-  tree[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = BLOCK / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) acc[0] += scale * tree[0];
+  __shared__ double tree[FINAL];
+  const double v = final_sum(partial, nb, tree);
+  if (threadIdx.x == 0) acc[0] += scale * v;
 }
 
 // Seed of the reverse sweep, L = sum_e qbar_e Q_e:
@@ -405,7 +398,7 @@ hipError_t launch_adj_fold(hipStream_t s, const Lattice &L, const Phys &P, const
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   // dL/dl_B gathers -4 pi lambda . rho_el from every reverse step
-  hipLaunchKernelGGL(k_adj_accumulate, dim3(1), dim3(BLOCK), 0, s, partial, nb, -4.0 * M_PI,
+  hipLaunchKernelGGL(k_adj_accumulate, dim3(1), dim3(FINAL), 0, s, partial, nb, -4.0 * M_PI,
                      lb_acc);
   return hipGetLastError();
 }

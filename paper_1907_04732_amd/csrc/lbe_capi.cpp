@@ -1018,22 +1018,18 @@ int one_step(lbe_ctx *c, bool record = true) {
                             c->u, c->n[b]);
   });
   if (rc) return rc;
+  // pass B also moves phi to the extrapolated start of this step's solve
   rc = run(c, KK_IONS, c->L.n, [&] {
     if (c->mixed)
       return launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a], c->nu32[b],
-                             c->src);
-    return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a], c->n[b], c->src);
+                             c->src, c->extrap_hist, c->phi, c->phi_prev);
+    return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a], c->n[b], c->src,
+                           c->extrap_hist, c->phi, c->phi_prev);
   });
   if (rc) return rc;
+  if (c->phi_prev) c->extrap_hist = std::min(c->extrap_hist + 1, 2);
   c->cur = b;
   if (record) c->step++;
-  if (c->phi_prev) {
-    rc = run(c, KK_EXTRAP, c->L.n, [&] {
-      return launch_extrapolate(c->stream, c->L, c->extrap_hist, c->mask, c->phi, c->phi_prev);
-    });
-    if (rc) return rc;
-    c->extrap_hist = std::min(c->extrap_hist + 1, 2);
-  }
   rc = poisson_solve(c, true);
   if (rc) return rc;
   return record ? record_charge(c) : LBE_OK;

@@ -93,41 +93,74 @@ __device__ double block_sum(double v, double *sm) {
   return v;
 }
 
-// ---- second stage of the reductions: one block combines the per-block
-// partials in a fixed order (the kernel boundary orders the partial writes
-// before these reads, with no device-wide fence in the first stage).
+// ---- second stage of the reductions: one block of FINAL threads combines
+// the per-block partials in a fixed order (the kernel boundary orders the
+// partial writes before these reads, with no device-wide fence in the first
+// stage).  Each thread folds a strided subset with four independent
+// accumulators, so the loads of a thread are in flight together.
 
-// out[0] = max over partial[0..nb)
-__global__ __launch_bounds__(BLOCK) void k_final_max(const double *__restrict__ partial, int nb,
-                                                     double *__restrict__ out) {
-  __shared__ double tree[BLOCK];
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nb; b += BLOCK) v = nanmax(v, partial[b]);
-  tree[threadIdx.x] = v;
+constexpr int FINAL = 1024;
+
+// sum of partial[0..nb) (fixed order); valid in every thread after the call
+__device__ double final_sum(const double *__restrict__ partial, int nb, double *tree) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int b = threadIdx.x;
+  for (; b + 3 * FINAL < nb; b += 4 * FINAL) {
+    a0 += partial[b];
+    a1 += partial[b + FINAL];
+    a2 += partial[b + 2 * FINAL];
+    a3 += partial[b + 3 * FINAL];
+  }
+  for (; b < nb; b += FINAL) a0 += partial[b];
+  tree[threadIdx.x] = (a0 + a1) + (a2 + a3);
   __syncthreads();
-  for (int s = BLOCK / 2; s > 0; s >>= 1) {
+  for (int s = FINAL / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double v = tree[0];
+  __syncthreads();  // tree may be reused by the caller
+  return v;
+}
+
+// NaN-propagating max of partial[0..nb) (>= 0 values); valid in every thread
+__device__ double final_max(const double *__restrict__ partial, int nb, double *tree) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int b = threadIdx.x;
+  for (; b + 3 * FINAL < nb; b += 4 * FINAL) {
+    a0 = nanmax(a0, partial[b]);
+    a1 = nanmax(a1, partial[b + FINAL]);
+    a2 = nanmax(a2, partial[b + 2 * FINAL]);
+    a3 = nanmax(a3, partial[b + 3 * FINAL]);
+  }
+  for (; b < nb; b += FINAL) a0 = nanmax(a0, partial[b]);
+  tree[threadIdx.x] = nanmax(nanmax(a0, a1), nanmax(a2, a3));
+  __syncthreads();
+  for (int s = FINAL / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) tree[threadIdx.x] = nanmax(tree[threadIdx.x], tree[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = tree[0];
+  const double v = tree[0];
+  __syncthreads();
+  return v;
+}
+
+// out[0] = max over partial[0..nb)
+__global__ __launch_bounds__(FINAL) void k_final_max(const double *__restrict__ partial, int nb,
+                                                     double *__restrict__ out) {
+  __shared__ double tree[FINAL];
+  const double v = final_max(partial, nb, tree);
+  if (threadIdx.x == 0) out[0] = v;
 }
 
 // Residual check of a Poisson solve: max over the block maxima into
 // ctl->resid; marks the solve done when the residual is <= tol or not finite.
-__global__ __launch_bounds__(BLOCK) void k_final_resid(const double *__restrict__ partial, int nb,
+__global__ __launch_bounds__(FINAL) void k_final_resid(const double *__restrict__ partial, int nb,
                                                        SolveCtl *__restrict__ ctl, int add) {
-  __shared__ double tree[BLOCK];
+  __shared__ double tree[FINAL];
   if (ctl->done) return;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nb; b += BLOCK) v = nanmax(v, partial[b]);
-  tree[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = BLOCK / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) tree[threadIdx.x] = nanmax(tree[threadIdx.x], tree[threadIdx.x + s]);
-    __syncthreads();
-  }
+  const double res = final_max(partial, nb, tree);
   if (threadIdx.x == 0) {
-    const double res = tree[0];
     const int count = ctl->count + add;
     ctl->count = count;
     ctl->resid = res;
@@ -141,21 +174,13 @@ __global__ __launch_bounds__(BLOCK) void k_final_resid(const double *__restrict_
   }
 }
 
-// out[q] = sum over partial[q*nb .. q*nb + nb), q < nq (fixed pairwise order)
-__global__ __launch_bounds__(BLOCK) void k_final_sum(const double *__restrict__ partial, int nb,
+// out[q] = sum over partial[q*nb .. q*nb + nb), q < nq (fixed order)
+__global__ __launch_bounds__(FINAL) void k_final_sum(const double *__restrict__ partial, int nb,
                                                      int nq, double *__restrict__ out) {
-  __shared__ double tree[BLOCK];
+  __shared__ double tree[FINAL];
   for (int q = 0; q < nq; ++q) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nb; b += BLOCK) v += partial[q * nb + b];
-    tree[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s) tree[threadIdx.x] += tree[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[q] = tree[0];
-    __syncthreads();
+    const double v = final_sum(partial + (size_t)q * nb, nb, tree);
+    if (threadIdx.x == 0) out[q] = v;
   }
 }
 
@@ -261,6 +286,19 @@ __device__ __forceinline__ float excess_link_f_series(float nh, float nt, float 
   float S, C;
   sinh_coshm1f_series(delta, S, C);
   return -((nt + nh) * S + (nt - nh) * C) * inv2len;
+}
+
+// Warm start of the next Poisson solve at fluid node r: phi extrapolated in
+// time from the last converged potentials prev = [phi(t-1) | phi(t-2)]
+// (order 2: 3 phi - 3 p1 + p2, quadratic; 1: 2 phi - p1; 0: phi), then the
+// history shifts.  Run by the ion pass, which does not read phi.
+__device__ __forceinline__ void extrapolate_at(int r, int n, int order, double *__restrict__ phi,
+                                               double *__restrict__ prev) {
+  const double now = phi[r], p1 = prev[r];
+  if (order >= 2) phi[r] = 3.0 * (now - p1) + prev[n + r];
+  else if (order == 1) phi[r] = 2.0 * now - p1;
+  prev[n + r] = p1;
+  prev[r] = now;
 }
 
 inline unsigned blocks_for(long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }

@@ -120,7 +120,7 @@ struct MgSmall {
 
 enum KernelKind {
   KK_FLUID = 0,   // link fluxes, force, LB collide/stream (pull); writes u, n*
-  KK_IONS,        // advective ion fluxes, n(t+1), Poisson source
+  KK_IONS,        // advective ion fluxes, n(t+1), Poisson source (and the warm start)
   KK_SOR,         // one colour of the FP64 SOR sweep
   KK_RESID,       // FP64 residual inf-norm
   KK_CHARGE,      // electrode charges
@@ -134,7 +134,6 @@ enum KernelKind {
   KK_MG_RESTRICT, // residual + restriction to the next level
   KK_MG_PROLONG,  // trilinear prolongation + correction
   KK_MG_COARSE,   // coarsest-level solve in one work-group
-  KK_EXTRAP,      // warm start: phi extrapolated in time from the last solutions
   KK_MG_SMALL,    // the coarse levels of a V-cycle in one work-group
   KK_FCG_BETA,    // Krylov: (z, q_prev) and beta
   KK_FCG_DIR,     // Krylov: p = z + beta p
@@ -158,8 +157,12 @@ hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, cons
                             const double *phi, const double *n, const double *fin, double *fout,
                             double *u, double *nstar);
 // Step pass B: advective outflow with u; nio holds n* on entry, n(t+1) on exit.
+// With prev = [phi(t-1) | phi(t-2)] (2 N; NULL: none) it also moves phi to
+// its extrapolation in time of the given order (0 constant, 1 linear, 2
+// quadratic) as the next solve's start, and shifts the history.
 hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const double *u, const double *n, double *nio, double *src);
+                           const double *u, const double *n, double *nio, double *src, int order,
+                           double *phi, double *prev);
 // dst[idx[t]] = val[t] for t < count (new solid-node potentials)
 hipError_t launch_scatter(hipStream_t s, int count, const int *idx, const double *val,
                           double *dst);
@@ -185,18 +188,14 @@ hipError_t launch_observe_f64(hipStream_t s, const Lattice &L, const Phys &P,
                               const uint32_t *mask, const double *phi, const double *n,
                               const double *fin, double *fpre, double *u);
 int totals_blocks(const Lattice &L);
-// on fluid nodes, with prev = [phi(t-1) | phi(t-2)] (2 N): phi <- its
-// extrapolation in time of the given order (0 constant, 1 linear, 2
-// quadratic), then the history shifts: prev <- [phi(t) | phi(t-1)]
-hipError_t launch_extrapolate(hipStream_t s, const Lattice &L, int order, const uint32_t *mask,
-                              double *phi, double *prev);
 
 // mixed form (lbe_kernels_f32.hip): h = f - w rho0 and nu = n - n_ref in FP32
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
                             float *u, float *nustar);
 hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const float *u, const float *nu, float *nuio, double *src);
+                           const float *u, const float *nu, float *nuio, double *src, int order,
+                           double *phi, double *prev);
 hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
                               const uint32_t *mask, const double *phi, const float *nu,
                               const float *hin, double *fpre, double *u);

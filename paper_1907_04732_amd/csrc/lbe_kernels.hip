@@ -21,7 +21,7 @@ namespace lbe {
 
 const char *const kKernelNames[KK_COUNT] = {
     "fluid", "ions", "sor", "resid", "charge", "totals", "observe", "sor32", "correct",
-    "mg_resid", "mg_smooth", "mg_smooth0", "mg_restrict", "mg_prolong", "mg_coarse", "extrap", "mg_small",
+    "mg_resid", "mg_smooth", "mg_smooth0", "mg_restrict", "mg_prolong", "mg_coarse", "mg_small",
     "fcg_beta", "fcg_dir", "fcg_apply", "fcg_update", "adj_fluid", "adj_ions", "adj_fold",
     "adj_seed", "adj_moments"};
 
@@ -151,7 +151,9 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f64(Lattice L, Phys P,
                                                     const double *__restrict__ u,
                                                     const double *__restrict__ n,
                                                     double *__restrict__ nio,
-                                                    double *__restrict__ src) {
+                                                    double *__restrict__ src, int order,
+                                                    double *__restrict__ phi,
+                                                    double *__restrict__ prev) {
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
@@ -185,6 +187,7 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f64(Lattice L, Phys P,
     q += P.z[k] * v;
   }
   src[r] = P.src_scale * q;
+  if (prev) extrapolate_at(r, N, order, phi, prev);
 }
 
 // ---- Poisson: one colour of the four-colour SOR sweep (Eqs. 13, 15) --------
@@ -293,21 +296,39 @@ __global__ __launch_bounds__(BLOCK) void k_charge(Lattice L, double q_scale,
   if (threadIdx.x == 0) partial[b] = v;
 }
 
-// per electrode, Neumaier-compensated sum of its blocks in block order
+// Per electrode (one block each), compensated sum of its blocks' partials:
+// each thread keeps a Neumaier sum over a strided subset, and the block
+// combines the (sum, compensation) pairs in a fixed tree with the exact
+// rounding error of every addition carried along.
+__device__ __forceinline__ double two_sum_err(double a, double b, double t) {
+  return fabs(a) >= fabs(b) ? (a - t) + b : (b - t) + a;
+}
+
 __global__ __launch_bounds__(BLOCK) void k_final_charge(const double *__restrict__ partial,
                                                         const int *__restrict__ blk_elec, int nb,
-                                                        int ne, double *__restrict__ out) {
-  for (int e = threadIdx.x; e < ne; e += BLOCK) {
-    double s = 0.0, c = 0.0;
-    for (int k = 0; k < nb; ++k) {
-      if (blk_elec[k] != e) continue;
-      const double x = partial[k];
-      const double t = s + x;
-      c += fabs(s) >= fabs(x) ? (s - t) + x : (x - t) + s;
-      s = t;
-    }
-    out[e] = s + c;
+                                                        double *__restrict__ out) {
+  __shared__ double ts[BLOCK], tc[BLOCK];
+  const int e = blockIdx.x;
+  double s = 0.0, c = 0.0;
+  for (int k = threadIdx.x; k < nb; k += BLOCK) {
+    if (blk_elec[k] != e) continue;
+    const double x = partial[k];
+    const double t = s + x;
+    c += two_sum_err(s, x, t);
+    s = t;
   }
+  ts[threadIdx.x] = s;
+  tc[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = BLOCK / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      const double a = ts[threadIdx.x], b = ts[threadIdx.x + h], t = a + b;
+      tc[threadIdx.x] += tc[threadIdx.x + h] + two_sum_err(a, b, t);
+      ts[threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[e] = ts[0] + tc[0];
 }
 
 // ---- conserved totals: mass, ionic charge, species amounts ------------------
@@ -390,23 +411,6 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int count, const int *__restr
   if (t < count) dst[idx[t]] = val[t];
 }
 
-// warm start of the next Poisson solve by extrapolation in time from the
-// last converged potentials p1 = phi(t-1), p2 = phi(t-2) (prev = [p1 | p2]):
-// order 2: 3 phi - 3 p1 + p2 (quadratic), 1: 2 phi - p1, 0: phi; then the
-// history shifts
-__global__ __launch_bounds__(BLOCK) void k_extrapolate(int n, int order,
-                                                       const uint32_t *__restrict__ mask,
-                                                       double *__restrict__ phi,
-                                                       double *__restrict__ prev) {
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
-  if (r >= n || (mask[r] & SOLID_BIT)) return;
-  const double now = phi[r], p1 = prev[r];
-  if (order >= 2) phi[r] = 3.0 * (now - p1) + prev[n + r];
-  else if (order == 1) phi[r] = 2.0 * now - p1;
-  prev[n + r] = p1;
-  prev[r] = now;
-}
-
 }  // namespace
 
 // ---- launchers ------------------------------------------------------------
@@ -430,9 +434,10 @@ hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, cons
 }
 
 hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const double *u, const double *n, double *nio, double *src) {
+                           const double *u, const double *n, double *nio, double *src, int order,
+                           double *phi, double *prev) {
 #define CALL(KK) \
-  hipLaunchKernelGGL(k_ions_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, u, n, nio, src)
+  hipLaunchKernelGGL(k_ions_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, u, n, nio, src, order, phi, prev)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   return hipGetLastError();
@@ -455,13 +460,6 @@ hipError_t launch_scatter(hipStream_t s, int count, const int *idx, const double
   return hipGetLastError();
 }
 
-hipError_t launch_extrapolate(hipStream_t s, const Lattice &L, int order, const uint32_t *mask,
-                              double *phi, double *prev) {
-  hipLaunchKernelGGL(k_extrapolate, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L.n, order, mask,
-                     phi, prev);
-  return hipGetLastError();
-}
-
 int residual_blocks(const Lattice &L) { return (int)blocks_for(L.n); }
 int totals_blocks(const Lattice &L) { return (int)blocks_for(L.n); }
 
@@ -470,7 +468,7 @@ hipError_t launch_resid_f64(hipStream_t s, const Lattice &L, const uint32_t *mas
                             int add) {
   const int nb = (int)blocks_for(L.n);
   hipLaunchKernelGGL(k_resid_f64, dim3(nb), dim3(BLOCK), 0, s, L, mask, src, phi, partial, ctl);
-  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(BLOCK), 0, s, partial, nb, ctl, add);
+  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
 
@@ -481,7 +479,7 @@ hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const 
   if (nblocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_charge, dim3(nblocks), dim3(BLOCK), 0, s, L, q_scale, mask, phi,
                      iface_site, blk_begin, blk_end, partial);
-  hipLaunchKernelGGL(k_final_charge, dim3(1), dim3(BLOCK), 0, s, partial, blk_elec, nblocks, ne,
+  hipLaunchKernelGGL(k_final_charge, dim3(ne), dim3(BLOCK), 0, s, partial, blk_elec, nblocks,
                      out);
   return hipGetLastError();
 }
@@ -492,7 +490,7 @@ hipError_t launch_totals_f64(hipStream_t s, const Lattice &L, int K, const int *
   int4 zk = make_int4(z[0], K > 1 ? z[1] : 0, K > 2 ? z[2] : 0, K > 3 ? z[3] : 0);
   const int nb = (int)blocks_for(L.n);
   hipLaunchKernelGGL(k_totals_f64, dim3(nb), dim3(BLOCK), 0, s, L, K, zk, mask, fin, n, partial);
-  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(BLOCK), 0, s, partial, nb, 2 + K, out);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(FINAL), 0, s, partial, nb, 2 + K, out);
   return hipGetLastError();
 }
 

@@ -156,7 +156,9 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f32(Lattice L, Phys P,
                                                     const float *__restrict__ u,
                                                     const float *__restrict__ nu,
                                                     float *__restrict__ nuio,
-                                                    double *__restrict__ src) {
+                                                    double *__restrict__ src, int order,
+                                                    double *__restrict__ phi,
+                                                    double *__restrict__ prev) {
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
@@ -194,6 +196,7 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f32(Lattice L, Phys P,
     q += P.z[k] * double(v);
   }
   src[r] = P.src_scale * q;
+  if (prev) extrapolate_at(r, N, order, phi, prev);
 }
 
 template <int K>
@@ -290,9 +293,10 @@ hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, cons
 }
 
 hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const float *u, const float *nu, float *nuio, double *src) {
+                           const float *u, const float *nu, float *nuio, double *src, int order,
+                           double *phi, double *prev) {
 #define CALL(KK) \
-  hipLaunchKernelGGL(k_ions_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, u, nu, nuio, src)
+  hipLaunchKernelGGL(k_ions_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, u, nu, nuio, src, order, phi, prev)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   return hipGetLastError();
@@ -312,7 +316,7 @@ hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, con
                              const float *hin, const float *nu, double *partial, double *out) {
   const int nb = (int)blocks_for(L.n);
   hipLaunchKernelGGL(k_totals_f32, dim3(nb), dim3(BLOCK), 0, s, L, P, mask, hin, nu, partial);
-  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(BLOCK), 0, s, partial, nb, 2 + P.K, out);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(FINAL), 0, s, partial, nb, 2 + P.K, out);
   return hipGetLastError();
 }
 

@@ -138,25 +138,12 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_dot(int n, const uint32_t *__rest
   if (threadIdx.x == 0) partial[blockIdx.x] = v;
 }
 
-// fixed-order sum of nb partials by one block (valid in thread 0)
-__device__ double sum_partials(const double *__restrict__ partial, int nb, double *tree) {
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nb; b += BLOCK) v += partial[b];
-  tree[threadIdx.x] = v;
-  __syncthreads();
-  for (int s2 = BLOCK / 2; s2 > 0; s2 >>= 1) {
-    if (threadIdx.x < s2) tree[threadIdx.x] += tree[threadIdx.x + s2];
-    __syncthreads();
-  }
-  return tree[0];
-}
-
-__global__ __launch_bounds__(BLOCK) void k_fcg_beta(const double *__restrict__ partial, int nb,
+__global__ __launch_bounds__(FINAL) void k_fcg_beta(const double *__restrict__ partial, int nb,
                                                     KrylovCtl *__restrict__ kc,
                                                     const SolveCtl *__restrict__ ctl) {
-  __shared__ double tree[BLOCK];
+  __shared__ double tree[FINAL];
   if (ctl->done) return;
-  const double zq = sum_partials(partial, nb, tree);
+  const double zq = final_sum(partial, nb, tree);
   if (threadIdx.x == 0) kc->beta = (kc->first || kc->pq_prev == 0.0) ? 0.0 : -zq / kc->pq_prev;
 }
 
@@ -199,14 +186,13 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_apply(MgLevel lv, const uint32_t 
   if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = rp;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_fcg_alpha(const double *__restrict__ partial, int nb,
+__global__ __launch_bounds__(FINAL) void k_fcg_alpha(const double *__restrict__ partial, int nb,
                                                      KrylovCtl *__restrict__ kc,
                                                      const SolveCtl *__restrict__ ctl) {
-  __shared__ double tree[BLOCK];
+  __shared__ double tree[FINAL];
   if (ctl->done) return;
-  const double pq = sum_partials(partial, nb, tree);
-  __syncthreads();
-  const double rp = sum_partials(partial + nb, nb, tree);
+  const double pq = final_sum(partial, nb, tree);
+  const double rp = final_sum(partial + nb, nb, tree);
   if (threadIdx.x == 0) {
     kc->alpha = pq > 0.0 ? rp / pq : 0.0;
     kc->pq_prev = pq;
@@ -725,7 +711,7 @@ hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_
   const int nb = (int)blocks_for(lv.n);
   hipLaunchKernelGGL(k_outer_resid<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, src, phi, r0, e0,
                      partial, ctl, r64, kc);
-  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(BLOCK), 0, s, partial, nb, ctl, add);
+  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
 
@@ -734,7 +720,7 @@ hipError_t launch_fcg_beta(hipStream_t s, int n, const uint32_t *mask, const T *
                            const double *q, double *partial, KrylovCtl *kc, const SolveCtl *ctl) {
   const int nb = (int)blocks_for(n);
   hipLaunchKernelGGL(k_fcg_dot<T>, dim3(nb), dim3(BLOCK), 0, s, n, mask, z, q, partial, ctl);
-  hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(BLOCK), 0, s, partial, nb, kc, ctl);
+  hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(FINAL), 0, s, partial, nb, kc, ctl);
   return hipGetLastError();
 }
 
@@ -750,7 +736,7 @@ hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *ma
                             KrylovCtl *kc, const SolveCtl *ctl) {
   const int nb = (int)blocks_for(lv.n);
   hipLaunchKernelGGL(k_fcg_apply, dim3(nb), dim3(BLOCK), 0, s, lv, mask, p, r, q, partial, ctl);
-  hipLaunchKernelGGL(k_fcg_alpha, dim3(1), dim3(BLOCK), 0, s, partial, nb, kc, ctl);
+  hipLaunchKernelGGL(k_fcg_alpha, dim3(1), dim3(FINAL), 0, s, partial, nb, kc, ctl);
   return hipGetLastError();
 }
 
@@ -761,7 +747,7 @@ hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const d
   const int nb = (int)blocks_for(n);
   hipLaunchKernelGGL(k_fcg_update<T>, dim3(nb), dim3(BLOCK), 0, s, n, mask, p, q, phi, r, r0, e0,
                      partial, kc, ctl);
-  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(BLOCK), 0, s, partial, nb, ctl, add);
+  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
 
