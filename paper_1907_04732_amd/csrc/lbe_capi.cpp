@@ -789,8 +789,11 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
 // One V-cycle from level l: e (zeroed by the residual / restriction kernel)
 // -> pre-smoothing -> restriction -> V-cycle below -> prolongation ->
 // post-smoothing; *out receives the level's correction.
+// One V-cycle on level l for A e = r (e starts at 0); *out receives the
+// buffer holding e.  With phi_add (finest level), the last smoothing launch
+// also adds e to phi and *added is set; otherwise the caller adds it.
 template <class T>
-int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
+int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *added = nullptr) {
   lbe_ctx::MgDev &L = c->mg[l];
   T *A = (T *)L.e, *r = (T *)L.r;
   int rc;
@@ -814,18 +817,21 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
   }
   const KernelKind sk = l == 0 ? KK_MG_SMOOTH0 : KK_MG_SMOOTH;
   T *cur = A;
-  // four-colour Gauss-Seidel in place, or damped Jacobi in pairs cur -> e2 -> cur
-  auto smooth = [&](int sweeps) -> int {
+  // four-colour Gauss-Seidel in place, or damped Jacobi in pairs
+  // cur -> e2 -> cur; the last sweep on the finest level may add the result
+  // to phi
+  auto smooth = [&](int sweeps, double *add_to) -> int {
     if (c->mg_jacobi > 0.0) {
       for (int s2 = 0; s2 < sweeps; s2 += 2) {
+        const bool last = s2 + 2 >= sweeps;
         int r2 = run(c, sk, L.lv.n, [&] {
           return launch_jacobi<T>(c->stream, L.lv, c->mg_jacobi, L.lv.h2 / 6.0, L.mask, r, cur,
-                                  (T *)L.e2, c->ctl);
+                                  (T *)L.e2, c->ctl, nullptr);
         });
         if (r2) return r2;
         r2 = run(c, sk, L.lv.n, [&] {
           return launch_jacobi<T>(c->stream, L.lv, c->mg_jacobi, L.lv.h2 / 6.0, L.mask, r,
-                                  (const T *)L.e2, cur, c->ctl);
+                                  (const T *)L.e2, cur, c->ctl, last ? add_to : nullptr);
         });
         if (r2) return r2;
       }
@@ -840,7 +846,7 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
       }
     return LBE_OK;
   };
-  if ((rc = smooth(c->p.mg_nu1))) return rc;
+  if ((rc = smooth(c->p.mg_nu1, nullptr))) return rc;
   lbe_ctx::MgDev &C = c->mg[l + 1];
   rc = run(c, KK_MG_RESTRICT, L.lv.n, [&] {
     return launch_mg_restrict<T>(c->stream, C.tr, L.mask, C.mask, r, cur, (T *)C.r, (T *)C.e,
@@ -853,7 +859,8 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out) {
     return launch_mg_prolong<T>(c->stream, C.tr, L.mask, C.mask, (const T *)ce, cur, c->ctl);
   });
   if (rc) return rc;
-  if ((rc = smooth(c->p.mg_nu2))) return rc;
+  if ((rc = smooth(c->p.mg_nu2, phi_add))) return rc;
+  if (added) *added = c->mg_jacobi > 0.0 && c->p.mg_nu2 > 0 && phi_add != nullptr;
   *out = cur;
   return LBE_OK;
 }
@@ -911,8 +918,10 @@ int mg_solve(lbe_ctx *c, bool learn) {
       [&](int m) -> int {
         for (int k = 0; k < m; ++k) {
           T *e0 = nullptr;
-          int rc = mg_vcycle<T>(c, 0, &e0);
+          bool added = false;
+          int rc = mg_vcycle<T>(c, 0, &e0, c->phi, &added);
           if (rc) return rc;
+          if (added) continue;  // the last smoothing launch has corrected phi
           rc = run(c, KK_CORRECT, L0.lv.n, [&] {
             return launch_mg_correct<T>(c->stream, L0.lv.n, c->mask, (const T *)e0, c->phi,
                                         c->ctl);

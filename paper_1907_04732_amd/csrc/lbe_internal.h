@@ -258,11 +258,12 @@ template <class T>
 hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int colour,
                             const uint32_t *mask, const T *rhs, T *e, const SolveCtl *ctl);
 // damped Jacobi sweep x_in -> x_out (different arrays):
-// x <- x + omega ([sum w s x' + hs rhs] / sum w s - x)
+// x <- x + omega ([sum w s x' + hs rhs] / sum w s - x); with phi_add the
+// result is also added to phi on fluid cells, as launch_mg_correct does
 template <class T>
 hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double hs,
                          const uint32_t *mask, const T *rhs, const T *x_in, T *x_out,
-                         const SolveCtl *ctl);
+                         const SolveCtl *ctl, double *phi_add);
 template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,

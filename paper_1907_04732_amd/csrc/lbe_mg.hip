@@ -271,13 +271,16 @@ __global__ __launch_bounds__(BLOCK) void k_smooth(MgLevel lv, T omega, int colou
 // ---- damped Jacobi sweep (one launch, every cell in parallel) --------------
 // x_out = x_in + omega ([sum_i w_i s_i x_in(r+c_i) + hs rhs] / sum_i w_i s_i - x_in)
 
+// With phi_add given (the last sweep of a V-cycle on the finest level), the
+// result is also added to phi on fluid cells, as k_correct does.
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
                                                   const uint32_t *__restrict__ mask,
                                                   const T *__restrict__ rhs,
                                                   const T *__restrict__ x_in,
                                                   T *__restrict__ x_out,
-                                                  const SolveCtl *__restrict__ ctl) {
+                                                  const SolveCtl *__restrict__ ctl,
+                                                  double *__restrict__ phi_add) {
   if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= lv.n) return;
@@ -300,7 +303,9 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
   }
   num += hs * rr;
   const T xr = v[0];
-  x_out[r] = xr + omega * (num / den - xr);
+  const T res = xr + omega * (num / den - xr);
+  x_out[r] = res;
+  if (phi_add) phi_add[r] += double(res);
 }
 
 // ---- restriction: coarse rhs = mean of the fluid children's residuals -------
@@ -763,9 +768,9 @@ hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int 
 template <class T>
 hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double hs,
                          const uint32_t *mask, const T *rhs, const T *x_in, T *x_out,
-                         const SolveCtl *ctl) {
+                         const SolveCtl *ctl, double *phi_add) {
   hipLaunchKernelGGL(k_jacobi<T>, dim3(blocks_for(lv.n)), dim3(BLOCK), 0, s, lv, T(omega), T(hs),
-                     mask, rhs, x_in, x_out, ctl);
+                     mask, rhs, x_in, x_out, ctl, phi_add);
   return hipGetLastError();
 }
 
@@ -840,7 +845,7 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                           const uint32_t *, const T *, T *, const SolveCtl *);  \
   template hipError_t launch_jacobi<T>(hipStream_t, const MgLevel &, double, double,             \
                                          const uint32_t *, const T *, const T *, T *,           \
-                                         const SolveCtl *);                                     \
+                                         const SolveCtl *, double *);                           \
   template hipError_t launch_mg_restrict<T>(hipStream_t, const MgTransfer &, const uint32_t *,  \
                                             const uint32_t *, const T *, const T *, T *, T *,   \
                                             const SolveCtl *);                                  \

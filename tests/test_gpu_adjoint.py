@@ -102,6 +102,39 @@ def test_adjoint_matches_tangent_oracle(kind, solver):
         g.adjoint(np.ones(g.ne))
 
 
+def test_adjoint_porous_crop_matches_tangent_oracle():
+    """A 24^3 crop of the porous electrode (sphere caps of electrode 1 and the
+    first planes of the counter-electrode), FP64 multigrid with flexible CG
+    and the extrapolated start, 20 steps in segments of 8: the voltage,
+    l_B and random solid-potential derivatives of both charges against the
+    tangent oracle, within RTOL of the largest."""
+    w = W.porous_crop()
+    t = w.node_type
+    rng = np.random.default_rng(7)
+    f0 = TG.rest_populations(t) * (1.0 + 1e-3 * rng.uniform(-1, 1, (19, t.size)))
+    kw = dict(z=w.z, D=w.D, lB=w.lB, tau=w.tau, Eapp=w.Eapp)
+    case = (w.shape, t, w.phi_s, w.n_init, f0, kw, 0)
+    steps = 20
+    g = _lbe(*case, poisson=lbe.MG, max_iter=400, extra_flags=lbe.KRYLOV | lbe.EXTRAPOLATE)
+    g.record(steps, every=8)
+    dirs = {"V1": dict(dphi_s=(t == 1).astype(float)), "V2": dict(dphi_s=(t == 2).astype(float)),
+            "lB": dict(dlB=1.0), "phi_s": dict(dphi_s=rng.standard_normal(t.size) * (t != 0))}
+    tangents = {}
+    for name, d in dirs.items():
+        q, tangents[name] = _tangent(case, steps, **d)
+    assert np.abs(g.qhist()[-1] - q).max() < 1e-11 * np.abs(q).max()
+    for e in range(g.ne):
+        qbar = np.zeros(g.ne)
+        qbar[e] = 1.0
+        gr = g.adjoint(qbar, n=False, f=False)
+        got = {"V1": gr["phi_s"][t == 1].sum(), "V2": gr["phi_s"][t == 2].sum(), "lB": gr["lB"],
+               "phi_s": gr["phi_s"] @ dirs["phi_s"]["dphi_s"]}
+        scale = max(abs(tangents[n][e]) for n in tangents)
+        for name in tangents:
+            assert abs(got[name] - tangents[name][e]) <= RTOL * scale, (e, name, got[name],
+                                                                       tangents[name][e])
+
+
 def test_adjoint_is_linear_in_the_weights():
     case = G.adjoint_case("k2_field")
     g = _lbe(*case, poisson=lbe.MG, max_iter=400)

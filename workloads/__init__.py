@@ -118,6 +118,22 @@ def porous_electrode(noise=True, n=192):
                     (0.0, 0.0, 0.0), (rs, rs), n_init, 1.8, 1e-10, 4000, dict(debye=debye))
 
 
+def porous_crop(n=24, z0=156, noise=True):
+    """An n^3 crop of the porous electrode (x, y in [0, n), z in [z0, z0 + n)),
+    periodic as a box of its own: with the default z0 it holds the caps of
+    the top spheres (electrode 1, +0.05) and the first planes of the
+    counter-electrode (z >= 176, -0.05) with the electrolyte between."""
+    w = porous_electrode(noise=False)
+    N = w.shape[0]
+    t3 = w.node_type.reshape(N, N, N)[z0:z0 + n, :n, :n].copy()
+    p3 = w.phi_s.reshape(N, N, N)[z0:z0 + n, :n, :n].copy()
+    t = t3.reshape(-1)
+    ps = p3.reshape(-1)
+    n_init = noisy_concentrations(t, w.n_ref, 1e-6, seed=5) if noise else None
+    return Workload(f"porous_crop_{n}^3", (n, n, n), t, ps, w.z, w.D, w.lB, w.tau, w.rho0, w.Eapp,
+                    w.n_ref, n_init, w.omega, w.tol, w.steps, dict(w.extra))
+
+
 def noisy_concentrations(node_type, rho, rel=1e-6, seed=1):
     """n_k(r) = rho_k (1 + rel * U(-1, 1)) on fluid nodes, 0 on solid nodes,
     drawn from a PCG64 stream seeded with `seed`.  Returns (K, N)."""
