@@ -94,11 +94,15 @@ typedef struct {
   int32_t mg_levels;    /* multigrid levels (LBE_MG): 0 = coarsen until at most
                            512 cells remain, whose operator is inverted exactly;
                            else the number of levels (>= 2) */
-  int32_t mg_nu1, mg_nu2; /* pre/post smoothing sweeps (LBE_MG); Jacobi sweeps
-                           run in pairs, an odd count is rounded up */
+  int32_t mg_nu1, mg_nu2; /* pre/post smoothing sweeps on the finest level
+                           (LBE_MG) */
   int32_t mg_smoother;  /* LBE_MG_JACOBI: undamped Jacobi (smoothing factor 1/2
                            for this stencil, one parallel launch per sweep);
                            LBE_MG_GS4: four-colour Gauss-Seidel */
+  int32_t mg_nu1_coarse, mg_nu2_coarse; /* pre/post sweeps on the coarser
+                           levels; 0 and 0: the finest level's counts (each
+                           launch on a coarse level costs a fixed ~5 us, so
+                           one sweep each way there can be the faster cycle) */
   void *stream;         /* hipStream_t to run on; NULL = library-owned stream */
 } lbe_params;
 

@@ -43,7 +43,7 @@ class Params(C.Structure):
         ("max_iter", C.c_int32), ("check_every", C.c_int32),
         ("flags", C.c_int32), ("precision", C.c_int32), ("poisson", C.c_int32),
         ("mg_levels", C.c_int32), ("mg_nu1", C.c_int32), ("mg_nu2", C.c_int32),
-        ("mg_smoother", C.c_int32),
+        ("mg_smoother", C.c_int32), ("mg_nu1_coarse", C.c_int32), ("mg_nu2_coarse", C.c_int32),
         ("stream", C.c_void_p),
     ]
 
@@ -122,7 +122,8 @@ def _dptr(a):
 
 def make_params(shape, z, D, lB, tau=1.0, rho0=1.0, Eapp=(0.0, 0.0, 0.0), omega=1.8, tol=1e-10,
                 max_iter=200000, check_every=4, flags=0, precision=FP64, poisson=SOR4,
-                mg_levels=0, mg_nu1=2, mg_nu2=2, mg_smoother=MG_JACOBI, stream=None) -> Params:
+                mg_levels=0, mg_nu1=2, mg_nu2=2, mg_smoother=MG_JACOBI, mg_nu1_coarse=0,
+                mg_nu2_coarse=0, stream=None) -> Params:
     p = Params()
     p.nx, p.ny, p.nz = (int(v) for v in shape)
     if not 1 <= len(z) <= 4 or len(D) != len(z):
@@ -139,6 +140,7 @@ def make_params(shape, z, D, lB, tau=1.0, rho0=1.0, Eapp=(0.0, 0.0, 0.0), omega=
     p.precision, p.poisson = int(precision), int(poisson)
     p.mg_levels, p.mg_nu1, p.mg_nu2 = int(mg_levels), int(mg_nu1), int(mg_nu2)
     p.mg_smoother = int(mg_smoother)
+    p.mg_nu1_coarse, p.mg_nu2_coarse = int(mg_nu1_coarse), int(mg_nu2_coarse)
     p.stream = stream
     return p
 

@@ -82,6 +82,7 @@ struct lbe_ctx {
   };
   std::vector<MgDev> mg;
   int mg_coarse_sweeps = 0;
+  int mg_nu1c = 0, mg_nu2c = 0;  // smoothing sweeps on the coarser levels
   double mg_jacobi = 0.0;   // > 0: Jacobi smoothing with this weight (else Gauss-Seidel)
   // coarsest level solved exactly: inverse of its operator over fluid cells
   int mg_nf = 0;
@@ -243,7 +244,8 @@ int validate(const lbe_params *p) {
   if (p->poisson != LBE_SOR4 && p->poisson != LBE_MG)
     return fail(nullptr, LBE_EINVAL, "unsupported Poisson solver");
   if (p->poisson == LBE_MG && (p->mg_levels < 0 || p->mg_levels == 1 || p->mg_levels > 16 ||
-                               p->mg_nu1 < 0 || p->mg_nu2 < 0 || p->mg_nu1 + p->mg_nu2 < 1))
+                               p->mg_nu1 < 0 || p->mg_nu2 < 0 || p->mg_nu1 + p->mg_nu2 < 1 ||
+                               p->mg_nu1_coarse < 0 || p->mg_nu2_coarse < 0))
     return fail(nullptr, LBE_EINVAL, "bad multigrid levels or smoothing counts");
   if (p->poisson == LBE_MG && p->mg_smoother != LBE_MG_JACOBI && p->mg_smoother != LBE_MG_GS4)
     return fail(nullptr, LBE_EINVAL, "unknown multigrid smoother");
@@ -707,8 +709,8 @@ int plan_small_levels(lbe_ctx *c) {
       S.off_m[k] = (int)me;
       me += c->mg[from + k].lv.n;
     }
-    S.nu1 = c->p.mg_nu1;
-    S.nu2 = c->p.mg_nu2;
+    S.nu1 = c->mg_nu1c;
+    S.nu2 = c->mg_nu2c;
     S.nf = c->mg_nf;
     S.ainv = c->mg_ainv;
     S.fcell = c->mg_fcell;
@@ -816,24 +818,21 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
     });
   }
   const KernelKind sk = l == 0 ? KK_MG_SMOOTH0 : KK_MG_SMOOTH;
-  T *cur = A;
-  // four-colour Gauss-Seidel in place, or damped Jacobi in pairs
-  // cur -> e2 -> cur; the last sweep on the finest level may add the result
-  // to phi
+  T *cur = A, *alt = (T *)L.e2;
+  const int nu1 = l == 0 ? c->p.mg_nu1 : c->mg_nu1c, nu2 = l == 0 ? c->p.mg_nu2 : c->mg_nu2c;
+  // four-colour Gauss-Seidel in place, or damped Jacobi from cur into the
+  // other buffer, which then becomes cur; the last sweep on the finest level
+  // may add the result to phi
   auto smooth = [&](int sweeps, double *add_to) -> int {
     if (c->mg_jacobi > 0.0) {
-      for (int s2 = 0; s2 < sweeps; s2 += 2) {
-        const bool last = s2 + 2 >= sweeps;
-        int r2 = run(c, sk, L.lv.n, [&] {
+      for (int s2 = 0; s2 < sweeps; ++s2) {
+        const bool last = s2 + 1 == sweeps;
+        const int r2 = run(c, sk, L.lv.n, [&] {
           return launch_jacobi<T>(c->stream, L.lv, c->mg_jacobi, L.lv.h2 / 6.0, L.mask, r, cur,
-                                  (T *)L.e2, c->ctl, nullptr);
+                                  alt, c->ctl, last ? add_to : nullptr);
         });
         if (r2) return r2;
-        r2 = run(c, sk, L.lv.n, [&] {
-          return launch_jacobi<T>(c->stream, L.lv, c->mg_jacobi, L.lv.h2 / 6.0, L.mask, r,
-                                  (const T *)L.e2, cur, c->ctl, last ? add_to : nullptr);
-        });
-        if (r2) return r2;
+        std::swap(cur, alt);
       }
       return LBE_OK;
     }
@@ -846,7 +845,7 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
       }
     return LBE_OK;
   };
-  if ((rc = smooth(c->p.mg_nu1, nullptr))) return rc;
+  if ((rc = smooth(nu1, nullptr))) return rc;
   lbe_ctx::MgDev &C = c->mg[l + 1];
   rc = run(c, KK_MG_RESTRICT, L.lv.n, [&] {
     return launch_mg_restrict<T>(c->stream, C.tr, L.mask, C.mask, r, cur, (T *)C.r, (T *)C.e,
@@ -859,8 +858,8 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
     return launch_mg_prolong<T>(c->stream, C.tr, L.mask, C.mask, (const T *)ce, cur, c->ctl);
   });
   if (rc) return rc;
-  if ((rc = smooth(c->p.mg_nu2, phi_add))) return rc;
-  if (added) *added = c->mg_jacobi > 0.0 && c->p.mg_nu2 > 0 && phi_add != nullptr;
+  if ((rc = smooth(nu2, phi_add))) return rc;
+  if (added) *added = c->mg_jacobi > 0.0 && nu2 > 0 && phi_add != nullptr;
   *out = cur;
   return LBE_OK;
 }
@@ -1430,6 +1429,9 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     const char *ng = getenv("LBE_NO_GRAPHS");
     c->use_graphs = !(ng && *ng && *ng != '0');
     c->mg_jacobi = p.mg_smoother == LBE_MG_JACOBI ? 1.0 : 0.0;
+    const bool same = p.mg_nu1_coarse == 0 && p.mg_nu2_coarse == 0;
+    c->mg_nu1c = same ? p.mg_nu1 : p.mg_nu1_coarse;
+    c->mg_nu2c = same ? p.mg_nu2 : p.mg_nu2_coarse;
   }
   c->type_h.assign(type, type + N);
   c->sys_h = sys_h;

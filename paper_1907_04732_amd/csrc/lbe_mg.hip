@@ -58,12 +58,10 @@ __device__ __forceinline__ void gather_lv(const MgLevel &lv, const Coords &c, in
   for (int i = 1; i < NQ; ++i) v[i] = e[nbr_of(lv, c, i)];
 }
 
-// A e at a fluid cell, in the level's units: (6/h^2) sum_i w_i s_i (e - e_i)
+// A e at a fluid cell from its gathered values v, in the level's units:
+// (6/h^2) sum_i w_i s_i (e - e_i)
 template <class T>
-__device__ __forceinline__ T apply_A(const MgLevel &lv, int r, uint32_t m, const Coords &c,
-                                     const T *__restrict__ e) {
-  T v[NQ];
-  gather_lv(lv, c, r, e, v);
+__device__ __forceinline__ T apply_A_v(const MgLevel &lv, uint32_t m, const T (&v)[NQ]) {
   T acc = T(0);
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
@@ -73,6 +71,18 @@ __device__ __forceinline__ T apply_A(const MgLevel &lv, int r, uint32_t m, const
   }
   return T(6.0) * T(lv.inv_h2) * acc;
 }
+
+template <class T>
+__device__ __forceinline__ T apply_A(const MgLevel &lv, int r, uint32_t m, const Coords &c,
+                                     const T *__restrict__ e) {
+  T v[NQ];
+  gather_lv(lv, c, r, e, v);
+  return apply_A_v(lv, m, v);
+}
+
+// The kernels below issue a cell's neighbour loads together with its flag
+// word and pick the result by the flag afterwards, so the two memory round
+// trips overlap instead of following each other.
 
 // ---- outer residual (FP64) ----------------------------------------------------
 
@@ -91,23 +101,20 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
   if (kc && r == 0) kc->first = 1;  // a new Krylov sequence starts from this residual
   double a = 0.0;
   if (r < lv.n) {
+    const Coords c = coords_of(r, lv.nx, lv.nxy);
+    double pn[NQ];
+    gather_lv(lv, c, r, phi, pn);
+    const double sr = src[r];
     const uint32_t m = mask[r];
-    double R = 0.0;
-    if (!(m & SOLID_BIT)) {
-      const Coords c = coords_of(r, lv.nx, lv.nxy);
-      double pn[NQ];
-      gather_lv(lv, c, r, phi, pn);
-      const double sr = src[r];
-      double acc = 0.0;
+    double acc = 0.0;
 #pragma unroll
-      for (int i = 1; i < NQ; ++i) {
-        if ((lv.selfm >> (i - 1)) & 1u) continue;
-        const double ws = solid_link(m, i) ? lv.wall * WQ[i] : WQ[i];
-        acc += ws * (pn[i] - pn[0]);
-      }
-      R = 6.0 * (acc + sr);
-      a = fabs(R);
+    for (int i = 1; i < NQ; ++i) {
+      if ((lv.selfm >> (i - 1)) & 1u) continue;
+      const double ws = solid_link(m, i) ? lv.wall * WQ[i] : WQ[i];
+      acc += ws * (pn[i] - pn[0]);
     }
+    const double R = (m & SOLID_BIT) ? 0.0 : 6.0 * (acc + sr);
+    a = fabs(R);
     r0[r] = T(R);
     e0[r] = T(0);
     if (r64) r64[r] = R;
@@ -171,13 +178,16 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_apply(MgLevel lv, const uint32_t 
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   double pq = 0.0, rp = 0.0;
   if (r < lv.n) {
+    const Coords c = coords_of(r, lv.nx, lv.nxy);
+    double v[NQ];
+    gather_lv(lv, c, r, p, v);
+    const double rr = rv[r];
     const uint32_t m = mask[r];
     if (!(m & SOLID_BIT)) {
-      const Coords c = coords_of(r, lv.nx, lv.nxy);
-      const double qr = apply_A<double>(lv, r, m, c, p);
+      const double qr = apply_A_v<double>(lv, m, v);
       q[r] = qr;
-      pq = p[r] * qr;
-      rp = rv[r] * p[r];
+      pq = v[0] * qr;
+      rp = rr * v[0];
     }
   }
   pq = block_sum(pq, sm);
@@ -284,15 +294,11 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
   if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= lv.n) return;
-  const uint32_t m = mask[r];
-  if (m & SOLID_BIT) {
-    x_out[r] = T(0);
-    return;
-  }
   const Coords c = coords_of(r, lv.nx, lv.nxy);
   T v[NQ];
   gather_lv(lv, c, r, x_in, v);
   const T rr = rhs[r];
+  const uint32_t m = mask[r];
   T num = T(0), den = T(0);
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
@@ -303,9 +309,10 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
   }
   num += hs * rr;
   const T xr = v[0];
-  const T res = xr + omega * (num / den - xr);
+  const bool solid = m & SOLID_BIT;
+  const T res = solid ? T(0) : xr + omega * (num / den - xr);
   x_out[r] = res;
-  if (phi_add) phi_add[r] += double(res);
+  if (phi_add && !solid) phi_add[r] += double(res);
 }
 
 // ---- restriction: coarse rhs = mean of the fluid children's residuals -------
@@ -323,16 +330,22 @@ __device__ __forceinline__ void restrict_child(const MgTransfer &tr, int R, int 
                                                const T *__restrict__ ef, T &v, int &cnt) {
   const Coords C = coords_of(R, tr.c.nx, tr.c.nxy);
   const int xp = 2 * C.x + (j & 1), yp = 2 * C.y + ((j >> 1) & 1), zp = 2 * C.z + (j >> 2);
-  if (xp >= tr.f.nx || yp >= tr.f.ny || zp >= tr.f.nz) return;
+  const bool inside = xp < tr.f.nx && yp < tr.f.ny && zp < tr.f.nz;
+  // a child beyond an odd-sized level reads a valid cell and is dropped
   Coords c;
-  c.x = wrapi(xp + tr.ox, tr.f.nx);
-  c.y = wrapi(yp + tr.oy, tr.f.ny);
-  c.z = wrapi(zp + tr.oz, tr.f.nz);
+  c.x = wrapi(min(xp, tr.f.nx - 1) + tr.ox, tr.f.nx);
+  c.y = wrapi(min(yp, tr.f.ny - 1) + tr.oy, tr.f.ny);
+  c.z = wrapi(min(zp, tr.f.nz - 1) + tr.oz, tr.f.nz);
   const int r = c.x + tr.f.nx * (c.y + tr.f.ny * c.z);
+  T e[NQ];
+  gather_lv(tr.f, c, r, ef, e);
+  const T rr = rf[r];
   const uint32_t m = mf[r];
-  if (m & SOLID_BIT) return;
-  v = rf[r] - apply_A<T>(tr.f, r, m, c, ef);
-  cnt = 1;
+  const T res = rr - apply_A_v<T>(tr.f, m, e);
+  if (inside && !(m & SOLID_BIT)) {
+    v = res;
+    cnt = 1;
+  }
 }
 
 // sum of v and cnt over the eight lanes of an aligned group
@@ -359,8 +372,12 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(MgTransfer tr, const uint32_
   int cnt = 0;
   bool fluid = false;
   if (R < tr.c.n) {
+    restrict_child<T>(tr, R, j, mf, rf, ef, v, cnt);
     fluid = !(mc[R] & SOLID_BIT);
-    if (fluid) restrict_child<T>(tr, R, j, mf, rf, ef, v, cnt);
+    if (!fluid) {
+      v = T(0);
+      cnt = 0;
+    }
   }
   group8_sum(v, cnt);
   if (j == 0 && R < tr.c.n) {
@@ -431,9 +448,9 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(MgTransfer tr, const uint32_t
   if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= tr.f.n) return;
-  if (mf[r] & SOLID_BIT) return;
   const T e0 = ef[r];
-  ef[r] = e0 + prolong_value<T>(tr, r, mc, ec);
+  const T pv = prolong_value<T>(tr, r, mc, ec);
+  if (!(mf[r] & SOLID_BIT)) ef[r] = e0 + pv;
 }
 
 // ---- coarsest level: one work-group, sweeps with barriers ----------------------
@@ -550,13 +567,14 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
   const uint32_t *mk = sm + S.off_m[k];
   const T hs = T(lv.h2 / 6.0);
   if (S.jacobi > 0.0) {
-    // Jacobi in pairs e -> e2 -> e, the arithmetic of k_jacobi
+    // Jacobi alternating e -> e2 -> e ..., the arithmetic of k_jacobi; an odd
+    // count ends with a copy back into e
     T *e2 = lds + S.off_e2[k];
     const T om = T(S.jacobi);
-    for (int s = 0; s < sweeps; s += 2)
-      for (int pass = 0; pass < 2; ++pass) {
-        const T *xi = pass ? e2 : e;
-        T *xo = pass ? e : e2;
+    for (int s = 0; s < sweeps; ++s) {
+      {
+        const T *xi = (s & 1) ? e2 : e;
+        T *xo = (s & 1) ? e : e2;
         for (int r = threadIdx.x; r < lv.n; r += SMALL_BLOCK) {
           const uint32_t m = mk[r];
           if (m & SOLID_BIT) {
@@ -579,6 +597,11 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
         }
         __syncthreads();
       }
+    }
+    if (sweeps & 1) {
+      for (int r = threadIdx.x; r < lv.n; r += SMALL_BLOCK) e[r] = e2[r];
+      __syncthreads();
+    }
     return;
   }
   // four-colour Gauss-Seidel

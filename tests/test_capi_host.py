@@ -55,7 +55,8 @@ def _slab_params(**kw):
                                 dict(D=(0.05, -1.0)), dict(Eapp=(np.nan, 0, 0)),
                                 dict(precision=7), dict(poisson=9), dict(flags=16),
                                 dict(flags=8),  # Krylov acceleration needs multigrid
-                                dict(poisson=1, mg_levels=1), dict(poisson=1, mg_nu1=0, mg_nu2=0)])
+                                dict(poisson=1, mg_levels=1), dict(poisson=1, mg_nu1=0, mg_nu2=0),
+                                dict(poisson=1, mg_nu1_coarse=-1)])
 def test_invalid_parameters_rejected(kw):
     p, t, ps = _slab_params(**kw)
     with pytest.raises(lbe.LbeError) as e:

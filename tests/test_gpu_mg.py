@@ -24,13 +24,31 @@ MG_TOL = 2e-11
 MG_QTOL = 1e-8
 
 
-def mg_pair(name, tol=1e-14, steps=None):
+def mg_pair(name, tol=1e-14, steps=None, **sweeps):
     kw, shape, t, ps, n0, nref, nsteps, _ = G.case(name)
     o = oracle.Oracle(oracle.make_params(shape, **kw, tol=tol, max_iter=10**6, check_every=1), t,
                       ps, n0, nref)
+    nu = dict(mg_nu1=2, mg_nu2=2)
+    nu.update(sweeps)
     g = lbe.Lbe(lbe.make_params(shape, **kw, tol=tol, max_iter=200, poisson=lbe.MG, mg_levels=0,
-                                mg_nu1=2, mg_nu2=2), t, ps, n0, nref)
+                                **nu), t, ps, n0, nref)
     return o, g, (nsteps if steps is None else steps), t
+
+
+@pytest.mark.parametrize("sweeps", [dict(mg_nu1_coarse=1, mg_nu2_coarse=1),
+                                    dict(mg_nu1=1, mg_nu2=3, mg_nu1_coarse=3, mg_nu2_coarse=1)])
+@pytest.mark.parametrize("name", ["slab_4x4x34", "coax_16x16x4"])
+def test_mg_sweep_counts_same_fixed_point(name, sweeps):
+    """Other smoothing counts (odd ones, and fewer sweeps on the coarser
+    levels) change the cycle, not its fixed point: the oracle's within the
+    multigrid bounds."""
+    o, g, nsteps, t = mg_pair(name, **sweeps)
+    o.step(nsteps)
+    g.step(nsteps)
+    fo, fg = o.fields(), g.fields()
+    assert rel(fg["phi"], fo["phi"], 0.1) <= MG_TOL
+    assert rel(fg["n"], fo["n"]) <= MG_TOL
+    assert rel(g.qhist(), o.qhist()) <= MG_QTOL
 
 
 @pytest.mark.parametrize("name", ["slab_4x4x34", "coax_16x16x4", "random_6x10x14_k3",
