@@ -202,9 +202,14 @@ int lbe_set_electrode_potential(lbe_ctx *ctx, const double *phi_s);
  * record.  Errors: LBE_EINVAL for nsteps < 0 or every < 1; LBE_ENOMEM; the
  * errors of lbe_step (then no record is kept).
  *
- * lbe_adjoint returns the gradient of L = sum_e qbar[e] Q_e(t1), with Q_e
- * the charges of Eq. 16 at the end t1 of the record (qbar: nelectrodes
- * weights), with respect to
+ * lbe_adjoint returns the gradient of
+ *   L = sum_e qbar[e] Q_e(t1) + sum_a ubar[a] M_a(t1),
+ * with Q_e the charges of Eq. 16 at the end t1 of the record (qbar:
+ * nelectrodes weights, NULL = 0) and M the total fluid momentum
+ * sum_r (sum_i f_i c_i + F/2), i.e. the mass flux of the velocity of Guo
+ * forcing over all fluid nodes (ubar: 3 weights, NULL = 0; under an applied
+ * field its component along the field is the electro-osmotic flux), with
+ * respect to
  *   grad_phi_s (N): the potential of every solid node (0 on fluid nodes;
  *     the derivative with respect to one electrode's voltage is the sum
  *     over its nodes);
@@ -226,13 +231,14 @@ int lbe_set_electrode_potential(lbe_ctx *ctx, const double *phi_s);
  * context is left at t1, and the record stays valid for further calls with
  * other weights until the state moves (lbe_step, lbe_record,
  * lbe_set_electrode_potential).
- * Errors: LBE_EINVAL for NULL qbar, a non-finite weight, no valid record, no
- * electrode or l_B = 0; LBE_ENOMEM; LBE_ENOCONV / LBE_ENONFINITE from a
- * recomputed step or an adjoint solve.
+ * Errors: LBE_EINVAL for qbar and ubar both NULL, a non-finite weight, no
+ * valid record, charge weights without an electrode, or l_B = 0;
+ * LBE_ENOMEM; LBE_ENOCONV / LBE_ENONFINITE from a recomputed step or an
+ * adjoint solve.
  */
 int lbe_record(lbe_ctx *ctx, int64_t nsteps, int32_t every);
-int lbe_adjoint(lbe_ctx *ctx, const double *qbar, double *grad_phi_s, double *grad_lB,
-                double *grad_n, double *grad_f);
+int lbe_adjoint(lbe_ctx *ctx, const double *qbar, const double *ubar, double *grad_phi_s,
+                double *grad_lB, double *grad_n, double *grad_f);
 
 /* Charge of each electrode, in units of e, from Gauss's law on the current
  * potential (Eq. 16 with the Laplacian of Eq. 15 taken on the electrode's

@@ -159,11 +159,12 @@ class ComplexLBE:
         return q
 
     # ---- one time step (Eqs. 7-10) ------------------------------------------
-    def step(self):
-        fl = self.fluid
-        n, phi, f = self.n, self.phi, self.f
+    def _link_terms(self):
+        """Force on the fluid (excess link fluxes projected on the node) and
+        the sum over links of each species' diffusion-migration flux."""
+        n, phi = self.n, self.phi
         force = np.zeros((3,) + self.shape3, complex)
-        flux = np.zeros_like(n)  # sum over links of the diffusion-migration flux
+        flux = np.zeros_like(n)
         for i in range(1, 19):
             link = self.ff[i]
             Ec = float(self.E @ _C[i])
@@ -177,6 +178,19 @@ class ComplexLBE:
                 flux[k] += self.d[k] * np.where(link, g - (n_there[k] - n[k]) / _LEN[i], 0.0)
             for a in range(3):
                 force[a] += 3.0 * _W[i] * _C[i, a] * _LEN[i] * g_sum
+        return force, flux
+
+    def momentum(self):
+        """Total fluid momentum sum_r (sum_i f_i c_i + F/2) of the current
+        state (the mass flux of the velocity of Guo forcing), 3 values."""
+        force, _ = self._link_terms()
+        mom = np.tensordot(_C.T.astype(float), self.f, axes=1) + 0.5 * force
+        return np.array([mom[a][self.fluid].sum() for a in range(3)])
+
+    def step(self):
+        fl = self.fluid
+        n, f = self.n, self.f
+        force, flux = self._link_terms()
         rho = f.sum(0)
         mom = np.tensordot(_C.T.astype(float), f, axes=1)
         safe = np.where(fl, rho, 1.0)

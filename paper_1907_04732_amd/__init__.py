@@ -90,7 +90,7 @@ def load(path: str = LIB_PATH):
     lib.lbe_set_electrode_potential.restype = C.c_int
     lib.lbe_record.argtypes = [C.c_void_p, C.c_int64, C.c_int32]
     lib.lbe_record.restype = C.c_int
-    lib.lbe_adjoint.argtypes = [C.c_void_p, d, d, d, d, d]
+    lib.lbe_adjoint.argtypes = [C.c_void_p, d, d, d, d, d, d]
     lib.lbe_adjoint.restype = C.c_int
     lib.lbe_electrode_charge.argtypes = [C.c_void_p, d, C.c_int32]
     lib.lbe_electrode_charge.restype = C.c_int
@@ -245,19 +245,24 @@ class Lbe:
         adjoint() (FP64 form)."""
         self._check(self._lib.lbe_record(self.h, int(nsteps), int(every)))
 
-    def adjoint(self, qbar, phi_s=True, lB=True, n=True, f=True):
-        """Gradient of sum_e qbar[e] Q_e at the end of the record: dict with
-        phi_s (N), lB (float), n (K, N) at the record's start and f (19, N),
-        the pre-collision populations at its start (each only if asked)."""
-        qb = np.ascontiguousarray(qbar, dtype=np.float64).reshape(-1)
-        if qb.size != self.ne:
+    def adjoint(self, qbar=None, ubar=None, phi_s=True, lB=True, n=True, f=True):
+        """Gradient of sum_e qbar[e] Q_e + ubar . M at the end of the record
+        (M: total fluid momentum, sum_i f_i c_i + F/2 over fluid nodes): dict
+        with phi_s (N), lB (float), n (K, N) at the record's start and f
+        (19, N), the pre-collision populations at its start (each only if
+        asked)."""
+        qb = None if qbar is None else np.ascontiguousarray(qbar, dtype=np.float64).reshape(-1)
+        ub = None if ubar is None else np.ascontiguousarray(ubar, dtype=np.float64).reshape(-1)
+        if qb is not None and qb.size != self.ne:
             raise ValueError("one weight per electrode")
+        if ub is not None and ub.size != 3:
+            raise ValueError("three momentum weights")
         g_ps = np.empty(self.N) if phi_s else None
         g_lb = np.zeros(1) if lB else None
         g_n = np.empty(self.K * self.N) if n else None
         g_f = np.empty(19 * self.N) if f else None
-        self._check(self._lib.lbe_adjoint(self.h, _dptr(qb), _dptr(g_ps), _dptr(g_lb), _dptr(g_n),
-                                          _dptr(g_f)))
+        self._check(self._lib.lbe_adjoint(self.h, _dptr(qb), _dptr(ub), _dptr(g_ps), _dptr(g_lb),
+                                          _dptr(g_n), _dptr(g_f)))
         out = {}
         if phi_s:
             out["phi_s"] = g_ps

@@ -1,8 +1,9 @@
 // lbe_adjoint.hip -- reverse-mode (adjoint) kernels of the FP64 time step
 // (gfx950).  They give the gradient of a weighted sum of electrode charges
-// L = sum_e qbar_e Q_e(T) (Eq. 16) with respect to the electrode potentials,
-// the Bjerrum length and the initial state, by running the step of
-// Secs. II B-C backwards.
+// and of the fluid momentum, L = sum_e qbar_e Q_e(T) (Eq. 16) +
+// ubar . sum_r rho u(r, T), with respect to the electrode potentials, the
+// Bjerrum length and the initial state, by running the step of Secs. II B-C
+// backwards.
 //
 // State at time t: stored (post-collision, pull-form) populations P_t, ion
 // concentrations n_t, and phi_t = Phi(n_t), the Poisson solution for n_t.
@@ -297,9 +298,9 @@ __global__ __launch_bounds__(FINAL) void k_adj_accumulate(const double *__restri
   if (threadIdx.x == 0) acc[0] += scale * v;
 }
 
-// Seed of the reverse sweep, L = sum_e qbar_e Q_e:
+// Seed of the reverse sweep from the charges, L = sum_e qbar_e Q_e:
 //  fluid r:  dL/dphi(r) = q_scale wall sum over links to an electrode node r'
-//            of w_i qbar_{e(r')}, stored as the adjoint solve's source -phib/6;
+//            of w_i qbar_{e(r')}, added to the adjoint solve's source as -phib/6;
 //  solid r:  the explicit derivative -q_scale wall qbar_e sum over links to
 //            fluid nodes of w_i (phi_s(r) enters Eq. 16 directly).
 __global__ __launch_bounds__(BLOCK) void k_adj_seed(Lattice L, double q_scale,
@@ -318,13 +319,30 @@ __global__ __launch_bounds__(BLOCK) void k_adj_seed(Lattice L, double q_scale,
     for (int i = 1; i < NQ; ++i)
       if (!solid_link(m, i)) acc += WQ[i];
     gphis[r] = -q_scale * L.wall * qbar[type[r] - 1] * acc;
-    src[r] = 0.0;
     return;
   }
   for (int i = 1; i < NQ; ++i)
     if (solid_link(m, i)) acc += WQ[i] * qbar[type[nbr(o, r, i)] - 1];
   gphis[r] = 0.0;
-  src[r] = -(q_scale * L.wall * acc) / 6.0;
+  src[r] += -(q_scale * L.wall * acc) / 6.0;  // after the momentum seed's share
+}
+
+// Seed of the momentum term ubar . sum_r (sum_i f_i c_i + F/2) at fluid
+// nodes: the population adjoint c_i . ubar and the force adjoint ubar / 2
+// (which k_adj_ions then carries to n and phi through the link fluxes).
+__global__ __launch_bounds__(BLOCK) void k_adj_seed_momentum(Lattice L,
+                                                             const uint32_t *__restrict__ mask,
+                                                             double ux, double uy, double uz,
+                                                             double *__restrict__ abar,
+                                                             double *__restrict__ fbar) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n || (mask[r] & SOLID_BIT)) return;
+  const int N = L.n;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) abar[i * N + r] = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+  fbar[r] = 0.5 * ux;
+  fbar[N + r] = 0.5 * uy;
+  fbar[2 * N + r] = 0.5 * uz;
 }
 
 // gphis(r) += -6 wall sum over links to fluid nodes r' of w_i lam_sum(r'):
@@ -425,6 +443,13 @@ hipError_t launch_adj_seed(hipStream_t s, const Lattice &L, double q_scale, cons
                            const uint8_t *type, const double *qbar, double *src, double *gphis) {
   hipLaunchKernelGGL(k_adj_seed, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, q_scale, mask, type,
                      qbar, src, gphis);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_seed_momentum(hipStream_t s, const Lattice &L, const uint32_t *mask,
+                                    const double *ubar, double *abar, double *fbar) {
+  hipLaunchKernelGGL(k_adj_seed_momentum, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, mask,
+                     ubar[0], ubar[1], ubar[2], abar, fbar);
   return hipGetLastError();
 }
 

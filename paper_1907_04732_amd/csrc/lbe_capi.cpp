@@ -1176,8 +1176,8 @@ int adjoint_fold(lbe_ctx *c, const S *n, double *nbar) {
 
 // The reverse sweep of lbe_adjoint; the caller restores the end state.
 template <class S>
-int adjoint_sweep(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *grad_lB,
-                  double *grad_n, double *grad_f) {
+int adjoint_sweep(lbe_ctx *c, const double *qbar, const double *ubar, double *grad_phi_s,
+                  double *grad_lB, double *grad_n, double *grad_f) {
   lbe_ctx::Tape &T = c->tape;
   const size_t N = c->L.n, K = c->K;
   const StateLayout ck = checkpoint_layout(c), sl = slot_layout(c);
@@ -1190,8 +1190,24 @@ int adjoint_sweep(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *gr
   HIPCHK(c, hipMemsetAsync(c->lam, 0, sizeof(double) * N, c->stream));
   HIPCHK(c, hipMemsetAsync(c->lam_sum, 0, sizeof(double) * N, c->stream));
   HIPCHK(c, hipMemsetAsync(c->lb_acc, 0, sizeof(double), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->src, 0, sizeof(double) * N, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->adj_u, 0, sizeof(double) * 3 * N, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->qbar_d, qbar, sizeof(double) * c->ne, hipMemcpyHostToDevice,
                            c->stream));
+  // the momentum term: seed A and Fb, then carry Fb through the link fluxes
+  // of the end state (zero concentration adjoint) into nb and the source
+  if (ubar[0] != 0.0 || ubar[1] != 0.0 || ubar[2] != 0.0) {
+    if ((rc = run(c, KK_ADJ_SEED, c->L.n, [&] {
+           return launch_adj_seed_momentum(c->stream, c->L, c->mask, ubar, c->abar[0], c->fbar);
+         })))
+      return rc;
+    if ((rc = run(c, KK_ADJ_IONS, c->L.n, [&] {
+           return launch_adj_ions<S>(c->stream, c->L, c->P, c->mask, c->phi,
+                                     (const S *)cur_concs(c), c->adj_u, c->fbar, c->nbar[1],
+                                     c->nbar[0], c->src);
+         })))
+      return rc;
+  }
   // dQ_e/dl_B = -Q_e / l_B at fixed potential (Eq. 16)
   std::vector<double> qend(c->ne);
   HIPCHK(c, hipMemcpyAsync(qend.data(), c->qhist + (c->qlen - 1) * c->ne,
@@ -1698,17 +1714,22 @@ int lbe_record(lbe_ctx *c, int64_t nsteps, int32_t every) {
   return LBE_OK;
 }
 
-int lbe_adjoint(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *grad_lB,
-                double *grad_n, double *grad_f) {
-  if (!c || !qbar) return fail(c, LBE_EINVAL, "bad arguments");
+int lbe_adjoint(lbe_ctx *c, const double *qbar, const double *ubar, double *grad_phi_s,
+                double *grad_lB, double *grad_n, double *grad_f) {
+  if (!c || (!qbar && !ubar)) return fail(c, LBE_EINVAL, "bad arguments");
   lbe_ctx::Tape &T = c->tape;
   if (T.t0 < 0) return fail(c, LBE_EINVAL, "no recorded steps (lbe_record)");
   if (c->step != T.t0 + T.nsteps || c->qlen < 1)
     return fail(c, LBE_EINVAL, "the state is not the end of the recorded steps");
-  if (c->ne == 0) return fail(c, LBE_EINVAL, "no electrode charge to differentiate");
+  if (c->ne == 0 && !ubar) return fail(c, LBE_EINVAL, "no electrode charge to differentiate");
   if (!(c->p.lB > 0.0)) return fail(c, LBE_EINVAL, "reverse mode needs l_B > 0");
-  for (int e = 0; e < c->ne; ++e)
-    if (!std::isfinite(qbar[e])) return fail(c, LBE_EINVAL, "non-finite charge weight");
+  std::vector<double> qb(std::max(c->ne, 1), 0.0), ub(3, 0.0);
+  for (int e = 0; e < c->ne && qbar; ++e) qb[e] = qbar[e];
+  for (int a = 0; a < 3 && ubar; ++a) ub[a] = ubar[a];
+  for (double v : qb)
+    if (!std::isfinite(v)) return fail(c, LBE_EINVAL, "non-finite charge weight");
+  for (double v : ub)
+    if (!std::isfinite(v)) return fail(c, LBE_EINVAL, "non-finite momentum weight");
   int rc = adjoint_buffers(c);
   if (rc) return rc;
   HIPCHK(c, hipMemcpyAsync(c->src_keep, c->src, sizeof(double) * c->L.n, hipMemcpyDeviceToDevice,
@@ -1716,8 +1737,8 @@ int lbe_adjoint(lbe_ctx *c, const double *qbar, double *grad_phi_s, double *grad
   const int keep_iters = c->last_iters, keep_pred = c->pred_iters;
   const double keep_resid = c->last_resid;
   const int64_t keep_total = c->total_iters;
-  rc = c->mixed ? adjoint_sweep<float>(c, qbar, grad_phi_s, grad_lB, grad_n, grad_f)
-                : adjoint_sweep<double>(c, qbar, grad_phi_s, grad_lB, grad_n, grad_f);
+  rc = c->mixed ? adjoint_sweep<float>(c, qb.data(), ub.data(), grad_phi_s, grad_lB, grad_n, grad_f)
+                : adjoint_sweep<double>(c, qb.data(), ub.data(), grad_phi_s, grad_lB, grad_n, grad_f);
   // back to the end of the recorded steps, whatever happened
   const int rc2 = load_state(c, T.ck + (size_t)T.nck * checkpoint_layout(c).bytes);
   c->extrap_hist = T.hist[(size_t)T.nck];

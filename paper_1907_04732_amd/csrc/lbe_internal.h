@@ -225,8 +225,13 @@ template <class S>
 hipError_t launch_adj_fold(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                            const double *lam, const S *n, double *nbar, double *lam_sum,
                            double *lam_keep, double *partial, double *lb_acc);
+// charge seed: adds its share of the adjoint source to src (solid entries
+// untouched), writes the explicit phi_s gradient
 hipError_t launch_adj_seed(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
                            const uint8_t *type, const double *qbar, double *src, double *gphis);
+// momentum seed (ubar: 3 host values): abar = c_i . ubar, fbar = ubar / 2 on fluid nodes
+hipError_t launch_adj_seed_momentum(hipStream_t s, const Lattice &L, const uint32_t *mask,
+                                    const double *ubar, double *abar, double *fbar);
 hipError_t launch_adj_phis(hipStream_t s, const Lattice &L, const uint32_t *mask,
                            const double *lam_sum, double *gphis);
 

@@ -102,6 +102,55 @@ def test_adjoint_matches_tangent_oracle(kind, solver):
         g.adjoint(np.ones(g.ne))
 
 
+@pytest.mark.parametrize("kind", ["k2_field", "k3_naive"])
+def test_momentum_adjoint_matches_tangent_oracle(kind):
+    """Gradient of the total fluid momentum sum_r (sum_i f_i c_i + F/2) at the
+    end (under the applied field, its component along the field is the
+    electro-osmotic flux), each component in turn, against the tangent
+    oracle along the voltage, l_B, random phi_s, n(0) and f(0); and the
+    gradient of a combined charge + momentum objective is the sum of the
+    two.  FP64 multigrid with flexible CG and the extrapolated start.
+    Bound 1e-7 of the largest derivative: the momentum is ~1e-4 and its
+    derivatives come through the force, which the Poisson tolerance moves by
+    ~1e-12 relative, with rounding in sums of ~1e-5-sized terms."""
+    case = G.adjoint_case(kind)
+    shape, t, ps, n0, f0, kw, flags = case
+    steps = 12
+    g = _lbe(*case, poisson=lbe.MG, max_iter=400, extra_flags=lbe.KRYLOV | lbe.EXTRAPOLATE)
+    g.record(steps, every=5)
+    rng = np.random.default_rng(17)
+    fluid = t == 0
+    dirs = {"V1": dict(dphi_s=(t == 1).astype(float)), "lB": dict(dlB=1.0),
+            "phi_s": dict(dphi_s=rng.standard_normal(t.size) * (~fluid)),
+            "n0": dict(dn=1e-3 * rng.standard_normal(n0.shape) * fluid),
+            "f0": dict(df=1e-2 * rng.standard_normal(f0.shape) * fluid)}
+    tp = dict(kw)
+    tp["wall"] = 1.0 if flags & lbe.NAIVE_DIRICHLET else 2.0
+    dm = {}
+    for name, d in dirs.items():
+        _, _, s_ = TG.charge_tangent(shape, tp, t, ps, n0, f0, steps, **d)
+        dm[name] = s_.momentum().imag / TG.STEP
+
+    def project(gr):
+        return {"V1": gr["phi_s"][t == 1].sum(), "lB": gr["lB"],
+                "phi_s": gr["phi_s"] @ dirs["phi_s"]["dphi_s"],
+                "n0": (gr["n"] * dirs["n0"]["dn"]).sum(), "f0": (gr["f"] * dirs["f0"]["df"]).sum()}
+
+    for a in range(3):
+        ubar = np.zeros(3)
+        ubar[a] = 1.0
+        got = project(g.adjoint(ubar=ubar))
+        scale = max(abs(dm[n][a]) for n in dm)
+        for name in dm:
+            assert abs(got[name] - dm[name][a]) <= 1e-7 * scale, (a, name, got[name], dm[name][a])
+    qbar = np.linspace(1.0, -0.5, g.ne)
+    ubar = np.array([0.3, -2.0, 1.1])
+    both, q_only, u_only = g.adjoint(qbar, ubar), g.adjoint(qbar), g.adjoint(ubar=ubar)
+    for key in ("phi_s", "n", "f"):
+        ref = q_only[key] + u_only[key]
+        assert np.abs(both[key] - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
 def test_adjoint_porous_crop_matches_tangent_oracle():
     """A 24^3 crop of the porous electrode (sphere caps of electrode 1 and the
     first planes of the counter-electrode), FP64 multigrid with flexible CG
@@ -205,7 +254,7 @@ def test_autograd_function():
     """torch.autograd: backward() equals lbe_adjoint; gradcheck in fast mode
     (one random projection checked by central differences of the forward)."""
     import torch
-    from paper_1907_04732_amd.autograd import electrode_charge
+    from paper_1907_04732_amd.autograd import charge_and_momentum, electrode_charge
 
     shape, t, ps, n0, f0, kw, flags = G.adjoint_case("k2_field")
     kw = dict(kw)
@@ -229,6 +278,15 @@ def test_autograd_function():
     fn = lambda a, b, c, d: electrode_charge(a, b, c, d, **opts)  # noqa: E731
     assert torch.autograd.gradcheck(fn, tuple(v.detach().requires_grad_() for v in x),
                                     eps=1e-6, atol=1e-7, rtol=1e-5, fast_mode=True)
+    # the momentum output: backward equals lbe_adjoint with momentum weights
+    y = [v.detach().requires_grad_() for v in x]
+    q2, m2 = charge_and_momentum(*y, **opts)
+    wm = torch.tensor([1.5, 0.0, -0.7], dtype=torch.float64)
+    ((q2 * w).sum() + (m2 * wm).sum()).backward()
+    ref = g.adjoint(w.numpy(), wm.numpy())
+    assert np.abs(y[0].grad.numpy() - ref["phi_s"]).max() <= 1e-12 * np.abs(ref["phi_s"]).max()
+    assert np.abs(y[2].grad.numpy() - ref["n"]).max() <= 1e-12 * np.abs(ref["n"]).max()
+    assert np.abs(y[3].grad.numpy() - ref["f"]).max() <= 1e-12 * np.abs(ref["f"]).max()
 
 
 def test_differential_capacitance_at_steady_state():

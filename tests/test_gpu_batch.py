@@ -101,3 +101,31 @@ def test_batch_mixed_form_against_oracle():
     for s in range(len(b.L)):
         m = (b.system == s) & (b.node_type == 0)
         assert rel(fg["n"][:, m], fo["n"][:, m]) <= 1e-5, s
+
+
+@pytest.mark.parametrize("precision", [lbe.FP64, lbe.FP32_MIXED])
+def test_batch_reverse_mode(precision):
+    """Reverse mode on the packed lattice: the gradient of one system's
+    charge is that system's own gradient (its run alone, same multigrid
+    settings, to the solver bound) and exactly zero on every other system's
+    nodes and on l_B's share from other systems (the systems do not couple,
+    and the coarse levels never merge two of them)."""
+    b = small_batch()
+    kw = dict(tol=1e-13, max_iter=200, poisson=lbe.MG, precision=precision)
+    g = gpu_batch(b, **kw)
+    g.record(24, every=10)
+    s = 2
+    qbar = np.zeros(2 * len(b.L))
+    qbar[2 * s] = 1.0  # bottom electrode of system s
+    gr = g.adjoint(qbar)
+    a, sl = _alone(b, s, **kw)
+    a.record(24, every=10)
+    ga = a.adjoint([1.0, 0.0])
+    inside = np.zeros(b.node_type.size, bool)
+    inside[sl] = True
+    assert not gr["phi_s"][~inside].any() and not gr["n"][:, ~inside].any()
+    assert not gr["f"][:, ~inside].any()
+    tol = 1e-9 if precision == lbe.FP64 else 1e-5
+    assert rel(gr["phi_s"][sl], ga["phi_s"]) <= tol
+    assert rel(gr["n"][:, sl], ga["n"]) <= tol
+    assert abs(gr["lB"] - ga["lB"]) <= tol * abs(ga["lB"])

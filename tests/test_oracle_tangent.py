@@ -162,3 +162,47 @@ def test_differential_capacitance_of_the_nonlinear_steady_state():
     assert abs(dq[1] / dq[0] + 1) < 1e-9
     # and it is not the linear (Debye-Hueckel) value: the pin sees the non-linearity
     assert abs(cdiff / T.dh_slab_capacitance(LB, debye, nf) - 1) > 0.05
+
+
+def _momentum_c(o, t):
+    F = o.fields()
+    return (F["u"] * F["rho"])[:, t == 0].sum(1)
+
+
+@pytest.mark.parametrize("kind", ["k2_field", "k3_naive"])
+def test_momentum_matches_oracle_and_differences(kind):
+    """The total fluid momentum sum_r (sum_i f_i c_i + F/2) (the mass flux of
+    the velocity of Guo forcing; under the applied field its component along
+    it is the electro-osmotic flux): real part against the C oracle's rho u,
+    derivatives along the voltage, l_B and random n(0), f(0) against central
+    differences of the C oracle."""
+    shape, t, ps, n0, f0, kw, flags = _case(kind)
+    steps = 10
+    o = _oracle(shape, t, ps, n0, f0, kw, flags)
+    o.step(steps)
+    rng = np.random.default_rng(9)
+    fluid = t == 0
+    dirs = {"V1": dict(dphi_s=(t == 1).astype(float)), "lB": dict(dlB=1.0),
+            "n0": dict(dn=1e-3 * rng.standard_normal(n0.shape) * fluid),
+            "f0": dict(df=1e-2 * rng.standard_normal(f0.shape) * fluid)}
+    m_c = _momentum_c(o, t)
+    for name, d in dirs.items():
+        _, _, s = TG.charge_tangent(shape, _tparams(kw, flags), t, ps, n0, f0, steps, **d)
+        m = s.momentum()
+        # rho u from u = (m + F/2) / rho rounds differently from m + F/2: ~1e-16 per site
+        assert np.abs(m.real - m_c).max() <= 1e-11 * np.abs(m_c).max() + 1e-15, (name, m, m_c)
+        h = 1e-5
+
+        def m_at(sgn):
+            kk = dict(kw)
+            kk["lB"] = kw["lB"] + sgn * h * d.get("dlB", 0.0)
+            oo = _oracle(shape, t, ps + sgn * h * d.get("dphi_s", 0.0),
+                         n0 + sgn * h * d.get("dn", 0.0), f0 + sgn * h * d.get("df", 0.0), kk, flags)
+            oo.step(steps)
+            return _momentum_c(oo, t)
+
+        fd = (m_at(1) - m_at(-1)) / (2 * h)
+        dm = m.imag / TG.STEP
+        # the momentum sum carries ~4e-16 of rounding, ~3e-11 after / 2h; the
+        # solves' 1e-14 residual adds as much
+        assert np.abs(dm - fd).max() <= 1e-7 * np.abs(fd).max() + 3e-10, (name, dm, fd)
