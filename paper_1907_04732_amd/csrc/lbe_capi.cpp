@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -46,7 +47,10 @@ struct lbe_ctx {
   double *dout = nullptr;  // small device results (totals)
   double *hpin = nullptr;  // pinned host mirror of dout
   SolveCtl *ctl = nullptr;    // device control block of the running Poisson solve
-  SolveCtl *ctl_h = nullptr;  // pinned host mirror
+  SolveCtl *ctl_h = nullptr;  // pinned host copy of it (what the driver reads)
+  SolveCtl *ctl_pub = nullptr;  // host-mapped copy the checks publish to (coherent)
+  SolveCtl *ctl_pub_d = nullptr;  // its device address
+  int checks_queued = 0;        // residual checks queued in the running solve
   int pred_iters = 0;         // iterations the last time-step solve needed
   bool use_graphs = true;     // replay one solver unit as a captured HIP graph
   hipGraphExec_t unit_exec = nullptr;
@@ -365,12 +369,42 @@ int read_scalars(lbe_ctx *c, int count) {
 }
 
 int reset_ctl(lbe_ctx *c) {
-  *c->ctl_h = SolveCtl{0.0, c->p.tol, 0, 0, 0, 0, 0, 0};
+  *c->ctl_h = SolveCtl{0.0, c->p.tol, 0, 0, 0, 0, 0, 0, c->ctl_pub_d};
+  if (c->ctl_pub) {
+    // nothing of an earlier solve is in flight: its last wait saw all its checks
+    volatile SolveCtl *v = c->ctl_pub;
+    v->done = 0;
+    v->checks = 0;
+  }
+  c->checks_queued = 0;
   HIPCHK(c, hipMemcpyAsync(c->ctl, c->ctl_h, sizeof(SolveCtl), hipMemcpyHostToDevice, c->stream));
   return LBE_OK;
 }
 
+// The state of the running solve after every check queued so far: polled
+// from the published copy (a check publishes when it ends, so the host learns
+// the outcome without a stream synchronisation); if nothing is published for
+// 100 ms, or there is no published copy, the block is copied back after a
+// synchronisation instead (same result, slower).
 int read_ctl(lbe_ctx *c) {
+  if (c->ctl_pub) {
+    volatile SolveCtl *v = c->ctl_pub;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (long spin = 0;; ++spin) {
+      if (v->done || v->checks >= c->checks_queued) {
+        c->ctl_h->done = v->done;
+        c->ctl_h->checks = v->checks;
+        c->ctl_h->resid = v->resid;
+        c->ctl_h->count = v->count;
+        c->ctl_h->iters = v->iters;
+        c->ctl_h->nonfinite = v->nonfinite;
+        return LBE_OK;
+      }
+      if ((spin & 1023) == 1023 &&
+          std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(100))
+        break;
+    }
+  }
   HIPCHK(c, hipMemcpyAsync(c->ctl_h, c->ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return LBE_OK;
@@ -394,6 +428,7 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
     int r2 = step(m);
     return r2 ? r2 : check(m);
   };
+  // every unit and the first check end in one residual check each
   auto unit_once = [&](int m) -> int {
     if (c->prof || !c->use_graphs || m != per_check) return unit_direct(m);
     if (!c->unit_exec) {
@@ -418,6 +453,7 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
     for (int it = 0; it < p.max_iter; it += per_check)
       if ((rc = step(std::min(per_check, p.max_iter - it)))) return rc;
     if ((rc = check(p.max_iter))) return rc;
+    c->checks_queued = 1;
     if ((rc = read_ctl(c))) return rc;
     c->last_iters = p.max_iter;
     c->last_resid = c->ctl_h->resid;
@@ -426,6 +462,7 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
     return LBE_OK;
   }
   if ((rc = check(0))) return rc;
+  c->checks_queued = 1;
   int queued = 0;
   // While profiling, one unit at a time with a read of the stop flag after
   // each, so that no timed launch is an early exit (the result is the same).
@@ -439,6 +476,7 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
     while (queued < target) {
       const int m = std::min(per_check, p.max_iter - queued);
       if ((rc = unit_once(m))) return rc;
+      c->checks_queued += 1;
       queued += m;
     }
     if ((rc = read_ctl(c))) return rc;
@@ -1300,6 +1338,7 @@ void free_ctx(lbe_ctx *c) {
   if (c->mg_fcell) (void)hipFree(c->mg_fcell);
   if (c->hpin) (void)hipHostFree(c->hpin);
   if (c->ctl_h) (void)hipHostFree(c->ctl_h);
+  if (c->ctl_pub) (void)hipHostFree(c->ctl_pub);
   for (int k = 0; k < KK_COUNT; ++k)
     for (auto &pr : c->pending[k]) {
       (void)hipEventDestroy(pr.a);
@@ -1541,6 +1580,15 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     if (hipHostMalloc((void **)&c->ctl_h, sizeof(SolveCtl)) != hipSuccess) {
       rc = fail(c, LBE_ENOMEM, "pinned host buffer");
       goto fail_;
+    }
+    // the published copy: coherent, device-mapped host memory (optional)
+    if (hipHostMalloc((void **)&c->ctl_pub, sizeof(SolveCtl),
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->ctl_pub_d, c->ctl_pub, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      if (c->ctl_pub) (void)hipHostFree(c->ctl_pub);
+      c->ctl_pub = nullptr;
+      c->ctl_pub_d = nullptr;
     }
     TRY(dalloc(c, &c->iface, g.iface.size()));
     TRY(dalloc(c, &c->blk_elec, g.blk_elec.size()));

@@ -171,6 +171,19 @@ __global__ __launch_bounds__(FINAL) void k_final_resid(const double *__restrict_
       ctl->iters = count;
       ctl->nonfinite = bad;
     }
+    // publish to the host: the values first, then (after a system-scope
+    // fence) the fields the host polls on
+    if (ctl->mirror) {
+      volatile SolveCtl *hm = ctl->mirror;
+      hm->resid = res;
+      hm->count = count;
+      hm->iters = ctl->iters;
+      hm->nonfinite = ctl->nonfinite;
+      __threadfence_system();
+      hm->done = ctl->done;
+      hm->checks = ctl->checks;
+      __threadfence_system();
+    }
   }
 }
 

@@ -78,7 +78,9 @@ struct MgTransfer {
 // Device-side control of one Poisson solve.  The residual check sets `done`
 // once ||R||_inf <= tol (or the residual is not finite); every kernel of the
 // solve returns at once when `done` is set, so the host can queue a predicted
-// number of sweeps or cycles and synchronise once.
+// number of sweeps or cycles and wait once.  Every check also publishes the
+// block to `mirror`, a host-mapped copy the host polls instead of copying the
+// block back and synchronising the stream.
 struct SolveCtl {
   double resid;   // last residual inf-norm
   double tol;     // <= 0: never done (fixed iteration count)
@@ -88,6 +90,7 @@ struct SolveCtl {
   int nonfinite;  // the residual was NaN or Inf
   int count;      // sweeps or cycles completed so far (each check adds its unit)
   int pad;
+  SolveCtl *mirror;  // host-mapped copy (device address), or null
 };
 
 // Flexible conjugate gradients preconditioned by one V-cycle (device state).
