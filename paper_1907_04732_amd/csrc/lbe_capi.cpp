@@ -833,7 +833,8 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
 // buffer holding e.  With phi_add (finest level), the last smoothing launch
 // also adds e to phi and *added is set; otherwise the caller adds it.
 template <class T>
-int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *added = nullptr) {
+int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *added = nullptr,
+              bool first_done = false) {
   lbe_ctx::MgDev &L = c->mg[l];
   T *A = (T *)L.e, *r = (T *)L.r;
   int rc;
@@ -883,7 +884,8 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
       }
     return LBE_OK;
   };
-  if ((rc = smooth(nu1, nullptr))) return rc;
+  // with first_done the correction already holds its first Jacobi sweep
+  if ((rc = smooth(first_done ? nu1 - 1 : nu1, nullptr))) return rc;
   lbe_ctx::MgDev &C = c->mg[l + 1];
   rc = run(c, KK_MG_RESTRICT, L.lv.n, [&] {
     return launch_mg_restrict<T>(c->stream, C.tr, L.mask, C.mask, r, cur, (T *)C.r, (T *)C.e,
@@ -946,17 +948,23 @@ int mg_solve(lbe_ctx *c, bool learn) {
           return run(c, KK_MG_RESID, n, [&] {
             return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi,
                                             (T *)L0.r, (T *)L0.e, c->partial, c->ctl, 0, c->kr,
-                                            c->kc);
+                                            c->kc, 0.0);
           });
         });
   }
+  // the residual check takes the V-cycle's first Jacobi sweep (from 0) on
+  // the finest level when that level is smoothed by the global kernels
+  const double first_sweep = (c->mg_jacobi > 0.0 && c->p.mg_nu1 >= 1 && c->mg.size() > 1 &&
+                              c->mg_small_from != 0)
+                                 ? c->mg_jacobi
+                                 : 0.0;
   return run_solve(
       c, 1, learn, "cycles",
       [&](int m) -> int {
         for (int k = 0; k < m; ++k) {
           T *e0 = nullptr;
           bool added = false;
-          int rc = mg_vcycle<T>(c, 0, &e0, c->phi, &added);
+          int rc = mg_vcycle<T>(c, 0, &e0, c->phi, &added, first_sweep > 0.0);
           if (rc) return rc;
           if (added) continue;  // the last smoothing launch has corrected phi
           rc = run(c, KK_CORRECT, L0.lv.n, [&] {
@@ -970,7 +978,8 @@ int mg_solve(lbe_ctx *c, bool learn) {
       [&](int add) -> int {
         return run(c, KK_MG_RESID, L0.lv.n, [&] {
           return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi, (T *)L0.r,
-                                          (T *)L0.e, c->partial, c->ctl, add, nullptr, nullptr);
+                                          (T *)L0.e, c->partial, c->ctl, add, nullptr, nullptr,
+                                          first_sweep);
         });
       });
 }
@@ -1017,7 +1026,7 @@ int mixed_sor_solve(lbe_ctx *c, bool learn) {
         return run(c, KK_MG_RESID, L0.lv.n, [&] {
           return launch_mg_outer_resid<float>(c->stream, L0.lv, c->mask, c->src, c->phi,
                                               (float *)L0.r, (float *)L0.e, c->partial, c->ctl,
-                                              add, nullptr, nullptr);
+                                              add, nullptr, nullptr, 0.0);
         });
       });
 }

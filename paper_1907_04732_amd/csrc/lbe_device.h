@@ -172,7 +172,8 @@ __global__ __launch_bounds__(FINAL) void k_final_resid(const double *__restrict_
       ctl->nonfinite = bad;
     }
     // publish to the host: the values first, then (after a system-scope
-    // fence) the fields the host polls on
+    // fence) the fields the host polls on, which the end of the kernel
+    // makes visible at the latest
     if (ctl->mirror) {
       volatile SolveCtl *hm = ctl->mirror;
       hm->resid = res;
@@ -182,7 +183,6 @@ __global__ __launch_bounds__(FINAL) void k_final_resid(const double *__restrict_
       __threadfence_system();
       hm->done = ctl->done;
       hm->checks = ctl->checks;
-      __threadfence_system();
     }
   }
 }

@@ -239,11 +239,14 @@ hipError_t launch_adj_phis(hipStream_t s, const Lattice &L, const uint32_t *mask
                            const double *lam_sum, double *gphis);
 
 // multigrid (lbe_mg.hip); T = double (FP64 form) or float (mixed form)
+// FP64 residual check; writes the correction's right-hand side r0 and its
+// start e0: 0, or with jacobi > 0 the result of one Jacobi sweep of that
+// weight from 0 (pointwise), so a V-cycle can skip its first sweep
 template <class T>
 hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
                                  const double *src, const double *phi, T *r0, T *e0,
                                  double *partial, SolveCtl *ctl, int add, double *r64,
-                                 KrylovCtl *kc);
+                                 KrylovCtl *kc, double jacobi);
 // Flexible CG on A e = R (A = -L_h, level 0), preconditioner z = V-cycle(r):
 //   beta = -(z, q_prev) / (p_prev, q_prev) (0 for the first direction),
 //   p = z + beta p,  q = A p,  alpha = (r, p) / (p, q),

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
                                                        double *__restrict__ partial,
                                                        const SolveCtl *__restrict__ ctl,
                                                        double *__restrict__ r64,
-                                                       KrylovCtl *__restrict__ kc) {
+                                                       KrylovCtl *__restrict__ kc, T jacobi) {
   __shared__ double sm[BLOCK / WAVE];
   if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
@@ -115,8 +115,25 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
     }
     const double R = (m & SOLID_BIT) ? 0.0 : 6.0 * (acc + sr);
     a = fabs(R);
-    r0[r] = T(R);
-    e0[r] = T(0);
+    const T rr = T(R);
+    r0[r] = rr;
+    // the correction starts at 0; with jacobi > 0 the V-cycle's first Jacobi
+    // sweep, which from 0 is pointwise, is taken here (the arithmetic of
+    // k_jacobi with every neighbour value 0)
+    T e = T(0);
+    if (jacobi > T(0) && !(m & SOLID_BIT)) {
+      T num = T(0), den = T(0);
+#pragma unroll
+      for (int i = 1; i < NQ; ++i) {
+        if ((lv.selfm >> (i - 1)) & 1u) continue;
+        const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
+        num += ws * T(0);
+        den += ws;
+      }
+      num += T(lv.h2 / 6.0) * rr;
+      e = T(0) + jacobi * (num / den - T(0));
+    }
+    e0[r] = e;
     if (r64) r64[r] = R;
   }
   a = block_max(a, sm);
@@ -735,10 +752,10 @@ template <class T>
 hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
                                  const double *src, const double *phi, T *r0, T *e0,
                                  double *partial, SolveCtl *ctl, int add, double *r64,
-                                 KrylovCtl *kc) {
+                                 KrylovCtl *kc, double jacobi) {
   const int nb = (int)blocks_for(lv.n);
   hipLaunchKernelGGL(k_outer_resid<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, src, phi, r0, e0,
-                     partial, ctl, r64, kc);
+                     partial, ctl, r64, kc, T(jacobi));
   hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
@@ -855,7 +872,7 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
   template hipError_t launch_mg_outer_resid<T>(hipStream_t, const MgLevel &, const uint32_t *,  \
                                                const double *, const double *, T *, T *,       \
                                                double *, SolveCtl *, int, double *,            \
-                                               KrylovCtl *);                                   \
+                                               KrylovCtl *, double);                           \
   template hipError_t launch_fcg_beta<T>(hipStream_t, int, const uint32_t *, const T *,         \
                                          const double *, double *, KrylovCtl *,                 \
                                          const SolveCtl *);                                     \
