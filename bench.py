@@ -45,7 +45,8 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False):
       ions (advection pass): K concentrations, K partial updates in, K new
       concentrations out, velocity in, Poisson source (FP64) out, flag word;
       with the extrapolated warm start also phi and the two previous
-      potentials in + out.  One colour of a four-colour SOR
+      potentials in + out, without it phi in and its kept copy out (the
+      state a failed step goes back to).  One colour of a four-colour SOR
       sweep reads phi (or the correction) at every site, and reads the
       source, reads the flag word and writes the value of its own quarter.
       Jacobi sweep (the multigrid smoother): correction in and out,
@@ -71,7 +72,7 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False):
     cor = 8 if f64 else 4     # Poisson correction storage (multigrid)
     table = {
         "fluid": 19 * pop * 2 + 2 * K * pop + 8 + 3 * vel + 4,
-        "ions": 3 * K * pop + 3 * vel + 8 + 4 + (48 if extrap else 0),
+        "ions": 3 * K * pop + 3 * vel + 8 + 4 + (48 if extrap else 16),
         "sor": 8 + (8 + 8 + 4) / 4,
         "sor32": 4 + (4 + 4 + 4) / 4,
         "mg_smooth0": 3 * cor + 4,

@@ -140,6 +140,23 @@ int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
              const double *n_init, const double *n_ref, const double *f_init, lbe_ctx **out);
 
 /*
+ * lbe_init with its arrays in device memory of the current device (for
+ * callers whose inputs already live on the GPU, e.g. framework tensors):
+ * type (N bytes), phi_s (N), n_init (nspecies*N, may be NULL), n_ref
+ * (nspecies, may be NULL) and f_init (19*N, may be NULL), in the layouts of
+ * lbe_init.  The arrays are borrowed for the call only: they are read on
+ * params->stream (the null stream when NULL), so work that writes them must
+ * be ordered before that stream, and the call returns once they are no
+ * longer needed.  The geometry is analysed on the host as in lbe_init.
+ * Errors: those of lbe_init, plus LBE_EINVAL when a non-NULL array is not
+ * device memory of the current device (nothing is read from it), and
+ * LBE_EDEVICE when a copy fails.
+ */
+int lbe_init_device(const lbe_params *params, const uint8_t *type, const double *phi_s,
+                    const double *n_init, const double *n_ref, const double *f_init,
+                    lbe_ctx **out);
+
+/*
  * Many independent systems in one context (the parameter sweeps of Sec. III:
  * plates of several widths, Debye lengths and voltages).  The systems share
  * one lattice, each enclosed by its own electrodes, and every kernel launch
@@ -168,11 +185,24 @@ int lbe_init_batch(const lbe_params *params, const uint8_t *type, const double *
  * and streaming with halfway bounce-back (Eq. 8); Poisson for n(t+1) with
  * the mid-link Dirichlet Laplacian (Eqs. 13, 15), warm-started; the
  * electrode charges Q(t+1) by Gauss's law (Eq. 16) appended to the history.
- * On LBE_ENOCONV / LBE_ENONFINITE the call stops after the failing solve:
- * n and f hold time t+1, phi the last iterate, the step is counted and its
- * charge is not recorded.
+ * On LBE_ENOCONV / LBE_ENONFINITE the call stops at the failing step and
+ * the context goes back to its start: n, f, phi, the step count and the
+ * charge history are those of time t (steps completed before it in the same
+ * call are kept), and lbe_observables' poisson_iters and poisson_resid
+ * report the failed solve.  Under LBE_EXTRAPOLATE the retried step starts
+ * from a linear extrapolation (phi(t-2) is not kept).  lbe_set_solver can
+ * raise the iteration limit or the tolerance before stepping again.
  */
 int lbe_step(lbe_ctx *ctx, int64_t nsteps);
+
+/*
+ * Change the Poisson stopping rule of a context (the tol and max_iter of
+ * lbe_params) for every later solve: tol <= 0 runs exactly max_iter sweeps
+ * (or cycles).  Nothing else changes, so a step that failed with
+ * LBE_ENOCONV can be retried with a larger limit.
+ * Errors: LBE_EINVAL for a non-finite tol or max_iter < 0 (nothing changed).
+ */
+int lbe_set_solver(lbe_ctx *ctx, double tol, int32_t max_iter);
 
 /* Re-solve Poisson for the current concentrations, warm-started from the
  * current potential (Sec. II C).  iters/resid may be NULL. */
@@ -256,6 +286,16 @@ int lbe_electrode_charge(lbe_ctx *ctx, double *q, int32_t ne);
  */
 int lbe_observables(lbe_ctx *ctx, lbe_obs *totals, double *phi, double *n, double *u,
                     double *f, double *q_hist, int64_t q_hist_cap, int64_t *q_hist_len);
+
+/*
+ * The fields of lbe_observables (phi: N; n: nspecies*N; u: 3*N; f: 19*N, in
+ * the same layouts, FP64) written into caller-owned device memory of the
+ * context's device instead of host memory; any pointer may be NULL.  The
+ * copies run on the context's stream and are complete when the call
+ * returns.  Errors: LBE_EINVAL when a non-NULL pointer is not device memory
+ * of the context's device (nothing written).
+ */
+int lbe_fields_device(lbe_ctx *ctx, double *phi, double *n, double *u, double *f);
 
 void lbe_destroy(lbe_ctx *ctx);
 const char *lbe_strerror(int code);

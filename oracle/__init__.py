@@ -81,6 +81,8 @@ def _load(path=None):
     lib.orc_init.restype = C.c_int
     lib.orc_step.argtypes = [C.c_void_p, C.c_long]
     lib.orc_step.restype = C.c_int
+    lib.orc_set_solver.argtypes = [C.c_void_p, C.c_double, C.c_int]
+    lib.orc_set_solver.restype = C.c_int
     lib.orc_poisson.argtypes = [C.c_void_p, P(C.c_int), d]
     lib.orc_poisson.restype = C.c_int
     lib.orc_set_electrode_potential.argtypes = [C.c_void_p, d]
@@ -189,6 +191,10 @@ class Oracle:
 
     def step(self, nsteps=1):
         self._check(self._lib.orc_step(self.h, int(nsteps)))
+
+    def set_solver(self, tol, max_iter):
+        """New Poisson stopping rule for later solves."""
+        self._check(self._lib.orc_set_solver(self.h, float(tol), int(max_iter)))
 
     def poisson(self):
         it = C.c_int()

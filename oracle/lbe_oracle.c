@@ -116,6 +116,7 @@ typedef struct {
   unsigned char *type;
   double *phi_s;
   double *phi;
+  double *phi_keep; /* phi(t) while step t runs: restored if its solve fails */
   double *n;     /* nspecies * N */
   double *f;     /* NQ * N, pre-collision populations f_i(r, t) */
   double *fnew;  /* NQ * N */
@@ -518,6 +519,7 @@ void orc_free(orc_state *s) {
   free(s->type);
   free(s->phi_s);
   free(s->phi);
+  free(s->phi_keep);
   free(s->n);
   free(s->nnew);
   free(s->f);
@@ -592,6 +594,7 @@ int orc_init(const orc_params *pin, const unsigned char *type, const double *phi
   s->type = (unsigned char *)malloc((size_t)N);
   s->phi_s = (double *)malloc(sizeof(double) * (size_t)N);
   s->phi = (double *)calloc((size_t)N, sizeof(double));
+  s->phi_keep = (double *)calloc((size_t)N, sizeof(double));
   s->n = (double *)calloc((size_t)N * K, sizeof(double));
   s->nnew = (double *)calloc((size_t)N * K, sizeof(double));
   s->f = (double *)calloc((size_t)N * NQ, sizeof(double));
@@ -673,17 +676,32 @@ int orc_init(const orc_params *pin, const unsigned char *type, const double *phi
   return ORC_OK;
 }
 
-/* Advance nsteps time steps. */
+/* Advance nsteps time steps.  When a step's Poisson solve fails, the state
+ * (n, f, phi, step count, charge history) goes back to the start of that
+ * step and its error code is returned. */
 int orc_step(orc_state *s, long nsteps) {
   if (!s || nsteps < 0) return ORC_EINVAL;
   for (long t = 0; t < nsteps; ++t) {
     compute_force(s);
     compute_velocity(s);
+    memcpy(s->phi_keep, s->phi, sizeof(double) * (size_t)s->N);
     update_ions(s);
     update_fluid(s);
     s->step++;
     int rc = poisson_solve(s);
-    if (rc) return rc;
+    if (rc) {
+      /* back to the start of the failing step: the previous n and f are
+       * still in the buffers the updates swapped out */
+      double *t = s->n;
+      s->n = s->nnew;
+      s->nnew = t;
+      t = s->f;
+      s->f = s->fnew;
+      s->fnew = t;
+      memcpy(s->phi, s->phi_keep, sizeof(double) * (size_t)s->N);
+      s->step--;
+      return rc;
+    }
     rc = record_charge(s);
     if (rc) return rc;
   }
@@ -716,6 +734,14 @@ int orc_set_electrode_potential(orc_state *s, const double *phi_s) {
 }
 
 /* Re-solve Poisson for the current concentrations (warm start). */
+/* New Poisson stopping rule (tol <= 0: exactly max_iter sweeps). */
+int orc_set_solver(orc_state *s, double tol, int max_iter) {
+  if (!s || !isfinite(tol) || max_iter < 0) return ORC_EINVAL;
+  s->p.tol = tol;
+  s->p.max_iter = max_iter;
+  return ORC_OK;
+}
+
 int orc_poisson(orc_state *s, int *iters, double *resid) {
   int rc = poisson_solve(s);
   if (iters) *iters = s->last_iters;

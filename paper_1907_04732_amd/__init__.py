@@ -24,8 +24,9 @@ KRYLOV = 8
 
 # public entry points of include/lbe.h
 ENTRY_POINTS = (
-    "lbe_init", "lbe_init_batch", "lbe_step", "lbe_poisson", "lbe_set_electrode_potential",
-    "lbe_record", "lbe_adjoint", "lbe_electrode_charge", "lbe_observables",
+    "lbe_init", "lbe_init_batch", "lbe_init_device", "lbe_step", "lbe_set_solver",
+    "lbe_poisson", "lbe_set_electrode_potential", "lbe_record", "lbe_adjoint",
+    "lbe_electrode_charge", "lbe_observables", "lbe_fields_device",
     "lbe_destroy", "lbe_strerror", "lbe_last_error", "lbe_profile", "lbe_kernel_times",
     "lbe_kernel_name", "lbe_num_kernel_kinds", "lbe_velocities",
 )
@@ -66,6 +67,19 @@ class LbeError(RuntimeError):
 _lib = None
 
 
+def _bring_up_torch_first():
+    """torch ships its own HIP runtime beside the system one the library links.
+    Both work in one process only when torch's initialises the device first
+    (the other order leaves torch with no GPU), so when torch is installed
+    and sees a GPU it is brought up before the library is loaded."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
 def load(path: str = LIB_PATH):
     """Load liblbe.so (built by paper_1907_04732_amd.build); raises if absent."""
     global _lib
@@ -74,6 +88,7 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise OSError(f"{path} is missing: build it with `python -m paper_1907_04732_amd.build` "
                       "(there is no CPU fallback)")
+    _bring_up_torch_first()
     lib = C.CDLL(path)
     P = C.POINTER
     d = P(C.c_double)
@@ -82,6 +97,13 @@ def load(path: str = LIB_PATH):
     lib.lbe_init_batch.argtypes = [P(Params), P(C.c_uint8), d, d, d, P(C.c_uint16), C.c_int32,
                                    P(C.c_void_p)]
     lib.lbe_init_batch.restype = C.c_int
+    v = C.c_void_p
+    lib.lbe_init_device.argtypes = [P(Params), v, v, v, v, v, P(C.c_void_p)]
+    lib.lbe_init_device.restype = C.c_int
+    lib.lbe_set_solver.argtypes = [C.c_void_p, C.c_double, C.c_int32]
+    lib.lbe_set_solver.restype = C.c_int
+    lib.lbe_fields_device.argtypes = [C.c_void_p, v, v, v, v]
+    lib.lbe_fields_device.restype = C.c_int
     lib.lbe_step.argtypes = [C.c_void_p, C.c_int64]
     lib.lbe_step.restype = C.c_int
     lib.lbe_poisson.argtypes = [C.c_void_p, P(C.c_int32), d]
@@ -158,18 +180,34 @@ def kernel_names():
     return [lib.lbe_kernel_name(k).decode() for k in range(lib.lbe_num_kernel_kinds())]
 
 
+def _is_gpu_tensor(a):
+    return getattr(a, "is_cuda", False)
+
+
+def _tptr(a):
+    return None if a is None else C.c_void_p(a.data_ptr())
+
+
 class Lbe:
     """One LBE context on the current HIP device (see include/lbe.h)."""
 
     def __init__(self, params: Params, node_type, phi_s, n_init=None, n_ref=None, f_init=None,
                  system=None, nsys=None):
         """system (N ints) and nsys select lbe_init_batch: independent systems
-        in one lattice, n_ref then holding nsys x nspecies values."""
+        in one lattice, n_ref then holding nsys x nspecies values.  With
+        node_type a GPU tensor, every array is read from device memory
+        (lbe_init_device)."""
         lib = load()
         self._lib = lib
         self.p = params
         self.N = params.nx * params.ny * params.nz
         self.K = params.nspecies
+        self.h = None
+        if _is_gpu_tensor(node_type):
+            if system is not None:
+                raise ValueError("batched systems take host arrays")
+            self._init_device(node_type, phi_s, n_init, n_ref, f_init)
+            return
         t = np.ascontiguousarray(node_type, dtype=np.uint8).reshape(-1)
         ps = np.ascontiguousarray(phi_s, dtype=np.float64).reshape(-1)
         if t.size != self.N or ps.size != self.N:
@@ -202,6 +240,36 @@ class Lbe:
         self.h = h
         self.ne = int(t.max()) if t.size else 0
 
+    def _init_device(self, node_type, phi_s, n_init, n_ref, f_init):
+        import torch
+
+        dev = node_type.device
+        sizes = {"node_type": self.N, "phi_s": self.N, "n_init": self.K * self.N,
+                 "n_ref": self.K, "f_init": 19 * self.N}
+        args = {}
+        for name, a in (("node_type", node_type), ("phi_s", phi_s), ("n_init", n_init),
+                        ("n_ref", n_ref), ("f_init", f_init)):
+            if a is None:
+                args[name] = None
+                continue
+            dtype = torch.uint8 if name == "node_type" else torch.float64
+            t = torch.as_tensor(a, device=dev).to(dtype).contiguous().reshape(-1)
+            if t.numel() != sizes[name]:
+                raise ValueError(f"{name} needs {sizes[name]} entries")
+            args[name] = t
+        # the library reads on its own stream: finish the work that made the inputs
+        torch.cuda.current_stream(dev).synchronize()
+        h = C.c_void_p()
+        with torch.cuda.device(dev):
+            rc = self._lib.lbe_init_device(C.byref(self.p), _tptr(args["node_type"]),
+                                           _tptr(args["phi_s"]), _tptr(args["n_init"]),
+                                           _tptr(args["n_ref"]), _tptr(args["f_init"]), C.byref(h))
+        if rc:
+            raise LbeError(rc, self._lib.lbe_last_error(None).decode())
+        self.h = h
+        self.ne = int(args["node_type"].max().item()) if self.N else 0
+        self.device = dev
+
     def close(self):
         if getattr(self, "h", None):
             self._lib.lbe_destroy(self.h)
@@ -225,6 +293,13 @@ class Lbe:
 
     def step(self, nsteps=1):
         self._check(self._lib.lbe_step(self.h, int(nsteps)))
+
+    def set_solver(self, tol=None, max_iter=None):
+        """New Poisson stopping rule for later solves (None keeps a value)."""
+        tol = self.p.tol if tol is None else float(tol)
+        max_iter = self.p.max_iter if max_iter is None else int(max_iter)
+        self._check(self._lib.lbe_set_solver(self.h, tol, max_iter))
+        self.p.tol, self.p.max_iter = tol, max_iter
 
     def poisson(self):
         it = C.c_int32()
@@ -287,9 +362,24 @@ class Lbe:
                     poisson_resid=o.poisson_resid, mass=o.mass, nk=list(o.nk)[: self.K],
                     q_ion=o.q_ion, poisson_total=o.poisson_total)
 
-    def fields(self, f=True):
-        """dict with phi (N), n (K,N), u (3,N) and, if f, populations (19,N)."""
+    def fields(self, f=True, device=None):
+        """dict with phi (N), n (K,N), u (3,N) and, if f, populations (19,N).
+        device (a torch device): float64 tensors written there by
+        lbe_fields_device instead of numpy arrays."""
         N, K = self.N, self.K
+        if device is not None:
+            import torch
+
+            out = dict(phi=torch.empty(N, dtype=torch.float64, device=device),
+                       n=torch.empty(K, N, dtype=torch.float64, device=device),
+                       u=torch.empty(3, N, dtype=torch.float64, device=device))
+            if f:
+                out["f"] = torch.empty(19, N, dtype=torch.float64, device=device)
+            # the library writes on its own stream
+            torch.cuda.current_stream(device).synchronize()
+            self._check(self._lib.lbe_fields_device(self.h, _tptr(out["phi"]), _tptr(out["n"]),
+                                                    _tptr(out["u"]), _tptr(out.get("f"))))
+            return out
         phi = np.empty(N)
         n = np.empty(K * N)
         u = np.empty(3 * N)

@@ -31,6 +31,7 @@ struct lbe_ctx {
   double *phi = nullptr, *src = nullptr, *u = nullptr;
   double *phi_prev = nullptr;  // converged phi(t-1), phi(t-2) (LBE_EXTRAPOLATE, 2 N)
   int extrap_hist = 0;         // how many of the two are valid
+  double *phi_keep = nullptr;  // phi(t) as the step started (N; without LBE_EXTRAPOLATE)
   double *n[2] = {nullptr, nullptr};
   double *f[2] = {nullptr, nullptr};
   // mixed form: FP32 deviations h = f - w rho0, nu = n - n_ref, FP32 velocity
@@ -1061,10 +1062,36 @@ int record_charge(lbe_ctx *c) {
   return LBE_OK;
 }
 
+// Back to the start of a step whose Poisson solve failed: n(t) and f(t) are
+// still in the buffers the step read, phi(t) in the copy pass B made (the
+// extrapolation history, else phi_keep).  Of the history only phi(t-2) is
+// lost, so the retried step starts from a linear extrapolation.
+int rewind_step(lbe_ctx *c, int a, int hist, bool record) {
+  c->cur = a;
+  if (record) c->step--;
+  double *keep = c->phi_prev ? c->phi_prev : c->phi_keep;
+  const int shift = c->phi_prev ? 1 : 0;
+  int rc = run(c, KK_REWIND, c->L.n, [&] {
+    if (c->mixed)
+      return launch_rewind_f32(c->stream, c->L, c->P, c->mask, c->nu32[a], c->src, c->phi, keep,
+                               shift);
+    return launch_rewind_f64(c->stream, c->L, c->P, c->mask, c->n[a], c->src, c->phi, keep, shift);
+  });
+  if (rc) return rc;
+  if (c->phi_prev) c->extrap_hist = std::min(hist, 1);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBE_OK;
+}
+
 // record = false: a replay of a recorded step (reverse mode), which neither
 // counts the step nor appends its charge
 int one_step(lbe_ctx *c, bool record = true) {
   const int a = c->cur, b = 1 - c->cur;
+  const int hist = c->extrap_hist;
+  // pass B keeps phi(t) for a rewind: in the extrapolation history, else in
+  // phi_keep (order -1: a plain copy)
+  double *keep = c->phi_prev ? c->phi_prev : c->phi_keep;
+  const int order = c->phi_prev ? hist : -1;
   int rc = run(c, KK_FLUID, c->L.n, [&] {
     if (c->mixed)
       return launch_fluid_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[a], c->h32[a],
@@ -1077,15 +1104,19 @@ int one_step(lbe_ctx *c, bool record = true) {
   rc = run(c, KK_IONS, c->L.n, [&] {
     if (c->mixed)
       return launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a], c->nu32[b],
-                             c->src, c->extrap_hist, c->phi, c->phi_prev);
+                             c->src, order, c->phi, keep);
     return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a], c->n[b], c->src,
-                           c->extrap_hist, c->phi, c->phi_prev);
+                           order, c->phi, keep);
   });
   if (rc) return rc;
-  if (c->phi_prev) c->extrap_hist = std::min(c->extrap_hist + 1, 2);
+  if (c->phi_prev) c->extrap_hist = std::min(hist + 1, 2);
   c->cur = b;
   if (record) c->step++;
   rc = poisson_solve(c, true);
+  if (rc == LBE_ENOCONV || rc == LBE_ENONFINITE) {
+    const int rc2 = rewind_step(c, a, hist, record);
+    return rc2 ? rc2 : rc;
+  }
   if (rc) return rc;
   return record ? record_charge(c) : LBE_OK;
 }
@@ -1323,10 +1354,68 @@ int adjoint_sweep(lbe_ctx *c, const double *qbar, const double *ubar, double *gr
   return LBE_OK;
 }
 
+// phi, n, u and f of the current state into caller buffers (host memory for
+// kind = hipMemcpyDeviceToHost, device memory for hipMemcpyDeviceToDevice);
+// NULL skips one.  Synchronises the stream before returning.
+int copy_fields(lbe_ctx *c, double *phi, double *n, double *u, double *f, hipMemcpyKind kind) {
+  const long N = c->L.n;
+  const int K = c->K;
+  int rc;
+  if (u || f) {
+    // FP64 form: the next step's output buffers are free between steps
+    double *fpre = c->mixed ? c->obs : c->f[1 - c->cur];
+    double *uo = c->mixed ? c->obs + (size_t)NQ * N : c->u;
+    rc = run(c, KK_OBSERVE, c->L.n, [&] {
+      if (c->mixed)
+        return launch_observe_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[c->cur],
+                                  c->h32[c->cur], fpre, uo);
+      return launch_observe_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[c->cur],
+                                c->f[c->cur], fpre, uo);
+    });
+    if (rc) return rc;
+    if (f) HIPCHK(c, hipMemcpyAsync(f, fpre, sizeof(double) * NQ * N, kind, c->stream));
+    if (u) HIPCHK(c, hipMemcpyAsync(u, uo, sizeof(double) * 3 * N, kind, c->stream));
+  }
+  if (phi) HIPCHK(c, hipMemcpyAsync(phi, c->phi, sizeof(double) * N, kind, c->stream));
+  std::vector<float> nu_h;
+  if (n) {
+    if (!c->mixed) {
+      HIPCHK(c, hipMemcpyAsync(n, c->n[c->cur], sizeof(double) * K * N, kind, c->stream));
+    } else if (kind == hipMemcpyDeviceToDevice) {
+      rc = run(c, KK_EXPAND_N, c->L.n, [&] {
+        return launch_expand_n_f32(c->stream, c->L, c->P, c->mask, c->nu32[c->cur], n);
+      });
+      if (rc) return rc;
+    } else {
+      nu_h.resize((size_t)K * N);
+      HIPCHK(c, hipMemcpyAsync(nu_h.data(), c->nu32[c->cur], sizeof(float) * K * N,
+                               hipMemcpyDeviceToHost, c->stream));
+    }
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (!nu_h.empty())
+    for (int k = 0; k < K; ++k)
+      for (long r = 0; r < N; ++r)
+        n[(size_t)k * N + r] =
+            c->type_h[r] ? 0.0 : c->nref_h[(size_t)c->sys_h[r] * 4 + k] + (double)nu_h[(size_t)k * N + r];
+  return LBE_OK;
+}
+
+// true when p is device memory of device dev (-1: the current device)
+bool on_device(const void *p, int dev = -1) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (dev < 0) (void)hipGetDevice(&dev);
+  return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == dev;
+}
+
 void free_ctx(lbe_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  void *ptrs[] = {c->mask, c->phi, c->phi_prev, c->src, c->u, c->n[0], c->n[1], c->f[0], c->f[1],
+  void *ptrs[] = {c->mask, c->phi, c->phi_prev, c->phi_keep, c->src, c->u, c->n[0], c->n[1], c->f[0], c->f[1],
                   c->h32[0], c->h32[1], c->nu32[0], c->nu32[1], c->u32, c->obs,
                   c->partial, c->dout, c->ctl, c->iface, c->blk_elec, c->blk_begin,
                   c->blk_end, c->qcur, c->qhist, c->solid_idx, c->solid_val,
@@ -1692,6 +1781,8 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
       rc = fail(c, LBE_EDEVICE, "memset failed");
       goto fail_;
     }
+  } else {
+    TRY(dalloc(c, &c->phi_keep, N));
   }
   if (hipStreamSynchronize(c->stream) != hipSuccess) {
     rc = fail(c, LBE_EDEVICE, "stream synchronize failed");
@@ -1724,6 +1815,55 @@ int lbe_init_batch(const lbe_params *params, const uint8_t *type, const double *
     return fail(nullptr, LBE_EINVAL, "system is NULL");
   }
   return init_impl(params, type, phi_s, n_init, n_ref, nullptr, system, nsys, out);
+}
+
+int lbe_init_device(const lbe_params *params, const uint8_t *type, const double *phi_s,
+                    const double *n_init, const double *n_ref, const double *f_init,
+                    lbe_ctx **out) {
+  g_init_error.clear();
+  if (out) *out = nullptr;
+  int rc = validate(params);
+  if (rc) return rc;
+  if (!type || !phi_s) return fail(nullptr, LBE_EINVAL, "type and phi_s are required");
+  if (!n_init && !n_ref) return fail(nullptr, LBE_EINVAL, "n_init or n_ref is required");
+  const size_t N = (size_t)params->nx * params->ny * params->nz;
+  const size_t K = (size_t)params->nspecies;
+  struct Arg {
+    const void *src;
+    size_t bytes;
+  } args[] = {{type, N}, {phi_s, N * sizeof(double)}, {n_init, K * N * sizeof(double)},
+              {n_ref, K * sizeof(double)}, {f_init, NQ * N * sizeof(double)}};
+  for (const Arg &a : args)
+    if (a.src && !on_device(a.src))
+      return fail(nullptr, LBE_EINVAL, "an input is not device memory of the current device");
+  // the geometry analysis runs on the host: copy the borrowed arrays there
+  std::vector<uint8_t> t(N);
+  std::vector<double> ps(N), ni(n_init ? K * N : 0), nr(n_ref ? K : 0), fi(f_init ? NQ * N : 0);
+  void *dst[] = {t.data(), ps.data(), ni.data(), nr.data(), fi.data()};
+  hipStream_t s = (hipStream_t)params->stream;
+  for (int i = 0; i < 5; ++i)
+    if (args[i].src && hipMemcpyAsync(dst[i], args[i].src, args[i].bytes, hipMemcpyDeviceToHost,
+                                      s) != hipSuccess)
+      return fail(nullptr, LBE_EDEVICE, "copy of an input failed");
+  if (hipStreamSynchronize(s) != hipSuccess)
+    return fail(nullptr, LBE_EDEVICE, "stream synchronize failed");
+  return init_impl(params, t.data(), ps.data(), n_init ? ni.data() : nullptr,
+                   n_ref ? nr.data() : nullptr, f_init ? fi.data() : nullptr, nullptr, 1, out);
+}
+
+int lbe_set_solver(lbe_ctx *c, double tol, int32_t max_iter) {
+  if (!c) return fail(c, LBE_EINVAL, "context is NULL");
+  if (!std::isfinite(tol) || max_iter < 0) return fail(c, LBE_EINVAL, "bad tol or max_iter");
+  c->p.tol = tol;
+  c->p.max_iter = max_iter;
+  return LBE_OK;
+}
+
+int lbe_fields_device(lbe_ctx *c, double *phi, double *n, double *u, double *f) {
+  if (!c) return fail(c, LBE_EINVAL, "context is NULL");
+  for (const void *q : {(const void *)phi, (const void *)n, (const void *)u, (const void *)f})
+    if (q && !on_device(q, c->device)) return fail(c, LBE_EINVAL, "an output is not device memory of the context's device");
+  return copy_fields(c, phi, n, u, f, hipMemcpyDeviceToDevice);
 }
 
 int lbe_step(lbe_ctx *c, int64_t nsteps) {
@@ -1865,7 +2005,6 @@ int lbe_electrode_charge(lbe_ctx *c, double *q, int32_t ne) {
 int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double *u, double *f,
                     double *q_hist, int64_t q_hist_cap, int64_t *q_hist_len) {
   if (!c) return fail(c, LBE_EINVAL, "context is NULL");
-  const long N = c->L.n;
   const int K = c->K;
   int rc;
   if (totals) {
@@ -1889,32 +2028,8 @@ int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double 
     for (int k = 0; k < K; ++k) totals->nk[k] = c->hpin[2 + k];
     totals->poisson_total = c->total_iters;
   }
-  if (u || f) {
-    // FP64 form: the next step's output buffers are free between steps
-    double *fpre = c->mixed ? c->obs : c->f[1 - c->cur];
-    double *uo = c->mixed ? c->obs + (size_t)NQ * N : c->u;
-    rc = run(c, KK_OBSERVE, c->L.n, [&] {
-      if (c->mixed)
-        return launch_observe_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[c->cur],
-                                  c->h32[c->cur], fpre, uo);
-      return launch_observe_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[c->cur],
-                                c->f[c->cur], fpre, uo);
-    });
-    if (rc) return rc;
-    if (f) HIPCHK(c, hipMemcpyAsync(f, fpre, sizeof(double) * NQ * N, hipMemcpyDeviceToHost, c->stream));
-    if (u) HIPCHK(c, hipMemcpyAsync(u, uo, sizeof(double) * 3 * N, hipMemcpyDeviceToHost, c->stream));
-  }
-  if (phi) HIPCHK(c, hipMemcpyAsync(phi, c->phi, sizeof(double) * N, hipMemcpyDeviceToHost, c->stream));
-  std::vector<float> nu_h;
-  if (n) {
-    if (c->mixed) {
-      nu_h.resize((size_t)K * N);
-      HIPCHK(c, hipMemcpyAsync(nu_h.data(), c->nu32[c->cur], sizeof(float) * K * N,
-                               hipMemcpyDeviceToHost, c->stream));
-    } else {
-      HIPCHK(c, hipMemcpyAsync(n, c->n[c->cur], sizeof(double) * K * N, hipMemcpyDeviceToHost, c->stream));
-    }
-  }
+  rc = copy_fields(c, phi, n, u, f, hipMemcpyDeviceToHost);
+  if (rc) return rc;
   if (q_hist && q_hist_cap > 0 && c->ne > 0) {
     const int64_t rows = std::min(q_hist_cap, c->qlen);
     HIPCHK(c, hipMemcpyAsync(q_hist, c->qhist, sizeof(double) * rows * c->ne, hipMemcpyDeviceToHost,
@@ -1922,11 +2037,6 @@ int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double 
   }
   if (q_hist_len) *q_hist_len = c->qlen;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (n && c->mixed)
-    for (int k = 0; k < K; ++k)
-      for (long r = 0; r < N; ++r)
-        n[(size_t)k * N + r] =
-            c->type_h[r] ? 0.0 : c->nref_h[(size_t)c->sys_h[r] * 4 + k] + (double)nu_h[(size_t)k * N + r];
   return LBE_OK;
 }
 

@@ -307,6 +307,10 @@ __device__ __forceinline__ float excess_link_f_series(float nh, float nt, float 
 // history shifts.  Run by the ion pass, which does not read phi.
 __device__ __forceinline__ void extrapolate_at(int r, int n, int order, double *__restrict__ phi,
                                                double *__restrict__ prev) {
+  if (order < 0) {  // no extrapolation: only keep phi(t)
+    prev[r] = phi[r];
+    return;
+  }
   const double now = phi[r], p1 = prev[r];
   if (order >= 2) phi[r] = 3.0 * (now - p1) + prev[n + r];
   else if (order == 1) phi[r] = 2.0 * now - p1;

@@ -147,6 +147,8 @@ enum KernelKind {
   KK_ADJ_FOLD,    // reverse step: fold the Poisson adjoint into the ion adjoint
   KK_ADJ_SEED,    // reverse sweep: seed from the charge weights; phi_s gradient
   KK_ADJ_MOMENTS, // reverse sweep: rho and m of a recomputed state
+  KK_REWIND,      // back to the start of a step whose solve failed
+  KK_EXPAND_N,    // mixed form: FP64 concentrations into a caller's device buffer
   KK_COUNT
 };
 
@@ -162,10 +164,16 @@ hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, cons
 // Step pass B: advective outflow with u; nio holds n* on entry, n(t+1) on exit.
 // With prev = [phi(t-1) | phi(t-2)] (2 N; NULL: none) it also moves phi to
 // its extrapolation in time of the given order (0 constant, 1 linear, 2
-// quadratic) as the next solve's start, and shifts the history.
+// quadratic) as the next solve's start, and shifts the history; order -1
+// (prev: N) only copies phi(t) into prev.
 hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                            const double *u, const double *n, double *nio, double *src, int order,
                            double *phi, double *prev);
+// A step's solve failed: phi = prev[0..N) (phi(t), kept by pass B), the
+// source recomputed from n(t), and with shift prev[0..N) = prev[N..2N)
+// (the extrapolation history back by one step).  Fluid nodes only.
+hipError_t launch_rewind_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                             const double *n, double *src, double *phi, double *prev, int shift);
 // dst[idx[t]] = val[t] for t < count (new solid-node potentials)
 hipError_t launch_scatter(hipStream_t s, int count, const int *idx, const double *val,
                           double *dst);
@@ -202,6 +210,11 @@ hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const
 hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
                               const uint32_t *mask, const double *phi, const float *nu,
                               const float *hin, double *fpre, double *u);
+hipError_t launch_rewind_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                             const float *nu, double *src, double *phi, double *prev, int shift);
+// n = n_ref + nu (K N doubles, species-major; 0 on solid nodes)
+hipError_t launch_expand_n_f32(hipStream_t s, const Lattice &L, const Phys &P,
+                               const uint32_t *mask, const float *nu, double *n);
 hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                              const float *hin, const float *nu, double *partial, double *out);
 

@@ -23,7 +23,7 @@ const char *const kKernelNames[KK_COUNT] = {
     "fluid", "ions", "sor", "resid", "charge", "totals", "observe", "sor32", "correct",
     "mg_resid", "mg_smooth", "mg_smooth0", "mg_restrict", "mg_prolong", "mg_coarse", "mg_small",
     "fcg_beta", "fcg_dir", "fcg_apply", "fcg_update", "adj_fluid", "adj_ions", "adj_fold",
-    "adj_seed", "adj_moments"};
+    "adj_seed", "adj_moments", "rewind", "expand_n"};
 
 namespace {
 
@@ -403,6 +403,27 @@ __global__ __launch_bounds__(BLOCK) void k_observe_f64(Lattice L, Phys P,
   u[2 * N + r] = (m2 + 0.5 * F2) / rho;
 }
 
+// Rewind of a step whose Poisson solve failed: phi(t), kept by pass B, goes
+// back into phi (and, under extrapolation, the history moves back by one),
+// and the source is recomputed from n(t) exactly as pass B forms it.
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_rewind_f64(Lattice L, Phys P,
+                                                      const uint32_t *__restrict__ mask,
+                                                      const double *__restrict__ n,
+                                                      double *__restrict__ src,
+                                                      double *__restrict__ phi,
+                                                      double *__restrict__ prev, int shift) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n || (mask[r] & SOLID_BIT)) return;
+  const int N = L.n;
+  double q = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) q += P.z[k] * n[k * N + r];
+  src[r] = P.src_scale * q;
+  phi[r] = prev[r];
+  if (shift) prev[r] = prev[N + r];
+}
+
 // dst[idx[t]] = val[t]: new potentials of the solid nodes
 __global__ __launch_bounds__(BLOCK) void k_scatter(int count, const int *__restrict__ idx,
                                                    const double *__restrict__ val,
@@ -438,6 +459,15 @@ hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const
                            double *phi, double *prev) {
 #define CALL(KK) \
   hipLaunchKernelGGL(k_ions_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, u, n, nio, src, order, phi, prev)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_rewind_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                             const double *n, double *src, double *phi, double *prev, int shift) {
+#define CALL(KK) \
+  hipLaunchKernelGGL(k_rewind_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, n, src, phi, prev, shift)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   return hipGetLastError();

@@ -272,6 +272,43 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f32(Lattice L, Phys P,
   }
 }
 
+// Rewind of a step whose Poisson solve failed (as k_rewind_f64): phi(t) back
+// from the copy pass B kept, the source recomputed from nu(t) as pass B forms
+// it.
+template <int K>
+__global__ __launch_bounds__(BLOCK) void k_rewind_f32(Lattice L, Phys P,
+                                                      const uint32_t *__restrict__ mask,
+                                                      const float *__restrict__ nu,
+                                                      double *__restrict__ src,
+                                                      double *__restrict__ phi,
+                                                      double *__restrict__ prev, int shift) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  if (m & SOLID_BIT) return;
+  const int N = L.n;
+  double q = P.qref[system_of(m)];
+#pragma unroll
+  for (int k = 0; k < K; ++k) q += P.z[k] * double(nu[k * N + r]);
+  src[r] = P.src_scale * q;
+  phi[r] = prev[r];
+  if (shift) prev[r] = prev[N + r];
+}
+
+// Concentrations in FP64, n = n_ref + nu on fluid nodes and 0 on solid ones
+// (species-major, as the host copy of the observables).
+__global__ __launch_bounds__(BLOCK) void k_expand_n_f32(Lattice L, int K, const double *__restrict__ nref,
+                                                        const uint32_t *__restrict__ mask,
+                                                        const float *__restrict__ nu,
+                                                        double *__restrict__ n) {
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  if (r >= L.n) return;
+  const uint32_t m = mask[r];
+  const int N = L.n;
+  for (int k = 0; k < K; ++k)
+    n[k * N + r] = (m & SOLID_BIT) ? 0.0 : nref[4 * system_of(m) + k] + double(nu[k * N + r]);
+}
+
 }  // namespace
 
 #define LBE_DISPATCH_K(K, CALL) \
@@ -289,6 +326,22 @@ hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, cons
   hipLaunchKernelGGL(k_fluid_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, nu, hin, hout, u, nustar)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_rewind_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
+                             const float *nu, double *src, double *phi, double *prev, int shift) {
+#define CALL(KK) \
+  hipLaunchKernelGGL(k_rewind_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, nu, src, phi, prev, shift)
+  LBE_DISPATCH_K(P.K, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_n_f32(hipStream_t s, const Lattice &L, const Phys &P,
+                               const uint32_t *mask, const float *nu, double *n) {
+  hipLaunchKernelGGL(k_expand_n_f32, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P.K, P.nref_d,
+                     mask, nu, n);
   return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+import gpu_cases as G
 import oracle
 import oracle_pins as P
 import workloads as W
@@ -175,6 +176,35 @@ def test_no_convergence_reported():
     with pytest.raises(oracle.OracleError) as e:
         oracle.Oracle(p, t, ps, None, (1e-3, 1e-3))
     assert e.value.code == oracle.ENOCONV
+
+
+def test_failed_step_goes_back_to_its_start():
+    """A step whose solve hits max_iter leaves n, f, phi, the step count and
+    the charge history as they were before it; with the limit raised the
+    same steps then give exactly the uninterrupted trajectory."""
+    kw, shape, t, ps, n0, nref, _, _ = G.case("slab_2x2x18_k1")
+    pk = dict(tol=1e-12, max_iter=100000, check_every=2)
+    a = oracle.Oracle(oracle.make_params(shape, **kw, **pk), t, ps, n0, nref)
+    b = oracle.Oracle(oracle.make_params(shape, **kw, **pk), t, ps, n0, nref)
+    a.step(4)
+    before = a.fields(), a.qhist(), a.step_count
+    a.set_solver(1e-14, 1)
+    with pytest.raises(oracle.OracleError) as e:
+        a.step(3)
+    assert e.value.code == oracle.ENOCONV
+    after = a.fields(), a.qhist(), a.step_count
+    for k in before[0]:
+        assert np.array_equal(before[0][k], after[0][k]), k
+    assert np.array_equal(before[1], after[1]) and before[2] == after[2] == 4
+    a.set_solver(1e-12, 100000)
+    a.step(3)
+    b.step(7)
+    fa, fb = a.fields(), b.fields()
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    assert np.array_equal(a.qhist(), b.qhist())
+    with pytest.raises(oracle.OracleError):
+        a.set_solver(float("nan"), 10)
 
 
 def test_equilibrium_moments():
