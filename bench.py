@@ -366,8 +366,8 @@ def run_adjoint(w: W.Workload, form: str, steps: int, every: int, check_every: i
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--forms", default="fp32-mg,fp64-mg,fp64-sor",
                     help="comma list of " + ",".join(FORMS) + "; the first is the headline")
     ap.add_argument("--check-every", type=int, default=8)

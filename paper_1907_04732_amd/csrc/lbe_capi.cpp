@@ -777,7 +777,7 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
   for (size_t r = 0; r < solid.size(); ++r) solid[r] = type[r] != 0;
   std::vector<uint16_t> sys = c->sys_h;
   lbe_ctx::MgDev l0;
-  l0.lv = MgLevel{nx, ny, nz, nx * ny, nx * ny * nz, c->L.selfm, 1.0, 1.0, c->L.wall};
+  l0.lv = make_level(nx, ny, nz, c->L.selfm, 1.0, c->L.wall);
   l0.mask = c->mask;
   HIPCHK(c, hipMalloc(&l0.e, esz * l0.lv.n));
   HIPCHK(c, hipMalloc(&l0.e2, esz * l0.lv.n));
@@ -797,8 +797,7 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
     if (c->mg_jacobi == 0.0 && !colouring_ok(cx, cy, cz, cs)) break;
     h2 *= 4.0;
     lbe_ctx::MgDev L;
-    L.lv = MgLevel{cx, cy, cz, cx * cy, cx * cy * cz, level_selfm(cx, cy, cz), h2, 1.0 / h2,
-                   c->L.wall};
+    L.lv = make_level(cx, cy, cz, level_selfm(cx, cy, cz), h2, c->L.wall);
     L.tr = MgTransfer{c->mg.back().lv, L.lv, ox, oy, oz};
     const std::vector<uint32_t> m = level_mask(cx, cy, cz, cs);
     HIPCHK(c, hipMalloc((void **)&L.mask, sizeof(uint32_t) * m.size()));

@@ -66,7 +66,13 @@ struct MgLevel {
   uint32_t selfm;
   double h2, inv_h2;
   double wall;      // as Lattice::wall
+  double rnx, rnxy; // 1 / nx and 1 / nxy: cell coordinates by multiplication
 };
+
+inline MgLevel make_level(int nx, int ny, int nz, uint32_t selfm, double h2, double wall) {
+  return MgLevel{nx, ny, nz, nx * ny, nx * ny * nz, selfm, h2, 1.0 / h2, wall,
+                 1.0 / nx, 1.0 / ((double)nx * ny)};
+}
 
 // Fine level f -> coarse level c: coarse cell (X, Y, Z) holds the fine cells
 // whose shifted indices ((x - ox) mod nx, ...) are (2X or 2X+1, ...).

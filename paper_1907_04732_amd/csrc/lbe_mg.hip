@@ -33,12 +33,22 @@ struct Coords {
   int x, y, z;
 };
 
-__device__ __forceinline__ Coords coords_of(int r, int nx, int nxy) {
+// a / b for 0 <= a < 2^31, 1 <= b, with rb = 1 / b rounded: the product is
+// within a/b * 2^-51 of a / b, so its floor is the quotient or one less,
+// and one step on the remainder makes it exact (cheaper than an integer
+// division by a value known only at run time)
+__device__ __forceinline__ int quot(int a, int b, double rb) {
+  int q = (int)((double)a * rb);
+  if (a - q * b >= b) ++q;
+  return q;
+}
+
+__device__ __forceinline__ Coords coords_of(int r, const MgLevel &lv) {
   Coords c;
-  c.z = r / nxy;
-  const int rem = r - c.z * nxy;
-  c.y = rem / nx;
-  c.x = rem - c.y * nx;
+  c.z = quot(r, lv.nxy, lv.rnxy);
+  const int rem = r - c.z * lv.nxy;
+  c.y = quot(rem, lv.nx, lv.rnx);
+  c.x = rem - c.y * lv.nx;
   return c;
 }
 
@@ -49,13 +59,19 @@ __device__ __forceinline__ int nbr_of(const MgLevel &lv, const Coords &c, int i)
 }
 
 // v[i] = e at the neighbour c + c_i of a level's cell (v[0] = e[r]); all loads
-// are issued before any value is used
+// are issued before any value is used.  The wrapped offsets along each axis
+// are formed once per cell, so a neighbour's index is one add per axis.
 template <class T>
 __device__ __forceinline__ void gather_lv(const MgLevel &lv, const Coords &c, int r,
                                           const T *__restrict__ e, T (&v)[NQ]) {
+  const int ox[3] = {c.x > 0 ? -1 : lv.nx - 1, 0, c.x + 1 < lv.nx ? 1 : 1 - lv.nx};
+  const int oy[3] = {c.y > 0 ? -lv.nx : (lv.ny - 1) * lv.nx, 0,
+                     c.y + 1 < lv.ny ? lv.nx : -(lv.ny - 1) * lv.nx};
+  const int oz[3] = {c.z > 0 ? -lv.nxy : (lv.nz - 1) * lv.nxy, 0,
+                     c.z + 1 < lv.nz ? lv.nxy : -(lv.nz - 1) * lv.nxy};
   v[0] = e[r];
 #pragma unroll
-  for (int i = 1; i < NQ; ++i) v[i] = e[nbr_of(lv, c, i)];
+  for (int i = 1; i < NQ; ++i) v[i] = e[r + ox[CX[i] + 1] + oy[CY[i] + 1] + oz[CZ[i] + 1]];
 }
 
 // A e at a fluid cell from its gathered values v, in the level's units:
@@ -101,7 +117,7 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
   if (kc && r == 0) kc->first = 1;  // a new Krylov sequence starts from this residual
   double a = 0.0;
   if (r < lv.n) {
-    const Coords c = coords_of(r, lv.nx, lv.nxy);
+    const Coords c = coords_of(r, lv);
     double pn[NQ];
     gather_lv(lv, c, r, phi, pn);
     const double sr = src[r];
@@ -195,7 +211,7 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_apply(MgLevel lv, const uint32_t 
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   double pq = 0.0, rp = 0.0;
   if (r < lv.n) {
-    const Coords c = coords_of(r, lv.nx, lv.nxy);
+    const Coords c = coords_of(r, lv);
     double v[NQ];
     gather_lv(lv, c, r, p, v);
     const double rr = rv[r];
@@ -311,7 +327,7 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
   if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= lv.n) return;
-  const Coords c = coords_of(r, lv.nx, lv.nxy);
+  const Coords c = coords_of(r, lv);
   T v[NQ];
   gather_lv(lv, c, r, x_in, v);
   const T rr = rhs[r];
@@ -345,7 +361,7 @@ __device__ __forceinline__ void restrict_child(const MgTransfer &tr, int R, int 
                                                const uint32_t *__restrict__ mf,
                                                const T *__restrict__ rf,
                                                const T *__restrict__ ef, T &v, int &cnt) {
-  const Coords C = coords_of(R, tr.c.nx, tr.c.nxy);
+  const Coords C = coords_of(R, tr.c);
   const int xp = 2 * C.x + (j & 1), yp = 2 * C.y + ((j >> 1) & 1), zp = 2 * C.z + (j >> 2);
   const bool inside = xp < tr.f.nx && yp < tr.f.ny && zp < tr.f.nz;
   // a child beyond an odd-sized level reads a valid cell and is dropped
@@ -410,7 +426,7 @@ template <class T>
 __device__ __forceinline__ T prolong_value(const MgTransfer &tr, int r,
                                            const uint32_t *__restrict__ mc,
                                            const T *__restrict__ ec) {
-  const Coords c = coords_of(r, tr.f.nx, tr.f.nxy);
+  const Coords c = coords_of(r, tr.f);
   // position in the block re-indexing, parent cell and the nearer neighbour
   int P[3], Nb[3];
   const int fx[3] = {wrapi(c.x - tr.ox, tr.f.nx), wrapi(c.y - tr.oy, tr.f.ny), wrapi(c.z - tr.oz, tr.f.nz)};
@@ -493,7 +509,7 @@ __global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, T 
             xo[r] = T(0);
             continue;
           }
-          const Coords c = coords_of(r, lv.nx, lv.nxy);
+          const Coords c = coords_of(r, lv);
           T v[NQ];
           gather_lv(lv, c, r, xi, v);
           T num = T(0), den = T(0);
@@ -515,7 +531,7 @@ __global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, T 
   for (int s = 0; s < sweeps; ++s) {
     for (int col = 0; col < 4; ++col) {
       for (int r = threadIdx.x; r < lv.n; r += COARSE_BLOCK) {
-        const Coords c = coords_of(r, lv.nx, lv.nxy);
+        const Coords c = coords_of(r, lv);
         if ((((c.x + c.z) & 1) + 2 * ((c.y + c.z) & 1)) != col) continue;
         const uint32_t m = mask[r];
         if (m & SOLID_BIT) continue;
@@ -598,7 +614,7 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
             xo[r] = T(0);
             continue;
           }
-          const Coords c = coords_of(r, lv.nx, lv.nxy);
+          const Coords c = coords_of(r, lv);
           T v[NQ];
           gather_lv(lv, c, r, xi, v);
           T num = T(0), den = T(0);
