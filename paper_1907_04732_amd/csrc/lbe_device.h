@@ -59,7 +59,7 @@ __device__ __forceinline__ void pull(const Lattice &L, int r, uint32_t m, const 
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     const int j = OPP[i];
-    f[i] = solid_link(m, j) ? fin[j * N + r] : fin[i * N + nbr(o, r, j)];
+    f[i] = fin[solid_link(m, j) ? j * N + r : i * N + nbr(o, r, j)];  // one unconditional load
   }
 }
 

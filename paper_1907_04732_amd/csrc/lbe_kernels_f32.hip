@@ -42,6 +42,7 @@ __device__ __forceinline__ void link_force_f32(const Lattice &L, const Phys &P, 
   }
 }
 
+// the source slot is selected, not the load, so all 19 loads are unconditional
 __device__ __forceinline__ void pull_f32(const Lattice &L, int r, uint32_t m, const Offs &o,
                                          const float *__restrict__ hin, float (&h)[NQ]) {
   const int N = L.n;
@@ -49,7 +50,7 @@ __device__ __forceinline__ void pull_f32(const Lattice &L, int r, uint32_t m, co
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     const int j = OPP[i];
-    h[i] = solid_link(m, j) ? hin[j * N + r] : hin[i * N + nbr(o, r, j)];
+    h[i] = hin[solid_link(m, j) ? j * N + r : i * N + nbr(o, r, j)];
   }
 }
 
@@ -175,18 +176,32 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f32(Lattice L, Phys P,
     nr[k] = ref[k] + nu[k * N + r];
     Js[k] = 0.f;
   }
+  // c_i . u and the deviations at every neighbour, loaded before any is used
+  // (solid neighbours too, skipped below)
+  float cut[NQ], nn[K][NQ];
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    const int rn = nbr(o, r, i);
+    float c = 0.f;
+    if (CX[i]) c += CX[i] * u[rn];
+    if (CY[i]) c += CY[i] * u[N + rn];
+    if (CZ[i]) c += CZ[i] * u[2 * N + rn];
+    cut[i] = c;
+#pragma unroll
+    for (int k = 0; k < K; ++k) nn[k][i] = nu[k * N + rn];
+  }
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if (solid_link(m, i)) continue;
-    const int rn = nbr(o, r, i);
-    float cu_h = 0.f, cu_t = 0.f;
-    if (CX[i]) { cu_h += CX[i] * ux; cu_t += CX[i] * u[rn]; }
-    if (CY[i]) { cu_h += CY[i] * uy; cu_t += CY[i] * u[N + rn]; }
-    if (CZ[i]) { cu_h += CZ[i] * uz; cu_t += CZ[i] * u[2 * N + rn]; }
+    float cu_h = 0.f;
+    if (CX[i]) cu_h += CX[i] * ux;
+    if (CY[i]) cu_h += CY[i] * uy;
+    if (CZ[i]) cu_h += CZ[i] * uz;
+    const float cu_t = cut[i];
     const float w3 = float(3.0 * WQ[i]);
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      Js[k] += w3 * (nr[k] * cu_h + (ref[k] + nu[k * N + rn]) * cu_t);
+      Js[k] += w3 * (nr[k] * cu_h + (ref[k] + nn[k][i]) * cu_t);
   }
   double q = P.qref[sy];
 #pragma unroll
