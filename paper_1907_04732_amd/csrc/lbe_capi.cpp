@@ -719,7 +719,9 @@ int plan_small_levels(lbe_ctx *c) {
     if (L - from > MG_MAX_SMALL || c->mg[from].lv.n > 2048) continue;
     // per cell: correction and right-hand side (and the second Jacobi buffer)
     const size_t per_cell = c->mg_jacobi > 0.0 ? 3 : 2;
-    size_t tbytes = tsz * (size_t)std::max(c->mg_nf, 0), mbytes = 0;
+    // the exact coarsest solve's compact right-hand side and its part sums
+    const size_t dense = c->mg_nf > 0 ? (size_t)c->mg_nf + 1024 : 0;
+    size_t tbytes = tsz * dense, mbytes = 0;
     for (int k = from; k < L; ++k) {
       tbytes += per_cell * tsz * (size_t)c->mg[k].lv.n;
       mbytes += 4 * (size_t)c->mg[k].lv.n;
@@ -742,7 +744,7 @@ int plan_small_levels(lbe_ctx *c) {
       if (per_cell == 3) te += D.lv.n;
     }
     S.off_x = (int)te;
-    te += std::max(c->mg_nf, 0);
+    te += dense;
     size_t me = te * tsz / 4;  // flag words follow, in 4-byte units
     for (int k = 0; k < S.nlev; ++k) {
       S.off_m[k] = (int)me;

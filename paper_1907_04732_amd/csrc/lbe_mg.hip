@@ -557,15 +557,25 @@ __global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, T 
 // group adds its partial sums.  The inverse is stored column-major
 // (ainv[j * nf + row]).
 
+// The exact coarsest solve e = A^-1 r over the nf fluid cells: the inverse is
+// column-major (ainv[j nf + row]).  Its columns are split into P = DENSE_T /
+// nf interleaved parts (column j in part j mod P); part p of a row is summed
+// in column order, and the P part sums in part order.  In one work-group of
+// DENSE_T threads, thread t takes row t mod nf of part t / nf, so the lanes
+// of a wave read consecutive rows of one column: contiguous loads.
+constexpr int DENSE_T = 1024;
+
 template <class T>
-__device__ __forceinline__ T dense_row_part(int nf, const T *__restrict__ ainv,
-                                            const T *__restrict__ x, int row, int part) {
+__device__ __forceinline__ T dense_part(int nf, int parts, const T *__restrict__ ainv,
+                                        const T *__restrict__ x, int row, int part) {
   T acc = T(0);
-#pragma unroll 6
-  for (int j = part; j < nf; j += 8) acc += ainv[(size_t)j * nf + row] * x[j];
+#pragma unroll 8
+  for (int j = part; j < nf; j += parts) acc += ainv[(size_t)j * nf + row] * x[j];
   return acc;
 }
 
+// one thread per row, the parts in sequence: the same sums as the split
+// across a work-group
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_coarse_dense(int nf, const T *__restrict__ ainv,
                                                         const int *__restrict__ fcell,
@@ -576,12 +586,12 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_dense(int nf, const T *__restr
   if (ctl->done) return;
   for (int j = threadIdx.x; j < nf; j += BLOCK) xc[j] = rhs[fcell[j]];
   __syncthreads();
-  const int t = blockIdx.x * BLOCK + threadIdx.x;
-  const int row = t >> 3, part = t & 7;
-  T acc = row < nf ? dense_row_part(nf, ainv, xc, row, part) : T(0);
-  int dummy = 0;
-  group8_sum(acc, dummy);
-  if (part == 0 && row < nf) e[fcell[row]] = acc;
+  const int row = blockIdx.x * BLOCK + threadIdx.x;
+  if (row >= nf) return;
+  const int parts = DENSE_T / nf;
+  T v = dense_part(nf, parts, ainv, xc, row, 0);
+  for (int p = 1; p < parts; ++p) v += dense_part(nf, parts, ainv, xc, row, p);
+  e[fcell[row]] = v;
 }
 
 // ---- the coarse end of the V-cycle in one work-group --------------------------
@@ -591,6 +601,7 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_dense(int nf, const T *__restr
 // prolongation, exact (dense inverse) or swept coarsest level.
 
 constexpr int SMALL_BLOCK = 1024;
+static_assert(SMALL_BLOCK == DENSE_T, "the dense solve splits one work-group's threads");
 
 template <class T>
 __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const uint32_t *sm) {
@@ -713,17 +724,23 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_mg_small(MgSmall S, const T *__
     T *e = lds + S.off_e[k];
     const T *rh = lds + S.off_r[k];
     if (S.ainv) {
-      // compact right-hand side over the fluid cells, then eight lanes per row
+      // compact right-hand side over the fluid cells, then the part sums of
+      // every row (k_coarse_dense's arithmetic) through LDS
       const T *ainv = reinterpret_cast<const T *>(S.ainv);
       T *xc = lds + S.off_x;
+      T *psum = xc + S.nf;  // DENSE_T entries
       for (int j = threadIdx.x; j < S.nf; j += SMALL_BLOCK) xc[j] = rh[S.fcell[j]];
       __syncthreads();
-      for (int t = threadIdx.x; t < 8 * S.nf; t += SMALL_BLOCK) {
-        const int row = t >> 3, part = t & 7;
-        T acc = dense_row_part(S.nf, ainv, xc, row, part);
-        int dummy = 0;
-        group8_sum(acc, dummy);
-        if (part == 0) e[S.fcell[row]] = acc;
+      const int parts = DENSE_T / S.nf;
+      {
+        const int row = threadIdx.x % S.nf, part = threadIdx.x / S.nf;
+        if (part < parts) psum[part * S.nf + row] = dense_part(S.nf, parts, ainv, xc, row, part);
+      }
+      __syncthreads();
+      for (int row = threadIdx.x; row < S.nf; row += SMALL_BLOCK) {
+        T v = psum[row];
+        for (int p = 1; p < parts; ++p) v += psum[p * S.nf + row];
+        e[S.fcell[row]] = v;
       }
       __syncthreads();
     } else {
@@ -859,7 +876,7 @@ hipError_t launch_mg_coarse(hipStream_t s, const MgLevel &lv, double omega, doub
 template <class T>
 hipError_t launch_mg_coarse_dense(hipStream_t s, int nf, const T *ainv, const int *fcell,
                                   const T *rhs, T *e, const SolveCtl *ctl) {
-  hipLaunchKernelGGL(k_coarse_dense<T>, dim3(blocks_for(8L * nf)), dim3(BLOCK), 0, s, nf, ainv,
+  hipLaunchKernelGGL(k_coarse_dense<T>, dim3(blocks_for(nf)), dim3(BLOCK), 0, s, nf, ainv,
                      fcell, rhs, e, ctl);
   return hipGetLastError();
 }
