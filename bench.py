@@ -377,7 +377,7 @@ def main():
     ap.add_argument("--shapes", default=",".join(SHAPES),
                     help="comma list of larger lattices measured beside the headline (empty: none)")
     ap.add_argument("--shape-forms", default="fp32-mg,fp64-mg")
-    ap.add_argument("--shape-steps", type=int, default=20)
+    ap.add_argument("--shape-steps", type=int, default=200)
     ap.add_argument("--adjoint-forms", default="fp32-mg",
                     help="forms of the reverse-mode measurement on the porous electrode "
                          "(empty: none)")
