@@ -349,10 +349,11 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
 }
 
 // ---- restriction: coarse rhs = mean of the fluid children's residuals -------
-// Eight consecutive lanes take the eight children of one coarse cell (lane
-// bits = dx, dy, dz) and combine their residuals with cross-lane adds, so
-// each lane evaluates one fine-cell residual.  Groups of eight never straddle
-// a wavefront.
+// Each lane evaluates one fine-cell residual.  On narrow levels eight
+// consecutive lanes take the eight children of one coarse cell (lane bits =
+// dx, dy, dz) and combine them with cross-lane adds (groups of eight never
+// straddle a wavefront); on wide levels k_restrict_tiled keeps the lanes in
+// row order and combines through LDS, in the same order.
 
 // Residual of child j (bits dx, dy, dz) of coarse cell R, or nothing when
 // the child is solid or falls outside an odd-sized fine level.
@@ -417,6 +418,62 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(MgTransfer tr, const uint32_
     ec[R] = T(0);
     rc[R] = (fluid && cnt) ? v / T(cnt) : T(0);
   }
+}
+
+// The same restriction with one fine cell per thread in row order: a block
+// takes a tile of 16 x 2 x 1 coarse cells, i.e. 32 x 4 x 2 fine cells, so
+// the lanes of a wave read 32 consecutive fine cells of two rows (whole
+// cache lines) instead of 2 x 2 x 2 blocks; the eight children of a coarse
+// cell then meet in LDS and are summed in the eight-lane tree's order, so
+// every sum is bit for bit that of k_restrict.
+constexpr int RT_X = 16, RT_Y = 2;  // coarse cells per tile along x and y
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_restrict_tiled(MgTransfer tr,
+                                                          const uint32_t *__restrict__ mf,
+                                                          const uint32_t *__restrict__ mc,
+                                                          const T *__restrict__ rf,
+                                                          const T *__restrict__ ef,
+                                                          T *__restrict__ rc, T *__restrict__ ec,
+                                                          const SolveCtl *__restrict__ ctl) {
+  static_assert(2 * RT_X * 2 * RT_Y * 2 == BLOCK, "one fine cell per thread");
+  __shared__ T sv[BLOCK];
+  __shared__ int sc[BLOCK];
+  if (ctl->done) return;
+  const int t = threadIdx.x;
+  const int fx = t & (2 * RT_X - 1), fy = (t / (2 * RT_X)) & (2 * RT_Y - 1), fz = t / (4 * RT_X * RT_Y);
+  const int X = blockIdx.x * RT_X + (fx >> 1), Y = blockIdx.y * RT_Y + (fy >> 1), Z = blockIdx.z;
+  T v = T(0);
+  int cnt = 0;
+  if (X < tr.c.nx && Y < tr.c.ny) {
+    const int R = X + tr.c.nx * (Y + tr.c.ny * Z);
+    if (!(mc[R] & SOLID_BIT))
+      restrict_child<T>(tr, R, (fx & 1) | ((fy & 1) << 1) | (fz << 2), mf, rf, ef, v, cnt);
+  }
+  sv[t] = v;
+  sc[t] = cnt;
+  __syncthreads();
+  if (t >= RT_X * RT_Y) return;
+  const int cx = t % RT_X, cy = t / RT_X;
+  const int Xo = blockIdx.x * RT_X + cx, Yo = blockIdx.y * RT_Y + cy;
+  if (Xo >= tr.c.nx || Yo >= tr.c.ny) return;
+  // child (a, b, d) of coarse cell (cx, cy) sits at thread
+  // (2 cx + a) + 2 RT_X (2 cy + b) + 4 RT_X RT_Y d
+  const int base = 2 * cx + 2 * RT_X * (2 * cy);
+  T q[8];
+  int n[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = base + (j & 1) + 2 * RT_X * ((j >> 1) & 1) + 4 * RT_X * RT_Y * (j >> 2);
+    q[j] = sv[k];
+    n[j] = sc[k];
+  }
+  const T sum = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+  const int cn = ((n[0] + n[1]) + (n[2] + n[3])) + ((n[4] + n[5]) + (n[6] + n[7]));
+  const int R = Xo + tr.c.nx * (Yo + tr.c.ny * blockIdx.z);
+  const bool fluid = !(mc[R] & SOLID_BIT);
+  ec[R] = T(0);
+  rc[R] = (fluid && cn) ? sum / T(cn) : T(0);
 }
 
 // ---- prolongation: e_f += trilinear interpolation of e_c --------------------
@@ -851,8 +908,16 @@ template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
                               const SolveCtl *ctl) {
-  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(8L * tr.c.n)), dim3(BLOCK), 0, s, tr, mf, mc,
-                     rf, ef, rc, ec, ctl);
+  // the tiled form where a level is wide enough to fill its tiles (and its
+  // planes fit the grid's z extent)
+  if (tr.c.nx >= RT_X && tr.c.ny >= RT_Y && tr.c.nz <= 65535) {
+    const dim3 grid((tr.c.nx + RT_X - 1) / RT_X, (tr.c.ny + RT_Y - 1) / RT_Y, tr.c.nz);
+    hipLaunchKernelGGL(k_restrict_tiled<T>, grid, dim3(BLOCK), 0, s, tr, mf, mc, rf, ef, rc, ec,
+                       ctl);
+  } else {
+    hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(8L * tr.c.n)), dim3(BLOCK), 0, s, tr, mf,
+                       mc, rf, ef, rc, ec, ctl);
+  }
   return hipGetLastError();
 }
 
