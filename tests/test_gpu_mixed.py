@@ -1,7 +1,7 @@
 """FP32-mixed form (FP32 deviation storage and collision, FP32 Poisson
 correction inside FP64 defect correction) against the FP64 oracle.
 
-Bars (the benchmark spec): potential within 1e-5 of the electrode voltage scale,
+Bars: potential within 1e-5 of the electrode voltage scale,
 electrode charge within 1e-5 of its magnitude, electro-osmotic velocity within
 1e-4 of its peak.  Concentrations are reported normalised by the largest
 departure from the bulk value.
