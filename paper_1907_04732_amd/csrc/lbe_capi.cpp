@@ -54,6 +54,7 @@ struct lbe_ctx {
   int checks_queued = 0;        // residual checks queued in the running solve
   int pred_iters = 0;         // iterations the last time-step solve needed
   bool use_graphs = true;     // replay one solver unit as a captured HIP graph
+  bool tiles = true;          // the row-order (LDS-combined) restriction where it applies
   hipGraphExec_t unit_exec = nullptr;
 
   // electrode charge tables
@@ -891,7 +892,7 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
   lbe_ctx::MgDev &C = c->mg[l + 1];
   rc = run(c, KK_MG_RESTRICT, L.lv.n, [&] {
     return launch_mg_restrict<T>(c->stream, C.tr, L.mask, C.mask, r, cur, (T *)C.r, (T *)C.e,
-                                 c->ctl);
+                                 c->ctl, c->tiles);
   });
   if (rc) return rc;
   T *ce = nullptr;
@@ -1582,6 +1583,8 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
   {
     const char *ng = getenv("LBE_NO_GRAPHS");
     c->use_graphs = !(ng && *ng && *ng != '0');
+    const char *nt = getenv("LBE_NO_TILES");  // the eight-lane restriction only (same results)
+    c->tiles = !(nt && *nt && *nt != '0');
     c->mg_jacobi = p.mg_smoother == LBE_MG_JACOBI ? 1.0 : 0.0;
     const bool same = p.mg_nu1_coarse == 0 && p.mg_nu2_coarse == 0;
     c->mg_nu1c = same ? p.mg_nu1 : p.mg_nu1_coarse;

@@ -297,7 +297,7 @@ hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double 
 template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
-                              const SolveCtl *ctl);
+                              const SolveCtl *ctl, bool tiled);  // tiled: k_restrict_tiled where it applies
 template <class T>
 hipError_t launch_mg_prolong(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                              const uint32_t *mc, const T *ec, T *ef, const SolveCtl *ctl);

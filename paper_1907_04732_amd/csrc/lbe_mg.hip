@@ -907,10 +907,10 @@ hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double 
 template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
-                              const SolveCtl *ctl) {
+                              const SolveCtl *ctl, bool tiled) {
   // the tiled form where a level is wide enough to fill its tiles (and its
   // planes fit the grid's z extent)
-  if (tr.c.nx >= RT_X && tr.c.ny >= RT_Y && tr.c.nz <= 65535) {
+  if (tiled && tr.c.nx >= RT_X && tr.c.ny >= RT_Y && tr.c.nz <= 65535) {
     const dim3 grid((tr.c.nx + RT_X - 1) / RT_X, (tr.c.ny + RT_Y - 1) / RT_Y, tr.c.nz);
     hipLaunchKernelGGL(k_restrict_tiled<T>, grid, dim3(BLOCK), 0, s, tr, mf, mc, rf, ef, rc, ec,
                        ctl);
@@ -986,7 +986,7 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                          const SolveCtl *, double *);                           \
   template hipError_t launch_mg_restrict<T>(hipStream_t, const MgTransfer &, const uint32_t *,  \
                                             const uint32_t *, const T *, const T *, T *, T *,   \
-                                            const SolveCtl *);                                  \
+                                            const SolveCtl *, bool);                            \
   template hipError_t launch_mg_prolong<T>(hipStream_t, const MgTransfer &, const uint32_t *,   \
                                            const uint32_t *, const T *, T *, const SolveCtl *); \
   template hipError_t launch_mg_coarse<T>(hipStream_t, const MgLevel &, double, double, int,    \

@@ -189,3 +189,36 @@ def test_krylov_fewer_cycles_on_the_coaxial_cell():
     assert kry < plain
     # |A^-1| <= (R2 - R1)^2 / 8 ~ 512 for the 64-wide gap: 5e-8 on phi at tol 1e-10
     assert rel(res[lbe.KRYLOV][1], res[0][1], 0.1) <= 1e-6
+
+
+@pytest.mark.parametrize("geometry", ["slab", "random"])
+@pytest.mark.parametrize("precision", [lbe.FP32_MIXED, lbe.FP64])
+def test_tiled_kernels_match_untiled(geometry, precision, monkeypatch):
+    """On levels wide enough for it the restriction runs in row order with
+    the children of a coarse cell combined in LDS, claiming the eight-lane
+    kernel's values and summation order; a run with it (the default) and one
+    without (LBE_NO_TILES=1) must agree bit for bit, here on a 64 x 8 x 34
+    lattice (both restrictions below it are tiled)."""
+    if geometry == "slab":
+        shape, t, ps = W.slab(64, 8, 32, 1, 0.05, -0.05)
+        flags = lbe.EXTRAPOLATE
+    else:
+        shape = (64, 8, 34)
+        t, ps = G.random_geometry(shape, 3, seed=13, fill=0.12)
+        # plain cycles can diverge around blobs: Krylov acceleration
+        flags = lbe.EXTRAPOLATE | lbe.ALLOW_FLOATING | lbe.KRYLOV
+    rs = W.salt_for_debye(4.0, G.LB)
+    n0 = W.noisy_concentrations(t, [rs, rs], 1e-2, seed=8)
+    p = dict(z=(1, -1), D=(0.05, 0.08), lB=G.LB, tau=0.9, Eapp=(1e-3, 0.0, 5e-4), tol=1e-11,
+             max_iter=1000, precision=precision, poisson=lbe.MG, flags=flags)
+    out = []
+    for no_tiles in ("0", "1"):
+        monkeypatch.setenv("LBE_NO_TILES", no_tiles)
+        g = lbe.Lbe(lbe.make_params(shape, **p), t, ps, n0, (rs, rs))
+        g.step(12)
+        out.append((g.fields(), g.qhist(), g.totals()["poisson_total"]))
+        g.close()
+    (fa, qa, ia), (fb, qb, ib) = out
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    assert np.array_equal(qa, qb) and ia == ib
