@@ -105,3 +105,34 @@ def test_mixed_full_slab_properties():
     # the library's residual uses the FP64 source accumulated from the FP32
     # deviations; recomputing it from the returned n adds ~1e-15 rounding
     assert np.abs(R).max() <= 1.05e-10
+
+
+def test_benchmark_configuration_properties():
+    """The 64x64x130 slab in the launch configuration the benchmark times
+    (mixed form, Jacobi V(1,1) on every level, quadratic warm start, tol
+    1e-10), past the warm-up: every step's solve meets the tolerance in the
+    FP64 residual recomputed from the returned fields, ions and mass are
+    conserved, and Gauss's law closes (sum of electrode charges = -ionic
+    charge, to the solve's tolerance)."""
+    w = W.eo_slab(noise=True)
+    p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, Eapp=w.Eapp, omega=w.omega,
+                        tol=1e-10, max_iter=1_000_000, check_every=8,
+                        precision=lbe.FP32_MIXED, poisson=lbe.MG, flags=lbe.EXTRAPOLATE,
+                        mg_nu1=1, mg_nu2=1, mg_nu1_coarse=1, mg_nu2_coarse=1)
+    g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref)
+    t0 = g.totals()
+    g.step(40)
+    t1 = g.totals()
+    assert t1["step"] == 40 and t1["poisson_resid"] <= 1e-10
+    assert abs(t1["mass"] / t0["mass"] - 1) < 1e-9
+    for k in range(2):
+        assert abs(t1["nk"][k] / t0["nk"][k] - 1) < 1e-9
+    fg = g.fields(f=False)
+    R = residual_numpy(w.shape, w.node_type, fg["phi"], fg["n"], w.z, w.lB)
+    assert np.abs(R).max() <= 1.05e-10
+    q = g.qhist()
+    assert q.shape == (41, 2)
+    # Gauss: Q_1 + Q_2 = -Q_ion up to eps * (sum of |R| over fluid nodes)
+    eps = T.permittivity(w.lB)
+    bound = eps * np.abs(R).sum() + 1e-12 * np.abs(q[-1]).max()
+    assert abs(q[-1].sum() + t1["q_ion"]) <= bound
