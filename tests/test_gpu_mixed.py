@@ -107,9 +107,10 @@ def test_mixed_full_slab_properties():
     assert np.abs(R).max() <= 1.05e-10
 
 
-def test_benchmark_configuration_properties():
+@pytest.mark.parametrize("precision", [lbe.FP32_MIXED, lbe.FP64])
+def test_benchmark_configuration_properties(precision):
     """The 64x64x130 slab in the launch configuration the benchmark times
-    (mixed form, Jacobi V(1,1) on every level, quadratic warm start, tol
+    (both forms, Jacobi V(1,1) on every level, quadratic warm start, tol
     1e-10), past the warm-up: every step's solve meets the tolerance in the
     FP64 residual recomputed from the returned fields, ions and mass are
     conserved, and Gauss's law closes (sum of electrode charges = -ionic
@@ -117,7 +118,7 @@ def test_benchmark_configuration_properties():
     w = W.eo_slab(noise=True)
     p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, Eapp=w.Eapp, omega=w.omega,
                         tol=1e-10, max_iter=1_000_000, check_every=8,
-                        precision=lbe.FP32_MIXED, poisson=lbe.MG, flags=lbe.EXTRAPOLATE,
+                        precision=precision, poisson=lbe.MG, flags=lbe.EXTRAPOLATE,
                         mg_nu1=1, mg_nu2=1, mg_nu1_coarse=1, mg_nu2_coarse=1)
     g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref)
     t0 = g.totals()
