@@ -407,7 +407,9 @@ def main():
     head = res[forms[0]]
     hform, hsolver = FORMS[forms[0]]
     out = {
-        "metric": "MLUPS per full LBE step (fluid+ions+Poisson)",
+        # value: the headline form's MLUPS; the FP64 form is in "forms", the
+        # fraction of the HBM peak in "roofline"
+        "metric": "MLUPS per full LBE step (fluid+ions+Poisson), FP64 vs FP32-mixed, % HBM peak",
         "value": head["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
