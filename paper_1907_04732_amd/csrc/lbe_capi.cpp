@@ -55,6 +55,10 @@ struct lbe_ctx {
   int pred_iters = 0;         // iterations the last time-step solve needed
   bool use_graphs = true;     // replay one solver unit as a captured HIP graph
   bool tiles = true;          // the row-order (LDS-combined) restriction where it applies
+  // a time step's charge row: queued by the solve right after its predicted
+  // units, gated on convergence, so it runs while the host waits
+  double *charge_dst = nullptr;
+  bool charge_queued = false;
   hipGraphExec_t unit_exec = nullptr;
 
   // electrode charge tables
@@ -421,6 +425,8 @@ int read_ctl(lbe_ctx *c) {
 // enough it adds a quarter more (at least one unit) and synchronises again.
 // A unit (per_check iterations + check) is captured once as a HIP graph and
 // replayed (not while per-kernel profiling is on).
+int charges_to(lbe_ctx *c, double *dst, const SolveCtl *gate = nullptr);
+
 template <class Step, class Check>
 int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&step,
               Check &&check) {
@@ -480,6 +486,12 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
       if ((rc = unit_once(m))) return rc;
       c->checks_queued += 1;
       queued += m;
+    }
+    // the step's charge behind the queued units: it runs while the host
+    // waits, and does nothing unless they reached the tolerance
+    if (c->charge_dst && !c->prof) {
+      if ((rc = charges_to(c, c->charge_dst, c->ctl))) return rc;
+      c->charge_queued = true;
     }
     if ((rc = read_ctl(c))) return rc;
     if (c->ctl_h->done) break;
@@ -1041,7 +1053,7 @@ int poisson_solve(lbe_ctx *c, bool learn) {
   return sor_solve(c, learn);
 }
 
-int charges_to(lbe_ctx *c, double *dst) {
+int charges_to(lbe_ctx *c, double *dst, const SolveCtl *gate) {
   if (c->ne == 0) return LBE_OK;
   if (c->nblk_charge == 0) {  // no electrode touches the fluid
     HIPCHK(c, hipMemsetAsync(dst, 0, sizeof(double) * c->ne, c->stream));
@@ -1051,7 +1063,7 @@ int charges_to(lbe_ctx *c, double *dst) {
   return run(c, KK_CHARGE, c->L.n, [&] {
     return launch_charge(c->stream, c->L, q_scale, c->mask, c->phi, c->iface, c->blk_elec,
                          c->blk_begin, c->blk_end, c->nblk_charge, c->ne, c->partial,
-                         dst);
+                         dst, gate);
   });
 }
 
@@ -1090,6 +1102,11 @@ int rewind_step(lbe_ctx *c, int a, int hist, bool record) {
 int one_step(lbe_ctx *c, bool record = true) {
   const int a = c->cur, b = 1 - c->cur;
   const int hist = c->extrap_hist;
+  // room for this step's charge row before anything moves
+  if (record) {
+    const int rc = grow_history(c);
+    if (rc) return rc;
+  }
   // pass B keeps phi(t) for a rewind: in the extrapolation history, else in
   // phi_keep (order -1: a plain copy)
   double *keep = c->phi_prev ? c->phi_prev : c->phi_keep;
@@ -1113,14 +1130,24 @@ int one_step(lbe_ctx *c, bool record = true) {
   if (rc) return rc;
   if (c->phi_prev) c->extrap_hist = std::min(hist + 1, 2);
   c->cur = b;
-  if (record) c->step++;
+  if (record) {
+    c->step++;
+    c->charge_dst = c->qhist + c->qlen * std::max(c->ne, 1);
+    c->charge_queued = false;
+  }
   rc = poisson_solve(c, true);
+  c->charge_dst = nullptr;
   if (rc == LBE_ENOCONV || rc == LBE_ENONFINITE) {
     const int rc2 = rewind_step(c, a, hist, record);
     return rc2 ? rc2 : rc;
   }
   if (rc) return rc;
-  return record ? record_charge(c) : LBE_OK;
+  if (!record) return LBE_OK;
+  if (c->charge_queued) {  // already computed behind the solve's last units
+    c->qlen++;
+    return LBE_OK;
+  }
+  return record_charge(c);
 }
 
 // ---- reverse mode -----------------------------------------------------------

@@ -194,10 +194,11 @@ int residual_blocks(const Lattice &L);
 hipError_t launch_resid_f64(hipStream_t s, const Lattice &L, const uint32_t *mask,
                             const double *src, const double *phi, double *partial, SolveCtl *ctl,
                             int add);
+// gate (may be NULL): both kernels return at once unless gate->done is set
 hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
                          const double *phi, const int *iface_site, const int *blk_elec,
                          const int *blk_begin, const int *blk_end, int nblocks, int ne,
-                         double *partial, double *out);
+                         double *partial, double *out, const SolveCtl *gate);
 hipError_t launch_totals_f64(hipStream_t s, const Lattice &L, int K, const int *z,
                              const uint32_t *mask, const double *fin, const double *n,
                              double *partial, double *out /*2+K*/);

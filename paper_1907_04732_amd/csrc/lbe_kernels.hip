@@ -272,8 +272,10 @@ __global__ __launch_bounds__(BLOCK) void k_charge(Lattice L, double q_scale,
                                                   const int *__restrict__ iface_site,
                                                   const int *__restrict__ blk_begin,
                                                   const int *__restrict__ blk_end,
-                                                  double *__restrict__ partial) {
+                                                  double *__restrict__ partial,
+                                                  const SolveCtl *__restrict__ gate) {
   __shared__ double sm[BLOCK / WAVE];
+  if (gate && !gate->done) return;  // queued ahead of a solve that has not converged
   const int b = blockIdx.x;
   const int idx = blk_begin[b] + threadIdx.x;
   double v = 0.0;
@@ -306,8 +308,10 @@ __device__ __forceinline__ double two_sum_err(double a, double b, double t) {
 
 __global__ __launch_bounds__(BLOCK) void k_final_charge(const double *__restrict__ partial,
                                                         const int *__restrict__ blk_elec, int nb,
-                                                        double *__restrict__ out) {
+                                                        double *__restrict__ out,
+                                                        const SolveCtl *__restrict__ gate) {
   __shared__ double ts[BLOCK], tc[BLOCK];
+  if (gate && !gate->done) return;
   const int e = blockIdx.x;
   double s = 0.0, c = 0.0;
   for (int k = threadIdx.x; k < nb; k += BLOCK) {
@@ -505,12 +509,12 @@ hipError_t launch_resid_f64(hipStream_t s, const Lattice &L, const uint32_t *mas
 hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
                          const double *phi, const int *iface_site, const int *blk_elec,
                          const int *blk_begin, const int *blk_end, int nblocks, int ne,
-                         double *partial, double *out) {
+                         double *partial, double *out, const SolveCtl *gate) {
   if (nblocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_charge, dim3(nblocks), dim3(BLOCK), 0, s, L, q_scale, mask, phi,
-                     iface_site, blk_begin, blk_end, partial);
+                     iface_site, blk_begin, blk_end, partial, gate);
   hipLaunchKernelGGL(k_final_charge, dim3(ne), dim3(BLOCK), 0, s, partial, blk_elec, nblocks,
-                     out);
+                     out, gate);
   return hipGetLastError();
 }
 
