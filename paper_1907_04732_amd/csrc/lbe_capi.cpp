@@ -52,6 +52,7 @@ struct lbe_ctx {
   SolveCtl *ctl_pub = nullptr;  // host-mapped copy the checks publish to (coherent)
   SolveCtl *ctl_pub_d = nullptr;  // its device address
   int checks_queued = 0;        // residual checks queued in the running solve
+  int seq = 0;                  // solves started (the running one's stamp)
   int pred_iters = 0;         // iterations the last time-step solve needed
   bool use_graphs = true;     // replay one solver unit as a captured HIP graph
   bool tiles = true;          // the row-order (LDS-combined) restriction where it applies
@@ -375,13 +376,9 @@ int read_scalars(lbe_ctx *c, int count) {
 }
 
 int reset_ctl(lbe_ctx *c) {
-  *c->ctl_h = SolveCtl{0.0, c->p.tol, 0, 0, 0, 0, 0, 0, c->ctl_pub_d};
-  if (c->ctl_pub) {
-    // nothing of an earlier solve is in flight: its last wait saw all its checks
-    volatile SolveCtl *v = c->ctl_pub;
-    v->done = 0;
-    v->checks = 0;
-  }
+  // a new sequence number: whatever an earlier solve published is ignored
+  // (its last stamp may still be on its way when this one starts)
+  *c->ctl_h = SolveCtl{0.0, c->p.tol, 0, 0, 0, 0, 0, ++c->seq, 0ull, c->ctl_pub_d};
   c->checks_queued = 0;
   HIPCHK(c, hipMemcpyAsync(c->ctl, c->ctl_h, sizeof(SolveCtl), hipMemcpyHostToDevice, c->stream));
   return LBE_OK;
@@ -397,9 +394,12 @@ int read_ctl(lbe_ctx *c) {
     volatile SolveCtl *v = c->ctl_pub;
     const auto t0 = std::chrono::steady_clock::now();
     for (long spin = 0;; ++spin) {
-      if (v->done || v->checks >= c->checks_queued) {
-        c->ctl_h->done = v->done;
-        c->ctl_h->checks = v->checks;
+      const unsigned long long st = v->stamp;  // one 8-byte load
+      const int done = (int)((st >> 31) & 1u), checks = (int)(st & 0x7fffffffu);
+      if ((unsigned)(st >> 32) == (unsigned)c->seq && (done || checks >= c->checks_queued)) {
+        // the values were written before the stamp (system-scope fence)
+        c->ctl_h->done = done;
+        c->ctl_h->checks = checks;
         c->ctl_h->resid = v->resid;
         c->ctl_h->count = v->count;
         c->ctl_h->iters = v->iters;
@@ -495,6 +495,9 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
     }
     if ((rc = read_ctl(c))) return rc;
     if (c->ctl_h->done) break;
+    // every check queued so far said not done, so the gated charge queued
+    // behind them returned at once; it is queued again behind the next units
+    c->charge_queued = false;
     if (queued >= p.max_iter) {
       c->last_iters = queued;
       c->last_resid = c->ctl_h->resid;
@@ -1718,6 +1721,8 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
       if (c->ctl_pub) (void)hipHostFree(c->ctl_pub);
       c->ctl_pub = nullptr;
       c->ctl_pub_d = nullptr;
+    } else {
+      memset((void *)c->ctl_pub, 0, sizeof(SolveCtl));  // the stamp of no solve
     }
     TRY(dalloc(c, &c->iface, g.iface.size()));
     TRY(dalloc(c, &c->blk_elec, g.blk_elec.size()));

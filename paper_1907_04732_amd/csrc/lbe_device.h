@@ -172,8 +172,8 @@ __global__ __launch_bounds__(FINAL) void k_final_resid(const double *__restrict_
       ctl->nonfinite = bad;
     }
     // publish to the host: the values first, then (after a system-scope
-    // fence) the fields the host polls on, which the end of the kernel
-    // makes visible at the latest
+    // fence) the stamp the host polls on, in one 8-byte store, which the end
+    // of the kernel makes visible at the latest
     if (ctl->mirror) {
       volatile SolveCtl *hm = ctl->mirror;
       hm->resid = res;
@@ -181,8 +181,9 @@ __global__ __launch_bounds__(FINAL) void k_final_resid(const double *__restrict_
       hm->iters = ctl->iters;
       hm->nonfinite = ctl->nonfinite;
       __threadfence_system();
-      hm->done = ctl->done;
-      hm->checks = ctl->checks;
+      hm->stamp = ((unsigned long long)(unsigned)ctl->seq << 32) |
+                  ((unsigned long long)(ctl->done ? 1u : 0u) << 31) |
+                  (unsigned long long)(unsigned)ctl->checks;
     }
   }
 }

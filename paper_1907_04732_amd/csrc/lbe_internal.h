@@ -95,7 +95,11 @@ struct SolveCtl {
   int checks;     // residual evaluations so far
   int nonfinite;  // the residual was NaN or Inf
   int count;      // sweeps or cycles completed so far (each check adds its unit)
-  int pad;
+  int seq;        // which solve of the context this is (set by the host)
+  // published to the mirror in one 8-byte store after the values above:
+  // seq << 32 | done << 31 | checks, so the host never pairs a stop flag or
+  // check count of one solve (or check) with another
+  unsigned long long stamp;
   SolveCtl *mirror;  // host-mapped copy (device address), or null
 };
 

@@ -275,7 +275,7 @@ __global__ __launch_bounds__(BLOCK) void k_charge(Lattice L, double q_scale,
                                                   double *__restrict__ partial,
                                                   const SolveCtl *__restrict__ gate) {
   __shared__ double sm[BLOCK / WAVE];
-  if (gate && !gate->done) return;  // queued ahead of a solve that has not converged
+  if (gate && (!gate->done || gate->nonfinite)) return;  // queued ahead of a solve that has not converged
   const int b = blockIdx.x;
   const int idx = blk_begin[b] + threadIdx.x;
   double v = 0.0;
@@ -311,7 +311,7 @@ __global__ __launch_bounds__(BLOCK) void k_final_charge(const double *__restrict
                                                         double *__restrict__ out,
                                                         const SolveCtl *__restrict__ gate) {
   __shared__ double ts[BLOCK], tc[BLOCK];
-  if (gate && !gate->done) return;
+  if (gate && (!gate->done || gate->nonfinite)) return;
   const int e = blockIdx.x;
   double s = 0.0, c = 0.0;
   for (int k = threadIdx.x; k < nb; k += BLOCK) {
