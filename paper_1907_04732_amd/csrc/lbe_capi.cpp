@@ -56,6 +56,7 @@ struct lbe_ctx {
   int pred_iters = 0;         // iterations the last time-step solve needed
   bool use_graphs = true;     // replay one solver unit as a captured HIP graph
   bool tiles = true;          // the row-order (LDS-combined) restriction where it applies
+  int tb_a = 256, tb_b = 256;  // block sizes of the step passes A and B (tuned at init)
   // a time step's charge row: queued by the solve right after its predicted
   // units, gated on convergence, so it runs while the host waits
   double *charge_dst = nullptr;
@@ -1117,18 +1118,18 @@ int one_step(lbe_ctx *c, bool record = true) {
   int rc = run(c, KK_FLUID, c->L.n, [&] {
     if (c->mixed)
       return launch_fluid_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[a], c->h32[a],
-                              c->h32[b], c->u32, c->nu32[b]);
+                              c->h32[b], c->u32, c->nu32[b], c->tb_a);
     return launch_fluid_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[a], c->f[a], c->f[b],
-                            c->u, c->n[b]);
+                            c->u, c->n[b], c->tb_a);
   });
   if (rc) return rc;
   // pass B also moves phi to the extrapolated start of this step's solve
   rc = run(c, KK_IONS, c->L.n, [&] {
     if (c->mixed)
       return launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a], c->nu32[b],
-                             c->src, order, c->phi, keep);
+                             c->src, order, c->phi, keep, c->tb_b);
     return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a], c->n[b], c->src,
-                           order, c->phi, keep);
+                           order, c->phi, keep, c->tb_b);
   });
   if (rc) return rc;
   if (c->phi_prev) c->extrap_hist = std::min(hist + 1, 2);
@@ -1521,6 +1522,66 @@ const char *lbe_kernel_name(int32_t kind) {
 namespace {
 
 // lbe_init and lbe_init_batch: system == nullptr means one system (nsys = 1).
+// Launch shape of the two step passes, picked by timing: each candidate
+// block size runs pass A, then pass B, on scratch outputs (the next step's
+// buffers; for pass B also a scratch source and a scratch copy of phi), best
+// of three launches after one to warm up.  Every site is computed on its own,
+// so the results are the same for any choice; only the time differs.
+int autotune_passes(lbe_ctx *c) {
+  static const int cand[3] = {128, 256, 512};
+  const int a = c->cur, b = 1 - c->cur;
+  const long N = c->L.n;
+  // scratch for pass B's source and kept potential: free between steps
+  double *src_s = c->mixed ? c->obs : c->f[b];
+  double *keep_s = src_s + N;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, LBE_EDEVICE, "event create failed");
+  }
+  int rc = LBE_OK;
+  for (int pass = 0; pass < 2 && rc == LBE_OK; ++pass) {
+    float best = 1e30f;
+    int pick = 256;
+    for (int tb : cand) {
+      float t_min = 1e30f;
+      for (int rep = 0; rep < 4 && rc == LBE_OK; ++rep) {
+        hipError_t e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess) {
+          if (pass == 0)
+            e = c->mixed ? launch_fluid_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[a],
+                                            c->h32[a], c->h32[b], c->u32, c->nu32[b], tb)
+                         : launch_fluid_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[a],
+                                            c->f[a], c->f[b], c->u, c->n[b], tb);
+          else
+            e = c->mixed ? launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a],
+                                           c->nu32[b], src_s, -1, c->phi, keep_s, tb)
+                         : launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a],
+                                           c->n[b], src_s, -1, c->phi, keep_s, tb);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+          rc = hip_fail(c, e, "pass timing");
+          break;
+        }
+        if (rep > 0) t_min = std::min(t_min, ms);
+      }
+      if (t_min < best) {
+        best = t_min;
+        pick = tb;
+      }
+    }
+    (pass == 0 ? c->tb_a : c->tb_b) = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
 int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s,
               const double *n_init, const double *n_ref, const double *f_init,
               const uint16_t *system, int nsys, lbe_ctx **out) {
@@ -1810,6 +1871,17 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
   }
   TRY(poisson_solve(c, false));
   TRY(record_charge(c));
+  {
+    // LBE_PASS_BLOCK=128|256|512 fixes the passes' block size; LBE_NO_AUTOTUNE
+    // keeps 256; otherwise the context times the candidates
+    const char *pb = getenv("LBE_PASS_BLOCK");
+    const int fixed = pb ? atoi(pb) : 0;
+    const char *na = getenv("LBE_NO_AUTOTUNE");
+    if (fixed == 128 || fixed == 256 || fixed == 512)
+      c->tb_a = c->tb_b = fixed;
+    else if (!(na && *na && *na != '0'))
+      TRY(autotune_passes(c));
+  }
   if (p.flags & LBE_EXTRAPOLATE) {
     TRY(dalloc(c, &c->phi_prev, 2 * N));
     c->extrap_hist = 0;  // the first step starts from phi(0) itself

@@ -321,5 +321,22 @@ __device__ __forceinline__ void extrapolate_at(int r, int n, int order, double *
 
 inline unsigned blocks_for(long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
+// The step passes come in three block sizes (the launch shape the context
+// picked by timing them, see lbe_capi.cpp): CALL(KK, TB) for species count K
+// and block size TBV (128, 256 or 512; anything else: 256).
+#define LBE_DISPATCH_TB(KK, TBV, CALL) \
+  switch (TBV) {                       \
+    case 128: CALL(KK, 128); break;    \
+    case 512: CALL(KK, 512); break;    \
+    default: CALL(KK, 256); break;     \
+  }
+#define LBE_DISPATCH_K_TB(K, TBV, CALL)           \
+  switch (K) {                                    \
+    case 1: LBE_DISPATCH_TB(1, TBV, CALL) break;  \
+    case 2: LBE_DISPATCH_TB(2, TBV, CALL) break;  \
+    case 3: LBE_DISPATCH_TB(3, TBV, CALL) break;  \
+    default: LBE_DISPATCH_TB(4, TBV, CALL) break; \
+  }
+
 }  // namespace
 }  // namespace lbe

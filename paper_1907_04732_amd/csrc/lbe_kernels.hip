@@ -60,8 +60,8 @@ __device__ __forceinline__ void link_force(const Lattice &L, const Phys &P, int 
 // diffusion-migration flux j_k = D_k/A0 (g_k - (n_k' - n_k)/Delta_i).  Writes
 // post-collision f, u, and n*_k = n_k - sum_i j_k (completed by pass B).
 
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_fluid_f64(Lattice L, Phys P,
+template <int K, int TB>
+__global__ __launch_bounds__(TB) void k_fluid_f64(Lattice L, Phys P,
                                                      const uint32_t *__restrict__ mask,
                                                      const double *__restrict__ phi,
                                                      const double *__restrict__ n,
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f64(Lattice L, Phys P,
                                                      double *__restrict__ fout,
                                                      double *__restrict__ u,
                                                      double *__restrict__ nstar) {
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int r = blockIdx.x * TB + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
   if (m & SOLID_BIT) return;
@@ -145,8 +145,8 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f64(Lattice L, Phys P,
 // Poisson source.  J_k = 3 w_i c_i . (n_k u + n_k' u') on every fluid link;
 // n_k(t+1) = n*_k - sum_i J_k, updated in place in nio. -------------------
 
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_ions_f64(Lattice L, Phys P,
+template <int K, int TB>
+__global__ __launch_bounds__(TB) void k_ions_f64(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
                                                     const double *__restrict__ u,
                                                     const double *__restrict__ n,
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f64(Lattice L, Phys P,
                                                     double *__restrict__ src, int order,
                                                     double *__restrict__ phi,
                                                     double *__restrict__ prev) {
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int r = blockIdx.x * TB + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
   if (m & SOLID_BIT) return;
@@ -450,20 +450,20 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int count, const int *__restr
 
 hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const double *n, const double *fin, double *fout,
-                            double *u, double *nstar) {
-#define CALL(KK) \
-  hipLaunchKernelGGL(k_fluid_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, n, fin, fout, u, nstar)
-  LBE_DISPATCH_K(P.K, CALL)
+                            double *u, double *nstar, int tb) {
+#define CALL(KK, TB) \
+  hipLaunchKernelGGL((k_fluid_f64<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, n, fin, fout, u, nstar)
+  LBE_DISPATCH_K_TB(P.K, tb, CALL)
 #undef CALL
   return hipGetLastError();
 }
 
 hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                            const double *u, const double *n, double *nio, double *src, int order,
-                           double *phi, double *prev) {
-#define CALL(KK) \
-  hipLaunchKernelGGL(k_ions_f64<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, u, n, nio, src, order, phi, prev)
-  LBE_DISPATCH_K(P.K, CALL)
+                           double *phi, double *prev, int tb) {
+#define CALL(KK, TB) \
+  hipLaunchKernelGGL((k_ions_f64<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, u, n, nio, src, order, phi, prev)
+  LBE_DISPATCH_K_TB(P.K, tb, CALL)
 #undef CALL
   return hipGetLastError();
 }

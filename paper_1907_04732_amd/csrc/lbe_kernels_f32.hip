@@ -57,8 +57,8 @@ __device__ __forceinline__ void pull_f32(const Lattice &L, int r, uint32_t m, co
 // Pass A: each fluid link's excess flux (Eq. 10) evaluated once, used for the
 // fluid force and for the diffusion-migration flux; collision; writes h, u and
 // nu*_k = nu_k - sum_i j_k (completed by k_ions_f32).
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_fluid_f32(Lattice L, Phys P,
+template <int K, int TB>
+__global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
                                                      const uint32_t *__restrict__ mask,
                                                      const double *__restrict__ phi,
                                                      const float *__restrict__ nu,
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f32(Lattice L, Phys P,
                                                      float *__restrict__ hout,
                                                      float *__restrict__ u,
                                                      float *__restrict__ nustar) {
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int r = blockIdx.x * TB + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
   if (m & SOLID_BIT) return;
@@ -151,8 +151,8 @@ __global__ __launch_bounds__(BLOCK) void k_fluid_f32(Lattice L, Phys P,
 // Pass B: advective link fluxes J_k = 3 w_i c_i . (n_k u + n_k' u') with the
 // step's velocity; nu_k(t+1) = nu*_k - sum_i J_k in place in nuio; Poisson
 // source (4 pi l_B / 6) rho_el accumulated in FP64.
-template <int K>
-__global__ __launch_bounds__(BLOCK) void k_ions_f32(Lattice L, Phys P,
+template <int K, int TB>
+__global__ __launch_bounds__(TB) void k_ions_f32(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
                                                     const float *__restrict__ u,
                                                     const float *__restrict__ nu,
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(BLOCK) void k_ions_f32(Lattice L, Phys P,
                                                     double *__restrict__ src, int order,
                                                     double *__restrict__ phi,
                                                     double *__restrict__ prev) {
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int r = blockIdx.x * TB + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
   if (m & SOLID_BIT) return;
@@ -336,10 +336,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand_n_f32(Lattice L, int K, const 
 
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
-                            float *u, float *nustar) {
-#define CALL(KK) \
-  hipLaunchKernelGGL(k_fluid_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, phi, nu, hin, hout, u, nustar)
-  LBE_DISPATCH_K(P.K, CALL)
+                            float *u, float *nustar, int tb) {
+#define CALL(KK, TB) \
+  hipLaunchKernelGGL((k_fluid_f32<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, nu, hin, hout, u, nustar)
+  LBE_DISPATCH_K_TB(P.K, tb, CALL)
 #undef CALL
   return hipGetLastError();
 }
@@ -362,10 +362,10 @@ hipError_t launch_expand_n_f32(hipStream_t s, const Lattice &L, const Phys &P,
 
 hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                            const float *u, const float *nu, float *nuio, double *src, int order,
-                           double *phi, double *prev) {
-#define CALL(KK) \
-  hipLaunchKernelGGL(k_ions_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, u, nu, nuio, src, order, phi, prev)
-  LBE_DISPATCH_K(P.K, CALL)
+                           double *phi, double *prev, int tb) {
+#define CALL(KK, TB) \
+  hipLaunchKernelGGL((k_ions_f32<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, u, nu, nuio, src, order, phi, prev)
+  LBE_DISPATCH_K_TB(P.K, tb, CALL)
 #undef CALL
   return hipGetLastError();
 }

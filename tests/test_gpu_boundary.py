@@ -175,3 +175,21 @@ def test_failed_step_goes_back_to_its_start_mixed_multigrid():
     nscale = np.abs(b["n"] - b["n"].mean(1, keepdims=True)).max()
     assert np.abs(a["n"] - b["n"]).max() <= 1e-6 * nscale
     assert g.qhist().shape == ref.qhist().shape
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+def test_pass_block_size_does_not_change_results(form, monkeypatch):
+    """The step passes compute every site on its own, so the block size the
+    context picks for them (timed at creation, or fixed by LBE_PASS_BLOCK)
+    changes no bit of the trajectory."""
+    kw, shape, t, ps, n0, nref, f0 = _inputs()
+    out = []
+    for tb in ("128", "256", "512"):
+        monkeypatch.setenv("LBE_PASS_BLOCK", tb)
+        g = lbe.Lbe(_params(kw, shape, form), t, ps, n0, nref, f0)
+        g.step(9)
+        out.append((g.fields(), g.qhist()))
+        g.close()
+    for fa, qa in out[1:]:
+        _same(out[0][0], fa)
+        assert np.array_equal(out[0][1], qa)
