@@ -56,6 +56,7 @@ struct lbe_ctx {
   int pred_iters = 0;         // iterations the last time-step solve needed
   bool use_graphs = true;     // replay one solver unit as a captured HIP graph
   bool tiles = true;          // the row-order (LDS-combined) restriction where it applies
+  bool coarse_start = true;   // restriction writes the coarse level's first Jacobi sweep
   int tb_a = 256, tb_b = 256;  // block sizes of the step passes A and B (tuned at init)
   // a time step's charge row: queued by the solve right after its predicted
   // units, gated on convergence, so it runs while the host waits
@@ -906,13 +907,17 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
   // with first_done the correction already holds its first Jacobi sweep
   if ((rc = smooth(first_done ? nu1 - 1 : nu1, nullptr))) return rc;
   lbe_ctx::MgDev &C = c->mg[l + 1];
+  // when the level below is smoothed by the global Jacobi kernels, its first
+  // sweep starts from zero and is pointwise: the restriction writes it
+  const bool start = c->coarse_start && c->mg_jacobi > 0.0 && c->mg_nu1c >= 1 &&
+                     (int)(l + 1) != c->mg_small_from && l + 2 < c->mg.size();
   rc = run(c, KK_MG_RESTRICT, L.lv.n, [&] {
     return launch_mg_restrict<T>(c->stream, C.tr, L.mask, C.mask, r, cur, (T *)C.r, (T *)C.e,
-                                 c->ctl, c->tiles);
+                                 c->ctl, c->tiles, start ? c->mg_jacobi : 0.0, C.lv.h2 / 6.0);
   });
   if (rc) return rc;
   T *ce = nullptr;
-  if ((rc = mg_vcycle<T>(c, l + 1, &ce))) return rc;
+  if ((rc = mg_vcycle<T>(c, l + 1, &ce, nullptr, nullptr, start))) return rc;
   rc = run(c, KK_MG_PROLONG, L.lv.n, [&] {
     return launch_mg_prolong<T>(c->stream, C.tr, L.mask, C.mask, (const T *)ce, cur, c->ctl);
   });
@@ -1676,6 +1681,9 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     c->use_graphs = !(ng && *ng && *ng != '0');
     const char *nt = getenv("LBE_NO_TILES");  // the eight-lane restriction only (same results)
     c->tiles = !(nt && *nt && *nt != '0');
+    // the coarse levels' first sweep as a separate launch (same results)
+    const char *ns = getenv("LBE_NO_COARSE_START");
+    c->coarse_start = !(ns && *ns && *ns != '0');
     c->mg_jacobi = p.mg_smoother == LBE_MG_JACOBI ? 1.0 : 0.0;
     const bool same = p.mg_nu1_coarse == 0 && p.mg_nu2_coarse == 0;
     c->mg_nu1c = same ? p.mg_nu1 : p.mg_nu1_coarse;

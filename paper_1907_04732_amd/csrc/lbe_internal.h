@@ -303,7 +303,10 @@ hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double 
 template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
-                              const SolveCtl *ctl, bool tiled);  // tiled: k_restrict_tiled where it applies
+                              const SolveCtl *ctl, bool tiled, double jac = 0.0, double hs = 0.0);
+// tiled: k_restrict_tiled where it applies; jac > 0: ec receives the coarse
+// level's first damped Jacobi sweep (relaxation jac, hs = h^2/6) from zero
+// instead of zero
 template <class T>
 hipError_t launch_mg_prolong(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                              const uint32_t *mc, const T *ec, T *ef, const SolveCtl *ctl);

@@ -392,22 +392,41 @@ __device__ __forceinline__ void group8_sum(T &v, int &cnt) {
   }
 }
 
+// The coarse correction starts at zero, so the first damped Jacobi sweep on
+// the coarse level is pointwise: at a fluid cell the neighbour sum vanishes
+// and x = omega hs rhs / sum_i w_i s_i.  With jac > 0 the restriction writes
+// that sweep (the value k_jacobi computes from x_in = 0) instead of zero.
+template <class T>
+__device__ __forceinline__ T coarse_start(const MgLevel &lv, uint32_t m, T rr, T jac, T hs) {
+  if (jac == T(0) || (m & SOLID_BIT)) return T(0);
+  T den = T(0);
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if ((lv.selfm >> (i - 1)) & 1u) continue;
+    den += solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
+  }
+  return jac * ((hs * rr) / den);
+}
+
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_restrict(MgTransfer tr, const uint32_t *__restrict__ mf,
                                                     const uint32_t *__restrict__ mc,
                                                     const T *__restrict__ rf,
                                                     const T *__restrict__ ef, T *__restrict__ rc,
                                                     T *__restrict__ ec,
-                                                    const SolveCtl *__restrict__ ctl) {
+                                                    const SolveCtl *__restrict__ ctl, T jac,
+                                                    T hs) {
   if (ctl->done) return;
   const int t = blockIdx.x * BLOCK + threadIdx.x;
   const int R = t >> 3, j = t & 7;
   T v = T(0);
   int cnt = 0;
   bool fluid = false;
+  uint32_t m = SOLID_BIT;
   if (R < tr.c.n) {
     restrict_child<T>(tr, R, j, mf, rf, ef, v, cnt);
-    fluid = !(mc[R] & SOLID_BIT);
+    m = mc[R];
+    fluid = !(m & SOLID_BIT);
     if (!fluid) {
       v = T(0);
       cnt = 0;
@@ -415,8 +434,9 @@ __global__ __launch_bounds__(BLOCK) void k_restrict(MgTransfer tr, const uint32_
   }
   group8_sum(v, cnt);
   if (j == 0 && R < tr.c.n) {
-    ec[R] = T(0);
-    rc[R] = (fluid && cnt) ? v / T(cnt) : T(0);
+    const T rv = (fluid && cnt) ? v / T(cnt) : T(0);
+    rc[R] = rv;
+    ec[R] = coarse_start<T>(tr.c, m, rv, jac, hs);
   }
 }
 
@@ -435,7 +455,8 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_tiled(MgTransfer tr,
                                                           const T *__restrict__ rf,
                                                           const T *__restrict__ ef,
                                                           T *__restrict__ rc, T *__restrict__ ec,
-                                                          const SolveCtl *__restrict__ ctl) {
+                                                          const SolveCtl *__restrict__ ctl, T jac,
+                                                          T hs) {
   static_assert(2 * RT_X * 2 * RT_Y * 2 == BLOCK, "one fine cell per thread");
   __shared__ T sv[BLOCK];
   __shared__ int sc[BLOCK];
@@ -471,9 +492,11 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_tiled(MgTransfer tr,
   const T sum = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
   const int cn = ((n[0] + n[1]) + (n[2] + n[3])) + ((n[4] + n[5]) + (n[6] + n[7]));
   const int R = Xo + tr.c.nx * (Yo + tr.c.ny * blockIdx.z);
-  const bool fluid = !(mc[R] & SOLID_BIT);
-  ec[R] = T(0);
-  rc[R] = (fluid && cn) ? sum / T(cn) : T(0);
+  const uint32_t m = mc[R];
+  const bool fluid = !(m & SOLID_BIT);
+  const T rv = (fluid && cn) ? sum / T(cn) : T(0);
+  rc[R] = rv;
+  ec[R] = coarse_start<T>(tr.c, m, rv, jac, hs);
 }
 
 // ---- prolongation: e_f += trilinear interpolation of e_c --------------------
@@ -907,16 +930,16 @@ hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double 
 template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
-                              const SolveCtl *ctl, bool tiled) {
+                              const SolveCtl *ctl, bool tiled, double jac, double hs) {
   // the tiled form where a level is wide enough to fill its tiles (and its
   // planes fit the grid's z extent)
   if (tiled && tr.c.nx >= RT_X && tr.c.ny >= RT_Y && tr.c.nz <= 65535) {
     const dim3 grid((tr.c.nx + RT_X - 1) / RT_X, (tr.c.ny + RT_Y - 1) / RT_Y, tr.c.nz);
     hipLaunchKernelGGL(k_restrict_tiled<T>, grid, dim3(BLOCK), 0, s, tr, mf, mc, rf, ef, rc, ec,
-                       ctl);
+                       ctl, T(jac), T(hs));
   } else {
     hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(8L * tr.c.n)), dim3(BLOCK), 0, s, tr, mf,
-                       mc, rf, ef, rc, ec, ctl);
+                       mc, rf, ef, rc, ec, ctl, T(jac), T(hs));
   }
   return hipGetLastError();
 }
@@ -986,7 +1009,7 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                          const SolveCtl *, double *);                           \
   template hipError_t launch_mg_restrict<T>(hipStream_t, const MgTransfer &, const uint32_t *,  \
                                             const uint32_t *, const T *, const T *, T *, T *,   \
-                                            const SolveCtl *, bool);                            \
+                                            const SolveCtl *, bool, double, double);            \
   template hipError_t launch_mg_prolong<T>(hipStream_t, const MgTransfer &, const uint32_t *,   \
                                            const uint32_t *, const T *, T *, const SolveCtl *); \
   template hipError_t launch_mg_coarse<T>(hipStream_t, const MgLevel &, double, double, int,    \

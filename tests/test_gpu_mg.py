@@ -222,3 +222,39 @@ def test_tiled_kernels_match_untiled(geometry, precision, monkeypatch):
     for k in fa:
         assert np.array_equal(fa[k], fb[k]), k
     assert np.array_equal(qa, qb) and ia == ib
+
+
+@pytest.mark.parametrize("geometry", ["slab", "random"])
+@pytest.mark.parametrize("precision", [lbe.FP32_MIXED, lbe.FP64])
+@pytest.mark.parametrize("cycle", ["V(2,2)", "V(1,1)"])
+def test_coarse_first_sweep_in_restriction_same_results(geometry, precision, cycle, monkeypatch):
+    """The coarse correction starts from zero, so the first Jacobi sweep on a
+    coarse level is pointwise and the restriction writes it; a run with that
+    (the default) and one with the sweep as its own launch
+    (LBE_NO_COARSE_START=1) must agree bit for bit.  On 64 x 64 x 34 the two
+    levels below the finest (32 x 32 x 17, 16 x 16 x 9) are smoothed by the
+    global kernels and the rest by the one-work-group kernel."""
+    shape = (64, 64, 34)
+    if geometry == "slab":
+        _, t, ps = W.slab(64, 64, 32, 1, 0.05, -0.05)
+        flags = lbe.EXTRAPOLATE
+    else:
+        t, ps = G.random_geometry(shape, 3, seed=29, fill=0.12)
+        flags = lbe.EXTRAPOLATE | lbe.ALLOW_FLOATING | lbe.KRYLOV
+    rs = W.salt_for_debye(4.0, G.LB)
+    n0 = W.noisy_concentrations(t, [rs, rs], 1e-2, seed=9)
+    nu = 1 if cycle == "V(1,1)" else 2
+    p = dict(z=(1, -1), D=(0.05, 0.08), lB=G.LB, tau=0.9, Eapp=(1e-3, 0.0, 5e-4), tol=1e-11,
+             max_iter=1000, precision=precision, poisson=lbe.MG, flags=flags, mg_nu1=nu,
+             mg_nu2=nu, mg_nu1_coarse=nu, mg_nu2_coarse=nu)
+    out = []
+    for off in ("0", "1"):
+        monkeypatch.setenv("LBE_NO_COARSE_START", off)
+        g = lbe.Lbe(lbe.make_params(shape, **p), t, ps, n0, (rs, rs))
+        g.step(10)
+        out.append((g.fields(), g.qhist(), g.totals()["poisson_total"]))
+        g.close()
+    (fa, qa, ia), (fb, qb, ib) = out
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    assert np.array_equal(qa, qb) and ia == ib
