@@ -35,7 +35,7 @@ import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
-def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False, charge: bool = False):
+def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False):
     """Algorithmic HBM bytes per cell of the grid level a launch works on
     (lattice sites for the finest level), or None where no byte model applies
     (the one-work-group coarse-level kernel, the electrode-charge gather).
@@ -55,9 +55,7 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False, charge: b
       zeroed correction out.  Prolongation, per fine cell: correction in and
       out, flag word; per coarse cell: correction and flag word.  Outer
       residual: phi, source, flag word in; correction rhs and zeroed
-      correction out (multigrid); with charge (plain multigrid cycles, whose
-      checks also sum the electrode charge) the electrode byte of each site
-      in.  correct: phi in + out, correction, flag
+      correction out (multigrid).  correct: phi in + out, correction, flag
       word.
       Reverse mode: adj_moments reads the 19 stored populations and writes
       rho and m; adj_fluid reads phi, the K concentrations, rho and m, the 19
@@ -82,7 +80,7 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False, charge: b
         "mg_restrict": 2 * cor + 4 + (4 + 2 * cor) / 8,
         "mg_prolong": 2 * cor + 4 + (cor + 4) / 8,
         "resid": 8 + 8 + 4,
-        "mg_resid": 8 + 8 + 4 + 2 * cor + (1 if charge else 0),
+        "mg_resid": 8 + 8 + 4 + 2 * cor,
         "correct": 16 + cor + 4,
         "fcg_beta": cor + 8 + 4,
         "fcg_dir": cor + 16 + 4,
@@ -170,9 +168,6 @@ def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, che
                         check_every=check_every, precision=precision, poisson=poisson,
                         flags=flags, mg_nu1=1 if light else 2, mg_nu2=1 if light else 2,
                         mg_nu1_coarse=1 if light else 0, mg_nu2_coarse=1 if light else 0)
-    # plain multigrid cycles: the residual checks also sum the electrode charge
-    fused_charge = (poisson == lbe.MG and not (flags & lbe.KRYLOV)
-                    and os.environ.get("LBE_NO_FUSED_CHARGE", "0") in ("", "0"))
     t_init = time.perf_counter()
     if isinstance(w, W.Batch):
         g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref.reshape(-1), system=w.system,
@@ -209,8 +204,7 @@ def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, che
         if not cnt:
             continue
         avg = ms / 1e3 / cnt
-        b = bytes_per_cell(k, form, len(w.z), extrap=bool(flags & lbe.EXTRAPOLATE),
-                           charge=fused_charge)
+        b = bytes_per_cell(k, form, len(w.z), extrap=bool(flags & lbe.EXTRAPOLATE))
         row = {"total_ms": round(ms, 4), "launches": cnt, "avg_us": round(avg * 1e6, 3),
                "cells_per_launch": int(round(cells / cnt))}
         if b is not None:
