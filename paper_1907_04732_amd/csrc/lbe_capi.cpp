@@ -62,12 +62,6 @@ struct lbe_ctx {
   // units, gated on convergence, so it runs while the host waits
   double *charge_dst = nullptr;
   bool charge_queued = false;
-  // plain multigrid: the residual checks carry the electrode charge (elec:
-  // per site the electrode of an interface node or -1; qpart: ne x blocks)
-  bool fuse_charge = false;
-  bool qfused = false;  // the running solve's checks write the charge row
-  int8_t *elec = nullptr;
-  double *qpart = nullptr;
   hipGraphExec_t unit_exec = nullptr;
 
   // electrode charge tables
@@ -386,11 +380,7 @@ int read_scalars(lbe_ctx *c, int count) {
 int reset_ctl(lbe_ctx *c) {
   // a new sequence number: whatever an earlier solve published is ignored
   // (its last stamp may still be on its way when this one starts)
-  *c->ctl_h = SolveCtl{0.0, c->p.tol, 0, 0, 0, 0, 0, ++c->seq, 0ull, c->ctl_pub_d, nullptr};
-  // a plain multigrid solve of a recorded step: the check that ends it
-  // writes the step's charge row
-  c->qfused = c->fuse_charge && !c->kc && c->charge_dst && c->p.poisson == LBE_MG;
-  if (c->qfused) c->ctl_h->qdst = c->charge_dst;
+  *c->ctl_h = SolveCtl{0.0, c->p.tol, 0, 0, 0, 0, 0, ++c->seq, 0ull, c->ctl_pub_d};
   c->checks_queued = 0;
   HIPCHK(c, hipMemcpyAsync(c->ctl, c->ctl_h, sizeof(SolveCtl), hipMemcpyHostToDevice, c->stream));
   return LBE_OK;
@@ -501,9 +491,7 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
     }
     // the step's charge behind the queued units: it runs while the host
     // waits, and does nothing unless they reached the tolerance
-    if (c->qfused) {
-      c->charge_queued = true;  // the check that ends the solve writes it
-    } else if (c->charge_dst && !c->prof) {
+    if (c->charge_dst && !c->prof) {
       if ((rc = charges_to(c, c->charge_dst, c->ctl))) return rc;
       c->charge_queued = true;
     }
@@ -1015,8 +1003,7 @@ int mg_solve(lbe_ctx *c, bool learn) {
         return run(c, KK_MG_RESID, L0.lv.n, [&] {
           return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi, (T *)L0.r,
                                           (T *)L0.e, c->partial, c->ctl, add, nullptr, nullptr,
-                                          first_sweep, c->fuse_charge ? c->elec : nullptr, c->ne,
-                                          -6.0 / (4.0 * M_PI * c->p.lB), c->qpart);
+                                          first_sweep);
         });
       });
 }
@@ -1473,7 +1460,7 @@ void free_ctx(lbe_ctx *c) {
                   c->nref_d_tab, c->qref_tab, c->nref_f_tab, c->kr, c->kp, c->kq, c->kc,
                   c->tape.ck, c->tape.seg, c->abar[0], c->abar[1], c->nbar[0], c->nbar[1],
                   c->fbar, c->adj_u, c->lam, c->lam_sum, c->gphis, c->src_keep, c->qbar_d,
-                  c->lb_acc, c->type_d, c->elec, c->qpart};
+                  c->lb_acc, c->type_d};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   for (auto &L : c->mg) {
@@ -1816,20 +1803,8 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
       goto fail_;
     }
     c->nblk_charge = (int)g.blk_elec.size();
-    {
-      // plain multigrid: the residual checks carry the electrode charge
-      // (LBE_NO_FUSED_CHARGE=1: separate charge kernels after the solve)
-      const char *nf = getenv("LBE_NO_FUSED_CHARGE");
-      c->fuse_charge = p.poisson == LBE_MG && !(p.flags & LBE_KRYLOV) && ne > 0 && ne <= 127 &&
-                       c->nblk_charge > 0 && !(nf && *nf && *nf != '0');
-    }
-    if (c->fuse_charge) {
-      TRY(dalloc(c, &c->elec, N));
-      TRY(dalloc(c, &c->qpart, (size_t)ne * residual_blocks(c->L)));
-    }
 
     std::vector<double> phi0(N, 0.0), src0(N, 0.0);
-    std::vector<int8_t> el;  // electrode of each interface node (fused charge)
     std::vector<float> nu0, h0;
     if (c->mixed) {
       nu0.assign((size_t)K * N, 0.f);
@@ -1878,12 +1853,6 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     TRY(up(c->blk_elec, g.blk_elec.data(), sizeof(int) * g.blk_elec.size()));
     TRY(up(c->blk_begin, g.blk_begin.data(), sizeof(int) * g.blk_begin.size()));
     TRY(up(c->blk_end, g.blk_end.data(), sizeof(int) * g.blk_end.size()));
-    if (c->fuse_charge) {
-      el.assign(N, -1);
-      for (size_t b = 0; b < g.blk_elec.size(); ++b)
-        for (int i = g.blk_begin[b]; i < g.blk_end[b]; ++i) el[g.iface[i]] = (int8_t)g.blk_elec[b];
-      TRY(up(c->elec, el.data(), N));
-    }
     if ((c->u && hipMemsetAsync(c->u, 0, sizeof(double) * 3 * N, c->stream) != hipSuccess) ||
         (c->u32 && hipMemsetAsync(c->u32, 0, sizeof(float) * 3 * N, c->stream) != hipSuccess)) {
       rc = fail(c, LBE_EDEVICE, "memset failed");

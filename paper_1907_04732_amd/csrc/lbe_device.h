@@ -153,51 +153,11 @@ __global__ __launch_bounds__(FINAL) void k_final_max(const double *__restrict__ 
   if (threadIdx.x == 0) out[0] = v;
 }
 
-// rounding error of t = a + b (Neumaier)
-__device__ __forceinline__ double two_sum_err(double a, double b, double t) {
-  return fabs(a) >= fabs(b) ? (a - t) + b : (b - t) + a;
-}
-
-// Compensated sum of p[k*stride] for k < n with blockDim.x = NT threads: each
-// thread keeps a Neumaier sum over a strided subset, and the block combines
-// the (sum, compensation) pairs in a fixed tree carrying the exact rounding
-// error of every addition; valid in thread 0.
-template <int NT>
-__device__ double compensated_sum(const double *__restrict__ p, int n, int stride, double *ts,
-                                  double *tc) {
-  double s = 0.0, c = 0.0;
-  for (int k = threadIdx.x; k < n; k += NT) {
-    const double x = p[(size_t)k * stride];
-    const double t = s + x;
-    c += two_sum_err(s, x, t);
-    s = t;
-  }
-  __syncthreads();
-  ts[threadIdx.x] = s;
-  tc[threadIdx.x] = c;
-  __syncthreads();
-  for (int h = NT / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) {
-      const double a = ts[threadIdx.x], b = ts[threadIdx.x + h], t = a + b;
-      tc[threadIdx.x] += tc[threadIdx.x + h] + two_sum_err(a, b, t);
-      ts[threadIdx.x] = t;
-    }
-    __syncthreads();
-  }
-  return ts[0] + tc[0];
-}
-
 // Residual check of a Poisson solve: max over the block maxima into
 // ctl->resid; marks the solve done when the residual is <= tol or not finite.
-// With qpart (ne electrodes x nb blocks of charge partials from the check's
-// first stage) the check that ends the solve with a finite residual also
-// writes each electrode's charge, their compensated sum, to ctl->qdst.
 __global__ __launch_bounds__(FINAL) void k_final_resid(const double *__restrict__ partial, int nb,
-                                                       SolveCtl *__restrict__ ctl, int add,
-                                                       const double *__restrict__ qpart, int ne) {
+                                                       SolveCtl *__restrict__ ctl, int add) {
   __shared__ double tree[FINAL];
-  __shared__ double tcomp[FINAL];
-  __shared__ int charge;
   if (ctl->done) return;
   const double res = final_max(partial, nb, tree);
   if (threadIdx.x == 0) {
@@ -211,25 +171,13 @@ __global__ __launch_bounds__(FINAL) void k_final_resid(const double *__restrict_
       ctl->iters = count;
       ctl->nonfinite = bad;
     }
-    charge = qpart && ctl->qdst && ctl->done && !ctl->nonfinite;
-  }
-  if (qpart) {
-    __syncthreads();
-    if (charge) {
-      for (int k = 0; k < ne; ++k) {
-        const double q = compensated_sum<FINAL>(qpart + (size_t)k * nb, nb, 1, tree, tcomp);
-        if (threadIdx.x == 0) ctl->qdst[k] = q;
-      }
-    }
-  }
-  if (threadIdx.x == 0) {
     // publish to the host: the values first, then (after a system-scope
     // fence) the stamp the host polls on, in one 8-byte store, which the end
     // of the kernel makes visible at the latest
     if (ctl->mirror) {
       volatile SolveCtl *hm = ctl->mirror;
       hm->resid = res;
-      hm->count = ctl->count;
+      hm->count = count;
       hm->iters = ctl->iters;
       hm->nonfinite = ctl->nonfinite;
       __threadfence_system();

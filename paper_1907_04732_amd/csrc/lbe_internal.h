@@ -101,9 +101,6 @@ struct SolveCtl {
   // check count of one solve (or check) with another
   unsigned long long stamp;
   SolveCtl *mirror;  // host-mapped copy (device address), or null
-  // where the residual check that ends the solve writes the electrode
-  // charges (one per electrode), when the check carries them; or null
-  double *qdst;
 };
 
 // Flexible conjugate gradients preconditioned by one V-cycle (device state).
@@ -274,12 +271,7 @@ template <class T>
 hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
                                  const double *src, const double *phi, T *r0, T *e0,
                                  double *partial, SolveCtl *ctl, int add, double *r64,
-                                 KrylovCtl *kc, double jacobi, const int8_t *elec = nullptr,
-                                 int ne = 0, double q_scale = 0.0, double *qpart = nullptr);
-// With elec (per site: the electrode index of an electrode's interface node,
-// else -1) the check also sums each electrode's charge (Eq. 16, scaled by
-// q_scale) per block into qpart (ne x blocks), and the check that ends the
-// solve writes the charges to ctl->qdst when that is set.
+                                 KrylovCtl *kc, double jacobi);
 // Flexible CG on A e = R (A = -L_h, level 0), preconditioner z = V-cycle(r):
 //   beta = -(z, q_prev) / (p_prev, q_prev) (0 for the first direction),
 //   p = z + beta p,  q = A p,  alpha = (r, p) / (p, q),

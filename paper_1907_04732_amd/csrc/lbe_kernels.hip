@@ -301,7 +301,10 @@ __global__ __launch_bounds__(BLOCK) void k_charge(Lattice L, double q_scale,
 // Per electrode (one block each), compensated sum of its blocks' partials:
 // each thread keeps a Neumaier sum over a strided subset, and the block
 // combines the (sum, compensation) pairs in a fixed tree with the exact
-// rounding error of every addition carried along (two_sum_err).
+// rounding error of every addition carried along.
+__device__ __forceinline__ double two_sum_err(double a, double b, double t) {
+  return fabs(a) >= fabs(b) ? (a - t) + b : (b - t) + a;
+}
 
 __global__ __launch_bounds__(BLOCK) void k_final_charge(const double *__restrict__ partial,
                                                         const int *__restrict__ blk_elec, int nb,
@@ -499,8 +502,7 @@ hipError_t launch_resid_f64(hipStream_t s, const Lattice &L, const uint32_t *mas
                             int add) {
   const int nb = (int)blocks_for(L.n);
   hipLaunchKernelGGL(k_resid_f64, dim3(nb), dim3(BLOCK), 0, s, L, mask, src, phi, partial, ctl);
-  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add, nullptr,
-                     0);
+  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
 

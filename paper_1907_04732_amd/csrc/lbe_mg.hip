@@ -110,33 +110,18 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
                                                        double *__restrict__ partial,
                                                        const SolveCtl *__restrict__ ctl,
                                                        double *__restrict__ r64,
-                                                       KrylovCtl *__restrict__ kc, T jacobi,
-                                                       const int8_t *__restrict__ elec, int ne,
-                                                       double q_scale, double *__restrict__ qpart) {
+                                                       KrylovCtl *__restrict__ kc, T jacobi) {
   __shared__ double sm[BLOCK / WAVE];
   if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (kc && r == 0) kc->first = 1;  // a new Krylov sequence starts from this residual
-  double a = 0.0, qv = 0.0;
-  int ek = -1;
+  double a = 0.0;
   if (r < lv.n) {
     const Coords c = coords_of(r, lv);
     double pn[NQ];
     gather_lv(lv, c, r, phi, pn);
     const double sr = src[r];
     const uint32_t m = mask[r];
-    if (elec) ek = elec[r];
-    // an electrode's interface node: its part of the electrode charge
-    // (Eq. 16), the flux over its fluid links, as k_charge computes it
-    if (ek >= 0) {
-      double lap = 0.0;
-#pragma unroll
-      for (int i = 1; i < NQ; ++i) {
-        if (solid_link(m, i)) continue;
-        lap += WQ[i] * lv.wall * (pn[i] - pn[0]);
-      }
-      qv = q_scale * lap;
-    }
     double acc = 0.0;
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
@@ -169,18 +154,6 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
   }
   a = block_max(a, sm);
   if (threadIdx.x == 0) partial[blockIdx.x] = a;
-  if (elec) {
-    // per electrode the block's sum of its interface nodes' parts (zero for
-    // the blocks without one, which skip the sums)
-    if (__syncthreads_or(ek >= 0)) {
-      for (int k = 0; k < ne; ++k) {
-        const double q = block_sum(ek == k ? qv : 0.0, sm);
-        if (threadIdx.x == 0) qpart[(size_t)k * gridDim.x + blockIdx.x] = q;
-      }
-    } else if (threadIdx.x < ne) {
-      qpart[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = 0.0;
-    }
-  }
 }
 
 // ---- flexible conjugate gradients around the V-cycle -------------------------
@@ -892,14 +865,11 @@ template <class T>
 hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
                                  const double *src, const double *phi, T *r0, T *e0,
                                  double *partial, SolveCtl *ctl, int add, double *r64,
-                                 KrylovCtl *kc, double jacobi, const int8_t *elec, int ne,
-                                 double q_scale, double *qpart) {
+                                 KrylovCtl *kc, double jacobi) {
   const int nb = (int)blocks_for(lv.n);
-  if (!elec) ne = 0;
   hipLaunchKernelGGL(k_outer_resid<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, src, phi, r0, e0,
-                     partial, ctl, r64, kc, T(jacobi), elec, ne, q_scale, qpart);
-  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add,
-                     elec ? (const double *)qpart : nullptr, ne);
+                     partial, ctl, r64, kc, T(jacobi));
+  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
 
@@ -935,8 +905,7 @@ hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const d
   const int nb = (int)blocks_for(n);
   hipLaunchKernelGGL(k_fcg_update<T>, dim3(nb), dim3(BLOCK), 0, s, n, mask, p, q, phi, r, r0, e0,
                      partial, kc, ctl);
-  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add, nullptr,
-                     0);
+  hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
 
@@ -1024,8 +993,7 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
   template hipError_t launch_mg_outer_resid<T>(hipStream_t, const MgLevel &, const uint32_t *,  \
                                                const double *, const double *, T *, T *,       \
                                                double *, SolveCtl *, int, double *,            \
-                                               KrylovCtl *, double, const int8_t *, int,       \
-                                               double, double *);                              \
+                                               KrylovCtl *, double);                           \
   template hipError_t launch_fcg_beta<T>(hipStream_t, int, const uint32_t *, const T *,         \
                                          const double *, double *, KrylovCtl *,                 \
                                          const SolveCtl *);                                     \

@@ -258,34 +258,3 @@ def test_coarse_first_sweep_in_restriction_same_results(geometry, precision, cyc
     for k in fa:
         assert np.array_equal(fa[k], fb[k]), k
     assert np.array_equal(qa, qb) and ia == ib
-
-
-@pytest.mark.parametrize("geometry", ["slab", "coax"])
-@pytest.mark.parametrize("precision", [lbe.FP32_MIXED, lbe.FP64])
-def test_charge_from_the_residual_check(geometry, precision, monkeypatch):
-    """With plain multigrid the residual check that ends a step's solve also
-    sums the electrode charge (Eq. 16) over the interface nodes it visits;
-    against the separate charge kernels (LBE_NO_FUSED_CHARGE=1) the fields
-    are the same bits and every recorded charge agrees to summation order
-    (the same per-node terms, summed per block and then compensated)."""
-    if geometry == "slab":
-        shape, t, ps = W.slab(48, 40, 32, 1, 0.05, -0.05)
-    else:
-        kw, shape, t, ps, _, _, _, _ = G.case("coax_16x16x4")
-    rs = W.salt_for_debye(4.0, G.LB)
-    n0 = W.noisy_concentrations(t, [rs, rs], 1e-2, seed=5)
-    p = dict(z=(1, -1), D=(0.05, 0.08), lB=G.LB, tau=0.9, Eapp=(1e-3, 0.0, 5e-4), tol=1e-11,
-             max_iter=1000, precision=precision, poisson=lbe.MG, flags=lbe.EXTRAPOLATE)
-    out = []
-    for off in ("0", "1"):
-        monkeypatch.setenv("LBE_NO_FUSED_CHARGE", off)
-        g = lbe.Lbe(lbe.make_params(shape, **p), t, ps, n0, (rs, rs))
-        g.step(15)
-        out.append((g.fields(), g.qhist(), g.totals()["poisson_total"]))
-        g.close()
-    (fa, qa, ia), (fb, qb, ib) = out
-    for k in fa:
-        assert np.array_equal(fa[k], fb[k]), k
-    assert ia == ib and qa.shape == qb.shape and qa.shape[0] >= 15
-    assert np.all(np.isfinite(qa)) and np.abs(qa).max() > 0
-    assert np.abs(qa - qb).max() <= 1e-13 * np.abs(qb).max()
