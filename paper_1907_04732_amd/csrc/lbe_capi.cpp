@@ -935,6 +935,13 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
 template <class T>
 int mg_solve(lbe_ctx *c, bool learn) {
   lbe_ctx::MgDev &L0 = c->mg[0];
+  // the kernel that writes the finest level's right-hand side (the residual
+  // check, or the Krylov update) takes the V-cycle's first Jacobi sweep
+  // (from 0) when that level is smoothed by the global kernels
+  const double first_sweep = (c->mg_jacobi > 0.0 && c->p.mg_nu1 >= 1 && c->mg.size() > 1 &&
+                              c->mg_small_from != 0 && c->coarse_start)
+                                 ? c->mg_jacobi
+                                 : 0.0;
   if (c->kc) {
     const int n = L0.lv.n;
     return run_solve(
@@ -942,7 +949,7 @@ int mg_solve(lbe_ctx *c, bool learn) {
         [&](int m) -> int {
           for (int k = 0; k < m; ++k) {
             T *z = nullptr;
-            int rc = mg_vcycle<T>(c, 0, &z);
+            int rc = mg_vcycle<T>(c, 0, &z, nullptr, nullptr, first_sweep > 0.0);
             if (rc) return rc;
             rc = run(c, KK_FCG_BETA, n, [&] {
               return launch_fcg_beta<T>(c->stream, n, c->mask, (const T *)z, c->kq, c->partial,
@@ -961,7 +968,8 @@ int mg_solve(lbe_ctx *c, bool learn) {
             // every iteration ends with its own stop check (one cycle each)
             rc = run(c, KK_FCG_UPDATE, n, [&] {
               return launch_fcg_update<T>(c->stream, n, c->mask, c->kp, c->kq, c->phi, c->kr,
-                                          (T *)L0.r, (T *)L0.e, c->partial, c->kc, c->ctl, 1);
+                                          (T *)L0.r, (T *)L0.e, c->partial, c->kc, c->ctl, 1,
+                                          L0.lv, first_sweep);
             });
             if (rc) return rc;
           }
@@ -972,16 +980,10 @@ int mg_solve(lbe_ctx *c, bool learn) {
           return run(c, KK_MG_RESID, n, [&] {
             return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi,
                                             (T *)L0.r, (T *)L0.e, c->partial, c->ctl, 0, c->kr,
-                                            c->kc, 0.0);
+                                            c->kc, first_sweep);
           });
         });
   }
-  // the residual check takes the V-cycle's first Jacobi sweep (from 0) on
-  // the finest level when that level is smoothed by the global kernels
-  const double first_sweep = (c->mg_jacobi > 0.0 && c->p.mg_nu1 >= 1 && c->mg.size() > 1 &&
-                              c->mg_small_from != 0)
-                                 ? c->mg_jacobi
-                                 : 0.0;
   return run_solve(
       c, 1, learn, "cycles",
       [&](int m) -> int {

@@ -289,7 +289,8 @@ hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *ma
 template <class T>
 hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const double *p,
                              const double *q, double *phi, double *r, T *r0, T *e0,
-                             double *partial, const KrylovCtl *kc, SolveCtl *ctl, int add);
+                             double *partial, const KrylovCtl *kc, SolveCtl *ctl, int add,
+                             const MgLevel &lv, double jac);  // jac > 0: e0 gets lv's first Jacobi sweep
 template <class T>
 hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int colour,
                             const uint32_t *mask, const T *rhs, T *e, const SolveCtl *ctl);

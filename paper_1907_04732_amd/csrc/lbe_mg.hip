@@ -100,6 +100,23 @@ __device__ __forceinline__ T apply_A(const MgLevel &lv, int r, uint32_t m, const
 // word and pick the result by the flag afterwards, so the two memory round
 // trips overlap instead of following each other.
 
+// A correction that starts at zero makes the first damped Jacobi sweep
+// pointwise: at a fluid cell the neighbour sum vanishes and
+// x = omega hs rhs / sum_i w_i s_i.  With jac > 0 the kernels that write a
+// level's right-hand side (the restriction, the Krylov update) write that
+// sweep (the value k_jacobi computes from x_in = 0) instead of zero.
+template <class T>
+__device__ __forceinline__ T coarse_start(const MgLevel &lv, uint32_t m, T rr, T jac, T hs) {
+  if (jac == T(0) || (m & SOLID_BIT)) return T(0);
+  T den = T(0);
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if ((lv.selfm >> (i - 1)) & 1u) continue;
+    den += solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
+  }
+  return jac * ((hs * rr) / den);
+}
+
 // ---- outer residual (FP64) ----------------------------------------------------
 
 template <class T>
@@ -252,22 +269,25 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_update(int n, const uint32_t *__r
                                                       T *__restrict__ r0, T *__restrict__ e0,
                                                       double *__restrict__ partial,
                                                       const KrylovCtl *__restrict__ kc,
-                                                      const SolveCtl *__restrict__ ctl) {
+                                                      const SolveCtl *__restrict__ ctl,
+                                                      MgLevel lv, T jac, T hs) {
   __shared__ double sm[BLOCK / WAVE];
   if (ctl->done) return;
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   double a = 0.0;
   if (r < n) {
     double R = 0.0;
-    if (!(mask[r] & SOLID_BIT)) {
+    const uint32_t m = mask[r];
+    if (!(m & SOLID_BIT)) {
       const double alpha = kc->alpha;
       phi[r] += alpha * p[r];
       R = rv[r] - alpha * q[r];
       rv[r] = R;
       a = fabs(R);
     }
-    r0[r] = T(R);
-    e0[r] = T(0);
+    const T rr = T(R);
+    r0[r] = rr;
+    e0[r] = coarse_start<T>(lv, m, rr, jac, hs);
   }
   a = block_max(a, sm);
   if (threadIdx.x == 0) partial[blockIdx.x] = a;
@@ -390,22 +410,6 @@ __device__ __forceinline__ void group8_sum(T &v, int &cnt) {
     v += __shfl_xor(v, off);
     cnt += __shfl_xor(cnt, off);
   }
-}
-
-// The coarse correction starts at zero, so the first damped Jacobi sweep on
-// the coarse level is pointwise: at a fluid cell the neighbour sum vanishes
-// and x = omega hs rhs / sum_i w_i s_i.  With jac > 0 the restriction writes
-// that sweep (the value k_jacobi computes from x_in = 0) instead of zero.
-template <class T>
-__device__ __forceinline__ T coarse_start(const MgLevel &lv, uint32_t m, T rr, T jac, T hs) {
-  if (jac == T(0) || (m & SOLID_BIT)) return T(0);
-  T den = T(0);
-#pragma unroll
-  for (int i = 1; i < NQ; ++i) {
-    if ((lv.selfm >> (i - 1)) & 1u) continue;
-    den += solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
-  }
-  return jac * ((hs * rr) / den);
 }
 
 template <class T>
@@ -901,10 +905,11 @@ hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *ma
 template <class T>
 hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const double *p,
                              const double *q, double *phi, double *r, T *r0, T *e0,
-                             double *partial, const KrylovCtl *kc, SolveCtl *ctl, int add) {
+                             double *partial, const KrylovCtl *kc, SolveCtl *ctl, int add,
+                             const MgLevel &lv, double jac) {
   const int nb = (int)blocks_for(n);
   hipLaunchKernelGGL(k_fcg_update<T>, dim3(nb), dim3(BLOCK), 0, s, n, mask, p, q, phi, r, r0, e0,
-                     partial, kc, ctl);
+                     partial, kc, ctl, lv, T(jac), T(lv.h2 / 6.0));
   hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
@@ -1001,7 +1006,8 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                         const KrylovCtl *, const SolveCtl *);                   \
   template hipError_t launch_fcg_update<T>(hipStream_t, int, const uint32_t *, const double *,  \
                                            const double *, double *, double *, T *, T *,        \
-                                           double *, const KrylovCtl *, SolveCtl *, int);       \
+                                           double *, const KrylovCtl *, SolveCtl *, int,        \
+                                           const MgLevel &, double);                            \
   template hipError_t launch_mg_smooth<T>(hipStream_t, const MgLevel &, double, int,            \
                                           const uint32_t *, const T *, T *, const SolveCtl *);  \
   template hipError_t launch_jacobi<T>(hipStream_t, const MgLevel &, double, double,             \
