@@ -228,9 +228,11 @@ def test_tiled_kernels_match_untiled(geometry, precision, monkeypatch):
 @pytest.mark.parametrize("precision", [lbe.FP32_MIXED, lbe.FP64])
 @pytest.mark.parametrize("cycle", ["V(2,2)", "V(1,1)"])
 def test_coarse_first_sweep_in_restriction_same_results(geometry, precision, cycle, monkeypatch):
-    """The coarse correction starts from zero, so the first Jacobi sweep on a
-    coarse level is pointwise and the restriction writes it; a run with that
-    (the default) and one with the sweep as its own launch
+    """A correction that starts from zero makes the first Jacobi sweep
+    pointwise, so the kernel writing a level's right-hand side writes it (the
+    restriction on coarse levels; on the finest level the residual check,
+    and under Krylov acceleration the update kernel); a run with that (the
+    default) and one with every such sweep as its own launch
     (LBE_NO_COARSE_START=1) must agree bit for bit.  On 64 x 64 x 34 the two
     levels below the finest (32 x 32 x 17, 16 x 16 x 9) are smoothed by the
     global kernels and the rest by the one-work-group kernel."""
