@@ -76,6 +76,8 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False):
         "sor": 8 + (8 + 8 + 4) / 4,
         "sor32": 4 + (4 + 4 + 4) / 4,
         "mg_smooth0": 3 * cor + 4,
+        # the finest level's last sweep of a cycle also adds e to phi
+        "mg_smooth0_phi": 3 * cor + 4 + 16,
         "mg_smooth": 3 * cor + 4,
         "mg_restrict": 2 * cor + 4 + (4 + 2 * cor) / 8,
         "mg_prolong": 2 * cor + 4 + (cor + 4) / 8,

@@ -115,6 +115,10 @@ typedef struct {
   double nk[4];           /* sum over fluid nodes of n_k */
   double q_ion;           /* sum over fluid nodes of sum_k z_k n_k */
   int64_t poisson_total;  /* sweeps (or cycles) summed over all solves */
+  double momentum[3];     /* total fluid momentum sum over fluid nodes of
+                             sum_i f_i c_i + F/2 (rho u of Guo forcing), the
+                             M of lbe_adjoint; its component along an applied
+                             field is the electro-osmotic flux */
 } lbe_obs;
 
 /*
@@ -317,6 +321,12 @@ int32_t lbe_num_kernel_kinds(void);
 
 /* The velocity set as the library uses it (19*3 ints, 19 weights). */
 void lbe_velocities(int32_t *c, double *w);
+
+/* Identity of the build: a hash of the sources the library was compiled
+ * from (a static string, never NULL; "unknown" when the build did not set
+ * it).  A binding compares it with the sources it ships beside, so that a
+ * stale library is refused instead of being run. */
+const char *lbe_build_id(void);
 
 #ifdef __cplusplus
 }

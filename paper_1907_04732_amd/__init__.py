@@ -28,7 +28,7 @@ ENTRY_POINTS = (
     "lbe_poisson", "lbe_set_electrode_potential", "lbe_record", "lbe_adjoint",
     "lbe_electrode_charge", "lbe_observables", "lbe_fields_device",
     "lbe_destroy", "lbe_strerror", "lbe_last_error", "lbe_profile", "lbe_kernel_times",
-    "lbe_kernel_name", "lbe_num_kernel_kinds", "lbe_velocities",
+    "lbe_kernel_name", "lbe_num_kernel_kinds", "lbe_velocities", "lbe_build_id",
 )
 
 
@@ -54,7 +54,7 @@ class Obs(C.Structure):
     _fields_ = [
         ("step", C.c_int64), ("nelectrodes", C.c_int32), ("poisson_iters", C.c_int32),
         ("poisson_resid", C.c_double), ("mass", C.c_double), ("nk", C.c_double * 4),
-        ("q_ion", C.c_double), ("poisson_total", C.c_int64),
+        ("q_ion", C.c_double), ("poisson_total", C.c_int64), ("momentum", C.c_double * 3),
     ]
 
 
@@ -90,6 +90,14 @@ def load(path: str = LIB_PATH):
                       "(there is no CPU fallback)")
     _bring_up_torch_first()
     lib = C.CDLL(path)
+    lib.lbe_build_id.argtypes = []
+    lib.lbe_build_id.restype = C.c_char_p
+    if os.path.isdir(os.path.join(_HERE, "csrc")):
+        from .build import source_hash
+        have, want = lib.lbe_build_id().decode(), source_hash()
+        if have != want:
+            raise OSError(f"{path} was built from other sources (build {have}, sources {want}): "
+                          "rebuild it with `python -m paper_1907_04732_amd.build`")
     P = C.POINTER
     d = P(C.c_double)
     lib.lbe_init.argtypes = [P(Params), P(C.c_uint8), d, d, d, d, P(C.c_void_p)]
@@ -360,7 +368,7 @@ class Lbe:
                                               None))
         return dict(step=o.step, nelectrodes=o.nelectrodes, poisson_iters=o.poisson_iters,
                     poisson_resid=o.poisson_resid, mass=o.mass, nk=list(o.nk)[: self.K],
-                    q_ion=o.q_ion, poisson_total=o.poisson_total)
+                    q_ion=o.q_ion, poisson_total=o.poisson_total, momentum=list(o.momentum))
 
     def fields(self, f=True, device=None):
         """dict with phi (N), n (K,N), u (3,N) and, if f, populations (19,N).

@@ -35,10 +35,7 @@ class ElectrodeCharge(torch.autograd.Function):
         sim.record(setup["nsteps"], setup.get("every", 64))
         ctx.sim = sim
         ctx.shapes = (phi_s.shape, n_init.shape, f_init.shape)
-        fl = sim.fields(f=True)
-        fluid = np.asarray(setup["node_type"]).reshape(-1) == 0
-        rho = fl["f"].sum(0)
-        mom = (fl["u"] * rho)[:, fluid].sum(1)
+        mom = np.array(sim.totals()["momentum"])
         return torch.from_numpy(sim.qhist()[-1].copy()), torch.from_numpy(mom)
 
     @staticmethod

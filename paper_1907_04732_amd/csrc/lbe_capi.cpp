@@ -459,11 +459,21 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
     return LBE_OK;
   };
   if ((rc = reset_ctl(c))) return rc;
-  if (p.tol <= 0.0) {  // exactly max_iter iterations
-    for (int it = 0; it < p.max_iter; it += per_check)
-      if ((rc = step(std::min(per_check, p.max_iter - it)))) return rc;
-    if ((rc = check(p.max_iter))) return rc;
+  if (p.tol <= 0.0) {
+    // exactly max_iter iterations on the schedule of a tolerance-driven
+    // solve: a check before the first unit and one after each.  The checks
+    // are part of the iteration where the solver needs them: the defect
+    // correction's V-cycle and the mixed SOR sweeps take their right-hand
+    // side (and the finest level's first sweep) from the check before them,
+    // and the Krylov iteration starts from the first check's residual.  With
+    // tol <= 0 no check ever ends the solve early.
+    if ((rc = check(0))) return rc;
     c->checks_queued = 1;
+    for (int it = 0; it < p.max_iter; it += per_check) {
+      const int m = std::min(per_check, p.max_iter - it);
+      if ((rc = unit_direct(m))) return rc;
+      c->checks_queued += 1;
+    }
     if ((rc = read_ctl(c))) return rc;
     c->last_iters = p.max_iter;
     c->last_resid = c->ctl_h->resid;
@@ -886,7 +896,8 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
     if (c->mg_jacobi > 0.0) {
       for (int s2 = 0; s2 < sweeps; ++s2) {
         const bool last = s2 + 1 == sweeps;
-        const int r2 = run(c, sk, L.lv.n, [&] {
+        const KernelKind kind = last && add_to ? KK_MG_SMOOTH0_PHI : sk;
+        const int r2 = run(c, kind, L.lv.n, [&] {
           return launch_jacobi<T>(c->stream, L.lv, c->mg_jacobi, L.lv.h2 / 6.0, L.mask, r, cur,
                                   alt, c->ctl, last ? add_to : nullptr);
         });
@@ -1507,6 +1518,11 @@ const char *lbe_strerror(int code) {
 }
 
 const char *lbe_last_error(const lbe_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+#ifndef LBE_BUILD_ID
+#define LBE_BUILD_ID "unknown"
+#endif
+const char *lbe_build_id(void) { return LBE_BUILD_ID; }
 
 void lbe_velocities(int32_t *c, double *w) {
   for (int i = 0; i < NQ; ++i) {
@@ -2134,7 +2150,25 @@ int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double 
                                c->partial, c->dout);
     });
     if (rc) return rc;
-    rc = read_scalars(c, 2 + K);
+    // total fluid momentum from the pre-collision populations and the Guo
+    // velocity of the current state (the observables kernel's output buffers
+    // are free between steps)
+    const size_t N = (size_t)c->L.n;
+    double *fpre = c->mixed ? c->obs : c->f[1 - c->cur];
+    double *uo = c->mixed ? c->obs + (size_t)NQ * N : c->u;
+    rc = run(c, KK_OBSERVE, c->L.n, [&] {
+      if (c->mixed)
+        return launch_observe_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[c->cur],
+                                  c->h32[c->cur], fpre, uo);
+      return launch_observe_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[c->cur],
+                                c->f[c->cur], fpre, uo);
+    });
+    if (rc) return rc;
+    rc = run(c, KK_MOMENTUM, c->L.n, [&] {
+      return launch_momentum(c->stream, c->L, c->mask, fpre, uo, c->partial, c->dout + 8);
+    });
+    if (rc) return rc;
+    rc = read_scalars(c, 11);
     if (rc) return rc;
     memset(totals, 0, sizeof *totals);
     totals->step = c->step;
@@ -2145,6 +2179,7 @@ int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double 
     totals->q_ion = c->hpin[1];
     for (int k = 0; k < K; ++k) totals->nk[k] = c->hpin[2 + k];
     totals->poisson_total = c->total_iters;
+    for (int a = 0; a < 3; ++a) totals->momentum[a] = c->hpin[8 + a];
   }
   rc = copy_fields(c, phi, n, u, f, hipMemcpyDeviceToHost);
   if (rc) return rc;

@@ -159,6 +159,8 @@ enum KernelKind {
   KK_ADJ_MOMENTS, // reverse sweep: rho and m of a recomputed state
   KK_REWIND,      // back to the start of a step whose solve failed
   KK_EXPAND_N,    // mixed form: FP64 concentrations into a caller's device buffer
+  KK_MG_SMOOTH0_PHI,  // the finest level's last Jacobi sweep of a cycle, with phi += e
+  KK_MOMENTUM,    // total fluid momentum
   KK_COUNT
 };
 
@@ -207,6 +209,8 @@ hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const 
 hipError_t launch_totals_f64(hipStream_t s, const Lattice &L, int K, const int *z,
                              const uint32_t *mask, const double *fin, const double *n,
                              double *partial, double *out /*2+K*/);
+hipError_t launch_momentum(hipStream_t s, const Lattice &L, const uint32_t *mask,
+                           const double *fpre, const double *u, double *partial, double *out);
 hipError_t launch_observe_f64(hipStream_t s, const Lattice &L, const Phys &P,
                               const uint32_t *mask, const double *phi, const double *n,
                               const double *fin, double *fpre, double *u);

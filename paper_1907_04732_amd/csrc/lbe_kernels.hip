@@ -23,7 +23,7 @@ const char *const kKernelNames[KK_COUNT] = {
     "fluid", "ions", "sor", "resid", "charge", "totals", "observe", "sor32", "correct",
     "mg_resid", "mg_smooth", "mg_smooth0", "mg_restrict", "mg_prolong", "mg_coarse", "mg_small",
     "fcg_beta", "fcg_dir", "fcg_apply", "fcg_update", "adj_fluid", "adj_ions", "adj_fold",
-    "adj_seed", "adj_moments", "rewind", "expand_n"};
+    "adj_seed", "adj_moments", "rewind", "expand_n", "mg_smooth0_phi", "momentum"};
 
 namespace {
 
@@ -364,6 +364,28 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f64(Lattice L, int K, int4 zk,
   }
 }
 
+// Total fluid momentum sum_r rho(r) u(r) = sum_r (sum_i f_i c_i + F/2) over
+// fluid nodes, from the pre-collision populations and the velocity of Guo
+// forcing that the observables kernel wrote (its component along an applied
+// field is the electro-osmotic flux).
+__global__ __launch_bounds__(BLOCK) void k_momentum(Lattice L, const uint32_t *__restrict__ mask,
+                                                    const double *__restrict__ fpre,
+                                                    const double *__restrict__ u,
+                                                    double *__restrict__ partial) {
+  __shared__ double sm[BLOCK / WAVE];
+  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int N = L.n;
+  const bool fluid = r < N && !(mask[r] & SOLID_BIT);
+  double rho = 0.0;
+  if (fluid)
+    for (int i = 0; i < NQ; ++i) rho += fpre[i * N + r];
+  for (int a = 0; a < 3; ++a) {
+    double v = fluid ? rho * u[a * N + r] : 0.0;
+    v = block_sum(v, sm);
+    if (threadIdx.x == 0) partial[a * gridDim.x + blockIdx.x] = v;
+  }
+}
+
 // ---- observables: pre-collision populations and the Guo velocity ----------
 
 template <int K>
@@ -525,6 +547,14 @@ hipError_t launch_totals_f64(hipStream_t s, const Lattice &L, int K, const int *
   const int nb = (int)blocks_for(L.n);
   hipLaunchKernelGGL(k_totals_f64, dim3(nb), dim3(BLOCK), 0, s, L, K, zk, mask, fin, n, partial);
   hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(FINAL), 0, s, partial, nb, 2 + K, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_momentum(hipStream_t s, const Lattice &L, const uint32_t *mask,
+                           const double *fpre, const double *u, double *partial, double *out) {
+  const int nb = (int)blocks_for(L.n);
+  hipLaunchKernelGGL(k_momentum, dim3(nb), dim3(BLOCK), 0, s, L, mask, fpre, u, partial);
+  hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(FINAL), 0, s, partial, nb, 3, out);
   return hipGetLastError();
 }
 

@@ -28,6 +28,30 @@ def test_library_exports_every_declared_symbol():
     assert set(lbe.ENTRY_POINTS) <= set(names)
 
 
+def test_library_is_built_from_these_sources():
+    """lbe_build_id is the hash of the sources beside the library (the
+    binding refuses a stale build), and a changed hash is refused."""
+    from paper_1907_04732_amd.build import source_hash
+    lib = lbe.load()
+    assert lib.lbe_build_id().decode() == source_hash()
+    import ctypes
+    raw = ctypes.CDLL(lbe.LIB_PATH)
+    raw.lbe_build_id.restype = ctypes.c_char_p
+    assert raw.lbe_build_id().decode() == source_hash()
+
+
+def test_stale_library_is_refused(tmp_path, monkeypatch):
+    """A library whose build id differs from the sources is not loaded."""
+    import shutil
+    import paper_1907_04732_amd.build as B
+    stale = tmp_path / "liblbe.so"
+    shutil.copy(lbe.LIB_PATH, stale)
+    monkeypatch.setattr(lbe, "_lib", None)
+    monkeypatch.setattr(B, "source_hash", lambda: "0000000000000000")
+    with pytest.raises(OSError, match="other sources"):
+        lbe.load(str(stale))
+
+
 def test_velocity_set_matches_oracle_order():
     import oracle
     c, w = lbe.velocities()

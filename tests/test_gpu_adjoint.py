@@ -136,6 +136,11 @@ def test_momentum_adjoint_matches_tangent_oracle(kind):
                 "phi_s": gr["phi_s"] @ dirs["phi_s"]["dphi_s"],
                 "n0": (gr["n"] * dirs["n0"]["dn"]).sum(), "f0": (gr["f"] * dirs["f0"]["df"]).sum()}
 
+    # the library's own value of the objective (lbe_obs.momentum) is the
+    # tangent oracle's real part
+    m_ref = s_.momentum().real
+    m_lib = np.array(g.totals()["momentum"])
+    assert np.abs(m_lib - m_ref).max() <= 1e-10 * np.abs(m_ref).max(), (m_lib, m_ref)
     for a in range(3):
         ubar = np.zeros(3)
         ubar[a] = 1.0

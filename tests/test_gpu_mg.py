@@ -260,3 +260,46 @@ def test_coarse_first_sweep_in_restriction_same_results(geometry, precision, cyc
     for k in fa:
         assert np.array_equal(fa[k], fb[k]), k
     assert np.array_equal(qa, qb) and ia == ib
+
+
+@pytest.mark.parametrize("precision", [lbe.FP64, lbe.FP32_MIXED])
+@pytest.mark.parametrize("solver", ["mg", "mg+krylov", "sor"])
+def test_fixed_iteration_count_follows_the_tolerance_schedule(solver, precision):
+    """tol <= 0 runs exactly max_iter cycles (or sweeps) with the residual
+    checks of a tolerance-driven solve between them (the defect correction's
+    V-cycle, the mixed SOR sweeps and the Krylov iteration take their
+    right-hand side from the check before them).  So a solve at tol = 0 with
+    max_iter = k must give the potential, bit for bit, of the same solve at a
+    tolerance it cannot reach, stopped by the same limit (LBE_ENOCONV), and
+    the residual must have fallen.  64 x 8 x 34 with random electrodes, so
+    the finest level and the one below it run in the global multigrid
+    kernels."""
+    shape = (64, 8, 34)
+    t, ps = G.random_geometry(shape, 3, seed=13, fill=0.12)
+    rs = W.salt_for_debye(4.0, G.LB)
+    n0 = W.noisy_concentrations(t, [rs, rs], 1e-2, seed=8)
+    flags = lbe.ALLOW_FLOATING | (lbe.KRYLOV if solver == "mg+krylov" else 0)
+    k = 3 if solver != "sor" else 12
+    p = dict(z=(1, -1), D=(0.05, 0.08), lB=G.LB, tau=0.9, Eapp=(1e-3, 0.0, 5e-4),
+             tol=1e-4, max_iter=5000, check_every=4, precision=precision,
+             poisson=lbe.SOR4 if solver == "sor" else lbe.MG, flags=flags)
+    out = []
+    for tol in (0.0, 1e-300):
+        g = lbe.Lbe(lbe.make_params(shape, **p), t, ps, n0, (rs, rs))
+        r0 = g.totals()["poisson_resid"]
+        g.set_solver(tol=tol, max_iter=k)
+        if tol > 0:
+            with pytest.raises(lbe.LbeError) as ei:
+                g.poisson()
+            assert ei.value.code == lbe.ENOCONV
+        else:
+            it, _ = g.poisson()
+            assert it == k
+        tot = g.totals()
+        out.append((g.fields(f=False)["phi"], tot["poisson_iters"], tot["poisson_resid"], r0))
+        g.close()
+    (pa, ia, ra, r0), (pb, ib, rb, _) = out
+    print(solver, precision, "residual", r0, "->", ra, "iterations", ia, ib)
+    assert ia == ib == k
+    assert np.array_equal(pa, pb)
+    assert ra == rb and ra < r0
