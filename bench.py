@@ -150,26 +150,34 @@ def sync():
     _torch.cuda.synchronize()
 
 
-def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, check_every: int,
-             traffic=None, krylov=False, light=False):
+def step_params(w, form: str, solver: str = "mg", check_every: int = 8, krylov=False,
+                light=False):
+    """The launch configuration the benchmark times on workload w.
+    Multigrid forms start each solve from the quadratic extrapolation of the
+    last three potentials; the SOR form keeps the paper's warm start from
+    phi(t).  light: one Jacobi sweep each way on every level, V(1,1): with the
+    extrapolated start a step needs little reduction, and on plates, whose
+    electrodes the coarse levels represent exactly, the lighter cycle needs no
+    more cycles per step; curved electrodes keep V(2,2) with Krylov
+    acceleration, where the V(1,1) cycle needs 1.3-2x the iterations."""
     precision = lbe.FP64 if form == "fp64" else lbe.FP32_MIXED
     poisson = lbe.SOR4 if solver == "sor" else lbe.MG
-    # multigrid forms start each solve from the quadratic extrapolation of the
-    # last three potentials; the SOR form keeps the paper's warm start from
-    # phi(t).  light: one Jacobi sweep each way on every level, V(1,1): with
-    # the extrapolated start a step needs little reduction, and on plates,
-    # whose electrodes the coarse levels represent exactly, the lighter cycle
-    # needs no more cycles per step; curved electrodes keep V(2,2) with Krylov
-    # acceleration, where the V(1,1) cycle needs 1.3-2x the iterations.
     flags = lbe.EXTRAPOLATE if solver == "mg" else 0
     if krylov and solver == "mg":
         flags |= lbe.KRYLOV
-    p = lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, rho0=getattr(w, "rho0", 1.0),
-                        Eapp=getattr(w, "Eapp", (0.0, 0.0, 0.0)), omega=getattr(w, "omega", 1.8),
-                        tol=getattr(w, "tol", 1e-10), max_iter=1_000_000,
-                        check_every=check_every, precision=precision, poisson=poisson,
-                        flags=flags, mg_nu1=1 if light else 2, mg_nu2=1 if light else 2,
-                        mg_nu1_coarse=1 if light else 0, mg_nu2_coarse=1 if light else 0)
+    return lbe.make_params(w.shape, w.z, w.D, w.lB, tau=w.tau, rho0=getattr(w, "rho0", 1.0),
+                           Eapp=getattr(w, "Eapp", (0.0, 0.0, 0.0)),
+                           omega=getattr(w, "omega", 1.8), tol=getattr(w, "tol", 1e-10),
+                           max_iter=1_000_000, check_every=check_every, precision=precision,
+                           poisson=poisson, flags=flags, mg_nu1=1 if light else 2,
+                           mg_nu2=1 if light else 2, mg_nu1_coarse=1 if light else 0,
+                           mg_nu2_coarse=1 if light else 0)
+
+
+def run_form(w: W.Workload, form: str, solver: str, steps: int, warmup: int, check_every: int,
+             traffic=None, krylov=False, light=False):
+    p = step_params(w, form, solver, check_every, krylov, light)
+    flags = p.flags
     t_init = time.perf_counter()
     if isinstance(w, W.Batch):
         g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref.reshape(-1), system=w.system,

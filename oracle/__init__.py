@@ -21,6 +21,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbe_oracle.c")
 _LIB = os.path.join(_HERE, "liblbe_oracle.so")
+# the same source built with OpenMP: the independent per-site loops run on
+# several threads, every value bit for bit the single-threaded one
+_LIB_OMP = os.path.join(_HERE, "liblbe_oracle_omp.so")
 
 FLAG_ALLOW_FLOATING = 1
 FLAG_NAIVE_DIRICHLET = 4  # first-order scheme: potential on the solid nodes, Eq. 12 everywhere
@@ -41,10 +44,12 @@ class OracleParams(C.Structure):
     ]
 
 
-def build(openmp: bool = False) -> str:
-    """Compile the oracle into a shared library next to its source."""
-    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
+def build() -> str:
+    """Compile the oracle into shared libraries next to its source: the
+    single-threaded one and the OpenMP one."""
+    base = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared"]
+    subprocess.run(base + ["-o", _LIB, _SRC, "-lm"], check=True)
+    subprocess.run(base + ["-fopenmp", "-o", _LIB_OMP, _SRC, "-lm"], check=True)
     return _LIB
 
 
@@ -67,11 +72,15 @@ def source_text() -> str:
         return fh.read()
 
 
+def _stale(lib_path):
+    return not os.path.exists(lib_path) or os.path.getmtime(lib_path) < os.path.getmtime(_SRC)
+
+
 def _load(path=None):
     key = path or _LIB
     if key in _libs:
         return _libs[key]
-    if path is None and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
+    if key in (_LIB, _LIB_OMP) and (_stale(_LIB) or _stale(_LIB_OMP)):
         build()
     lib = C.CDLL(key)
     P = C.POINTER
@@ -111,6 +120,8 @@ def _load(path=None):
     lib.orc_strerror.restype = C.c_char_p
     lib.orc_velocities.argtypes = [P(C.c_int), d]
     lib.orc_velocities.restype = None
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_set_threads.restype = C.c_int
     _libs[key] = lib
     return lib
 
@@ -148,8 +159,14 @@ class Oracle:
     """One oracle state.  Arrays use site index x + nx*(y + ny*z)."""
 
     def __init__(self, params: OracleParams, node_type, phi_s, n_init=None, n_ref=None,
-                 f_init=None, libpath=None):
-        lib = _load(libpath)
+                 f_init=None, libpath=None, threads=None):
+        """threads: run the per-site loops on that many OpenMP threads (the
+        same values bit for bit; None = the single-threaded build)."""
+        lib = _load(_LIB_OMP if threads and libpath is None else libpath)
+        if threads and libpath is None:
+            self.threads = lib.orc_set_threads(int(threads))
+        else:
+            self.threads = 1
         self._lib = lib
         self.p = params
         self.N = params.nx * params.ny * params.nz
@@ -190,6 +207,8 @@ class Oracle:
             raise OracleError(rc, self._lib.orc_last_error(self.h).decode())
 
     def step(self, nsteps=1):
+        if self.threads > 1:
+            self._lib.orc_set_threads(self.threads)
         self._check(self._lib.orc_step(self.h, int(nsteps)))
 
     def set_solver(self, tol, max_iter):

@@ -9,8 +9,17 @@
  * baseline leg of the benchmark may load it; the product path never does.
  * It shares no code, header, table or helper with the GPU library.
  *
- * Everything is double precision, single threaded, in the order the paper
- * states the method, with no blocking, fusion or reordering:
+ * Everything is double precision, in the order the paper states the method,
+ * with no blocking, fusion or reordering.  Built without OpenMP it is single
+ * threaded; built with it (only for timing on many cores, and for long test
+ * runs) the loops over sites whose iterations are independent run in
+ * parallel: one colour of an SOR sweep (no two nodes of a colour are
+ * neighbours), the residual maximum, the force, the velocity, the ion update
+ * and the LB update (each writes its own site, or, for streaming, a slot no
+ * other site writes).  Every value is then bit for bit the single-threaded
+ * one; sums over sites (charges, totals) stay serial, in site order.
+ *
+ *   init : phi <- Poisson(n(0))            (Sec. II C, Eqs. 13 and 15)
  *
  *   init : phi <- Poisson(n(0))            (Sec. II C, Eqs. 13 and 15)
  *          Q(0) from Gauss's law             (Sec. II C, Eq. 16)
@@ -50,6 +59,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ---- error codes (same meaning as the GPU library's) ------------------- */
 #define ORC_OK 0
@@ -196,12 +208,24 @@ static double residual_at(const orc_state *s, long r) {
   return laplacian_fluid(s, r) + 4.0 * M_PI * s->p.lB * charge_density(s, r);
 }
 
+/* max of a and b that keeps a NaN once one has appeared */
+static double max_keep_nan(double m, double a) {
+  if (m != m) return m;
+  return (a != a || a > m) ? a : m;
+}
+
 static double residual_inf(const orc_state *s) {
   double m = 0.0;
-  for (long r = 0; r < s->N; ++r) {
-    if (!is_fluid(s, r)) continue;
-    double a = fabs(residual_at(s, r));
-    if (!(a <= m)) m = a; /* also propagates NaN */
+#pragma omp parallel
+  {
+    double mt = 0.0;
+#pragma omp for schedule(static) nowait
+    for (long r = 0; r < s->N; ++r) {
+      if (!is_fluid(s, r)) continue;
+      mt = max_keep_nan(mt, fabs(residual_at(s, r)));
+    }
+#pragma omp critical
+    m = max_keep_nan(m, mt);
   }
   return m;
 }
@@ -230,6 +254,7 @@ static void sor_update(orc_state *s, long r) {
 /* One SOR sweep: the four colour classes in order 0, 1, 2, 3. */
 static void sor_sweep(orc_state *s) {
   for (int c = 0; c < 4; ++c)
+#pragma omp parallel for schedule(static)
     for (long r = 0; r < s->N; ++r)
       if (is_fluid(s, r) && colour(&s->p, r) == c) sor_update(s, r);
 }
@@ -324,6 +349,7 @@ static double excess_link(double n_here, double n_there, double delta, double le
 /* Force density on the fluid at every fluid node (reading R3). */
 static void compute_force(orc_state *s) {
   const orc_params *p = &s->p;
+#pragma omp parallel for schedule(static)
   for (long r = 0; r < s->N; ++r) {
     double F[3] = {0.0, 0.0, 0.0};
     if (is_fluid(s, r)) {
@@ -347,6 +373,7 @@ static void compute_force(orc_state *s) {
 /* Density and velocity (Eq. 7, reading R1) with the half-force shift of Guo
  * forcing: u = (sum_i f_i c_i + F/2) / rho. */
 static void compute_velocity(orc_state *s) {
+#pragma omp parallel for schedule(static)
   for (long r = 0; r < s->N; ++r) {
     double rho = 0.0, m[3] = {0.0, 0.0, 0.0};
     if (is_fluid(s, r)) {
@@ -376,6 +403,7 @@ static void update_ions(orc_state *s) {
     const double *nk = s->n + (long)k * s->N;
     double *out = s->nnew + (long)k * s->N;
     double dk = p->D[k] / A0;
+#pragma omp parallel for schedule(static)
     for (long r = 0; r < s->N; ++r) {
       if (!is_fluid(s, r)) {
         out[r] = nk[r];
@@ -415,6 +443,7 @@ static void update_ions(orc_state *s) {
 static void update_fluid(orc_state *s) {
   const orc_params *p = &s->p;
   const double tau = p->tau;
+#pragma omp parallel for schedule(static)
   for (long r = 0; r < s->N; ++r) {
     if (!is_fluid(s, r)) continue;
     double rho = 0.0;
@@ -800,6 +829,18 @@ long orc_qhist(const orc_state *s, double *out, long cap) {
   long m = s->qlen < cap ? s->qlen : cap;
   if (out && s->ne) memcpy(out, s->qhist, sizeof(double) * (size_t)m * s->ne);
   return s->qlen;
+}
+
+/* Threads of the parallel loops: sets the count when n > 0 and returns the
+ * count in use (1 when built without OpenMP). */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 /* The velocity set, for checking that both implementations agree on it. */

@@ -1,0 +1,148 @@
+"""The FP32-mixed form at the benchmark's own solver settings and at the
+configurations' full size and length.
+
+1. Against the FP64 oracle, element by element, on lattices large enough that
+   the finest multigrid level and the one below it run in the global
+   kernels (more than 2048 cells on each; the coarser levels go to the
+   one-work-group kernel): a 16 x 16 x 130 lateral crop of the
+   electro-osmosis slab with Jacobi V(1,1) on every level and the quadratic
+   warm start, and a 40 x 40 x 16 coaxial cell and a 32^3 crop of the porous
+   electrode with V(2,2), Krylov acceleration and the quadratic warm start,
+   all at tol 1e-10: exactly the launch configuration bench.py times.  The
+   oracle runs its SOR (four colours, diagonal-normalised, omega 1.95: only
+   the iterates depend on omega, not the fixed point) to 1e-12 on many
+   threads (its OpenMP build is bit for bit the single-threaded one).
+2. Against the FP64 form on the GPU (itself within 1e-12 of the oracle on
+   the parity cases) at full size for thousands of steps: the 64 x 64 x 130
+   electro-osmosis slab, the 160 x 160 x 64 coaxial cell, the 192^3 porous
+   electrode and the 96-system batch, each in its benchmark configuration.
+
+Bars (the benchmark spec): potential within 1e-5 of the electrode voltage
+difference; electrode charge Q(t) over the whole history and capacitance
+Q(T)/dV within 1e-5 of |Q|; velocity within 1e-4 of its largest magnitude,
+and the electro-osmotic flux (total momentum along the applied field)
+within 1e-4 of the flux of |u|.
+Concentrations are reported normalised by their largest departure from the
+bulk value (bar 1e-3, as for the small parity cases).  The FP64 solve stops
+at 1e-10 too, so part of each difference is the solver's own tolerance
+(|A^-1| tol <= L^2/8 x 1e-10 on the potential: 2e-7 at L = 128).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import bench
+import oracle
+import paper_1907_04732_amd as lbe
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PHI_BAR, Q_BAR, U_BAR, N_BAR = 1e-5, 1e-5, 1e-4, 1e-3
+THREADS = int(os.environ.get("OMP_NUM_THREADS", "8"))
+
+
+def errors(t, nref, phi_s, a, b, qa, qb):
+    """Normalised maximum differences of run a against reference b."""
+    fl = t == 0
+    dv = phi_s[~fl].max() - phi_s[~fl].min()
+    dn = np.abs(b["n"][:, fl] - np.asarray(nref).reshape(-1, 1)[: b["n"].shape[0]]).max()
+    umax = np.abs(b["u"][:, fl]).max()
+    return dict(
+        phi=float(np.abs(a["phi"] - b["phi"]).max() / dv),
+        q=float(np.abs(qa - qb).max() / np.abs(qb).max()),
+        C=float((np.abs(qa[-1] - qb[-1]) / np.abs(qb[-1])).max()),
+        u=float(np.abs(a["u"][:, fl] - b["u"][:, fl]).max() / umax),
+        n=float(np.abs(a["n"][:, fl] - b["n"][:, fl]).max() / dn),
+        umax=float(umax))
+
+
+def check(errs):
+    assert errs["phi"] <= PHI_BAR, errs
+    assert errs["q"] <= Q_BAR and errs["C"] <= Q_BAR, errs
+    assert errs["u"] <= U_BAR, errs
+    assert errs["n"] <= N_BAR, errs
+
+
+CROPS = {
+    "eo_slab_16x16x130": lambda: (W.eo_slab(noise=True, nx=16, ny=16), dict(light=True), 200),
+    "coaxial_40x40x16": lambda: (W.coaxial(noise=True, nx=40, ny=40, nz=16, R1=4.0, R2=18.0),
+                                 dict(krylov=True), 200),
+    "porous_crop_32^3": lambda: (W.porous_crop(n=32), dict(krylov=True), 120),
+}
+
+
+@pytest.mark.parametrize("name", list(CROPS))
+def test_mixed_at_bench_settings_matches_oracle(name):
+    w, settings, steps = CROPS[name]()
+    g = lbe.Lbe(bench.step_params(w, "fp32", **settings), w.node_type, w.phi_s, w.n_init,
+                w.n_ref)
+    assert g.totals()["step"] == 0
+    o = oracle.Oracle(oracle.make_params(w.shape, w.z, w.D, w.lB, w.tau, w.rho0, w.Eapp, 1.95,
+                                         1e-12, 10**6, 4), w.node_type, w.phi_s, w.n_init,
+                      w.n_ref, threads=THREADS)
+    g.step(steps)
+    o.step(steps)
+    errs = errors(w.node_type, w.n_ref, w.phi_s, g.fields(f=False), o.fields(), g.qhist(),
+                  o.qhist())
+    print(name, steps, "steps, mixed at bench settings vs oracle:",
+          {k: f"{v:.2e}" for k, v in errs.items()}, "cycles", g.totals()["poisson_total"])
+    check(errs)
+
+
+FULL = {
+    "eo_slab_64x64x130": lambda: (W.eo_slab(noise=True), dict(light=True), 5000),
+    "coaxial_160x160x64": lambda: (W.coaxial(noise=True), dict(krylov=True), 3000),
+    "porous_electrode_192^3": lambda: (W.porous_electrode(noise=True), dict(krylov=True), 2000),
+}
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_mixed_matches_fp64_at_full_size(name):
+    w, settings, steps = FULL[name]()
+    runs = {}
+    for form in ("fp32", "fp64"):
+        g = lbe.Lbe(bench.step_params(w, form, **settings), w.node_type, w.phi_s, w.n_init,
+                    w.n_ref)
+        g.step(steps)
+        runs[form] = (g.fields(f=False), g.qhist(), g.totals())
+        g.close()
+    (fa, qa, ta), (fb, qb, tb) = runs["fp32"], runs["fp64"]
+    errs = errors(w.node_type, w.n_ref, w.phi_s, fa, fb, qa, qb)
+    if any(w.Eapp):
+        # the electro-osmotic flux along the applied field (the total
+        # momentum), against the flux of |u|: on the slab the profile is odd
+        # about the mid-plane (Eq. 20) and its net flux nearly cancels
+        ax = int(np.argmax(np.abs(w.Eapp)))
+        scale = np.abs(fb["u"][ax][w.node_type == 0]).sum()
+        errs["eo_flux"] = abs(ta["momentum"][ax] - tb["momentum"][ax]) / scale
+    print(name, steps, "steps, mixed vs FP64 on the GPU:",
+          {k: f"{v:.2e}" for k, v in errs.items()})
+    check(errs)
+    assert errs.get("eo_flux", 0.0) <= U_BAR
+
+
+def test_batch_capacitance_mixed_matches_fp64():
+    """The 96-system batch (8 x 8 x L, L 16..256, Debye length 2..16, voltage
+    0.01..0.2) in its benchmark configuration for 2000 steps: every system's
+    charge history and capacitance Q(T)/V in the mixed form against the FP64
+    form, and the potential of every system against its own voltage."""
+    w = W.batch_slabs(noise=True)
+    runs = {}
+    for form in ("fp32", "fp64"):
+        p = bench.step_params(w, form, krylov=True)
+        g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref.reshape(-1), system=w.system,
+                    nsys=len(w.L))
+        g.step(2000)
+        runs[form] = (g.fields(f=False)["phi"], g.qhist())
+        g.close()
+    (pa, qa), (pb, qb) = runs["fp32"], runs["fp64"]
+    nsys = len(w.L)
+    # electrodes 2s+1 and 2s+2 belong to system s
+    qa3, qb3 = qa.reshape(len(qa), nsys, 2), qb.reshape(len(qb), nsys, 2)
+    e_q = np.abs(qa3 - qb3).max(axis=(0, 2)) / np.abs(qb3).max(axis=(0, 2))
+    e_c = np.abs(qa3[-1] - qb3[-1]).max(axis=1) / np.abs(qb3[-1]).max(axis=1)
+    e_phi = np.array([np.abs(pa - pb)[w.system == s].max() for s in range(nsys)]) / w.V
+    print("batch: worst system Q(t)", e_q.max(), "capacitance", e_c.max(), "phi/V", e_phi.max())
+    assert e_q.max() <= Q_BAR and e_c.max() <= Q_BAR and e_phi.max() <= PHI_BAR
