@@ -53,7 +53,7 @@ enum { LBE_MG_JACOBI = 0, LBE_MG_GS4 = 1 };  /* multigrid smoother */
 enum { LBE_ALLOW_FLOATING = 1, LBE_EXTRAPOLATE = 2, LBE_NAIVE_DIRICHLET = 4,
        LBE_KRYLOV = 8 };  /* flags */
 enum { LBE_MAX_SPECIES = 4, LBE_MAX_ELECTRODES = 255, LBE_MAX_SITES = 100000000,
-       LBE_MAX_SYSTEMS = 8192 };
+       LBE_MAX_SYSTEMS = 8192, LBE_NOALLOC_MAX_ELECTRODES = 16 };
 
 typedef struct lbe_ctx lbe_ctx;
 
@@ -279,6 +279,36 @@ int lbe_adjoint(lbe_ctx *ctx, const double *qbar, const double *ubar, double *gr
  * solid nodes, the difference doubled on each solid-fluid link).
  * q has room for ne >= nelectrodes values.  LBE_EINVAL if ne is too small. */
 int lbe_electrode_charge(lbe_ctx *ctx, double *q, int32_t ne);
+
+/*
+ * lbe_electrode_charge without a context and without allocating, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The charge of each
+ * electrode e = 1..ne from Gauss's law on a potential field, as
+ * lbe_electrode_charge computes it (Eq. 16 with the Laplacian of Eq. 15, the
+ * difference doubled on each solid-fluid link, or taken once with
+ * LBE_NAIVE_DIRICHLET in flags, the only flag accepted):
+ *   Q_e = -(6 / 4 pi lB) sum over nodes r of type e of
+ *         sum over links i to fluid nodes of wall w_i (phi(r + c_i) - phi(r)).
+ * type (N bytes, the node types of lbe_init), phi (N doubles; solid nodes
+ * hold their electrode potential) and q (ne doubles, written) are device
+ * memory of the current device, in the site order above; nodes of a type
+ * above ne are ignored.  The kernels run on `stream` (a hipStream_t; NULL =
+ * the null stream) and the call returns without waiting for them.
+ * Scratch: the per-block partial sums live in a fixed device array of
+ * 256 KiB that the library holds on each GPU it runs on until the process
+ * ends; every call on a GPU shares it, so calls that overlap on one GPU
+ * (on different streams, or from several threads) race.  Nothing needs
+ * clearing between calls.
+ * Errors (lbe_last_error(NULL) says which): LBE_EINVAL for a dimension < 1,
+ * more than LBE_MAX_SITES sites, ne outside 1..LBE_NOALLOC_MAX_ELECTRODES,
+ * lB not finite and > 0, another flag, or a pointer that is NULL or not
+ * device memory of the current device (nothing launched); LBE_EDEVICE when
+ * the device or a launch fails.
+ */
+int lbe_electrode_charge_noalloc(int32_t nx, int32_t ny, int32_t nz, double lB, int32_t flags,
+                                 const uint8_t *type, const double *phi, double *q, int32_t ne,
+                                 void *stream);
 
 /*
  * Copy observables to host buffers; any pointer may be NULL to skip it.

@@ -21,6 +21,7 @@ ALLOW_FLOATING = 1
 EXTRAPOLATE = 2
 NAIVE_DIRICHLET = 4
 KRYLOV = 8
+NOALLOC_MAX_ELECTRODES = 16
 
 # public entry points of include/lbe.h
 ENTRY_POINTS = (
@@ -29,6 +30,7 @@ ENTRY_POINTS = (
     "lbe_electrode_charge", "lbe_observables", "lbe_fields_device",
     "lbe_destroy", "lbe_strerror", "lbe_last_error", "lbe_profile", "lbe_kernel_times",
     "lbe_kernel_name", "lbe_num_kernel_kinds", "lbe_velocities", "lbe_build_id",
+    "lbe_electrode_charge_noalloc",
 )
 
 
@@ -142,6 +144,9 @@ def load(path: str = LIB_PATH):
     lib.lbe_num_kernel_kinds.restype = C.c_int32
     lib.lbe_velocities.argtypes = [P(C.c_int32), d]
     lib.lbe_velocities.restype = None
+    lib.lbe_electrode_charge_noalloc.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                                 C.c_int32, v, v, v, C.c_int32, v]
+    lib.lbe_electrode_charge_noalloc.restype = C.c_int
     _lib = lib
     return lib
 
@@ -173,6 +178,32 @@ def make_params(shape, z, D, lB, tau=1.0, rho0=1.0, Eapp=(0.0, 0.0, 0.0), omega=
     p.mg_nu1_coarse, p.mg_nu2_coarse = int(mg_nu1_coarse), int(mg_nu2_coarse)
     p.stream = stream
     return p
+
+
+def electrode_charge_noalloc(shape, lB, node_type, phi, q, naive=False, stream=None):
+    """lbe_electrode_charge_noalloc: electrode charges of the potential `phi`
+    (float64 GPU tensor, N) on the node types `node_type` (uint8 GPU tensor,
+    N) into `q` (float64 GPU tensor, one entry per electrode 1..len(q)),
+    launched on `stream` (a torch stream; None = torch's current stream) and
+    not waited for.  Nothing is allocated."""
+    import torch
+
+    lib = load()
+    for name, a, dt in (("node_type", node_type, torch.uint8), ("phi", phi, torch.float64),
+                        ("q", q, torch.float64)):
+        if not _is_gpu_tensor(a) or a.dtype != dt or not a.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dt} GPU tensor")
+    nx, ny, nz = (int(v) for v in shape)
+    if node_type.numel() != nx * ny * nz or phi.numel() != nx * ny * nz:
+        raise ValueError("node_type and phi need nx*ny*nz entries")
+    s = stream if stream is not None else torch.cuda.current_stream(q.device)
+    with torch.cuda.device(q.device):
+        rc = lib.lbe_electrode_charge_noalloc(nx, ny, nz, float(lB),
+                                              NAIVE_DIRICHLET if naive else 0,
+                                              _tptr(node_type), _tptr(phi), _tptr(q), q.numel(),
+                                              C.c_void_p(s.cuda_stream))
+    if rc:
+        raise LbeError(rc, lib.lbe_last_error(None).decode())
 
 
 def velocities():

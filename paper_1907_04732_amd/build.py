@@ -20,7 +20,7 @@ HEADER = os.path.join(ROOT, "include", "lbe.h")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbe.so")
 SOURCES = ["lbe_kernels.hip", "lbe_kernels_f32.hip", "lbe_mg.hip", "lbe_adjoint.hip",
-           "lbe_capi.cpp"]
+           "lbe_noalloc.hip", "lbe_capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -166,6 +166,15 @@ int hip_fail(lbe_ctx *c, hipError_t e, const char *what) {
               std::string(what) + ": " + hipGetErrorString(e));
 }
 
+}  // namespace
+
+namespace lbe {
+// A failure of a call without a context, reported by lbe_last_error(NULL).
+int report_init_error(int code, const char *msg) { return fail(nullptr, code, msg); }
+}  // namespace lbe
+
+namespace {
+
 #define HIPCHK(c, call)                                   \
   do {                                                    \
     hipError_t e_ = (call);                               \

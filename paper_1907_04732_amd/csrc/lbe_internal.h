@@ -209,6 +209,10 @@ hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const 
 hipError_t launch_totals_f64(hipStream_t s, const Lattice &L, int K, const int *z,
                              const uint32_t *mask, const double *fin, const double *n,
                              double *partial, double *out /*2+K*/);
+// Records msg for lbe_last_error(NULL) and returns code (calls without a
+// context).
+int report_init_error(int code, const char *msg);
+
 hipError_t launch_momentum(hipStream_t s, const Lattice &L, const uint32_t *mask,
                            const double *fpre, const double *u, double *partial, double *out);
 hipError_t launch_observe_f64(hipStream_t s, const Lattice &L, const Phys &P,
