@@ -334,9 +334,10 @@ __global__ __launch_bounds__(BLOCK) void k_smooth(MgLevel lv, T omega, int colou
 // ---- damped Jacobi sweep (one launch, every cell in parallel) --------------
 // x_out = x_in + omega ([sum_i w_i s_i x_in(r+c_i) + hs rhs] / sum_i w_i s_i - x_in)
 
-// With phi_add given (the last sweep of a V-cycle on the finest level), the
-// result is also added to phi on fluid cells, as k_correct does.
-template <class T>
+// With ADD_PHI (the last sweep of a V-cycle on the finest level), the result
+// is also added to phi_add on fluid cells, as k_correct does (a kernel of its
+// own name, so that profiles tell the two apart).
+template <class T, bool ADD_PHI>
 __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
                                                   const uint32_t *__restrict__ mask,
                                                   const T *__restrict__ rhs,
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
   const bool solid = m & SOLID_BIT;
   const T res = solid ? T(0) : xr + omega * (num / den - xr);
   x_out[r] = res;
-  if (phi_add && !solid) phi_add[r] += double(res);
+  if (ADD_PHI && !solid) phi_add[r] += double(res);
 }
 
 // ---- restriction: coarse rhs = mean of the fluid children's residuals -------
@@ -927,8 +928,12 @@ template <class T>
 hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double hs,
                          const uint32_t *mask, const T *rhs, const T *x_in, T *x_out,
                          const SolveCtl *ctl, double *phi_add) {
-  hipLaunchKernelGGL(k_jacobi<T>, dim3(blocks_for(lv.n)), dim3(BLOCK), 0, s, lv, T(omega), T(hs),
-                     mask, rhs, x_in, x_out, ctl, phi_add);
+  if (phi_add)
+    hipLaunchKernelGGL((k_jacobi<T, true>), dim3(blocks_for(lv.n)), dim3(BLOCK), 0, s, lv,
+                       T(omega), T(hs), mask, rhs, x_in, x_out, ctl, phi_add);
+  else
+    hipLaunchKernelGGL((k_jacobi<T, false>), dim3(blocks_for(lv.n)), dim3(BLOCK), 0, s, lv,
+                       T(omega), T(hs), mask, rhs, x_in, x_out, ctl, phi_add);
   return hipGetLastError();
 }
 

@@ -134,6 +134,20 @@ def porous_crop(n=24, z0=156, noise=True):
                     w.n_ref, n_init, w.omega, w.tol, w.steps, dict(w.extra))
 
 
+def porous_column(nxy=32, noise=True):
+    """A lateral crop of the porous electrode that keeps its whole height:
+    x, y in [0, nxy), every z (sphere packing, gap and counter-electrode),
+    periodic as a box of its own."""
+    w = porous_electrode(noise=False)
+    N = w.shape[0]
+    t = w.node_type.reshape(N, N, N)[:, :nxy, :nxy].copy().reshape(-1)
+    ps = w.phi_s.reshape(N, N, N)[:, :nxy, :nxy].copy().reshape(-1)
+    n_init = noisy_concentrations(t, w.n_ref, 1e-6, seed=5) if noise else None
+    return Workload(f"porous_column_{nxy}x{nxy}x{N}", (nxy, nxy, N), t, ps, w.z, w.D, w.lB,
+                    w.tau, w.rho0, w.Eapp, w.n_ref, n_init, w.omega, w.tol, w.steps,
+                    dict(w.extra))
+
+
 def noisy_concentrations(node_type, rho, rel=1e-6, seed=1):
     """n_k(r) = rho_k (1 + rel * U(-1, 1)) on fluid nodes, 0 on solid nodes,
     drawn from a PCG64 stream seeded with `seed`.  Returns (K, N)."""
