@@ -154,15 +154,13 @@ def sync():
 
 
 def step_params(w, form: str, solver: str = "mg", check_every: int = 8, krylov=False,
-                light=False):
+                nu=(2, 2, 0, 0)):
     """The launch configuration the benchmark times on workload w.
     Multigrid forms start each solve from the quadratic extrapolation of the
     last three potentials; the SOR form keeps the paper's warm start from
-    phi(t).  light: one Jacobi sweep each way on every level, V(1,1): with the
-    extrapolated start a step needs little reduction, and on plates, whose
-    electrodes the coarse levels represent exactly, the lighter cycle needs no
-    more cycles per step; curved electrodes keep V(2,2) with Krylov
-    acceleration, where the V(1,1) cycle needs 1.3-2x the iterations."""
+    phi(t).  nu = (pre, post) Jacobi sweeps on the finest level and (pre,
+    post) on the coarser ones (0, 0: the finest level's); krylov: each
+    V-cycle preconditions flexible CG."""
     precision = lbe.FP64 if form == "fp64" else lbe.FP32_MIXED
     poisson = lbe.SOR4 if solver == "sor" else lbe.MG
     flags = lbe.EXTRAPOLATE if solver == "mg" else 0
@@ -172,9 +170,8 @@ def step_params(w, form: str, solver: str = "mg", check_every: int = 8, krylov=F
                            Eapp=getattr(w, "Eapp", (0.0, 0.0, 0.0)),
                            omega=getattr(w, "omega", 1.8), tol=getattr(w, "tol", 1e-10),
                            max_iter=1_000_000, check_every=check_every, precision=precision,
-                           poisson=poisson, flags=flags, mg_nu1=1 if light else 2,
-                           mg_nu2=1 if light else 2, mg_nu1_coarse=1 if light else 0,
-                           mg_nu2_coarse=1 if light else 0)
+                           poisson=poisson, flags=flags, mg_nu1=nu[0], mg_nu2=nu[1],
+                           mg_nu1_coarse=nu[2], mg_nu2_coarse=nu[3])
 
 
 def make_context(w, p):
@@ -206,8 +203,8 @@ def roofline_of(kernels, kinds, label):
 
 
 def run_form(w, form: str, solver: str, steps: int, warmup: int, start_step: int,
-             check_every: int, traffic=None, krylov=False, light=False):
-    p = step_params(w, form, solver, check_every, krylov, light)
+             check_every: int, traffic=None, krylov=False, nu=(2, 2, 0, 0)):
+    p = step_params(w, form, solver, check_every, krylov, nu)
     flags = p.flags
     t_init = time.perf_counter()
     g = make_context(w, p)
@@ -343,15 +340,21 @@ def copy_calibration(nbytes=1 << 28, reps=5):
 FORMS = {"fp32-mg": ("fp32", "mg"), "fp64-mg": ("fp64", "mg"), "fp64-sor": ("fp64", "sor"),
          "fp32-sor": ("fp32", "sor")}
 
-# Workloads: builder and solver settings.  Curved electrodes (coaxial cell,
-# porous electrode) and the batch take V(2,2) cycles with Krylov
-# acceleration; the slab takes V(1,1) cycles (its electrodes are represented
-# exactly on every level).
+# Workloads: builder and multigrid cycle, chosen by timing the cycles on the
+# same GPU from a running state.  The slab's electrodes are represented
+# exactly on every level: V(1,1) everywhere.  The porous electrode's spheres
+# are not: V(2,2) with four Jacobi sweeps each way on the coarse levels, as
+# the preconditioner of flexible CG (plain cycles diverge there).  The
+# coaxial cell: V(1,1) with two sweeps each way on the coarse levels, plain.
+# The 96-system batch: V(1,2), two sweeps each way on the coarse levels,
+# with Krylov acceleration.
 WORKLOADS = {
-    "porous_electrode_192^3": (lambda: W.porous_electrode(noise=True), dict(krylov=True)),
-    "eo_slab_64x64x130": (lambda: W.eo_slab(noise=True), dict(light=True)),
-    "coaxial_160x160x64": (lambda: W.coaxial(noise=True), dict(krylov=True)),
-    "batched_96_slabs_8x8": (lambda: W.batch_slabs(noise=True), dict(krylov=True)),
+    "porous_electrode_192^3": (lambda: W.porous_electrode(noise=True),
+                               dict(krylov=True, nu=(2, 2, 4, 4))),
+    "eo_slab_64x64x130": (lambda: W.eo_slab(noise=True), dict(nu=(1, 1, 1, 1))),
+    "coaxial_160x160x64": (lambda: W.coaxial(noise=True), dict(nu=(1, 1, 2, 2))),
+    "batched_96_slabs_8x8": (lambda: W.batch_slabs(noise=True),
+                             dict(krylov=True, nu=(1, 2, 2, 2))),
 }
 
 
@@ -374,7 +377,10 @@ def run_workload(name, forms, steps, warmup, start_step, check_every, traffic=No
 
 
 def poisson_text(settings):
-    cyc = "Jacobi V(1,1) on every level" if settings.get("light") else "Jacobi V(2,2)"
+    n1, n2, c1, c2 = settings.get("nu", (2, 2, 0, 0))
+    if not (c1 or c2):
+        c1, c2 = n1, n2
+    cyc = f"Jacobi V({n1},{n2}) on the finest level, V({c1},{c2}) on the coarser ones"
     kry = ", each V-cycle preconditioning flexible CG" if settings.get("krylov") else ""
     return (f"geometric multigrid ({cyc}){kry}, FP64 defect correction, warm start "
             "extrapolated quadratically in time")

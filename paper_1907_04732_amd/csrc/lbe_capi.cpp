@@ -92,6 +92,10 @@ struct lbe_ctx {
     bool own_mask = false;
     void *e = nullptr, *r = nullptr;  // correction and right-hand side (T)
     void *e2 = nullptr;               // second correction buffer (Jacobi smoothing)
+    // host copies of the level's solid flags and fluid cells' systems (kept
+    // for the small levels only: they decide the work-group split)
+    std::vector<uint8_t> solid_h;
+    std::vector<uint16_t> sys_h;
   };
   std::vector<MgDev> mg;
   int mg_coarse_sweeps = 0;
@@ -105,6 +109,7 @@ struct lbe_ctx {
   int mg_small_from = -1;
   MgSmall mg_small{};
   size_t mg_small_lds = 0;
+  int *mg_groups = nullptr;  // range table of the independent groups (mg_small.ngroups > 1)
 
   // reverse mode: checkpoints kept by lbe_record, buffers of lbe_adjoint
   struct Tape {
@@ -740,6 +745,124 @@ int build_coarse_inverse(lbe_ctx *c, const std::vector<uint8_t> &solid) {
   return LBE_OK;
 }
 
+// Independent groups of the small levels (batched systems): when, on every
+// level the one-work-group kernel handles, the fluid cells of each system lie
+// in a cyclic index range of their own (the ranges may wrap through the
+// periodic boundary), no fluid cell has a fluid cell of another system among
+// its 26 neighbours (so neither the stencil nor the prolongation couples two
+// systems, and the exact coarsest solve is block-diagonal by system), each
+// system's part of the V-cycle is computed by a work-group of its own, all in
+// one launch.  The ranges are widened over the solid cells after them so
+// that they tile every level.  The table holds, per level and group, the
+// first cell and the length of its range, and for the exact solve the first
+// fluid row and the row count.  The arithmetic of every cell is that of one
+// work-group doing everything (the exact solve skips only columns that are
+// exact zeros), so the results are the same bit for bit.
+int plan_small_groups(lbe_ctx *c) {
+  MgSmall &S = c->mg_small;
+  S.ngroups = 1;
+  S.groups = nullptr;
+  {
+    const char *ng = getenv("LBE_NO_SMALL_GROUPS");  // one work-group (same results)
+    if (ng && *ng && *ng != '0') return LBE_OK;
+  }
+  const int k0 = c->mg_small_from, L = (int)c->mg.size();
+  for (int k = k0; k < L; ++k)
+    if (c->mg[k].solid_h.size() != (size_t)c->mg[k].lv.n) return LBE_OK;
+  // systems present on the first small level
+  const lbe_ctx::MgDev &F = c->mg[k0];
+  std::vector<int> gid(LBE_MAX_SYSTEMS, -1);
+  int G = 0;
+  for (int r = 0; r < F.lv.n; ++r)
+    if (!F.solid_h[r] && gid[F.sys_h[r]] < 0) gid[F.sys_h[r]] = G++;
+  if (G < 2) return LBE_OK;
+  // per level and group: first cell and length; then the exact solve's rows
+  std::vector<int> table((size_t)(S.nlev + 1) * G * 2, 0);
+  for (int k = k0; k < L; ++k) {
+    const lbe_ctx::MgDev &D = c->mg[k];
+    const MgLevel &lv = D.lv;
+    const int n = lv.n;
+    std::vector<std::vector<int>> cells(G);
+    for (int r = 0; r < n; ++r) {
+      if (D.solid_h[r]) continue;
+      const int g = gid[D.sys_h[r]];
+      if (g < 0) return LBE_OK;
+      cells[g].push_back(r);
+      const int z = r / lv.nxy, y = (r - z * lv.nxy) / lv.nx, x = r - z * lv.nxy - y * lv.nx;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int rn = wrap(x + dx, lv.nx) + lv.nx * (wrap(y + dy, lv.ny) + lv.ny * wrap(z + dz, lv.nz));
+            if (!D.solid_h[rn] && D.sys_h[rn] != D.sys_h[r]) return LBE_OK;
+          }
+    }
+    // each group's smallest cyclic interval: the complement of the largest
+    // gap between its cells
+    std::vector<int> owner(n, -1), st(G, -1);
+    std::vector<std::pair<int, int>> starts;
+    for (int g = 0; g < G; ++g) {
+      const std::vector<int> &v = cells[g];
+      if (v.empty()) continue;
+      const int m = (int)v.size();
+      int best = 0, gap = v[0] + n - v[m - 1];
+      for (int i = 0; i + 1 < m; ++i)
+        if (v[i + 1] - v[i] > gap) {
+          gap = v[i + 1] - v[i];
+          best = i + 1;
+        }
+      const int s0 = v[best], len = n - gap + 1;
+      for (int i = 0; i < len; ++i) {
+        const int r = (s0 + i) % n;
+        if (owner[r] >= 0) return LBE_OK;  // two systems interleave
+        owner[r] = g;
+      }
+      st[g] = s0;
+      starts.push_back({s0, g});
+    }
+    // widen each range up to the next one (cyclically), so that they tile
+    std::sort(starts.begin(), starts.end());
+    int *row = table.data() + (size_t)(k - k0) * G * 2;
+    const int np = (int)starts.size();
+    for (int i = 0; i < np; ++i) {
+      const int s0 = starts[i].first, g = starts[i].second;
+      const int s1 = starts[(i + 1) % np].first;
+      row[2 * g] = s0;
+      row[2 * g + 1] = np == 1 ? n : ((s1 - s0) % n + n) % n;
+    }
+    (void)st;
+  }
+  // the exact solve's rows: the fluid cells of the coarsest level in each
+  // group's range, a cyclic range of fluid indices (fluid cells in cell order)
+  if (S.ainv) {
+    const lbe_ctx::MgDev &D = c->mg[L - 1];
+    const int n = D.lv.n;
+    std::vector<int> fidx(n, -1);
+    int nf = 0;
+    for (int r = 0; r < n; ++r)
+      if (!D.solid_h[r]) fidx[r] = nf++;
+    if (nf != S.nf) return LBE_OK;
+    const int *crow = table.data() + (size_t)(S.nlev - 1) * G * 2;
+    int *frow = table.data() + (size_t)S.nlev * G * 2;
+    for (int g = 0; g < G; ++g) {
+      int f0 = -1, cnt = 0;
+      for (int i = 0; i < crow[2 * g + 1]; ++i) {
+        const int r = (crow[2 * g] + i) % n;
+        if (fidx[r] < 0) continue;
+        if (f0 < 0) f0 = fidx[r];
+        ++cnt;
+      }
+      frow[2 * g] = f0 < 0 ? 0 : f0;
+      frow[2 * g + 1] = cnt;
+    }
+  }
+  HIPCHK(c, hipMalloc((void **)&c->mg_groups, sizeof(int) * table.size()));
+  HIPCHK(c, hipMemcpy(c->mg_groups, table.data(), sizeof(int) * table.size(),
+                      hipMemcpyHostToDevice));
+  S.ngroups = G;
+  S.groups = c->mg_groups;
+  return LBE_OK;
+}
+
 // Choose the first level, of at most 2048 cells, from which the rest of the
 // hierarchy fits in one work-group's LDS (correction and right-hand side per
 // cell in T, flag words).  Larger levels are faster as multi-block kernels.
@@ -803,7 +926,7 @@ int plan_small_levels(lbe_ctx *c) {
     c->mg_small = S;
     c->mg_small_from = from;
     c->mg_small_lds = total;
-    return LBE_OK;
+    return plan_small_groups(c);
   }
   return LBE_OK;
 }
@@ -816,8 +939,12 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
   for (size_t r = 0; r < solid.size(); ++r) solid[r] = type[r] != 0;
   std::vector<uint16_t> sys = c->sys_h;
   lbe_ctx::MgDev l0;
-  l0.lv = make_level(nx, ny, nz, c->L.selfm, 1.0, c->L.wall);
+  l0.lv = make_level(nx, ny, nz, c->L.selfm, 1.0, c->L.wall, c->L.xcd);
   l0.mask = c->mask;
+  if (l0.lv.n <= MG_GROUP_SCAN) {
+    l0.solid_h = solid;
+    l0.sys_h = sys.empty() ? std::vector<uint16_t>(solid.size(), 0) : sys;
+  }
   HIPCHK(c, hipMalloc(&l0.e, esz * l0.lv.n));
   HIPCHK(c, hipMalloc(&l0.e2, esz * l0.lv.n));
   HIPCHK(c, hipMalloc(&l0.r, esz * l0.lv.n));
@@ -836,13 +963,17 @@ int build_multigrid(lbe_ctx *c, const uint8_t *type, bool only_top) {
     if (c->mg_jacobi == 0.0 && !colouring_ok(cx, cy, cz, cs)) break;
     h2 *= 4.0;
     lbe_ctx::MgDev L;
-    L.lv = make_level(cx, cy, cz, level_selfm(cx, cy, cz), h2, c->L.wall);
+    L.lv = make_level(cx, cy, cz, level_selfm(cx, cy, cz), h2, c->L.wall, c->L.xcd);
     L.tr = MgTransfer{c->mg.back().lv, L.lv, ox, oy, oz};
     const std::vector<uint32_t> m = level_mask(cx, cy, cz, cs);
     HIPCHK(c, hipMalloc((void **)&L.mask, sizeof(uint32_t) * m.size()));
     L.own_mask = true;
     c->mg.push_back(L);  // owned from here on, freed with the context
     lbe_ctx::MgDev &B = c->mg.back();
+    if (B.lv.n <= MG_GROUP_SCAN) {
+      B.solid_h = cs;
+      B.sys_h = csy;
+    }
     HIPCHK(c, hipMemcpy(B.mask, m.data(), sizeof(uint32_t) * m.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMalloc(&B.e, esz * B.lv.n));
     HIPCHK(c, hipMalloc(&B.e2, esz * B.lv.n));
@@ -1494,6 +1625,7 @@ void free_ctx(lbe_ctx *c) {
   if (c->unit_exec) (void)hipGraphExecDestroy(c->unit_exec);
   if (c->mg_ainv) (void)hipFree(c->mg_ainv);
   if (c->mg_fcell) (void)hipFree(c->mg_fcell);
+  if (c->mg_groups) (void)hipFree(c->mg_groups);
   if (c->hpin) (void)hipHostFree(c->hpin);
   if (c->ctl_h) (void)hipHostFree(c->ctl_h);
   if (c->ctl_pub) (void)hipHostFree(c->ctl_pub);
@@ -1692,6 +1824,11 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
   c->L.n = (int)N;
   c->L.selfm = g.selfm;
   c->L.wall = (p.flags & LBE_NAIVE_DIRICHLET) ? 1.0 : 2.0;
+  {
+    // stencil kernels give each die a contiguous run of blocks (same results)
+    const char *nx = getenv("LBE_NO_XCD_MAP");
+    c->L.xcd = (nx && *nx && *nx != '0') ? 0 : 1;
+  }
   c->P.K = K;
   for (int k = 0; k < K; ++k) {
     c->P.z[k] = p.z[k];

@@ -34,12 +34,17 @@ constexpr uint32_t SYS_MASK = 0x1fffu;
 constexpr int MAX_SYSTEMS = 8192;
 __host__ __device__ inline int system_of(uint32_t m) { return (int)((m >> SYS_SHIFT) & SYS_MASK); }
 
+// Accelerator complex dies (XCDs) of the part, each with its own L2; the
+// hardware hands out the blocks of a launch round-robin over them.
+constexpr int NXCD = 8;
+
 struct Lattice {
   int nx, ny, nz;
   int nxy;
   int n;            // sites
   uint32_t selfm;   // bit (i-1) set when link i maps a node onto itself
   double wall;      // factor on a solid-fluid link: 2 (Eq. 15) or 1 (first-order scheme)
+  int xcd;          // 1: stencil kernels give each XCD a contiguous run of blocks
 };
 
 // Physical constants of one context, passed by value to the kernels.
@@ -67,11 +72,13 @@ struct MgLevel {
   double h2, inv_h2;
   double wall;      // as Lattice::wall
   double rnx, rnxy; // 1 / nx and 1 / nxy: cell coordinates by multiplication
+  int xcd;          // as Lattice::xcd
 };
 
-inline MgLevel make_level(int nx, int ny, int nz, uint32_t selfm, double h2, double wall) {
+inline MgLevel make_level(int nx, int ny, int nz, uint32_t selfm, double h2, double wall,
+                          int xcd) {
   return MgLevel{nx, ny, nz, nx * ny, nx * ny * nz, selfm, h2, 1.0 / h2, wall,
-                 1.0 / nx, 1.0 / ((double)nx * ny)};
+                 1.0 / nx, 1.0 / ((double)nx * ny), xcd};
 }
 
 // Fine level f -> coarse level c: coarse cell (X, Y, Z) holds the fine cells
@@ -114,6 +121,7 @@ struct KrylovCtl {
 // The coarse end of the hierarchy handled by one work-group in LDS.
 constexpr int MG_MAX_SMALL = 8;
 constexpr int MG_MAX_DENSE = 512;         // largest coarsest level solved with a dense inverse
+constexpr int MG_GROUP_SCAN = 1 << 16;    // levels up to this size keep host copies of their cells
 struct MgSmall {
   int nlev;                               // levels in the set; the last is the coarsest
   MgLevel lv[MG_MAX_SMALL];
@@ -129,6 +137,13 @@ struct MgSmall {
   int coarse_sweeps;
   double omega;
   double jacobi;                          // > 0: Jacobi smoothing with this weight, else GS
+  // independent groups, one work-group each (batched systems):
+  // groups[2 (k G + g)] and groups[2 (k G + g) + 1] are the first cell and the
+  // length of group g's cyclic range on level k; row k = nlev holds the first
+  // fluid row and the row count of the group in the exact solve; null: one
+  // group, whole levels
+  int ngroups;
+  const int *groups;
 };
 
 enum KernelKind {

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(TB) void k_fluid_f64(Lattice L, Phys P,
                                                      double *__restrict__ fout,
                                                      double *__restrict__ u,
                                                      double *__restrict__ nstar) {
-  const int r = blockIdx.x * TB + threadIdx.x;
+  const int r = xcd_block(blockIdx.x, gridDim.x, TB, L.nxy, L.xcd) * TB + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
   if (m & SOLID_BIT) return;
@@ -239,7 +239,8 @@ __global__ __launch_bounds__(BLOCK) void k_resid_f64(Lattice L, const uint32_t *
                                                      const SolveCtl *__restrict__ ctl) {
   __shared__ double sm[BLOCK / WAVE];
   if (ctl->done) return;
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int lb = xcd_block(blockIdx.x, gridDim.x, BLOCK, L.nxy, L.xcd);
+  const int r = lb * BLOCK + threadIdx.x;
   double a = 0.0;
   if (r < L.n) {
     const uint32_t m = mask[r];
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(BLOCK) void k_resid_f64(Lattice L, const uint32_t *
     }
   }
   a = block_max(a, sm);
-  if (threadIdx.x == 0) partial[blockIdx.x] = a;
+  if (threadIdx.x == 0) partial[lb] = a;
 }
 
 // ---- electrode charge (Eq. 16): Q_e = -(6/4 pi l_B) sum over the electrode's

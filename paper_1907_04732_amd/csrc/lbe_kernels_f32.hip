@@ -66,7 +66,7 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
                                                      float *__restrict__ hout,
                                                      float *__restrict__ u,
                                                      float *__restrict__ nustar) {
-  const int r = blockIdx.x * TB + threadIdx.x;
+  const int r = xcd_block(blockIdx.x, gridDim.x, TB, L.nxy, L.xcd) * TB + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
   if (m & SOLID_BIT) return;

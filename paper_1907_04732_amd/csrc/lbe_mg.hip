@@ -130,7 +130,8 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
                                                        KrylovCtl *__restrict__ kc, T jacobi) {
   __shared__ double sm[BLOCK / WAVE];
   if (ctl->done) return;
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int lb = xcd_block(blockIdx.x, gridDim.x, BLOCK, lv.nxy, lv.xcd);
+  const int r = lb * BLOCK + threadIdx.x;
   if (kc && r == 0) kc->first = 1;  // a new Krylov sequence starts from this residual
   double a = 0.0;
   if (r < lv.n) {
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
     if (r64) r64[r] = R;
   }
   a = block_max(a, sm);
-  if (threadIdx.x == 0) partial[blockIdx.x] = a;
+  if (threadIdx.x == 0) partial[lb] = a;
 }
 
 // ---- flexible conjugate gradients around the V-cycle -------------------------
@@ -225,7 +226,8 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_apply(MgLevel lv, const uint32_t 
                                                      const SolveCtl *__restrict__ ctl) {
   __shared__ double sm[BLOCK / WAVE];
   if (ctl->done) return;
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
+  const int lb = xcd_block(blockIdx.x, gridDim.x, BLOCK, lv.nxy, lv.xcd);
+  const int r = lb * BLOCK + threadIdx.x;
   double pq = 0.0, rp = 0.0;
   if (r < lv.n) {
     const Coords c = coords_of(r, lv);
@@ -241,9 +243,9 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_apply(MgLevel lv, const uint32_t 
     }
   }
   pq = block_sum(pq, sm);
-  if (threadIdx.x == 0) partial[blockIdx.x] = pq;
+  if (threadIdx.x == 0) partial[lb] = pq;
   rp = block_sum(rp, sm);
-  if (threadIdx.x == 0) partial[gridDim.x + blockIdx.x] = rp;
+  if (threadIdx.x == 0) partial[gridDim.x + lb] = rp;
 }
 
 __global__ __launch_bounds__(FINAL) void k_fcg_alpha(const double *__restrict__ partial, int nb,
@@ -466,9 +468,10 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_tiled(MgTransfer tr,
   __shared__ T sv[BLOCK];
   __shared__ int sc[BLOCK];
   if (ctl->done) return;
+  const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
   const int t = threadIdx.x;
   const int fx = t & (2 * RT_X - 1), fy = (t / (2 * RT_X)) & (2 * RT_Y - 1), fz = t / (4 * RT_X * RT_Y);
-  const int X = blockIdx.x * RT_X + (fx >> 1), Y = blockIdx.y * RT_Y + (fy >> 1), Z = blockIdx.z;
+  const int X = bx * RT_X + (fx >> 1), Y = by * RT_Y + (fy >> 1), Z = bz;
   T v = T(0);
   int cnt = 0;
   if (X < tr.c.nx && Y < tr.c.ny) {
@@ -481,7 +484,7 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_tiled(MgTransfer tr,
   __syncthreads();
   if (t >= RT_X * RT_Y) return;
   const int cx = t % RT_X, cy = t / RT_X;
-  const int Xo = blockIdx.x * RT_X + cx, Yo = blockIdx.y * RT_Y + cy;
+  const int Xo = bx * RT_X + cx, Yo = by * RT_Y + cy;
   if (Xo >= tr.c.nx || Yo >= tr.c.ny) return;
   // child (a, b, d) of coarse cell (cx, cy) sits at thread
   // (2 cx + a) + 2 RT_X (2 cy + b) + 4 RT_X RT_Y d
@@ -496,7 +499,7 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_tiled(MgTransfer tr,
   }
   const T sum = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
   const int cn = ((n[0] + n[1]) + (n[2] + n[3])) + ((n[4] + n[5]) + (n[6] + n[7]));
-  const int R = Xo + tr.c.nx * (Yo + tr.c.ny * blockIdx.z);
+  const int R = Xo + tr.c.nx * (Yo + tr.c.ny * bz);
   const uint32_t m = mc[R];
   const bool fluid = !(m & SOLID_BIT);
   const T rv = (fluid && cn) ? sum / T(cn) : T(0);
@@ -688,8 +691,16 @@ __global__ __launch_bounds__(BLOCK) void k_coarse_dense(int nf, const T *__restr
 constexpr int SMALL_BLOCK = 1024;
 static_assert(SMALL_BLOCK == DENSE_T, "the dense solve splits one work-group's threads");
 
+// A work-group's cells of a level: the cyclic range of len cells from start
+// (start 0 and the whole level for one group).
+__device__ __forceinline__ int range_cell(int start, int i, int n) {
+  const int r = start + i;
+  return r < n ? r : r - n;
+}
+
 template <class T>
-__device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const uint32_t *sm) {
+__device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const uint32_t *sm,
+                             int start, int len) {
   const MgLevel &lv = S.lv[k];
   T *e = lds + S.off_e[k];
   const T *rh = lds + S.off_r[k];
@@ -704,7 +715,8 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
       {
         const T *xi = (s & 1) ? e2 : e;
         T *xo = (s & 1) ? e : e2;
-        for (int r = threadIdx.x; r < lv.n; r += SMALL_BLOCK) {
+        for (int i = threadIdx.x; i < len; i += SMALL_BLOCK) {
+          const int r = range_cell(start, i, lv.n);
           const uint32_t m = mk[r];
           if (m & SOLID_BIT) {
             xo[r] = T(0);
@@ -728,7 +740,10 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
       }
     }
     if (sweeps & 1) {
-      for (int r = threadIdx.x; r < lv.n; r += SMALL_BLOCK) e[r] = e2[r];
+      for (int i = threadIdx.x; i < len; i += SMALL_BLOCK) {
+        const int r = range_cell(start, i, lv.n);
+        e[r] = e2[r];
+      }
       __syncthreads();
     }
     return;
@@ -746,6 +761,7 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
         c.y = 2 * iy + (((col >> 1) ^ c.z) & 1);
         if (c.x >= lv.nx || c.y >= lv.ny) continue;
         const int r = c.x + lv.nx * (c.y + lv.ny * c.z);
+        if (((r - start) % lv.n + lv.n) % lv.n >= len) continue;  // another group's cell
         const uint32_t m = mk[r];
         if (m & SOLID_BIT) continue;
         T v[NQ];
@@ -773,24 +789,36 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_mg_small(MgSmall S, const T *__
   if (ctl->done) return;
   T *lds = reinterpret_cast<T *>(smem_raw);
   uint32_t *sm = reinterpret_cast<uint32_t *>(smem_raw);  // flag words, offsets in 4-byte units
-  // flags of every level, rhs and zero correction of the first
+  // this work-group's group: a range of cells on every level (whole levels
+  // when there is one group)
+  const int G = S.ngroups, g = blockIdx.x;
+  auto first = [&](int k) { return S.groups ? S.groups[2 * (k * G + g)] : 0; };
+  auto count = [&](int k) { return S.groups ? S.groups[2 * (k * G + g) + 1] : S.lv[k].n; };
+  // flags of every level; with several groups every correction and
+  // right-hand side starts at zero, so that cells of other groups (never
+  // written here) read as the solid cells between them
   for (int k = 0; k < S.nlev; ++k)
     for (int r = threadIdx.x; r < S.lv[k].n; r += SMALL_BLOCK) sm[S.off_m[k] + r] = S.mask[k][r];
-  for (int r = threadIdx.x; r < S.lv[0].n; r += SMALL_BLOCK) {
+  if (S.groups)
+    for (int i = threadIdx.x; i < S.off_x; i += SMALL_BLOCK) lds[i] = T(0);
+  __syncthreads();
+  // rhs and zero correction of the first level
+  for (int i = threadIdx.x; i < count(0); i += SMALL_BLOCK) {
+    const int r = range_cell(first(0), i, S.lv[0].n);
     lds[S.off_r[0] + r] = r_in[r];
     lds[S.off_e[0] + r] = T(0);
   }
   __syncthreads();
   // down: smooth, restrict (eight lanes per coarse cell, as k_restrict)
   for (int k = 0; k + 1 < S.nlev; ++k) {
-    small_smooth<T>(S, k, S.nu1, lds, sm);
+    small_smooth<T>(S, k, S.nu1, lds, sm, first(k), count(k));
     const MgTransfer &tr = S.tr[k + 1];
     const T *ef = lds + S.off_e[k];
     const T *rf = lds + S.off_r[k];
     const uint32_t *mf = sm + S.off_m[k];
     const uint32_t *mc = sm + S.off_m[k + 1];
-    for (int t = threadIdx.x; t < 8 * tr.c.n; t += SMALL_BLOCK) {
-      const int R = t >> 3, j = t & 7;
+    for (int t = threadIdx.x; t < 8 * count(k + 1); t += SMALL_BLOCK) {
+      const int R = range_cell(first(k + 1), t >> 3, tr.c.n), j = t & 7;
       const bool fluid = !(mc[R] & SOLID_BIT);
       T v = T(0);
       int cnt = 0;
@@ -810,26 +838,48 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_mg_small(MgSmall S, const T *__
     const T *rh = lds + S.off_r[k];
     if (S.ainv) {
       // compact right-hand side over the fluid cells, then the part sums of
-      // every row (k_coarse_dense's arithmetic) through LDS
+      // every row (k_coarse_dense's arithmetic) through LDS; a group's rows
+      // and columns are its own fluid cells (the inverse is block-diagonal
+      // by group), so the columns of other groups, exact zeros, are skipped
       const T *ainv = reinterpret_cast<const T *>(S.ainv);
+      // the group's rows: a cyclic range of fluid indices; its columns, in
+      // increasing order, are one run or (through the wrap) two
+      const int nf = S.nf;
+      const int f0 = S.groups ? S.groups[2 * (S.nlev * G + g)] : 0;
+      const int ng = S.groups ? S.groups[2 * (S.nlev * G + g) + 1] : nf;
+      const int wrapped = f0 + ng > nf ? f0 + ng - nf : 0;  // columns [0, wrapped)
+      const int f1 = f0 + ng - wrapped;                       // and [f0, f1)
       T *xc = lds + S.off_x;
-      T *psum = xc + S.nf;  // DENSE_T entries
-      for (int j = threadIdx.x; j < S.nf; j += SMALL_BLOCK) xc[j] = rh[S.fcell[j]];
-      __syncthreads();
-      const int parts = DENSE_T / S.nf;
-      {
-        const int row = threadIdx.x % S.nf, part = threadIdx.x / S.nf;
-        if (part < parts) psum[part * S.nf + row] = dense_part(S.nf, parts, ainv, xc, row, part);
+      T *psum = xc + nf;  // DENSE_T entries
+      for (int i = threadIdx.x; i < ng; i += SMALL_BLOCK) {
+        const int j = range_cell(f0, i, nf);
+        xc[j] = rh[S.fcell[j]];
       }
       __syncthreads();
-      for (int row = threadIdx.x; row < S.nf; row += SMALL_BLOCK) {
+      const int parts = DENSE_T / nf;
+      if (ng > 0) {
+        const int row = range_cell(f0, threadIdx.x % ng, nf), part = threadIdx.x / ng;
+        if (part < parts) {
+          // the columns j = part (mod parts) of the row in increasing order
+          T acc = T(0);
+#pragma unroll 8
+          for (int j = part; j < wrapped; j += parts) acc += ainv[(size_t)j * nf + row] * xc[j];
+          const int j0 = f0 + ((part - f0) % parts + parts) % parts;
+#pragma unroll 8
+          for (int j = j0; j < f1; j += parts) acc += ainv[(size_t)j * nf + row] * xc[j];
+          psum[part * nf + row] = acc;
+        }
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < ng; i += SMALL_BLOCK) {
+        const int row = range_cell(f0, i, nf);
         T v = psum[row];
-        for (int p = 1; p < parts; ++p) v += psum[p * S.nf + row];
+        for (int p = 1; p < parts; ++p) v += psum[p * nf + row];
         e[S.fcell[row]] = v;
       }
       __syncthreads();
     } else {
-      small_smooth<T>(S, k, S.coarse_sweeps, lds, sm);
+      small_smooth<T>(S, k, S.coarse_sweeps, lds, sm, first(k), count(k));
     }
   }
   // up: prolong, smooth
@@ -839,15 +889,19 @@ __global__ __launch_bounds__(SMALL_BLOCK) void k_mg_small(MgSmall S, const T *__
     T *ef = lds + S.off_e[k];
     const uint32_t *mf = sm + S.off_m[k];
     const uint32_t *mc = sm + S.off_m[k + 1];
-    for (int r = threadIdx.x; r < tr.f.n; r += SMALL_BLOCK) {
+    for (int i = threadIdx.x; i < count(k); i += SMALL_BLOCK) {
+      const int r = range_cell(first(k), i, tr.f.n);
       if (mf[r] & SOLID_BIT) continue;
       const T e0 = ef[r];
       ef[r] = e0 + prolong_value<T>(tr, r, mc, ec);
     }
     __syncthreads();
-    small_smooth<T>(S, k, S.nu2, lds, sm);
+    small_smooth<T>(S, k, S.nu2, lds, sm, first(k), count(k));
   }
-  for (int r = threadIdx.x; r < S.lv[0].n; r += SMALL_BLOCK) e_out[r] = lds[S.off_e[0] + r];
+  for (int i = threadIdx.x; i < count(0); i += SMALL_BLOCK) {
+    const int r = range_cell(first(0), i, S.lv[0].n);
+    e_out[r] = lds[S.off_e[0] + r];
+  }
 }
 
 // ---- phi += e --------------------------------------------------------------
@@ -988,7 +1042,8 @@ hipError_t prepare_mg_small(size_t lds_bytes) {
 template <class T>
 hipError_t launch_mg_small(hipStream_t s, const MgSmall &S, size_t lds_bytes, const T *r_in,
                            T *e_out, const SolveCtl *ctl) {
-  hipLaunchKernelGGL(k_mg_small<T>, dim3(1), dim3(SMALL_BLOCK), lds_bytes, s, S, r_in, e_out, ctl);
+  hipLaunchKernelGGL(k_mg_small<T>, dim3(S.ngroups), dim3(SMALL_BLOCK), lds_bytes, s, S, r_in,
+                     e_out, ctl);
   return hipGetLastError();
 }
 

@@ -129,3 +129,29 @@ def test_batch_reverse_mode(precision):
     assert rel(gr["phi_s"][sl], ga["phi_s"]) <= tol
     assert rel(gr["n"][:, sl], ga["n"]) <= tol
     assert abs(gr["lB"] - ga["lB"]) <= tol * abs(ga["lB"])
+
+
+@pytest.mark.parametrize("krylov", [False, True])
+@pytest.mark.parametrize("precision", [lbe.FP64, lbe.FP32_MIXED])
+def test_small_levels_split_by_system_same_results(precision, krylov, monkeypatch):
+    """On the coarse levels that one work-group handles in LDS, independent
+    systems (no fluid cell next to another system's, the exact coarsest solve
+    block-diagonal) get a work-group each; every cell's arithmetic is that of
+    one work-group doing all of them, so a run with the split (the default)
+    and one without (LBE_NO_SMALL_GROUPS=1) must agree bit for bit.  24
+    systems of 8 x 8 x L (L 16..64; the small levels are 1 x 1 columns whose
+    systems wrap through the periodic boundary on some levels)."""
+    b = W.batch_slabs(nsys=24, nxy=8, Lmin=16, Lmax=64, seed=11)
+    flags = lbe.EXTRAPOLATE | (lbe.KRYLOV if krylov else 0)
+    out = []
+    for off in ("0", "1"):
+        monkeypatch.setenv("LBE_NO_SMALL_GROUPS", off)
+        g = gpu_batch(b, tol=1e-11, max_iter=400, precision=precision, poisson=lbe.MG,
+                      flags=flags)
+        g.step(8)
+        out.append((g.fields(), g.qhist(), g.totals()["poisson_total"]))
+        g.close()
+    (fa, qa, ia), (fb, qb, ib) = out
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    assert np.array_equal(qa, qb) and ia == ib

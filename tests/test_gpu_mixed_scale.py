@@ -5,10 +5,10 @@ configurations' full size and length.
    the finest multigrid level and the one below it run in the global
    kernels (more than 2048 cells on each; the coarser levels go to the
    one-work-group kernel): a 16 x 16 x 130 lateral crop of the
-   electro-osmosis slab with Jacobi V(1,1) on every level and the quadratic
-   warm start, and a 40 x 40 x 16 coaxial cell and a 32^3 crop of the porous
-   electrode with V(2,2), Krylov acceleration and the quadratic warm start,
-   all at tol 1e-10: exactly the launch configuration bench.py times.  The
+   electro-osmosis slab, a 40 x 40 x 16 coaxial cell and a 32^3 crop of the
+   porous electrode, each with the multigrid cycle, Krylov setting and
+   quadratic warm start bench.py uses for the workload it comes from, at tol
+   1e-10: exactly the launch configuration bench.py times.  The
    oracle runs its SOR (four colours, diagonal-normalised, omega 1.95: only
    the iterates depend on omega, not the fixed point) to 1e-12 on many
    threads (its OpenMP build is bit for bit the single-threaded one).
@@ -65,11 +65,14 @@ def check(errs):
     assert errs["n"] <= N_BAR, errs
 
 
+# the solver settings bench.py uses for the workload each crop comes from
+SETTINGS = {k: v[1] for k, v in bench.WORKLOADS.items()}
 CROPS = {
-    "eo_slab_16x16x130": lambda: (W.eo_slab(noise=True, nx=16, ny=16), dict(light=True), 200),
+    "eo_slab_16x16x130": lambda: (W.eo_slab(noise=True, nx=16, ny=16),
+                                  SETTINGS["eo_slab_64x64x130"], 200),
     "coaxial_40x40x16": lambda: (W.coaxial(noise=True, nx=40, ny=40, nz=16, R1=4.0, R2=18.0),
-                                 dict(krylov=True), 200),
-    "porous_crop_32^3": lambda: (W.porous_crop(n=32), dict(krylov=True), 120),
+                                 SETTINGS["coaxial_160x160x64"], 200),
+    "porous_crop_32^3": lambda: (W.porous_crop(n=32), SETTINGS["porous_electrode_192^3"], 120),
 }
 
 
@@ -92,9 +95,10 @@ def test_mixed_at_bench_settings_matches_oracle(name):
 
 
 FULL = {
-    "eo_slab_64x64x130": lambda: (W.eo_slab(noise=True), dict(light=True), 5000),
-    "coaxial_160x160x64": lambda: (W.coaxial(noise=True), dict(krylov=True), 3000),
-    "porous_electrode_192^3": lambda: (W.porous_electrode(noise=True), dict(krylov=True), 2000),
+    "eo_slab_64x64x130": lambda: (W.eo_slab(noise=True), SETTINGS["eo_slab_64x64x130"], 5000),
+    "coaxial_160x160x64": lambda: (W.coaxial(noise=True), SETTINGS["coaxial_160x160x64"], 3000),
+    "porous_electrode_192^3": lambda: (W.porous_electrode(noise=True),
+                                       SETTINGS["porous_electrode_192^3"], 2000),
 }
 
 
@@ -131,7 +135,7 @@ def test_batch_capacitance_mixed_matches_fp64():
     w = W.batch_slabs(noise=True)
     runs = {}
     for form in ("fp32", "fp64"):
-        p = bench.step_params(w, form, krylov=True)
+        p = bench.step_params(w, form, **SETTINGS["batched_96_slabs_8x8"])
         g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref.reshape(-1), system=w.system,
                     nsys=len(w.L))
         g.step(2000)
