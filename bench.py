@@ -66,7 +66,9 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False):
       out, flag word; per coarse cell: correction and flag word.  Outer
       residual: phi, source, flag word in; correction rhs and zeroed
       correction out (multigrid).  correct: phi in + out, correction, flag
-      word.
+      word.  Krylov iteration: fcg_apply gathers the V-cycle's output z
+      and reads q', p' and r, writing A z; fcg_update reads z, A z, p', q',
+      phi and r and writes p, q, phi, r and the next cycle's rhs and start.
       Reverse mode: adj_moments reads the 19 stored populations and writes
       rho and m; adj_fluid reads phi, the K concentrations, rho and m, the 19
       population adjoints and K concentration adjoints of t+1, and writes 19
@@ -94,10 +96,11 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False):
         "resid": 8 + 8 + 4,
         "mg_resid": 8 + 8 + 4 + 2 * cor,
         "correct": 16 + cor + 4,
-        "fcg_beta": cor + 8 + 4,
-        "fcg_dir": cor + 16 + 4,
-        "fcg_apply": 8 + 8 + 8 + 4,
-        "fcg_update": 8 + 8 + 16 + 16 + 2 * cor + 4,
+        # Krylov: A z and four sums (z, q', p', r in; A z out); then p, q,
+        # phi, r updated (z, A z, p', q', phi, r in; p, q, phi, r, the
+        # correction's rhs and start out)
+        "fcg_apply": cor + 8 + 8 + 8 + 4 + 8,
+        "fcg_update": cor + 8 + 8 + 8 + 16 + 16 + 8 + 8 + 2 * cor + 4,
         # reverse mode: FP64 adjoint fields, concentrations in the form's storage
         "adj_moments": 19 * pop + 32 + 4,
         "adj_fluid": 8 + K * pop + 32 + 2 * 19 * 8 + 8 * K + 24 + 24 + 4,
@@ -486,12 +489,12 @@ def _grid(row):
 # the kind of the launch before it
 KIND_OF = [("k_fluid_", "fluid"), ("k_ions_", "ions"), ("k_outer_resid", "mg_resid"),
            ("k_jacobi", "jacobi"), ("k_restrict", "mg_restrict"), ("k_prolong", "mg_prolong"),
-           ("k_mg_small", "mg_small"), ("k_fcg_dot", "fcg_beta"), ("k_fcg_dir", "fcg_dir"),
-           ("k_fcg_apply", "fcg_apply"), ("k_fcg_update", "fcg_update"), ("k_charge", "charge"),
+           ("k_mg_small", "mg_small"), ("k_fcg_az", "fcg_apply"), ("k_fcg_update", "fcg_update"),
+           ("k_charge", "charge"),
            ("k_totals", "totals"), ("k_momentum", "momentum"), ("k_observe", "observe"),
            ("k_smooth", "mg_smooth"), ("k_coarse", "mg_coarse"), ("k_correct", "correct"),
            ("k_sor", "sor"), ("k_resid", "resid")]
-SECOND_STAGE = ("k_final_resid", "k_fcg_beta", "k_fcg_alpha", "k_final_charge", "k_final_sum",
+SECOND_STAGE = ("k_final_resid", "k_fcg_coef", "k_final_charge", "k_final_sum",
                 "k_final_max")
 
 

@@ -68,6 +68,7 @@ struct lbe_ctx {
   int *iface = nullptr, *blk_elec = nullptr, *blk_begin = nullptr, *blk_end = nullptr;
   // flexible-CG state (LBE_KRYLOV): residual, direction, A direction (FP64)
   double *kr = nullptr, *kp = nullptr, *kq = nullptr;
+  double *kaz = nullptr;  // A z of the current iteration
   KrylovCtl *kc = nullptr;
   // per-system references of the mixed form (device tables) and each node's system
   std::vector<uint16_t> sys_h;
@@ -1102,25 +1103,16 @@ int mg_solve(lbe_ctx *c, bool learn) {
             T *z = nullptr;
             int rc = mg_vcycle<T>(c, 0, &z, nullptr, nullptr, first_sweep > 0.0);
             if (rc) return rc;
-            rc = run(c, KK_FCG_BETA, n, [&] {
-              return launch_fcg_beta<T>(c->stream, n, c->mask, (const T *)z, c->kq, c->partial,
-                                        c->kc, c->ctl);
-            });
-            if (rc) return rc;
-            rc = run(c, KK_FCG_DIR, n, [&] {
-              return launch_fcg_dir<T>(c->stream, n, c->mask, (const T *)z, c->kp, c->kc, c->ctl);
-            });
-            if (rc) return rc;
             rc = run(c, KK_FCG_APPLY, n, [&] {
-              return launch_fcg_apply(c->stream, L0.lv, c->mask, c->kp, c->kr, c->kq, c->partial,
-                                      c->kc, c->ctl);
+              return launch_fcg_apply<T>(c->stream, L0.lv, c->mask, (const T *)z, c->kq, c->kp,
+                                         c->kr, c->kaz, c->partial, c->kc, c->ctl);
             });
             if (rc) return rc;
             // every iteration ends with its own stop check (one cycle each)
             rc = run(c, KK_FCG_UPDATE, n, [&] {
-              return launch_fcg_update<T>(c->stream, n, c->mask, c->kp, c->kq, c->phi, c->kr,
-                                          (T *)L0.r, (T *)L0.e, c->partial, c->kc, c->ctl, 1,
-                                          L0.lv, first_sweep);
+              return launch_fcg_update<T>(c->stream, n, c->mask, (const T *)z, c->kaz, c->kp,
+                                          c->kq, c->phi, c->kr, (T *)L0.r, (T *)L0.e, c->partial,
+                                          c->kc, c->ctl, 1, L0.lv, first_sweep);
             });
             if (rc) return rc;
           }
@@ -1610,7 +1602,7 @@ void free_ctx(lbe_ctx *c) {
                   c->h32[0], c->h32[1], c->nu32[0], c->nu32[1], c->u32, c->obs,
                   c->partial, c->dout, c->ctl, c->iface, c->blk_elec, c->blk_begin,
                   c->blk_end, c->qcur, c->qhist, c->solid_idx, c->solid_val,
-                  c->nref_d_tab, c->qref_tab, c->nref_f_tab, c->kr, c->kp, c->kq, c->kc,
+                  c->nref_d_tab, c->qref_tab, c->nref_f_tab, c->kr, c->kp, c->kq, c->kaz, c->kc,
                   c->tape.ck, c->tape.seg, c->abar[0], c->abar[1], c->nbar[0], c->nbar[1],
                   c->fbar, c->adj_u, c->lam, c->lam_sum, c->gphis, c->src_keep, c->qbar_d,
                   c->lb_acc, c->type_d};
@@ -1899,7 +1891,8 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
   {
     const int nres = residual_blocks(c->L);
     const int ntot = totals_blocks(c->L) * (2 + K);
-    const int npart = std::max({nres, ntot, (int)g.blk_elec.size(), 1});
+    // the Krylov iteration's four sums take 4 partials per block
+    const int npart = std::max({nres, ntot, 4 * totals_blocks(c->L), (int)g.blk_elec.size(), 1});
     TRY(dalloc(c, &c->mask, N));
     TRY(dalloc(c, &c->phi, N));
     TRY(dalloc(c, &c->src, N));
@@ -2033,9 +2026,11 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     TRY(dalloc(c, &c->kr, N));
     TRY(dalloc(c, &c->kp, N));
     TRY(dalloc(c, &c->kq, N));
+    TRY(dalloc(c, &c->kaz, N));
     TRY(dalloc(c, &c->kc, 1));
     if (hipMemsetAsync(c->kp, 0, sizeof(double) * N, c->stream) != hipSuccess ||
         hipMemsetAsync(c->kq, 0, sizeof(double) * N, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->kaz, 0, sizeof(double) * N, c->stream) != hipSuccess ||
         hipMemsetAsync(c->kc, 0, sizeof(KrylovCtl), c->stream) != hipSuccess) {
       rc = fail(c, LBE_EDEVICE, "memset failed");
       goto fail_;

@@ -163,10 +163,8 @@ enum KernelKind {
   KK_MG_PROLONG,  // trilinear prolongation + correction
   KK_MG_COARSE,   // coarsest-level solve in one work-group
   KK_MG_SMALL,    // the coarse levels of a V-cycle in one work-group
-  KK_FCG_BETA,    // Krylov: (z, q_prev) and beta
-  KK_FCG_DIR,     // Krylov: p = z + beta p
-  KK_FCG_APPLY,   // Krylov: q = A p, (p, q), (r, p), alpha
-  KK_FCG_UPDATE,  // Krylov: phi += alpha p, r -= alpha q, stop check
+  KK_FCG_APPLY,   // Krylov: A z and the sums that give beta and alpha
+  KK_FCG_UPDATE,  // Krylov: p, q = A p, phi += alpha p, r -= alpha q, stop check
   KK_ADJ_FLUID,   // reverse step: streaming, collision and velocity adjoints
   KK_ADJ_IONS,    // reverse step: link-flux and force adjoints, Poisson-adjoint source
   KK_ADJ_FOLD,    // reverse step: fold the Poisson adjoint into the ion adjoint
@@ -299,21 +297,20 @@ hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_
 //   beta = -(z, q_prev) / (p_prev, q_prev) (0 for the first direction),
 //   p = z + beta p,  q = A p,  alpha = (r, p) / (p, q),
 //   phi += alpha p,  r -= alpha q  (r also copied to r0 in T, e0 zeroed),
-// then the stop check on ||r||_inf.
+// then the stop check on ||r||_inf.  Two passes: launch_fcg_apply forms A z
+// (into az) and the sums from which beta, (p, q) = (z, A z) + 2 beta (z, q') +
+// beta^2 (p', q') and (r, p) = (r, z) + beta (r, p') follow; launch_fcg_update
+// writes p = z + beta p', q = A z + beta q', updates phi and r and checks.
 template <class T>
-hipError_t launch_fcg_beta(hipStream_t s, int n, const uint32_t *mask, const T *z,
-                           const double *q, double *partial, KrylovCtl *kc, const SolveCtl *ctl);
+hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *mask, const T *z,
+                            const double *q_prev, const double *p_prev, const double *r,
+                            double *az, double *partial, KrylovCtl *kc, const SolveCtl *ctl);
 template <class T>
-hipError_t launch_fcg_dir(hipStream_t s, int n, const uint32_t *mask, const T *z, double *p,
-                          const KrylovCtl *kc, const SolveCtl *ctl);
-hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
-                            const double *p, const double *r, double *q, double *partial,
-                            KrylovCtl *kc, const SolveCtl *ctl);
-template <class T>
-hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const double *p,
-                             const double *q, double *phi, double *r, T *r0, T *e0,
-                             double *partial, const KrylovCtl *kc, SolveCtl *ctl, int add,
-                             const MgLevel &lv, double jac);  // jac > 0: e0 gets lv's first Jacobi sweep
+hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const T *z,
+                             const double *az, double *p, double *q, double *phi, double *r,
+                             T *r0, T *e0, double *partial, const KrylovCtl *kc, SolveCtl *ctl,
+                             int add, const MgLevel &lv,
+                             double jac);  // jac > 0: e0 gets lv's first Jacobi sweep
 template <class T>
 hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int colour,
                             const uint32_t *mask, const T *rhs, T *e, const SolveCtl *ctl);

@@ -22,7 +22,7 @@ namespace lbe {
 const char *const kKernelNames[KK_COUNT] = {
     "fluid", "ions", "sor", "resid", "charge", "totals", "observe", "sor32", "correct",
     "mg_resid", "mg_smooth", "mg_smooth0", "mg_restrict", "mg_prolong", "mg_coarse", "mg_small",
-    "fcg_beta", "fcg_dir", "fcg_apply", "fcg_update", "adj_fluid", "adj_ions", "adj_fold",
+    "fcg_apply", "fcg_update", "adj_fluid", "adj_ions", "adj_fold",
     "adj_seed", "adj_moments", "rewind", "expand_n", "mg_smooth0_phi", "momentum"};
 
 namespace {

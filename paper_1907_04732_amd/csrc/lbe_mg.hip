@@ -180,95 +180,93 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
 // in FP32), so directions are A-orthogonalised against the previous one only
 // (flexible CG with one stored direction).  All scalars stay on the device.
 
-// partial sums of (a, b) over fluid sites, one per block (fixed tree order)
+// One iteration takes two passes over the finest level.  The new direction
+// is p = z + beta p' (z: the V-cycle's output for the current residual r; p',
+// q' = A p': the previous direction and its image), so its image needs no
+// stencil of its own: q = A z + beta q'.  The first pass forms A z and the
+// sums (z, q'), (z, A z), (r, z), (r, p'); from them, with beta = -(z, q') /
+// (p', q'), follow (p, q) = (z, A z) + 2 beta (z, q') + beta^2 (p', q') and
+// (r, p) = (r, z) + beta (r, p'), hence alpha = (r, p) / (p, q) (one small
+// kernel).  The second pass writes p and q, moves phi by alpha p and r by
+// -alpha q, and checks the residual.
+
 template <class T>
-__global__ __launch_bounds__(BLOCK) void k_fcg_dot(int n, const uint32_t *__restrict__ mask,
-                                                   const T *__restrict__ a,
-                                                   const double *__restrict__ b,
-                                                   double *__restrict__ partial,
-                                                   const SolveCtl *__restrict__ ctl) {
+__global__ __launch_bounds__(BLOCK) void k_fcg_az(MgLevel lv, const uint32_t *__restrict__ mask,
+                                                  const T *__restrict__ z,
+                                                  const double *__restrict__ q_prev,
+                                                  const double *__restrict__ p_prev,
+                                                  const double *__restrict__ rv,
+                                                  double *__restrict__ az,
+                                                  double *__restrict__ partial,
+                                                  const SolveCtl *__restrict__ ctl) {
   __shared__ double sm[BLOCK / WAVE];
   if (ctl->done) return;
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
-  double v = 0.0;
-  if (r < n && !(mask[r] & SOLID_BIT)) v = double(a[r]) * b[r];
-  v = block_sum(v, sm);
-  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+  const int lb = xcd_block(blockIdx.x, gridDim.x, BLOCK, lv.nxy, lv.xcd);
+  const int r = lb * BLOCK + threadIdx.x;
+  double zq = 0.0, zaz = 0.0, rz = 0.0, rp = 0.0;
+  if (r < lv.n) {
+    const Coords c = coords_of(r, lv);
+    T v[NQ];
+    gather_lv(lv, c, r, z, v);
+    const uint32_t m = mask[r];
+    if (!(m & SOLID_BIT)) {
+      double vd[NQ];
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) vd[i] = double(v[i]);
+      const double a = apply_A_v<double>(lv, m, vd);
+      az[r] = a;
+      const double rr = rv[r];
+      zq = vd[0] * q_prev[r];
+      zaz = vd[0] * a;
+      rz = rr * vd[0];
+      rp = rr * p_prev[r];
+    }
+  }
+  const int nb = gridDim.x;
+  zq = block_sum(zq, sm);
+  if (threadIdx.x == 0) partial[lb] = zq;
+  zaz = block_sum(zaz, sm);
+  if (threadIdx.x == 0) partial[nb + lb] = zaz;
+  rz = block_sum(rz, sm);
+  if (threadIdx.x == 0) partial[2 * nb + lb] = rz;
+  rp = block_sum(rp, sm);
+  if (threadIdx.x == 0) partial[3 * nb + lb] = rp;
 }
 
-__global__ __launch_bounds__(FINAL) void k_fcg_beta(const double *__restrict__ partial, int nb,
+__global__ __launch_bounds__(FINAL) void k_fcg_coef(const double *__restrict__ partial, int nb,
                                                     KrylovCtl *__restrict__ kc,
                                                     const SolveCtl *__restrict__ ctl) {
   __shared__ double tree[FINAL];
   if (ctl->done) return;
   const double zq = final_sum(partial, nb, tree);
-  if (threadIdx.x == 0) kc->beta = (kc->first || kc->pq_prev == 0.0) ? 0.0 : -zq / kc->pq_prev;
-}
-
-template <class T>
-__global__ __launch_bounds__(BLOCK) void k_fcg_dir(int n, const uint32_t *__restrict__ mask,
-                                                   const T *__restrict__ z, double *__restrict__ p,
-                                                   const KrylovCtl *__restrict__ kc,
-                                                   const SolveCtl *__restrict__ ctl) {
-  if (ctl->done) return;
-  const int r = blockIdx.x * BLOCK + threadIdx.x;
-  if (r >= n || (mask[r] & SOLID_BIT)) return;
-  const double beta = kc->beta;
-  p[r] = beta == 0.0 ? double(z[r]) : double(z[r]) + beta * p[r];
-}
-
-// q = A p on fluid sites (p = 0 on solid ones), partials of (p, q) and (r, p)
-__global__ __launch_bounds__(BLOCK) void k_fcg_apply(MgLevel lv, const uint32_t *__restrict__ mask,
-                                                     const double *__restrict__ p,
-                                                     const double *__restrict__ rv,
-                                                     double *__restrict__ q,
-                                                     double *__restrict__ partial,
-                                                     const SolveCtl *__restrict__ ctl) {
-  __shared__ double sm[BLOCK / WAVE];
-  if (ctl->done) return;
-  const int lb = xcd_block(blockIdx.x, gridDim.x, BLOCK, lv.nxy, lv.xcd);
-  const int r = lb * BLOCK + threadIdx.x;
-  double pq = 0.0, rp = 0.0;
-  if (r < lv.n) {
-    const Coords c = coords_of(r, lv);
-    double v[NQ];
-    gather_lv(lv, c, r, p, v);
-    const double rr = rv[r];
-    const uint32_t m = mask[r];
-    if (!(m & SOLID_BIT)) {
-      const double qr = apply_A_v<double>(lv, m, v);
-      q[r] = qr;
-      pq = v[0] * qr;
-      rp = rr * v[0];
-    }
-  }
-  pq = block_sum(pq, sm);
-  if (threadIdx.x == 0) partial[lb] = pq;
-  rp = block_sum(rp, sm);
-  if (threadIdx.x == 0) partial[gridDim.x + lb] = rp;
-}
-
-__global__ __launch_bounds__(FINAL) void k_fcg_alpha(const double *__restrict__ partial, int nb,
-                                                     KrylovCtl *__restrict__ kc,
-                                                     const SolveCtl *__restrict__ ctl) {
-  __shared__ double tree[FINAL];
-  if (ctl->done) return;
-  const double pq = final_sum(partial, nb, tree);
-  const double rp = final_sum(partial + nb, nb, tree);
+  const double zaz = final_sum(partial + nb, nb, tree);
+  const double rz = final_sum(partial + 2 * nb, nb, tree);
+  const double rp_prev = final_sum(partial + 3 * nb, nb, tree);
   if (threadIdx.x == 0) {
+    // a new sequence (first) starts from p = z
+    const bool fresh = kc->first || kc->pq_prev == 0.0;
+    const double beta = fresh ? 0.0 : -zq / kc->pq_prev;
+    const double pq = fresh ? zaz : zaz + beta * (2.0 * zq + beta * kc->pq_prev);
+    const double rp = fresh ? rz : rz + beta * rp_prev;
+    kc->beta = beta;
     kc->alpha = pq > 0.0 ? rp / pq : 0.0;
     kc->pq_prev = pq;
     kc->first = 0;
   }
 }
 
+// z may be the buffer e0 points to (the V-cycle's output on the finest
+// level): each site reads its z before writing its e0, so neither is
+// declared __restrict__.
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_fcg_update(int n, const uint32_t *__restrict__ mask,
-                                                      const double *__restrict__ p,
-                                                      const double *__restrict__ q,
+                                                      const T *z,
+                                                      const double *__restrict__ az,
+                                                      double *__restrict__ p,
+                                                      double *__restrict__ q,
                                                       double *__restrict__ phi,
                                                       double *__restrict__ rv,
-                                                      T *__restrict__ r0, T *__restrict__ e0,
+                                                      T *__restrict__ r0, T *e0,
                                                       double *__restrict__ partial,
                                                       const KrylovCtl *__restrict__ kc,
                                                       const SolveCtl *__restrict__ ctl,
@@ -281,9 +279,14 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_update(int n, const uint32_t *__r
     double R = 0.0;
     const uint32_t m = mask[r];
     if (!(m & SOLID_BIT)) {
-      const double alpha = kc->alpha;
-      phi[r] += alpha * p[r];
-      R = rv[r] - alpha * q[r];
+      const double beta = kc->beta, alpha = kc->alpha;
+      const double zr = double(z[r]);
+      const double pr = beta == 0.0 ? zr : zr + beta * p[r];
+      const double qr = beta == 0.0 ? az[r] : az[r] + beta * q[r];
+      p[r] = pr;
+      q[r] = qr;
+      phi[r] += alpha * pr;
+      R = rv[r] - alpha * qr;
       rv[r] = R;
       a = fabs(R);
     }
@@ -933,38 +936,24 @@ hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_
 }
 
 template <class T>
-hipError_t launch_fcg_beta(hipStream_t s, int n, const uint32_t *mask, const T *z,
-                           const double *q, double *partial, KrylovCtl *kc, const SolveCtl *ctl) {
-  const int nb = (int)blocks_for(n);
-  hipLaunchKernelGGL(k_fcg_dot<T>, dim3(nb), dim3(BLOCK), 0, s, n, mask, z, q, partial, ctl);
-  hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(FINAL), 0, s, partial, nb, kc, ctl);
-  return hipGetLastError();
-}
-
-template <class T>
-hipError_t launch_fcg_dir(hipStream_t s, int n, const uint32_t *mask, const T *z, double *p,
-                          const KrylovCtl *kc, const SolveCtl *ctl) {
-  hipLaunchKernelGGL(k_fcg_dir<T>, dim3(blocks_for(n)), dim3(BLOCK), 0, s, n, mask, z, p, kc, ctl);
-  return hipGetLastError();
-}
-
-hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
-                            const double *p, const double *r, double *q, double *partial,
-                            KrylovCtl *kc, const SolveCtl *ctl) {
+hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *mask, const T *z,
+                            const double *q_prev, const double *p_prev, const double *r,
+                            double *az, double *partial, KrylovCtl *kc, const SolveCtl *ctl) {
   const int nb = (int)blocks_for(lv.n);
-  hipLaunchKernelGGL(k_fcg_apply, dim3(nb), dim3(BLOCK), 0, s, lv, mask, p, r, q, partial, ctl);
-  hipLaunchKernelGGL(k_fcg_alpha, dim3(1), dim3(FINAL), 0, s, partial, nb, kc, ctl);
+  hipLaunchKernelGGL(k_fcg_az<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, z, q_prev, p_prev, r,
+                     az, partial, ctl);
+  hipLaunchKernelGGL(k_fcg_coef, dim3(1), dim3(FINAL), 0, s, partial, nb, kc, ctl);
   return hipGetLastError();
 }
 
 template <class T>
-hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const double *p,
-                             const double *q, double *phi, double *r, T *r0, T *e0,
-                             double *partial, const KrylovCtl *kc, SolveCtl *ctl, int add,
-                             const MgLevel &lv, double jac) {
+hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const T *z,
+                             const double *az, double *p, double *q, double *phi, double *r,
+                             T *r0, T *e0, double *partial, const KrylovCtl *kc, SolveCtl *ctl,
+                             int add, const MgLevel &lv, double jac) {
   const int nb = (int)blocks_for(n);
-  hipLaunchKernelGGL(k_fcg_update<T>, dim3(nb), dim3(BLOCK), 0, s, n, mask, p, q, phi, r, r0, e0,
-                     partial, kc, ctl, lv, T(jac), T(lv.h2 / 6.0));
+  hipLaunchKernelGGL(k_fcg_update<T>, dim3(nb), dim3(BLOCK), 0, s, n, mask, z, az, p, q, phi, r,
+                     r0, e0, partial, kc, ctl, lv, T(jac), T(lv.h2 / 6.0));
   hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
@@ -1059,15 +1048,14 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                                const double *, const double *, T *, T *,       \
                                                double *, SolveCtl *, int, double *,            \
                                                KrylovCtl *, double);                           \
-  template hipError_t launch_fcg_beta<T>(hipStream_t, int, const uint32_t *, const T *,         \
-                                         const double *, double *, KrylovCtl *,                 \
-                                         const SolveCtl *);                                     \
-  template hipError_t launch_fcg_dir<T>(hipStream_t, int, const uint32_t *, const T *, double *, \
-                                        const KrylovCtl *, const SolveCtl *);                   \
-  template hipError_t launch_fcg_update<T>(hipStream_t, int, const uint32_t *, const double *,  \
-                                           const double *, double *, double *, T *, T *,        \
-                                           double *, const KrylovCtl *, SolveCtl *, int,        \
-                                           const MgLevel &, double);                            \
+  template hipError_t launch_fcg_apply<T>(hipStream_t, const MgLevel &, const uint32_t *,      \
+                                          const T *, const double *, const double *,            \
+                                          const double *, double *, double *, KrylovCtl *,      \
+                                          const SolveCtl *);                                    \
+  template hipError_t launch_fcg_update<T>(hipStream_t, int, const uint32_t *, const T *,       \
+                                           const double *, double *, double *, double *,        \
+                                           double *, T *, T *, double *, const KrylovCtl *,     \
+                                           SolveCtl *, int, const MgLevel &, double);           \
   template hipError_t launch_mg_smooth<T>(hipStream_t, const MgLevel &, double, int,            \
                                           const uint32_t *, const T *, T *, const SolveCtl *);  \
   template hipError_t launch_jacobi<T>(hipStream_t, const MgLevel &, double, double,             \
