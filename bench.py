@@ -535,7 +535,7 @@ def _classify(name, grid, nsites, prev_form=None):
     return None
 
 
-def summarize_rocprof(root, workload):
+def summarize_rocprof(root, workload, window=(22, 10)):
     """Summaries of the kernel-trace run (root/trace) and the two counter runs
     (root/fetch, root/write) of one workload, as text."""
     build, _ = WORKLOADS[workload]
@@ -573,6 +573,31 @@ def summarize_rocprof(root, workload):
             a = agg.setdefault(cls, [0, 0.0])
             a[0] += 1
             a[1] += dur
+        # GPU occupancy of the timed steps: per form, the pass-A launches
+        # after the launch-shape trials mark the steps; over the timed window
+        # the union of kernel intervals against the wall span
+        skip, count = window
+        out.append(f"GPU busy fraction over the timed window (steps {skip}..{skip + count} "
+                   "after the launch-shape trials, pass-A launch to pass-A launch):")
+        for form_tag in ("_f32", "_f64"):
+            fl = [r for r in trace if "k_fluid" + form_tag in r["Kernel_Name"]]
+            fl = fl[12:]  # 4 trial launches at each of 128, 256 and 512 threads
+            if len(fl) < skip + count + 1:
+                continue
+            t0 = int(fl[skip]["Start_Timestamp"])
+            t1 = int(fl[skip + count]["Start_Timestamp"])
+            busy, last = 0, t0
+            for r in trace:
+                a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+                if b <= t0 or a >= t1:
+                    continue
+                a, b = max(a, last), min(b, t1)
+                if b > a:
+                    busy += b - a
+                    last = b
+            out.append(f"  {'fp32' if form_tag == '_f32' else 'fp64'}: {(t1 - t0) / 1e3 / count:.1f} "
+                       f"us per step, GPU busy {100.0 * busy / (t1 - t0):.1f}%")
+        out.append("")
         out.append("first-stage kernels by form and kind (dispatches longer than 3 us):")
         out.append(f"{'form':8s} {'kind':16s} {'launches':>8s} {'avg_us':>9s}")
         for (form, kind), (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
@@ -669,10 +694,12 @@ def main():
     ap.add_argument("--adjoint-profile-steps", type=int, default=400)
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="print the summary of the rocprofv3 CSV output under DIR (trace/, "
-                         "fetch/, write/) for --workload and exit (no GPU)")
+                         "fetch/, write/) for --workload and exit (no GPU); --start-step, "
+                         "--warmup and --steps name the profiled run's timed window")
     args = ap.parse_args()
     if args.summarize_rocprof:
-        sys.stdout.write(summarize_rocprof(args.summarize_rocprof, args.workload))
+        sys.stdout.write(summarize_rocprof(args.summarize_rocprof, args.workload,
+                                           (args.start_step + args.warmup, args.steps)))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the LBE step is not sharded across GPUs in this "

@@ -26,8 +26,9 @@ constexpr int WAVE = 64;
 // logical index keep their order (the results are the same bit for bit).
 // Measured on the 192^3 porous electrode it cuts the HBM-side reads of the
 // neighbour-gathering kernels by 30-40%, but their time only where it is
-// used: the LB pass, the residual checks and the Krylov operator (0.8-2%);
-// the smoothers, transfers and the ion pass run 2-8% slower with it.
+// used: the LB pass, the residual checks and the Krylov operator (0.8-2%
+// faster) and the FP64 ion pass (same time); the smoothers, the transfers
+// and the FP32 ion pass run 1.5-8% slower with it.
 __device__ __forceinline__ int xcd_block(int b, int nb, int tb, int nxy, int on) {
   if (!on) return b;
   int chunk = (nxy + tb * NXCD / 2) / (tb * NXCD);

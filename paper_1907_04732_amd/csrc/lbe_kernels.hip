@@ -154,7 +154,7 @@ __global__ __launch_bounds__(TB) void k_ions_f64(Lattice L, Phys P,
                                                     double *__restrict__ src, int order,
                                                     double *__restrict__ phi,
                                                     double *__restrict__ prev) {
-  const int r = blockIdx.x * TB + threadIdx.x;
+  const int r = xcd_block(blockIdx.x, gridDim.x, TB, L.nxy, L.xcd) * TB + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
   if (m & SOLID_BIT) return;
