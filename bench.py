@@ -45,7 +45,7 @@ import workloads as W  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
-def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False):
+def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False, krylov: bool = False):
     """Algorithmic HBM bytes per cell of the grid level a launch works on
     (lattice sites for the finest level), or None where no byte model applies
     (the one-work-group coarse-level kernel, the electrode-charge gather).
@@ -65,7 +65,8 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False):
       zeroed correction out.  Prolongation, per fine cell: correction in and
       out, flag word; per coarse cell: correction and flag word.  Outer
       residual: phi, source, flag word in; correction rhs and zeroed
-      correction out (multigrid).  correct: phi in + out, correction, flag
+      correction out (multigrid), and the FP64 residual out under Krylov
+      acceleration.  correct: phi in + out, correction, flag
       word.  Krylov iteration: fcg_apply gathers the V-cycle's output z
       and reads q', p' and r, writing A z; fcg_update reads z, A z, p', q',
       phi and r and writes p, q, phi, r and the next cycle's rhs and start.
@@ -94,7 +95,8 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False):
         "mg_restrict": 2 * cor + 4 + (4 + 2 * cor) / 8,
         "mg_prolong": 2 * cor + 4 + (cor + 4) / 8,
         "resid": 8 + 8 + 4,
-        "mg_resid": 8 + 8 + 4 + 2 * cor,
+        # with Krylov acceleration the check also keeps the FP64 residual
+        "mg_resid": 8 + 8 + 4 + 2 * cor + (8 if krylov else 0),
         "correct": 16 + cor + 4,
         # Krylov: A z and four sums (z, q', p', r in; A z out); then p, q,
         # phi, r updated (z, A z, p', q', phi, r in; p, q, phi, r, the
@@ -241,7 +243,8 @@ def run_form(w, form: str, solver: str, steps: int, warmup: int, start_step: int
         if not cnt:
             continue
         avg = ms / 1e3 / cnt
-        b = bytes_per_cell(k, form, len(w.z), extrap=bool(flags & lbe.EXTRAPOLATE))
+        b = bytes_per_cell(k, form, len(w.z), extrap=bool(flags & lbe.EXTRAPOLATE),
+                           krylov=bool(flags & lbe.KRYLOV))
         row = {"total_ms": round(ms, 4), "launches": cnt, "avg_us": round(avg * 1e6, 3),
                "cells_per_launch": int(round(cells / cnt))}
         if b is not None:
@@ -432,7 +435,7 @@ def run_adjoint(w, form: str, steps: int, every: int, check_every: int, profile_
             continue
         avg = ms / 1e3 / cnt
         row = {"total_ms": round(ms, 4), "launches": cnt, "avg_us": round(avg * 1e6, 3)}
-        b = bytes_per_cell(k, form, len(w.z), extrap=True)
+        b = bytes_per_cell(k, form, len(w.z), extrap=True, krylov=True)
         if b is not None:
             per_launch = (ffrac * b + (1.0 - ffrac) * 4) * cells / cnt
             row["bytes_per_launch"] = int(round(per_launch))
@@ -672,9 +675,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--start-step", type=int, default=100,
+    ap.add_argument("--start-step", type=int, default=1000,
                     help="untimed steps before the warm-up: the timed window starts from a "
-                         "running state")
+                         "running state (the configured runs are 4000-50000 steps long)")
     ap.add_argument("--workload", default="porous_electrode_192^3", choices=list(WORKLOADS))
     ap.add_argument("--forms", default="fp32-mg,fp64-mg",
                     help="comma list of " + ",".join(FORMS) + "; the first is the headline")
@@ -731,8 +734,9 @@ def main():
         "dtype": "f64" if hform == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": w.name, "sites": int(w.node_type.size), "fluid_sites": nfluid,
-                   "form": forms[0], "tol": w.tol, "debye": w.extra.get("debye"),
-                   "Eapp": list(w.Eapp),
+                   "form": forms[0], "tol": getattr(w, "tol", 1e-10),
+                   "debye": getattr(w, "extra", {}).get("debye"),
+                   "Eapp": list(getattr(w, "Eapp", (0.0, 0.0, 0.0))),
                    "timed_steps_from": head["first_step"],
                    "poisson": (poisson_text(settings) if hsolver == "mg" else
                                "four-colour SOR"),

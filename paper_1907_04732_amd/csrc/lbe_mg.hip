@@ -233,15 +233,27 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_az(MgLevel lv, const uint32_t *__
   if (threadIdx.x == 0) partial[3 * nb + lb] = rp;
 }
 
+// The four sums of k_fcg_az's partials in one pass (their loads in flight
+// together), each combined in a fixed order.
 __global__ __launch_bounds__(FINAL) void k_fcg_coef(const double *__restrict__ partial, int nb,
                                                     KrylovCtl *__restrict__ kc,
                                                     const SolveCtl *__restrict__ ctl) {
-  __shared__ double tree[FINAL];
+  __shared__ double tree[4][FINAL];
   if (ctl->done) return;
-  const double zq = final_sum(partial, nb, tree);
-  const double zaz = final_sum(partial + nb, nb, tree);
-  const double rz = final_sum(partial + 2 * nb, nb, tree);
-  const double rp_prev = final_sum(partial + 3 * nb, nb, tree);
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += FINAL)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] += partial[k * nb + b];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) tree[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int h = FINAL / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) tree[k][threadIdx.x] += tree[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  const double zq = tree[0][0], zaz = tree[1][0], rz = tree[2][0], rp_prev = tree[3][0];
   if (threadIdx.x == 0) {
     // a new sequence (first) starts from p = z
     const bool fresh = kc->first || kc->pq_prev == 0.0;
