@@ -347,20 +347,20 @@ FORMS = {"fp32-mg": ("fp32", "mg"), "fp64-mg": ("fp64", "mg"), "fp64-sor": ("fp6
          "fp32-sor": ("fp32", "sor")}
 
 # Workloads: builder and multigrid cycle, chosen by timing the cycles on the
-# same GPU from a running state.  The slab's electrodes are represented
-# exactly on every level: V(1,1) everywhere.  The porous electrode's spheres
-# are not: V(2,2) with four Jacobi sweeps each way on the coarse levels, as
-# the preconditioner of flexible CG (plain cycles diverge there).  The
-# coaxial cell: V(1,1) with two sweeps each way on the coarse levels, plain.
-# The 96-system batch: V(1,2), two sweeps each way on the coarse levels,
-# with Krylov acceleration.
+# same GPU from a running state (steps 1000-1200).  The slab's electrodes are
+# represented exactly on every level: V(1,1) everywhere.  The porous
+# electrode's spheres are not: V(1,2) with three Jacobi sweeps each way on
+# the coarse levels, as the preconditioner of flexible CG (plain cycles
+# diverge there).  The coaxial cell: V(1,1) with three sweeps each way on
+# the coarse levels, plain.  The 96-system batch: V(1,1), two sweeps each
+# way on the coarse levels, with Krylov acceleration.
 WORKLOADS = {
     "porous_electrode_192^3": (lambda: W.porous_electrode(noise=True),
-                               dict(krylov=True, nu=(2, 2, 4, 4))),
+                               dict(krylov=True, nu=(1, 2, 3, 3))),
     "eo_slab_64x64x130": (lambda: W.eo_slab(noise=True), dict(nu=(1, 1, 1, 1))),
-    "coaxial_160x160x64": (lambda: W.coaxial(noise=True), dict(nu=(1, 1, 2, 2))),
+    "coaxial_160x160x64": (lambda: W.coaxial(noise=True), dict(nu=(1, 1, 3, 3))),
     "batched_96_slabs_8x8": (lambda: W.batch_slabs(noise=True),
-                             dict(krylov=True, nu=(1, 2, 2, 2))),
+                             dict(krylov=True, nu=(1, 1, 2, 2))),
 }
 
 

@@ -13,9 +13,10 @@ configurations' full size and length.
    the iterates depend on omega, not the fixed point) to 1e-12 on many
    threads (its OpenMP build is bit for bit the single-threaded one).
 2. Against the FP64 form on the GPU (itself within 1e-12 of the oracle on
-   the parity cases) at full size for thousands of steps: the 64 x 64 x 130
-   electro-osmosis slab, the 160 x 160 x 64 coaxial cell, the 192^3 porous
-   electrode and the 96-system batch, each in its benchmark configuration.
+   the parity cases) at full size for the configured number of steps: the
+   64 x 64 x 130 electro-osmosis slab (50000), the 160 x 160 x 64 coaxial
+   cell (30000), the 192^3 porous electrode (4000) and the 96-system batch
+   (one 10000-step chunk), each in its benchmark configuration.
 
 Bars (the benchmark spec): potential within 1e-5 of the electrode voltage
 difference; electrode charge Q(t) over the whole history and capacitance
@@ -94,24 +95,37 @@ def test_mixed_at_bench_settings_matches_oracle(name):
     check(errs)
 
 
+# the configured run lengths: 50000 steps of the slab, 30000 of the coaxial
+# cell, 4000 of the porous electrode
 FULL = {
-    "eo_slab_64x64x130": lambda: (W.eo_slab(noise=True), SETTINGS["eo_slab_64x64x130"], 5000),
-    "coaxial_160x160x64": lambda: (W.coaxial(noise=True), SETTINGS["coaxial_160x160x64"], 3000),
+    "eo_slab_64x64x130": lambda: (W.eo_slab(noise=True), SETTINGS["eo_slab_64x64x130"], 50000),
+    "coaxial_160x160x64": lambda: (W.coaxial(noise=True), SETTINGS["coaxial_160x160x64"], 30000),
     "porous_electrode_192^3": lambda: (W.porous_electrode(noise=True),
-                                       SETTINGS["porous_electrode_192^3"], 2000),
+                                       SETTINGS["porous_electrode_192^3"], 4000),
 }
 
 
 @pytest.mark.parametrize("name", list(FULL))
 def test_mixed_matches_fp64_at_full_size(name):
+    """Full size, the configured number of steps.  Also the conservation of
+    each ion species and of the fluid mass over the run, in both forms: the
+    FP64 form to rounding, the mixed form within the drift of its FP32
+    deviation updates (bound 1e-6 relative)."""
     w, settings, steps = FULL[name]()
     runs = {}
     for form in ("fp32", "fp64"):
         g = lbe.Lbe(bench.step_params(w, form, **settings), w.node_type, w.phi_s, w.n_init,
                     w.n_ref)
+        t0 = g.totals()
         g.step(steps)
-        runs[form] = (g.fields(f=False), g.qhist(), g.totals())
+        t1 = g.totals()
+        runs[form] = (g.fields(f=False), g.qhist(), t1)
         g.close()
+        drift = max([abs(t1["nk"][k] / t0["nk"][k] - 1) for k in range(len(w.z))]
+                    + [abs(t1["mass"] / t0["mass"] - 1)])
+        print(name, form, f"{steps} steps: largest relative drift of the ion counts and the "
+                          f"fluid mass {drift:.2e}")
+        assert drift <= (1e-12 if form == "fp64" else 1e-6)
     (fa, qa, ta), (fb, qb, tb) = runs["fp32"], runs["fp64"]
     errs = errors(w.node_type, w.n_ref, w.phi_s, fa, fb, qa, qb)
     if any(w.Eapp):
@@ -129,16 +143,17 @@ def test_mixed_matches_fp64_at_full_size(name):
 
 def test_batch_capacitance_mixed_matches_fp64():
     """The 96-system batch (8 x 8 x L, L 16..256, Debye length 2..16, voltage
-    0.01..0.2) in its benchmark configuration for 2000 steps: every system's
-    charge history and capacitance Q(T)/V in the mixed form against the FP64
-    form, and the potential of every system against its own voltage."""
+    0.01..0.2) in its benchmark configuration for one configured chunk of
+    10000 steps: every system's charge history and capacitance Q(T)/V in the
+    mixed form against the FP64 form, and the potential of every system
+    against its own voltage."""
     w = W.batch_slabs(noise=True)
     runs = {}
     for form in ("fp32", "fp64"):
         p = bench.step_params(w, form, **SETTINGS["batched_96_slabs_8x8"])
         g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref.reshape(-1), system=w.system,
                     nsys=len(w.L))
-        g.step(2000)
+        g.step(10000)
         runs[form] = (g.fields(f=False)["phi"], g.qhist())
         g.close()
     (pa, qa), (pb, qb) = runs["fp32"], runs["fp64"]
