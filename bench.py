@@ -50,10 +50,12 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False, krylov: b
     (lattice sites for the finest level), or None where no byte model applies
     (the one-work-group coarse-level kernel, the electrode-charge gather).
 
-    fluid: 19 populations in + out, K concentrations in, K partially
-      updated concentrations out, phi (FP64), velocity out, flag word.
-      ions (advection pass): K concentrations, K partial updates in, K new
-      concentrations out, velocity in, Poisson source (FP64) out, flag word;
+    fluid: 19 populations in + out, K concentrations in, K increments out,
+      phi (FP64), velocity out, flag word.
+      ions (advection pass): K concentrations, K increments in, K new
+      concentrations out (the mixed form also reads and writes the K low
+      words of its concentration pairs), velocity in, Poisson source (FP64)
+      out, flag word;
       with the extrapolated warm start also phi and the two previous
       potentials in + out, without it phi in and its kept copy out (the
       state a failed step goes back to).  One colour of a four-colour SOR
@@ -85,7 +87,8 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False, krylov: b
     cor = 8 if f64 else 4     # Poisson correction storage (multigrid)
     table = {
         "fluid": 19 * pop * 2 + 2 * K * pop + 8 + 3 * vel + 4,
-        "ions": 3 * K * pop + 3 * vel + 8 + 4 + (48 if extrap else 16),
+        "ions": 3 * K * pop + (0 if f64 else 2 * K * 4) + 3 * vel + 8 + 4
+                + (48 if extrap else 16),
         "sor": 8 + (8 + 8 + 4) / 4,
         "sor32": 4 + (4 + 4 + 4) / 4,
         "mg_smooth0": 3 * cor + 4,

@@ -34,9 +34,12 @@ struct lbe_ctx {
   double *phi_keep = nullptr;  // phi(t) as the step started (N; without LBE_EXTRAPOLATE)
   double *n[2] = {nullptr, nullptr};
   double *f[2] = {nullptr, nullptr};
-  // mixed form: FP32 deviations h = f - w rho0, nu = n - n_ref, FP32 velocity
+  // mixed form: FP32 deviations h = f - w rho0, nu = n - n_ref held as the
+  // pair nu32 + lo32 (lo32 only read and written by a node's own update),
+  // FP32 velocity
   float *h32[2] = {nullptr, nullptr};
   float *nu32[2] = {nullptr, nullptr};
+  float *lo32[2] = {nullptr, nullptr};
   float *u32 = nullptr;
   double *obs = nullptr;  // FP64 scratch for observables of the mixed form (22 N)
   bool mixed = false;
@@ -1241,8 +1244,8 @@ int rewind_step(lbe_ctx *c, int a, int hist, bool record) {
   const int shift = c->phi_prev ? 1 : 0;
   int rc = run(c, KK_REWIND, c->L.n, [&] {
     if (c->mixed)
-      return launch_rewind_f32(c->stream, c->L, c->P, c->mask, c->nu32[a], c->src, c->phi, keep,
-                               shift);
+      return launch_rewind_f32(c->stream, c->L, c->P, c->mask, c->nu32[a], c->lo32[a], c->src,
+                               c->phi, keep, shift);
     return launch_rewind_f64(c->stream, c->L, c->P, c->mask, c->n[a], c->src, c->phi, keep, shift);
   });
   if (rc) return rc;
@@ -1276,8 +1279,8 @@ int one_step(lbe_ctx *c, bool record = true) {
   // pass B also moves phi to the extrapolated start of this step's solve
   rc = run(c, KK_IONS, c->L.n, [&] {
     if (c->mixed)
-      return launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a], c->nu32[b],
-                             c->src, order, c->phi, keep, c->tb_b);
+      return launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a], c->lo32[a],
+                             c->nu32[b], c->lo32[b], c->src, order, c->phi, keep, c->tb_b);
     return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a], c->n[b], c->src,
                            order, c->phi, keep, c->tb_b);
   });
@@ -1310,11 +1313,13 @@ inline size_t pad256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Byte layout of a saved state.  A checkpoint holds the populations and
 // concentrations in the context's storage (FP64, or the FP32 deviations of
-// the mixed form), phi and, under LBE_EXTRAPOLATE, phi(t-1).  A recomputed
-// state of one reverse step holds rho and m (4 N FP64: the collision sees the
-// populations only through them), the concentrations and phi.
+// the mixed form with the low words of the concentration pairs), phi and,
+// under LBE_EXTRAPOLATE, phi(t-1).  A recomputed state of one reverse step
+// holds rho and m (4 N FP64: the collision sees the populations only through
+// them), the concentrations (the high words in the mixed form: the reverse
+// step linearises about them) and phi.
 struct StateLayout {
-  size_t f, n, phi, prev, bytes;
+  size_t f, n, lo, phi, prev, bytes;
 };
 
 StateLayout checkpoint_layout(const lbe_ctx *c) {
@@ -1322,7 +1327,8 @@ StateLayout checkpoint_layout(const lbe_ctx *c) {
   StateLayout l;
   l.f = 0;
   l.n = pad256(NQ * N * sf);
-  l.phi = l.n + pad256(c->K * N * sf);
+  l.lo = l.n + pad256(c->K * N * sf);
+  l.phi = l.lo + (c->mixed ? pad256(c->K * N * sizeof(float)) : 0);
   l.prev = l.phi + pad256(N * sizeof(double));
   l.bytes = l.prev + (c->phi_prev ? pad256(2 * N * sizeof(double)) : 0);
   return l;
@@ -1333,7 +1339,7 @@ StateLayout slot_layout(const lbe_ctx *c) {
   StateLayout l;
   l.f = 0;
   l.n = pad256(4 * N * sizeof(double));
-  l.phi = l.n + pad256(c->K * N * sf);
+  l.lo = l.phi = l.n + pad256(c->K * N * sf);
   l.prev = l.bytes = l.phi + pad256(N * sizeof(double));
   return l;
 }
@@ -1354,6 +1360,8 @@ int save_state(lbe_ctx *c, char *dst) {
       (rc = copy_dd(c, dst + l.n, cur_concs(c), c->K * N * sf)) ||
       (rc = copy_dd(c, dst + l.phi, c->phi, N * sizeof(double))))
     return rc;
+  if (c->mixed && (rc = copy_dd(c, dst + l.lo, c->lo32[c->cur], c->K * N * sizeof(float))))
+    return rc;
   if (c->phi_prev) return copy_dd(c, dst + l.prev, c->phi_prev, 2 * N * sizeof(double));
   return LBE_OK;
 }
@@ -1365,6 +1373,8 @@ int load_state(lbe_ctx *c, const char *src) {
   if ((rc = copy_dd(c, cur_pops(c), src + l.f, NQ * N * sf)) ||
       (rc = copy_dd(c, cur_concs(c), src + l.n, c->K * N * sf)) ||
       (rc = copy_dd(c, c->phi, src + l.phi, N * sizeof(double))))
+    return rc;
+  if (c->mixed && (rc = copy_dd(c, c->lo32[c->cur], src + l.lo, c->K * N * sizeof(float))))
     return rc;
   if (c->phi_prev) return copy_dd(c, c->phi_prev, src + l.prev, 2 * N * sizeof(double));
   return LBE_OK;
@@ -1566,21 +1576,27 @@ int copy_fields(lbe_ctx *c, double *phi, double *n, double *u, double *f, hipMem
       HIPCHK(c, hipMemcpyAsync(n, c->n[c->cur], sizeof(double) * K * N, kind, c->stream));
     } else if (kind == hipMemcpyDeviceToDevice) {
       rc = run(c, KK_EXPAND_N, c->L.n, [&] {
-        return launch_expand_n_f32(c->stream, c->L, c->P, c->mask, c->nu32[c->cur], n);
+        return launch_expand_n_f32(c->stream, c->L, c->P, c->mask, c->nu32[c->cur],
+                                   c->lo32[c->cur], n);
       });
       if (rc) return rc;
     } else {
-      nu_h.resize((size_t)K * N);
+      nu_h.resize((size_t)2 * K * N);
       HIPCHK(c, hipMemcpyAsync(nu_h.data(), c->nu32[c->cur], sizeof(float) * K * N,
                                hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipMemcpyAsync(nu_h.data() + (size_t)K * N, c->lo32[c->cur],
+                               sizeof(float) * K * N, hipMemcpyDeviceToHost, c->stream));
     }
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (!nu_h.empty())
     for (int k = 0; k < K; ++k)
-      for (long r = 0; r < N; ++r)
-        n[(size_t)k * N + r] =
-            c->type_h[r] ? 0.0 : c->nref_h[(size_t)c->sys_h[r] * 4 + k] + (double)nu_h[(size_t)k * N + r];
+      for (long r = 0; r < N; ++r) {
+        const size_t i = (size_t)k * N + r;
+        n[i] = c->type_h[r] ? 0.0
+                            : c->nref_h[(size_t)c->sys_h[r] * 4 + k] +
+                                  ((double)nu_h[i] + (double)nu_h[(size_t)K * N + i]);
+      }
   return LBE_OK;
 }
 
@@ -1599,7 +1615,8 @@ void free_ctx(lbe_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   void *ptrs[] = {c->mask, c->phi, c->phi_prev, c->phi_keep, c->src, c->u, c->n[0], c->n[1], c->f[0], c->f[1],
-                  c->h32[0], c->h32[1], c->nu32[0], c->nu32[1], c->u32, c->obs,
+                  c->h32[0], c->h32[1], c->nu32[0], c->nu32[1], c->lo32[0], c->lo32[1],
+                  c->u32, c->obs,
                   c->partial, c->dout, c->ctl, c->iface, c->blk_elec, c->blk_begin,
                   c->blk_end, c->qcur, c->qhist, c->solid_idx, c->solid_val,
                   c->nref_d_tab, c->qref_tab, c->nref_f_tab, c->kr, c->kp, c->kq, c->kaz, c->kc,
@@ -1712,7 +1729,8 @@ int autotune_passes(lbe_ctx *c) {
                                             c->f[a], c->f[b], c->u, c->n[b], tb);
           else
             e = c->mixed ? launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a],
-                                           c->nu32[b], src_s, -1, c->phi, keep_s, tb)
+                                           c->lo32[a], c->nu32[b], c->lo32[b], src_s, -1,
+                                           c->phi, keep_s, tb)
                          : launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a],
                                            c->n[b], src_s, -1, c->phi, keep_s, tb);
         }
@@ -1923,6 +1941,7 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
       TRY(dalloc(c, &c->obs, (size_t)(NQ + 3) * N));
       for (int s = 0; s < 2; ++s) {
         TRY(dalloc(c, &c->nu32[s], (size_t)K * N));
+        TRY(dalloc(c, &c->lo32[s], (size_t)K * N));
         TRY(dalloc(c, &c->h32[s], (size_t)NQ * N));
       }
     } else {
@@ -1962,15 +1981,20 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     c->nblk_charge = (int)g.blk_elec.size();
 
     std::vector<double> phi0(N, 0.0), src0(N, 0.0);
-    std::vector<float> nu0, h0;
+    std::vector<float> nu0, lo0, h0;
     if (c->mixed) {
       nu0.assign((size_t)K * N, 0.f);
+      lo0.assign((size_t)K * N, 0.f);
       h0.assign((size_t)NQ * N, 0.f);
+      // the pair: hi the deviation rounded to FP32, lo what that rounding left
       for (int k = 0; k < K; ++k)
         for (long r = 0; r < N; ++r)
-          if (!type[r])
-            nu0[(size_t)k * N + r] =
-                (float)(n0[(size_t)k * N + r] - c->nref_h[(size_t)sys_h[r] * 4 + k]);
+          if (!type[r]) {
+            const size_t i = (size_t)k * N + r;
+            const double d = n0[i] - c->nref_h[(size_t)sys_h[r] * 4 + k];
+            nu0[i] = (float)d;
+            lo0[i] = (float)(d - (double)nu0[i]);
+          }
       for (int i = 0; i < NQ; ++i)
         for (long r = 0; r < N; ++r)
           if (!type[r]) h0[(size_t)i * N + r] = (float)(fs[(size_t)i * N + r] - WQ[i] * p.rho0);
@@ -1983,7 +2007,8 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
       double q = 0.0;
       if (c->mixed) {
         q = c->qref_h[sys_h[r]];
-        for (int k = 0; k < K; ++k) q += p.z[k] * (double)nu0[(size_t)k * N + r];
+        for (int k = 0; k < K; ++k)
+          q += p.z[k] * ((double)nu0[(size_t)k * N + r] + (double)lo0[(size_t)k * N + r]);
       } else {
         for (int k = 0; k < K; ++k) q += p.z[k] * n0[(size_t)k * N + r];
       }
@@ -2000,6 +2025,7 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     for (int s = 0; s < 2; ++s) {
       if (c->mixed) {
         TRY(up(c->nu32[s], nu0.data(), sizeof(float) * K * N));
+        TRY(up(c->lo32[s], lo0.data(), sizeof(float) * K * N));
         TRY(up(c->h32[s], h0.data(), sizeof(float) * NQ * N));
       } else {
         TRY(up(c->n[s], n0.data(), sizeof(double) * K * N));
@@ -2286,7 +2312,7 @@ int lbe_observables(lbe_ctx *c, lbe_obs *totals, double *phi, double *n, double 
     rc = run(c, KK_TOTALS, c->L.n, [&] {
       if (c->mixed)
         return launch_totals_f32(c->stream, c->L, c->P, c->mask, c->h32[c->cur], c->nu32[c->cur],
-                                 c->partial, c->dout);
+                                 c->lo32[c->cur], c->partial, c->dout);
       return launch_totals_f64(c->stream, c->L, K, c->p.z, c->mask, c->f[c->cur], c->n[c->cur],
                                c->partial, c->dout);
     });

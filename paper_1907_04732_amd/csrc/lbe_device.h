@@ -287,6 +287,15 @@ __device__ __forceinline__ double excess_link_series(double nh, double nt, doubl
   return -((nt + nh) * S + (nt - nh) * C) * inv2len;
 }
 
+// Knuth's two-sum: s + e == a + b exactly, s = fl(a + b), for any a, b (no
+// ordering of magnitudes needed; six additions, none contracted or
+// reassociated at -O3 without fast-math).
+__device__ __forceinline__ void two_sum_f(float a, float b, float &s, float &e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
 __device__ __forceinline__ void sinh_coshm1f_series(float d, float &S, float &C) {
   const float x = d * d;
   S = d * (1.f + x * (1.f / 6 + x * (1.f / 120 + x * (1.f / 5040 + x * (1.f / 362880)))));

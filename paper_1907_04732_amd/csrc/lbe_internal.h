@@ -233,23 +233,28 @@ hipError_t launch_observe_f64(hipStream_t s, const Lattice &L, const Phys &P,
                               const double *fin, double *fpre, double *u);
 int totals_blocks(const Lattice &L);
 
-// mixed form (lbe_kernels_f32.hip): h = f - w rho0 and nu = n - n_ref in FP32
+// mixed form (lbe_kernels_f32.hip): h = f - w rho0 in FP32, nu = n - n_ref as
+// the FP32 pair nu + lo.  Pass A writes its increment into dnu; pass B adds
+// it and its own to (nu, lo_in), writing the new pair to (nuio, lo_out).
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
-                            float *u, float *nustar, int tb);
+                            float *u, float *dnu, int tb);
 hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const float *u, const float *nu, float *nuio, double *src, int order,
-                           double *phi, double *prev, int tb);
+                           const float *u, const float *nu, const float *lo_in, float *nuio,
+                           float *lo_out, double *src, int order, double *phi, double *prev,
+                           int tb);
 hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
                               const uint32_t *mask, const double *phi, const float *nu,
                               const float *hin, double *fpre, double *u);
 hipError_t launch_rewind_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                             const float *nu, double *src, double *phi, double *prev, int shift);
-// n = n_ref + nu (K N doubles, species-major; 0 on solid nodes)
+                             const float *nu, const float *lo, double *src, double *phi,
+                             double *prev, int shift);
+// n = n_ref + (nu + lo) (K N doubles, species-major; 0 on solid nodes)
 hipError_t launch_expand_n_f32(hipStream_t s, const Lattice &L, const Phys &P,
-                               const uint32_t *mask, const float *nu, double *n);
+                               const uint32_t *mask, const float *nu, const float *lo, double *n);
 hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                             const float *hin, const float *nu, double *partial, double *out);
+                             const float *hin, const float *nu, const float *lo, double *partial,
+                             double *out);
 
 // reverse mode (lbe_adjoint.hip).  S: storage of the recomputed state,
 // double (FP64 form) or float (mixed form: h = f - w rho0, nu = n - n_ref).

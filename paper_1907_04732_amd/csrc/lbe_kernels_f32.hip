@@ -4,7 +4,13 @@
 // state, h_i = f_i - w_i rho0, and concentrations as deviations from a
 // reference, nu_k = n_k - n_ref,k: the physical signals (|u| ~ 1e-4, charge
 // densities ~ 1e-3 n_ref) then keep FP32's relative precision instead of
-// being rounded against the O(1) background.  The potential stays FP64: it is
+// being rounded against the O(1) background.  Each deviation is held as an
+// unevaluated FP32 pair nu = hi + lo (|lo| <= ulp(hi) / 2): the fluxes read hi
+// only, and a node's own update adds its increment to the pair with an exact
+// two-sum.  A single FP32 word loses every increment below half an ulp of
+// the value it is added to; at the large deviations inside a double layer
+// that loss is one-signed over thousands of steps, and the ion counts (hence
+// the electrode charges) drift.  The pair keeps the update to ~2^-48.  The potential stays FP64: it is
 // read once per step, and the differences phi' - phi that drive migration
 // (~1e-3 of phi) are taken in FP64 before rounding.  The Poisson source
 // (4 pi l_B / 6) rho_el is accumulated in FP64 from the FP32 deviations.
@@ -56,7 +62,7 @@ __device__ __forceinline__ void pull_f32(const Lattice &L, int r, uint32_t m, co
 
 // Pass A: each fluid link's excess flux (Eq. 10) evaluated once, used for the
 // fluid force and for the diffusion-migration flux; collision; writes h, u and
-// nu*_k = nu_k - sum_i j_k (completed by k_ions_f32).
+// the increment dnu_k = -sum_i j_k (applied by k_ions_f32).
 template <int K, int TB>
 __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
                                                      const uint32_t *__restrict__ mask,
@@ -65,7 +71,7 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
                                                      const float *__restrict__ hin,
                                                      float *__restrict__ hout,
                                                      float *__restrict__ u,
-                                                     float *__restrict__ nustar) {
+                                                     float *__restrict__ dnu) {
   const int r = xcd_block(blockIdx.x, gridDim.x, TB, L.nxy, L.xcd) * TB + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
@@ -145,18 +151,23 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
   u[N + r] = uy;
   u[2 * N + r] = uz;
 #pragma unroll
-  for (int k = 0; k < K; ++k) nustar[k * N + r] = dv[k] - js[k];
+  for (int k = 0; k < K; ++k) dnu[k * N + r] = -js[k];
 }
 
 // Pass B: advective link fluxes J_k = 3 w_i c_i . (n_k u + n_k' u') with the
-// step's velocity; nu_k(t+1) = nu*_k - sum_i J_k in place in nuio; Poisson
-// source (4 pi l_B / 6) rho_el accumulated in FP64.
+// step's velocity; the step's increment t = dnu_k - sum_i J_k (dnu_k from pass
+// A, in nuio) goes onto the pair (nu, lo_in) of nu_k(t): lo + t first (both
+// small), then the two-sum of hi with it gives the new pair, hi to nuio and lo
+// to lo_out.  Poisson source (4 pi l_B / 6) rho_el accumulated in FP64 from
+// hi + lo.
 template <int K, int TB>
 __global__ __launch_bounds__(TB) void k_ions_f32(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
                                                     const float *__restrict__ u,
                                                     const float *__restrict__ nu,
+                                                    const float *__restrict__ lo_in,
                                                     float *__restrict__ nuio,
+                                                    float *__restrict__ lo_out,
                                                     double *__restrict__ src, int order,
                                                     double *__restrict__ phi,
                                                     double *__restrict__ prev) {
@@ -170,10 +181,11 @@ __global__ __launch_bounds__(TB) void k_ions_f32(Lattice L, Phys P,
   const float ux = u[r], uy = u[N + r], uz = u[2 * N + r];
   const int sy = system_of(m);
   const float *ref = P.nref_f + 4 * sy;
-  float nr[K], Js[K];
+  float hv[K], nr[K], Js[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    nr[k] = ref[k] + nu[k * N + r];
+    hv[k] = nu[k * N + r];
+    nr[k] = ref[k] + hv[k];
     Js[k] = 0.f;
   }
   // c_i . u and the deviations at every neighbour, loaded before any is used
@@ -206,9 +218,12 @@ __global__ __launch_bounds__(TB) void k_ions_f32(Lattice L, Phys P,
   double q = P.qref[sy];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const float v = nuio[k * N + r] - Js[k];
-    nuio[k * N + r] = v;
-    q += P.z[k] * double(v);
+    const float t = lo_in[k * N + r] + (nuio[k * N + r] - Js[k]);
+    float hi, lo;
+    two_sum_f(hv[k], t, hi, lo);
+    nuio[k * N + r] = hi;
+    lo_out[k * N + r] = lo;
+    q += P.z[k] * (double(hi) + double(lo));
   }
   src[r] = P.src_scale * q;
   if (prev) extrapolate_at(r, N, order, phi, prev);
@@ -261,6 +276,7 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f32(Lattice L, Phys P,
                                                       const uint32_t *__restrict__ mask,
                                                       const float *__restrict__ hin,
                                                       const float *__restrict__ nu,
+                                                      const float *__restrict__ lo,
                                                       double *__restrict__ partial) {
   __shared__ double sm[BLOCK / WAVE];
   const int r = blockIdx.x * BLOCK + threadIdx.x;
@@ -277,9 +293,10 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f32(Lattice L, Phys P,
         v = P.rho0_d;
         for (int i = 0; i < NQ; ++i) v += double(hin[i * N + r]);
       } else if (q == 1) {
-        for (int k = 0; k < K; ++k) v += P.z[k] * (ref[k] + double(nu[k * N + r]));
+        for (int k = 0; k < K; ++k)
+          v += P.z[k] * (ref[k] + (double(nu[k * N + r]) + double(lo[k * N + r])));
       } else {
-        v = ref[q - 2] + double(nu[(q - 2) * N + r]);
+        v = ref[q - 2] + (double(nu[(q - 2) * N + r]) + double(lo[(q - 2) * N + r]));
       }
     }
     v = block_sum(v, sm);
@@ -288,12 +305,13 @@ __global__ __launch_bounds__(BLOCK) void k_totals_f32(Lattice L, Phys P,
 }
 
 // Rewind of a step whose Poisson solve failed (as k_rewind_f64): phi(t) back
-// from the copy pass B kept, the source recomputed from nu(t) as pass B forms
-// it.
+// from the copy pass B kept, the source recomputed from the pair nu(t) + lo(t)
+// as pass B forms it.
 template <int K>
 __global__ __launch_bounds__(BLOCK) void k_rewind_f32(Lattice L, Phys P,
                                                       const uint32_t *__restrict__ mask,
                                                       const float *__restrict__ nu,
+                                                      const float *__restrict__ lo,
                                                       double *__restrict__ src,
                                                       double *__restrict__ phi,
                                                       double *__restrict__ prev, int shift) {
@@ -304,24 +322,27 @@ __global__ __launch_bounds__(BLOCK) void k_rewind_f32(Lattice L, Phys P,
   const int N = L.n;
   double q = P.qref[system_of(m)];
 #pragma unroll
-  for (int k = 0; k < K; ++k) q += P.z[k] * double(nu[k * N + r]);
+  for (int k = 0; k < K; ++k) q += P.z[k] * (double(nu[k * N + r]) + double(lo[k * N + r]));
   src[r] = P.src_scale * q;
   phi[r] = prev[r];
   if (shift) prev[r] = prev[N + r];
 }
 
-// Concentrations in FP64, n = n_ref + nu on fluid nodes and 0 on solid ones
-// (species-major, as the host copy of the observables).
+// Concentrations in FP64, n = n_ref + (nu + lo) on fluid nodes and 0 on solid
+// ones (species-major, as the host copy of the observables).
 __global__ __launch_bounds__(BLOCK) void k_expand_n_f32(Lattice L, int K, const double *__restrict__ nref,
                                                         const uint32_t *__restrict__ mask,
                                                         const float *__restrict__ nu,
+                                                        const float *__restrict__ lo,
                                                         double *__restrict__ n) {
   const int r = blockIdx.x * BLOCK + threadIdx.x;
   if (r >= L.n) return;
   const uint32_t m = mask[r];
   const int N = L.n;
   for (int k = 0; k < K; ++k)
-    n[k * N + r] = (m & SOLID_BIT) ? 0.0 : nref[4 * system_of(m) + k] + double(nu[k * N + r]);
+    n[k * N + r] = (m & SOLID_BIT) ? 0.0
+                                   : nref[4 * system_of(m) + k] +
+                                         (double(nu[k * N + r]) + double(lo[k * N + r]));
 }
 
 }  // namespace
@@ -336,35 +357,37 @@ __global__ __launch_bounds__(BLOCK) void k_expand_n_f32(Lattice L, int K, const 
 
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
-                            float *u, float *nustar, int tb) {
+                            float *u, float *dnu, int tb) {
 #define CALL(KK, TB) \
-  hipLaunchKernelGGL((k_fluid_f32<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, nu, hin, hout, u, nustar)
+  hipLaunchKernelGGL((k_fluid_f32<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, nu, hin, hout, u, dnu)
   LBE_DISPATCH_K_TB(P.K, tb, CALL)
 #undef CALL
   return hipGetLastError();
 }
 
 hipError_t launch_rewind_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                             const float *nu, double *src, double *phi, double *prev, int shift) {
+                             const float *nu, const float *lo, double *src, double *phi,
+                             double *prev, int shift) {
 #define CALL(KK) \
-  hipLaunchKernelGGL(k_rewind_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, nu, src, phi, prev, shift)
+  hipLaunchKernelGGL(k_rewind_f32<KK>, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P, mask, nu, lo, src, phi, prev, shift)
   LBE_DISPATCH_K(P.K, CALL)
 #undef CALL
   return hipGetLastError();
 }
 
 hipError_t launch_expand_n_f32(hipStream_t s, const Lattice &L, const Phys &P,
-                               const uint32_t *mask, const float *nu, double *n) {
+                               const uint32_t *mask, const float *nu, const float *lo, double *n) {
   hipLaunchKernelGGL(k_expand_n_f32, dim3(blocks_for(L.n)), dim3(BLOCK), 0, s, L, P.K, P.nref_d,
-                     mask, nu, n);
+                     mask, nu, lo, n);
   return hipGetLastError();
 }
 
 hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                           const float *u, const float *nu, float *nuio, double *src, int order,
-                           double *phi, double *prev, int tb) {
+                           const float *u, const float *nu, const float *lo_in, float *nuio,
+                           float *lo_out, double *src, int order, double *phi, double *prev,
+                           int tb) {
 #define CALL(KK, TB) \
-  hipLaunchKernelGGL((k_ions_f32<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, u, nu, nuio, src, order, phi, prev)
+  hipLaunchKernelGGL((k_ions_f32<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, u, nu, lo_in, nuio, lo_out, src, order, phi, prev)
   LBE_DISPATCH_K_TB(P.K, tb, CALL)
 #undef CALL
   return hipGetLastError();
@@ -381,9 +404,10 @@ hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
 }
 
 hipError_t launch_totals_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
-                             const float *hin, const float *nu, double *partial, double *out) {
+                             const float *hin, const float *nu, const float *lo, double *partial,
+                             double *out) {
   const int nb = (int)blocks_for(L.n);
-  hipLaunchKernelGGL(k_totals_f32, dim3(nb), dim3(BLOCK), 0, s, L, P, mask, hin, nu, partial);
+  hipLaunchKernelGGL(k_totals_f32, dim3(nb), dim3(BLOCK), 0, s, L, P, mask, hin, nu, lo, partial);
   hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(FINAL), 0, s, partial, nb, 2 + P.K, out);
   return hipGetLastError();
 }
