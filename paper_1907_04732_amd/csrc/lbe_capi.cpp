@@ -61,6 +61,7 @@ struct lbe_ctx {
   bool tiles = true;          // the row-order (LDS-combined) restriction where it applies
   bool coarse_start = true;   // restriction writes the coarse level's first Jacobi sweep
   int tb_a = 256, tb_b = 256;  // block sizes of the step passes A and B (tuned at init)
+  bool nt = false;             // non-temporal streams in the step passes (set at init)
   // a time step's charge row: queued by the solve right after its predicted
   // units, gated on convergence, so it runs while the host waits
   double *charge_dst = nullptr;
@@ -1271,18 +1272,19 @@ int one_step(lbe_ctx *c, bool record = true) {
   int rc = run(c, KK_FLUID, c->L.n, [&] {
     if (c->mixed)
       return launch_fluid_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[a], c->h32[a],
-                              c->h32[b], c->u32, c->nu32[b], c->tb_a);
+                              c->h32[b], c->u32, c->nu32[b], c->tb_a, c->nt);
     return launch_fluid_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[a], c->f[a], c->f[b],
-                            c->u, c->n[b], c->tb_a);
+                            c->u, c->n[b], c->tb_a, c->nt);
   });
   if (rc) return rc;
   // pass B also moves phi to the extrapolated start of this step's solve
   rc = run(c, KK_IONS, c->L.n, [&] {
     if (c->mixed)
       return launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a], c->lo32[a],
-                             c->nu32[b], c->lo32[b], c->src, order, c->phi, keep, c->tb_b);
+                             c->nu32[b], c->lo32[b], c->src, order, c->phi, keep, c->tb_b,
+                             c->nt);
     return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a], c->n[b], c->src,
-                           order, c->phi, keep, c->tb_b);
+                           order, c->phi, keep, c->tb_b, c->nt);
   });
   if (rc) return rc;
   if (c->phi_prev) c->extrap_hist = std::min(hist + 1, 2);
@@ -1724,15 +1726,15 @@ int autotune_passes(lbe_ctx *c) {
         if (e == hipSuccess) {
           if (pass == 0)
             e = c->mixed ? launch_fluid_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[a],
-                                            c->h32[a], c->h32[b], c->u32, c->nu32[b], tb)
+                                            c->h32[a], c->h32[b], c->u32, c->nu32[b], tb, c->nt)
                          : launch_fluid_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[a],
-                                            c->f[a], c->f[b], c->u, c->n[b], tb);
+                                            c->f[a], c->f[b], c->u, c->n[b], tb, c->nt);
           else
             e = c->mixed ? launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a],
                                            c->lo32[a], c->nu32[b], c->lo32[b], src_s, -1,
-                                           c->phi, keep_s, tb)
+                                           c->phi, keep_s, tb, c->nt)
                          : launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a],
-                                           c->n[b], src_s, -1, c->phi, keep_s, tb);
+                                           c->n[b], src_s, -1, c->phi, keep_s, tb, c->nt);
         }
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -2065,6 +2067,14 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
   TRY(poisson_solve(c, false));
   TRY(record_charge(c));
   {
+    // Non-temporal streams in the step passes when the populations alone
+    // overflow the 256 MB last-level cache (measured on the 192^3 porous
+    // electrode: pass A 385 -> 368 us in FP32; on the cache-resident
+    // 64x64x130 slab they cost 7%).  LBE_NT=0|1 overrides.
+    const char *ntv = getenv("LBE_NT");
+    c->nt = ntv && *ntv ? (*ntv != '0')
+                        : (size_t)NQ * N * (c->mixed ? sizeof(float) : sizeof(double)) >
+                              ((size_t)256 << 20);
     // LBE_PASS_BLOCK=128|256|512 fixes the passes' block size; LBE_NO_AUTOTUNE
     // keeps 256; otherwise the context times the candidates
     const char *pb = getenv("LBE_PASS_BLOCK");

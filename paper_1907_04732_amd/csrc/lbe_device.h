@@ -66,6 +66,55 @@ __device__ __forceinline__ int nbr(const Offs &o, int r, int i) {
 
 __device__ __forceinline__ bool solid_link(uint32_t m, int i) { return (m >> (i - 1)) & 1u; }
 
+// a[i] with a wave-uniform base a (a kernel argument plus a uniform array
+// offset such as k N) and a lane's element index i: the byte offset stays a
+// 32-bit lane value (i sizeof(T) < 2^32 for i < LBE_MAX_SITES), so the
+// access is one scalar-base load or store with no 64-bit address arithmetic
+// per lane.
+// A wave-uniform pointer held in scalar registers (readfirstlane of both
+// halves), so that the compiler keeps it as the scalar base of ld32/st32
+// instead of folding a uniform array offset into per-lane 64-bit addresses.
+template <class T>
+__device__ __forceinline__ T *sbase(T *p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (T *)(((uint64_t)hi << 32) | lo);
+}
+
+template <class T>
+__device__ __forceinline__ T ld32(const T *a, uint32_t i) {
+  typedef __attribute__((address_space(1))) const char gchar;
+  typedef __attribute__((address_space(1))) const T gT;
+  return *(gT *)((gchar *)a + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void st32(T *a, uint32_t i, T v) {
+  typedef __attribute__((address_space(1))) char gchar;
+  typedef __attribute__((address_space(1))) T gT;
+  *(gT *)((gchar *)a + i * (uint32_t)sizeof(T)) = v;
+}
+// The step passes' streams, each written or read once per pass: with NT as
+// non-temporal accesses, which leave the caches to the neighbour data the
+// passes re-read.  That pays on lattices whose streams overflow the 256 MB
+// last-level cache; on smaller ones the next kernel would find the data
+// there, so the context picks NT by the size of its populations.
+template <bool NT, class T>
+__device__ __forceinline__ void st_stream(T *a, uint32_t i, T v) {
+  typedef __attribute__((address_space(1))) char gchar;
+  typedef __attribute__((address_space(1))) T gT;
+  gT *p = (gT *)((gchar *)a + i * (uint32_t)sizeof(T));
+  if (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+template <bool NT, class T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+  if (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+
 // v[i] = a[r + c_i] for the 19 velocities (v[0] = a[r]).  Every load is
 // unconditional (periodic neighbours are always in range) and issued before
 // any value is used, so a wave keeps all of them in flight together instead
@@ -80,14 +129,16 @@ __device__ __forceinline__ void gather(const Offs &o, int r, const T *__restrict
 // gather pre-collision populations from the pull-form array (streaming with
 // halfway bounce-back): f_i(r) = stored_i(r - c_i), or the node's own
 // opposite slot when r - c_i is solid
+template <bool NT = false>
 __device__ __forceinline__ void pull(const Lattice &L, int r, uint32_t m, const Offs &o,
                                      const double *__restrict__ fin, double (&f)[NQ]) {
   const int N = L.n;
-  f[0] = fin[r];
+  f[0] = ld_stream<NT>(&fin[r]);
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     const int j = OPP[i];
-    f[i] = fin[solid_link(m, j) ? j * N + r : i * N + nbr(o, r, j)];  // one unconditional load
+    // one unconditional load
+    f[i] = ld_stream<NT>(&fin[solid_link(m, j) ? j * N + r : i * N + nbr(o, r, j)]);
   }
 }
 
@@ -342,18 +393,27 @@ __device__ __forceinline__ float excess_link_f_series(float nh, float nt, float 
 // Warm start of the next Poisson solve at fluid node r: phi extrapolated in
 // time from the last converged potentials prev = [phi(t-1) | phi(t-2)]
 // (order 2: 3 phi - 3 p1 + p2, quadratic; 1: 2 phi - p1; 0: phi), then the
-// history shifts.  Run by the ion pass, which does not read phi.
-__device__ __forceinline__ void extrapolate_at(int r, int n, int order, double *__restrict__ phi,
+// history shifts.  Run by the ion pass, which does not read phi.  Every node
+// runs it so that each store writes whole cache lines: a solid node writes
+// its potential (the electrode's) back unchanged and zeros into the history,
+// which is never read there and starts at zero.
+__device__ __forceinline__ void extrapolate_at(int r, int n, int order, bool solid,
+                                               double *__restrict__ phi,
                                                double *__restrict__ prev) {
+  const double now = phi[r];
   if (order < 0) {  // no extrapolation: only keep phi(t)
-    prev[r] = phi[r];
+    prev[r] = now;
     return;
   }
-  const double now = phi[r], p1 = prev[r];
-  if (order >= 2) phi[r] = 3.0 * (now - p1) + prev[n + r];
-  else if (order == 1) phi[r] = 2.0 * now - p1;
-  prev[n + r] = p1;
-  prev[r] = now;
+  const double p1 = prev[r];
+  double next = now;
+  if (!solid) {
+    if (order >= 2) next = 3.0 * (now - p1) + prev[n + r];
+    else if (order == 1) next = 2.0 * now - p1;
+  }
+  phi[r] = next;
+  prev[n + r] = solid ? 0.0 : p1;
+  prev[r] = solid ? 0.0 : now;
 }
 
 inline unsigned blocks_for(long n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
@@ -373,6 +433,27 @@ inline unsigned blocks_for(long n) { return (unsigned)((n + BLOCK - 1) / BLOCK);
     case 2: LBE_DISPATCH_TB(2, TBV, CALL) break;  \
     case 3: LBE_DISPATCH_TB(3, TBV, CALL) break;  \
     default: LBE_DISPATCH_TB(4, TBV, CALL) break; \
+  }
+// ... and with the stream kind of the step passes: CALL(KK, TB, NT), NT
+// true for non-temporal population and output streams
+#define LBE_DISPATCH_TB_NT(KK, TBV, NT, CALL) \
+  switch (TBV) {                              \
+    case 128: CALL(KK, 128, NT); break;       \
+    case 512: CALL(KK, 512, NT); break;       \
+    default: CALL(KK, 256, NT); break;        \
+  }
+#define LBE_DISPATCH_K_NT(K, TBV, NT, CALL)               \
+  switch (K) {                                            \
+    case 1: LBE_DISPATCH_TB_NT(1, TBV, NT, CALL) break;   \
+    case 2: LBE_DISPATCH_TB_NT(2, TBV, NT, CALL) break;   \
+    case 3: LBE_DISPATCH_TB_NT(3, TBV, NT, CALL) break;   \
+    default: LBE_DISPATCH_TB_NT(4, TBV, NT, CALL) break;  \
+  }
+#define LBE_DISPATCH_K_TB_NT(K, TBV, NTV, CALL) \
+  if (NTV) {                                    \
+    LBE_DISPATCH_K_NT(K, TBV, true, CALL)       \
+  } else {                                      \
+    LBE_DISPATCH_K_NT(K, TBV, false, CALL)      \
   }
 
 }  // namespace

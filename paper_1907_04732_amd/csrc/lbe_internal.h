@@ -185,8 +185,8 @@ extern const char *const kKernelNames[KK_COUNT];
 // n* = n - (diffusion-migration outflow) into nstar.
 hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const double *n, const double *fin, double *fout,
-                            double *u, double *nstar, int tb);
-// tb: block size of the step passes (128, 256 or 512).
+                            double *u, double *nstar, int tb, bool nt);
+// tb: block size of the step passes (128, 256 or 512); nt: non-temporal streams.
 // Step pass B: advective outflow with u; nio holds n* on entry, n(t+1) on exit.
 // With prev = [phi(t-1) | phi(t-2)] (2 N; NULL: none) it also moves phi to
 // its extrapolation in time of the given order (0 constant, 1 linear, 2
@@ -194,7 +194,7 @@ hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, cons
 // (prev: N) only copies phi(t) into prev.
 hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                            const double *u, const double *n, double *nio, double *src, int order,
-                           double *phi, double *prev, int tb);
+                           double *phi, double *prev, int tb, bool nt);
 // A step's solve failed: phi = prev[0..N) (phi(t), kept by pass B), the
 // source recomputed from n(t), and with shift prev[0..N) = prev[N..2N)
 // (the extrapolation history back by one step).  Fluid nodes only.
@@ -238,11 +238,11 @@ int totals_blocks(const Lattice &L);
 // it and its own to (nu, lo_in), writing the new pair to (nuio, lo_out).
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
-                            float *u, float *dnu, int tb);
+                            float *u, float *dnu, int tb, bool nt);
 hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                            const float *u, const float *nu, const float *lo_in, float *nuio,
                            float *lo_out, double *src, int order, double *phi, double *prev,
-                           int tb);
+                           int tb, bool nt);
 hipError_t launch_observe_f32(hipStream_t s, const Lattice &L, const Phys &P,
                               const uint32_t *mask, const double *phi, const float *nu,
                               const float *hin, double *fpre, double *u);

@@ -60,7 +60,7 @@ __device__ __forceinline__ void link_force(const Lattice &L, const Phys &P, int 
 // diffusion-migration flux j_k = D_k/A0 (g_k - (n_k' - n_k)/Delta_i).  Writes
 // post-collision f, u, and n*_k = n_k - sum_i j_k (completed by pass B).
 
-template <int K, int TB>
+template <int K, int TB, bool NT>
 __global__ __launch_bounds__(TB) void k_fluid_f64(Lattice L, Phys P,
                                                      const uint32_t *__restrict__ mask,
                                                      const double *__restrict__ phi,
@@ -71,81 +71,105 @@ __global__ __launch_bounds__(TB) void k_fluid_f64(Lattice L, Phys P,
                                                      double *__restrict__ nstar) {
   const int r = xcd_block(blockIdx.x, gridDim.x, TB, L.nxy, L.xcd) * TB + threadIdx.x;
   if (r >= L.n) return;
-  const uint32_t m = mask[r];
-  if (m & SOLID_BIT) return;
   const int N = L.n;
-  Offs o;
-  site_offsets(L, r, o);
-  const double ph = phi[r];
-  double nr[K], js[K];
+  const uint32_t m = mask[r];
+  // Every node stores all its outputs in the same store instructions, a
+  // solid node the zeros its slots hold from the start (they are never
+  // read): each store then writes whole cache lines, which costs far less
+  // than the part-filled lines of a store from the fluid nodes alone.
+  double fn[NQ], nso[K], ux = 0.0, uy = 0.0, uz = 0.0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    nr[k] = n[k * N + r];
-    js[k] = 0.0;
-  }
-  double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+  for (int i = 0; i < NQ; ++i) fn[i] = 0.0;
 #pragma unroll
-  for (int i = 1; i < NQ; ++i) {
-    if (solid_link(m, i)) continue;  // no flux into an electrode
-    const int rn = nbr(o, r, i);
-    const double dphi = phi[rn] - ph - P.Ec[i];
-    double S1, C1;
-    sinh_coshm1(dphi, S1, C1);
-    double g = 0.0;
+  for (int k = 0; k < K; ++k) nso[k] = 0.0;
+  if (!(m & SOLID_BIT)) {
+    Offs o;
+    site_offsets(L, r, o);
+    const double ph = phi[r];
+    double nr[K], js[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const double nt = n[k * N + rn];
-      double S, C;
-      valence_sc(P.z[k], dphi, S1, C1, S, C);
-      const double gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * (0.5 / LEN[i]);
-      g += gk;
-      js[k] += P.dk[k] * (gk - (nt - nr[k]) / LEN[i]);
+      nr[k] = n[k * N + r];
+      js[k] = 0.0;
     }
-    const double c = 3.0 * WQ[i] * LEN[i] * g;
-    if (CX[i]) F0 += CX[i] * c;
-    if (CY[i]) F1 += CY[i] * c;
-    if (CZ[i]) F2 += CZ[i] * c;
-  }
+    // every neighbour's potential and concentrations first, solid
+    // neighbours too (their links are skipped below): all 18 (1 + K) gathers
+    // are then in flight together rather than one link's at a time
+    double pn[NQ], nn[K][NQ];
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      const uint32_t rn = nbr(o, r, i);
+      pn[i] = ld32(phi, rn);
+#pragma unroll
+      for (int k = 0; k < K; ++k) nn[k][i] = ld32(sbase(n + k * N), rn);
+    }
+    double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      if (solid_link(m, i)) continue;  // no flux into an electrode
+      const double dphi = pn[i] - ph - P.Ec[i];
+      double S1, C1;
+      sinh_coshm1(dphi, S1, C1);
+      double g = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double nt = nn[k][i];
+        double S, C;
+        valence_sc(P.z[k], dphi, S1, C1, S, C);
+        const double gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * (0.5 / LEN[i]);
+        g += gk;
+        js[k] += P.dk[k] * (gk - (nt - nr[k]) / LEN[i]);
+      }
+      const double c = 3.0 * WQ[i] * LEN[i] * g;
+      if (CX[i]) F0 += CX[i] * c;
+      if (CY[i]) F1 += CY[i] * c;
+      if (CZ[i]) F2 += CZ[i] * c;
+    }
 
-  double f[NQ];
-  pull(L, r, m, o, fin, f);
-  double rho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    double f[NQ];
+    pull<NT>(L, r, m, o, fin, f);
+    double rho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    rho += f[i];
-    if (CX[i]) m0 += CX[i] * f[i];
-    if (CY[i]) m1 += CY[i] * f[i];
-    if (CZ[i]) m2 += CZ[i] * f[i];
+    for (int i = 0; i < NQ; ++i) {
+      rho += f[i];
+      if (CX[i]) m0 += CX[i] * f[i];
+      if (CY[i]) m1 += CY[i] * f[i];
+      if (CZ[i]) m2 += CZ[i] * f[i];
+    }
+    // Guo forcing: velocity with the half-force shift
+    ux = (m0 + 0.5 * F0) / rho;
+    uy = (m1 + 0.5 * F1) / rho;
+    uz = (m2 + 0.5 * F2) / rho;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double itau = 1.0 / P.tau;
+    const double guo = 1.0 - 0.5 * itau;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+      const double feq = WQ[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+      const double s = ((3.0 * (CX[i] - ux) + 9.0 * cu * CX[i]) * F0 +
+                        (3.0 * (CY[i] - uy) + 9.0 * cu * CY[i]) * F1 +
+                        (3.0 * (CZ[i] - uz) + 9.0 * cu * CZ[i]) * F2) *
+                       (guo * WQ[i]);
+      fn[i] = f[i] - (f[i] - feq) * itau + s;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) nso[k] = nr[k] - js[k];
   }
-  // Guo forcing: velocity with the half-force shift
-  const double ux = (m0 + 0.5 * F0) / rho;
-  const double uy = (m1 + 0.5 * F1) / rho;
-  const double uz = (m2 + 0.5 * F2) / rho;
-  const double uu = ux * ux + uy * uy + uz * uz;
-  const double itau = 1.0 / P.tau;
-  const double guo = 1.0 - 0.5 * itau;
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-    const double feq = WQ[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-    const double s = ((3.0 * (CX[i] - ux) + 9.0 * cu * CX[i]) * F0 +
-                      (3.0 * (CY[i] - uy) + 9.0 * cu * CY[i]) * F1 +
-                      (3.0 * (CZ[i] - uz) + 9.0 * cu * CZ[i]) * F2) *
-                     (guo * WQ[i]);
-    fout[i * N + r] = f[i] - (f[i] - feq) * itau + s;
-  }
-  u[r] = ux;
-  u[N + r] = uy;
-  u[2 * N + r] = uz;
+  for (int i = 0; i < NQ; ++i) st_stream<NT>(sbase(fout + i * N), r, fn[i]);
+  st_stream<NT>(u, r, ux);
+  st_stream<NT>(sbase(u + N), r, uy);
+  st_stream<NT>(sbase(u + 2 * N), r, uz);
 #pragma unroll
-  for (int k = 0; k < K; ++k) nstar[k * N + r] = nr[k] - js[k];
+  for (int k = 0; k < K; ++k) st_stream<NT>(sbase(nstar + k * N), r, nso[k]);
 }
 
 // ---- pass B: advective link fluxes with the step's velocity, new n and
 // Poisson source.  J_k = 3 w_i c_i . (n_k u + n_k' u') on every fluid link;
 // n_k(t+1) = n*_k - sum_i J_k, updated in place in nio. -------------------
 
-template <int K, int TB>
+template <int K, int TB, bool NT>
 __global__ __launch_bounds__(TB) void k_ions_f64(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
                                                     const double *__restrict__ u,
@@ -156,38 +180,58 @@ __global__ __launch_bounds__(TB) void k_ions_f64(Lattice L, Phys P,
                                                     double *__restrict__ prev) {
   const int r = xcd_block(blockIdx.x, gridDim.x, TB, L.nxy, L.xcd) * TB + threadIdx.x;
   if (r >= L.n) return;
-  const uint32_t m = mask[r];
-  if (m & SOLID_BIT) return;
   const int N = L.n;
-  Offs o;
-  site_offsets(L, r, o);
-  const double ux = u[r], uy = u[N + r], uz = u[2 * N + r];
-  double nr[K], Js[K];
+  const uint32_t m = mask[r];
+  const bool solid = m & SOLID_BIT;
+  // all nodes store, as in pass A (a solid node its zeros)
+  double no[K], q = 0.0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    nr[k] = n[k * N + r];
-    Js[k] = 0.0;
+  for (int k = 0; k < K; ++k) no[k] = 0.0;
+  if (!solid) {
+    Offs o;
+    site_offsets(L, r, o);
+    const double ux = u[r], uy = u[N + r], uz = u[2 * N + r];
+    double nr[K], Js[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      nr[k] = n[k * N + r];
+      Js[k] = 0.0;
+    }
+    // c_i . u and the concentrations at every neighbour, loaded before any
+    // is used (solid neighbours too, skipped below)
+    double cut[NQ], nn[K][NQ];
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      const uint32_t rn = nbr(o, r, i);
+      double c = 0.0;
+      if (CX[i]) c += CX[i] * ld32(u, rn);
+      if (CY[i]) c += CY[i] * ld32(sbase(u + N), rn);
+      if (CZ[i]) c += CZ[i] * ld32(sbase(u + 2 * N), rn);
+      cut[i] = c;
+#pragma unroll
+      for (int k = 0; k < K; ++k) nn[k][i] = ld32(sbase(n + k * N), rn);
+    }
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      if (solid_link(m, i)) continue;
+      double cu_h = 0.0;
+      if (CX[i]) cu_h += CX[i] * ux;
+      if (CY[i]) cu_h += CY[i] * uy;
+      if (CZ[i]) cu_h += CZ[i] * uz;
+      const double cu_t = cut[i];
+#pragma unroll
+      for (int k = 0; k < K; ++k) Js[k] += 3.0 * WQ[i] * (nr[k] * cu_h + nn[k][i] * cu_t);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      no[k] = nio[k * N + r] - Js[k];
+      q += P.z[k] * no[k];
+    }
   }
 #pragma unroll
-  for (int i = 1; i < NQ; ++i) {
-    if (solid_link(m, i)) continue;
-    const int rn = nbr(o, r, i);
-    double cu_h = 0.0, cu_t = 0.0;
-    if (CX[i]) { cu_h += CX[i] * ux; cu_t += CX[i] * u[rn]; }
-    if (CY[i]) { cu_h += CY[i] * uy; cu_t += CY[i] * u[N + rn]; }
-    if (CZ[i]) { cu_h += CZ[i] * uz; cu_t += CZ[i] * u[2 * N + rn]; }
-#pragma unroll
-    for (int k = 0; k < K; ++k) Js[k] += 3.0 * WQ[i] * (nr[k] * cu_h + n[k * N + rn] * cu_t);
-  }
-  double q = 0.0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const double v = nio[k * N + r] - Js[k];
-    nio[k * N + r] = v;
-    q += P.z[k] * v;
-  }
-  src[r] = P.src_scale * q;
-  if (prev) extrapolate_at(r, N, order, phi, prev);
+  for (int k = 0; k < K; ++k) st_stream<NT>(sbase(nio + k * N), r, no[k]);
+  st_stream<NT>(src, r, P.src_scale * q);
+  if (prev) extrapolate_at(r, N, order, solid, phi, prev);
 }
 
 // ---- Poisson: one colour of the four-colour SOR sweep (Eqs. 13, 15) --------
@@ -473,20 +517,20 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(int count, const int *__restr
 
 hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const double *n, const double *fin, double *fout,
-                            double *u, double *nstar, int tb) {
-#define CALL(KK, TB) \
-  hipLaunchKernelGGL((k_fluid_f64<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, n, fin, fout, u, nstar)
-  LBE_DISPATCH_K_TB(P.K, tb, CALL)
+                            double *u, double *nstar, int tb, bool nt) {
+#define CALL(KK, TB, NT) \
+  hipLaunchKernelGGL((k_fluid_f64<KK, TB, NT>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, n, fin, fout, u, nstar)
+  LBE_DISPATCH_K_TB_NT(P.K, tb, nt, CALL)
 #undef CALL
   return hipGetLastError();
 }
 
 hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                            const double *u, const double *n, double *nio, double *src, int order,
-                           double *phi, double *prev, int tb) {
-#define CALL(KK, TB) \
-  hipLaunchKernelGGL((k_ions_f64<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, u, n, nio, src, order, phi, prev)
-  LBE_DISPATCH_K_TB(P.K, tb, CALL)
+                           double *phi, double *prev, int tb, bool nt) {
+#define CALL(KK, TB, NT) \
+  hipLaunchKernelGGL((k_ions_f64<KK, TB, NT>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, u, n, nio, src, order, phi, prev)
+  LBE_DISPATCH_K_TB_NT(P.K, tb, nt, CALL)
 #undef CALL
   return hipGetLastError();
 }

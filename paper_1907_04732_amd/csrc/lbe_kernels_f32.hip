@@ -48,22 +48,24 @@ __device__ __forceinline__ void link_force_f32(const Lattice &L, const Phys &P, 
   }
 }
 
-// the source slot is selected, not the load, so all 19 loads are unconditional
+// the source slot is selected, not the load, so all 19 loads are
+// unconditional
+template <bool NT = false>
 __device__ __forceinline__ void pull_f32(const Lattice &L, int r, uint32_t m, const Offs &o,
                                          const float *__restrict__ hin, float (&h)[NQ]) {
   const int N = L.n;
-  h[0] = hin[r];
+  h[0] = ld_stream<NT>(&hin[r]);
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     const int j = OPP[i];
-    h[i] = hin[solid_link(m, j) ? j * N + r : i * N + nbr(o, r, j)];
+    h[i] = ld_stream<NT>(&hin[solid_link(m, j) ? j * N + r : i * N + nbr(o, r, j)]);
   }
 }
 
 // Pass A: each fluid link's excess flux (Eq. 10) evaluated once, used for the
 // fluid force and for the diffusion-migration flux; collision; writes h, u and
 // the increment dnu_k = -sum_i j_k (applied by k_ions_f32).
-template <int K, int TB>
+template <int K, int TB, bool NT>
 __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
                                                      const uint32_t *__restrict__ mask,
                                                      const double *__restrict__ phi,
@@ -74,84 +76,111 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
                                                      float *__restrict__ dnu) {
   const int r = xcd_block(blockIdx.x, gridDim.x, TB, L.nxy, L.xcd) * TB + threadIdx.x;
   if (r >= L.n) return;
-  const uint32_t m = mask[r];
-  if (m & SOLID_BIT) return;
   const int N = L.n;
-  Offs o;
-  site_offsets(L, r, o);
-  const double ph = phi[r];
-  // deviation reference of this node's system (fluid neighbours share it)
-  const float *ref = P.nref_f + 4 * system_of(m);
-  float dv[K], nr[K], js[K];
+  const uint32_t m = mask[r];
+  // Every node stores all its outputs in the same store instructions, a
+  // solid node the zeros its slots hold from the start (they are never
+  // read): each store then writes whole cache lines, which costs far less
+  // than the part-filled lines of a store from the fluid nodes alone.
+  float hn[NQ], dno[K], ux = 0.f, uy = 0.f, uz = 0.f;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    dv[k] = nu[k * N + r];
-    nr[k] = ref[k] + dv[k];
-    js[k] = 0.f;
-  }
-  float F0 = 0.f, F1 = 0.f, F2 = 0.f;
+  for (int i = 0; i < NQ; ++i) hn[i] = 0.f;
 #pragma unroll
-  for (int i = 1; i < NQ; ++i) {
-    if (solid_link(m, i)) continue;  // no flux into an electrode
-    const int rn = nbr(o, r, i);
-    const double dphi = phi[rn] - ph - P.Ec[i];
-    const float d1 = float(dphi);
-    float S1, C1;
-    sinh_coshm1f(d1, S1, C1);
-    const float il = float(1.0 / LEN[i]);
-    float g = 0.f;
+  for (int k = 0; k < K; ++k) dno[k] = 0.f;
+  if (!(m & SOLID_BIT)) {
+    Offs o;
+    site_offsets(L, r, o);
+    const double ph = phi[r];
+    // deviation reference of this node's system (fluid neighbours share
+    // it), held in registers: the link loop adds it at every neighbour
+    const float *refp = P.nref_f + 4 * system_of(m);
+    float ref[K], dv[K], nr[K], js[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const float dn = nu[k * N + rn];
-      const float nt = ref[k] + dn;
-      float S, C;
-      valence_scf(P.z[k], dphi, d1, S1, C1, S, C);
-      const float gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * float(0.5 / LEN[i]);
-      g += gk;
-      // the ideal part uses the deviations directly: (n' - n) = (nu' - nu)
-      js[k] += P.dk_f[k] * (gk - (dn - dv[k]) * il);
+      ref[k] = refp[k];
+      dv[k] = nu[k * N + r];
+      nr[k] = ref[k] + dv[k];
+      js[k] = 0.f;
     }
-    const float c = float(3.0 * WQ[i] * LEN[i]) * g;
-    if (CX[i]) F0 += CX[i] * c;
-    if (CY[i]) F1 += CY[i] * c;
-    if (CZ[i]) F2 += CZ[i] * c;
-  }
+    // every neighbour's potential and deviations first, solid neighbours
+    // too (their links are skipped below): all 18 (1 + K) gathers are then
+    // in flight together rather than one link's at a time behind a branch
+    double pn[NQ];
+    float nn[K][NQ];
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      const uint32_t rn = nbr(o, r, i);
+      pn[i] = ld32(phi, rn);
+#pragma unroll
+      for (int k = 0; k < K; ++k) nn[k][i] = ld32(sbase(nu + k * N), rn);
+    }
+    float F0 = 0.f, F1 = 0.f, F2 = 0.f;
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      if (solid_link(m, i)) continue;  // no flux into an electrode
+      const double dphi = pn[i] - ph - P.Ec[i];
+      const float d1 = float(dphi);
+      float S1, C1;
+      sinh_coshm1f(d1, S1, C1);
+      const float il = float(1.0 / LEN[i]);
+      float g = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float dn = nn[k][i];
+        const float nt = ref[k] + dn;
+        float S, C;
+        valence_scf(P.z[k], dphi, d1, S1, C1, S, C);
+        const float gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * float(0.5 / LEN[i]);
+        g += gk;
+        // the ideal part uses the deviations directly: (n' - n) = (nu' - nu)
+        js[k] += P.dk_f[k] * (gk - (dn - dv[k]) * il);
+      }
+      const float c = float(3.0 * WQ[i] * LEN[i]) * g;
+      if (CX[i]) F0 += CX[i] * c;
+      if (CY[i]) F1 += CY[i] * c;
+      if (CZ[i]) F2 += CZ[i] * c;
+    }
 
-  float h[NQ];
-  pull_f32(L, r, m, o, hin, h);
-  float drho = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
+    float h[NQ];
+    pull_f32<NT>(L, r, m, o, hin, h);
+    float drho = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    drho += h[i];
-    if (CX[i]) m0 += CX[i] * h[i];
-    if (CY[i]) m1 += CY[i] * h[i];
-    if (CZ[i]) m2 += CZ[i] * h[i];
+    for (int i = 0; i < NQ; ++i) {
+      drho += h[i];
+      if (CX[i]) m0 += CX[i] * h[i];
+      if (CY[i]) m1 += CY[i] * h[i];
+      if (CZ[i]) m2 += CZ[i] * h[i];
+    }
+    // sum_i w_i rho0 c_i = 0, so the momentum is carried by the deviations
+    const float rho = P.rho0_f + drho;
+    ux = (m0 + 0.5f * F0) / rho;
+    uy = (m1 + 0.5f * F1) / rho;
+    uz = (m2 + 0.5f * F2) / rho;
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float itau = P.itau_f;
+    const float guo = 1.f - 0.5f * itau;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+      const float w = float(WQ[i]);
+      const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+      // equilibrium minus the rest state w_i rho0
+      const float heq = w * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+      const float s = ((3.f * (CX[i] - ux) + 9.f * cu * CX[i]) * F0 +
+                       (3.f * (CY[i] - uy) + 9.f * cu * CY[i]) * F1 +
+                       (3.f * (CZ[i] - uz) + 9.f * cu * CZ[i]) * F2) *
+                      (guo * w);
+      hn[i] = h[i] - (h[i] - heq) * itau + s;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) dno[k] = -js[k];
   }
-  // sum_i w_i rho0 c_i = 0, so the momentum is carried by the deviations
-  const float rho = P.rho0_f + drho;
-  const float ux = (m0 + 0.5f * F0) / rho;
-  const float uy = (m1 + 0.5f * F1) / rho;
-  const float uz = (m2 + 0.5f * F2) / rho;
-  const float uu = ux * ux + uy * uy + uz * uz;
-  const float itau = P.itau_f;
-  const float guo = 1.f - 0.5f * itau;
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) {
-    const float w = float(WQ[i]);
-    const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-    // equilibrium minus the rest state w_i rho0
-    const float heq = w * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-    const float s = ((3.f * (CX[i] - ux) + 9.f * cu * CX[i]) * F0 +
-                     (3.f * (CY[i] - uy) + 9.f * cu * CY[i]) * F1 +
-                     (3.f * (CZ[i] - uz) + 9.f * cu * CZ[i]) * F2) *
-                    (guo * w);
-    hout[i * N + r] = h[i] - (h[i] - heq) * itau + s;
-  }
-  u[r] = ux;
-  u[N + r] = uy;
-  u[2 * N + r] = uz;
+  for (int i = 0; i < NQ; ++i) st_stream<NT>(sbase(hout + i * N), r, hn[i]);
+  st_stream<NT>(u, r, ux);
+  st_stream<NT>(sbase(u + N), r, uy);
+  st_stream<NT>(sbase(u + 2 * N), r, uz);
 #pragma unroll
-  for (int k = 0; k < K; ++k) dnu[k * N + r] = -js[k];
+  for (int k = 0; k < K; ++k) st_stream<NT>(sbase(dnu + k * N), r, dno[k]);
 }
 
 // Pass B: advective link fluxes J_k = 3 w_i c_i . (n_k u + n_k' u') with the
@@ -160,7 +189,7 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
 // small), then the two-sum of hi with it gives the new pair, hi to nuio and lo
 // to lo_out.  Poisson source (4 pi l_B / 6) rho_el accumulated in FP64 from
 // hi + lo.
-template <int K, int TB>
+template <int K, int TB, bool NT>
 __global__ __launch_bounds__(TB) void k_ions_f32(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
                                                     const float *__restrict__ u,
@@ -173,60 +202,69 @@ __global__ __launch_bounds__(TB) void k_ions_f32(Lattice L, Phys P,
                                                     double *__restrict__ prev) {
   const int r = blockIdx.x * TB + threadIdx.x;
   if (r >= L.n) return;
-  const uint32_t m = mask[r];
-  if (m & SOLID_BIT) return;
   const int N = L.n;
-  Offs o;
-  site_offsets(L, r, o);
-  const float ux = u[r], uy = u[N + r], uz = u[2 * N + r];
-  const int sy = system_of(m);
-  const float *ref = P.nref_f + 4 * sy;
-  float hv[K], nr[K], Js[K];
+  const uint32_t m = mask[r];
+  const bool solid = m & SOLID_BIT;
+  // all nodes store, as in pass A (a solid node its zeros)
+  float hio[K], loo[K];
+  double q = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) hio[k] = loo[k] = 0.f;
+  if (!solid) {
+    Offs o;
+    site_offsets(L, r, o);
+    const float ux = u[r], uy = u[N + r], uz = u[2 * N + r];
+    const int sy = system_of(m);
+    const float *ref = P.nref_f + 4 * sy;
+    float hv[K], nr[K], Js[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      hv[k] = nu[k * N + r];
+      nr[k] = ref[k] + hv[k];
+      Js[k] = 0.f;
+    }
+    // c_i . u and the deviations at every neighbour, loaded before any is
+    // used (solid neighbours too, skipped below)
+    float cut[NQ], nn[K][NQ];
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      const uint32_t rn = nbr(o, r, i);
+      float c = 0.f;
+      if (CX[i]) c += CX[i] * ld32(u, rn);
+      if (CY[i]) c += CY[i] * ld32(sbase(u + N), rn);
+      if (CZ[i]) c += CZ[i] * ld32(sbase(u + 2 * N), rn);
+      cut[i] = c;
+#pragma unroll
+      for (int k = 0; k < K; ++k) nn[k][i] = ld32(sbase(nu + k * N), rn);
+    }
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      if (solid_link(m, i)) continue;
+      float cu_h = 0.f;
+      if (CX[i]) cu_h += CX[i] * ux;
+      if (CY[i]) cu_h += CY[i] * uy;
+      if (CZ[i]) cu_h += CZ[i] * uz;
+      const float cu_t = cut[i];
+      const float w3 = float(3.0 * WQ[i]);
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        Js[k] += w3 * (nr[k] * cu_h + (ref[k] + nn[k][i]) * cu_t);
+    }
+    q = P.qref[sy];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float t = lo_in[k * N + r] + (nuio[k * N + r] - Js[k]);
+      two_sum_f(hv[k], t, hio[k], loo[k]);
+      q += P.z[k] * (double(hio[k]) + double(loo[k]));
+    }
+  }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    hv[k] = nu[k * N + r];
-    nr[k] = ref[k] + hv[k];
-    Js[k] = 0.f;
+    st_stream<NT>(sbase(nuio + k * N), r, hio[k]);
+    st_stream<NT>(sbase(lo_out + k * N), r, loo[k]);
   }
-  // c_i . u and the deviations at every neighbour, loaded before any is used
-  // (solid neighbours too, skipped below)
-  float cut[NQ], nn[K][NQ];
-#pragma unroll
-  for (int i = 1; i < NQ; ++i) {
-    const int rn = nbr(o, r, i);
-    float c = 0.f;
-    if (CX[i]) c += CX[i] * u[rn];
-    if (CY[i]) c += CY[i] * u[N + rn];
-    if (CZ[i]) c += CZ[i] * u[2 * N + rn];
-    cut[i] = c;
-#pragma unroll
-    for (int k = 0; k < K; ++k) nn[k][i] = nu[k * N + rn];
-  }
-#pragma unroll
-  for (int i = 1; i < NQ; ++i) {
-    if (solid_link(m, i)) continue;
-    float cu_h = 0.f;
-    if (CX[i]) cu_h += CX[i] * ux;
-    if (CY[i]) cu_h += CY[i] * uy;
-    if (CZ[i]) cu_h += CZ[i] * uz;
-    const float cu_t = cut[i];
-    const float w3 = float(3.0 * WQ[i]);
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      Js[k] += w3 * (nr[k] * cu_h + (ref[k] + nn[k][i]) * cu_t);
-  }
-  double q = P.qref[sy];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const float t = lo_in[k * N + r] + (nuio[k * N + r] - Js[k]);
-    float hi, lo;
-    two_sum_f(hv[k], t, hi, lo);
-    nuio[k * N + r] = hi;
-    lo_out[k * N + r] = lo;
-    q += P.z[k] * (double(hi) + double(lo));
-  }
-  src[r] = P.src_scale * q;
-  if (prev) extrapolate_at(r, N, order, phi, prev);
+  st_stream<NT>(src, r, P.src_scale * q);
+  if (prev) extrapolate_at(r, N, order, solid, phi, prev);
 }
 
 template <int K>
@@ -357,10 +395,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand_n_f32(Lattice L, int K, const 
 
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
-                            float *u, float *dnu, int tb) {
-#define CALL(KK, TB) \
-  hipLaunchKernelGGL((k_fluid_f32<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, nu, hin, hout, u, dnu)
-  LBE_DISPATCH_K_TB(P.K, tb, CALL)
+                            float *u, float *dnu, int tb, bool nt) {
+#define CALL(KK, TB, NT) \
+  hipLaunchKernelGGL((k_fluid_f32<KK, TB, NT>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, nu, hin, hout, u, dnu)
+  LBE_DISPATCH_K_TB_NT(P.K, tb, nt, CALL)
 #undef CALL
   return hipGetLastError();
 }
@@ -385,10 +423,10 @@ hipError_t launch_expand_n_f32(hipStream_t s, const Lattice &L, const Phys &P,
 hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                            const float *u, const float *nu, const float *lo_in, float *nuio,
                            float *lo_out, double *src, int order, double *phi, double *prev,
-                           int tb) {
-#define CALL(KK, TB) \
-  hipLaunchKernelGGL((k_ions_f32<KK, TB>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, u, nu, lo_in, nuio, lo_out, src, order, phi, prev)
-  LBE_DISPATCH_K_TB(P.K, tb, CALL)
+                           int tb, bool nt) {
+#define CALL(KK, TB, NT) \
+  hipLaunchKernelGGL((k_ions_f32<KK, TB, NT>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, u, nu, lo_in, nuio, lo_out, src, order, phi, prev)
+  LBE_DISPATCH_K_TB_NT(P.K, tb, nt, CALL)
 #undef CALL
   return hipGetLastError();
 }
