@@ -1889,6 +1889,9 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
         c->nref_h[(size_t)sy * 4 + k] = ref;
       }
     for (int k = 0; k < K; ++k) c->P.dk_f[k] = (float)c->P.dk[k];
+    c->P.unit_z = 1;
+    for (int k = 0; k < K; ++k)
+      if (p.z[k] != 1 && p.z[k] != -1) c->P.unit_z = 0;
     c->P.rho0_d = p.rho0;
     c->P.rho0_f = (float)p.rho0;
     c->P.itau_f = (float)(1.0 / p.tau);

@@ -66,8 +66,10 @@ __device__ __forceinline__ int nbr(const Offs &o, int r, int i) {
 
 __device__ __forceinline__ bool solid_link(uint32_t m, int i) { return (m >> (i - 1)) & 1u; }
 
-// a[i] with a wave-uniform base a (a kernel argument plus a uniform array
-// offset such as k N) and a lane's element index i: the byte offset stays a
+// a[i] for an array in global memory (never LDS: the pointer is taken as a
+// global one) with a wave-uniform base a (a kernel argument plus a uniform
+// array offset such as k N) and a lane's element index i: the byte offset
+// stays a
 // 32-bit lane value (i sizeof(T) < 2^32 for i < LBE_MAX_SITES), so the
 // access is one scalar-base load or store with no 64-bit address arithmetic
 // per lane.

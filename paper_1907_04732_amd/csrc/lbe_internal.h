@@ -63,6 +63,7 @@ struct Phys {
   const double *qref;    // sum_k z_k n_ref,k of system s at [s] (device)
   float rho0_f, itau_f;
   float dk_f[4];
+  int unit_z;            // every species has |z| = 1 (the mixed form's fast link loop)
 };
 
 // One multigrid level (cell-centred; spacing h = 2^level in fine units).

@@ -114,31 +114,72 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
 #pragma unroll
       for (int k = 0; k < K; ++k) nn[k][i] = ld32(sbase(nu + k * N), rn);
     }
-    float F0 = 0.f, F1 = 0.f, F2 = 0.f;
+    // Each link's potential difference in FP64, rounded once.  When every
+    // species has |z| = 1 and every fluid link of the wave lies in the
+    // series range (a wave-wide vote), the links run without a branch: a
+    // wall link's terms are computed from the electrode's values and
+    // multiplied by zero (no flux into an electrode).  Otherwise the loop
+    // below takes each link's own path.
+    float dl[NQ];
+    float dmax = 0.f;
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
-      if (solid_link(m, i)) continue;  // no flux into an electrode
-      const double dphi = pn[i] - ph - P.Ec[i];
-      const float d1 = float(dphi);
-      float S1, C1;
-      sinh_coshm1f(d1, S1, C1);
-      const float il = float(1.0 / LEN[i]);
-      float g = 0.f;
+      dl[i] = solid_link(m, i) ? 0.f : float(pn[i] - ph - P.Ec[i]);
+      dmax = fmaxf(dmax, fabsf(dl[i]));
+    }
+    const bool fast = P.unit_z && __all(dmax <= float(TAYLOR_MAX));
+    float F0 = 0.f, F1 = 0.f, F2 = 0.f;
+    if (fast) {
+      float zf[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const float dn = nn[k][i];
-        const float nt = ref[k] + dn;
-        float S, C;
-        valence_scf(P.z[k], dphi, d1, S1, C1, S, C);
-        const float gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * float(0.5 / LEN[i]);
-        g += gk;
-        // the ideal part uses the deviations directly: (n' - n) = (nu' - nu)
-        js[k] += P.dk_f[k] * (gk - (dn - dv[k]) * il);
+      for (int k = 0; k < K; ++k) zf[k] = float(P.z[k]);
+#pragma unroll
+      for (int i = 1; i < NQ; ++i) {
+        const float open = solid_link(m, i) ? 0.f : 1.f;
+        float S1, C1;
+        sinh_coshm1f_series(dl[i], S1, C1);
+        const float il = float(1.0 / LEN[i]);
+        float g = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float dn = nn[k][i];
+          const float nt = ref[k] + dn;
+          const float gk = -((nt + nr[k]) * (zf[k] * S1) + (nt - nr[k]) * C1) *
+                           float(0.5 / LEN[i]);
+          g += gk;
+          // the ideal part uses the deviations directly: (n' - n) = (nu' - nu)
+          js[k] += open * (P.dk_f[k] * (gk - (dn - dv[k]) * il));
+        }
+        const float c = open * (float(3.0 * WQ[i] * LEN[i]) * g);
+        if (CX[i]) F0 += CX[i] * c;
+        if (CY[i]) F1 += CY[i] * c;
+        if (CZ[i]) F2 += CZ[i] * c;
       }
-      const float c = float(3.0 * WQ[i] * LEN[i]) * g;
-      if (CX[i]) F0 += CX[i] * c;
-      if (CY[i]) F1 += CY[i] * c;
-      if (CZ[i]) F2 += CZ[i] * c;
+    } else {
+#pragma unroll
+      for (int i = 1; i < NQ; ++i) {
+        if (solid_link(m, i)) continue;  // no flux into an electrode
+        const double dphi = pn[i] - ph - P.Ec[i];
+        const float d1 = dl[i];
+        float S1, C1;
+        sinh_coshm1f(d1, S1, C1);
+        const float il = float(1.0 / LEN[i]);
+        float g = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const float dn = nn[k][i];
+          const float nt = ref[k] + dn;
+          float S, C;
+          valence_scf(P.z[k], dphi, d1, S1, C1, S, C);
+          const float gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * float(0.5 / LEN[i]);
+          g += gk;
+          js[k] += P.dk_f[k] * (gk - (dn - dv[k]) * il);
+        }
+        const float c = float(3.0 * WQ[i] * LEN[i]) * g;
+        if (CX[i]) F0 += CX[i] * c;
+        if (CY[i]) F1 += CY[i] * c;
+        if (CZ[i]) F2 += CZ[i] * c;
+      }
     }
 
     float h[NQ];

@@ -74,6 +74,22 @@ __device__ __forceinline__ void gather_lv(const MgLevel &lv, const Coords &c, in
   for (int i = 1; i < NQ; ++i) v[i] = e[r + ox[CX[i] + 1] + oy[CY[i] + 1] + oz[CZ[i] + 1]];
 }
 
+// The same for a level in global memory (not LDS): each load is a 32-bit
+// lane offset on the array's wave-uniform base.
+template <class T>
+__device__ __forceinline__ void gather_lv_g(const MgLevel &lv, const Coords &c, int r,
+                                            const T *__restrict__ e, T (&v)[NQ]) {
+  const int ox[3] = {c.x > 0 ? -1 : lv.nx - 1, 0, c.x + 1 < lv.nx ? 1 : 1 - lv.nx};
+  const int oy[3] = {c.y > 0 ? -lv.nx : (lv.ny - 1) * lv.nx, 0,
+                     c.y + 1 < lv.ny ? lv.nx : -(lv.ny - 1) * lv.nx};
+  const int oz[3] = {c.z > 0 ? -lv.nxy : (lv.nz - 1) * lv.nxy, 0,
+                     c.z + 1 < lv.nz ? lv.nxy : -(lv.nz - 1) * lv.nxy};
+  v[0] = ld32(e, (uint32_t)r);
+#pragma unroll
+  for (int i = 1; i < NQ; ++i)
+    v[i] = ld32(e, (uint32_t)(r + ox[CX[i] + 1] + oy[CY[i] + 1] + oz[CZ[i] + 1]));
+}
+
 // A e at a fluid cell from its gathered values v, in the level's units:
 // (6/h^2) sum_i w_i s_i (e - e_i)
 template <class T>
@@ -137,7 +153,7 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
   if (r < lv.n) {
     const Coords c = coords_of(r, lv);
     double pn[NQ];
-    gather_lv(lv, c, r, phi, pn);
+    gather_lv_g(lv, c, r, phi, pn);
     const double sr = src[r];
     const uint32_t m = mask[r];
     double acc = 0.0;
@@ -207,20 +223,21 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_az(MgLevel lv, const uint32_t *__
   if (r < lv.n) {
     const Coords c = coords_of(r, lv);
     T v[NQ];
-    gather_lv(lv, c, r, z, v);
+    gather_lv_g(lv, c, r, z, v);
     const uint32_t m = mask[r];
+    double a = 0.0;  // a solid cell stores its zero too: whole cache lines
     if (!(m & SOLID_BIT)) {
       double vd[NQ];
 #pragma unroll
       for (int i = 0; i < NQ; ++i) vd[i] = double(v[i]);
-      const double a = apply_A_v<double>(lv, m, vd);
-      az[r] = a;
+      a = apply_A_v<double>(lv, m, vd);
       const double rr = rv[r];
       zq = vd[0] * q_prev[r];
       zaz = vd[0] * a;
       rz = rr * vd[0];
       rp = rr * p_prev[r];
     }
+    az[r] = a;
   }
   const int nb = gridDim.x;
   zq = block_sum(zq, sm);
@@ -290,18 +307,21 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_update(int n, const uint32_t *__r
   if (r < n) {
     double R = 0.0;
     const uint32_t m = mask[r];
-    if (!(m & SOLID_BIT)) {
-      const double beta = kc->beta, alpha = kc->alpha;
-      const double zr = double(z[r]);
-      const double pr = beta == 0.0 ? zr : zr + beta * p[r];
-      const double qr = beta == 0.0 ? az[r] : az[r] + beta * q[r];
-      p[r] = pr;
-      q[r] = qr;
-      phi[r] += alpha * pr;
-      R = rv[r] - alpha * qr;
-      rv[r] = R;
-      a = fabs(R);
-    }
+    // Every cell stores p, q, phi and r, so each store writes whole cache
+    // lines: a solid cell its zeros (p, q, r hold zeros there) and its
+    // potential, the electrode's, unchanged.
+    const bool solid = m & SOLID_BIT;
+    const double beta = kc->beta, alpha = kc->alpha;
+    const double zr = solid ? 0.0 : double(z[r]);
+    const double pr = solid ? 0.0 : (beta == 0.0 ? zr : zr + beta * p[r]);
+    const double qr = solid ? 0.0 : (beta == 0.0 ? az[r] : az[r] + beta * q[r]);
+    p[r] = pr;
+    q[r] = qr;
+    const double ph = phi[r];
+    phi[r] = solid ? ph : ph + alpha * pr;
+    R = solid ? 0.0 : rv[r] - alpha * qr;
+    rv[r] = R;
+    a = fabs(R);
     const T rr = T(R);
     r0[r] = rr;
     e0[r] = coarse_start<T>(lv, m, rr, jac, hs);
@@ -367,7 +387,7 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
   if (r >= lv.n) return;
   const Coords c = coords_of(r, lv);
   T v[NQ];
-  gather_lv(lv, c, r, x_in, v);
+  gather_lv_g(lv, c, r, x_in, v);
   const T rr = rhs[r];
   const uint32_t m = mask[r];
   T num = T(0), den = T(0);
@@ -383,7 +403,9 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
   const bool solid = m & SOLID_BIT;
   const T res = solid ? T(0) : xr + omega * (num / den - xr);
   x_out[r] = res;
-  if (ADD_PHI && !solid) phi_add[r] += double(res);
+  // every cell, so that the store writes whole lines (a solid cell adds 0 to
+  // its electrode potential)
+  if (ADD_PHI) phi_add[r] += double(res);
 }
 
 // ---- restriction: coarse rhs = mean of the fluid children's residuals -------
@@ -410,7 +432,7 @@ __device__ __forceinline__ void restrict_child(const MgTransfer &tr, int R, int 
   c.z = wrapi(min(zp, tr.f.nz - 1) + tr.oz, tr.f.nz);
   const int r = c.x + tr.f.nx * (c.y + tr.f.ny * c.z);
   T e[NQ];
-  gather_lv(tr.f, c, r, ef, e);
+  gather_lv(tr.f, c, r, ef, e);  // also on LDS levels (k_mg_small)
   const T rr = rf[r];
   const uint32_t m = mf[r];
   const T res = rr - apply_A_v<T>(tr.f, m, e);
@@ -586,7 +608,9 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(MgTransfer tr, const uint32_t
   if (r >= tr.f.n) return;
   const T e0 = ef[r];
   const T pv = prolong_value<T>(tr, r, mc, ec);
-  if (!(mf[r] & SOLID_BIT)) ef[r] = e0 + pv;
+  // every cell stores (a solid one its value back), so that the store
+  // writes whole cache lines
+  ef[r] = (mf[r] & SOLID_BIT) ? e0 : e0 + pv;
 }
 
 // ---- coarsest level: one work-group, sweeps with barriers ----------------------
