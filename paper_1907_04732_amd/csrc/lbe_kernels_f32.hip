@@ -114,12 +114,16 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
 #pragma unroll
       for (int k = 0; k < K; ++k) nn[k][i] = ld32(sbase(nu + k * N), rn);
     }
+    // the populations too, so that their loads overlap the link arithmetic
+    float h[NQ];
+    pull_f32<NT>(L, r, m, o, hin, h);
     // Each link's potential difference in FP64, rounded once.  When every
-    // species has |z| = 1 and every fluid link of the wave lies in the
-    // series range (a wave-wide vote), the links run without a branch: a
-    // wall link's terms are computed from the electrode's values and
-    // multiplied by zero (no flux into an electrode).  Otherwise the loop
-    // below takes each link's own path.
+    // species has |z| = 1 and every fluid link of the wave has |delta| <=
+    // 1/8 (a wave-wide vote), the links run without a branch, on the series
+    // through delta^5 (sinh) and delta^6 (cosh - 1), whose next terms are
+    // below 1e-9 relative there, with a wall link's factors zeroed (no flux
+    // into an electrode).  Otherwise the loop below takes each link's own
+    // path.
     float dl[NQ];
     float dmax = 0.f;
 #pragma unroll
@@ -127,30 +131,36 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
       dl[i] = solid_link(m, i) ? 0.f : float(pn[i] - ph - P.Ec[i]);
       dmax = fmaxf(dmax, fabsf(dl[i]));
     }
-    const bool fast = P.unit_z && __all(dmax <= float(TAYLOR_MAX));
+    const bool fast = P.unit_z && __all(dmax <= 0.125f);
     float F0 = 0.f, F1 = 0.f, F2 = 0.f;
     if (fast) {
-      float zf[K];
+      // per species: n' + n = dnu' + (2 ref + nu) and n' - n = dnu' - nu
+      float zf[K], sum0[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) zf[k] = float(P.z[k]);
+      for (int k = 0; k < K; ++k) {
+        zf[k] = float(P.z[k]);
+        sum0[k] = ref[k] + nr[k];
+      }
 #pragma unroll
       for (int i = 1; i < NQ; ++i) {
         const float open = solid_link(m, i) ? 0.f : 1.f;
-        float S1, C1;
-        sinh_coshm1f_series(dl[i], S1, C1);
-        const float il = float(1.0 / LEN[i]);
+        const float d = dl[i], x = d * d;
+        // -(sinh, cosh - 1) / (2 |c_i|), and 1 / |c_i|, zero on a wall link
+        const float hl = open * float(-0.5 / LEN[i]);
+        const float a = hl * (d * (1.f + x * (1.f / 6 + x * (1.f / 120))));
+        const float b = hl * (x * (0.5f + x * (1.f / 24 + x * (1.f / 720))));
+        const float il = open * float(1.0 / LEN[i]);
         float g = 0.f;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const float dn = nn[k][i];
-          const float nt = ref[k] + dn;
-          const float gk = -((nt + nr[k]) * (zf[k] * S1) + (nt - nr[k]) * C1) *
-                           float(0.5 / LEN[i]);
+          const float t = dn - dv[k];
+          const float gk = (dn + sum0[k]) * (zf[k] * a) + t * b;
           g += gk;
           // the ideal part uses the deviations directly: (n' - n) = (nu' - nu)
-          js[k] += open * (P.dk_f[k] * (gk - (dn - dv[k]) * il));
+          js[k] += P.dk_f[k] * (gk - t * il);
         }
-        const float c = open * (float(3.0 * WQ[i] * LEN[i]) * g);
+        const float c = float(3.0 * WQ[i] * LEN[i]) * g;
         if (CX[i]) F0 += CX[i] * c;
         if (CY[i]) F1 += CY[i] * c;
         if (CZ[i]) F2 += CZ[i] * c;
@@ -182,8 +192,6 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
       }
     }
 
-    float h[NQ];
-    pull_f32<NT>(L, r, m, o, hin, h);
     float drho = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
