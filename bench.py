@@ -216,8 +216,13 @@ def run_form(w, form: str, solver: str, steps: int, warmup: int, start_step: int
     flags = p.flags
     t_init = time.perf_counter()
     g = make_context(w, p)
+    blk_a, blk_b, nt = g.pass_blocks()
+    launch = {"pass_a": "lds_tiles" if blk_a == 1 else f"block_{blk_a}",
+              "pass_b": "lds_tiles" if blk_b == 1 else f"block_{blk_b}",
+              "nontemporal_streams": bool(nt)}
     print(f"bench: {w.name} {form}/{solver}: context ready in "
-          f"{time.perf_counter() - t_init:.2f} s", file=sys.stderr, flush=True)
+          f"{time.perf_counter() - t_init:.2f} s, step passes {launch}", file=sys.stderr,
+          flush=True)
     N = w.node_type.size
     nfluid = int((w.node_type == 0).sum())
     ffrac = nfluid / N
@@ -265,6 +270,7 @@ def run_form(w, form: str, solver: str, steps: int, warmup: int, start_step: int
               file=sys.stderr, flush=True)
     dom = next(iter(kernels))
     return {"mlups": round(mlups, 3), "ms_per_step": round(el / steps * 1e3, 4),
+            "launch": launch,
             "fluid_mlups": round(nfluid * steps / el / 1e6, 3),
             "first_step": int(tot0["step"]),
             "poisson_iters_per_step": round(iters, 3),
@@ -748,7 +754,7 @@ def main():
         "roofline": head["roofline"],
         "roofline_step_passes": head["roofline_step_passes"],
         "forms": {k: {kk: v[kk] for kk in ("mlups", "ms_per_step", "poisson_iters_per_step",
-                                            "roofline", "roofline_step_passes")}
+                                            "launch", "roofline", "roofline_step_passes")}
                   for k, v in res.items()},
         "kernels": head["kernels"],
     }
@@ -764,8 +770,8 @@ def main():
                 "sites": int(ws.node_type.size), "fluid_sites": nf,
                 "steps": args.shape_steps, "poisson": poisson_text(WORKLOADS[name][1]),
                 "forms": {k: {kk: v[kk] for kk in ("mlups", "ms_per_step", "first_step",
-                                                    "poisson_iters_per_step", "roofline",
-                                                    "roofline_step_passes")}
+                                                    "poisson_iters_per_step", "launch",
+                                                    "roofline", "roofline_step_passes")}
                           for k, v in r.items()}}
     aforms = [f.strip() for f in args.adjoint_forms.split(",") if f.strip()]
     if aforms:

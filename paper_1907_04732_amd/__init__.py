@@ -30,7 +30,7 @@ ENTRY_POINTS = (
     "lbe_electrode_charge", "lbe_observables", "lbe_fields_device",
     "lbe_destroy", "lbe_strerror", "lbe_last_error", "lbe_profile", "lbe_kernel_times",
     "lbe_kernel_name", "lbe_num_kernel_kinds", "lbe_velocities", "lbe_build_id",
-    "lbe_electrode_charge_noalloc",
+    "lbe_electrode_charge_noalloc", "lbe_launch_shape",
 )
 
 
@@ -142,6 +142,9 @@ def load(path: str = LIB_PATH):
     lib.lbe_kernel_name.restype = C.c_char_p
     lib.lbe_num_kernel_kinds.argtypes = []
     lib.lbe_num_kernel_kinds.restype = C.c_int32
+    i32p = P(C.c_int32)
+    lib.lbe_launch_shape.argtypes = [v, i32p, i32p, i32p]
+    lib.lbe_launch_shape.restype = C.c_int
     lib.lbe_velocities.argtypes = [P(C.c_int32), d]
     lib.lbe_velocities.restype = None
     lib.lbe_electrode_charge_noalloc.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_double,
@@ -442,6 +445,13 @@ class Lbe:
 
     def profile(self, enable=True):
         self._check(self._lib.lbe_profile(self.h, 1 if enable else 0))
+
+    def pass_blocks(self):
+        """(block of pass A, block of pass B (1: LDS tiles), non-temporal
+        streams) as the context chose them."""
+        a, b, nt = C.c_int32(), C.c_int32(), C.c_int32()
+        self._check(self._lib.lbe_launch_shape(self.h, C.byref(a), C.byref(b), C.byref(nt)))
+        return a.value, b.value, nt.value
 
     def kernel_times(self):
         """{kind: (total ms, launches, cells covered)} since profile(True)."""

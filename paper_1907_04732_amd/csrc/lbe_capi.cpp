@@ -1688,6 +1688,14 @@ void lbe_velocities(int32_t *c, double *w) {
 }
 
 int32_t lbe_num_kernel_kinds(void) { return KK_COUNT; }
+
+int lbe_launch_shape(const lbe_ctx *c, int32_t *block_a, int32_t *block_b, int32_t *nontemporal) {
+  if (!c) return fail(nullptr, LBE_EINVAL, "context is NULL");
+  if (block_a) *block_a = c->tb_a;
+  if (block_b) *block_b = c->tb_b;
+  if (nontemporal) *nontemporal = c->nt ? 1 : 0;
+  return LBE_OK;
+}
 const char *lbe_kernel_name(int32_t kind) {
   return (kind >= 0 && kind < KK_COUNT) ? kKernelNames[kind] : "";
 }
@@ -1703,7 +1711,7 @@ namespace {
 // of three launches after one to warm up.  Every site is computed on its own,
 // so the results are the same for any choice; only the time differs.
 int autotune_passes(lbe_ctx *c) {
-  static const int cand[3] = {128, 256, 512};
+  static const int cand_all[4] = {128, 256, 512, TB_TILED};
   const int a = c->cur, b = 1 - c->cur;
   const long N = c->L.n;
   // scratch for pass B's source and kept potential: free between steps
@@ -1715,11 +1723,18 @@ int autotune_passes(lbe_ctx *c) {
     (void)hipEventDestroy(e0);
     return fail(c, LBE_EDEVICE, "event create failed");
   }
+  // the LDS-tiled passes (mixed form) are candidates where their tiles fit
+  // the lattice; LBE_PASS_TILE=0 leaves them out, =1 takes them untimed
+  const char *pt = getenv("LBE_PASS_TILE");
+  const int tile_env = pt && *pt ? (*pt != '0' ? 1 : 0) : -1;
+  const bool tile_ok = c->mixed && tiles_fit(c->L) && tile_env != 0;
   int rc = LBE_OK;
   for (int pass = 0; pass < 2 && rc == LBE_OK; ++pass) {
     float best = 1e30f;
     int pick = 256;
-    for (int tb : cand) {
+    for (int tb : cand_all) {
+      if (tb == TB_TILED && !tile_ok) continue;
+      if (tile_ok && tile_env == 1 && tb != TB_TILED) continue;
       float t_min = 1e30f;
       for (int rep = 0; rep < 4 && rc == LBE_OK; ++rep) {
         hipError_t e = hipEventRecord(e0, c->stream);

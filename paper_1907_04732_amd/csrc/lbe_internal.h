@@ -55,6 +55,13 @@ struct Lattice {
   int xcd;          // 1: stencil kernels give each XCD a contiguous run of blocks
 };
 
+// Step passes on LDS-staged tiles: a block of TILE_X x TILE_Y nodes marching
+// through TILE_Z planes along z.  TB_TILED as a pass's launch shape selects
+// them (the context's timing picks it where the tiles fit the lattice).
+constexpr int TILE_X = 64, TILE_Y = 4, TILE_Z = 16;
+constexpr int TB_TILED = 1;
+inline bool tiles_fit(const Lattice &L) { return L.nx % TILE_X == 0 && L.ny % TILE_Y == 0; }
+
 // Physical constants of one context, passed by value to the kernels.
 struct Phys {
   int K;                 // species

@@ -65,6 +65,157 @@ __device__ __forceinline__ void pull_f32(const Lattice &L, int r, uint32_t m, co
 // Pass A: each fluid link's excess flux (Eq. 10) evaluated once, used for the
 // fluid force and for the diffusion-migration flux; collision; writes h, u and
 // the increment dnu_k = -sum_i j_k (applied by k_ions_f32).
+//
+// The arithmetic at a fluid node r, its neighbours' potential and deviations
+// taken from nb (nb.phi(i), nb.nu(k, i) at r + c_i): registers loaded by
+// k_fluid_f32, or the LDS planes of k_fluid_f32_tiled.  Writes the new
+// populations hn, the velocity and the increments dno.
+template <int K, bool NT, class NB>
+__device__ __forceinline__ void fluid_node_f32(const Lattice &L, const Phys &P, int r, uint32_t m,
+                                               const Offs &o, double ph, const float (&dv)[K],
+                                               const NB &nb, const float *__restrict__ hin,
+                                               float (&hn)[NQ], float &ux, float &uy, float &uz,
+                                               float (&dno)[K]) {
+  // deviation reference of this node's system (fluid neighbours share it),
+  // held in registers: the link loop adds it at every neighbour
+  const float *refp = P.nref_f + 4 * system_of(m);
+  float ref[K], nr[K], js[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    ref[k] = refp[k];
+    nr[k] = ref[k] + dv[k];
+    js[k] = 0.f;
+  }
+  // the populations first, so that their loads overlap the link arithmetic
+  float h[NQ];
+  pull_f32<NT>(L, r, m, o, hin, h);
+  // Each link's potential difference in FP64, rounded once.  When every
+  // species has |z| = 1 and every fluid link of the wave has |delta| <=
+  // 1/8 (a wave-wide vote), the links run without a branch, on the series
+  // through delta^5 (sinh) and delta^6 (cosh - 1), whose next terms are
+  // below 1e-9 relative there, with a wall link's factors zeroed (no flux
+  // into an electrode).  Otherwise the loop below takes each link's own
+  // path.
+  float dl[NQ];
+  float dmax = 0.f;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    dl[i] = solid_link(m, i) ? 0.f : float(nb.phi(i) - ph - P.Ec[i]);
+    dmax = fmaxf(dmax, fabsf(dl[i]));
+  }
+  const bool fast = P.unit_z && __all(dmax <= 0.125f);
+  float F0 = 0.f, F1 = 0.f, F2 = 0.f;
+  if (fast) {
+    // per species: n' + n = dnu' + (2 ref + nu) and n' - n = dnu' - nu
+    float zf[K], sum0[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      zf[k] = float(P.z[k]);
+      sum0[k] = ref[k] + nr[k];
+    }
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      const float open = solid_link(m, i) ? 0.f : 1.f;
+      const float d = dl[i], x = d * d;
+      // -(sinh, cosh - 1) / (2 |c_i|), and 1 / |c_i|, zero on a wall link
+      const float hl = open * float(-0.5 / LEN[i]);
+      const float a = hl * (d * (1.f + x * (1.f / 6 + x * (1.f / 120))));
+      const float b = hl * (x * (0.5f + x * (1.f / 24 + x * (1.f / 720))));
+      const float il = open * float(1.0 / LEN[i]);
+      float g = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float dn = nb.nu(k, i);
+        const float t = dn - dv[k];
+        const float gk = (dn + sum0[k]) * (zf[k] * a) + t * b;
+        g += gk;
+        // the ideal part uses the deviations directly: (n' - n) = (nu' - nu)
+        js[k] += P.dk_f[k] * (gk - t * il);
+      }
+      const float c = float(3.0 * WQ[i] * LEN[i]) * g;
+      if (CX[i]) F0 += CX[i] * c;
+      if (CY[i]) F1 += CY[i] * c;
+      if (CZ[i]) F2 += CZ[i] * c;
+    }
+  } else {
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      if (solid_link(m, i)) continue;  // no flux into an electrode
+      const double dphi = nb.phi(i) - ph - P.Ec[i];
+      const float d1 = dl[i];
+      float S1, C1;
+      sinh_coshm1f(d1, S1, C1);
+      const float il = float(1.0 / LEN[i]);
+      float g = 0.f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const float dn = nb.nu(k, i);
+        const float nt = ref[k] + dn;
+        float S, C;
+        valence_scf(P.z[k], dphi, d1, S1, C1, S, C);
+        const float gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * float(0.5 / LEN[i]);
+        g += gk;
+        js[k] += P.dk_f[k] * (gk - (dn - dv[k]) * il);
+      }
+      const float c = float(3.0 * WQ[i] * LEN[i]) * g;
+      if (CX[i]) F0 += CX[i] * c;
+      if (CY[i]) F1 += CY[i] * c;
+      if (CZ[i]) F2 += CZ[i] * c;
+    }
+  }
+
+  float drho = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    drho += h[i];
+    if (CX[i]) m0 += CX[i] * h[i];
+    if (CY[i]) m1 += CY[i] * h[i];
+    if (CZ[i]) m2 += CZ[i] * h[i];
+  }
+  // sum_i w_i rho0 c_i = 0, so the momentum is carried by the deviations
+  const float rho = P.rho0_f + drho;
+  ux = (m0 + 0.5f * F0) / rho;
+  uy = (m1 + 0.5f * F1) / rho;
+  uz = (m2 + 0.5f * F2) / rho;
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float uF = ux * F0 + uy * F1 + uz * F2;
+  const float itau = P.itau_f;
+  const float guo = 1.f - 0.5f * itau;
+  // Equilibrium (minus the rest state w_i rho0) and Guo source, a pair of
+  // opposite velocities at a time: with cu = c_i . u and cF = c_i . F,
+  // heq = w (drho + rho (4.5 cu^2 - 1.5 u.u)) +- 3 w rho cu and
+  // s = w guo (9 cu cF - 3 u.F) +- 3 w guo cF for c_i and -c_i.
+  {
+    const float w = float(WQ[0]);
+    const float heq = w * (drho + rho * (-1.5f * uu));
+    hn[0] = h[0] - (h[0] - heq) * itau + (w * guo) * (-3.f * uF);
+  }
+#pragma unroll
+  for (int i = 1; i < NQ; i += 2) {
+    const int j = OPP[i];
+    const float w = float(WQ[i]);
+    const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+    const float cF = CX[i] * F0 + CY[i] * F1 + CZ[i] * F2;
+    const float even = w * (drho + rho * (4.5f * cu * cu - 1.5f * uu));
+    const float odd = (3.f * w) * rho * cu;
+    const float se = (w * guo) * (9.f * cu * cF - 3.f * uF);
+    const float so = (3.f * w * guo) * cF;
+    hn[i] = h[i] - (h[i] - (even + odd)) * itau + (se + so);
+    hn[j] = h[j] - (h[j] - (even - odd)) * itau + (se - so);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) dno[k] = -js[k];
+}
+
+// neighbour values held in registers
+template <int K>
+struct NbRegs {
+  double p[NQ];
+  float n[K][NQ];
+  __device__ __forceinline__ double phi(int i) const { return p[i]; }
+  __device__ __forceinline__ float nu(int k, int i) const { return n[k][i]; }
+};
+
 template <int K, int TB, bool NT>
 __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
                                                      const uint32_t *__restrict__ mask,
@@ -91,148 +242,21 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
     Offs o;
     site_offsets(L, r, o);
     const double ph = phi[r];
-    // deviation reference of this node's system (fluid neighbours share
-    // it), held in registers: the link loop adds it at every neighbour
-    const float *refp = P.nref_f + 4 * system_of(m);
-    float ref[K], dv[K], nr[K], js[K];
+    float dv[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      ref[k] = refp[k];
-      dv[k] = nu[k * N + r];
-      nr[k] = ref[k] + dv[k];
-      js[k] = 0.f;
-    }
+    for (int k = 0; k < K; ++k) dv[k] = nu[k * N + r];
     // every neighbour's potential and deviations first, solid neighbours
-    // too (their links are skipped below): all 18 (1 + K) gathers are then
-    // in flight together rather than one link's at a time behind a branch
-    double pn[NQ];
-    float nn[K][NQ];
+    // too (their links are skipped): all 18 (1 + K) gathers are then in
+    // flight together rather than one link's at a time behind a branch
+    NbRegs<K> nb;
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
       const uint32_t rn = nbr(o, r, i);
-      pn[i] = ld32(phi, rn);
+      nb.p[i] = ld32(phi, rn);
 #pragma unroll
-      for (int k = 0; k < K; ++k) nn[k][i] = ld32(sbase(nu + k * N), rn);
+      for (int k = 0; k < K; ++k) nb.n[k][i] = ld32(sbase(nu + k * N), rn);
     }
-    // the populations too, so that their loads overlap the link arithmetic
-    float h[NQ];
-    pull_f32<NT>(L, r, m, o, hin, h);
-    // Each link's potential difference in FP64, rounded once.  When every
-    // species has |z| = 1 and every fluid link of the wave has |delta| <=
-    // 1/8 (a wave-wide vote), the links run without a branch, on the series
-    // through delta^5 (sinh) and delta^6 (cosh - 1), whose next terms are
-    // below 1e-9 relative there, with a wall link's factors zeroed (no flux
-    // into an electrode).  Otherwise the loop below takes each link's own
-    // path.
-    float dl[NQ];
-    float dmax = 0.f;
-#pragma unroll
-    for (int i = 1; i < NQ; ++i) {
-      dl[i] = solid_link(m, i) ? 0.f : float(pn[i] - ph - P.Ec[i]);
-      dmax = fmaxf(dmax, fabsf(dl[i]));
-    }
-    const bool fast = P.unit_z && __all(dmax <= 0.125f);
-    float F0 = 0.f, F1 = 0.f, F2 = 0.f;
-    if (fast) {
-      // per species: n' + n = dnu' + (2 ref + nu) and n' - n = dnu' - nu
-      float zf[K], sum0[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        zf[k] = float(P.z[k]);
-        sum0[k] = ref[k] + nr[k];
-      }
-#pragma unroll
-      for (int i = 1; i < NQ; ++i) {
-        const float open = solid_link(m, i) ? 0.f : 1.f;
-        const float d = dl[i], x = d * d;
-        // -(sinh, cosh - 1) / (2 |c_i|), and 1 / |c_i|, zero on a wall link
-        const float hl = open * float(-0.5 / LEN[i]);
-        const float a = hl * (d * (1.f + x * (1.f / 6 + x * (1.f / 120))));
-        const float b = hl * (x * (0.5f + x * (1.f / 24 + x * (1.f / 720))));
-        const float il = open * float(1.0 / LEN[i]);
-        float g = 0.f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float dn = nn[k][i];
-          const float t = dn - dv[k];
-          const float gk = (dn + sum0[k]) * (zf[k] * a) + t * b;
-          g += gk;
-          // the ideal part uses the deviations directly: (n' - n) = (nu' - nu)
-          js[k] += P.dk_f[k] * (gk - t * il);
-        }
-        const float c = float(3.0 * WQ[i] * LEN[i]) * g;
-        if (CX[i]) F0 += CX[i] * c;
-        if (CY[i]) F1 += CY[i] * c;
-        if (CZ[i]) F2 += CZ[i] * c;
-      }
-    } else {
-#pragma unroll
-      for (int i = 1; i < NQ; ++i) {
-        if (solid_link(m, i)) continue;  // no flux into an electrode
-        const double dphi = pn[i] - ph - P.Ec[i];
-        const float d1 = dl[i];
-        float S1, C1;
-        sinh_coshm1f(d1, S1, C1);
-        const float il = float(1.0 / LEN[i]);
-        float g = 0.f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const float dn = nn[k][i];
-          const float nt = ref[k] + dn;
-          float S, C;
-          valence_scf(P.z[k], dphi, d1, S1, C1, S, C);
-          const float gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * float(0.5 / LEN[i]);
-          g += gk;
-          js[k] += P.dk_f[k] * (gk - (dn - dv[k]) * il);
-        }
-        const float c = float(3.0 * WQ[i] * LEN[i]) * g;
-        if (CX[i]) F0 += CX[i] * c;
-        if (CY[i]) F1 += CY[i] * c;
-        if (CZ[i]) F2 += CZ[i] * c;
-      }
-    }
-
-    float drho = 0.f, m0 = 0.f, m1 = 0.f, m2 = 0.f;
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      drho += h[i];
-      if (CX[i]) m0 += CX[i] * h[i];
-      if (CY[i]) m1 += CY[i] * h[i];
-      if (CZ[i]) m2 += CZ[i] * h[i];
-    }
-    // sum_i w_i rho0 c_i = 0, so the momentum is carried by the deviations
-    const float rho = P.rho0_f + drho;
-    ux = (m0 + 0.5f * F0) / rho;
-    uy = (m1 + 0.5f * F1) / rho;
-    uz = (m2 + 0.5f * F2) / rho;
-    const float uu = ux * ux + uy * uy + uz * uz;
-    const float uF = ux * F0 + uy * F1 + uz * F2;
-    const float itau = P.itau_f;
-    const float guo = 1.f - 0.5f * itau;
-    // Equilibrium (minus the rest state w_i rho0) and Guo source, a pair of
-    // opposite velocities at a time: with cu = c_i . u and cF = c_i . F,
-    // heq = w (drho + rho (4.5 cu^2 - 1.5 u.u)) +- 3 w rho cu and
-    // s = w guo (9 cu cF - 3 u.F) +- 3 w guo cF for c_i and -c_i.
-    {
-      const float w = float(WQ[0]);
-      const float heq = w * (drho + rho * (-1.5f * uu));
-      hn[0] = h[0] - (h[0] - heq) * itau + (w * guo) * (-3.f * uF);
-    }
-#pragma unroll
-    for (int i = 1; i < NQ; i += 2) {
-      const int j = OPP[i];
-      const float w = float(WQ[i]);
-      const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-      const float cF = CX[i] * F0 + CY[i] * F1 + CZ[i] * F2;
-      const float even = w * (drho + rho * (4.5f * cu * cu - 1.5f * uu));
-      const float odd = (3.f * w) * rho * cu;
-      const float se = (w * guo) * (9.f * cu * cF - 3.f * uF);
-      const float so = (3.f * w * guo) * cF;
-      hn[i] = h[i] - (h[i] - (even + odd)) * itau + (se + so);
-      hn[j] = h[j] - (h[j] - (even - odd)) * itau + (se - so);
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) dno[k] = -js[k];
+    fluid_node_f32<K, NT>(L, P, r, m, o, ph, dv, nb, hin, hn, ux, uy, uz, dno);
   }
 #pragma unroll
   for (int i = 0; i < NQ; ++i) st_stream<NT>(sbase(hout + i * N), r, hn[i]);
@@ -243,12 +267,172 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
   for (int k = 0; k < K; ++k) st_stream<NT>(sbase(dnu + k * N), r, dno[k]);
 }
 
+// neighbour values from the LDS planes of a tile (slot of plane z + c_z,
+// halo cell hc + c_x + (TILE_X + 2) c_y)
+template <int K>
+struct NbTile {
+  const double (*sp)[(TILE_X + 2) * (TILE_Y + 2)];
+  const float (*sn)[K][(TILE_X + 2) * (TILE_Y + 2)];
+  int zrel, hc;  // z - z0 + 1 of the node, its halo cell
+  __device__ __forceinline__ int slot(int i) const { return (zrel + CZ[i]) & 3; }
+  __device__ __forceinline__ int cell(int i) const { return hc + CX[i] + (TILE_X + 2) * CY[i]; }
+  __device__ __forceinline__ double phi(int i) const { return sp[slot(i)][cell(i)]; }
+  __device__ __forceinline__ float nu(int k, int i) const { return sn[slot(i)][k][cell(i)]; }
+};
+
+// Pass A on LDS-staged tiles, as k_ions_f32_tiled: the potential and the
+// deviations of three planes (with the x, y halo) in LDS, the next plane's
+// loads in flight during the current one, a ring of four slots and one
+// barrier per plane.  Same arithmetic as k_fluid_f32, hence the same bits.
+template <int K, bool NT>
+__global__ __launch_bounds__(TILE_X * TILE_Y) void k_fluid_f32_tiled(
+    Lattice L, Phys P, const uint32_t *__restrict__ mask, const double *__restrict__ phi,
+    const float *__restrict__ nu, const float *__restrict__ hin, float *__restrict__ hout,
+    float *__restrict__ u, float *__restrict__ dnu) {
+  constexpr int NT_ = TILE_X * TILE_Y, HX = TILE_X + 2, HP = (TILE_X + 2) * (TILE_Y + 2);
+  constexpr int PER = (HP + NT_ - 1) / NT_;
+  __shared__ double sp[4][HP];
+  __shared__ float sn[4][K][HP];
+  const int N = L.n;
+  int b = blockIdx.x;
+  const int ntx = L.nx / TILE_X, nty = L.ny / TILE_Y;
+  const int x0 = (b % ntx) * TILE_X;
+  b /= ntx;
+  const int y0 = (b % nty) * TILE_Y;
+  const int z0 = (b / nty) * TILE_Z;
+  const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
+  uint32_t gxy[PER];
+  int cidx[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int c = threadIdx.x + j * NT_;
+    cidx[j] = c < HP ? c : -1;
+    const int cc = c < HP ? c : 0;
+    const int hy = cc / HX, hx = cc - hy * HX;
+    int gx = x0 + hx - 1, gy = y0 + hy - 1;
+    gx = gx < 0 ? gx + L.nx : (gx >= L.nx ? gx - L.nx : gx);
+    gy = gy < 0 ? gy + L.ny : (gy >= L.ny ? gy - L.ny : gy);
+    gxy[j] = gx + L.nx * gy;
+  }
+  double rp[PER];
+  float rn[PER][K];
+  auto fetch = [&](int z) {
+    const int zz = z < 0 ? z + L.nz : (z >= L.nz ? z - L.nz : z);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (cidx[j] < 0) continue;
+      const uint32_t g = gxy[j] + (uint32_t)L.nxy * zz;
+      rp[j] = ld32(phi, g);
+#pragma unroll
+      for (int k = 0; k < K; ++k) rn[j][k] = ld32(sbase(nu + k * N), g);
+    }
+  };
+  auto put = [&](int slot) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (cidx[j] < 0) continue;
+      sp[slot][cidx[j]] = rp[j];
+#pragma unroll
+      for (int k = 0; k < K; ++k) sn[slot][k][cidx[j]] = rn[j][k];
+    }
+  };
+  fetch(z0 - 1);
+  put(0);
+  fetch(z0);
+  put(1);
+  fetch(z0 + 1);
+  const int zend = min(z0 + TILE_Z, L.nz);
+  const int hc = (lx + 1) + HX * (ly + 1);
+  const int rxy = (x0 + lx) + L.nx * (y0 + ly);
+  for (int z = z0; z < zend; ++z) {
+    put((z - z0 + 2) & 3);  // plane z + 1
+    if (z + 1 < zend) fetch(z + 2);
+    __syncthreads();
+    const int r = rxy + L.nxy * z;
+    const uint32_t m = mask[r];
+    float hn[NQ], dno[K], ux = 0.f, uy = 0.f, uz = 0.f;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) hn[i] = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) dno[k] = 0.f;
+    if (!(m & SOLID_BIT)) {
+      Offs o;
+      site_offsets(L, r, o);
+      const int s0 = (z - z0 + 1) & 3;
+      const double ph = sp[s0][hc];
+      float dv[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) dv[k] = sn[s0][k][hc];
+      NbTile<K> nb{sp, sn, z - z0 + 1, hc};
+      fluid_node_f32<K, NT>(L, P, r, m, o, ph, dv, nb, hin, hn, ux, uy, uz, dno);
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) st_stream<NT>(sbase(hout + i * N), r, hn[i]);
+    st_stream<NT>(u, r, ux);
+    st_stream<NT>(sbase(u + N), r, uy);
+    st_stream<NT>(sbase(u + 2 * N), r, uz);
+#pragma unroll
+    for (int k = 0; k < K; ++k) st_stream<NT>(sbase(dnu + k * N), r, dno[k]);
+  }
+}
+
 // Pass B: advective link fluxes J_k = 3 w_i c_i . (n_k u + n_k' u') with the
 // step's velocity; the step's increment t = dnu_k - sum_i J_k (dnu_k from pass
 // A, in nuio) goes onto the pair (nu, lo_in) of nu_k(t): lo + t first (both
 // small), then the two-sum of hi with it gives the new pair, hi to nuio and lo
 // to lo_out.  Poisson source (4 pi l_B / 6) rho_el accumulated in FP64 from
 // hi + lo.
+//
+// The arithmetic at a fluid node, from its own values (u, the deviations hv,
+// the low words lo and pass A's increments dn) and its neighbours' (cut[i] =
+// c_i . u(r + c_i), nn[k][i] = nu_k(r + c_i)); returns sum_k z_k n_k.
+template <int K>
+__device__ __forceinline__ double ions_node_f32(const Phys &P, uint32_t m, float ux, float uy,
+                                                float uz, const float (&hv)[K],
+                                                const float (&lo)[K], const float (&dn)[K],
+                                                const float (&cut)[NQ],
+                                                const float (&nn)[K][NQ], float (&hio)[K],
+                                                float (&loo)[K]) {
+  const int sy = system_of(m);
+  const float *ref = P.nref_f + 4 * sy;
+  float nr[K], Js[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    nr[k] = ref[k] + hv[k];
+    Js[k] = 0.f;
+  }
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;
+    float cu_h = 0.f;
+    if (CX[i]) cu_h += CX[i] * ux;
+    if (CY[i]) cu_h += CY[i] * uy;
+    if (CZ[i]) cu_h += CZ[i] * uz;
+    const float cu_t = cut[i];
+    const float w3 = float(3.0 * WQ[i]);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      Js[k] += w3 * (nr[k] * cu_h + (ref[k] + nn[k][i]) * cu_t);
+  }
+  double q = P.qref[sy];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float t = lo[k] + (dn[k] - Js[k]);
+    two_sum_f(hv[k], t, hio[k], loo[k]);
+    q += P.z[k] * (double(hio[k]) + double(loo[k]));
+  }
+  return q;
+}
+
+// c_i . u for a neighbour's velocity components
+__device__ __forceinline__ float c_dot(int i, float vx, float vy, float vz) {
+  float c = 0.f;
+  if (CX[i]) c += CX[i] * vx;
+  if (CY[i]) c += CY[i] * vy;
+  if (CZ[i]) c += CZ[i] * vz;
+  return c;
+}
+
 template <int K, int TB, bool NT>
 __global__ __launch_bounds__(TB) void k_ions_f32(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
@@ -274,49 +458,25 @@ __global__ __launch_bounds__(TB) void k_ions_f32(Lattice L, Phys P,
     Offs o;
     site_offsets(L, r, o);
     const float ux = u[r], uy = u[N + r], uz = u[2 * N + r];
-    const int sy = system_of(m);
-    const float *ref = P.nref_f + 4 * sy;
-    float hv[K], nr[K], Js[K];
+    float hv[K], lo[K], dn[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       hv[k] = nu[k * N + r];
-      nr[k] = ref[k] + hv[k];
-      Js[k] = 0.f;
+      lo[k] = lo_in[k * N + r];
+      dn[k] = nuio[k * N + r];
     }
     // c_i . u and the deviations at every neighbour, loaded before any is
-    // used (solid neighbours too, skipped below)
+    // used (solid neighbours too, skipped by the link loop)
     float cut[NQ], nn[K][NQ];
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
       const uint32_t rn = nbr(o, r, i);
-      float c = 0.f;
-      if (CX[i]) c += CX[i] * ld32(u, rn);
-      if (CY[i]) c += CY[i] * ld32(sbase(u + N), rn);
-      if (CZ[i]) c += CZ[i] * ld32(sbase(u + 2 * N), rn);
-      cut[i] = c;
+      cut[i] = c_dot(i, CX[i] ? ld32(u, rn) : 0.f, CY[i] ? ld32(sbase(u + N), rn) : 0.f,
+                     CZ[i] ? ld32(sbase(u + 2 * N), rn) : 0.f);
 #pragma unroll
       for (int k = 0; k < K; ++k) nn[k][i] = ld32(sbase(nu + k * N), rn);
     }
-#pragma unroll
-    for (int i = 1; i < NQ; ++i) {
-      if (solid_link(m, i)) continue;
-      float cu_h = 0.f;
-      if (CX[i]) cu_h += CX[i] * ux;
-      if (CY[i]) cu_h += CY[i] * uy;
-      if (CZ[i]) cu_h += CZ[i] * uz;
-      const float cu_t = cut[i];
-      const float w3 = float(3.0 * WQ[i]);
-#pragma unroll
-      for (int k = 0; k < K; ++k)
-        Js[k] += w3 * (nr[k] * cu_h + (ref[k] + nn[k][i]) * cu_t);
-    }
-    q = P.qref[sy];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const float t = lo_in[k * N + r] + (nuio[k * N + r] - Js[k]);
-      two_sum_f(hv[k], t, hio[k], loo[k]);
-      q += P.z[k] * (double(hio[k]) + double(loo[k]));
-    }
+    q = ions_node_f32<K>(P, m, ux, uy, uz, hv, lo, dn, cut, nn, hio, loo);
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -325,6 +485,141 @@ __global__ __launch_bounds__(TB) void k_ions_f32(Lattice L, Phys P,
   }
   st_stream<NT>(src, r, P.src_scale * q);
   if (prev) extrapolate_at(r, N, order, solid, phi, prev);
+}
+
+// Pass B on an LDS-staged tile: a block of TILE_X x TILE_Y nodes marches
+// along z through TILE_Z planes, keeping the planes z - 1, z, z + 1 of the
+// velocity and the deviations (with a one-node halo in x and y, wrapped
+// periodically) in LDS, so each value is read from memory once per tile
+// instead of once per neighbour.  The plane z + 2 is loaded into registers
+// while the plane z is computed and goes to LDS at the next step (a ring of
+// four slots), so its latency hides behind the arithmetic.  Same arithmetic
+// as k_ions_f32, hence the same bits.  Needs nx a multiple of TILE_X and ny
+// of TILE_Y.
+template <int K, bool NT>
+__global__ __launch_bounds__(TILE_X * TILE_Y) void k_ions_f32_tiled(
+    Lattice L, Phys P, const uint32_t *__restrict__ mask, const float *__restrict__ u,
+    const float *__restrict__ nu, const float *__restrict__ lo_in, float *__restrict__ nuio,
+    float *__restrict__ lo_out, double *__restrict__ src, int order,
+    double *__restrict__ phi, double *__restrict__ prev) {
+  constexpr int NT_ = TILE_X * TILE_Y, HX = TILE_X + 2, HP = (TILE_X + 2) * (TILE_Y + 2);
+  constexpr int NV = 3 + K, PER = (HP + NT_ - 1) / NT_;  // halo cells per thread
+  __shared__ float sv[4][NV][HP];  // [slot][u_x, u_y, u_z, nu_0..][halo cell]
+  const int N = L.n;
+  int b = blockIdx.x;
+  const int ntx = L.nx / TILE_X, nty = L.ny / TILE_Y;
+  const int x0 = (b % ntx) * TILE_X;
+  b /= ntx;
+  const int y0 = (b % nty) * TILE_Y;
+  const int z0 = (b / nty) * TILE_Z;
+  const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
+  // this thread's halo cells: their offset in a plane (g) and LDS index (c)
+  uint32_t gxy[PER];
+  int cidx[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int c = threadIdx.x + j * NT_;
+    cidx[j] = c < HP ? c : -1;
+    const int cc = c < HP ? c : 0;
+    const int hy = cc / HX, hx = cc - hy * HX;
+    int gx = x0 + hx - 1, gy = y0 + hy - 1;
+    gx = gx < 0 ? gx + L.nx : (gx >= L.nx ? gx - L.nx : gx);
+    gy = gy < 0 ? gy + L.ny : (gy >= L.ny ? gy - L.ny : gy);
+    gxy[j] = gx + L.nx * gy;
+  }
+  float reg[PER][NV];
+  auto fetch = [&](int z) {  // plane z (wrapped) into registers
+    const int zz = z < 0 ? z + L.nz : (z >= L.nz ? z - L.nz : z);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (cidx[j] < 0) continue;
+      const uint32_t g = gxy[j] + (uint32_t)L.nxy * zz;
+      reg[j][0] = ld32(u, g);
+      reg[j][1] = ld32(sbase(u + N), g);
+      reg[j][2] = ld32(sbase(u + 2 * N), g);
+#pragma unroll
+      for (int k = 0; k < K; ++k) reg[j][3 + k] = ld32(sbase(nu + k * N), g);
+    }
+  };
+  auto put = [&](int slot) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (cidx[j] < 0) continue;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sv[slot][v][cidx[j]] = reg[j][v];
+    }
+  };
+  // the plane z sits in slot (z - z0 + 1) & 3
+  fetch(z0 - 1);
+  put(0);
+  fetch(z0);
+  put(1);
+  fetch(z0 + 1);
+  const int zend = min(z0 + TILE_Z, L.nz);
+  const int hc = (lx + 1) + HX * (ly + 1);  // this node's halo cell
+  // the node's own flag word, low words and pass A increments, one plane
+  // ahead as well
+  const uint32_t rxy = (x0 + lx) + L.nx * (y0 + ly);
+  uint32_t m_next;
+  float lo_next[K], dn_next[K];
+  auto fetch_own = [&](int z) {
+    const uint32_t r = rxy + (uint32_t)L.nxy * z;
+    m_next = ld32(mask, r);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      lo_next[k] = ld32(sbase(lo_in + k * N), r);
+      dn_next[k] = ld32(sbase((const float *)nuio + k * N), r);
+    }
+  };
+  fetch_own(z0);
+  for (int z = z0; z < zend; ++z) {
+    put((z - z0 + 2) & 3);                   // plane z + 1
+    const uint32_t m = m_next;
+    float lo[K], dn[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      lo[k] = lo_next[k];
+      dn[k] = dn_next[k];
+    }
+    if (z + 1 < zend) {                      // in flight during this plane
+      fetch(z + 2);
+      fetch_own(z + 1);
+    }
+    __syncthreads();
+    const int r = rxy + L.nxy * z;
+    const bool solid = m & SOLID_BIT;
+    float hio[K], loo[K];
+    double q = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) hio[k] = loo[k] = 0.f;
+    if (!solid) {
+      const int s0 = (z - z0 + 1) & 3;
+      const float ux = sv[s0][0][hc], uy = sv[s0][1][hc], uz = sv[s0][2][hc];
+      float hv[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) hv[k] = sv[s0][3 + k][hc];
+      float cut[NQ], nn[K][NQ];
+#pragma unroll
+      for (int i = 1; i < NQ; ++i) {
+        const int sl = (z - z0 + 1 + CZ[i]) & 3, cc = hc + CX[i] + HX * CY[i];
+        cut[i] = c_dot(i, CX[i] ? sv[sl][0][cc] : 0.f, CY[i] ? sv[sl][1][cc] : 0.f,
+                       CZ[i] ? sv[sl][2][cc] : 0.f);
+#pragma unroll
+        for (int k = 0; k < K; ++k) nn[k][i] = sv[sl][3 + k][cc];
+      }
+      q = ions_node_f32<K>(P, m, ux, uy, uz, hv, lo, dn, cut, nn, hio, loo);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      st_stream<NT>(sbase(nuio + k * N), r, hio[k]);
+      st_stream<NT>(sbase(lo_out + k * N), r, loo[k]);
+    }
+    st_stream<NT>(src, r, P.src_scale * q);
+    if (prev) extrapolate_at(r, N, order, solid, phi, prev);
+    // no second barrier: the slot the next step fills held plane z - 2,
+    // read in the previous step, which every thread left at this step's
+    // barrier
+  }
 }
 
 template <int K>
@@ -456,6 +751,24 @@ __global__ __launch_bounds__(BLOCK) void k_expand_n_f32(Lattice L, int K, const 
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
                             float *u, float *dnu, int tb, bool nt) {
+  if (tb == TB_TILED) {
+    if (!tiles_fit(L)) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((L.nx / TILE_X) * (L.ny / TILE_Y) *
+                                   ((L.nz + TILE_Z - 1) / TILE_Z));
+#define CALL(KK, NT) \
+  hipLaunchKernelGGL((k_fluid_f32_tiled<KK, NT>), dim3(nb), dim3(TILE_X * TILE_Y), 0, s, L, P, mask, phi, nu, hin, hout, u, dnu)
+#define CALL_T(KK) CALL(KK, true)
+#define CALL_F(KK) CALL(KK, false)
+    if (nt) {
+      LBE_DISPATCH_K(P.K, CALL_T)
+    } else {
+      LBE_DISPATCH_K(P.K, CALL_F)
+    }
+#undef CALL_T
+#undef CALL_F
+#undef CALL
+    return hipGetLastError();
+  }
 #define CALL(KK, TB, NT) \
   hipLaunchKernelGGL((k_fluid_f32<KK, TB, NT>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, nu, hin, hout, u, dnu)
   LBE_DISPATCH_K_TB_NT(P.K, tb, nt, CALL)
@@ -484,6 +797,24 @@ hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const
                            const float *u, const float *nu, const float *lo_in, float *nuio,
                            float *lo_out, double *src, int order, double *phi, double *prev,
                            int tb, bool nt) {
+  if (tb == TB_TILED) {
+    if (!tiles_fit(L)) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((L.nx / TILE_X) * (L.ny / TILE_Y) *
+                                   ((L.nz + TILE_Z - 1) / TILE_Z));
+#define CALL(KK, NT) \
+  hipLaunchKernelGGL((k_ions_f32_tiled<KK, NT>), dim3(nb), dim3(TILE_X * TILE_Y), 0, s, L, P, mask, u, nu, lo_in, nuio, lo_out, src, order, phi, prev)
+#define CALL_T(KK) CALL(KK, true)
+#define CALL_F(KK) CALL(KK, false)
+    if (nt) {
+      LBE_DISPATCH_K(P.K, CALL_T)
+    } else {
+      LBE_DISPATCH_K(P.K, CALL_F)
+    }
+#undef CALL_T
+#undef CALL_F
+#undef CALL
+    return hipGetLastError();
+  }
 #define CALL(KK, TB, NT) \
   hipLaunchKernelGGL((k_ions_f32<KK, TB, NT>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, u, nu, lo_in, nuio, lo_out, src, order, phi, prev)
   LBE_DISPATCH_K_TB_NT(P.K, tb, nt, CALL)

@@ -339,3 +339,35 @@ def test_die_contiguous_block_order_same_results(solver, precision, monkeypatch)
     for k in fa:
         assert np.array_equal(fa[k], fb[k]), k
     assert np.array_equal(qa, qb) and ia == ib
+
+
+@pytest.mark.parametrize("shape", [(64, 8, 24), (128, 12, 40)])
+def test_tiled_ion_pass_same_bits(monkeypatch, shape):
+    """The mixed form's passes A and B on LDS-staged tiles (64 x 4 nodes marching
+    through 16 planes, three planes of the neighbour data in LDS with a
+    periodic halo: potential and deviations for A, velocity and deviations
+    for B) do the arithmetic of the per-node kernels on the same values, so a
+    run forced onto them (LBE_PASS_TILE=1) and one kept off them
+    (LBE_PASS_TILE=0) must agree bit for bit: random electrodes, an applied
+    field, two species of unequal D, the quadratic warm start; the second
+    lattice has a last chunk of 8 planes and two tiles across x."""
+    t, ps = G.random_geometry(shape, 3, seed=7, fill=0.1)
+    rs = W.salt_for_debye(4.0, G.LB)
+    n0 = W.noisy_concentrations(t, [rs, rs], 1e-2, seed=5)
+    p = lbe.make_params(shape, (1, -1), (0.05, 0.08), G.LB, tau=0.9, Eapp=(1e-3, 0.0, 5e-4),
+                        tol=1e-11, max_iter=100000, precision=lbe.FP32_MIXED, poisson=lbe.MG,
+                        flags=lbe.EXTRAPOLATE | lbe.ALLOW_FLOATING | lbe.KRYLOV)
+    out = []
+    for tile in ("1", "0"):
+        monkeypatch.setenv("LBE_PASS_TILE", tile)
+        g = lbe.Lbe(p, t, ps, n0, (rs, rs))
+        assert (g.pass_blocks()[:2] == (1, 1)) == (tile == "1")
+        assert 1 not in g.pass_blocks()[:2] or tile == "1"
+        g.step(8)
+        out.append((g.fields(), g.qhist(), g.totals()))
+        g.close()
+    (fa, qa, ta), (fb, qb, tb) = out
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    assert np.array_equal(qa, qb) and ta["poisson_total"] == tb["poisson_total"]
+    assert ta["nk"] == tb["nk"]
