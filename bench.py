@@ -219,7 +219,7 @@ def run_form(w, form: str, solver: str, steps: int, warmup: int, start_step: int
     blk_a, blk_b, nt = g.pass_blocks()
     launch = {"pass_a": "lds_tiles" if blk_a == 1 else f"block_{blk_a}",
               "pass_b": "lds_tiles" if blk_b == 1 else f"block_{blk_b}",
-              "nontemporal_streams": bool(nt)}
+              "nontemporal_streams": {"pass_a": bool(nt & 1), "pass_b": bool(nt & 2)}}
     print(f"bench: {w.name} {form}/{solver}: context ready in "
           f"{time.perf_counter() - t_init:.2f} s, step passes {launch}", file=sys.stderr,
           flush=True)
@@ -592,8 +592,14 @@ def summarize_rocprof(root, workload, window=(22, 10)):
         out.append(f"GPU busy fraction over the timed window (steps {skip}..{skip + count} "
                    "after the launch-shape trials, pass-A launch to pass-A launch):")
         for form_tag in ("_f32", "_f64"):
-            fl = [r for r in trace if "k_fluid" + form_tag in r["Kernel_Name"]]
-            fl = fl[12:]  # 4 trial launches at each of 128, 256 and 512 threads
+            # the context's timing runs every pass-A candidate before the
+            # first pass-B launch, so the steps' pass-A launches follow it
+            fb = [int(r["Start_Timestamp"]) for r in trace
+                  if "k_ions" + form_tag in r["Kernel_Name"]]
+            if not fb:
+                continue
+            fl = [r for r in trace if "k_fluid" + form_tag in r["Kernel_Name"]
+                  and int(r["Start_Timestamp"]) > fb[0]]
             if len(fl) < skip + count + 1:
                 continue
             t0 = int(fl[skip]["Start_Timestamp"])

@@ -448,7 +448,7 @@ class Lbe:
 
     def pass_blocks(self):
         """(block of pass A, block of pass B (1: LDS tiles), non-temporal
-        streams) as the context chose them."""
+        streams: bit 0 pass A, bit 1 pass B) as the context chose them."""
         a, b, nt = C.c_int32(), C.c_int32(), C.c_int32()
         self._check(self._lib.lbe_launch_shape(self.h, C.byref(a), C.byref(b), C.byref(nt)))
         return a.value, b.value, nt.value

@@ -61,7 +61,7 @@ struct lbe_ctx {
   bool tiles = true;          // the row-order (LDS-combined) restriction where it applies
   bool coarse_start = true;   // restriction writes the coarse level's first Jacobi sweep
   int tb_a = 256, tb_b = 256;  // block sizes of the step passes A and B (tuned at init)
-  bool nt = false;             // non-temporal streams in the step passes (set at init)
+  bool nt_a = false, nt_b = false;  // non-temporal streams in passes A and B (set at init)
   // a time step's charge row: queued by the solve right after its predicted
   // units, gated on convergence, so it runs while the host waits
   double *charge_dst = nullptr;
@@ -1272,9 +1272,9 @@ int one_step(lbe_ctx *c, bool record = true) {
   int rc = run(c, KK_FLUID, c->L.n, [&] {
     if (c->mixed)
       return launch_fluid_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[a], c->h32[a],
-                              c->h32[b], c->u32, c->nu32[b], c->tb_a, c->nt);
+                              c->h32[b], c->u32, c->nu32[b], c->tb_a, c->nt_a);
     return launch_fluid_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[a], c->f[a], c->f[b],
-                            c->u, c->n[b], c->tb_a, c->nt);
+                            c->u, c->n[b], c->tb_a, c->nt_a);
   });
   if (rc) return rc;
   // pass B also moves phi to the extrapolated start of this step's solve
@@ -1282,9 +1282,9 @@ int one_step(lbe_ctx *c, bool record = true) {
     if (c->mixed)
       return launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a], c->lo32[a],
                              c->nu32[b], c->lo32[b], c->src, order, c->phi, keep, c->tb_b,
-                             c->nt);
+                             c->nt_b);
     return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a], c->n[b], c->src,
-                           order, c->phi, keep, c->tb_b, c->nt);
+                           order, c->phi, keep, c->tb_b, c->nt_b);
   });
   if (rc) return rc;
   if (c->phi_prev) c->extrap_hist = std::min(hist + 1, 2);
@@ -1693,7 +1693,7 @@ int lbe_launch_shape(const lbe_ctx *c, int32_t *block_a, int32_t *block_b, int32
   if (!c) return fail(nullptr, LBE_EINVAL, "context is NULL");
   if (block_a) *block_a = c->tb_a;
   if (block_b) *block_b = c->tb_b;
-  if (nontemporal) *nontemporal = c->nt ? 1 : 0;
+  if (nontemporal) *nontemporal = (c->nt_a ? 1 : 0) | (c->nt_b ? 2 : 0);
   return LBE_OK;
 }
 const char *lbe_kernel_name(int32_t kind) {
@@ -1723,8 +1723,8 @@ int autotune_passes(lbe_ctx *c) {
     (void)hipEventDestroy(e0);
     return fail(c, LBE_EDEVICE, "event create failed");
   }
-  // the LDS-tiled passes (mixed form) are candidates where their tiles fit
-  // the lattice; LBE_PASS_TILE=0 leaves them out, =1 takes them untimed
+  // the LDS-tiled pass B (mixed form) is a candidate where its tiles fit
+  // the lattice; LBE_PASS_TILE=0 leaves it out, =1 takes it untimed
   const char *pt = getenv("LBE_PASS_TILE");
   const int tile_env = pt && *pt ? (*pt != '0' ? 1 : 0) : -1;
   const bool tile_ok = c->mixed && tiles_fit(c->L) && tile_env != 0;
@@ -1733,23 +1733,24 @@ int autotune_passes(lbe_ctx *c) {
     float best = 1e30f;
     int pick = 256;
     for (int tb : cand_all) {
-      if (tb == TB_TILED && !tile_ok) continue;
-      if (tile_ok && tile_env == 1 && tb != TB_TILED) continue;
+      // LDS tiles for pass B only
+      if (tb == TB_TILED && !(pass == 1 && tile_ok)) continue;
+      if (pass == 1 && tile_ok && tile_env == 1 && tb != TB_TILED) continue;
       float t_min = 1e30f;
       for (int rep = 0; rep < 4 && rc == LBE_OK; ++rep) {
         hipError_t e = hipEventRecord(e0, c->stream);
         if (e == hipSuccess) {
           if (pass == 0)
             e = c->mixed ? launch_fluid_f32(c->stream, c->L, c->P, c->mask, c->phi, c->nu32[a],
-                                            c->h32[a], c->h32[b], c->u32, c->nu32[b], tb, c->nt)
+                                            c->h32[a], c->h32[b], c->u32, c->nu32[b], tb, c->nt_a)
                          : launch_fluid_f64(c->stream, c->L, c->P, c->mask, c->phi, c->n[a],
-                                            c->f[a], c->f[b], c->u, c->n[b], tb, c->nt);
+                                            c->f[a], c->f[b], c->u, c->n[b], tb, c->nt_a);
           else
             e = c->mixed ? launch_ions_f32(c->stream, c->L, c->P, c->mask, c->u32, c->nu32[a],
                                            c->lo32[a], c->nu32[b], c->lo32[b], src_s, -1,
-                                           c->phi, keep_s, tb, c->nt)
+                                           c->phi, keep_s, tb, c->nt_b)
                          : launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a],
-                                           c->n[b], src_s, -1, c->phi, keep_s, tb, c->nt);
+                                           c->n[b], src_s, -1, c->phi, keep_s, tb, c->nt_b);
         }
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -2086,13 +2087,20 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
   TRY(record_charge(c));
   {
     // Non-temporal streams in the step passes when the populations alone
-    // overflow the 256 MB last-level cache (measured on the 192^3 porous
-    // electrode: pass A 385 -> 368 us in FP32; on the cache-resident
-    // 64x64x130 slab they cost 7%).  LBE_NT=0|1 overrides.
-    const char *ntv = getenv("LBE_NT");
-    c->nt = ntv && *ntv ? (*ntv != '0')
-                        : (size_t)NQ * N * (c->mixed ? sizeof(float) : sizeof(double)) >
-                              ((size_t)256 << 20);
+    // overflow the 256 MB last-level cache (on the cache-resident 64x64x130
+    // slab they cost 7%).  LBE_NT=0|1 sets both passes, LBE_NT_A, LBE_NT_B
+    // one each.
+    {
+      const bool big = (size_t)NQ * N * (c->mixed ? sizeof(float) : sizeof(double)) >
+                       ((size_t)256 << 20);
+      auto env_flag = [](const char *name, int dflt) {
+        const char *v = getenv(name);
+        return v && *v ? (*v != '0' ? 1 : 0) : dflt;
+      };
+      const int both = env_flag("LBE_NT", -1);
+      c->nt_a = env_flag("LBE_NT_A", both >= 0 ? both : (big ? 1 : 0)) != 0;
+      c->nt_b = env_flag("LBE_NT_B", both >= 0 ? both : (big ? 1 : 0)) != 0;
+    }
     // LBE_PASS_BLOCK=128|256|512 fixes the passes' block size; LBE_NO_AUTOTUNE
     // keeps 256; otherwise the context times the candidates
     const char *pb = getenv("LBE_PASS_BLOCK");

@@ -67,9 +67,12 @@ __device__ __forceinline__ void pull_f32(const Lattice &L, int r, uint32_t m, co
 // the increment dnu_k = -sum_i j_k (applied by k_ions_f32).
 //
 // The arithmetic at a fluid node r, its neighbours' potential and deviations
-// taken from nb (nb.phi(i), nb.nu(k, i) at r + c_i): registers loaded by
-// k_fluid_f32, or the LDS planes of k_fluid_f32_tiled.  Writes the new
-// populations hn, the velocity and the increments dno.
+// taken from nb (nb.phi(i), nb.nu(k, i) at r + c_i).  Writes the new
+// populations hn, the velocity and the increments dno.  (Pass A keeps its
+// neighbour loads in registers: on LDS tiles like pass B's its population
+// pulls cross the tile boundaries at other times than the neighbouring
+// tiles read the same lines, which measured 1.06 GB fetched per launch at
+// 192^3 against 0.64 GB, for no gain in time.)
 template <int K, bool NT, class NB>
 __device__ __forceinline__ void fluid_node_f32(const Lattice &L, const Phys &P, int r, uint32_t m,
                                                const Offs &o, double ph, const float (&dv)[K],
@@ -265,115 +268,6 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
   st_stream<NT>(sbase(u + 2 * N), r, uz);
 #pragma unroll
   for (int k = 0; k < K; ++k) st_stream<NT>(sbase(dnu + k * N), r, dno[k]);
-}
-
-// neighbour values from the LDS planes of a tile (slot of plane z + c_z,
-// halo cell hc + c_x + (TILE_X + 2) c_y)
-template <int K>
-struct NbTile {
-  const double (*sp)[(TILE_X + 2) * (TILE_Y + 2)];
-  const float (*sn)[K][(TILE_X + 2) * (TILE_Y + 2)];
-  int zrel, hc;  // z - z0 + 1 of the node, its halo cell
-  __device__ __forceinline__ int slot(int i) const { return (zrel + CZ[i]) & 3; }
-  __device__ __forceinline__ int cell(int i) const { return hc + CX[i] + (TILE_X + 2) * CY[i]; }
-  __device__ __forceinline__ double phi(int i) const { return sp[slot(i)][cell(i)]; }
-  __device__ __forceinline__ float nu(int k, int i) const { return sn[slot(i)][k][cell(i)]; }
-};
-
-// Pass A on LDS-staged tiles, as k_ions_f32_tiled: the potential and the
-// deviations of three planes (with the x, y halo) in LDS, the next plane's
-// loads in flight during the current one, a ring of four slots and one
-// barrier per plane.  Same arithmetic as k_fluid_f32, hence the same bits.
-template <int K, bool NT>
-__global__ __launch_bounds__(TILE_X * TILE_Y) void k_fluid_f32_tiled(
-    Lattice L, Phys P, const uint32_t *__restrict__ mask, const double *__restrict__ phi,
-    const float *__restrict__ nu, const float *__restrict__ hin, float *__restrict__ hout,
-    float *__restrict__ u, float *__restrict__ dnu) {
-  constexpr int NT_ = TILE_X * TILE_Y, HX = TILE_X + 2, HP = (TILE_X + 2) * (TILE_Y + 2);
-  constexpr int PER = (HP + NT_ - 1) / NT_;
-  __shared__ double sp[4][HP];
-  __shared__ float sn[4][K][HP];
-  const int N = L.n;
-  int b = blockIdx.x;
-  const int ntx = L.nx / TILE_X, nty = L.ny / TILE_Y;
-  const int x0 = (b % ntx) * TILE_X;
-  b /= ntx;
-  const int y0 = (b % nty) * TILE_Y;
-  const int z0 = (b / nty) * TILE_Z;
-  const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
-  uint32_t gxy[PER];
-  int cidx[PER];
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int c = threadIdx.x + j * NT_;
-    cidx[j] = c < HP ? c : -1;
-    const int cc = c < HP ? c : 0;
-    const int hy = cc / HX, hx = cc - hy * HX;
-    int gx = x0 + hx - 1, gy = y0 + hy - 1;
-    gx = gx < 0 ? gx + L.nx : (gx >= L.nx ? gx - L.nx : gx);
-    gy = gy < 0 ? gy + L.ny : (gy >= L.ny ? gy - L.ny : gy);
-    gxy[j] = gx + L.nx * gy;
-  }
-  double rp[PER];
-  float rn[PER][K];
-  auto fetch = [&](int z) {
-    const int zz = z < 0 ? z + L.nz : (z >= L.nz ? z - L.nz : z);
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      if (cidx[j] < 0) continue;
-      const uint32_t g = gxy[j] + (uint32_t)L.nxy * zz;
-      rp[j] = ld32(phi, g);
-#pragma unroll
-      for (int k = 0; k < K; ++k) rn[j][k] = ld32(sbase(nu + k * N), g);
-    }
-  };
-  auto put = [&](int slot) {
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      if (cidx[j] < 0) continue;
-      sp[slot][cidx[j]] = rp[j];
-#pragma unroll
-      for (int k = 0; k < K; ++k) sn[slot][k][cidx[j]] = rn[j][k];
-    }
-  };
-  fetch(z0 - 1);
-  put(0);
-  fetch(z0);
-  put(1);
-  fetch(z0 + 1);
-  const int zend = min(z0 + TILE_Z, L.nz);
-  const int hc = (lx + 1) + HX * (ly + 1);
-  const int rxy = (x0 + lx) + L.nx * (y0 + ly);
-  for (int z = z0; z < zend; ++z) {
-    put((z - z0 + 2) & 3);  // plane z + 1
-    if (z + 1 < zend) fetch(z + 2);
-    __syncthreads();
-    const int r = rxy + L.nxy * z;
-    const uint32_t m = mask[r];
-    float hn[NQ], dno[K], ux = 0.f, uy = 0.f, uz = 0.f;
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) hn[i] = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) dno[k] = 0.f;
-    if (!(m & SOLID_BIT)) {
-      Offs o;
-      site_offsets(L, r, o);
-      const int s0 = (z - z0 + 1) & 3;
-      const double ph = sp[s0][hc];
-      float dv[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) dv[k] = sn[s0][k][hc];
-      NbTile<K> nb{sp, sn, z - z0 + 1, hc};
-      fluid_node_f32<K, NT>(L, P, r, m, o, ph, dv, nb, hin, hn, ux, uy, uz, dno);
-    }
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) st_stream<NT>(sbase(hout + i * N), r, hn[i]);
-    st_stream<NT>(u, r, ux);
-    st_stream<NT>(sbase(u + N), r, uy);
-    st_stream<NT>(sbase(u + 2 * N), r, uz);
-#pragma unroll
-    for (int k = 0; k < K; ++k) st_stream<NT>(sbase(dnu + k * N), r, dno[k]);
-  }
 }
 
 // Pass B: advective link fluxes J_k = 3 w_i c_i . (n_k u + n_k' u') with the
@@ -751,24 +645,6 @@ __global__ __launch_bounds__(BLOCK) void k_expand_n_f32(Lattice L, int K, const 
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
                             float *u, float *dnu, int tb, bool nt) {
-  if (tb == TB_TILED) {
-    if (!tiles_fit(L)) return hipErrorInvalidValue;
-    const unsigned nb = (unsigned)((L.nx / TILE_X) * (L.ny / TILE_Y) *
-                                   ((L.nz + TILE_Z - 1) / TILE_Z));
-#define CALL(KK, NT) \
-  hipLaunchKernelGGL((k_fluid_f32_tiled<KK, NT>), dim3(nb), dim3(TILE_X * TILE_Y), 0, s, L, P, mask, phi, nu, hin, hout, u, dnu)
-#define CALL_T(KK) CALL(KK, true)
-#define CALL_F(KK) CALL(KK, false)
-    if (nt) {
-      LBE_DISPATCH_K(P.K, CALL_T)
-    } else {
-      LBE_DISPATCH_K(P.K, CALL_F)
-    }
-#undef CALL_T
-#undef CALL_F
-#undef CALL
-    return hipGetLastError();
-  }
 #define CALL(KK, TB, NT) \
   hipLaunchKernelGGL((k_fluid_f32<KK, TB, NT>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, nu, hin, hout, u, dnu)
   LBE_DISPATCH_K_TB_NT(P.K, tb, nt, CALL)
