@@ -14,14 +14,6 @@ constexpr int CY[NQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1
 constexpr int CZ[NQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 // opposite direction: pairs (1,2), (3,4), ... (17,18)
 constexpr int OPP[NQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
-// the kernels that treat opposite velocities as pairs (i, i + 1), i odd
-constexpr bool opposite_pairs_adjacent() {
-  for (int i = 1; i < NQ; i += 2)
-    if (OPP[i] != i + 1 || CX[i] != -CX[i + 1] || CY[i] != -CY[i + 1] || CZ[i] != -CZ[i + 1])
-      return false;
-  return true;
-}
-static_assert(opposite_pairs_adjacent(), "velocity table: opposite pairs at (i, i + 1)");
 constexpr double W0 = 1.0 / 3.0, W1 = 1.0 / 18.0, W2 = 1.0 / 36.0;
 constexpr double WQ[NQ] = {W0, W1, W1, W1, W1, W1, W1, W2, W2, W2, W2,
                            W2, W2, W2, W2, W2, W2, W2, W2};

@@ -181,30 +181,24 @@ __device__ __forceinline__ void fluid_node_f32(const Lattice &L, const Phys &P, 
   uy = (m1 + 0.5f * F1) / rho;
   uz = (m2 + 0.5f * F2) / rho;
   const float uu = ux * ux + uy * uy + uz * uz;
-  const float uF = ux * F0 + uy * F1 + uz * F2;
   const float itau = P.itau_f;
   const float guo = 1.f - 0.5f * itau;
-  // Equilibrium (minus the rest state w_i rho0) and Guo source, a pair of
-  // opposite velocities at a time: with cu = c_i . u and cF = c_i . F,
-  // heq = w (drho + rho (4.5 cu^2 - 1.5 u.u)) +- 3 w rho cu and
-  // s = w guo (9 cu cF - 3 u.F) +- 3 w guo cF for c_i and -c_i.
-  {
-    const float w = float(WQ[0]);
-    const float heq = w * (drho + rho * (-1.5f * uu));
-    hn[0] = h[0] - (h[0] - heq) * itau + (w * guo) * (-3.f * uF);
-  }
+  // Each velocity on its own: forming the pairs c_i, -c_i from shared even
+  // and odd parts (w rho 3 c.u added after the rest) measured 11 us faster
+  // at 192^3 but tripled the velocity's difference from the FP64 form over
+  // the configured runs (coaxial cell, 30000 steps: 1.1e-4 of max |u|
+  // against 3.6e-5).
 #pragma unroll
-  for (int i = 1; i < NQ; i += 2) {
-    const int j = OPP[i];
+  for (int i = 0; i < NQ; ++i) {
     const float w = float(WQ[i]);
     const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-    const float cF = CX[i] * F0 + CY[i] * F1 + CZ[i] * F2;
-    const float even = w * (drho + rho * (4.5f * cu * cu - 1.5f * uu));
-    const float odd = (3.f * w) * rho * cu;
-    const float se = (w * guo) * (9.f * cu * cF - 3.f * uF);
-    const float so = (3.f * w * guo) * cF;
-    hn[i] = h[i] - (h[i] - (even + odd)) * itau + (se + so);
-    hn[j] = h[j] - (h[j] - (even - odd)) * itau + (se - so);
+    // equilibrium minus the rest state w_i rho0
+    const float heq = w * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+    const float s = ((3.f * (CX[i] - ux) + 9.f * cu * CX[i]) * F0 +
+                     (3.f * (CY[i] - uy) + 9.f * cu * CY[i]) * F1 +
+                     (3.f * (CZ[i] - uz) + 9.f * cu * CZ[i]) * F2) *
+                    (guo * w);
+    hn[i] = h[i] - (h[i] - heq) * itau + s;
   }
 #pragma unroll
   for (int k = 0; k < K; ++k) dno[k] = -js[k];
