@@ -90,17 +90,44 @@ __device__ __forceinline__ void gather_lv_g(const MgLevel &lv, const Coords &c, 
     v[i] = ld32(e, (uint32_t)(r + ox[CX[i] + 1] + oy[CY[i] + 1] + oz[CZ[i] + 1]));
 }
 
-// A e at a fluid cell from its gathered values v, in the level's units:
-// (6/h^2) sum_i w_i s_i (e - e_i)
+// Weights of a fluid cell's links that do not map it onto itself, from two
+// popcounts of its flag word (links 1-6 carry W1, links 7-18 W2): all of
+// them (live) or those towards a solid cell (wall).
+template <class T>
+__device__ __forceinline__ T link_weight(uint32_t bits) {
+  return T(W1) * T(__popc(bits & 0x3Fu)) + T(W2) * T(__popc(bits & 0x3FFC0u));
+}
+
+// The stencil's diagonal at a fluid cell, sum_i w_i s_i over the non-self
+// links (s_i = wall towards a solid cell, 1 otherwise).  Every kernel that
+// needs it takes it from here, so that a first sweep taken by another kernel
+// matches k_jacobi's bit for bit.
+template <class T>
+__device__ __forceinline__ T stencil_diag(const MgLevel &lv, uint32_t m) {
+  const uint32_t live = ~lv.selfm & 0x3FFFFu;
+  return link_weight<T>(live) + T(lv.wall - 1.0) * link_weight<T>(m & live);
+}
+
+// A correction is exactly zero at every solid cell on every level: each
+// kernel that writes one writes T(0) there (or leaves the zero in place).
+// So in the sums below the wall factor s_i only ever multiplies a zero
+// neighbour value, and a link towards a solid cell needs no select of its
+// own: the sums run over the plain weights w_i and the wall's extra
+// (s_i - 1) w_i e enters once, through the flag word.
+
+// A e at a fluid cell from its gathered correction values v, in the level's
+// units: (6/h^2) sum_i w_i s_i (e - e_i), as differences (accurate when e is
+// smooth), with e_i = 0 towards a solid cell.
 template <class T>
 __device__ __forceinline__ T apply_A_v(const MgLevel &lv, uint32_t m, const T (&v)[NQ]) {
   T acc = T(0);
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((lv.selfm >> (i - 1)) & 1u) continue;
-    const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
-    acc += ws * (v[0] - v[i]);
+    acc += T(WQ[i]) * (v[0] - v[i]);
   }
+  const uint32_t live = ~lv.selfm & 0x3FFFFu;
+  acc += (T(lv.wall - 1.0) * link_weight<T>(m & live)) * v[0];
   return T(6.0) * T(lv.inv_h2) * acc;
 }
 
@@ -124,13 +151,7 @@ __device__ __forceinline__ T apply_A(const MgLevel &lv, int r, uint32_t m, const
 template <class T>
 __device__ __forceinline__ T coarse_start(const MgLevel &lv, uint32_t m, T rr, T jac, T hs) {
   if (jac == T(0) || (m & SOLID_BIT)) return T(0);
-  T den = T(0);
-#pragma unroll
-  for (int i = 1; i < NQ; ++i) {
-    if ((lv.selfm >> (i - 1)) & 1u) continue;
-    den += solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
-  }
-  return jac * ((hs * rr) / den);
+  return jac * ((hs * rr) / stencil_diag<T>(lv, m));
 }
 
 // ---- outer residual (FP64) ----------------------------------------------------
@@ -156,6 +177,8 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
     gather_lv_g(lv, c, r, phi, pn);
     const double sr = src[r];
     const uint32_t m = mask[r];
+    // the potential itself, not a correction: solid neighbours hold the
+    // electrode's value, so each wall link takes its factor here
     double acc = 0.0;
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
@@ -172,16 +195,8 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
     // k_jacobi with every neighbour value 0)
     T e = T(0);
     if (jacobi > T(0) && !(m & SOLID_BIT)) {
-      T num = T(0), den = T(0);
-#pragma unroll
-      for (int i = 1; i < NQ; ++i) {
-        if ((lv.selfm >> (i - 1)) & 1u) continue;
-        const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
-        num += ws * T(0);
-        den += ws;
-      }
-      num += T(lv.h2 / 6.0) * rr;
-      e = T(0) + jacobi * (num / den - T(0));
+      const T num = T(lv.h2 / 6.0) * rr;  // the neighbour sum is +0
+      e = T(0) + jacobi * (num / stencil_diag<T>(lv, m) - T(0));
     }
     e0[r] = e;
     if (r64) r64[r] = R;
@@ -356,14 +371,13 @@ __global__ __launch_bounds__(BLOCK) void k_smooth(MgLevel lv, T omega, int colou
   T v[NQ];
   gather_lv(lv, c, r, (const T *)e, v);
   const T rr = rhs[r];
-  T num = T(0), den = T(0);
+  T num = T(0);
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((lv.selfm >> (i - 1)) & 1u) continue;
-    const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
-    num += ws * v[i];
-    den += ws;
+    num += T(WQ[i]) * v[i];
   }
+  const T den = stencil_diag<T>(lv, m);
   num += T(lv.h2 / 6.0) * rr;
   e[r] = (T(1) - omega) * v[0] + omega * (num / den);
 }
@@ -390,14 +404,13 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
   gather_lv_g(lv, c, r, x_in, v);
   const T rr = rhs[r];
   const uint32_t m = mask[r];
-  T num = T(0), den = T(0);
+  T num = T(0);
 #pragma unroll
   for (int i = 1; i < NQ; ++i) {
     if ((lv.selfm >> (i - 1)) & 1u) continue;
-    const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
-    num += ws * v[i];
-    den += ws;
+    num += T(WQ[i]) * v[i];
   }
+  const T den = stencil_diag<T>(lv, m);
   num += hs * rr;
   const T xr = v[0];
   const bool solid = m & SOLID_BIT;
@@ -639,14 +652,13 @@ __global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, T 
           const Coords c = coords_of(r, lv);
           T v[NQ];
           gather_lv(lv, c, r, xi, v);
-          T num = T(0), den = T(0);
+          T num = T(0);
 #pragma unroll
           for (int i = 1; i < NQ; ++i) {
             if ((lv.selfm >> (i - 1)) & 1u) continue;
-            const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
-            num += ws * v[i];
-            den += ws;
+            num += T(WQ[i]) * v[i];
           }
+          const T den = stencil_diag<T>(lv, m);
           num += hs * rhs[r];
           xo[r] = v[0] + jacobi * (num / den - v[0]);
         }
@@ -662,14 +674,13 @@ __global__ __launch_bounds__(COARSE_BLOCK) void k_coarse(MgLevel lv, T omega, T 
         if ((((c.x + c.z) & 1) + 2 * ((c.y + c.z) & 1)) != col) continue;
         const uint32_t m = mask[r];
         if (m & SOLID_BIT) continue;
-        T num = T(0), den = T(0);
+        T num = T(0);
 #pragma unroll
         for (int i = 1; i < NQ; ++i) {
           if ((lv.selfm >> (i - 1)) & 1u) continue;
-          const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
-          num += ws * e[nbr_of(lv, c, i)];
-          den += ws;
+          num += T(WQ[i]) * e[nbr_of(lv, c, i)];
         }
+        const T den = stencil_diag<T>(lv, m);
         num += hs * rhs[r];
         e[r] = (T(1) - omega) * e[r] + omega * (num / den);
       }
@@ -764,14 +775,13 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
           const Coords c = coords_of(r, lv);
           T v[NQ];
           gather_lv(lv, c, r, xi, v);
-          T num = T(0), den = T(0);
+          T num = T(0);
 #pragma unroll
           for (int i = 1; i < NQ; ++i) {
             if ((lv.selfm >> (i - 1)) & 1u) continue;
-            const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
-            num += ws * v[i];
-            den += ws;
+            num += T(WQ[i]) * v[i];
           }
+          const T den = stencil_diag<T>(lv, m);
           num += hs * rh[r];
           xo[r] = v[0] + om * (num / den - v[0]);
         }
@@ -805,14 +815,13 @@ __device__ void small_smooth(const MgSmall &S, int k, int sweeps, T *lds, const 
         if (m & SOLID_BIT) continue;
         T v[NQ];
         gather_lv(lv, c, r, (const T *)e, v);
-        T num = T(0), den = T(0);
+        T num = T(0);
 #pragma unroll
         for (int i = 1; i < NQ; ++i) {
           if ((lv.selfm >> (i - 1)) & 1u) continue;
-          const T ws = solid_link(m, i) ? T(lv.wall * WQ[i]) : T(WQ[i]);
-          num += ws * v[i];
-          den += ws;
+          num += T(WQ[i]) * v[i];
         }
+        const T den = stencil_diag<T>(lv, m);
         num += hs * rh[r];
         e[r] = num / den;  // Gauss-Seidel (omega = 1)
       }
