@@ -59,6 +59,7 @@ struct lbe_ctx {
   int pred_iters = 0;         // iterations the last time-step solve needed
   bool use_graphs = true;     // replay one solver unit as a captured HIP graph
   bool tiles = true;          // the row-order (LDS-combined) restriction where it applies
+  int rings = RING_AUTO;      // plane-ring stencil kernels (RING_OFF, RING_AUTO, a run length)
   bool coarse_start = true;   // restriction writes the coarse level's first Jacobi sweep
   int tb_a = 256, tb_b = 256;  // block sizes of the step passes A and B (tuned at init)
   bool nt_a = false, nt_b = false;  // non-temporal streams in passes A and B (set at init)
@@ -1044,7 +1045,7 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
         const KernelKind kind = last && add_to ? KK_MG_SMOOTH0_PHI : sk;
         const int r2 = run(c, kind, L.lv.n, [&] {
           return launch_jacobi<T>(c->stream, L.lv, c->mg_jacobi, L.lv.h2 / 6.0, L.mask, r, cur,
-                                  alt, c->ctl, last ? add_to : nullptr);
+                                  alt, c->ctl, last ? add_to : nullptr, c->rings);
         });
         if (r2) return r2;
         std::swap(cur, alt);
@@ -1109,7 +1110,7 @@ int mg_solve(lbe_ctx *c, bool learn) {
             if (rc) return rc;
             rc = run(c, KK_FCG_APPLY, n, [&] {
               return launch_fcg_apply<T>(c->stream, L0.lv, c->mask, (const T *)z, c->kq, c->kp,
-                                         c->kr, c->kaz, c->partial, c->kc, c->ctl);
+                                         c->kr, c->kaz, c->partial, c->kc, c->ctl, c->rings);
             });
             if (rc) return rc;
             // every iteration ends with its own stop check (one cycle each)
@@ -1127,7 +1128,7 @@ int mg_solve(lbe_ctx *c, bool learn) {
           return run(c, KK_MG_RESID, n, [&] {
             return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi,
                                             (T *)L0.r, (T *)L0.e, c->partial, c->ctl, 0, c->kr,
-                                            c->kc, first_sweep);
+                                            c->kc, first_sweep, c->rings);
           });
         });
   }
@@ -1152,7 +1153,7 @@ int mg_solve(lbe_ctx *c, bool learn) {
         return run(c, KK_MG_RESID, L0.lv.n, [&] {
           return launch_mg_outer_resid<T>(c->stream, L0.lv, c->mask, c->src, c->phi, (T *)L0.r,
                                           (T *)L0.e, c->partial, c->ctl, add, nullptr, nullptr,
-                                          first_sweep);
+                                          first_sweep, c->rings);
         });
       });
 }
@@ -1199,7 +1200,7 @@ int mixed_sor_solve(lbe_ctx *c, bool learn) {
         return run(c, KK_MG_RESID, L0.lv.n, [&] {
           return launch_mg_outer_resid<float>(c->stream, L0.lv, c->mask, c->src, c->phi,
                                               (float *)L0.r, (float *)L0.e, c->partial, c->ctl,
-                                              add, nullptr, nullptr, 0.0);
+                                              add, nullptr, nullptr, 0.0, c->rings);
         });
       });
 }
@@ -1873,6 +1874,12 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     c->use_graphs = !(ng && *ng && *ng != '0');
     const char *nt = getenv("LBE_NO_TILES");  // the eight-lane restriction only (same results)
     c->tiles = !(nt && *nt && *nt != '0');
+    // the stencil kernels gathering from global memory (same results, the
+    // Krylov sums aside), or their plane rings at a given run length on every
+    // level that fits them
+    const char *nr = getenv("LBE_NO_RINGS");
+    const char *zr = getenv("LBE_RING_ZRUN");
+    c->rings = (nr && *nr && *nr != '0') ? RING_OFF : (zr && atoi(zr) > 0 ? atoi(zr) : RING_AUTO);
     // the coarse levels' first sweep as a separate launch (same results)
     const char *ns = getenv("LBE_NO_COARSE_START");
     c->coarse_start = !(ns && *ns && *ns != '0');

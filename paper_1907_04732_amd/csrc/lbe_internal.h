@@ -89,6 +89,30 @@ inline MgLevel make_level(int nx, int ny, int nz, uint32_t selfm, double h2, dou
                  1.0 / nx, 1.0 / ((double)nx * ny), xcd};
 }
 
+// The stencil kernels' plane-ring form (LDS-staged TILE_X x TILE_Y tiles,
+// each block marching along z through a run of zrun planes) applies to a
+// level whose nx and ny are multiples of the tile's.  A run takes RING_ZRUN
+// planes, or fewer so that the launch keeps RING_MIN_BLOCKS blocks, but not
+// fewer than RING_MIN_ZRUN (each run reloads two planes around it); below
+// that the level is too small for the form and ring_zrun returns 0.  (On
+// the 192^3 lattice runs of 16, 8, 4 and 2 planes gave the finest-level
+// kernels 1728, 3456, 6912 and 13824 blocks; 8 was the fastest.)
+// A launcher's `ring` is RING_OFF, RING_AUTO (that rule) or a run length
+// forced (> 0, on levels that fit).
+constexpr int RING_ZRUN = 8, RING_MIN_BLOCKS = 1024, RING_MIN_ZRUN = 4;
+constexpr int RING_OFF = -1, RING_AUTO = 0;
+inline int ring_zrun(const MgLevel &lv, int ring) {  // 0: the gathering kernels
+  if (ring == RING_OFF || lv.nx % TILE_X || lv.ny % TILE_Y) return 0;
+  if (ring > 0) return ring;
+  const long tiles = (long)(lv.nx / TILE_X) * (lv.ny / TILE_Y);
+  for (int zr = RING_ZRUN; zr >= RING_MIN_ZRUN; zr /= 2)
+    if (tiles * ((lv.nz + zr - 1) / zr) >= RING_MIN_BLOCKS) return zr;
+  return 0;
+}
+inline int ring_blocks(const MgLevel &lv, int zrun) {
+  return (lv.nx / TILE_X) * (lv.ny / TILE_Y) * ((lv.nz + zrun - 1) / zrun);
+}
+
 // Fine level f -> coarse level c: coarse cell (X, Y, Z) holds the fine cells
 // whose shifted indices ((x - ox) mod nx, ...) are (2X or 2X+1, ...).
 struct MgTransfer {
@@ -297,7 +321,10 @@ hipError_t launch_adj_seed_momentum(hipStream_t s, const Lattice &L, const uint3
 hipError_t launch_adj_phis(hipStream_t s, const Lattice &L, const uint32_t *mask,
                            const double *lam_sum, double *gphis);
 
-// multigrid (lbe_mg.hip); T = double (FP64 form) or float (mixed form)
+// multigrid (lbe_mg.hip); T = double (FP64 form) or float (mixed form).
+// `ring` selects the plane-ring form of a stencil kernel (ring_zrun): the
+// same values per cell, and in launch_fcg_apply the Krylov sums in another
+// (fixed) order.
 // FP64 residual check; writes the correction's right-hand side r0 and its
 // start e0: 0, or with jacobi > 0 the result of one Jacobi sweep of that
 // weight from 0 (pointwise), so a V-cycle can skip its first sweep
@@ -305,7 +332,7 @@ template <class T>
 hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
                                  const double *src, const double *phi, T *r0, T *e0,
                                  double *partial, SolveCtl *ctl, int add, double *r64,
-                                 KrylovCtl *kc, double jacobi);
+                                 KrylovCtl *kc, double jacobi, int ring);
 // Flexible CG on A e = R (A = -L_h, level 0), preconditioner z = V-cycle(r):
 //   beta = -(z, q_prev) / (p_prev, q_prev) (0 for the first direction),
 //   p = z + beta p,  q = A p,  alpha = (r, p) / (p, q),
@@ -317,7 +344,8 @@ hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_
 template <class T>
 hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *mask, const T *z,
                             const double *q_prev, const double *p_prev, const double *r,
-                            double *az, double *partial, KrylovCtl *kc, const SolveCtl *ctl);
+                            double *az, double *partial, KrylovCtl *kc, const SolveCtl *ctl,
+                            int ring);
 template <class T>
 hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const T *z,
                              const double *az, double *p, double *q, double *phi, double *r,
@@ -333,7 +361,7 @@ hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int 
 template <class T>
 hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double hs,
                          const uint32_t *mask, const T *rhs, const T *x_in, T *x_out,
-                         const SolveCtl *ctl, double *phi_add);
+                         const SolveCtl *ctl, double *phi_add, int ring);
 template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,

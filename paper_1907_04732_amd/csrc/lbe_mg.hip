@@ -205,6 +205,171 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
   if (threadIdx.x == 0) partial[lb] = a;
 }
 
+// ---- LDS plane rings on wide levels -------------------------------------------
+// Where a level's nx is a multiple of TILE_X and its ny of TILE_Y, the stencil
+// kernels below also come in a form where a block of TILE_X x TILE_Y cells
+// marches along z through a run of zrun planes (ring_zrun).  The planes
+// z - 1, z, z + 1 of the gathered array (with a one-cell halo in x and y,
+// wrapped periodically) sit in a ring of four LDS slots, and the plane z + 2
+// travels in registers while the plane z is computed.  Each value is then
+// read from memory about once per tile instead of once per neighbour: the
+// gathers of the untiled kernels keep the texture units busy long before
+// memory is.  A cell sees the same neighbour values as through gather_lv_g,
+// so its arithmetic is unchanged.
+
+constexpr int RING_HX = TILE_X + 2, RING_HP = RING_HX * (TILE_Y + 2);
+constexpr int RING_PER = (RING_HP + BLOCK - 1) / BLOCK;  // halo cells per thread
+static_assert(TILE_X * TILE_Y == BLOCK, "one cell of a plane per thread");
+
+struct RingTile {
+  int x0, y0, z0, zend;  // the tile's corner and its planes [z0, zend)
+  int lb;                // logical block: reduction partials keep this order
+  uint32_t rxy;          // this thread's cell within a plane
+  int hc;                // and its halo cell in a slot
+};
+
+__device__ __forceinline__ RingTile ring_tile(const MgLevel &lv, int zrun) {
+  const int ntx = lv.nx / TILE_X, nty = lv.ny / TILE_Y;
+  RingTile t;
+  // consecutive tiles of a run of planes on one die, so that the halos they
+  // share meet in its L2
+  int b = xcd_block(blockIdx.x, gridDim.x, 1, ntx * nty, lv.xcd);
+  t.lb = b;
+  t.x0 = (b % ntx) * TILE_X;
+  b /= ntx;
+  t.y0 = (b % nty) * TILE_Y;
+  t.z0 = (b / nty) * zrun;
+  t.zend = min(t.z0 + zrun, lv.nz);
+  const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
+  t.rxy = (uint32_t)((t.x0 + lx) + lv.nx * (t.y0 + ly));
+  t.hc = (lx + 1) + RING_HX * (ly + 1);
+  return t;
+}
+
+// This thread's share of a plane's halo cells: loaded into registers by
+// fetch, stored into a slot by put.
+template <class T>
+struct PlaneRing {
+  uint32_t gxy[RING_PER];  // offset of the cell within a plane
+  int cidx[RING_PER];      // its index in a slot, -1 for none
+  T reg[RING_PER];
+
+  __device__ __forceinline__ void init(const MgLevel &lv, const RingTile &t) {
+#pragma unroll
+    for (int j = 0; j < RING_PER; ++j) {
+      const int c = threadIdx.x + j * BLOCK;
+      cidx[j] = c < RING_HP ? c : -1;
+      const int cc = c < RING_HP ? c : 0;
+      const int hy = cc / RING_HX, hx = cc - hy * RING_HX;
+      const int gx = wrapi(t.x0 + hx - 1, lv.nx), gy = wrapi(t.y0 + hy - 1, lv.ny);
+      gxy[j] = (uint32_t)(gx + lv.nx * gy);
+    }
+  }
+  // plane z, wrapped periodically
+  __device__ __forceinline__ void fetch(const MgLevel &lv, const T *__restrict__ a, int z) {
+    const int zz = wrapi(z, lv.nz);
+#pragma unroll
+    for (int j = 0; j < RING_PER; ++j)
+      if (cidx[j] >= 0) reg[j] = ld32(a, gxy[j] + (uint32_t)lv.nxy * (uint32_t)zz);
+  }
+  __device__ __forceinline__ void put(T *slot) const {
+#pragma unroll
+    for (int j = 0; j < RING_PER; ++j)
+      if (cidx[j] >= 0) slot[cidx[j]] = reg[j];
+  }
+};
+
+// The slots start as planes z0 - 1 and z0, with z0 + 1 in registers; the
+// plane z0 + k then sits in slot (k + 1) & 3.
+template <class T>
+__device__ __forceinline__ void ring_start(const MgLevel &lv, const RingTile &t,
+                                           PlaneRing<T> &pr, T (*ring)[RING_HP],
+                                           const T *__restrict__ a) {
+  pr.init(lv, t);
+  pr.fetch(lv, a, t.z0 - 1);
+  pr.put(ring[0]);
+  pr.fetch(lv, a, t.z0);
+  pr.put(ring[1]);
+  pr.fetch(lv, a, t.z0 + 1);
+}
+
+// At plane z: store plane z + 1 into its slot and start loading z + 2.
+// The slot written held plane z - 2, read in the previous step, which every
+// thread has left at the barrier the caller passes next; so one barrier per
+// plane suffices.
+template <class T>
+__device__ __forceinline__ void ring_advance(const MgLevel &lv, const RingTile &t, int z,
+                                             PlaneRing<T> &pr, T (*ring)[RING_HP],
+                                             const T *__restrict__ a) {
+  pr.put(ring[(z - t.z0 + 2) & 3]);
+  if (z + 1 < t.zend) pr.fetch(lv, a, z + 2);
+}
+
+// v[i] = the value at the neighbour c + c_i of this thread's cell in plane z
+template <class T>
+__device__ __forceinline__ void ring_gather(const RingTile &t, int z, const T (*ring)[RING_HP],
+                                            T (&v)[NQ]) {
+  const int k = z - t.z0 + 1;
+  v[0] = ring[k & 3][t.hc];
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) v[i] = ring[(k + CZ[i]) & 3][t.hc + CX[i] + RING_HX * CY[i]];
+}
+
+// The residual check of k_outer_resid on a ring of phi.  The maximum over a
+// block's cells does not depend on which cells a block takes.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_outer_resid_ring(
+    MgLevel lv, const uint32_t *__restrict__ mask, const double *__restrict__ src,
+    const double *__restrict__ phi, T *__restrict__ r0, T *__restrict__ e0,
+    double *__restrict__ partial, const SolveCtl *__restrict__ ctl, double *__restrict__ r64,
+    KrylovCtl *__restrict__ kc, T jacobi, int zrun) {
+  __shared__ double ring[4][RING_HP];
+  __shared__ double sm[BLOCK / WAVE];
+  if (ctl->done) return;
+  const RingTile t = ring_tile(lv, zrun);
+  if (kc && t.lb == 0 && threadIdx.x == 0) kc->first = 1;  // a new Krylov sequence
+  PlaneRing<double> pr;
+  ring_start(lv, t, pr, ring, phi);
+  uint32_t rn = t.rxy + (uint32_t)lv.nxy * (uint32_t)t.z0;
+  uint32_t m_next = ld32(mask, rn);
+  double s_next = ld32(src, rn);
+  double a = 0.0;
+  for (int z = t.z0; z < t.zend; ++z) {
+    const int r = (int)rn;
+    const uint32_t m = m_next;
+    const double sr = s_next;
+    ring_advance(lv, t, z, pr, ring, phi);
+    if (z + 1 < t.zend) {
+      rn += (uint32_t)lv.nxy;
+      m_next = ld32(mask, rn);
+      s_next = ld32(src, rn);
+    }
+    __syncthreads();
+    double pn[NQ];
+    ring_gather(t, z, ring, pn);
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      if ((lv.selfm >> (i - 1)) & 1u) continue;
+      const double ws = solid_link(m, i) ? lv.wall * WQ[i] : WQ[i];
+      acc += ws * (pn[i] - pn[0]);
+    }
+    const double R = (m & SOLID_BIT) ? 0.0 : 6.0 * (acc + sr);
+    a = nanmax(a, fabs(R));
+    const T rr = T(R);
+    r0[r] = rr;
+    T e = T(0);
+    if (jacobi > T(0) && !(m & SOLID_BIT)) {
+      const T num = T(lv.h2 / 6.0) * rr;
+      e = T(0) + jacobi * (num / stencil_diag<T>(lv, m) - T(0));
+    }
+    e0[r] = e;
+    if (r64) r64[r] = R;
+  }
+  a = block_max(a, sm);
+  if (threadIdx.x == 0) partial[t.lb] = a;
+}
+
 // ---- flexible conjugate gradients around the V-cycle -------------------------
 // The V-cycle is a fixed but non-symmetric preconditioner (mean restriction is
 // not the transpose of the mirrored prolongation, and the mixed form applies it
@@ -263,6 +428,68 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_az(MgLevel lv, const uint32_t *__
   if (threadIdx.x == 0) partial[2 * nb + lb] = rz;
   rp = block_sum(rp, sm);
   if (threadIdx.x == 0) partial[3 * nb + lb] = rp;
+}
+
+// k_fcg_az on a ring of z.  Each thread adds its cells' terms plane by
+// plane before the block sums, so the sums take another order than the
+// untiled kernel's (fixed for a given lattice).
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_fcg_az_ring(MgLevel lv, const uint32_t *__restrict__ mask,
+                                                       const T *__restrict__ z,
+                                                       const double *__restrict__ q_prev,
+                                                       const double *__restrict__ p_prev,
+                                                       const double *__restrict__ rv,
+                                                       double *__restrict__ az,
+                                                       double *__restrict__ partial,
+                                                       const SolveCtl *__restrict__ ctl,
+                                                       int zrun) {
+  __shared__ T ring[4][RING_HP];
+  __shared__ double sm[BLOCK / WAVE];
+  if (ctl->done) return;
+  const RingTile t = ring_tile(lv, zrun);
+  PlaneRing<T> pr;
+  ring_start(lv, t, pr, ring, z);
+  uint32_t rn = t.rxy + (uint32_t)lv.nxy * (uint32_t)t.z0;
+  uint32_t m_next = ld32(mask, rn);
+  double q_next = ld32(q_prev, rn), p_next = ld32(p_prev, rn), r_next = ld32(rv, rn);
+  double zq = 0.0, zaz = 0.0, rz = 0.0, rp = 0.0;
+  for (int zp = t.z0; zp < t.zend; ++zp) {
+    const int r = (int)rn;
+    const uint32_t m = m_next;
+    const double qv = q_next, pv = p_next, rr = r_next;
+    ring_advance(lv, t, zp, pr, ring, z);
+    if (zp + 1 < t.zend) {
+      rn += (uint32_t)lv.nxy;
+      m_next = ld32(mask, rn);
+      q_next = ld32(q_prev, rn);
+      p_next = ld32(p_prev, rn);
+      r_next = ld32(rv, rn);
+    }
+    __syncthreads();
+    T v[NQ];
+    ring_gather(t, zp, ring, v);
+    double a = 0.0;  // a solid cell stores its zero too: whole cache lines
+    if (!(m & SOLID_BIT)) {
+      double vd[NQ];
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) vd[i] = double(v[i]);
+      a = apply_A_v<double>(lv, m, vd);
+      zq += vd[0] * qv;
+      zaz += vd[0] * a;
+      rz += rr * vd[0];
+      rp += rr * pv;
+    }
+    az[r] = a;
+  }
+  const int nb = gridDim.x;
+  zq = block_sum(zq, sm);
+  if (threadIdx.x == 0) partial[t.lb] = zq;
+  zaz = block_sum(zaz, sm);
+  if (threadIdx.x == 0) partial[nb + t.lb] = zaz;
+  rz = block_sum(rz, sm);
+  if (threadIdx.x == 0) partial[2 * nb + t.lb] = rz;
+  rp = block_sum(rp, sm);
+  if (threadIdx.x == 0) partial[3 * nb + t.lb] = rp;
 }
 
 // The four sums of k_fcg_az's partials in one pass (their loads in flight
@@ -419,6 +646,52 @@ __global__ __launch_bounds__(BLOCK) void k_jacobi(MgLevel lv, T omega, T hs,
   // every cell, so that the store writes whole lines (a solid cell adds 0 to
   // its electrode potential)
   if (ADD_PHI) phi_add[r] += double(res);
+}
+
+// k_jacobi on a ring of x_in: the same values and arithmetic per cell.
+template <class T, bool ADD_PHI>
+__global__ __launch_bounds__(BLOCK) void k_jacobi_ring(MgLevel lv, T omega, T hs,
+                                                       const uint32_t *__restrict__ mask,
+                                                       const T *__restrict__ rhs,
+                                                       const T *__restrict__ x_in,
+                                                       T *__restrict__ x_out,
+                                                       const SolveCtl *__restrict__ ctl,
+                                                       double *__restrict__ phi_add, int zrun) {
+  __shared__ T ring[4][RING_HP];
+  if (ctl->done) return;
+  const RingTile t = ring_tile(lv, zrun);
+  PlaneRing<T> pr;
+  ring_start(lv, t, pr, ring, x_in);
+  uint32_t rn = t.rxy + (uint32_t)lv.nxy * (uint32_t)t.z0;
+  uint32_t m_next = ld32(mask, rn);
+  T r_next = ld32(rhs, rn);
+  for (int z = t.z0; z < t.zend; ++z) {
+    const int r = (int)rn;
+    const uint32_t m = m_next;
+    const T rr = r_next;
+    ring_advance(lv, t, z, pr, ring, x_in);
+    if (z + 1 < t.zend) {
+      rn += (uint32_t)lv.nxy;
+      m_next = ld32(mask, rn);
+      r_next = ld32(rhs, rn);
+    }
+    __syncthreads();
+    T v[NQ];
+    ring_gather(t, z, ring, v);
+    T num = T(0);
+#pragma unroll
+    for (int i = 1; i < NQ; ++i) {
+      if ((lv.selfm >> (i - 1)) & 1u) continue;
+      num += T(WQ[i]) * v[i];
+    }
+    const T den = stencil_diag<T>(lv, m);
+    num += hs * rr;
+    const T xr = v[0];
+    const bool solid = m & SOLID_BIT;
+    const T res = solid ? T(0) : xr + omega * (num / den - xr);
+    x_out[r] = res;
+    if (ADD_PHI) phi_add[r] += double(res);
+  }
 }
 
 // ---- restriction: coarse rhs = mean of the fluid children's residuals -------
@@ -972,10 +1245,15 @@ template <class T>
 hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_t *mask,
                                  const double *src, const double *phi, T *r0, T *e0,
                                  double *partial, SolveCtl *ctl, int add, double *r64,
-                                 KrylovCtl *kc, double jacobi) {
-  const int nb = (int)blocks_for(lv.n);
-  hipLaunchKernelGGL(k_outer_resid<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, src, phi, r0, e0,
-                     partial, ctl, r64, kc, T(jacobi));
+                                 KrylovCtl *kc, double jacobi, int ring) {
+  const int zrun = ring_zrun(lv, ring);
+  const int nb = zrun ? ring_blocks(lv, zrun) : (int)blocks_for(lv.n);
+  if (zrun)
+    hipLaunchKernelGGL(k_outer_resid_ring<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, src, phi, r0,
+                       e0, partial, ctl, r64, kc, T(jacobi), zrun);
+  else
+    hipLaunchKernelGGL(k_outer_resid<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, src, phi, r0, e0,
+                       partial, ctl, r64, kc, T(jacobi));
   hipLaunchKernelGGL(k_final_resid, dim3(1), dim3(FINAL), 0, s, partial, nb, ctl, add);
   return hipGetLastError();
 }
@@ -983,10 +1261,16 @@ hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_
 template <class T>
 hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *mask, const T *z,
                             const double *q_prev, const double *p_prev, const double *r,
-                            double *az, double *partial, KrylovCtl *kc, const SolveCtl *ctl) {
-  const int nb = (int)blocks_for(lv.n);
-  hipLaunchKernelGGL(k_fcg_az<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, z, q_prev, p_prev, r,
-                     az, partial, ctl);
+                            double *az, double *partial, KrylovCtl *kc, const SolveCtl *ctl,
+                            int ring) {
+  const int zrun = ring_zrun(lv, ring);
+  const int nb = zrun ? ring_blocks(lv, zrun) : (int)blocks_for(lv.n);
+  if (zrun)
+    hipLaunchKernelGGL(k_fcg_az_ring<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, z, q_prev, p_prev,
+                       r, az, partial, ctl, zrun);
+  else
+    hipLaunchKernelGGL(k_fcg_az<T>, dim3(nb), dim3(BLOCK), 0, s, lv, mask, z, q_prev, p_prev, r,
+                       az, partial, ctl);
   hipLaunchKernelGGL(k_fcg_coef, dim3(1), dim3(FINAL), 0, s, partial, nb, kc, ctl);
   return hipGetLastError();
 }
@@ -1015,7 +1299,18 @@ hipError_t launch_mg_smooth(hipStream_t s, const MgLevel &lv, double omega, int 
 template <class T>
 hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double hs,
                          const uint32_t *mask, const T *rhs, const T *x_in, T *x_out,
-                         const SolveCtl *ctl, double *phi_add) {
+                         const SolveCtl *ctl, double *phi_add, int ring) {
+  const int zrun = ring_zrun(lv, ring);
+  if (zrun) {
+    const int nb = ring_blocks(lv, zrun);
+    if (phi_add)
+      hipLaunchKernelGGL((k_jacobi_ring<T, true>), dim3(nb), dim3(BLOCK), 0, s, lv, T(omega),
+                         T(hs), mask, rhs, x_in, x_out, ctl, phi_add, zrun);
+    else
+      hipLaunchKernelGGL((k_jacobi_ring<T, false>), dim3(nb), dim3(BLOCK), 0, s, lv, T(omega),
+                         T(hs), mask, rhs, x_in, x_out, ctl, phi_add, zrun);
+    return hipGetLastError();
+  }
   if (phi_add)
     hipLaunchKernelGGL((k_jacobi<T, true>), dim3(blocks_for(lv.n)), dim3(BLOCK), 0, s, lv,
                        T(omega), T(hs), mask, rhs, x_in, x_out, ctl, phi_add);
@@ -1092,11 +1387,11 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
   template hipError_t launch_mg_outer_resid<T>(hipStream_t, const MgLevel &, const uint32_t *,  \
                                                const double *, const double *, T *, T *,       \
                                                double *, SolveCtl *, int, double *,            \
-                                               KrylovCtl *, double);                           \
+                                               KrylovCtl *, double, int);                     \
   template hipError_t launch_fcg_apply<T>(hipStream_t, const MgLevel &, const uint32_t *,      \
                                           const T *, const double *, const double *,            \
                                           const double *, double *, double *, KrylovCtl *,      \
-                                          const SolveCtl *);                                    \
+                                          const SolveCtl *, int);                               \
   template hipError_t launch_fcg_update<T>(hipStream_t, int, const uint32_t *, const T *,       \
                                            const double *, double *, double *, double *,        \
                                            double *, T *, T *, double *, const KrylovCtl *,     \
@@ -1105,7 +1400,7 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                           const uint32_t *, const T *, T *, const SolveCtl *);  \
   template hipError_t launch_jacobi<T>(hipStream_t, const MgLevel &, double, double,             \
                                          const uint32_t *, const T *, const T *, T *,           \
-                                         const SolveCtl *, double *);                           \
+                                         const SolveCtl *, double *, int);                      \
   template hipError_t launch_mg_restrict<T>(hipStream_t, const MgTransfer &, const uint32_t *,  \
                                             const uint32_t *, const T *, const T *, T *, T *,   \
                                             const SolveCtl *, bool, double, double);            \

@@ -341,6 +341,51 @@ def test_die_contiguous_block_order_same_results(solver, precision, monkeypatch)
     assert np.array_equal(qa, qb) and ia == ib
 
 
+@pytest.mark.parametrize("solver", ["mg", "mg+krylov"])
+@pytest.mark.parametrize("precision", [lbe.FP32_MIXED, lbe.FP64])
+@pytest.mark.parametrize("shape,zrun", [((64, 64, 34), 16), ((128, 8, 22), 5)])
+def test_plane_ring_stencils_same_results(solver, precision, shape, zrun, monkeypatch):
+    """On a level whose nx is a multiple of 64 and ny of 4, the residual
+    check, the Jacobi sweeps and the Krylov operator can stage their
+    gathered array in LDS planes (a tile marching along z through a run of
+    planes; on their own they do so on levels large enough to fill the
+    part, so here the run length is forced, with z extents that leave a
+    ragged last run, and on 128 x 8 x 22 the level below fits too).  A cell
+    sees the values the global gathers load, so with plain cycles a run with
+    the rings and one without (LBE_NO_RINGS=1) agree bit for bit.  The
+    Krylov sums then add a block's cells plane by plane, another order: the
+    two runs take the same number of cycles and agree to rounding."""
+    nx, ny, nz = shape
+    rs = W.salt_for_debye(4.0, G.LB)
+    if solver == "mg":
+        _, t, ps = W.slab(nx, ny, nz - 2, 1, 0.05, -0.05)
+        flags = lbe.EXTRAPOLATE
+    else:
+        t, ps = G.random_geometry(shape, 3, seed=37, fill=0.1)
+        flags = lbe.EXTRAPOLATE | lbe.ALLOW_FLOATING | lbe.KRYLOV
+    n0 = W.noisy_concentrations(t, [rs, rs], 1e-2, seed=6)
+    p = dict(z=(1, -1), D=(0.05, 0.08), lB=G.LB, tau=0.9, Eapp=(1e-3, 0.0, 5e-4), tol=1e-11,
+             max_iter=1000, precision=precision, poisson=lbe.MG, flags=flags)
+    out = []
+    monkeypatch.setenv("LBE_RING_ZRUN", str(zrun))
+    for off in ("0", "1"):
+        monkeypatch.setenv("LBE_NO_RINGS", off)
+        g = lbe.Lbe(lbe.make_params(shape, **p), t, ps, n0, (rs, rs))
+        g.step(8)
+        out.append((g.fields(), g.qhist(), g.totals()["poisson_total"]))
+        g.close()
+    (fa, qa, ia), (fb, qb, ib) = out
+    print(shape, solver, precision, "cycles", ia, ib)
+    if solver == "mg":
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), k
+        assert np.array_equal(qa, qb) and ia == ib
+    else:
+        assert ia == ib
+        assert rel(fa["phi"], fb["phi"], 0.1) <= 1e-9
+        assert np.abs(qa - qb).max() <= 1e-9 * np.abs(qb).max()
+
+
 @pytest.mark.parametrize("shape", [(64, 8, 24), (128, 12, 40)])
 def test_tiled_ion_pass_same_bits(monkeypatch, shape):
     """The mixed form's pass B on LDS-staged tiles (64 x 4 nodes marching
