@@ -1070,7 +1070,8 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
                      (int)(l + 1) != c->mg_small_from && l + 2 < c->mg.size();
   rc = run(c, KK_MG_RESTRICT, L.lv.n, [&] {
     return launch_mg_restrict<T>(c->stream, C.tr, L.mask, C.mask, r, cur, (T *)C.r, (T *)C.e,
-                                 c->ctl, c->tiles, start ? c->mg_jacobi : 0.0, C.lv.h2 / 6.0);
+                                 c->ctl, c->tiles, start ? c->mg_jacobi : 0.0, C.lv.h2 / 6.0,
+                                 c->rings);
   });
   if (rc) return rc;
   T *ce = nullptr;

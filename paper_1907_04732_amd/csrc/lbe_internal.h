@@ -89,28 +89,38 @@ inline MgLevel make_level(int nx, int ny, int nz, uint32_t selfm, double h2, dou
                  1.0 / nx, 1.0 / ((double)nx * ny), xcd};
 }
 
-// The stencil kernels' plane-ring form (LDS-staged TILE_X x TILE_Y tiles,
-// each block marching along z through a run of zrun planes) applies to a
-// level whose nx and ny are multiples of the tile's.  A run takes RING_ZRUN
-// planes, or fewer so that the launch keeps RING_MIN_BLOCKS blocks, but not
-// fewer than RING_MIN_ZRUN (each run reloads two planes around it); below
-// that the level is too small for the form and ring_zrun returns 0.  (On
-// the 192^3 lattice runs of 16, 8, 4 and 2 planes gave the finest-level
-// kernels 1728, 3456, 6912 and 13824 blocks; 8 was the fastest.)
-// A launcher's `ring` is RING_OFF, RING_AUTO (that rule) or a run length
-// forced (> 0, on levels that fit).
+// The multigrid stencil kernels' plane-ring form: LDS-staged tiles of
+// RING_TX x RING_TY cells (a wavefront holds two rows), each block marching
+// along z through a run of zrun planes, on a level whose nx and ny are
+// multiples of the tile's.  A run takes RING_ZRUN planes, or fewer so that
+// the launch keeps RING_MIN_BLOCKS blocks, but not fewer than RING_MIN_ZRUN
+// (each run reloads two planes around it); below that the level is too small
+// for the form and ring_zrun returns 0.  (On the 192^3 lattice runs of 16,
+// 8, 4 and 2 planes gave the finest-level kernels 1728, 3456, 6912 and
+// 13824 blocks; 8 was the fastest.)  A launcher's `ring` is RING_OFF,
+// RING_AUTO (that rule) or a run length forced (> 0, on levels that fit).
+constexpr int RING_TX = 32, RING_TY = 8;
 constexpr int RING_ZRUN = 8, RING_MIN_BLOCKS = 1024, RING_MIN_ZRUN = 4;
 constexpr int RING_OFF = -1, RING_AUTO = 0;
 inline int ring_zrun(const MgLevel &lv, int ring) {  // 0: the gathering kernels
-  if (ring == RING_OFF || lv.nx % TILE_X || lv.ny % TILE_Y) return 0;
+  if (ring == RING_OFF || lv.nx % RING_TX || lv.ny % RING_TY) return 0;
   if (ring > 0) return ring;
-  const long tiles = (long)(lv.nx / TILE_X) * (lv.ny / TILE_Y);
+  const long tiles = (long)(lv.nx / RING_TX) * (lv.ny / RING_TY);
   for (int zr = RING_ZRUN; zr >= RING_MIN_ZRUN; zr /= 2)
     if (tiles * ((lv.nz + zr - 1) / zr) >= RING_MIN_BLOCKS) return zr;
   return 0;
 }
 inline int ring_blocks(const MgLevel &lv, int zrun) {
-  return (lv.nx / TILE_X) * (lv.ny / TILE_Y) * ((lv.nz + zrun - 1) / zrun);
+  return (lv.nx / RING_TX) * (lv.ny / RING_TY) * ((lv.nz + zrun - 1) / zrun);
+}
+// The restriction from a fine level in that form: each coarse cell's
+// children are pairs of neighbours along x, y (within a wavefront) and z
+// (consecutive planes of a run), so the fine level needs even sizes and
+// the run an even length.
+inline int ring_zrun_restrict(const MgLevel &f, int ring) {
+  if (f.nz % 2) return 0;
+  const int zr = ring_zrun(f, ring);
+  return zr + (zr & 1);
 }
 
 // Fine level f -> coarse level c: coarse cell (X, Y, Z) holds the fine cells
@@ -365,7 +375,8 @@ hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double 
 template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
-                              const SolveCtl *ctl, bool tiled, double jac = 0.0, double hs = 0.0);
+                              const SolveCtl *ctl, bool tiled, double jac = 0.0, double hs = 0.0,
+                              int ring = RING_OFF);
 // tiled: k_restrict_tiled where it applies; jac > 0: ec receives the coarse
 // level's first damped Jacobi sweep (relaxation jac, hs = h^2/6) from zero
 // instead of zero

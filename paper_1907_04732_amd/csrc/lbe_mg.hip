@@ -206,42 +206,49 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
 }
 
 // ---- LDS plane rings on wide levels -------------------------------------------
-// Where a level's nx is a multiple of TILE_X and its ny of TILE_Y, the stencil
-// kernels below also come in a form where a block of TILE_X x TILE_Y cells
-// marches along z through a run of zrun planes (ring_zrun).  The planes
-// z - 1, z, z + 1 of the gathered array (with a one-cell halo in x and y,
-// wrapped periodically) sit in a ring of four LDS slots, and the plane z + 2
-// travels in registers while the plane z is computed.  Each value is then
-// read from memory about once per tile instead of once per neighbour: the
-// gathers of the untiled kernels keep the texture units busy long before
-// memory is.  A cell sees the same neighbour values as through gather_lv_g,
-// so its arithmetic is unchanged.
+// Where a level's nx is a multiple of RING_TX and its ny of RING_TY, the
+// stencil kernels below also come in a form where a block of RING_TX x
+// RING_TY cells marches along z through a run of zrun planes (ring_zrun).
+// The planes z - 1, z, z + 1 of the gathered array (with a one-cell halo in
+// x and y, wrapped periodically) sit in a ring of four LDS slots, and the
+// plane z + 2 travels in registers while the plane z is computed.  Each
+// value is then read from memory about once per tile instead of once per
+// neighbour: the gathers of the untiled kernels keep the texture units busy
+// long before memory is.  A cell sees the same neighbour values as through
+// gather_lv_g, so its arithmetic is unchanged.
 
-constexpr int RING_HX = TILE_X + 2, RING_HP = RING_HX * (TILE_Y + 2);
+constexpr int RING_HX = RING_TX + 2, RING_HP = RING_HX * (RING_TY + 2);
 constexpr int RING_PER = (RING_HP + BLOCK - 1) / BLOCK;  // halo cells per thread
-static_assert(TILE_X * TILE_Y == BLOCK, "one cell of a plane per thread");
+static_assert(RING_TX * RING_TY == BLOCK, "one cell of a plane per thread");
+static_assert(2 * RING_TX == WAVE, "a wavefront holds two rows of a tile");
 
 struct RingTile {
-  int x0, y0, z0, zend;  // the tile's corner and its planes [z0, zend)
+  int x0, y0, z0, zend;  // the tile's corner and its planes [z0, zend), all
+                         // before wrapping (an origin offset may push them past
+                         // the level's end)
   int lb;                // logical block: reduction partials keep this order
-  uint32_t rxy;          // this thread's cell within a plane
+  uint32_t rxy;          // this thread's cell within a plane (wrapped)
   int hc;                // and its halo cell in a slot
 };
 
-__device__ __forceinline__ RingTile ring_tile(const MgLevel &lv, int zrun) {
-  const int ntx = lv.nx / TILE_X, nty = lv.ny / TILE_Y;
+// Tiles start at the origin (ox, oy, oz): the stencil kernels take 0, the
+// restriction its transfer's offsets so that a tile holds whole children
+// blocks.
+__device__ __forceinline__ RingTile ring_tile(const MgLevel &lv, int zrun, int ox = 0,
+                                              int oy = 0, int oz = 0) {
+  const int ntx = lv.nx / RING_TX, nty = lv.ny / RING_TY;
   RingTile t;
   // consecutive tiles of a run of planes on one die, so that the halos they
   // share meet in its L2
   int b = xcd_block(blockIdx.x, gridDim.x, 1, ntx * nty, lv.xcd);
   t.lb = b;
-  t.x0 = (b % ntx) * TILE_X;
+  t.x0 = (b % ntx) * RING_TX + ox;
   b /= ntx;
-  t.y0 = (b % nty) * TILE_Y;
-  t.z0 = (b / nty) * zrun;
-  t.zend = min(t.z0 + zrun, lv.nz);
-  const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
-  t.rxy = (uint32_t)((t.x0 + lx) + lv.nx * (t.y0 + ly));
+  t.y0 = (b % nty) * RING_TY + oy;
+  t.z0 = (b / nty) * zrun + oz;
+  t.zend = min(t.z0 + zrun, lv.nz + oz);
+  const int lx = threadIdx.x % RING_TX, ly = threadIdx.x / RING_TX;
+  t.rxy = (uint32_t)(wrapi(t.x0 + lx, lv.nx) + lv.nx * wrapi(t.y0 + ly, lv.ny));
   t.hc = (lx + 1) + RING_HX * (ly + 1);
   return t;
 }
@@ -830,6 +837,76 @@ __global__ __launch_bounds__(BLOCK) void k_restrict_tiled(MgTransfer tr,
   ec[R] = coarse_start<T>(tr.c, m, rv, jac, hs);
 }
 
+// The restriction on a ring of the fine correction.  A tile starts at the
+// transfer's offsets, so the children of a coarse cell are lanes 2k, 2k + 1
+// of a row (dx), the same lanes of the next row, 32 lanes on (dy), and two
+// consecutive planes of a run (dz); their residuals are summed in that
+// order, which is k_restrict's eight-lane tree, so the results are its bits.
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_restrict_ring(MgTransfer tr,
+                                                         const uint32_t *__restrict__ mf,
+                                                         const uint32_t *__restrict__ mc,
+                                                         const T *__restrict__ rf,
+                                                         const T *__restrict__ ef,
+                                                         T *__restrict__ rc, T *__restrict__ ec,
+                                                         const SolveCtl *__restrict__ ctl, T jac,
+                                                         T hs, int zrun) {
+  __shared__ T ring[4][RING_HP];
+  if (ctl->done) return;
+  const MgLevel &lv = tr.f;
+  const RingTile t = ring_tile(lv, zrun, tr.ox, tr.oy, tr.oz);
+  PlaneRing<T> pr;
+  ring_start(lv, t, pr, ring, ef);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int lx = threadIdx.x % RING_TX, ly = threadIdx.x / RING_TX;
+  // the coarse cell of this thread's children pair along x and y
+  const int X = (t.x0 - tr.ox + lx) >> 1, Y = (t.y0 - tr.oy + ly) >> 1;
+  const bool writer = !(lane & 1) && !(lane & RING_TX);
+  uint32_t rn = t.rxy + (uint32_t)lv.nxy * (uint32_t)wrapi(t.z0, lv.nz);
+  uint32_t m_next = ld32(mf, rn);
+  T r_next = ld32(rf, rn);
+  T s_lo = T(0);
+  int c_lo = 0;
+  for (int z = t.z0; z < t.zend; ++z) {
+    const uint32_t m = m_next;
+    const T rr = r_next;
+    ring_advance(lv, t, z, pr, ring, ef);
+    if (z + 1 < t.zend) {
+      rn = t.rxy + (uint32_t)lv.nxy * (uint32_t)wrapi(z + 1, lv.nz);
+      m_next = ld32(mf, rn);
+      r_next = ld32(rf, rn);
+    }
+    __syncthreads();
+    T e[NQ];
+    ring_gather(t, z, ring, e);
+    T v = T(0);
+    int cnt = 0;
+    if (!(m & SOLID_BIT)) {
+      v = rr - apply_A_v<T>(lv, m, e);
+      cnt = 1;
+    }
+    v += __shfl_xor(v, 1);  // dx
+    cnt += __shfl_xor(cnt, 1);
+    v += __shfl_xor(v, RING_TX);  // dy
+    cnt += __shfl_xor(cnt, RING_TX);
+    if (!((z - t.z0) & 1)) {  // dz = 0
+      s_lo = v;
+      c_lo = cnt;
+      continue;
+    }
+    if (writer) {
+      const T sum = s_lo + v;
+      const int cn = c_lo + cnt;
+      const int Z = (z - tr.oz) >> 1;
+      const int R = X + tr.c.nx * (Y + tr.c.ny * Z);
+      const uint32_t mcr = mc[R];
+      const T rv = (!(mcr & SOLID_BIT) && cn) ? sum / T(cn) : T(0);
+      rc[R] = rv;
+      ec[R] = coarse_start<T>(tr.c, mcr, rv, jac, hs);
+    }
+  }
+}
+
 // ---- prolongation: e_f += trilinear interpolation of e_c --------------------
 
 // trilinear interpolation of e_c at fine cell r (mirrored across solid cells)
@@ -1323,7 +1400,13 @@ hipError_t launch_jacobi(hipStream_t s, const MgLevel &lv, double omega, double 
 template <class T>
 hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
                               const uint32_t *mc, const T *rf, const T *ef, T *rc, T *ec,
-                              const SolveCtl *ctl, bool tiled, double jac, double hs) {
+                              const SolveCtl *ctl, bool tiled, double jac, double hs, int ring) {
+  const int zrun = ring_zrun_restrict(tr.f, ring);
+  if (zrun) {
+    hipLaunchKernelGGL(k_restrict_ring<T>, dim3(ring_blocks(tr.f, zrun)), dim3(BLOCK), 0, s, tr,
+                       mf, mc, rf, ef, rc, ec, ctl, T(jac), T(hs), zrun);
+    return hipGetLastError();
+  }
   // the tiled form where a level is wide enough to fill its tiles (and its
   // planes fit the grid's z extent)
   if (tiled && tr.c.nx >= RT_X && tr.c.ny >= RT_Y && tr.c.nz <= 65535) {
@@ -1403,7 +1486,7 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                          const SolveCtl *, double *, int);                      \
   template hipError_t launch_mg_restrict<T>(hipStream_t, const MgTransfer &, const uint32_t *,  \
                                             const uint32_t *, const T *, const T *, T *, T *,   \
-                                            const SolveCtl *, bool, double, double);            \
+                                            const SolveCtl *, bool, double, double, int);       \
   template hipError_t launch_mg_prolong<T>(hipStream_t, const MgTransfer &, const uint32_t *,   \
                                            const uint32_t *, const T *, T *, const SolveCtl *); \
   template hipError_t launch_mg_coarse<T>(hipStream_t, const MgLevel &, double, double, int,    \
