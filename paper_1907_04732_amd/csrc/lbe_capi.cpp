@@ -1077,7 +1077,8 @@ int mg_vcycle(lbe_ctx *c, size_t l, T **out, double *phi_add = nullptr, bool *ad
   T *ce = nullptr;
   if ((rc = mg_vcycle<T>(c, l + 1, &ce, nullptr, nullptr, start))) return rc;
   rc = run(c, KK_MG_PROLONG, L.lv.n, [&] {
-    return launch_mg_prolong<T>(c->stream, C.tr, L.mask, C.mask, (const T *)ce, cur, c->ctl);
+    return launch_mg_prolong<T>(c->stream, C.tr, L.mask, C.mask, (const T *)ce, cur, c->ctl,
+                                c->rings);
   });
   if (rc) return rc;
   if ((rc = smooth(nu2, phi_add))) return rc;

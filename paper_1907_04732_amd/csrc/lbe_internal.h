@@ -382,7 +382,8 @@ hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_
 // instead of zero
 template <class T>
 hipError_t launch_mg_prolong(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
-                             const uint32_t *mc, const T *ec, T *ef, const SolveCtl *ctl);
+                             const uint32_t *mc, const T *ec, T *ef, const SolveCtl *ctl,
+                             int ring = RING_OFF);
 template <class T>
 hipError_t launch_mg_coarse(hipStream_t s, const MgLevel &lv, double omega, double jacobi,
                             int sweeps, const uint32_t *mask, const T *rhs, T *e, T *e2,

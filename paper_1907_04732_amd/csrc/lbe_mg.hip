@@ -976,6 +976,75 @@ __global__ __launch_bounds__(BLOCK) void k_prolong(MgTransfer tr, const uint32_t
   ef[r] = (mf[r] & SOLID_BIT) ? e0 : e0 + pv;
 }
 
+// The prolongation on a fine tile of RING_TX x RING_TY cells and a run of
+// zrun planes (even, at most RING_PROLONG_ZRUN), starting at the transfer's
+// offsets like k_restrict_ring: the coarse cells it interpolates from, a box
+// of (RING_TX / 2 + 2) x (RING_TY / 2 + 2) x (zrun / 2 + 2), are loaded into
+// LDS once, then each fine plane is interpolated from there with
+// prolong_value's arithmetic (same bits).
+constexpr int RING_PROLONG_ZRUN = 16;
+constexpr int PR_CX = RING_TX / 2 + 2, PR_CY = RING_TY / 2 + 2, PR_CP = PR_CX * PR_CY;
+constexpr int PR_CZ = RING_PROLONG_ZRUN / 2 + 2;
+
+template <class T>
+__global__ __launch_bounds__(BLOCK) void k_prolong_ring(MgTransfer tr, const uint32_t *__restrict__ mf,
+                                                        const uint32_t *__restrict__ mc,
+                                                        const T *__restrict__ ec,
+                                                        T *__restrict__ ef,
+                                                        const SolveCtl *__restrict__ ctl,
+                                                        int zrun) {
+  __shared__ T cv[PR_CZ][PR_CP];
+  __shared__ uint32_t cs[PR_CZ][PR_CP];
+  if (ctl->done) return;
+  const MgLevel &f = tr.f, &c = tr.c;
+  const RingTile t = ring_tile(f, zrun, tr.ox, tr.oy, tr.oz);
+  // the coarse box: parents of the tile's cells and one cell around them
+  const int X0 = (t.x0 - tr.ox) / 2 - 1, Y0 = (t.y0 - tr.oy) / 2 - 1, Z0 = (t.z0 - tr.oz) / 2 - 1;
+  const int ncp = (t.zend - t.z0) / 2 + 2;
+  for (int i = threadIdx.x; i < ncp * PR_CP; i += BLOCK) {
+    const int pz = i / PR_CP, rem = i - pz * PR_CP, py = rem / PR_CX, px = rem - py * PR_CX;
+    const int R = wrapi(X0 + px, c.nx) + c.nx * (wrapi(Y0 + py, c.ny) + c.ny * wrapi(Z0 + pz, c.nz));
+    cv[pz][rem] = ec[R];
+    cs[pz][rem] = mc[R] & SOLID_BIT;
+  }
+  const int lx = threadIdx.x % RING_TX, ly = threadIdx.x / RING_TX;
+  // parent and nearer neighbour in the box along x and y
+  const int P0 = (lx >> 1) + 1, N0 = P0 + ((lx & 1) ? 1 : -1);
+  const int P1 = (ly >> 1) + 1, N1 = P1 + ((ly & 1) ? 1 : -1);
+  const T wgt = T(0.75);
+  uint32_t rn = t.rxy + (uint32_t)f.nxy * (uint32_t)wrapi(t.z0, f.nz);
+  T e_next = ld32(ef, rn);
+  uint32_t m_next = ld32(mf, rn);
+  __syncthreads();
+  for (int z = t.z0; z < t.zend; ++z) {
+    const uint32_t r = rn;
+    const T e0 = e_next;
+    const uint32_t m = m_next;
+    if (z + 1 < t.zend) {
+      rn = t.rxy + (uint32_t)f.nxy * (uint32_t)wrapi(z + 1, f.nz);
+      e_next = ld32(ef, rn);
+      m_next = ld32(mf, rn);
+    }
+    const int fz = z - t.z0;
+    const int P2 = (fz >> 1) + 1, N2 = P2 + ((fz & 1) ? 1 : -1);
+    T pv = T(0);
+    if (!cs[P2][P0 + PR_CX * P1]) {
+      const T ev0 = cv[P2][P0 + PR_CX * P1];
+      const T ep = c.wall > 1.5 ? -ev0 : T(0);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const T w = ((k & 1) ? T(1) - wgt : wgt) * ((k & 2) ? T(1) - wgt : wgt) *
+                    ((k & 4) ? T(1) - wgt : wgt);
+        const int i = ((k & 1) ? N0 : P0) + PR_CX * ((k & 2) ? N1 : P1);
+        const int pz = (k & 4) ? N2 : P2;
+        const T val = cs[pz][i] ? ep : cv[pz][i];
+        pv += w * val;
+      }
+    }
+    st32(ef, r, (m & SOLID_BIT) ? e0 : e0 + pv);
+  }
+}
+
 // ---- coarsest level: one work-group, sweeps with barriers ----------------------
 // Jacobi in pairs through e2 (jacobi > 0, the level needs no colouring) or
 // four-colour Gauss-Seidel with relaxation omega.
@@ -1422,7 +1491,14 @@ hipError_t launch_mg_restrict(hipStream_t s, const MgTransfer &tr, const uint32_
 
 template <class T>
 hipError_t launch_mg_prolong(hipStream_t s, const MgTransfer &tr, const uint32_t *mf,
-                             const uint32_t *mc, const T *ec, T *ef, const SolveCtl *ctl) {
+                             const uint32_t *mc, const T *ec, T *ef, const SolveCtl *ctl,
+                             int ring) {
+  const int zrun = ring_zrun_restrict(tr.f, ring);
+  if (zrun && zrun <= RING_PROLONG_ZRUN) {
+    hipLaunchKernelGGL(k_prolong_ring<T>, dim3(ring_blocks(tr.f, zrun)), dim3(BLOCK), 0, s, tr,
+                       mf, mc, ec, ef, ctl, zrun);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_prolong<T>, dim3(blocks_for(tr.f.n)), dim3(BLOCK), 0, s, tr, mf, mc, ec,
                      ef, ctl);
   return hipGetLastError();
@@ -1488,7 +1564,8 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                             const uint32_t *, const T *, const T *, T *, T *,   \
                                             const SolveCtl *, bool, double, double, int);       \
   template hipError_t launch_mg_prolong<T>(hipStream_t, const MgTransfer &, const uint32_t *,   \
-                                           const uint32_t *, const T *, T *, const SolveCtl *); \
+                                           const uint32_t *, const T *, T *, const SolveCtl *,  \
+                                           int);                                                \
   template hipError_t launch_mg_coarse<T>(hipStream_t, const MgLevel &, double, double, int,    \
                                           const uint32_t *, const T *, T *, T *,                \
                                           const SolveCtl *);                                    \
