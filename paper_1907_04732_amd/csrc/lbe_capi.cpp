@@ -1852,6 +1852,8 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
   c->L.ny = p.ny;
   c->L.nz = p.nz;
   c->L.nxy = p.nx * p.ny;
+  c->L.rnx = 1.0 / p.nx;
+  c->L.rnxy = 1.0 / ((double)p.nx * p.ny);
   c->L.n = (int)N;
   c->L.selfm = g.selfm;
   c->L.wall = (p.flags & LBE_NAIVE_DIRICHLET) ? 1.0 : 2.0;

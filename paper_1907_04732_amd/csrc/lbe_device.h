@@ -39,15 +39,25 @@ __device__ __forceinline__ int xcd_block(int b, int nb, int tb, int nxy, int on)
   return ((j / chunk) * NXCD + x) * chunk + j % chunk;
 }
 
+// a / b for 0 <= a < 2^31, 1 <= b, with rb = 1 / b rounded: the product is
+// within a/b * 2^-51 of a / b, so its floor is the quotient or one less,
+// and one step on the remainder makes it exact (cheaper than an integer
+// division by a value known only at run time)
+__device__ __forceinline__ int quot(int a, int b, double rb) {
+  int q = (int)((double)a * rb);
+  if (a - q * b >= b) ++q;
+  return q;
+}
+
 // Periodic neighbour offsets of a site, indexed by c + 1.
 struct Offs {
   int x[3], y[3], z[3];
 };
 
 __device__ __forceinline__ void site_offsets(const Lattice &L, int r, Offs &o) {
-  const int z = r / L.nxy;
+  const int z = quot(r, L.nxy, L.rnxy);
   const int rem = r - z * L.nxy;
-  const int y = rem / L.nx;
+  const int y = quot(rem, L.nx, L.rnx);
   const int x = rem - y * L.nx;
   o.x[0] = x > 0 ? -1 : L.nx - 1;
   o.x[1] = 0;

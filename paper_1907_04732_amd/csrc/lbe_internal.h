@@ -45,6 +45,7 @@ struct Lattice {
   uint32_t selfm;   // bit (i-1) set when link i maps a node onto itself
   double wall;      // factor on a solid-fluid link: 2 (Eq. 15) or 1 (first-order scheme)
   int xcd;          // 1: stencil kernels give each XCD a contiguous run of blocks
+  double rnx, rnxy; // 1 / nx and 1 / nxy: site coordinates by multiplication
 };
 
 // Step passes on LDS-staged tiles: a block of TILE_X x TILE_Y nodes marching
@@ -97,7 +98,9 @@ inline MgLevel make_level(int nx, int ny, int nz, uint32_t selfm, double h2, dou
 // (each run reloads two planes around it); below that the level is too small
 // for the form and ring_zrun returns 0.  (On the 192^3 lattice runs of 16,
 // 8, 4 and 2 planes gave the finest-level kernels 1728, 3456, 6912 and
-// 13824 blocks; 8 was the fastest.)  A launcher's `ring` is RING_OFF,
+// 13824 blocks; 8 was the fastest.  On the 160 x 160 x 64 cell runs of 8
+// planes, 800 blocks, were slower than runs of 4, and the 96^3 level gained
+// nothing from runs of 4 in 864 blocks.)  A launcher's `ring` is RING_OFF,
 // RING_AUTO (that rule) or a run length forced (> 0, on levels that fit).
 constexpr int RING_TX = 32, RING_TY = 8;
 constexpr int RING_ZRUN = 8, RING_MIN_BLOCKS = 1024, RING_MIN_ZRUN = 4;

@@ -33,16 +33,6 @@ struct Coords {
   int x, y, z;
 };
 
-// a / b for 0 <= a < 2^31, 1 <= b, with rb = 1 / b rounded: the product is
-// within a/b * 2^-51 of a / b, so its floor is the quotient or one less,
-// and one step on the remainder makes it exact (cheaper than an integer
-// division by a value known only at run time)
-__device__ __forceinline__ int quot(int a, int b, double rb) {
-  int q = (int)((double)a * rb);
-  if (a - q * b >= b) ++q;
-  return q;
-}
-
 __device__ __forceinline__ Coords coords_of(int r, const MgLevel &lv) {
   Coords c;
   c.z = quot(r, lv.nxy, lv.rnxy);
