@@ -358,16 +358,16 @@ FORMS = {"fp32-mg": ("fp32", "mg"), "fp64-mg": ("fp64", "mg"), "fp64-sor": ("fp6
 # Workloads: builder and multigrid cycle, chosen by timing the cycles on the
 # same GPU from a running state (steps 1000-1200).  The slab's electrodes are
 # represented exactly on every level: V(1,1) everywhere.  The porous
-# electrode's spheres are not: V(1,2) with three Jacobi sweeps each way on
-# the coarse levels, as the preconditioner of flexible CG (plain cycles
-# diverge there).  The coaxial cell: V(1,1) with three sweeps each way on
-# the coarse levels, plain.  The 96-system batch: V(1,1), two sweeps each
-# way on the coarse levels, with Krylov acceleration.
+# electrode's spheres are not: V(1,2) with two Jacobi sweeps before and three
+# after on the coarse levels, as the preconditioner of flexible CG (plain
+# cycles diverge there).  The coaxial cell: V(1,1) with two sweeps each way
+# on the coarse levels, under flexible CG.  The 96-system batch: V(1,1), two
+# sweeps each way on the coarse levels, with Krylov acceleration.
 WORKLOADS = {
     "porous_electrode_192^3": (lambda: W.porous_electrode(noise=True),
-                               dict(krylov=True, nu=(1, 2, 3, 3))),
+                               dict(krylov=True, nu=(1, 2, 2, 3))),
     "eo_slab_64x64x130": (lambda: W.eo_slab(noise=True), dict(nu=(1, 1, 1, 1))),
-    "coaxial_160x160x64": (lambda: W.coaxial(noise=True), dict(nu=(1, 1, 3, 3))),
+    "coaxial_160x160x64": (lambda: W.coaxial(noise=True), dict(krylov=True, nu=(1, 1, 2, 2))),
     "batched_96_slabs_8x8": (lambda: W.batch_slabs(noise=True),
                              dict(krylov=True, nu=(1, 1, 2, 2))),
 }

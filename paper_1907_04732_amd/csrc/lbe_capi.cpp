@@ -1848,19 +1848,12 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     free_ctx(c);
     return fail(nullptr, LBE_EDEVICE, "library is built for gfx950, device is " + arch);
   }
-  c->L.nx = p.nx;
-  c->L.ny = p.ny;
-  c->L.nz = p.nz;
-  c->L.nxy = p.nx * p.ny;
-  c->L.rnx = 1.0 / p.nx;
-  c->L.rnxy = 1.0 / ((double)p.nx * p.ny);
-  c->L.n = (int)N;
-  c->L.selfm = g.selfm;
-  c->L.wall = (p.flags & LBE_NAIVE_DIRICHLET) ? 1.0 : 2.0;
   {
     // stencil kernels give each die a contiguous run of blocks (same results)
     const char *nx = getenv("LBE_NO_XCD_MAP");
-    c->L.xcd = (nx && *nx && *nx != '0') ? 0 : 1;
+    c->L = make_lattice(p.nx, p.ny, p.nz, g.selfm,
+                        (p.flags & LBE_NAIVE_DIRICHLET) ? 1.0 : 2.0,
+                        (nx && *nx && *nx != '0') ? 0 : 1);
   }
   c->P.K = K;
   for (int k = 0; k < K; ++k) {

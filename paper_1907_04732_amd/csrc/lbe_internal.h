@@ -48,6 +48,23 @@ struct Lattice {
   double rnx, rnxy; // 1 / nx and 1 / nxy: site coordinates by multiplication
 };
 
+// Every field of a lattice, the reciprocals included (the kernels take a
+// site's coordinates from them).
+inline Lattice make_lattice(int nx, int ny, int nz, uint32_t selfm, double wall, int xcd) {
+  Lattice L{};
+  L.nx = nx;
+  L.ny = ny;
+  L.nz = nz;
+  L.nxy = nx * ny;
+  L.n = nx * ny * nz;
+  L.selfm = selfm;
+  L.wall = wall;
+  L.xcd = xcd;
+  L.rnx = 1.0 / nx;
+  L.rnxy = 1.0 / ((double)nx * ny);
+  return L;
+}
+
 // Step passes on LDS-staged tiles: a block of TILE_X x TILE_Y nodes marching
 // through TILE_Z planes along z.  TB_TILED as a pass's launch shape selects
 // them (the context's timing picks it where the tiles fit the lattice).

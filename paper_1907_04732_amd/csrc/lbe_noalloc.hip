@@ -168,13 +168,7 @@ extern "C" int lbe_electrode_charge_noalloc(int32_t nx, int32_t ny, int32_t nz, 
   double *part = nullptr;
   hipError_t e = scratch_on(dev, &part);
   if (e != hipSuccess) return report_init_error(LBE_EDEVICE, hipGetErrorString(e));
-  Lattice L{};
-  L.nx = nx;
-  L.ny = ny;
-  L.nz = nz;
-  L.nxy = nx * ny;
-  L.n = nx * ny * nz;
-  L.wall = (flags & LBE_NAIVE_DIRICHLET) ? 1.0 : 2.0;
+  const Lattice L = make_lattice(nx, ny, nz, 0u, (flags & LBE_NAIVE_DIRICHLET) ? 1.0 : 2.0, 0);
   const double q_scale = -6.0 / (4.0 * M_PI * lB);
   const int nb = (int)std::min<long>((L.n + NA_BLOCK - 1) / NA_BLOCK, NA_MAX_BLOCKS);
   hipStream_t s = (hipStream_t)stream;
