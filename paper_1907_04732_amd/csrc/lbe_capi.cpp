@@ -166,6 +166,13 @@ namespace {
 
 thread_local std::string g_init_error;
 
+// An on/off switch from the environment: 1 for a value other than "0", 0
+// for "0", dflt when unset or empty.
+int env_flag(const char *name, int dflt) {
+  const char *v = getenv(name);
+  return v && *v ? (*v != '0' ? 1 : 0) : dflt;
+}
+
 int fail(lbe_ctx *c, int code, const std::string &msg) {
   if (c) c->err = msg;
   else g_init_error = msg;
@@ -1726,19 +1733,30 @@ int autotune_passes(lbe_ctx *c) {
     (void)hipEventDestroy(e0);
     return fail(c, LBE_EDEVICE, "event create failed");
   }
-  // the LDS-tiled pass B (mixed form) is a candidate where its tiles fit
-  // the lattice; LBE_PASS_TILE=0 leaves it out, =1 takes it untimed
-  const char *pt = getenv("LBE_PASS_TILE");
-  const int tile_env = pt && *pt ? (*pt != '0' ? 1 : 0) : -1;
-  const bool tile_ok = c->mixed && tiles_fit(c->L) && tile_env != 0;
+  // The LDS-staged forms of the mixed passes where their tiles fit the
+  // lattice.  Pass B's tiles are a timed candidate.  Pass A's plane rings
+  // pay only where the populations stream from HBM (they overflow the
+  // 256 MB last-level cache): on the 192^3 porous electrode 301 us against
+  // 317 us for the best block size, in a running state, while the trial
+  // launches from the initial state tell the two apart by less than their
+  // noise; on the cache-resident 160 x 160 x 64 and 64 x 64 x 130 lattices
+  // 97 and 43 us against 81 and 27 us.  So pass A takes them there
+  // untimed, and only there.  LBE_PASS_TILE=0 leaves both out, =1 takes
+  // both untimed where they fit (LBE_PASS_TILE_A, LBE_PASS_TILE_B for one
+  // pass).
+  const int both = env_flag("LBE_PASS_TILE", -1);
+  const bool big = (size_t)NQ * c->L.n * sizeof(float) > ((size_t)256 << 20);
+  const int tile_env[2] = {env_flag("LBE_PASS_TILE_A", both >= 0 ? both : (big ? 1 : 0)),
+                           env_flag("LBE_PASS_TILE_B", both)};
+  const bool tile_ok[2] = {c->mixed && rings_fit(c->L) && tile_env[0] != 0,
+                           c->mixed && tiles_fit(c->L) && tile_env[1] != 0};
   int rc = LBE_OK;
   for (int pass = 0; pass < 2 && rc == LBE_OK; ++pass) {
     float best = 1e30f;
     int pick = 256;
     for (int tb : cand_all) {
-      // LDS tiles for pass B only
-      if (tb == TB_TILED && !(pass == 1 && tile_ok)) continue;
-      if (pass == 1 && tile_ok && tile_env == 1 && tb != TB_TILED) continue;
+      if (tb == TB_TILED && !tile_ok[pass]) continue;
+      if (tile_ok[pass] && tile_env[pass] == 1 && tb != TB_TILED) continue;
       float t_min = 1e30f;
       for (int rep = 0; rep < 4 && rc == LBE_OK; ++rep) {
         hipError_t e = hipEventRecord(e0, c->stream);
@@ -2097,10 +2115,6 @@ int init_impl(const lbe_params *params, const uint8_t *type, const double *phi_s
     {
       const bool big = (size_t)NQ * N * (c->mixed ? sizeof(float) : sizeof(double)) >
                        ((size_t)256 << 20);
-      auto env_flag = [](const char *name, int dflt) {
-        const char *v = getenv(name);
-        return v && *v ? (*v != '0' ? 1 : 0) : dflt;
-      };
       const int both = env_flag("LBE_NT", -1);
       c->nt_a = env_flag("LBE_NT_A", both >= 0 ? both : (big ? 1 : 0)) != 0;
       c->nt_b = env_flag("LBE_NT_B", both >= 0 ? both : (big ? 1 : 0)) != 0;

@@ -65,9 +65,10 @@ inline Lattice make_lattice(int nx, int ny, int nz, uint32_t selfm, double wall,
   return L;
 }
 
-// Step passes on LDS-staged tiles: a block of TILE_X x TILE_Y nodes marching
-// through TILE_Z planes along z.  TB_TILED as a pass's launch shape selects
-// them (the context's timing picks it where the tiles fit the lattice).
+// Step passes on LDS-staged tiles, selected by TB_TILED as a pass's launch
+// shape (the context's timing picks it where the tiles fit the lattice):
+// pass B on blocks of TILE_X x TILE_Y nodes marching through TILE_Z planes
+// along z (tiles_fit), pass A on the plane rings below (rings_fit).
 constexpr int TILE_X = 64, TILE_Y = 4, TILE_Z = 16;
 constexpr int TB_TILED = 1;
 inline bool tiles_fit(const Lattice &L) { return L.nx % TILE_X == 0 && L.ny % TILE_Y == 0; }
@@ -130,6 +131,7 @@ inline int ring_zrun(const MgLevel &lv, int ring) {  // 0: the gathering kernels
     if (tiles * ((lv.nz + zr - 1) / zr) >= RING_MIN_BLOCKS) return zr;
   return 0;
 }
+inline bool rings_fit(const Lattice &L) { return L.nx % RING_TX == 0 && L.ny % RING_TY == 0; }
 inline int ring_blocks(const MgLevel &lv, int zrun) {
   return (lv.nx / RING_TX) * (lv.ny / RING_TY) * ((lv.nz + zrun - 1) / zrun);
 }

@@ -264,6 +264,99 @@ __global__ __launch_bounds__(TB) void k_fluid_f32(Lattice L, Phys P,
   for (int k = 0; k < K; ++k) st_stream<NT>(sbase(dnu + k * N), r, dno[k]);
 }
 
+// neighbour values from the LDS rings of a tile: the plane z + c_z in slot
+// (k + c_z) & 3 with k = z - z0 + 1, halo cell hc + c_x + RING_HX c_y
+template <int K>
+struct NbRing {
+  const double (*sp)[RING_HP];
+  const float (*sn)[K][RING_HP];
+  int k, hc;
+  __device__ __forceinline__ int cell(int i) const { return hc + CX[i] + RING_HX * CY[i]; }
+  __device__ __forceinline__ double phi(int i) const { return sp[(k + CZ[i]) & 3][cell(i)]; }
+  __device__ __forceinline__ float nu(int s, int i) const { return sn[(k + CZ[i]) & 3][s][cell(i)]; }
+};
+
+// Pass A on plane rings: a block of RING_TX x RING_TY nodes marches along z
+// through zrun planes with the potential and the deviations of the planes
+// z - 1, z, z + 1 (with the x, y halo) in LDS, the plane z + 2 loading into
+// registers meanwhile.  Only the population pulls remain gathers from
+// memory.  Tiles of a run of planes go to one die in consecutive chunks, so
+// the pulls that cross a tile's edge find the lines its neighbours fetched
+// in that die's L2.  Same arithmetic as k_fluid_f32, hence the same bits.
+template <int K, bool NT>
+__global__ __launch_bounds__(BLOCK) void k_fluid_f32_ring(Lattice L, Phys P,
+                                                         const uint32_t *__restrict__ mask,
+                                                         const double *__restrict__ phi,
+                                                         const float *__restrict__ nu,
+                                                         const float *__restrict__ hin,
+                                                         float *__restrict__ hout,
+                                                         float *__restrict__ u,
+                                                         float *__restrict__ dnu, int zrun) {
+  __shared__ double sp[4][RING_HP];
+  __shared__ float sn[4][K][RING_HP];
+  const int N = L.n;
+  const RingTile t = ring_tile(L, zrun);
+  PlaneRing<double> rp;
+  PlaneRing<float> rn[K];
+  rp.init(L, t);
+#pragma unroll
+  for (int k = 0; k < K; ++k) rn[k].init(L, t);
+  auto fetch = [&](int z) {
+    rp.fetch(L, phi, z);
+#pragma unroll
+    for (int k = 0; k < K; ++k) rn[k].fetch(L, sbase(nu + k * N), z);
+  };
+  auto put = [&](int slot) {
+    rp.put(sp[slot]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) rn[k].put(sn[slot][k]);
+  };
+  // the plane z0 + k sits in slot (k + 1) & 3
+  fetch(t.z0 - 1);
+  put(0);
+  fetch(t.z0);
+  put(1);
+  fetch(t.z0 + 1);
+  uint32_t rn_next = t.rxy + (uint32_t)L.nxy * (uint32_t)t.z0;
+  uint32_t m_next = ld32(mask, rn_next);
+  for (int z = t.z0; z < t.zend; ++z) {
+    const uint32_t r = rn_next;
+    const uint32_t m = m_next;
+    put((z - t.z0 + 2) & 3);  // plane z + 1
+    if (z + 1 < t.zend) {     // in flight during this plane
+      fetch(z + 2);
+      rn_next += (uint32_t)L.nxy;
+      m_next = ld32(mask, rn_next);
+    }
+    // the slot just written held plane z - 2, last read in the previous
+    // step, which every thread has left at this barrier
+    __syncthreads();
+    float hn[NQ], dno[K], ux = 0.f, uy = 0.f, uz = 0.f;
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) hn[i] = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) dno[k] = 0.f;
+    if (!(m & SOLID_BIT)) {
+      Offs o;
+      site_offsets(L, (int)r, o);
+      const int kk = z - t.z0 + 1;
+      const double ph = sp[kk & 3][t.hc];
+      float dv[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) dv[k] = sn[kk & 3][k][t.hc];
+      const NbRing<K> nb{sp, sn, kk, t.hc};
+      fluid_node_f32<K, NT>(L, P, (int)r, m, o, ph, dv, nb, hin, hn, ux, uy, uz, dno);
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) st_stream<NT>(sbase(hout + i * N), r, hn[i]);
+    st_stream<NT>(u, r, ux);
+    st_stream<NT>(sbase(u + N), r, uy);
+    st_stream<NT>(sbase(u + 2 * N), r, uz);
+#pragma unroll
+    for (int k = 0; k < K; ++k) st_stream<NT>(sbase(dnu + k * N), r, dno[k]);
+  }
+}
+
 // Pass B: advective link fluxes J_k = 3 w_i c_i . (n_k u + n_k' u') with the
 // step's velocity; the step's increment t = dnu_k - sum_i J_k (dnu_k from pass
 // A, in nuio) goes onto the pair (nu, lo_in) of nu_k(t): lo + t first (both
@@ -639,6 +732,24 @@ __global__ __launch_bounds__(BLOCK) void k_expand_n_f32(Lattice L, int K, const 
 hipError_t launch_fluid_f32(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                             const double *phi, const float *nu, const float *hin, float *hout,
                             float *u, float *dnu, int tb, bool nt) {
+  if (tb == TB_TILED) {
+    if (!rings_fit(L)) return hipErrorInvalidValue;
+    const int zrun = RING_ZRUN;
+    const unsigned nb = (unsigned)((L.nx / RING_TX) * (L.ny / RING_TY) * ((L.nz + zrun - 1) / zrun));
+#define CALL(KK, NT) \
+  hipLaunchKernelGGL((k_fluid_f32_ring<KK, NT>), dim3(nb), dim3(BLOCK), 0, s, L, P, mask, phi, nu, hin, hout, u, dnu, zrun)
+#define CALL_T(KK) CALL(KK, true)
+#define CALL_F(KK) CALL(KK, false)
+    if (nt) {
+      LBE_DISPATCH_K(P.K, CALL_T)
+    } else {
+      LBE_DISPATCH_K(P.K, CALL_F)
+    }
+#undef CALL_T
+#undef CALL_F
+#undef CALL
+    return hipGetLastError();
+  }
 #define CALL(KK, TB, NT) \
   hipLaunchKernelGGL((k_fluid_f32<KK, TB, NT>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, phi, nu, hin, hout, u, dnu)
   LBE_DISPATCH_K_TB_NT(P.K, tb, nt, CALL)

@@ -42,8 +42,6 @@ __device__ __forceinline__ Coords coords_of(int r, const MgLevel &lv) {
   return c;
 }
 
-__device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
-
 __device__ __forceinline__ int nbr_of(const MgLevel &lv, const Coords &c, int i) {
   return wrapi(c.x + CX[i], lv.nx) + lv.nx * (wrapi(c.y + CY[i], lv.ny) + lv.ny * wrapi(c.z + CZ[i], lv.nz));
 }
@@ -195,122 +193,7 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid(MgLevel lv, const uint32_
   if (threadIdx.x == 0) partial[lb] = a;
 }
 
-// ---- LDS plane rings on wide levels -------------------------------------------
-// Where a level's nx is a multiple of RING_TX and its ny of RING_TY, the
-// stencil kernels below also come in a form where a block of RING_TX x
-// RING_TY cells marches along z through a run of zrun planes (ring_zrun).
-// The planes z - 1, z, z + 1 of the gathered array (with a one-cell halo in
-// x and y, wrapped periodically) sit in a ring of four LDS slots, and the
-// plane z + 2 travels in registers while the plane z is computed.  Each
-// value is then read from memory about once per tile instead of once per
-// neighbour: the gathers of the untiled kernels keep the texture units busy
-// long before memory is.  A cell sees the same neighbour values as through
-// gather_lv_g, so its arithmetic is unchanged.
-
-constexpr int RING_HX = RING_TX + 2, RING_HP = RING_HX * (RING_TY + 2);
-constexpr int RING_PER = (RING_HP + BLOCK - 1) / BLOCK;  // halo cells per thread
-static_assert(RING_TX * RING_TY == BLOCK, "one cell of a plane per thread");
-static_assert(2 * RING_TX == WAVE, "a wavefront holds two rows of a tile");
-
-struct RingTile {
-  int x0, y0, z0, zend;  // the tile's corner and its planes [z0, zend), all
-                         // before wrapping (an origin offset may push them past
-                         // the level's end)
-  int lb;                // logical block: reduction partials keep this order
-  uint32_t rxy;          // this thread's cell within a plane (wrapped)
-  int hc;                // and its halo cell in a slot
-};
-
-// Tiles start at the origin (ox, oy, oz): the stencil kernels take 0, the
-// restriction its transfer's offsets so that a tile holds whole children
-// blocks.
-__device__ __forceinline__ RingTile ring_tile(const MgLevel &lv, int zrun, int ox = 0,
-                                              int oy = 0, int oz = 0) {
-  const int ntx = lv.nx / RING_TX, nty = lv.ny / RING_TY;
-  RingTile t;
-  // consecutive tiles of a run of planes on one die, so that the halos they
-  // share meet in its L2
-  int b = xcd_block(blockIdx.x, gridDim.x, 1, ntx * nty, lv.xcd);
-  t.lb = b;
-  t.x0 = (b % ntx) * RING_TX + ox;
-  b /= ntx;
-  t.y0 = (b % nty) * RING_TY + oy;
-  t.z0 = (b / nty) * zrun + oz;
-  t.zend = min(t.z0 + zrun, lv.nz + oz);
-  const int lx = threadIdx.x % RING_TX, ly = threadIdx.x / RING_TX;
-  t.rxy = (uint32_t)(wrapi(t.x0 + lx, lv.nx) + lv.nx * wrapi(t.y0 + ly, lv.ny));
-  t.hc = (lx + 1) + RING_HX * (ly + 1);
-  return t;
-}
-
-// This thread's share of a plane's halo cells: loaded into registers by
-// fetch, stored into a slot by put.
-template <class T>
-struct PlaneRing {
-  uint32_t gxy[RING_PER];  // offset of the cell within a plane
-  int cidx[RING_PER];      // its index in a slot, -1 for none
-  T reg[RING_PER];
-
-  __device__ __forceinline__ void init(const MgLevel &lv, const RingTile &t) {
-#pragma unroll
-    for (int j = 0; j < RING_PER; ++j) {
-      const int c = threadIdx.x + j * BLOCK;
-      cidx[j] = c < RING_HP ? c : -1;
-      const int cc = c < RING_HP ? c : 0;
-      const int hy = cc / RING_HX, hx = cc - hy * RING_HX;
-      const int gx = wrapi(t.x0 + hx - 1, lv.nx), gy = wrapi(t.y0 + hy - 1, lv.ny);
-      gxy[j] = (uint32_t)(gx + lv.nx * gy);
-    }
-  }
-  // plane z, wrapped periodically
-  __device__ __forceinline__ void fetch(const MgLevel &lv, const T *__restrict__ a, int z) {
-    const int zz = wrapi(z, lv.nz);
-#pragma unroll
-    for (int j = 0; j < RING_PER; ++j)
-      if (cidx[j] >= 0) reg[j] = ld32(a, gxy[j] + (uint32_t)lv.nxy * (uint32_t)zz);
-  }
-  __device__ __forceinline__ void put(T *slot) const {
-#pragma unroll
-    for (int j = 0; j < RING_PER; ++j)
-      if (cidx[j] >= 0) slot[cidx[j]] = reg[j];
-  }
-};
-
-// The slots start as planes z0 - 1 and z0, with z0 + 1 in registers; the
-// plane z0 + k then sits in slot (k + 1) & 3.
-template <class T>
-__device__ __forceinline__ void ring_start(const MgLevel &lv, const RingTile &t,
-                                           PlaneRing<T> &pr, T (*ring)[RING_HP],
-                                           const T *__restrict__ a) {
-  pr.init(lv, t);
-  pr.fetch(lv, a, t.z0 - 1);
-  pr.put(ring[0]);
-  pr.fetch(lv, a, t.z0);
-  pr.put(ring[1]);
-  pr.fetch(lv, a, t.z0 + 1);
-}
-
-// At plane z: store plane z + 1 into its slot and start loading z + 2.
-// The slot written held plane z - 2, read in the previous step, which every
-// thread has left at the barrier the caller passes next; so one barrier per
-// plane suffices.
-template <class T>
-__device__ __forceinline__ void ring_advance(const MgLevel &lv, const RingTile &t, int z,
-                                             PlaneRing<T> &pr, T (*ring)[RING_HP],
-                                             const T *__restrict__ a) {
-  pr.put(ring[(z - t.z0 + 2) & 3]);
-  if (z + 1 < t.zend) pr.fetch(lv, a, z + 2);
-}
-
-// v[i] = the value at the neighbour c + c_i of this thread's cell in plane z
-template <class T>
-__device__ __forceinline__ void ring_gather(const RingTile &t, int z, const T (*ring)[RING_HP],
-                                            T (&v)[NQ]) {
-  const int k = z - t.z0 + 1;
-  v[0] = ring[k & 3][t.hc];
-#pragma unroll
-  for (int i = 1; i < NQ; ++i) v[i] = ring[(k + CZ[i]) & 3][t.hc + CX[i] + RING_HX * CY[i]];
-}
+// ---- the stencil kernels on plane rings (see lbe_device.h) ---------------------
 
 // The residual check of k_outer_resid on a ring of phi.  The maximum over a
 // block's cells does not depend on which cells a block takes.

@@ -386,15 +386,20 @@ def test_plane_ring_stencils_same_results(solver, precision, shape, zrun, monkey
         assert np.abs(qa - qb).max() <= 1e-9 * np.abs(qb).max()
 
 
-@pytest.mark.parametrize("shape", [(64, 8, 24), (128, 12, 40)])
-def test_tiled_ion_pass_same_bits(monkeypatch, shape):
-    """The mixed form's pass B on LDS-staged tiles (64 x 4 nodes marching
-    through 16 planes, three planes of velocity and deviations in LDS with a
-    periodic halo) does the arithmetic of the per-node kernel on the same
-    values, so a run forced onto it (LBE_PASS_TILE=1) and one kept off it
-    (LBE_PASS_TILE=0) must agree bit for bit: random electrodes, an applied
-    field, two species of unequal D, the quadratic warm start; the second
-    lattice has a last chunk of 8 planes and two tiles across x."""
+@pytest.mark.parametrize("shape", [(64, 8, 24), (128, 12, 40), (96, 16, 20)])
+def test_tiled_step_passes_same_bits(monkeypatch, shape):
+    """The mixed form's step passes on LDS-staged tiles do the arithmetic of
+    the per-node kernels on the same values: pass B on tiles of 64 x 4 nodes
+    marching through 16 planes (velocity and deviations of three planes in
+    LDS with a periodic halo), pass A on plane rings of 32 x 8 nodes marching
+    through 8 planes (potential and deviations).  So a run forced onto them
+    where they fit (LBE_PASS_TILE=1) and one kept off them (LBE_PASS_TILE=0)
+    must agree bit for bit: random electrodes, an applied field, two species
+    of unequal D, the quadratic warm start.  64 x 8 x 24 takes both, 128 x 12
+    x 40 pass B's tiles only (with a last chunk of 8 planes and two tiles
+    across x), 96 x 16 x 20 pass A's rings only (a last run of 4 planes)."""
+    fit_a = shape[0] % 32 == 0 and shape[1] % 8 == 0
+    fit_b = shape[0] % 64 == 0 and shape[1] % 4 == 0
     t, ps = G.random_geometry(shape, 3, seed=7, fill=0.1)
     rs = W.salt_for_debye(4.0, G.LB)
     n0 = W.noisy_concentrations(t, [rs, rs], 1e-2, seed=5)
@@ -405,7 +410,8 @@ def test_tiled_ion_pass_same_bits(monkeypatch, shape):
     for tile in ("1", "0"):
         monkeypatch.setenv("LBE_PASS_TILE", tile)
         g = lbe.Lbe(p, t, ps, n0, (rs, rs))
-        assert (g.pass_blocks()[1] == 1) == (tile == "1") and g.pass_blocks()[0] != 1
+        blk_a, blk_b, _ = g.pass_blocks()
+        assert (blk_a == 1) == (tile == "1" and fit_a) and (blk_b == 1) == (tile == "1" and fit_b)
         g.step(8)
         out.append((g.fields(), g.qhist(), g.totals()))
         g.close()
