@@ -335,18 +335,26 @@ __device__ double final_sum(const double *__restrict__ partial, int nb, double *
   return v;
 }
 
-// NaN-propagating max of partial[0..nb) (>= 0 values); valid in every thread
+// NaN-propagating max of partial[0..nb) (>= 0 values); valid in every thread.
+// The maximum does not depend on the order, so a thread keeps eight loads in
+// flight at a time (tens of thousands of partials take few round trips).
 __device__ double final_max(const double *__restrict__ partial, int nb, double *tree) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  constexpr int U = 8;
+  double a[U];
+#pragma unroll
+  for (int j = 0; j < U; ++j) a[j] = 0.0;
   int b = threadIdx.x;
-  for (; b + 3 * FINAL < nb; b += 4 * FINAL) {
-    a0 = nanmax(a0, partial[b]);
-    a1 = nanmax(a1, partial[b + FINAL]);
-    a2 = nanmax(a2, partial[b + 2 * FINAL]);
-    a3 = nanmax(a3, partial[b + 3 * FINAL]);
+  for (; b + (U - 1) * FINAL < nb; b += U * FINAL) {
+    double v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) v[j] = partial[b + j * FINAL];
+#pragma unroll
+    for (int j = 0; j < U; ++j) a[j] = nanmax(a[j], v[j]);
   }
-  for (; b < nb; b += FINAL) a0 = nanmax(a0, partial[b]);
-  tree[threadIdx.x] = nanmax(nanmax(a0, a1), nanmax(a2, a3));
+  for (; b < nb; b += FINAL) a[0] = nanmax(a[0], partial[b]);
+#pragma unroll
+  for (int j = 1; j < U; ++j) a[0] = nanmax(a[0], a[j]);
+  tree[threadIdx.x] = a[0];
   __syncthreads();
   for (int s = FINAL / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) tree[threadIdx.x] = nanmax(tree[threadIdx.x], tree[threadIdx.x + s]);

@@ -329,13 +329,19 @@ __global__ __launch_bounds__(BLOCK) void k_charge(Lattice L, double q_scale,
     const uint32_t m = mask[r];
     Offs o;
     site_offsets(L, r, o);
+    // only the fluid neighbours' potentials: an interface site has few, and
+    // the sites of a wavefront lie scattered over the electrode's surface,
+    // so each load touches its own cache lines
+    const double p0 = ld32(phi, (uint32_t)r);
     double pn[NQ];
-    gather(o, r, phi, pn);
+#pragma unroll
+    for (int i = 1; i < NQ; ++i)
+      if (!solid_link(m, i)) pn[i] = ld32(phi, (uint32_t)nbr(o, r, i));
     double lap = 0.0;
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
       if (solid_link(m, i)) continue;
-      lap += WQ[i] * L.wall * (pn[i] - pn[0]);
+      lap += WQ[i] * L.wall * (pn[i] - p0);
     }
     v = q_scale * lap;
   }
