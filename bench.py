@@ -497,6 +497,8 @@ def _grid(row):
         return g
 
 
+RING_ZRUN = 8  # planes per tile run of the plane-ring kernels (the library's default)
+
 # (pattern in the kernel name, bench kind); a one-block second stage joins
 # the kind of the launch before it
 KIND_OF = [("k_fluid_", "fluid"), ("k_ions_", "ions"), ("k_outer_resid", "mg_resid"),
@@ -539,7 +541,10 @@ def _classify(name, grid, nsites, prev_form=None):
     for pat, kind in KIND_OF:
         if pat in base:
             if kind == "jacobi":
-                if grid < nsites:
+                # a plane-ring launch has one work-item per cell of a plane
+                # of each tile's run of RING_ZRUN planes
+                cells = grid * RING_ZRUN if "_ring" in base else grid
+                if cells < nsites:
                     kind = "mg_smooth"
                 else:
                     kind = "mg_smooth0_phi" if "true" in base else "mg_smooth0"

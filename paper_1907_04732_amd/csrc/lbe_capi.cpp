@@ -71,7 +71,9 @@ struct lbe_ctx {
 
   // electrode charge tables
   int *iface = nullptr, *blk_elec = nullptr, *blk_begin = nullptr, *blk_end = nullptr;
-  // flexible-CG state (LBE_KRYLOV): residual, direction, A direction (FP64)
+  // flexible-CG state (LBE_KRYLOV): residual (FP64), direction and its image
+  // (in the correction's precision: FP32 in the mixed form, in buffers sized
+  // for FP64)
   double *kr = nullptr, *kp = nullptr, *kq = nullptr;
   double *kaz = nullptr;  // A z of the current iteration
   KrylovCtl *kc = nullptr;
@@ -1118,15 +1120,17 @@ int mg_solve(lbe_ctx *c, bool learn) {
             int rc = mg_vcycle<T>(c, 0, &z, nullptr, nullptr, first_sweep > 0.0);
             if (rc) return rc;
             rc = run(c, KK_FCG_APPLY, n, [&] {
-              return launch_fcg_apply<T>(c->stream, L0.lv, c->mask, (const T *)z, c->kq, c->kp,
+              return launch_fcg_apply<T>(c->stream, L0.lv, c->mask, (const T *)z,
+                                         (const T *)c->kq, (const T *)c->kp,
                                          c->kr, c->kaz, c->partial, c->kc, c->ctl, c->rings);
             });
             if (rc) return rc;
             // every iteration ends with its own stop check (one cycle each)
             rc = run(c, KK_FCG_UPDATE, n, [&] {
-              return launch_fcg_update<T>(c->stream, n, c->mask, (const T *)z, c->kaz, c->kp,
-                                          c->kq, c->phi, c->kr, (T *)L0.r, (T *)L0.e, c->partial,
-                                          c->kc, c->ctl, 1, L0.lv, first_sweep);
+              return launch_fcg_update<T>(c->stream, n, c->mask, (const T *)z, c->kaz,
+                                          (T *)c->kp, (T *)c->kq, c->phi, c->kr, (T *)L0.r,
+                                          (T *)L0.e, c->partial, c->kc, c->ctl, 1, L0.lv,
+                                          first_sweep);
             });
             if (rc) return rc;
           }

@@ -369,18 +369,20 @@ hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_
 //   beta = -(z, q_prev) / (p_prev, q_prev) (0 for the first direction),
 //   p = z + beta p,  q = A p,  alpha = (r, p) / (p, q),
 //   phi += alpha p,  r -= alpha q  (r also copied to r0 in T, e0 zeroed),
-// then the stop check on ||r||_inf.  Two passes: launch_fcg_apply forms A z
+// then the stop check on ||r||_inf.  The directions p, q are held in T (the
+// correction's precision; phi and r stay FP64 and move along the stored
+// vectors).  Two passes: launch_fcg_apply forms A z
 // (into az) and the sums from which beta, (p, q) = (z, A z) + 2 beta (z, q') +
 // beta^2 (p', q') and (r, p) = (r, z) + beta (r, p') follow; launch_fcg_update
 // writes p = z + beta p', q = A z + beta q', updates phi and r and checks.
 template <class T>
 hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *mask, const T *z,
-                            const double *q_prev, const double *p_prev, const double *r,
+                            const T *q_prev, const T *p_prev, const double *r,
                             double *az, double *partial, KrylovCtl *kc, const SolveCtl *ctl,
                             int ring);
 template <class T>
 hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const T *z,
-                             const double *az, double *p, double *q, double *phi, double *r,
+                             const double *az, T *p, T *q, double *phi, double *r,
                              T *r0, T *e0, double *partial, const KrylovCtl *kc, SolveCtl *ctl,
                              int add, const MgLevel &lv,
                              double jac);  // jac > 0: e0 gets lv's first Jacobi sweep

@@ -269,8 +269,8 @@ __global__ __launch_bounds__(BLOCK) void k_outer_resid_ring(
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_fcg_az(MgLevel lv, const uint32_t *__restrict__ mask,
                                                   const T *__restrict__ z,
-                                                  const double *__restrict__ q_prev,
-                                                  const double *__restrict__ p_prev,
+                                                  const T *__restrict__ q_prev,
+                                                  const T *__restrict__ p_prev,
                                                   const double *__restrict__ rv,
                                                   double *__restrict__ az,
                                                   double *__restrict__ partial,
@@ -292,10 +292,10 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_az(MgLevel lv, const uint32_t *__
       for (int i = 0; i < NQ; ++i) vd[i] = double(v[i]);
       a = apply_A_v<double>(lv, m, vd);
       const double rr = rv[r];
-      zq = vd[0] * q_prev[r];
+      zq = vd[0] * double(q_prev[r]);
       zaz = vd[0] * a;
       rz = rr * vd[0];
-      rp = rr * p_prev[r];
+      rp = rr * double(p_prev[r]);
     }
     az[r] = a;
   }
@@ -316,8 +316,8 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_az(MgLevel lv, const uint32_t *__
 template <class T>
 __global__ __launch_bounds__(BLOCK) void k_fcg_az_ring(MgLevel lv, const uint32_t *__restrict__ mask,
                                                        const T *__restrict__ z,
-                                                       const double *__restrict__ q_prev,
-                                                       const double *__restrict__ p_prev,
+                                                       const T *__restrict__ q_prev,
+                                                       const T *__restrict__ p_prev,
                                                        const double *__restrict__ rv,
                                                        double *__restrict__ az,
                                                        double *__restrict__ partial,
@@ -331,7 +331,8 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_az_ring(MgLevel lv, const uint32_
   ring_start(lv, t, pr, ring, z);
   uint32_t rn = t.rxy + (uint32_t)lv.nxy * (uint32_t)t.z0;
   uint32_t m_next = ld32(mask, rn);
-  double q_next = ld32(q_prev, rn), p_next = ld32(p_prev, rn), r_next = ld32(rv, rn);
+  double q_next = double(ld32(q_prev, rn)), p_next = double(ld32(p_prev, rn));
+  double r_next = ld32(rv, rn);
   double zq = 0.0, zaz = 0.0, rz = 0.0, rp = 0.0;
   for (int zp = t.z0; zp < t.zend; ++zp) {
     const int r = (int)rn;
@@ -341,8 +342,8 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_az_ring(MgLevel lv, const uint32_
     if (zp + 1 < t.zend) {
       rn += (uint32_t)lv.nxy;
       m_next = ld32(mask, rn);
-      q_next = ld32(q_prev, rn);
-      p_next = ld32(p_prev, rn);
+      q_next = double(ld32(q_prev, rn));
+      p_next = double(ld32(p_prev, rn));
       r_next = ld32(rv, rn);
     }
     __syncthreads();
@@ -413,8 +414,8 @@ template <class T>
 __global__ __launch_bounds__(BLOCK) void k_fcg_update(int n, const uint32_t *__restrict__ mask,
                                                       const T *z,
                                                       const double *__restrict__ az,
-                                                      double *__restrict__ p,
-                                                      double *__restrict__ q,
+                                                      T *__restrict__ p,
+                                                      T *__restrict__ q,
                                                       double *__restrict__ phi,
                                                       double *__restrict__ rv,
                                                       T *__restrict__ r0, T *e0,
@@ -435,10 +436,13 @@ __global__ __launch_bounds__(BLOCK) void k_fcg_update(int n, const uint32_t *__r
     const bool solid = m & SOLID_BIT;
     const double beta = kc->beta, alpha = kc->alpha;
     const double zr = solid ? 0.0 : double(z[r]);
-    const double pr = solid ? 0.0 : (beta == 0.0 ? zr : zr + beta * p[r]);
-    const double qr = solid ? 0.0 : (beta == 0.0 ? az[r] : az[r] + beta * q[r]);
-    p[r] = pr;
-    q[r] = qr;
+    // the directions are stored in the correction's precision, and phi and r
+    // move along the stored vectors
+    const T pt = T(solid ? 0.0 : (beta == 0.0 ? zr : zr + beta * double(p[r])));
+    const T qt = T(solid ? 0.0 : (beta == 0.0 ? az[r] : az[r] + beta * double(q[r])));
+    p[r] = pt;
+    q[r] = qt;
+    const double pr = double(pt), qr = double(qt);
     const double ph = phi[r];
     phi[r] = solid ? ph : ph + alpha * pr;
     R = solid ? 0.0 : rv[r] - alpha * qr;
@@ -1279,7 +1283,7 @@ hipError_t launch_mg_outer_resid(hipStream_t s, const MgLevel &lv, const uint32_
 
 template <class T>
 hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *mask, const T *z,
-                            const double *q_prev, const double *p_prev, const double *r,
+                            const T *q_prev, const T *p_prev, const double *r,
                             double *az, double *partial, KrylovCtl *kc, const SolveCtl *ctl,
                             int ring) {
   const int zrun = ring_zrun(lv, ring);
@@ -1296,7 +1300,7 @@ hipError_t launch_fcg_apply(hipStream_t s, const MgLevel &lv, const uint32_t *ma
 
 template <class T>
 hipError_t launch_fcg_update(hipStream_t s, int n, const uint32_t *mask, const T *z,
-                             const double *az, double *p, double *q, double *phi, double *r,
+                             const double *az, T *p, T *q, double *phi, double *r,
                              T *r0, T *e0, double *partial, const KrylovCtl *kc, SolveCtl *ctl,
                              int add, const MgLevel &lv, double jac) {
   const int nb = (int)blocks_for(n);
@@ -1421,11 +1425,11 @@ hipError_t launch_mg_correct(hipStream_t s, int n, const uint32_t *mask, const T
                                                double *, SolveCtl *, int, double *,            \
                                                KrylovCtl *, double, int);                     \
   template hipError_t launch_fcg_apply<T>(hipStream_t, const MgLevel &, const uint32_t *,      \
-                                          const T *, const double *, const double *,            \
+                                          const T *, const T *, const T *,                      \
                                           const double *, double *, double *, KrylovCtl *,      \
                                           const SolveCtl *, int);                               \
   template hipError_t launch_fcg_update<T>(hipStream_t, int, const uint32_t *, const T *,       \
-                                           const double *, double *, double *, double *,        \
+                                           const double *, T *, T *, double *,                  \
                                            double *, T *, T *, double *, const KrylovCtl *,     \
                                            SolveCtl *, int, const MgLevel &, double);           \
   template hipError_t launch_mg_smooth<T>(hipStream_t, const MgLevel &, double, int,            \
