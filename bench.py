@@ -71,7 +71,8 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False, krylov: b
       acceleration.  correct: phi in + out, correction, flag
       word.  Krylov iteration: fcg_apply gathers the V-cycle's output z
       and reads q', p' and r, writing A z; fcg_update reads z, A z, p', q',
-      phi and r and writes p, q, phi, r and the next cycle's rhs and start.
+      phi and r and writes p, q, phi, r and the next cycle's rhs and start
+      (the directions p, q are held in the correction's precision).
       Reverse mode: adj_moments reads the 19 stored populations and writes
       rho and m; adj_fluid reads phi, the K concentrations, rho and m, the 19
       population adjoints and K concentration adjoints of t+1, and writes 19
@@ -104,8 +105,8 @@ def bytes_per_cell(kind: str, form: str, K: int, extrap: bool = False, krylov: b
         # Krylov: A z and four sums (z, q', p', r in; A z out); then p, q,
         # phi, r updated (z, A z, p', q', phi, r in; p, q, phi, r, the
         # correction's rhs and start out)
-        "fcg_apply": cor + 8 + 8 + 8 + 4 + 8,
-        "fcg_update": cor + 8 + 8 + 8 + 16 + 16 + 8 + 8 + 2 * cor + 4,
+        "fcg_apply": 3 * cor + 8 + 4 + 8,
+        "fcg_update": 7 * cor + 8 + 16 + 16 + 4,
         # reverse mode: FP64 adjoint fields, concentrations in the form's storage
         "adj_moments": 19 * pop + 32 + 4,
         "adj_fluid": 8 + K * pop + 32 + 2 * 19 * 8 + 8 * K + 24 + 24 + 4,

@@ -351,8 +351,8 @@ int32_t lbe_num_kernel_kinds(void);
 
 /* Launch shape of the two step passes as the context chose it at init (by
  * timing, or from LBE_PASS_BLOCK / LBE_PASS_TILE): block size of pass A and
- * of pass B (128, 256 or 512; 1 for a pass on LDS-staged tiles marching
- * along z: pass A on 32 x 8 nodes, pass B on 64 x 4), and which passes use
+ * of pass B (128, 256 or 512; 1 for a pass on LDS-staged tiles of 32 x 8
+ * nodes marching along z through runs of 8 planes), and which passes use
  * non-temporal streams (bit 0 pass A, bit 1 pass B).  Any output may be
  * NULL.  Returns LBE_EINVAL for a NULL context. */
 int lbe_launch_shape(const lbe_ctx *ctx, int32_t *block_a, int32_t *block_b, int32_t *nontemporal);

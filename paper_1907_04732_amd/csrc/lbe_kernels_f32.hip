@@ -487,8 +487,10 @@ __global__ __launch_bounds__(TILE_X * TILE_Y) void k_ions_f32_tiled(
   constexpr int NV = 3 + K, PER = (HP + NT_ - 1) / NT_;  // halo cells per thread
   __shared__ float sv[4][NV][HP];  // [slot][u_x, u_y, u_z, nu_0..][halo cell]
   const int N = L.n;
-  int b = blockIdx.x;
   const int ntx = L.nx / TILE_X, nty = L.ny / TILE_Y;
+  // consecutive tiles of a run of planes on one die, so that the halos they
+  // share meet in its L2
+  int b = xcd_block(blockIdx.x, gridDim.x, 1, ntx * nty, L.xcd);
   const int x0 = (b % ntx) * TILE_X;
   b /= ntx;
   const int y0 = (b % nty) * TILE_Y;

@@ -386,20 +386,18 @@ def test_plane_ring_stencils_same_results(solver, precision, shape, zrun, monkey
         assert np.abs(qa - qb).max() <= 1e-9 * np.abs(qb).max()
 
 
-@pytest.mark.parametrize("shape", [(64, 8, 24), (128, 12, 40), (96, 16, 20)])
+@pytest.mark.parametrize("shape", [(64, 8, 24), (128, 16, 36), (96, 12, 20)])
 def test_tiled_step_passes_same_bits(monkeypatch, shape):
-    """The mixed form's step passes on LDS-staged tiles do the arithmetic of
-    the per-node kernels on the same values: pass B on tiles of 64 x 4 nodes
-    marching through 16 planes (velocity and deviations of three planes in
-    LDS with a periodic halo), pass A on plane rings of 32 x 8 nodes marching
-    through 8 planes (potential and deviations).  So a run forced onto them
-    where they fit (LBE_PASS_TILE=1) and one kept off them (LBE_PASS_TILE=0)
-    must agree bit for bit: random electrodes, an applied field, two species
-    of unequal D, the quadratic warm start.  64 x 8 x 24 takes both, 128 x 12
-    x 40 pass B's tiles only (with a last chunk of 8 planes and two tiles
-    across x), 96 x 16 x 20 pass A's rings only (a last run of 4 planes)."""
-    fit_a = shape[0] % 32 == 0 and shape[1] % 8 == 0
-    fit_b = shape[0] % 64 == 0 and shape[1] % 4 == 0
+    """The mixed form's step passes on LDS-staged tiles of 32 x 8 nodes
+    marching through runs of 8 planes do the arithmetic of the per-node
+    kernels on the same values: pass B with the velocity and deviations of
+    three planes in LDS (with a periodic halo), pass A with the potential and
+    deviations.  So a run forced onto them where they fit (LBE_PASS_TILE=1)
+    and one kept off them (LBE_PASS_TILE=0) must agree bit for bit: random
+    electrodes, an applied field, two species of unequal D, the quadratic
+    warm start.  64 x 8 x 24 and 128 x 16 x 36 (four tiles across x, two
+    along y, a last run of 4 planes) take both; 96 x 12 x 20 neither."""
+    fit_a = fit_b = shape[0] % 32 == 0 and shape[1] % 8 == 0
     t, ps = G.random_geometry(shape, 3, seed=7, fill=0.1)
     rs = W.salt_for_debye(4.0, G.LB)
     n0 = W.noisy_concentrations(t, [rs, rs], 1e-2, seed=5)
