@@ -1737,8 +1737,9 @@ int autotune_passes(lbe_ctx *c) {
     (void)hipEventDestroy(e0);
     return fail(c, LBE_EDEVICE, "event create failed");
   }
-  // The LDS-staged forms of the mixed passes where their tiles fit the
-  // lattice.  Pass B's tiles are a timed candidate.  Pass A's plane rings
+  // The LDS-staged forms of the passes where their tiles fit the lattice.
+  // Pass B's tiles are a timed candidate (in the FP64 form for one or two
+  // species, whose values fill 54 KB of LDS).  The mixed pass A's plane rings
   // pay only where the populations stream from HBM (they overflow the
   // 256 MB last-level cache): on the 192^3 porous electrode 301 us against
   // 317 us for the best block size, in a running state, while the trial
@@ -1753,7 +1754,7 @@ int autotune_passes(lbe_ctx *c) {
   const int tile_env[2] = {env_flag("LBE_PASS_TILE_A", both >= 0 ? both : (big ? 1 : 0)),
                            env_flag("LBE_PASS_TILE_B", both)};
   const bool tile_ok[2] = {c->mixed && rings_fit(c->L) && tile_env[0] != 0,
-                           c->mixed && tiles_fit(c->L) && tile_env[1] != 0};
+                           (c->mixed || c->P.K <= 2) && tiles_fit(c->L) && tile_env[1] != 0};
   int rc = LBE_OK;
   for (int pass = 0; pass < 2 && rc == LBE_OK; ++pass) {
     float best = 1e30f;

@@ -169,6 +169,37 @@ __global__ __launch_bounds__(TB) void k_fluid_f64(Lattice L, Phys P,
 // Poisson source.  J_k = 3 w_i c_i . (n_k u + n_k' u') on every fluid link;
 // n_k(t+1) = n*_k - sum_i J_k, updated in place in nio. -------------------
 
+// The advective flux sums at a fluid node, from its velocity and
+// concentrations and its neighbours' (nb.cut(i) = c_i . u(r + c_i),
+// nb.n(k, i) = n_k(r + c_i)): J_k = sum over fluid links of
+// 3 w_i (n_k c_i . u + n_k' c_i . u').
+template <int K, class NB>
+__device__ __forceinline__ void ions_flux_f64(uint32_t m, double ux, double uy, double uz,
+                                              const double (&nr)[K], const NB &nb,
+                                              double (&Js)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) Js[k] = 0.0;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;
+    double cu_h = 0.0;
+    if (CX[i]) cu_h += CX[i] * ux;
+    if (CY[i]) cu_h += CY[i] * uy;
+    if (CZ[i]) cu_h += CZ[i] * uz;
+    const double cu_t = nb.cut(i);
+#pragma unroll
+    for (int k = 0; k < K; ++k) Js[k] += 3.0 * WQ[i] * (nr[k] * cu_h + nb.n(k, i) * cu_t);
+  }
+}
+
+// neighbour values gathered into registers
+template <int K>
+struct IonRegs {
+  double c[NQ], nn[K][NQ];
+  __device__ __forceinline__ double cut(int i) const { return c[i]; }
+  __device__ __forceinline__ double n(int k, int i) const { return nn[k][i]; }
+};
+
 template <int K, int TB, bool NT>
 __global__ __launch_bounds__(TB) void k_ions_f64(Lattice L, Phys P,
                                                     const uint32_t *__restrict__ mask,
@@ -193,13 +224,10 @@ __global__ __launch_bounds__(TB) void k_ions_f64(Lattice L, Phys P,
     const double ux = u[r], uy = u[N + r], uz = u[2 * N + r];
     double nr[K], Js[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      nr[k] = n[k * N + r];
-      Js[k] = 0.0;
-    }
+    for (int k = 0; k < K; ++k) nr[k] = n[k * N + r];
     // c_i . u and the concentrations at every neighbour, loaded before any
     // is used (solid neighbours too, skipped below)
-    double cut[NQ], nn[K][NQ];
+    IonRegs<K> nb;
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
       const uint32_t rn = nbr(o, r, i);
@@ -207,21 +235,11 @@ __global__ __launch_bounds__(TB) void k_ions_f64(Lattice L, Phys P,
       if (CX[i]) c += CX[i] * ld32(u, rn);
       if (CY[i]) c += CY[i] * ld32(sbase(u + N), rn);
       if (CZ[i]) c += CZ[i] * ld32(sbase(u + 2 * N), rn);
-      cut[i] = c;
+      nb.c[i] = c;
 #pragma unroll
-      for (int k = 0; k < K; ++k) nn[k][i] = ld32(sbase(n + k * N), rn);
+      for (int k = 0; k < K; ++k) nb.nn[k][i] = ld32(sbase(n + k * N), rn);
     }
-#pragma unroll
-    for (int i = 1; i < NQ; ++i) {
-      if (solid_link(m, i)) continue;
-      double cu_h = 0.0;
-      if (CX[i]) cu_h += CX[i] * ux;
-      if (CY[i]) cu_h += CY[i] * uy;
-      if (CZ[i]) cu_h += CZ[i] * uz;
-      const double cu_t = cut[i];
-#pragma unroll
-      for (int k = 0; k < K; ++k) Js[k] += 3.0 * WQ[i] * (nr[k] * cu_h + nn[k][i] * cu_t);
-    }
+    ions_flux_f64<K>(m, ux, uy, uz, nr, nb, Js);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       no[k] = nio[k * N + r] - Js[k];
@@ -232,6 +250,115 @@ __global__ __launch_bounds__(TB) void k_ions_f64(Lattice L, Phys P,
   for (int k = 0; k < K; ++k) st_stream<NT>(sbase(nio + k * N), r, no[k]);
   st_stream<NT>(src, r, P.src_scale * q);
   if (prev) extrapolate_at(r, N, order, solid, phi, prev);
+}
+
+// Pass B on LDS-staged tiles of TILE_X x TILE_Y nodes marching through
+// TILE_Z planes, as the mixed form's k_ions_f32_tiled: the velocity and the
+// concentrations of the planes z - 1, z, z + 1 (with the x, y halo) in a
+// ring of four LDS slots, the plane z + 2 and the node's own flag word and
+// n* loading meanwhile, one barrier per plane.  The gathering kernel's
+// arithmetic on the same values, hence the same bits.  Five FP64 values
+// per halo cell fill 54 KB of LDS for two species, so one or two species.
+static_assert(TILE_X == RING_TX && TILE_Y == RING_TY, "pass B tiles are the plane rings' tiles");
+
+// neighbour values from the LDS slots of a tile: the plane z + c_z in slot
+// (k + c_z) & 3 with k = z - z0 + 1, halo cell hc + c_x + RING_HX c_y
+template <int K>
+struct IonLds {
+  const double (*sv)[3 + K][RING_HP];
+  int k, hc;
+  __device__ __forceinline__ int slot(int i) const { return (k + CZ[i]) & 3; }
+  __device__ __forceinline__ int cell(int i) const { return hc + CX[i] + RING_HX * CY[i]; }
+  __device__ __forceinline__ double cut(int i) const {
+    double c = 0.0;
+    if (CX[i]) c += CX[i] * sv[slot(i)][0][cell(i)];
+    if (CY[i]) c += CY[i] * sv[slot(i)][1][cell(i)];
+    if (CZ[i]) c += CZ[i] * sv[slot(i)][2][cell(i)];
+    return c;
+  }
+  __device__ __forceinline__ double n(int s, int i) const { return sv[slot(i)][3 + s][cell(i)]; }
+};
+
+template <int K, bool NT>
+__global__ __launch_bounds__(BLOCK) void k_ions_f64_tiled(Lattice L, Phys P,
+                                                         const uint32_t *__restrict__ mask,
+                                                         const double *__restrict__ u,
+                                                         const double *__restrict__ n,
+                                                         double *__restrict__ nio,
+                                                         double *__restrict__ src, int order,
+                                                         double *__restrict__ phi,
+                                                         double *__restrict__ prev) {
+  static_assert(K >= 1 && K <= 2, "at most two species in LDS");
+  constexpr int NV = 3 + K;
+  __shared__ double sv[4][NV][RING_HP];  // [slot][u_x, u_y, u_z, n_0..][halo cell]
+  const int N = L.n;
+  const RingTile t = ring_tile(L, TILE_Z);
+  PlaneRing<double> rv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) rv[v].init(L, t);
+  auto fetch = [&](int z) {
+    rv[0].fetch(L, u, z);
+    rv[1].fetch(L, sbase(u + N), z);
+    rv[2].fetch(L, sbase(u + 2 * N), z);
+#pragma unroll
+    for (int k = 0; k < K; ++k) rv[3 + k].fetch(L, sbase(n + k * N), z);
+  };
+  auto put = [&](int slot) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) rv[v].put(sv[slot][v]);
+  };
+  // the plane z0 + k sits in slot (k + 1) & 3
+  fetch(t.z0 - 1);
+  put(0);
+  fetch(t.z0);
+  put(1);
+  fetch(t.z0 + 1);
+  uint32_t rn = t.rxy + (uint32_t)L.nxy * (uint32_t)t.z0;
+  uint32_t m_next = ld32(mask, rn);
+  double ns_next[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) ns_next[k] = ld32(sbase((const double *)nio + k * N), rn);
+  for (int z = t.z0; z < t.zend; ++z) {
+    const uint32_t r = rn;
+    const uint32_t m = m_next;
+    double ns[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) ns[k] = ns_next[k];
+    put((z - t.z0 + 2) & 3);  // plane z + 1
+    if (z + 1 < t.zend) {     // in flight during this plane
+      fetch(z + 2);
+      rn += (uint32_t)L.nxy;
+      m_next = ld32(mask, rn);
+#pragma unroll
+      for (int k = 0; k < K; ++k) ns_next[k] = ld32(sbase((const double *)nio + k * N), rn);
+    }
+    // the slot just written held plane z - 2, last read in the previous
+    // step, which every thread has left at this barrier
+    __syncthreads();
+    const bool solid = m & SOLID_BIT;
+    double no[K], q = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) no[k] = 0.0;
+    if (!solid) {
+      const int kk = z - t.z0 + 1, s0 = kk & 3;
+      const double ux = sv[s0][0][t.hc], uy = sv[s0][1][t.hc], uz = sv[s0][2][t.hc];
+      double nr[K], Js[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) nr[k] = sv[s0][3 + k][t.hc];
+      // the neighbours' values read from LDS link by link
+      const IonLds<K> nb{sv, kk, t.hc};
+      ions_flux_f64<K>(m, ux, uy, uz, nr, nb, Js);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        no[k] = ns[k] - Js[k];
+        q += P.z[k] * no[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) st_stream<NT>(sbase(nio + k * N), r, no[k]);
+    st_stream<NT>(src, r, P.src_scale * q);
+    if (prev) extrapolate_at((int)r, N, order, solid, phi, prev);
+  }
 }
 
 // ---- Poisson: one colour of the four-colour SOR sweep (Eqs. 13, 15) --------
@@ -534,6 +661,20 @@ hipError_t launch_fluid_f64(hipStream_t s, const Lattice &L, const Phys &P, cons
 hipError_t launch_ions_f64(hipStream_t s, const Lattice &L, const Phys &P, const uint32_t *mask,
                            const double *u, const double *n, double *nio, double *src, int order,
                            double *phi, double *prev, int tb, bool nt) {
+  if (tb == TB_TILED) {
+    if (!tiles_fit(L) || P.K > 2) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((L.nx / TILE_X) * (L.ny / TILE_Y) *
+                                   ((L.nz + TILE_Z - 1) / TILE_Z));
+#define CALL(KK, NT) \
+  hipLaunchKernelGGL((k_ions_f64_tiled<KK, NT>), dim3(nb), dim3(BLOCK), 0, s, L, P, mask, u, n, nio, src, order, phi, prev)
+    if (P.K == 1) {
+      if (nt) CALL(1, true); else CALL(1, false);
+    } else {
+      if (nt) CALL(2, true); else CALL(2, false);
+    }
+#undef CALL
+    return hipGetLastError();
+  }
 #define CALL(KK, TB, NT) \
   hipLaunchKernelGGL((k_ions_f64<KK, TB, NT>), dim3((L.n + TB - 1) / TB), dim3(TB), 0, s, L, P, mask, u, n, nio, src, order, phi, prev)
   LBE_DISPATCH_K_TB_NT(P.K, tb, nt, CALL)

@@ -386,23 +386,26 @@ def test_plane_ring_stencils_same_results(solver, precision, shape, zrun, monkey
         assert np.abs(qa - qb).max() <= 1e-9 * np.abs(qb).max()
 
 
+@pytest.mark.parametrize("precision", [lbe.FP32_MIXED, lbe.FP64])
 @pytest.mark.parametrize("shape", [(64, 8, 24), (128, 16, 36), (96, 12, 20)])
-def test_tiled_step_passes_same_bits(monkeypatch, shape):
-    """The mixed form's step passes on LDS-staged tiles of 32 x 8 nodes
-    marching through runs of 8 planes do the arithmetic of the per-node
-    kernels on the same values: pass B with the velocity and deviations of
-    three planes in LDS (with a periodic halo), pass A with the potential and
-    deviations.  So a run forced onto them where they fit (LBE_PASS_TILE=1)
-    and one kept off them (LBE_PASS_TILE=0) must agree bit for bit: random
-    electrodes, an applied field, two species of unequal D, the quadratic
-    warm start.  64 x 8 x 24 and 128 x 16 x 36 (four tiles across x, two
-    along y, a last run of 4 planes) take both; 96 x 12 x 20 neither."""
-    fit_a = fit_b = shape[0] % 32 == 0 and shape[1] % 8 == 0
+def test_tiled_step_passes_same_bits(monkeypatch, shape, precision):
+    """The step passes on LDS-staged tiles of 32 x 8 nodes marching through
+    runs of 8 planes do the arithmetic of the per-node kernels on the same
+    values: pass B with the velocity and concentrations (deviations in the
+    mixed form) of three planes in LDS (with a periodic halo), in both
+    forms; pass A with the potential and deviations, in the mixed form.  So
+    a run forced onto them where they fit (LBE_PASS_TILE=1) and one kept off
+    them (LBE_PASS_TILE=0) must agree bit for bit: random electrodes, an
+    applied field, two species of unequal D, the quadratic warm start.
+    64 x 8 x 24 and 128 x 16 x 36 (four tiles across x, two along y, a last
+    run of 4 planes) take them; 96 x 12 x 20 does not."""
+    fit = shape[0] % 32 == 0 and shape[1] % 8 == 0
+    fit_a, fit_b = fit and precision == lbe.FP32_MIXED, fit
     t, ps = G.random_geometry(shape, 3, seed=7, fill=0.1)
     rs = W.salt_for_debye(4.0, G.LB)
     n0 = W.noisy_concentrations(t, [rs, rs], 1e-2, seed=5)
     p = lbe.make_params(shape, (1, -1), (0.05, 0.08), G.LB, tau=0.9, Eapp=(1e-3, 0.0, 5e-4),
-                        tol=1e-11, max_iter=100000, precision=lbe.FP32_MIXED, poisson=lbe.MG,
+                        tol=1e-11, max_iter=100000, precision=precision, poisson=lbe.MG,
                         flags=lbe.EXTRAPOLATE | lbe.ALLOW_FLOATING | lbe.KRYLOV)
     out = []
     for tile in ("1", "0"):
