@@ -1746,11 +1746,13 @@ int autotune_passes(lbe_ctx *c) {
   // launches from the initial state tell the two apart by less than their
   // noise; on the cache-resident 160 x 160 x 64 and 64 x 64 x 130 lattices
   // 97 and 43 us against 81 and 27 us.  So pass A takes them there
-  // untimed, and only there.  LBE_PASS_TILE=0 leaves both out, =1 takes
+  // untimed, and only there.  (The FP64 pass A, bound by its arithmetic,
+  // took 648 us on the rings against 624 us: it has none.)  LBE_PASS_TILE=0 leaves both out, =1 takes
   // both untimed where they fit (LBE_PASS_TILE_A, LBE_PASS_TILE_B for one
   // pass).
   const int both = env_flag("LBE_PASS_TILE", -1);
-  const bool big = (size_t)NQ * c->L.n * sizeof(float) > ((size_t)256 << 20);
+  const bool big = (size_t)NQ * c->L.n * (c->mixed ? sizeof(float) : sizeof(double)) >
+                   ((size_t)256 << 20);
   const int tile_env[2] = {env_flag("LBE_PASS_TILE_A", both >= 0 ? both : (big ? 1 : 0)),
                            env_flag("LBE_PASS_TILE_B", both)};
   const bool tile_ok[2] = {c->mixed && rings_fit(c->L) && tile_env[0] != 0,

@@ -60,6 +60,80 @@ __device__ __forceinline__ void link_force(const Lattice &L, const Phys &P, int 
 // diffusion-migration flux j_k = D_k/A0 (g_k - (n_k' - n_k)/Delta_i).  Writes
 // post-collision f, u, and n*_k = n_k - sum_i j_k (completed by pass B).
 
+// The arithmetic of pass A at a fluid node r, from its own potential ph and
+// concentrations nr and its neighbours' (nb.phi(i), nb.n(k, i) at r + c_i):
+// post-collision populations fn, velocity and n* = n - sum_i j.
+template <int K, bool NT, class NB>
+__device__ __forceinline__ void fluid_node_f64(const Lattice &L, const Phys &P, int r, uint32_t m,
+                                               const Offs &o, double ph, const double (&nr)[K],
+                                               const NB &nb, const double *__restrict__ fin,
+                                               double (&fn)[NQ], double &ux, double &uy,
+                                               double &uz, double (&nso)[K]) {
+  double js[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) js[k] = 0.0;
+  double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+#pragma unroll
+  for (int i = 1; i < NQ; ++i) {
+    if (solid_link(m, i)) continue;  // no flux into an electrode
+    const double dphi = nb.phi(i) - ph - P.Ec[i];
+    double S1, C1;
+    sinh_coshm1(dphi, S1, C1);
+    double g = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double nt = nb.n(k, i);
+      double S, C;
+      valence_sc(P.z[k], dphi, S1, C1, S, C);
+      const double gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * (0.5 / LEN[i]);
+      g += gk;
+      js[k] += P.dk[k] * (gk - (nt - nr[k]) / LEN[i]);
+    }
+    const double c = 3.0 * WQ[i] * LEN[i] * g;
+    if (CX[i]) F0 += CX[i] * c;
+    if (CY[i]) F1 += CY[i] * c;
+    if (CZ[i]) F2 += CZ[i] * c;
+  }
+
+  double f[NQ];
+  pull<NT>(L, r, m, o, fin, f);
+  double rho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    rho += f[i];
+    if (CX[i]) m0 += CX[i] * f[i];
+    if (CY[i]) m1 += CY[i] * f[i];
+    if (CZ[i]) m2 += CZ[i] * f[i];
+  }
+  // Guo forcing: velocity with the half-force shift
+  ux = (m0 + 0.5 * F0) / rho;
+  uy = (m1 + 0.5 * F1) / rho;
+  uz = (m2 + 0.5 * F2) / rho;
+  const double uu = ux * ux + uy * uy + uz * uz;
+  const double itau = 1.0 / P.tau;
+  const double guo = 1.0 - 0.5 * itau;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+    const double feq = WQ[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    const double s = ((3.0 * (CX[i] - ux) + 9.0 * cu * CX[i]) * F0 +
+                      (3.0 * (CY[i] - uy) + 9.0 * cu * CY[i]) * F1 +
+                      (3.0 * (CZ[i] - uz) + 9.0 * cu * CZ[i]) * F2) *
+                     (guo * WQ[i]);
+    fn[i] = f[i] - (f[i] - feq) * itau + s;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) nso[k] = nr[k] - js[k];
+}
+
+// neighbour values gathered into registers
+template <int K>
+struct FluidRegs64 {
+  double p[NQ], nn[K][NQ];
+  __device__ __forceinline__ double phi(int i) const { return p[i]; }
+  __device__ __forceinline__ double n(int k, int i) const { return nn[k][i]; }
+};
+
 template <int K, int TB, bool NT>
 __global__ __launch_bounds__(TB) void k_fluid_f64(Lattice L, Phys P,
                                                      const uint32_t *__restrict__ mask,
@@ -86,75 +160,21 @@ __global__ __launch_bounds__(TB) void k_fluid_f64(Lattice L, Phys P,
     Offs o;
     site_offsets(L, r, o);
     const double ph = phi[r];
-    double nr[K], js[K];
+    double nr[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      nr[k] = n[k * N + r];
-      js[k] = 0.0;
-    }
+    for (int k = 0; k < K; ++k) nr[k] = n[k * N + r];
     // every neighbour's potential and concentrations first, solid
-    // neighbours too (their links are skipped below): all 18 (1 + K) gathers
-    // are then in flight together rather than one link's at a time
-    double pn[NQ], nn[K][NQ];
+    // neighbours too (their links are skipped): all 18 (1 + K) gathers are
+    // then in flight together rather than one link's at a time
+    FluidRegs64<K> nb;
 #pragma unroll
     for (int i = 1; i < NQ; ++i) {
       const uint32_t rn = nbr(o, r, i);
-      pn[i] = ld32(phi, rn);
+      nb.p[i] = ld32(phi, rn);
 #pragma unroll
-      for (int k = 0; k < K; ++k) nn[k][i] = ld32(sbase(n + k * N), rn);
+      for (int k = 0; k < K; ++k) nb.nn[k][i] = ld32(sbase(n + k * N), rn);
     }
-    double F0 = 0.0, F1 = 0.0, F2 = 0.0;
-#pragma unroll
-    for (int i = 1; i < NQ; ++i) {
-      if (solid_link(m, i)) continue;  // no flux into an electrode
-      const double dphi = pn[i] - ph - P.Ec[i];
-      double S1, C1;
-      sinh_coshm1(dphi, S1, C1);
-      double g = 0.0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double nt = nn[k][i];
-        double S, C;
-        valence_sc(P.z[k], dphi, S1, C1, S, C);
-        const double gk = -((nt + nr[k]) * S + (nt - nr[k]) * C) * (0.5 / LEN[i]);
-        g += gk;
-        js[k] += P.dk[k] * (gk - (nt - nr[k]) / LEN[i]);
-      }
-      const double c = 3.0 * WQ[i] * LEN[i] * g;
-      if (CX[i]) F0 += CX[i] * c;
-      if (CY[i]) F1 += CY[i] * c;
-      if (CZ[i]) F2 += CZ[i] * c;
-    }
-
-    double f[NQ];
-    pull<NT>(L, r, m, o, fin, f);
-    double rho = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      rho += f[i];
-      if (CX[i]) m0 += CX[i] * f[i];
-      if (CY[i]) m1 += CY[i] * f[i];
-      if (CZ[i]) m2 += CZ[i] * f[i];
-    }
-    // Guo forcing: velocity with the half-force shift
-    ux = (m0 + 0.5 * F0) / rho;
-    uy = (m1 + 0.5 * F1) / rho;
-    uz = (m2 + 0.5 * F2) / rho;
-    const double uu = ux * ux + uy * uy + uz * uz;
-    const double itau = 1.0 / P.tau;
-    const double guo = 1.0 - 0.5 * itau;
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) {
-      const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-      const double feq = WQ[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-      const double s = ((3.0 * (CX[i] - ux) + 9.0 * cu * CX[i]) * F0 +
-                        (3.0 * (CY[i] - uy) + 9.0 * cu * CY[i]) * F1 +
-                        (3.0 * (CZ[i] - uz) + 9.0 * cu * CZ[i]) * F2) *
-                       (guo * WQ[i]);
-      fn[i] = f[i] - (f[i] - feq) * itau + s;
-    }
-#pragma unroll
-    for (int k = 0; k < K; ++k) nso[k] = nr[k] - js[k];
+    fluid_node_f64<K, NT>(L, P, r, m, o, ph, nr, nb, fin, fn, ux, uy, uz, nso);
   }
 #pragma unroll
   for (int i = 0; i < NQ; ++i) st_stream<NT>(sbase(fout + i * N), r, fn[i]);
