@@ -72,7 +72,7 @@ inline Lattice make_lattice(int nx, int ny, int nz, uint32_t selfm, double wall,
 // 192^3 porous electrode pass B took 191 us on 64 x 4 x 16 tiles, 187 us
 // with the tiles of a run of planes given to one die in consecutive chunks,
 // and 185 us on 32 x 8 x 8 tiles in that order (199 us without it).
-constexpr int TILE_X = 32, TILE_Y = 8, TILE_Z = 8;
+constexpr int TILE_X = 32, TILE_Y = 8, TILE_Z = 8;  // the plane rings' tiles (below)
 constexpr int TB_TILED = 1;
 inline bool tiles_fit(const Lattice &L) { return L.nx % TILE_X == 0 && L.ny % TILE_Y == 0; }
 
@@ -124,6 +124,7 @@ inline MgLevel make_level(int nx, int ny, int nz, uint32_t selfm, double h2, dou
 // nothing from runs of 4 in 864 blocks.)  A launcher's `ring` is RING_OFF,
 // RING_AUTO (that rule) or a run length forced (> 0, on levels that fit).
 constexpr int RING_TX = 32, RING_TY = 8;
+static_assert(TILE_X == RING_TX && TILE_Y == RING_TY, "pass B's tiles are the plane rings' tiles");
 constexpr int RING_ZRUN = 8, RING_MIN_BLOCKS = 1024, RING_MIN_ZRUN = 4;
 constexpr int RING_OFF = -1, RING_AUTO = 0;
 inline int ring_zrun(const MgLevel &lv, int ring) {  // 0: the gathering kernels

@@ -279,8 +279,6 @@ __global__ __launch_bounds__(TB) void k_ions_f64(Lattice L, Phys P,
 // n* loading meanwhile, one barrier per plane.  The gathering kernel's
 // arithmetic on the same values, hence the same bits.  Five FP64 values
 // per halo cell fill 54 KB of LDS for two species, so one or two species.
-static_assert(TILE_X == RING_TX && TILE_Y == RING_TY, "pass B tiles are the plane rings' tiles");
-
 // neighbour values from the LDS slots of a tile: the plane z + c_z in slot
 // (k + c_z) & 3 with k = z - z0 + 1, halo cell hc + c_x + RING_HX c_y
 template <int K>

@@ -468,85 +468,52 @@ __global__ __launch_bounds__(TB) void k_ions_f32(Lattice L, Phys P,
   if (prev) extrapolate_at(r, N, order, solid, phi, prev);
 }
 
-// Pass B on an LDS-staged tile: a block of TILE_X x TILE_Y nodes marches
-// along z through TILE_Z planes, keeping the planes z - 1, z, z + 1 of the
-// velocity and the deviations (with a one-node halo in x and y, wrapped
-// periodically) in LDS, so each value is read from memory once per tile
-// instead of once per neighbour.  The plane z + 2 is loaded into registers
-// while the plane z is computed and goes to LDS at the next step (a ring of
-// four slots), so its latency hides behind the arithmetic.  Same arithmetic
-// as k_ions_f32, hence the same bits.  Needs nx a multiple of TILE_X and ny
-// of TILE_Y.
+// Pass B on an LDS-staged tile: a block of TILE_X x TILE_Y nodes (the plane
+// rings' tiles) marches along z through TILE_Z planes, keeping the planes
+// z - 1, z, z + 1 of the velocity and the deviations (with a one-node halo
+// in x and y, wrapped periodically) in LDS, so each value is read from
+// memory once per tile instead of once per neighbour.  The plane z + 2 is
+// loaded into registers while the plane z is computed and goes to LDS at
+// the next step (a ring of four slots), so its latency hides behind the
+// arithmetic.  Same arithmetic as k_ions_f32, hence the same bits.  Needs
+// nx a multiple of TILE_X and ny of TILE_Y.
 template <int K, bool NT>
-__global__ __launch_bounds__(TILE_X * TILE_Y) void k_ions_f32_tiled(
+__global__ __launch_bounds__(BLOCK) void k_ions_f32_tiled(
     Lattice L, Phys P, const uint32_t *__restrict__ mask, const float *__restrict__ u,
     const float *__restrict__ nu, const float *__restrict__ lo_in, float *__restrict__ nuio,
     float *__restrict__ lo_out, double *__restrict__ src, int order,
     double *__restrict__ phi, double *__restrict__ prev) {
-  constexpr int NT_ = TILE_X * TILE_Y, HX = TILE_X + 2, HP = (TILE_X + 2) * (TILE_Y + 2);
-  constexpr int NV = 3 + K, PER = (HP + NT_ - 1) / NT_;  // halo cells per thread
-  __shared__ float sv[4][NV][HP];  // [slot][u_x, u_y, u_z, nu_0..][halo cell]
+  constexpr int NV = 3 + K;
+  __shared__ float sv[4][NV][RING_HP];  // [slot][u_x, u_y, u_z, nu_0..][halo cell]
   const int N = L.n;
-  const int ntx = L.nx / TILE_X, nty = L.ny / TILE_Y;
-  // consecutive tiles of a run of planes on one die, so that the halos they
-  // share meet in its L2
-  int b = xcd_block(blockIdx.x, gridDim.x, 1, ntx * nty, L.xcd);
-  const int x0 = (b % ntx) * TILE_X;
-  b /= ntx;
-  const int y0 = (b % nty) * TILE_Y;
-  const int z0 = (b / nty) * TILE_Z;
-  const int lx = threadIdx.x % TILE_X, ly = threadIdx.x / TILE_X;
-  // this thread's halo cells: their offset in a plane (g) and LDS index (c)
-  uint32_t gxy[PER];
-  int cidx[PER];
+  const RingTile t = ring_tile(L, TILE_Z);
+  PlaneRing<float> rv[NV];
 #pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int c = threadIdx.x + j * NT_;
-    cidx[j] = c < HP ? c : -1;
-    const int cc = c < HP ? c : 0;
-    const int hy = cc / HX, hx = cc - hy * HX;
-    int gx = x0 + hx - 1, gy = y0 + hy - 1;
-    gx = gx < 0 ? gx + L.nx : (gx >= L.nx ? gx - L.nx : gx);
-    gy = gy < 0 ? gy + L.ny : (gy >= L.ny ? gy - L.ny : gy);
-    gxy[j] = gx + L.nx * gy;
-  }
-  float reg[PER][NV];
-  auto fetch = [&](int z) {  // plane z (wrapped) into registers
-    const int zz = z < 0 ? z + L.nz : (z >= L.nz ? z - L.nz : z);
+  for (int v = 0; v < NV; ++v) rv[v].init(L, t);
+  auto fetch = [&](int z) {
+    rv[0].fetch(L, u, z);
+    rv[1].fetch(L, sbase(u + N), z);
+    rv[2].fetch(L, sbase(u + 2 * N), z);
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      if (cidx[j] < 0) continue;
-      const uint32_t g = gxy[j] + (uint32_t)L.nxy * zz;
-      reg[j][0] = ld32(u, g);
-      reg[j][1] = ld32(sbase(u + N), g);
-      reg[j][2] = ld32(sbase(u + 2 * N), g);
-#pragma unroll
-      for (int k = 0; k < K; ++k) reg[j][3 + k] = ld32(sbase(nu + k * N), g);
-    }
+    for (int k = 0; k < K; ++k) rv[3 + k].fetch(L, sbase(nu + k * N), z);
   };
   auto put = [&](int slot) {
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      if (cidx[j] < 0) continue;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sv[slot][v][cidx[j]] = reg[j][v];
-    }
+    for (int v = 0; v < NV; ++v) rv[v].put(sv[slot][v]);
   };
+  const int z0 = t.z0, zend = t.zend, hc = t.hc;
   // the plane z sits in slot (z - z0 + 1) & 3
   fetch(z0 - 1);
   put(0);
   fetch(z0);
   put(1);
   fetch(z0 + 1);
-  const int zend = min(z0 + TILE_Z, L.nz);
-  const int hc = (lx + 1) + HX * (ly + 1);  // this node's halo cell
   // the node's own flag word, low words and pass A increments, one plane
   // ahead as well
-  const uint32_t rxy = (x0 + lx) + L.nx * (y0 + ly);
   uint32_t m_next;
   float lo_next[K], dn_next[K];
   auto fetch_own = [&](int z) {
-    const uint32_t r = rxy + (uint32_t)L.nxy * z;
+    const uint32_t r = t.rxy + (uint32_t)L.nxy * z;
     m_next = ld32(mask, r);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -569,7 +536,7 @@ __global__ __launch_bounds__(TILE_X * TILE_Y) void k_ions_f32_tiled(
       fetch_own(z + 1);
     }
     __syncthreads();
-    const int r = rxy + L.nxy * z;
+    const int r = (int)(t.rxy + (uint32_t)L.nxy * z);
     const bool solid = m & SOLID_BIT;
     float hio[K], loo[K];
     double q = 0.0;
@@ -584,7 +551,7 @@ __global__ __launch_bounds__(TILE_X * TILE_Y) void k_ions_f32_tiled(
       float cut[NQ], nn[K][NQ];
 #pragma unroll
       for (int i = 1; i < NQ; ++i) {
-        const int sl = (z - z0 + 1 + CZ[i]) & 3, cc = hc + CX[i] + HX * CY[i];
+        const int sl = (z - z0 + 1 + CZ[i]) & 3, cc = hc + CX[i] + RING_HX * CY[i];
         cut[i] = c_dot(i, CX[i] ? sv[sl][0][cc] : 0.f, CY[i] ? sv[sl][1][cc] : 0.f,
                        CZ[i] ? sv[sl][2][cc] : 0.f);
 #pragma unroll
@@ -785,7 +752,7 @@ hipError_t launch_ions_f32(hipStream_t s, const Lattice &L, const Phys &P, const
     const unsigned nb = (unsigned)((L.nx / TILE_X) * (L.ny / TILE_Y) *
                                    ((L.nz + TILE_Z - 1) / TILE_Z));
 #define CALL(KK, NT) \
-  hipLaunchKernelGGL((k_ions_f32_tiled<KK, NT>), dim3(nb), dim3(TILE_X * TILE_Y), 0, s, L, P, mask, u, nu, lo_in, nuio, lo_out, src, order, phi, prev)
+  hipLaunchKernelGGL((k_ions_f32_tiled<KK, NT>), dim3(nb), dim3(BLOCK), 0, s, L, P, mask, u, nu, lo_in, nuio, lo_out, src, order, phi, prev)
 #define CALL_T(KK) CALL(KK, true)
 #define CALL_F(KK) CALL(KK, false)
     if (nt) {
