@@ -726,8 +726,8 @@ def main():
                                            (args.start_step + args.warmup, args.steps)))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: the LBE step is not sharded across GPUs in this "
-              "build (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the LBE step has no multi-GPU sharding "
+              "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     init_device()
     if args.copy_calibration:

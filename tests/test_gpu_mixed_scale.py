@@ -18,7 +18,7 @@ configurations' full size and length.
    cell (30000), the 192^3 porous electrode (4000) and the 96-system batch
    (one 10000-step chunk), each in its benchmark configuration.
 
-Bars (the benchmark spec): potential within 1e-5 of the electrode voltage
+Bars: potential within 1e-5 of the electrode voltage
 difference; electrode charge Q(t) over the whole history and capacitance
 Q(T)/dV within 1e-5 of |Q|; velocity within 1e-4 of its largest magnitude,
 and the electro-osmotic flux (total momentum along the applied field)
