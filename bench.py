@@ -211,8 +211,31 @@ def roofline_of(kernels, kinds, label):
             "traffic": None if traffic is None else int(round(traffic))}
 
 
+def time_window(g, steps, chunk_units=0):
+    """Wall time of `steps` steps from the context's current state: one by
+    one (lbe_step), or replayed from captured graphs with `chunk_units`
+    solver units per step (lbe_step_chunk).  Returns (seconds, first step,
+    Poisson iterations per step, error text or None)."""
+    tot0 = g.totals()
+    sync()
+    t0 = time.perf_counter()
+    err = None
+    try:
+        if chunk_units:
+            g.step_chunk(steps, chunk_units)
+        else:
+            g.step(steps)
+    except lbe.LbeError as e:  # a replayed solve short of the tolerance
+        err = str(e)
+    sync()
+    el = time.perf_counter() - t0
+    tot1 = g.totals()
+    done = tot1["step"] - tot0["step"]
+    return el, int(tot0["step"]), (tot1["poisson_total"] - tot0["poisson_total"]) / max(done, 1), err
+
+
 def run_form(w, form: str, solver: str, steps: int, warmup: int, start_step: int,
-             check_every: int, traffic=None, krylov=False, nu=(2, 2, 0, 0)):
+             check_every: int, traffic=None, krylov=False, nu=(2, 2, 0, 0), chunk_units=()):
     p = step_params(w, form, solver, check_every, krylov, nu)
     flags = p.flags
     t_init = time.perf_counter()
@@ -240,6 +263,27 @@ def run_form(w, form: str, solver: str, steps: int, warmup: int, start_step: int
     print(f"bench: {w.name} {form}/{solver}: steps {tot0['step']}..{tot1['step']} in "
           f"{el:.4f} s, {mlups:.2f} MLUPS, {iters:.2f} "
           f"{'sweeps' if solver == 'sor' else 'iterations'}/step", file=sys.stderr, flush=True)
+
+    # graph-replayed steps (a whole number of 16-step graphs) with a fixed
+    # number of solver units per step, bracketed by windows of the same
+    # length stepped one by one
+    chunks = {}
+    if chunk_units:
+        csteps = 16 * max(1, (steps + 15) // 16)
+        runs = [0] + [u for u in chunk_units] + [0]
+        for i, u in enumerate(runs):
+            el2, first, it2, err = time_window(g, csteps, u)
+            key = f"units_{u}" if u else ("steps_before" if i == 0 else "steps_after")
+            chunks[key] = {"mlups": round(N * csteps / el2 / 1e6, 3),
+                           "ms_per_step": round(el2 / csteps * 1e3, 4), "first_step": first,
+                           "poisson_iters_per_step": round(it2, 3), "steps": csteps}
+            if err:
+                chunks[key]["error"] = err
+            print(f"bench: {w.name} {form}/{solver}: "
+                  f"{'graphs, ' + str(u) + ' units/step' if u else 'one by one'}: "
+                  f"steps {first}..{first + csteps} in {el2:.4f} s, "
+                  f"{N * csteps / el2 / 1e6:.2f} MLUPS, {it2:.2f} iterations/step"
+                  + (f" ({err})" if err else ""), file=sys.stderr, flush=True)
 
     # second window: HIP events around every launch, on the library's stream
     g.profile(True)
@@ -277,7 +321,7 @@ def run_form(w, form: str, solver: str, steps: int, warmup: int, start_step: int
             "poisson_iters_per_step": round(iters, 3),
             "roofline": roofline_of(kernels, [dom], dom),
             "roofline_step_passes": roofline_of(kernels, ["fluid", "ions"], "fluid+ions"),
-            "kernels": kernels}
+            "kernels": kernels, **({"graph_chunks": chunks} if chunks else {})}
 
 
 def cpu_model():
@@ -373,6 +417,10 @@ WORKLOADS = {
                              dict(krylov=True, nu=(1, 1, 2, 2))),
 }
 
+# workloads also timed with their steps replayed from captured graphs, at
+# these fixed numbers of solver units per step
+CHUNK_UNITS = {"batched_96_slabs_8x8": (2, 3)}
+
 
 def run_workload(name, forms, steps, warmup, start_step, check_every, traffic=None):
     build, settings = WORKLOADS[name]
@@ -388,7 +436,7 @@ def run_workload(name, forms, steps, warmup, start_step, check_every, traffic=No
             res[f] = run_form(w, form, solver, max(2, steps // 10), 2, 0, check_every, traffic)
         else:
             res[f] = run_form(w, form, solver, steps, warmup, start_step, check_every, traffic,
-                              **settings)
+                              chunk_units=CHUNK_UNITS.get(name, ()), **settings)
     return w, nfluid, res
 
 
@@ -783,7 +831,8 @@ def main():
                 "steps": args.shape_steps, "poisson": poisson_text(WORKLOADS[name][1]),
                 "forms": {k: {kk: v[kk] for kk in ("mlups", "ms_per_step", "first_step",
                                                     "poisson_iters_per_step", "launch",
-                                                    "roofline", "roofline_step_passes")}
+                                                    "roofline", "roofline_step_passes",
+                                                    "graph_chunks") if kk in v}
                           for k, v in r.items()}}
     aforms = [f.strip() for f in args.adjoint_forms.split(",") if f.strip()]
     if aforms:

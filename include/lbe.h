@@ -200,6 +200,34 @@ int lbe_init_batch(const lbe_params *params, const uint8_t *type, const double *
 int lbe_step(lbe_ctx *ctx, int64_t nsteps);
 
 /*
+ * Advance nsteps time steps as lbe_step does, with the steps launched from
+ * graphs instead of one by one: 16 whole steps (both passes, the Poisson
+ * solve, the electrode charges) are captured once as a HIP graph and
+ * replayed, and the host does not wait between steps.  Each replayed step
+ * queues the solve's first residual check and then exactly `units` solver
+ * units (check_every SOR sweeps, or one multigrid cycle, each ending in a
+ * check); a unit that starts after the tolerance was met does nothing on
+ * the device, so a step whose solve converges within `units` units gives
+ * the same bits as lbe_step.  The steps right after lbe_init or
+ * lbe_set_electrode_potential (under LBE_EXTRAPOLATE, until two earlier
+ * potentials are kept) and the last nsteps mod 16 run as in lbe_step, as
+ * do all steps while per-kernel profiling is on or graphs are disabled.
+ * The graph is kept by the context and captured again when units, the
+ * tolerance or the buffer parity differ from the last call.
+ * The call waits once, after the last replay.  Errors: LBE_EINVAL for
+ * nsteps < 0, units < 1, tol <= 0 or units x (iterations per unit) above
+ * max_iter; LBE_ENOMEM; LBE_ENOCONV when a replayed step's solve ended
+ * above the tolerance, LBE_ENONFINITE when its residual was not finite:
+ * unlike lbe_step these are reported after all replays, the context is not
+ * rewound, and the state is that after every replayed step (an
+ * unconverged step's charges are those of its last iterate; the remaining
+ * nsteps mod 16 steps are not taken); lbe_observables' poisson_iters and
+ * poisson_resid report the last replayed step.  Otherwise the errors of
+ * lbe_step.
+ */
+int lbe_step_chunk(lbe_ctx *ctx, int64_t nsteps, int32_t units);
+
+/*
  * Change the Poisson stopping rule of a context (the tol and max_iter of
  * lbe_params) for every later solve: tol <= 0 runs exactly max_iter sweeps
  * (or cycles).  Nothing else changes, so a step that failed with

@@ -25,7 +25,8 @@ NOALLOC_MAX_ELECTRODES = 16
 
 # public entry points of include/lbe.h
 ENTRY_POINTS = (
-    "lbe_init", "lbe_init_batch", "lbe_init_device", "lbe_step", "lbe_set_solver",
+    "lbe_init", "lbe_init_batch", "lbe_init_device", "lbe_step", "lbe_step_chunk",
+    "lbe_set_solver",
     "lbe_poisson", "lbe_set_electrode_potential", "lbe_record", "lbe_adjoint",
     "lbe_electrode_charge", "lbe_observables", "lbe_fields_device",
     "lbe_destroy", "lbe_strerror", "lbe_last_error", "lbe_profile", "lbe_kernel_times",
@@ -116,6 +117,8 @@ def load(path: str = LIB_PATH):
     lib.lbe_fields_device.restype = C.c_int
     lib.lbe_step.argtypes = [C.c_void_p, C.c_int64]
     lib.lbe_step.restype = C.c_int
+    lib.lbe_step_chunk.argtypes = [C.c_void_p, C.c_int64, C.c_int32]
+    lib.lbe_step_chunk.restype = C.c_int
     lib.lbe_poisson.argtypes = [C.c_void_p, P(C.c_int32), d]
     lib.lbe_poisson.restype = C.c_int
     lib.lbe_set_electrode_potential.argtypes = [C.c_void_p, d]
@@ -335,6 +338,11 @@ class Lbe:
 
     def step(self, nsteps=1):
         self._check(self._lib.lbe_step(self.h, int(nsteps)))
+
+    def step_chunk(self, nsteps, units):
+        """nsteps steps replayed from captured 16-step graphs with `units`
+        solver units per step (lbe_step_chunk)."""
+        self._check(self._lib.lbe_step_chunk(self.h, int(nsteps), int(units)))
 
     def set_solver(self, tol=None, max_iter=None):
         """New Poisson stopping rule for later solves (None keeps a value)."""

@@ -17,6 +17,10 @@
 
 using namespace lbe;
 
+// Whole time steps captured in one graph by lbe_step_chunk (even, so that a
+// replay ends on the buffer parity it started from).
+constexpr int CHUNK_STEPS = 16;
+
 struct lbe_ctx {
   lbe_params p{};
   Lattice L{};
@@ -68,6 +72,15 @@ struct lbe_ctx {
   double *charge_dst = nullptr;
   bool charge_queued = false;
   hipGraphExec_t unit_exec = nullptr;
+  // graph-replayed steps (lbe_step_chunk): CHUNK_STEPS whole steps captured
+  // for one unit count, buffer parity and tolerance; each step's charges
+  // staged in chunk_q and its outcome folded into chunk_st
+  hipGraphExec_t chunk_exec = nullptr;
+  int chunk_units = 0, chunk_cur = -1;
+  double chunk_tol = 0.0;
+  int queue_units = 0;  // > 0 while a chunk is captured: fixed units, no host reads
+  double *chunk_q = nullptr;
+  ChunkStatus *chunk_st = nullptr;
 
   // electrode charge tables
   int *iface = nullptr, *blk_elec = nullptr, *blk_begin = nullptr, *blk_end = nullptr;
@@ -487,6 +500,20 @@ int run_solve(lbe_ctx *c, int per_check, bool learn, const char *unit, Step &&st
     HIPCHK(c, hipGraphLaunch(c->unit_exec, c->stream));
     return LBE_OK;
   };
+  if (c->queue_units > 0) {
+    // one step of a captured chunk: the control block cleared on the device,
+    // the first check, a fixed number of units (each a no-op on the device
+    // once the solve is done), the step's charge (of the converged
+    // potential, or of the last iterate when the units did not suffice) and
+    // its outcome; the host reads nothing
+    HIPCHK(c, launch_ctl_reset(c->stream, c->ctl, p.tol));
+    if ((rc = check(0))) return rc;
+    for (int u = 0; u < c->queue_units; ++u)
+      if ((rc = unit_direct(per_check))) return rc;
+    if (c->charge_dst && (rc = charges_to(c, c->charge_dst, nullptr))) return rc;
+    HIPCHK(c, launch_chunk_status(c->stream, c->ctl, c->chunk_st));
+    return LBE_OK;
+  }
   if ((rc = reset_ctl(c))) return rc;
   if (p.tol <= 0.0) {
     // exactly max_iter iterations on the schedule of a tolerance-driven
@@ -1171,9 +1198,12 @@ int mg_solve(lbe_ctx *c, bool learn) {
       });
 }
 
-int grow_history(lbe_ctx *c) {
-  if (c->qlen < c->qcap) return LBE_OK;
-  const int64_t cap = c->qcap ? 2 * c->qcap : 4096;
+// room for `rows` charge rows in all (default: one more than recorded)
+int grow_history(lbe_ctx *c, int64_t rows = -1) {
+  if (rows < 0) rows = c->qlen + 1;
+  if (rows <= c->qcap) return LBE_OK;
+  int64_t cap = c->qcap ? 2 * c->qcap : 4096;
+  while (cap < rows) cap *= 2;
   double *nh = nullptr;
   int rc = dalloc(c, &nh, (size_t)cap * std::max(c->ne, 1));
   if (rc) return rc;
@@ -1271,14 +1301,10 @@ int rewind_step(lbe_ctx *c, int a, int hist, bool record) {
 
 // record = false: a replay of a recorded step (reverse mode), which neither
 // counts the step nor appends its charge
-int one_step(lbe_ctx *c, bool record = true) {
-  const int a = c->cur, b = 1 - c->cur;
-  const int hist = c->extrap_hist;
-  // room for this step's charge row before anything moves
-  if (record) {
-    const int rc = grow_history(c);
-    if (rc) return rc;
-  }
+// The two passes of a step from buffers a to b: LB and ion link fluxes
+// (pass A), advection and the new concentrations (pass B), which also moves
+// phi to the start of the step's solve.  hist: the extrapolation history.
+int step_passes(lbe_ctx *c, int a, int b, int hist) {
   // pass B keeps phi(t) for a rewind: in the extrapolation history, else in
   // phi_keep (order -1: a plain copy)
   double *keep = c->phi_prev ? c->phi_prev : c->phi_keep;
@@ -1300,6 +1326,18 @@ int one_step(lbe_ctx *c, bool record = true) {
     return launch_ions_f64(c->stream, c->L, c->P, c->mask, c->u, c->n[a], c->n[b], c->src,
                            order, c->phi, keep, c->tb_b, c->nt_b);
   });
+  return rc;
+}
+
+int one_step(lbe_ctx *c, bool record = true) {
+  const int a = c->cur, b = 1 - c->cur;
+  const int hist = c->extrap_hist;
+  // room for this step's charge row before anything moves
+  if (record) {
+    const int rc = grow_history(c);
+    if (rc) return rc;
+  }
+  int rc = step_passes(c, a, b, hist);
   if (rc) return rc;
   if (c->phi_prev) c->extrap_hist = std::min(hist + 1, 2);
   c->cur = b;
@@ -1648,6 +1686,9 @@ void free_ctx(lbe_ctx *c) {
     if (L.r) (void)hipFree(L.r);
   }
   if (c->unit_exec) (void)hipGraphExecDestroy(c->unit_exec);
+  if (c->chunk_exec) (void)hipGraphExecDestroy(c->chunk_exec);
+  if (c->chunk_q) (void)hipFree(c->chunk_q);
+  if (c->chunk_st) (void)hipFree(c->chunk_st);
   if (c->mg_ainv) (void)hipFree(c->mg_ainv);
   if (c->mg_fcell) (void)hipFree(c->mg_fcell);
   if (c->mg_groups) (void)hipFree(c->mg_groups);
@@ -2161,6 +2202,51 @@ fail_:
 
 }  // namespace
 
+// Capture CHUNK_STEPS whole steps from the current buffers, each with `units`
+// solver units, as one graph.  Nothing runs: the host-side state the
+// queueing moves (buffer parity, extrapolation history) is put back, and
+// since CHUNK_STEPS is even and the history is full, a replay ends where it
+// began.
+int capture_chunk(lbe_ctx *c, int units) {
+  if (c->chunk_exec) {
+    (void)hipGraphExecDestroy(c->chunk_exec);
+    c->chunk_exec = nullptr;
+  }
+  const int cur0 = c->cur, hist0 = c->extrap_hist, ne = std::max(c->ne, 1);
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = LBE_OK;
+  c->queue_units = units;
+  for (int s = 0; s < CHUNK_STEPS && !rc; ++s) {
+    const int a = c->cur, b = 1 - a;
+    if ((rc = step_passes(c, a, b, c->extrap_hist))) break;
+    if (c->phi_prev) c->extrap_hist = std::min(c->extrap_hist + 1, 2);
+    c->cur = b;
+    // no charge kernel when no electrode touches the fluid (rows filled after)
+    c->charge_dst = c->nblk_charge > 0 ? c->chunk_q + (size_t)s * ne : nullptr;
+    rc = poisson_solve(c, false);
+  }
+  c->queue_units = 0;
+  c->charge_dst = nullptr;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  c->cur = cur0;
+  c->extrap_hist = hist0;
+  if (rc || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : hip_fail(c, e, "chunk graph capture");
+  }
+  const hipError_t e2 = hipGraphInstantiate(&c->chunk_exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) {
+    c->chunk_exec = nullptr;
+    return hip_fail(c, e2, "chunk graph instantiate");
+  }
+  c->chunk_units = units;
+  c->chunk_cur = cur0;
+  c->chunk_tol = c->p.tol;
+  return LBE_OK;
+}
+
 extern "C" {
 
 int lbe_init(const lbe_params *params, const uint8_t *type, const double *phi_s,
@@ -2234,6 +2320,66 @@ int lbe_step(lbe_ctx *c, int64_t nsteps) {
     int rc = one_step(c);
     if (rc) return rc;
   }
+  return LBE_OK;
+}
+
+int lbe_step_chunk(lbe_ctx *c, int64_t nsteps, int32_t units) {
+  if (!c || nsteps < 0 || units < 1)
+    return fail(c, LBE_EINVAL, "bad context, step count or unit count");
+  const lbe_params &p = c->p;
+  const int per_check = p.poisson == LBE_MG ? 1 : p.check_every;
+  if (!(p.tol > 0.0)) return fail(c, LBE_EINVAL, "graph-replayed steps need a tolerance > 0");
+  if ((int64_t)units * per_check > (int64_t)p.max_iter)
+    return fail(c, LBE_EINVAL, "units x iterations per unit exceed max_iter");
+  int64_t t = 0;
+  int rc;
+  // the steps after init or a change of the electrode potentials start from
+  // a lower extrapolation order: taken one by one
+  for (; t < nsteps && c->phi_prev && c->extrap_hist < 2; ++t)
+    if ((rc = one_step(c))) return rc;
+  const int64_t reps = (c->prof || !c->use_graphs) ? 0 : (nsteps - t) / CHUNK_STEPS;
+  if (reps > 0) {
+    const int ne = std::max(c->ne, 1);
+    if ((rc = grow_history(c, c->qlen + reps * CHUNK_STEPS))) return rc;
+    if (!c->chunk_q && (rc = dalloc(c, &c->chunk_q, (size_t)CHUNK_STEPS * ne))) return rc;
+    if (!c->chunk_st && (rc = dalloc(c, &c->chunk_st, 1))) return rc;
+    if (!c->chunk_exec || c->chunk_units != units || c->chunk_cur != c->cur ||
+        c->chunk_tol != p.tol)
+      if ((rc = capture_chunk(c, units))) return rc;
+    HIPCHK(c, hipMemsetAsync(c->chunk_st, 0, sizeof(ChunkStatus), c->stream));
+    const size_t rows = (size_t)CHUNK_STEPS * ne;
+    for (int64_t r = 0; r < reps; ++r) {
+      HIPCHK(c, hipGraphLaunch(c->chunk_exec, c->stream));
+      double *dst = c->qhist + (size_t)c->qlen * ne;
+      if (c->nblk_charge > 0)
+        HIPCHK(c, hipMemcpyAsync(dst, c->chunk_q, sizeof(double) * rows,
+                                 hipMemcpyDeviceToDevice, c->stream));
+      else
+        HIPCHK(c, hipMemsetAsync(dst, 0, sizeof(double) * rows, c->stream));
+      c->qlen += CHUNK_STEPS;
+      c->step += CHUNK_STEPS;
+    }
+    ChunkStatus st{};
+    HIPCHK(c, hipMemcpyAsync(&st, c->chunk_st, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->ctl_h, c->ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->last_iters = c->ctl_h->done ? c->ctl_h->iters : c->ctl_h->count;
+    c->last_resid = c->ctl_h->resid;
+    c->total_iters += st.iters;
+    if (st.nonfinite) return fail(c, LBE_ENONFINITE, "non-finite Poisson residual in a replayed step");
+    if (st.unconverged) {
+      char buf[200];
+      snprintf(buf, sizeof buf,
+               "Poisson not converged in %d of %lld replayed steps with %d units each "
+               "(largest residual %.3e)",
+               st.unconverged, (long long)(reps * CHUNK_STEPS), units, st.resid_max);
+      return fail(c, LBE_ENOCONV, buf);
+    }
+    t += reps * CHUNK_STEPS;
+  }
+  for (; t < nsteps; ++t)
+    if ((rc = one_step(c))) return rc;
   return LBE_OK;
 }
 

@@ -178,6 +178,15 @@ struct SolveCtl {
   SolveCtl *mirror;  // host-mapped copy (device address), or null
 };
 
+// Outcome of a run of graph-replayed time steps (lbe_step_chunk), folded by
+// every step after its solve; zeroed by the host before the run.
+struct ChunkStatus {
+  double resid_max;  // largest final residual of the steps' solves
+  long long iters;   // sweeps or cycles summed over the steps
+  int unconverged;   // steps whose solve ended above the tolerance
+  int nonfinite;     // steps whose residual was NaN or Inf
+};
+
 // Flexible conjugate gradients preconditioned by one V-cycle (device state).
 struct KrylovCtl {
   double alpha, beta;
@@ -282,6 +291,11 @@ int residual_blocks(const Lattice &L);
 hipError_t launch_resid_f64(hipStream_t s, const Lattice &L, const uint32_t *mask,
                             const double *src, const double *phi, double *partial, SolveCtl *ctl,
                             int add);
+// Start of a solve queued without the host: the control block cleared on
+// the device (tolerance tol, no host-mapped copy), one thread.
+hipError_t launch_ctl_reset(hipStream_t s, SolveCtl *ctl, double tol);
+// Fold the finished solve in ctl into st (one thread).
+hipError_t launch_chunk_status(hipStream_t s, const SolveCtl *ctl, ChunkStatus *st);
 // gate (may be NULL): both kernels return at once unless gate->done is set
 hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
                          const double *phi, const int *iface_site, const int *blk_elec,

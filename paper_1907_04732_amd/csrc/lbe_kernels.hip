@@ -738,6 +738,29 @@ hipError_t launch_resid_f64(hipStream_t s, const Lattice &L, const uint32_t *mas
   return hipGetLastError();
 }
 
+__global__ void k_ctl_reset(SolveCtl *__restrict__ ctl, double tol) {
+  if (threadIdx.x == 0) *ctl = SolveCtl{0.0, tol, 0, 0, 0, 0, 0, 0, 0ull, nullptr};
+}
+
+__global__ void k_chunk_status(const SolveCtl *__restrict__ ctl, ChunkStatus *__restrict__ st) {
+  if (threadIdx.x != 0) return;
+  // a non-finite residual also ends the solve, so done covers both outcomes
+  if (!ctl->done) st->unconverged += 1;
+  if (ctl->nonfinite) st->nonfinite += 1;
+  st->iters += ctl->done ? ctl->iters : ctl->count;
+  if (!(ctl->resid <= st->resid_max)) st->resid_max = ctl->resid;
+}
+
+hipError_t launch_ctl_reset(hipStream_t s, SolveCtl *ctl, double tol) {
+  hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_status(hipStream_t s, const SolveCtl *ctl, ChunkStatus *st) {
+  hipLaunchKernelGGL(k_chunk_status, dim3(1), dim3(64), 0, s, ctl, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_charge(hipStream_t s, const Lattice &L, double q_scale, const uint32_t *mask,
                          const double *phi, const int *iface_site, const int *blk_elec,
                          const int *blk_begin, const int *blk_end, int nblocks, int ne,
