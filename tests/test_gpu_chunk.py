@@ -76,6 +76,41 @@ def test_chunk_on_a_curved_lattice_same_bits():
     same_state(g1, g2)
 
 
+def test_chunk_with_the_papers_sor_same_bits():
+    """FP64 four-colour SOR (the paper's solver, the path the oracle
+    reproduces sweep for sweep), four sweeps per unit: replayed steps equal
+    lbe_step bit for bit."""
+    kwc, shape, t, ps, n0, nref, _, _ = G.case("slab_4x4x34")
+    kwc = dict(kwc)
+    kwc.update(tol=1e-10, max_iter=2000, check_every=4)
+    print("chunk parity: slab 4x4x34, FP64 SOR", flush=True)
+    g1 = lbe.Lbe(lbe.make_params(shape, **kwc), t, ps, n0, nref)
+    g2 = lbe.Lbe(lbe.make_params(shape, **kwc), t, ps, n0, nref)
+    g1.step(35)
+    g2.step_chunk(35, units=150)
+    same_state(g1, g2)
+
+
+def test_chunk_graph_kept_across_a_potential_change():
+    """A new set of electrode potentials restarts the extrapolation history:
+    the next call takes two steps one by one and then replays the graph
+    captured before the change (same buffers, same unit count)."""
+    b = small_batch()
+    kw = dict(tol=1e-10, max_iter=200, poisson=lbe.MG, precision=lbe.FP32_MIXED,
+              flags=lbe.EXTRAPOLATE | lbe.KRYLOV)
+    g1, g2 = batch_ctx(b, **kw), batch_ctx(b, **kw)
+    print(f"chunk parity: batch {b.shape}, potential change between calls", flush=True)
+    g1.step(18)
+    g2.step_chunk(18, units=24)
+    same_state(g1, g2)
+    ps = np.where(b.node_type > 0, 1.5 * b.phi_s, 0.0)
+    g1.set_electrode_potential(ps)
+    g2.set_electrode_potential(ps)
+    g1.step(34)
+    g2.step_chunk(34, units=24)
+    same_state(g1, g2)
+
+
 def test_chunk_reports_an_unconverged_solve():
     """SOR with one sweep per unit and a single unit per step cannot reach
     1e-10: the replays run to the end and the call reports LBE_ENOCONV, with
