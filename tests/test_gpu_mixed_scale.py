@@ -16,7 +16,8 @@ configurations' full size and length.
    the parity cases) at full size for the configured number of steps: the
    64 x 64 x 130 electro-osmosis slab (50000), the 160 x 160 x 64 coaxial
    cell (30000), the 192^3 porous electrode (4000) and the 96-system batch
-   (one 10000-step chunk), each in its benchmark configuration.
+   (one 10000-step chunk, replayed from captured graphs), each in its benchmark
+   configuration.
 
 Bars: potential within 1e-5 of the electrode voltage
 difference; electrode charge Q(t) over the whole history and capacitance
@@ -152,25 +153,33 @@ def test_mixed_matches_fp64_at_full_size(name):
 def test_batch_capacitance_mixed_matches_fp64():
     """The 96-system batch (8 x 8 x L, L 16..256, Debye length 2..16, voltage
     0.01..0.2) in its benchmark configuration for one configured chunk of
-    10000 steps: every system's charge history and capacitance Q(T)/V in the
-    mixed form against the FP64 form, and the potential of every system
-    against its own voltage."""
+    10000 steps, the mixed form replayed from captured 16-step graphs
+    (lbe_step_chunk, 16 solver units per step): every system's charge
+    history and capacitance Q(T)/V against the FP64 form, and the potential
+    of every system against its own voltage.  The replayed chunk gives the
+    same bits as the mixed form stepped one by one."""
     w = W.batch_slabs(noise=True)
     runs = {}
-    for form in ("fp32", "fp64"):
+    for form, graphs in (("fp32", True), ("fp32", False), ("fp64", False)):
         p = bench.step_params(w, form, **SETTINGS["batched_96_slabs_8x8"])
         g = lbe.Lbe(p, w.node_type, w.phi_s, w.n_init, w.n_ref.reshape(-1), system=w.system,
                     nsys=len(w.L))
+        print("batch", form, "graphs" if graphs else "one by one", flush=True)
         t0 = g.totals()
-        g.step(10000)
+        if graphs:
+            g.step_chunk(10000, units=16)
+        else:
+            g.step(10000)
         t1 = g.totals()
-        runs[form] = (g.fields(f=False)["phi"], g.qhist())
+        runs[form, graphs] = (g.fields(f=False)["phi"], g.qhist())
         g.close()
         dn = [t1["nk"][k] / t0["nk"][k] - 1 for k in range(len(w.z))]
         print("batch", form, "relative drift of the ion counts",
               ", ".join(f"{v:.2e}" for v in dn))
         assert max(abs(v) for v in dn) <= (1e-13 if form == "fp64" else 1e-9)
-    (pa, qa), (pb, qb) = runs["fp32"], runs["fp64"]
+    assert np.array_equal(runs["fp32", True][0], runs["fp32", False][0])
+    assert np.array_equal(runs["fp32", True][1], runs["fp32", False][1])
+    (pa, qa), (pb, qb) = runs["fp32", True], runs["fp64", False]
     nsys = len(w.L)
     # electrodes 2s+1 and 2s+2 belong to system s
     qa3, qb3 = qa.reshape(len(qa), nsys, 2), qb.reshape(len(qb), nsys, 2)
