@@ -20,8 +20,10 @@ for the two passes of the LB and ion update together; measured traffic
 comes from the rocprofv3 summary in profiles/ while the sources still hash to
 the build it was taken on.  "shapes" repeats the measurement on the
 electro-osmosis slab (with the paper's SOR solver as well), the coaxial cell
-and the 96-system batch; "adjoint" times the reverse mode on the porous
-electrode (a checkpointed FP32-mixed record and one gradient of the
+and the 96-system batch, whose forms also carry "graph_chunks": its steps
+replayed from captured 16-step graphs with 2 and 3 solver units per step
+(lbe_step_chunk) between two windows stepped one by one; "adjoint" times
+the reverse mode on the porous electrode (a checkpointed FP32-mixed record and one gradient of the
 electrode charge).  cpu_baseline times the FP64 oracle on a lateral column
 of the same porous electrode, single-threaded and on all host cores.
 
