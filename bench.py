@@ -20,9 +20,10 @@ for the two passes of the LB and ion update together; measured traffic
 comes from the rocprofv3 summary in profiles/ while the sources still hash to
 the build it was taken on.  "shapes" repeats the measurement on the
 electro-osmosis slab (with the paper's SOR solver as well), the coaxial cell
-and the 96-system batch, whose forms also carry "graph_chunks": its steps
-replayed from captured 16-step graphs with 2 and 3 solver units per step
-(lbe_step_chunk) between two windows stepped one by one; "adjoint" times
+and the 96-system batch, whose multigrid forms also carry "graph_chunks":
+steps replayed from captured 16-step graphs with a fixed number of solver
+units per step (lbe_step_chunk; CHUNK_UNITS) between two windows stepped
+one by one; "adjoint" times
 the reverse mode on the porous electrode (a checkpointed FP32-mixed record and one gradient of the
 electrode charge).  cpu_baseline times the FP64 oracle on a lateral column
 of the same porous electrode, single-threaded and on all host cores.
@@ -421,7 +422,8 @@ WORKLOADS = {
 
 # workloads also timed with their steps replayed from captured graphs, at
 # these fixed numbers of solver units per step
-CHUNK_UNITS = {"batched_96_slabs_8x8": (2, 3)}
+CHUNK_UNITS = {"eo_slab_64x64x130": (1, 2), "coaxial_160x160x64": (2, 3),
+               "batched_96_slabs_8x8": (2, 3)}
 
 
 def run_workload(name, forms, steps, warmup, start_step, check_every, traffic=None):
