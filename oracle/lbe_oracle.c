@@ -20,8 +20,6 @@
  * one; sums over sites (charges, totals) stay serial, in site order.
  *
  *   init : phi <- Poisson(n(0))            (Sec. II C, Eqs. 13 and 15)
- *
- *   init : phi <- Poisson(n(0))            (Sec. II C, Eqs. 13 and 15)
  *          Q(0) from Gauss's law             (Sec. II C, Eq. 16)
  *   step : link fluxes, force, velocity u(t) (Sec. II B, Eqs. 7, 9-11)
  *          n(t+1) = n(t) - sum of link fluxes
