@@ -1,7 +1,8 @@
 """bench.py's host logic on the CPU: the algorithmic byte model behind the
-roofline figures, the mapping of kernel names onto bench kinds, and the
+roofline figures, the mapping of kernel names onto bench kinds, the
 rocprofv3 summary (calibrated HBM traffic per launch) that the bench reads
-back while the library's sources are unchanged."""
+back while the library's sources are unchanged, and the bookkeeping of its
+timing windows."""
 import csv
 import os
 
@@ -90,3 +91,37 @@ def test_rocprof_summary_is_calibrated_and_read_back(tmp_path, monkeypatch):
     (prof / f"step_traffic_{SLAB}.txt").write_text(
         text.replace(f"sources {bench.sources_hash()}", "sources 0000000000000000"))
     assert bench.load_traffic(SLAB) == {}
+
+
+class _FakeContext:
+    """Stands in for lbe.Lbe in the window bookkeeping: each step adds one
+    Poisson iteration, a replayed window with one unit fails after its
+    steps as lbe_step_chunk does."""
+
+    def __init__(self):
+        self.step_no, self.iters = 1000, 0
+
+    def totals(self):
+        return {"step": self.step_no, "poisson_total": self.iters}
+
+    def step(self, n):
+        self.step_no += n
+        self.iters += n
+
+    def step_chunk(self, n, units):
+        self.step_no += n
+        self.iters += 2 * n
+        if units < 2:
+            raise bench.lbe.LbeError(bench.lbe.ENOCONV, "Poisson not converged")
+
+
+def test_timing_windows_count_steps_and_keep_replay_errors(monkeypatch):
+    monkeypatch.setattr(bench, "sync", lambda: None)
+    g = _FakeContext()
+    el, first, it, err = bench.time_window(g, 32)
+    assert first == 1000 and it == 1.0 and err is None and el >= 0.0
+    el, first, it, err = bench.time_window(g, 32, chunk_units=3)
+    assert first == 1032 and it == 2.0 and err is None
+    el, first, it, err = bench.time_window(g, 32, chunk_units=1)
+    assert first == 1064 and it == 2.0 and "not converged" in err
+    assert g.totals()["step"] == 1096
