@@ -7,6 +7,7 @@ r > R2) and the diffusion coefficient of the coaxial runs are readings; the
 steady state does not depend on D, which is raised to reach it sooner.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -18,6 +19,18 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 LB = 0.4
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def table1():
+    """(lambda_D, printed relative deviation) rows of the paper's Table 1."""
+    rows = []
+    with open(os.path.join(GOLDEN, "coaxial_capacitance_table1.txt")) as fh:
+        for line in fh:
+            cols = line.split("#", 1)[0].split()
+            if cols:
+                rows.append((int(cols[0]), float(cols[1])))
+    return rows
 
 
 def steady_charge(shape, t, ps, debye, D, steps, tau=1.0, precision=lbe.FP64):
@@ -30,7 +43,7 @@ def steady_charge(shape, t, ps, debye, D, steps, tau=1.0, precision=lbe.FP64):
     return g, q
 
 
-@pytest.mark.parametrize("debye,paper_err", [(3, 0.023), (6, 0.012), (9, 0.010), (12, 0.0094)])
+@pytest.mark.parametrize("debye,paper_err", table1())
 def test_coaxial_capacitance_table1(debye, paper_err):
     """Table 1: 54x54 cross-section (Nz = 2 here; the four-colour order
     needs an even periodic extent, the paper uses 3, which is equivalent for
