@@ -200,7 +200,7 @@ int lbe_init_batch(const lbe_params *params, const uint8_t *type, const double *
 int lbe_step(lbe_ctx *ctx, int64_t nsteps);
 
 /*
- * Advance nsteps time steps as lbe_step does, with the steps launched from
+ * Advance nsteps time steps (Sec. II B-C) as lbe_step does, with the steps launched from
  * graphs instead of one by one: 16 whole steps (both passes, the Poisson
  * solve, the electrode charges) are captured once as a HIP graph and
  * replayed, and the host does not wait between steps.  Each replayed step
@@ -229,7 +229,7 @@ int lbe_step_chunk(lbe_ctx *ctx, int64_t nsteps, int32_t units);
 
 /*
  * Change the Poisson stopping rule of a context (the tol and max_iter of
- * lbe_params) for every later solve: tol <= 0 runs exactly max_iter sweeps
+ * lbe_params; the iteration of Sec. II C, Eq. 13) for every later solve: tol <= 0 runs exactly max_iter sweeps
  * (or cycles).  Nothing else changes, so a step that failed with
  * LBE_ENOCONV can be retried with a larger limit.
  * Errors: LBE_EINVAL for a non-finite tol or max_iter < 0 (nothing changed).
@@ -339,7 +339,9 @@ int lbe_electrode_charge_noalloc(int32_t nx, int32_t ny, int32_t nz, double lB, 
                                  void *stream);
 
 /*
- * Copy observables to host buffers; any pointer may be NULL to skip it.
+ * Copy observables to host buffers (Sec. II B: the moments of the
+ * populations and the velocity of Eq. 7; Sec. II C: the electrode charges
+ * of Eq. 16); any pointer may be NULL to skip it.
  * totals: lbe_obs; phi: N; n: nspecies*N; u: 3*N component-major (u[a*N+r],
  * the velocity of Guo forcing, (sum_i f_i c_i + F/2)/rho, of the current
  * state); f: 19*N pre-collision populations of the current time; q_hist:
@@ -385,7 +387,8 @@ int32_t lbe_num_kernel_kinds(void);
  * NULL.  Returns LBE_EINVAL for a NULL context. */
 int lbe_launch_shape(const lbe_ctx *ctx, int32_t *block_a, int32_t *block_b, int32_t *nontemporal);
 
-/* The velocity set as the library uses it (19*3 ints, 19 weights). */
+/* The D3Q19 velocity set as the library uses it (Sec. II B; 19*3 ints,
+ * 19 weights). */
 void lbe_velocities(int32_t *c, double *w);
 
 /* Identity of the build: a hash of the sources the library was compiled
