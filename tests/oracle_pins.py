@@ -508,3 +508,44 @@ def pin_nonlinear_steady_state(z=(1, -1), D=(0.2, 0.2), V=0.5, debye=4.0, flags=
     q = o.electrode_charge()
     assert abs(q[0] / q1 - 1) < 1e-7 and abs(q[1] / q[0] + 1) < 1e-6, (q, q1)
     return o
+
+
+def pin_sor_rate(libpath=None):
+    """The SOR iteration itself, not only its fixed point (Sec. II C, Eq. 13
+    with Eq. 15).  On a 1 x 1 x 32 slab every in-plane link of the D3Q19 set
+    joins a node to itself and is left out, the five links along each z
+    direction sum to the weight 1/6, and the four colour classes reduce to
+    two alternating planes: the sweep is SOR on the tridiagonal operator with
+    diagonal 2 (3 next to a wall, the doubled wall link) and off-diagonal 1,
+    in red-black order, a consistently ordered matrix.  Young's theorem then
+    gives the asymptotic contraction per sweep from the Jacobi spectral
+    radius mu (computed here as an eigenvalue): ((omega mu + sqrt(omega^2
+    mu^2 - 4 (omega - 1))) / 2)^2 below the optimal omega.  The residual's
+    decay between sweeps 100 and 160 after a change of the electrode
+    potentials (one that excites the slowest mode) must show it, for omega
+    1.8 (the configured value) and 1.5."""
+    nf = 32
+    shape, t, ps = W.slab(1, 1, nf, 1, 0.05, -0.05)
+    rs = W.salt_for_debye(4.0, LB)
+    n0 = W.noisy_concentrations(t, [rs, rs], 1e-3, seed=1)
+    diag = np.full(nf, 2.0)
+    diag[0] = diag[-1] = 3.0
+    off = np.diag(np.ones(nf - 1), 1) + np.diag(np.ones(nf - 1), -1)
+    mu = float(np.abs(np.linalg.eigvals(off / diag[:, None])).max())
+    new_ps = np.where(t == 1, 0.1, 0.0)
+
+    def resid_after(sweeps, omega):
+        o = _run(shape, t, ps, (1, -1), (0.05, 0.05), n_init=n0, n_ref=(rs, rs), omega=omega,
+                 tol=1e-14, max_iter=100000, check_every=1, libpath=libpath)
+        o.set_solver(0.0, sweeps)
+        o.set_electrode_potential(new_ps)
+        return float(np.abs(o.residual()).max())
+
+    rates = {}
+    for omega in (1.8, 1.5):
+        assert omega < 2.0 / (1.0 + math.sqrt(1.0 - mu * mu))  # below the optimum
+        young = ((omega * mu + math.sqrt(omega ** 2 * mu ** 2 - 4.0 * (omega - 1.0))) / 2.0) ** 2
+        rate = (resid_after(160, omega) / resid_after(100, omega)) ** (1.0 / 60.0)
+        assert abs(rate / young - 1.0) < 1e-4, (omega, rate, young)
+        rates[omega] = rate
+    return rates

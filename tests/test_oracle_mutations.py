@@ -79,6 +79,13 @@ MUTATIONS = [
      "return -(n_there * expm1(delta) - n_here * expm1(-delta)) / (2.0 * len);",
      "return -(n_there * delta + n_here * delta) / (2.0 * len);",
      [P.pin_nonlinear_steady_state]),
+    ("SOR relaxation factor ignored (Gauss-Seidel)",
+     "s->phi[r] = (1.0 - s->p.omega) * s->phi[r] + s->p.omega * gs;", "s->phi[r] = gs;",
+     [P.pin_sor_rate]),
+    ("SOR relaxation weights swapped",
+     "s->phi[r] = (1.0 - s->p.omega) * s->phi[r] + s->p.omega * gs;",
+     "s->phi[r] = s->p.omega * s->phi[r] + (1.0 - s->p.omega) * gs;",
+     [P.pin_sor_rate]),
     ("bounce-back into the same direction",
      "s->fnew[(long)opposite(i) * s->N + r] = post;", "s->fnew[(long)i * s->N + r] = post;",
      [P.pin_eo_slab, P.pin_equilibrium_moments]),

@@ -233,3 +233,7 @@ def test_set_electrode_potential():
                                          ((1, -1), (0.2, 0.2), 0.5, P.NAIVE)])
 def test_nonlinear_steady_state(z, D, V, flags):
     P.pin_nonlinear_steady_state(z, D, V, flags=flags)
+
+
+def test_sor_contraction_follows_young():
+    P.pin_sor_rate()
